@@ -1,0 +1,189 @@
+"""Element and face blocks of the scheme (oracle), eqs. (MD_2)-(MD_6).
+
+All integrals use the exact rules of ``quad`` in physical coordinates, with
+the stress basis in its *raw* form (``basis.DualRawBasis``), so the dual mass
+matrices M_j are full.  The canonical orthonormal dual basis is only used to
+translate stress DOFs at the boundary with the library.
+
+Readings of the paper taken here:
+  * Free-surface (boundary) faces: the dual element is T_{l,j} alone and the
+    face integral over Gamma_j is dropped from D and Q (traction-free
+    natural condition, sigma.n = 0).
+  * Material: rho_i constant per element; E_j constant per dual element with
+    the volume-weighted means lambda_j = (|T_l,j| lambda_l + |T_r,j| lambda_r)
+    / |R_j| (and likewise mu_j), i.e. the L2 projection onto constants.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import quad
+from .basis import (DualRawBasis, ElementMap, LagrangeBasis, n_phi, n_psi,
+                    phys_basis)
+from .mesh import Topology
+
+
+def voigt_index(dim: int):
+    """vo[c][l]: Voigt component of the symmetric tensor entry (c, l).
+    2D (xx, yy, xy); 3D (xx, yy, zz, yz, xz, xy), Section 2."""
+    if dim == 2:
+        return np.array([[0, 2], [2, 1]])
+    return np.array([[0, 5, 4], [5, 1, 3], [4, 3, 2]])
+
+
+def n_sigma(dim: int) -> int:
+    return dim * (dim + 1) // 2
+
+
+def stiffness(dim, lam, mu):
+    """E[p,q,c,l] of the isotropic Hooke law, eq. (1.1b):
+    sigma_pq = lambda div(v) delta_pq + mu (d_q v_p + d_p v_q),
+    written as sigma_pq = sum_cl E[p,q,c,l] d_l v_c."""
+    I = np.eye(dim)
+    return (lam * np.einsum("pq,cl->pqcl", I, I)
+            + mu * (np.einsum("pc,ql->pqcl", I, I) + np.einsum("pl,qc->pqcl", I, I)))
+
+
+def compliance_voigt(dim, lam, mu):
+    """C with sigma : E^{-1} sigma = s^T C s for the Voigt vector s.
+
+    3D: the inverse of the paper's 6x6 stiffness (eq. 5) with the factor 2
+    on shear entries that turns the Voigt product into the tensor product.
+    2D plane strain: the 3x3 restriction of the stiffness (normal block
+    [[l+2m, l], [l, l+2m]], shear 2m), inverted the same way.
+    """
+    if dim == 3:
+        Et = np.zeros((6, 6))
+        Et[:3, :3] = lam
+        Et[np.arange(3), np.arange(3)] = lam + 2 * mu
+        Et[np.arange(3, 6), np.arange(3, 6)] = 2 * mu
+        Wt = np.diag([1, 1, 1, 2, 2, 2.0])
+    else:
+        Et = np.array([[lam + 2 * mu, lam, 0], [lam, lam + 2 * mu, 0], [0, 0, 2 * mu]])
+        Wt = np.diag([1, 1, 2.0])
+    return Wt @ np.linalg.inv(Et)
+
+
+class Blocks:
+    """All blocks of one mesh / degree pair.
+
+    Mbar[e]      (N_phi, N_phi)       int_{T_e} phi_k phi_m        (MD_2, spatial part)
+    M[j]         (N_psi, N_psi)       int_{R_j} psi_k psi_m        (MD_2, spatial part)
+    D[j][s]      (N_phi, d, N_psi)    int_G phi_k psi_m n_{i,j} - int_{T_ij} d_l phi_k psi_m   (MD_3)
+    Qt[j][s]     (N_psi, d, N_phi)    int_{T_ij} psi d_l phi - int_G psi phi s_ij n_j          (qtilde)
+    L[j]         Cholesky factor of M[j]: canonical coefficients = L^T raw coefficients
+    lam_j, mu_j  dual-element material
+    """
+
+    def __init__(self, topo: Topology, p: int, lam, mu, rho):
+        self.topo = topo
+        d = self.dim = topo.dim
+        self.p = p
+        self.lb = LagrangeBasis(d, p)
+        self.nphi = n_phi(d, p)
+        self.npsi = n_psi(d, p)
+        self.nsig = n_sigma(d)
+        self.rho = np.asarray(rho, float)
+        lam = np.asarray(lam, float)
+        mu = np.asarray(mu, float)
+        psi_deg = 2 * p if d == 2 else p
+
+        self.maps = [ElementMap(topo.V[e]) for e in range(topo.n_elem)]
+        self.Mbar = []
+        for e in range(topo.n_elem):
+            x, w = quad.simplex_rule(topo.V[e], 2 * p)
+            phi, _ = phys_basis(self.lb, self.maps[e], x)
+            self.Mbar.append((phi * w[:, None]).T @ phi)
+
+        self.duals, self.M, self.L, self.D, self.Qt = [], [], [], [], []
+        self.lam_j = np.zeros(topo.n_face)
+        self.mu_j = np.zeros(topo.n_face)
+        self.vol_sub = np.zeros((topo.n_face, 2))
+        for j, F in enumerate(topo.faces):
+            sides = [0] if F.right < 0 else [0, 1]
+            psi = self._dual_basis(F)
+            self.duals.append(psi)
+            G = np.zeros((self.npsi, self.npsi))
+            Dj, Qj = [], []
+            for s in sides:
+                e = F.left if s == 0 else F.right
+                emap = self.maps[e] if s == 0 else ElementMap(F.Vr)
+                Tij = topo.sub_simplex(j, s)
+                x, w = quad.simplex_rule(Tij, 2 * psi_deg)
+                pv = psi.eval(x)
+                G += (pv * w[:, None]).T @ pv
+                self.vol_sub[j, s] = w.sum()
+                # volume parts
+                x, w = quad.simplex_rule(Tij, max(p - 1, 0) + psi_deg)
+                pv = psi.eval(x)
+                _, gphi = phys_basis(self.lb, emap, x)
+                Dv = -np.einsum("q,qlk,qm->klm", w, gphi, pv)
+                Qv = np.einsum("q,qm,qlk->mlk", w, pv, gphi)
+                if F.right >= 0:
+                    x, w = quad.simplex_rule(F.X, p + psi_deg)
+                    pv = psi.eval(x)
+                    phi, _ = phys_basis(self.lb, emap, x)
+                    sgn = 1.0 if s == 0 else -1.0
+                    n_ij = sgn * F.normal
+                    Df = np.einsum("q,qk,qm,l->klm", w, phi, pv, n_ij)
+                    Qf = -sgn * np.einsum("q,qm,qk,l->mlk", w, pv, phi, F.normal)
+                    Dv = Dv + Df
+                    Qv = Qv + Qf
+                Dj.append(Dv)
+                Qj.append(Qv)
+            self.M.append(G)
+            self.L.append(np.linalg.cholesky(G))
+            self.D.append(Dj)
+            self.Qt.append(Qj)
+            vl = self.vol_sub[j, 0]
+            if F.right >= 0:
+                vr = self.vol_sub[j, 1]
+                self.lam_j[j] = (vl * lam[F.left] + vr * lam[F.right]) / (vl + vr)
+                self.mu_j[j] = (vl * mu[F.left] + vr * mu[F.right]) / (vl + vr)
+            else:
+                self.lam_j[j] = lam[F.left]
+                self.mu_j[j] = mu[F.left]
+
+    def _dual_basis(self, F):
+        if self.dim == 2:
+            n1, n2 = F.X[0], F.X[1]
+            br = F.br if F.br is not None else (n1 + n2 - F.bl)
+            d1 = n2 - n1
+            d2 = br - F.bl
+            return DualRawBasis(2, self.p, n1, axes=[(d1 - d2) / 2, (d1 + d2) / 2])
+        pts = [F.X, F.bl[None, :]]
+        if F.br is not None:
+            pts.append(F.br[None, :])
+        c = np.vstack(pts).mean(axis=0)
+        h = np.max(np.linalg.norm(F.X - c[None, :], axis=1))
+        return DualRawBasis(3, self.p, c, scale=h)
+
+    # ------------------------------------------------------------ evaluation
+
+    def velocity_at(self, v_elem, e, x):
+        """v_elem (d, N_phi) of element e evaluated at physical points x."""
+        phi, _ = phys_basis(self.lb, self.maps[e], x)
+        return phi @ v_elem.T
+
+    def stress_at(self, s_raw, j, x):
+        """s_raw (n_sigma, N_psi) raw stress DOFs of face j at points x."""
+        return self.duals[j].eval(x) @ s_raw.T
+
+    def to_canonical(self, j, s_raw):
+        return s_raw @ self.L[j]
+
+    def from_canonical(self, j, s_can):
+        return np.linalg.solve(self.L[j].T, s_can.T).T
+
+
+def locate(topo: Topology, x, tol=1e-12):
+    """Brute-force point location: lowest element index whose closed simplex
+    contains x (ties between elements go to the lowest index)."""
+    for e in range(topo.n_elem):
+        V = topo.V[e]
+        J = (V[1:] - V[0]).T
+        lam = np.linalg.solve(J, np.asarray(x, float) - V[0])
+        bary = np.concatenate([[1 - lam.sum()], lam])
+        if np.all(bary >= -tol):
+            return e
+    return -1
