@@ -185,7 +185,8 @@ def dual_exponents(dim: int, p: int):
 class DualRawBasis:
     """Raw (non-orthonormal) dual basis of one dual element.
 
-    2D: monomials xi^a eta^b in the frame (origin n1, axes e1, e2).
+    2D: monomials (2 xi - 1)^a (2 eta - 1)^b in the frame (origin n1, axes
+        e1, e2); the affine shift keeps the nested spans of xi^a eta^b.
     3D: monomials ((x - c)/h)^alpha with c the dual element centroid and h
         a length scale (neither changes the canonical basis).
     """
@@ -202,7 +203,12 @@ class DualRawBasis:
         self.n = len(self.exps)
 
     def coords(self, x):
-        return (np.atleast_2d(x) - self.origin[None, :]) @ self.Ainv.T
+        y = (np.atleast_2d(x) - self.origin[None, :]) @ self.Ainv.T
+        if self.dim == 2:
+            # centre the frame coordinates on [-1, 1] (same nested spans,
+            # better conditioned Gram matrices)
+            y = 2.0 * y - 1.0
+        return y
 
     def eval(self, x):
         y = self.coords(x)
