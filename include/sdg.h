@@ -1,0 +1,225 @@
+/*
+ * sdg.h -- C ABI of the MI355X library for the staggered space-time
+ * discontinuous Galerkin scheme for linear elasticity of Tavelli & Dumbser
+ * (arXiv:1802.04516).
+ *
+ * The hot path is the matrix-free application of the velocity Schur
+ * complement, eq. (velocity.sys) of Section 4 and its Crank-Nicolson form
+ * (velocity.sys.cn):
+ *
+ *     A = T (x) rho Mbar  +  dt^2 (W T^-1 W) (x) K,
+ *     K v = sum_j D_j E_j sum_{i in {l(j), r(j)}} D_{i,j}^T v_i,
+ *
+ * where T, W are the time matrices of the Gauss-Legendre-Lagrange time basis
+ * (Section 3), D_{i,j} the blocks of eq. (MD_3) expressed in an orthonormal
+ * dual (stress) basis so that the dual mass matrices M_j of eq. (MD_2) are
+ * the identity, and E_j the isotropic Hooke law of eq. (1.1b).  For
+ * Crank-Nicolson A = rho Mbar + dt^2/4 K.
+ *
+ * Conventions
+ *   - Every function returns SDG_OK (0) or a negative SDG_E* code; the
+ *     message of the last failure on the calling thread is returned by
+ *     sdg_last_error().  No C++ exception crosses the boundary.
+ *   - Host arrays (const pointers documented as "host") are read during the
+ *     call and copied; the caller keeps ownership.
+ *   - Device arrays (documented as "device") are caller-owned allocations on
+ *     the context's device, contiguous, float64 unless stated otherwise.
+ *     The library never frees them and keeps no reference after the call.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued
+ *     in stream order; only sdg_solve_step and the reductions returning host
+ *     scalars synchronise the stream.
+ *   - All workspace is allocated by sdg_assemble; the apply and solve entry
+ *     points allocate nothing.
+ *   - A context is used by one host thread at a time.
+ *
+ * Layouts at the boundary
+ *   velocity slab    [elem][a][c][k]     a < N_gamma time node, c < dim
+ *                                        component, k < N_phi nodal basis
+ *                                        function (equispaced nodes of the
+ *                                        reference simplex, order: 2D
+ *                                        for j, for i: (i,j)/p; 3D for k,
+ *                                        for j, for i: (i,j,k)/p).
+ *   velocity state   [elem][c][k]        the end-of-slab value v(t^{n,-}).
+ *   stress state     [face][s][m]        Voigt component s (2D: xx, yy, xy;
+ *                                        3D: xx, yy, zz, yz, xz, xy,
+ *                                        Section 2) and canonical dual basis
+ *                                        function m.
+ *   batched vectors  [...][r] with the right-hand-side index r innermost.
+ *   Faces are numbered by ascending (l(j), local face of l(j)) where the
+ *   left element l(j) is the lower element index and local face f of a
+ *   simplex is the one opposite its local vertex f.
+ *   Canonical dual basis of face j: the Gram-Schmidt orthonormalisation over
+ *   the dual element R_j of
+ *     2D: xi^a eta^b, (a, b) lexicographic with a major, a, b <= p, in the
+ *         frame x = n1 + xi e1 + eta e2, e1 = (d1 - d2)/2, e2 = (d1 + d2)/2,
+ *         d1 = n2 - n1 (face vertices, n1 of lower global vertex index),
+ *         d2 = b_r - b_l (barycentres; on a boundary face b_r = n1 + n2 - b_l);
+ *     3D: x^a y^b z^c of total degree <= p, by degree, then a descending,
+ *         then b descending.
+ */
+#ifndef SDG_H
+#define SDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SDG_OK = 0,
+  SDG_EINVAL = -1,        /* bad argument (null pointer, size, enum value)          */
+  SDG_ENOMEM = -2,        /* host or device allocation failed                       */
+  SDG_EDEVICE = -3,       /* a HIP call failed                                      */
+  SDG_EMESH = -4,         /* degenerate element, non-manifold or unmatched face     */
+  SDG_ENOCONV = -5,       /* Krylov solver hit max_iter; state holds last iterate   */
+  SDG_ENONFINITE = -6,    /* NaN/Inf met in a residual                              */
+  SDG_EUNSUPPORTED = -7,  /* degree / dimension combination not compiled in         */
+  SDG_ESTATE = -8         /* call order violated (e.g. apply before assemble)       */
+};
+
+enum { SDG_SCHEME_STDG = 0, SDG_SCHEME_CN = 1 };
+enum { SDG_PREC_F64 = 1, SDG_PREC_F32 = 2 };
+enum { SDG_SOLVER_AUTO = 0, SDG_SOLVER_CG = 1, SDG_SOLVER_GMRES = 2 };
+
+typedef struct sdg_ctx sdg_ctx;
+
+typedef struct {
+  int32_t dim, p, p_gamma, scheme;
+  int32_t n_phi, n_psi, n_gamma, n_sigma;
+  int64_t n_elem, n_face, n_face_boundary;
+  int64_t n_vel_slab;     /* n_elem * n_gamma * dim * n_phi            */
+  int64_t n_vel_state;    /* n_elem * dim * n_phi                      */
+  int64_t n_stress_state; /* n_face * n_sigma * n_psi                  */
+  int64_t n_stress_slab;  /* n_face * n_gamma * n_sigma * n_psi        */
+  double dt;
+  double tau[8];          /* time nodes of the slab in [0, 1]          */
+  int64_t op_bytes_f64;   /* bytes of the stored FP64 operator blocks  */
+  int64_t op_bytes_f32;
+  int32_t max_rhs;        /* largest n_rhs accepted by the apply calls */
+  int32_t pad;
+} sdg_sizes;
+
+typedef struct {
+  int32_t solver;      /* SDG_SOLVER_*; AUTO = CG for Crank-Nicolson, GMRES otherwise    */
+  int32_t precision;   /* SDG_PREC_F64, or SDG_PREC_F32 = FP32 operator inside FP64
+                          iterative refinement (dots, residuals, updates stay FP64)     */
+  double rtol;         /* stop when ||b - A v||_2 <= rtol ||b||_2                       */
+  int32_t max_iter;    /* total Krylov iterations (inner iterations for FP32)          */
+  int32_t restart;     /* GMRES restart length (<= 64)                                  */
+  int32_t check_every; /* host convergence poll period in iterations                    */
+  int32_t max_refine;  /* outer refinement sweeps for SDG_PREC_F32                      */
+  double inner_rtol;   /* relative tolerance of each inner FP32 solve                   */
+} sdg_solve_opts;
+
+typedef struct {
+  int32_t iterations;  /* Krylov iterations performed                     */
+  int32_t matvecs;     /* operator applications (all precisions)          */
+  int32_t refinements; /* outer refinement sweeps (FP32 mode)             */
+  int32_t converged;
+  double rel_residual; /* final ||b - A v|| / ||b|| in FP64               */
+  double b_norm;
+} sdg_solve_info;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* sdg_last_error(void);
+
+/* Create a context bound to HIP device `device`.  *out is set to NULL on
+ * failure.  Returns SDG_EDEVICE if the device cannot be used. */
+int sdg_create(sdg_ctx** out, int device);
+
+/* Free the context and everything it allocated.  NULL-safe. */
+void sdg_destroy(sdg_ctx* ctx);
+
+/* Mesh (Section 3): n_vert vertices xyz[n_vert*dim] (host), n_elem simplices
+ * elem[n_elem*(dim+1)] (host, vertex indices).  period (host, dim doubles)
+ * or NULL: on a periodic mesh vertices on opposite sides are identified and
+ * each element is unwrapped by the minimum-image rule relative to its first
+ * vertex.  Faces with a single element are free-surface boundaries.
+ * Returns SDG_EMESH for a degenerate element, a face shared by more than
+ * two elements or an unmatched periodic face. */
+int sdg_set_mesh(sdg_ctx* ctx, int dim, int64_t n_vert, const double* xyz,
+                 int64_t n_elem, const int64_t* elem, const double* period);
+
+/* Space degree p (Section 3: N_phi = C(p+dim, dim) velocity functions,
+ * N_psi = (p+1)^2 in 2D and N_phi in 3D stress functions), time degree
+ * p_gamma (N_gamma = p_gamma + 1), scheme SDG_SCHEME_STDG (eqs. NM25-NM26)
+ * or SDG_SCHEME_CN (eqs. NM25.cn-NM26.cn, requires p_gamma = 0), time step
+ * dt > 0.  SDG_EUNSUPPORTED if the (dim, p, N_gamma) kernels are not
+ * compiled in. */
+int sdg_set_discretization(sdg_ctx* ctx, int p, int p_gamma, int scheme, double dt);
+
+/* Per-element Lame parameters and density (host, n_elem each, > 0).
+ * E_j is constant per dual element with volume-weighted lambda, mu. */
+int sdg_set_material(sdg_ctx* ctx, const double* lambda, const double* mu, const double* rho);
+
+/* Build topology, geometry, bases and the operator blocks on the host and
+ * upload them.  precisions = SDG_PREC_F64 | SDG_PREC_F32 selects which
+ * copies of the blocks are stored.  max_rhs (>= 1) sizes the workspaces for
+ * batched applies and solves. */
+int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs);
+
+int sdg_query(const sdg_ctx* ctx, sdg_sizes* out);
+
+/* Face table in the library's face order (host arrays of n_face entries):
+ * left element, its local face, right element (-1 on the boundary), its
+ * local face (-1 on the boundary).  Any pointer may be NULL. */
+int sdg_face_table(const sdg_ctx* ctx, int64_t* left, int32_t* left_face,
+                   int64_t* right, int32_t* right_face);
+
+/* y = A v for n_rhs right-hand sides (device, slab layout, r innermost).
+ * precision SDG_PREC_F64 or SDG_PREC_F32 (FP32 blocks and arithmetic, FP64
+ * input/output).  v and y must not alias. */
+int sdg_apply_velocity_operator(sdg_ctx* ctx, const double* v, double* y, int n_rhs,
+                                int precision, void* stream);
+
+/* y = A^T w, A^T = T^T (x) rho Mbar + dt^2 (W T^-T W) (x) K (K symmetric). */
+int sdg_apply_adjoint(sdg_ctx* ctx, const double* w, double* y, int n_rhs,
+                      int precision, void* stream);
+
+/* Point sources S_v = d delta(x - x_s) S(t) / rho (Section 6.3): positions
+ * pos[n_src*dim], directions dir[n_src*dim] (host).  Each source is located
+ * once (lowest element index on ties) and its nodal basis values stored.
+ * With n_rhs > 1, right-hand side r of a batched solve carries source
+ * r % n_src only; with n_rhs = 1 all sources act together. */
+int sdg_set_sources(sdg_ctx* ctx, int64_t n_src, const double* pos, const double* dir);
+
+/* One implicit time step of n_rhs independent states:
+ *   1. right-hand side of eq. (velocity.sys) (or velocity.sys.cn) from the
+ *      old state v_state (device [elem][c][k][r]) and sigma_state (device
+ *      [face][s][m][r]) plus the point sources with amplitudes
+ *      amp[n_src*N_gamma] (host; S(t) at the slab's time nodes, the
+ *      midpoint for Crank-Nicolson; NULL = no source);
+ *   2. Krylov solve for the velocity slab (CG or restarted GMRES);
+ *   3. stress back-substitution, eq. (NM26) or (NM26.cn);
+ *   4. overwrite v_state and sigma_state with the end-of-slab values.
+ * v_slab / sigma_slab (device, optional) receive the slab DOFs.
+ * The initial guess is the old state copied to every time node.
+ * On SDG_ENOCONV the states hold the step computed from the last iterate
+ * and *info is filled. */
+int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const double* amp,
+                   int n_rhs, const sdg_solve_opts* opts, sdg_solve_info* info,
+                   double* v_slab, double* sigma_slab, void* stream);
+
+/* Total energy 1/2 sum_i rho_i int |v|^2 + 1/2 sum_j int sigma : E_j^-1 sigma
+ * (Section 5.2) of a state, FP64, written to out[n_rhs] (host). */
+int sdg_energy(sdg_ctx* ctx, const double* v_state, const double* sigma_state, int n_rhs,
+               double* out, void* stream);
+
+/* Velocity of a state at n_pts host points pts[n_pts*dim], written to
+ * out[n_pts*dim*n_rhs] (device, [pt][c][r]).  Points outside the mesh give
+ * SDG_EINVAL. */
+int sdg_sample_velocity(sdg_ctx* ctx, const double* v_state, int n_rhs, int64_t n_pts,
+                        const double* pts, double* out, void* stream);
+
+/* Stress of a state at points: pts[n_pts*dim] (host) with the face index
+ * face[n_pts] (host) of the dual element each point lies in; out
+ * [pt][s][r] (device). */
+int sdg_eval_stress(sdg_ctx* ctx, const double* sigma_state, int n_rhs, int64_t n_pts,
+                    const double* pts, const int64_t* face, double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDG_H */

@@ -1,0 +1,302 @@
+"""MI355X library for the staggered space-time DG scheme for linear elasticity
+(Tavelli & Dumbser, arXiv:1802.04516): Python binding of the C ABI.
+
+This module only marshals arguments into ``libsdg.so`` (see include/sdg.h);
+every step of the hot path runs in the library's HIP kernels.  PyTorch is
+used for device memory and streams.  There is no fallback: if the library is
+not built, or a GPU is not present, the calls raise.
+
+The functions ``sdg_*`` mirror the C entry points one to one; ``Context``
+wraps them for convenience.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsdg.so")
+
+SDG_OK = 0
+SDG_EINVAL, SDG_ENOMEM, SDG_EDEVICE, SDG_EMESH = -1, -2, -3, -4
+SDG_ENOCONV, SDG_ENONFINITE, SDG_EUNSUPPORTED, SDG_ESTATE = -5, -6, -7, -8
+SDG_SCHEME_STDG, SDG_SCHEME_CN = 0, 1
+SDG_PREC_F64, SDG_PREC_F32 = 1, 2
+SDG_SOLVER_AUTO, SDG_SOLVER_CG, SDG_SOLVER_GMRES = 0, 1, 2
+
+_ERRNAMES = {SDG_EINVAL: "EINVAL", SDG_ENOMEM: "ENOMEM", SDG_EDEVICE: "EDEVICE", SDG_EMESH: "EMESH",
+             SDG_ENOCONV: "ENOCONV", SDG_ENONFINITE: "ENONFINITE", SDG_EUNSUPPORTED: "EUNSUPPORTED",
+             SDG_ESTATE: "ESTATE"}
+
+EXPORTED = ("sdg_last_error", "sdg_create", "sdg_destroy", "sdg_set_mesh", "sdg_set_discretization",
+            "sdg_set_material", "sdg_assemble", "sdg_query", "sdg_face_table",
+            "sdg_apply_velocity_operator", "sdg_apply_adjoint", "sdg_set_sources", "sdg_solve_step",
+            "sdg_energy", "sdg_sample_velocity", "sdg_eval_stress")
+
+
+class SdgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("p", ctypes.c_int32), ("p_gamma", ctypes.c_int32),
+                ("scheme", ctypes.c_int32), ("n_phi", ctypes.c_int32), ("n_psi", ctypes.c_int32),
+                ("n_gamma", ctypes.c_int32), ("n_sigma", ctypes.c_int32), ("n_elem", ctypes.c_int64),
+                ("n_face", ctypes.c_int64), ("n_face_boundary", ctypes.c_int64),
+                ("n_vel_slab", ctypes.c_int64), ("n_vel_state", ctypes.c_int64),
+                ("n_stress_state", ctypes.c_int64), ("n_stress_slab", ctypes.c_int64),
+                ("dt", ctypes.c_double), ("tau", ctypes.c_double * 8), ("op_bytes_f64", ctypes.c_int64),
+                ("op_bytes_f32", ctypes.c_int64), ("max_rhs", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int32), ("precision", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("max_refine", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("matvecs", ctypes.c_int32), ("refinements", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("b_norm", ctypes.c_double)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_I32P = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    """Load libsdg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1802_04516_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    i = ctypes.c_int
+    sig = {
+        "sdg_last_error": ([], ctypes.c_char_p),
+        "sdg_create": ([ctypes.POINTER(_P), i], i),
+        "sdg_destroy": ([_P], None),
+        "sdg_set_mesh": ([_P, i, ctypes.c_int64, _DP, ctypes.c_int64, _I64P, _DP], i),
+        "sdg_set_discretization": ([_P, i, i, i, ctypes.c_double], i),
+        "sdg_set_material": ([_P, _DP, _DP, _DP], i),
+        "sdg_assemble": ([_P, ctypes.c_uint, i], i),
+        "sdg_query": ([_P, ctypes.POINTER(Sizes)], i),
+        "sdg_face_table": ([_P, _I64P, _I32P, _I64P, _I32P], i),
+        "sdg_apply_velocity_operator": ([_P, _P, _P, i, i, _P], i),
+        "sdg_apply_adjoint": ([_P, _P, _P, i, i, _P], i),
+        "sdg_set_sources": ([_P, ctypes.c_int64, _DP, _DP], i),
+        "sdg_solve_step": ([_P, _P, _P, _DP, i, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P, _P, _P], i),
+        "sdg_energy": ([_P, _P, _P, i, _DP, _P], i),
+        "sdg_sample_velocity": ([_P, _P, i, ctypes.c_int64, _DP, _P, _P], i),
+        "sdg_eval_stress": ([_P, _P, i, ctypes.c_int64, _DP, _I64P, _P, _P], i),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != SDG_OK:
+        raise SdgError(rc, lib().sdg_last_error().decode())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a
+
+
+def _hp(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype)) if a is not None else None
+
+
+def _dev(t, numel=None, name="tensor"):
+    """Device pointer of a contiguous float64 CUDA/HIP tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor on the GPU")
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 GPU tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------- C mirrors
+
+def sdg_create(device: int = 0):
+    h = _P()
+    _check(lib().sdg_create(ctypes.byref(h), device))
+    return h
+
+
+def sdg_destroy(h):
+    lib().sdg_destroy(h)
+
+
+def sdg_set_mesh(h, xyz, elem, period=None):
+    xyz = _host(xyz, np.float64)
+    elem = _host(elem, np.int64)
+    dim = xyz.shape[1]
+    per = _host(period, np.float64) if period is not None else None
+    _check(lib().sdg_set_mesh(h, dim, xyz.shape[0], _hp(xyz, ctypes.c_double), elem.shape[0],
+                              _hp(elem, ctypes.c_int64), _hp(per, ctypes.c_double)))
+
+
+def sdg_set_discretization(h, p, p_gamma, scheme, dt):
+    _check(lib().sdg_set_discretization(h, p, p_gamma, scheme, float(dt)))
+
+
+def sdg_set_material(h, lam, mu, rho):
+    lam, mu, rho = (_host(x, np.float64) for x in (lam, mu, rho))
+    _check(lib().sdg_set_material(h, _hp(lam, ctypes.c_double), _hp(mu, ctypes.c_double),
+                                  _hp(rho, ctypes.c_double)))
+
+
+def sdg_assemble(h, precisions=SDG_PREC_F64 | SDG_PREC_F32, max_rhs=1):
+    _check(lib().sdg_assemble(h, precisions, max_rhs))
+
+
+def sdg_query(h) -> dict:
+    s = Sizes()
+    _check(lib().sdg_query(h, ctypes.byref(s)))
+    out = {f: getattr(s, f) for f, _ in Sizes._fields_ if f not in ("tau", "pad")}
+    out["tau"] = [s.tau[a] for a in range(s.n_gamma)]
+    return out
+
+
+def sdg_face_table(h, n_face):
+    l = np.empty(n_face, np.int64)
+    lf = np.empty(n_face, np.int32)
+    r = np.empty(n_face, np.int64)
+    rf = np.empty(n_face, np.int32)
+    _check(lib().sdg_face_table(h, _hp(l, ctypes.c_int64), _hp(lf, ctypes.c_int32), _hp(r, ctypes.c_int64),
+                                _hp(rf, ctypes.c_int32)))
+    return l, lf, r, rf
+
+
+def sdg_apply_velocity_operator(h, v, y, n_rhs=1, precision=SDG_PREC_F64, stream=None):
+    _check(lib().sdg_apply_velocity_operator(h, _dev(v, name="v"), _dev(y, name="y"), n_rhs, precision,
+                                             _stream(stream)))
+
+
+def sdg_apply_adjoint(h, w, y, n_rhs=1, precision=SDG_PREC_F64, stream=None):
+    _check(lib().sdg_apply_adjoint(h, _dev(w, name="w"), _dev(y, name="y"), n_rhs, precision, _stream(stream)))
+
+
+def sdg_set_sources(h, pos, direction):
+    pos = _host(pos, np.float64)
+    d = _host(direction, np.float64)
+    _check(lib().sdg_set_sources(h, pos.shape[0], _hp(pos, ctypes.c_double), _hp(d, ctypes.c_double)))
+
+
+def sdg_solve_step(h, v_state, sigma_state, amp=None, n_rhs=1, opts: SolveOpts | None = None,
+                   v_slab=None, sigma_slab=None, stream=None, raise_on_noconv=True):
+    opts = opts or SolveOpts(SDG_SOLVER_AUTO, SDG_PREC_F64, 1e-10, 1000, 30, 5, 10, 1e-4)
+    info = SolveInfo()
+    a = _host(amp, np.float64) if amp is not None else None
+    rc = lib().sdg_solve_step(h, _dev(v_state, name="v_state"), _dev(sigma_state, name="sigma_state"),
+                              _hp(a, ctypes.c_double), n_rhs, ctypes.byref(opts), ctypes.byref(info),
+                              _dev(v_slab, name="v_slab") if v_slab is not None else None,
+                              _dev(sigma_slab, name="sigma_slab") if sigma_slab is not None else None,
+                              _stream(stream))
+    res = {f: getattr(info, f) for f, _ in SolveInfo._fields_}
+    if rc == SDG_ENOCONV and not raise_on_noconv:
+        return res
+    _check(rc)
+    return res
+
+
+def sdg_energy(h, v_state, sigma_state, n_rhs=1, stream=None):
+    out = np.zeros(n_rhs)
+    _check(lib().sdg_energy(h, _dev(v_state, name="v_state"), _dev(sigma_state, name="sigma_state"), n_rhs,
+                            _hp(out, ctypes.c_double), _stream(stream)))
+    return out
+
+
+def sdg_sample_velocity(h, v_state, pts, out, n_rhs=1, stream=None):
+    pts = _host(pts, np.float64)
+    _check(lib().sdg_sample_velocity(h, _dev(v_state, name="v_state"), n_rhs, pts.shape[0],
+                                     _hp(pts, ctypes.c_double), _dev(out, name="out"), _stream(stream)))
+
+
+def sdg_eval_stress(h, sigma_state, pts, face, out, n_rhs=1, stream=None):
+    pts = _host(pts, np.float64)
+    face = _host(face, np.int64)
+    _check(lib().sdg_eval_stress(h, _dev(sigma_state, name="sigma_state"), n_rhs, pts.shape[0],
+                                 _hp(pts, ctypes.c_double), _hp(face, ctypes.c_int64), _dev(out, name="out"),
+                                 _stream(stream)))
+
+
+# ---------------------------------------------------------------- convenience wrapper
+
+class Context:
+    """One mesh / discretisation / material on one GPU."""
+
+    def __init__(self, device: int = 0):
+        self.h = sdg_create(device)
+        self.device = device
+        self.sizes = None
+
+    def close(self):
+        if self.h:
+            sdg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def setup(self, mesh_xyz, elem, period, p, p_gamma, scheme, dt, lam, mu, rho,
+              precisions=SDG_PREC_F64 | SDG_PREC_F32, max_rhs=1):
+        sdg_set_mesh(self.h, mesh_xyz, elem, period)
+        sdg_set_discretization(self.h, p, p_gamma, scheme, dt)
+        sdg_set_material(self.h, lam, mu, rho)
+        sdg_assemble(self.h, precisions, max_rhs)
+        self.sizes = sdg_query(self.h)
+        return self.sizes
+
+    def face_table(self):
+        return sdg_face_table(self.h, self.sizes["n_face"])
+
+    def _n(self, key):
+        return self.sizes[key]
+
+    def apply(self, v, y, precision=SDG_PREC_F64, stream=None):
+        n = self._n("n_vel_slab")
+        _dev(v, n, "v"), _dev(y, n, "y")
+        sdg_apply_velocity_operator(self.h, v, y, 1, precision, stream)
+
+    def apply_adjoint(self, w, y, precision=SDG_PREC_F64, stream=None):
+        n = self._n("n_vel_slab")
+        _dev(w, n, "w"), _dev(y, n, "y")
+        sdg_apply_adjoint(self.h, w, y, 1, precision, stream)
+
+    def set_sources(self, pos, direction):
+        sdg_set_sources(self.h, pos, direction)
+
+    def step(self, v_state, sigma_state, amp=None, **kw):
+        _dev(v_state, self._n("n_vel_state"), "v_state")
+        _dev(sigma_state, self._n("n_stress_state"), "sigma_state")
+        return sdg_solve_step(self.h, v_state, sigma_state, amp, **kw)
+
+    def energy(self, v_state, sigma_state):
+        return float(sdg_energy(self.h, v_state, sigma_state)[0])

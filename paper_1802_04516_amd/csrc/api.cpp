@@ -1,0 +1,630 @@
+// C-ABI entry points (include/sdg.h): context lifecycle, assembly, operator
+// application, one implicit time step, energy and point evaluation.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "context.hpp"
+
+namespace sdg {
+
+bool dispatch_2d(int which, int dim, int p, int ng, int prec, int mode, const OpArgs& a, hipStream_t s);
+bool dispatch_3d(int which, int dim, int p, int ng, int prec, int mode, const OpArgs& a, hipStream_t s);
+
+bool launch_face(int dim, int p, int ng, int prec, int mode, const OpArgs& a, hipStream_t s) {
+  return dim == 2 ? dispatch_2d(0, dim, p, ng, prec, mode, a, s) : dispatch_3d(0, dim, p, ng, prec, mode, a, s);
+}
+bool launch_elem(int dim, int p, int ng, const OpArgs& a, hipStream_t s) {
+  return dim == 2 ? dispatch_2d(1, dim, p, ng, SDG_PREC_F64, 0, a, s)
+                  : dispatch_3d(1, dim, p, ng, SDG_PREC_F64, 0, a, s);
+}
+bool have_kernels(int dim, int p, int ng) {
+  OpArgs a{};
+  return dim == 2 ? dispatch_2d(2, dim, p, ng, SDG_PREC_F64, 0, a, nullptr)
+                  : dispatch_3d(2, dim, p, ng, SDG_PREC_F64, 0, a, nullptr);
+}
+
+namespace {
+
+thread_local std::string g_err;
+
+template <class F>
+int guard(F&& f) {
+  try {
+    f();
+    g_err.clear();
+    return SDG_OK;
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return SDG_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return SDG_EINVAL;
+  }
+}
+
+Ctx& ctx_of(sdg_ctx* c) {
+  require(c != nullptr, SDG_EINVAL, "null context");
+  return *reinterpret_cast<Ctx*>(c);
+}
+
+// small dense helpers for the N_gamma x N_gamma time matrices
+std::vector<double> inverse(const std::vector<double>& A, int n) {
+  std::vector<double> M = A, I(n * n, 0.0);
+  for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(M[r * n + c]) > std::fabs(M[piv * n + c])) piv = r;
+    for (int k = 0; k < n; ++k) { std::swap(M[c * n + k], M[piv * n + k]); std::swap(I[c * n + k], I[piv * n + k]); }
+    const double d = M[c * n + c];
+    for (int k = 0; k < n; ++k) { M[c * n + k] /= d; I[c * n + k] /= d; }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = M[r * n + c];
+      for (int k = 0; k < n; ++k) { M[r * n + k] -= f * M[c * n + k]; I[r * n + k] -= f * I[c * n + k]; }
+    }
+  }
+  return I;
+}
+
+void set_sq(double* dst, const std::vector<double>& m, int n, bool transpose) {
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) dst[a * n + b] = transpose ? m[b * n + a] : m[a * n + b];
+}
+
+OpArgs base_args(Ctx& c, int prec) {
+  OpArgs a{};
+  a.n_face = c.hs.n_face;
+  a.n_elem = c.hs.n_elem;
+  a.faces = c.d_faces.p;
+  a.Dt = prec == SDG_PREC_F32 ? (const void*)c.d_Dt32.p : (const void*)c.d_Dt64.p;
+  a.face_lm = c.d_face_lm.p;
+  a.elem_w = c.d_elem_w.p;
+  a.Mref = c.d_Mref.p;
+  a.y_scale = 1.0;
+  return a;
+}
+
+void check_prec(Ctx& c, int prec) {
+  require(prec == SDG_PREC_F64 || prec == SDG_PREC_F32, SDG_EINVAL, "precision must be SDG_PREC_F64 or SDG_PREC_F32");
+  require((c.precisions & prec) != 0, SDG_ESTATE, "operator blocks of this precision were not assembled");
+}
+
+}  // namespace
+
+void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s) {
+  OpArgs a = base_args(c, prec);
+  a.v = v;
+  a.z = c.d_z.p;
+  a.y = y;
+  a.use_g = 1;
+  a.c = transpose ? c.adj : c.op;
+  launch_face(c.hs.dim, c.hs.p, c.hs.ng, prec, kScatter, a, s);
+  SDG_HIP(hipGetLastError());
+  launch_elem(c.hs.dim, c.hs.p, c.hs.ng, a, s);
+  SDG_HIP(hipGetLastError());
+}
+
+}  // namespace sdg
+
+using namespace sdg;
+
+extern "C" {
+
+const char* sdg_last_error(void) { return g_err.c_str(); }
+
+int sdg_create(sdg_ctx** out, int device) {
+  if (out) *out = nullptr;
+  return guard([&] {
+    require(out != nullptr, SDG_EINVAL, "null output pointer");
+    int n = 0;
+    SDG_HIP(hipGetDeviceCount(&n));
+    require(device >= 0 && device < n, SDG_EDEVICE, "no such HIP device");
+    SDG_HIP(hipSetDevice(device));
+    Ctx* c = new Ctx();
+    c->device = device;
+    *out = reinterpret_cast<sdg_ctx*>(c);
+  });
+}
+
+void sdg_destroy(sdg_ctx* ctx) {
+  if (!ctx) return;
+  Ctx* c = reinterpret_cast<Ctx*>(ctx);
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  delete c;
+}
+
+int sdg_set_mesh(sdg_ctx* ctx, int dim, int64_t n_vert, const double* xyz, int64_t n_elem, const int64_t* elem,
+                 const double* period) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(dim == 2 || dim == 3, SDG_EINVAL, "dim must be 2 or 3");
+    require(n_vert > 0 && n_elem > 0 && xyz && elem, SDG_EINVAL, "empty mesh");
+    require(n_elem < (int64_t)1 << 31, SDG_EINVAL, "too many elements");
+    c.dim = dim;
+    c.xyz.assign(xyz, xyz + n_vert * dim);
+    c.elem.assign(elem, elem + n_elem * (dim + 1));
+    if (period) {
+      c.period.assign(period, period + dim);
+      for (double P : c.period) require(P > 0 && std::isfinite(P), SDG_EINVAL, "period must be positive");
+    } else {
+      c.period.clear();
+    }
+    for (double x : c.xyz) require(std::isfinite(x), SDG_EINVAL, "non-finite vertex coordinate");
+    c.have_mesh = true;
+    c.assembled = false;
+  });
+}
+
+int sdg_set_discretization(sdg_ctx* ctx, int p, int p_gamma, int scheme, double dt) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.have_mesh, SDG_ESTATE, "set the mesh first");
+    require(p >= 1 && p_gamma >= 0 && p_gamma + 1 <= kMaxGamma, SDG_EINVAL, "degree out of range");
+    require(scheme == SDG_SCHEME_STDG || scheme == SDG_SCHEME_CN, SDG_EINVAL, "unknown scheme");
+    require(scheme != SDG_SCHEME_CN || p_gamma == 0, SDG_EINVAL, "Crank-Nicolson requires p_gamma = 0");
+    require(dt > 0 && std::isfinite(dt), SDG_EINVAL, "dt must be positive");
+    require(have_kernels(c.dim, p, p_gamma + 1), SDG_EUNSUPPORTED,
+            "no kernels compiled for dim=" + std::to_string(c.dim) + " p=" + std::to_string(p) +
+                " N_gamma=" + std::to_string(p_gamma + 1));
+    require(have_kernels(c.dim, p, 1), SDG_EUNSUPPORTED, "no N_gamma=1 kernels for this degree");
+    c.p = p;
+    c.pg = p_gamma;
+    c.scheme = scheme;
+    c.dt = dt;
+    c.have_disc = true;
+    c.assembled = false;
+  });
+}
+
+int sdg_set_material(sdg_ctx* ctx, const double* lambda, const double* mu, const double* rho) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.have_mesh, SDG_ESTATE, "set the mesh first");
+    require(lambda && mu && rho, SDG_EINVAL, "null material array");
+    const size_t n = c.elem.size() / (c.dim + 1);
+    c.lam.assign(lambda, lambda + n);
+    c.mu.assign(mu, mu + n);
+    c.rho.assign(rho, rho + n);
+    for (size_t i = 0; i < n; ++i)
+      require(std::isfinite(lambda[i]) && std::isfinite(mu[i]) && std::isfinite(rho[i]) && lambda[i] >= 0 &&
+                  mu[i] > 0 && rho[i] > 0,
+              SDG_EINVAL, "material parameters must be finite with lambda >= 0, mu > 0, rho > 0");
+    c.have_mat = true;
+    c.assembled = false;
+  });
+}
+
+int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.have_mesh && c.have_disc && c.have_mat, SDG_ESTATE, "mesh, discretization and material must be set");
+    require((precisions & (SDG_PREC_F64 | SDG_PREC_F32)) != 0 && (precisions & ~3u) == 0, SDG_EINVAL,
+            "precisions must be a non-empty subset of SDG_PREC_F64 | SDG_PREC_F32");
+    require(max_rhs == 1, SDG_EUNSUPPORTED, "batched right-hand sides are not built in this version");
+    SDG_HIP(hipSetDevice(c.device));
+    c.assembled = false;
+    HostSetup& hs = c.hs;
+    const int64_t n_elem = (int64_t)(c.elem.size() / (c.dim + 1));
+    const int64_t n_vert = (int64_t)(c.xyz.size() / c.dim);
+    build_host_setup(hs, c.dim, n_vert, c.xyz.data(), n_elem, c.elem.data(), c.period.empty() ? nullptr : c.period.data(),
+                     c.p, c.pg, c.scheme, c.dt, c.lam.data(), c.mu.data(), c.rho.data());
+    const int d = hs.dim, ng = hs.ng, nphi = hs.nphi;
+    c.n_slab = hs.n_elem * ng * d * nphi;
+    c.n_state = hs.n_elem * d * nphi;
+    c.n_sig_state = hs.n_face * hs.nsig * hs.npsi;
+    c.precisions = precisions;
+    c.max_rhs = max_rhs;
+
+    // time coefficients
+    const double dt = hs.dt;
+    Coefs op{}, adj{};
+    if (c.scheme == SDG_SCHEME_CN) {
+      op.Tm[0] = 1.0;
+      op.Cg[0] = dt * dt / 4.0;
+    } else {
+      std::vector<double> Ti = inverse(hs.T, ng), WTW(ng * ng);
+      for (int a = 0; a < ng; ++a)
+        for (int b = 0; b < ng; ++b) WTW[a * ng + b] = dt * dt * hs.w[a] * Ti[a * ng + b] * hs.w[b];
+      set_sq(op.Tm, hs.T, ng, false);
+      set_sq(op.Cg, WTW, ng, false);
+      set_sq(adj.Tm, hs.T, ng, true);
+      set_sq(adj.Cg, WTW, ng, true);
+    }
+    if (c.scheme == SDG_SCHEME_CN) adj = op;
+    c.op = op;
+    c.adj = adj;
+
+    // operator blocks
+    c.d_faces.alloc(hs.n_face);
+    SDG_HIP(hipMemcpy(c.d_faces.p, hs.faces.data(), hs.n_face * sizeof(FaceRec), hipMemcpyHostToDevice));
+    if (precisions & SDG_PREC_F64) {
+      c.d_Dt64.alloc(hs.Dt.size());
+      SDG_HIP(hipMemcpy(c.d_Dt64.p, hs.Dt.data(), hs.Dt.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+      c.d_Dt64.free();
+    }
+    if (precisions & SDG_PREC_F32) {
+      std::vector<float> f(hs.Dt.begin(), hs.Dt.end());
+      c.d_Dt32.alloc(f.size());
+      SDG_HIP(hipMemcpy(c.d_Dt32.p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+      c.d_Dt32.free();
+    }
+    c.d_face_lm.alloc(hs.face_lm.size());
+    SDG_HIP(hipMemcpy(c.d_face_lm.p, hs.face_lm.data(), hs.face_lm.size() * sizeof(double), hipMemcpyHostToDevice));
+    c.d_elem_w.alloc(hs.elem_w.size());
+    SDG_HIP(hipMemcpy(c.d_elem_w.p, hs.elem_w.data(), hs.elem_w.size() * sizeof(double), hipMemcpyHostToDevice));
+    c.d_Mref.alloc(hs.Mref.size());
+    SDG_HIP(hipMemcpy(c.d_Mref.p, hs.Mref.data(), hs.Mref.size() * sizeof(double), hipMemcpyHostToDevice));
+    {
+      std::vector<double> tw(ng, 1.0);
+      if (c.scheme != SDG_SCHEME_CN) tw = hs.w;
+      c.d_tw.alloc(ng);
+      SDG_HIP(hipMemcpy(c.d_tw.p, tw.data(), ng * sizeof(double), hipMemcpyHostToDevice));
+      c.d_e1.alloc(ng);
+      SDG_HIP(hipMemcpy(c.d_e1.p, hs.e1.data(), ng * sizeof(double), hipMemcpyHostToDevice));
+    }
+
+    // workspaces
+    c.d_z.alloc((size_t)hs.n_elem * (d + 1) * ng * d * nphi);
+    const size_t n = c.n_slab;
+    c.d_V.alloc(c.scheme == SDG_SCHEME_CN ? 0 : (size_t)(kMaxRestart + 1) * n);
+    c.d_x.alloc(n);
+    c.d_b.alloc(n);
+    c.d_r.alloc(n);
+    c.d_w.alloc(n);
+    c.d_t.alloc(n);
+    c.d_d.alloc(n);
+    c.d_e.alloc(n);
+    c.d_partials.alloc((size_t)kRedBlocks * kRedSlots);
+    c.d_sc.alloc(1);
+    SDG_HIP(hipMemset(c.d_sc.p, 0, sizeof(DevScalars)));
+    if (!c.h_pinned) SDG_HIP(hipHostMalloc((void**)&c.h_pinned, 16 * sizeof(double), hipHostMallocDefault));
+    c.d_tmp_state.alloc(c.n_state);
+    c.d_tmp_sig.alloc(c.n_sig_state);
+    c.d_src_amp.alloc((size_t)std::max<int64_t>(c.n_src, 1) * ng);
+    SDG_HIP(hipDeviceSynchronize());
+    c.assembled = true;
+  });
+}
+
+int sdg_query(const sdg_ctx* ctx, sdg_sizes* out) {
+  return guard([&] {
+    require(ctx && out, SDG_EINVAL, "null argument");
+    const Ctx& c = *reinterpret_cast<const Ctx*>(ctx);
+    require(c.assembled, SDG_ESTATE, "assemble first");
+    const HostSetup& hs = c.hs;
+    std::memset(out, 0, sizeof(*out));
+    out->dim = hs.dim;
+    out->p = hs.p;
+    out->p_gamma = hs.pg;
+    out->scheme = hs.scheme;
+    out->n_phi = hs.nphi;
+    out->n_psi = hs.npsi;
+    out->n_gamma = hs.ng;
+    out->n_sigma = hs.nsig;
+    out->n_elem = hs.n_elem;
+    out->n_face = hs.n_face;
+    out->n_face_boundary = hs.n_bface;
+    out->n_vel_slab = c.n_slab;
+    out->n_vel_state = c.n_state;
+    out->n_stress_state = c.n_sig_state;
+    out->n_stress_slab = c.n_sig_state * hs.ng;
+    out->dt = hs.dt;
+    for (int a = 0; a < hs.ng; ++a) out->tau[a] = hs.scheme == SDG_SCHEME_CN ? 0.5 : hs.tau[a];
+    // bytes actually read per apply: boundary faces carry one block
+    const int64_t blk = (int64_t)hs.nphi * hs.dim * hs.npsi;
+    const int64_t nblk = 2 * hs.n_face - hs.n_bface;
+    out->op_bytes_f64 = nblk * blk * 8;
+    out->op_bytes_f32 = nblk * blk * 4;
+    out->max_rhs = c.max_rhs;
+  });
+}
+
+int sdg_face_table(const sdg_ctx* ctx, int64_t* left, int32_t* left_face, int64_t* right, int32_t* right_face) {
+  return guard([&] {
+    require(ctx != nullptr, SDG_EINVAL, "null context");
+    const Ctx& c = *reinterpret_cast<const Ctx*>(ctx);
+    require(c.assembled, SDG_ESTATE, "assemble first");
+    for (int64_t j = 0; j < c.hs.n_face; ++j) {
+      const FaceRec& r = c.hs.faces[j];
+      if (left) left[j] = r.left;
+      if (left_face) left_face[j] = r.lf;
+      if (right) right[j] = r.right;
+      if (right_face) right_face[j] = r.rf;
+    }
+  });
+}
+
+static int apply_common(sdg_ctx* ctx, const double* v, double* y, int n_rhs, int precision, void* stream,
+                        bool transpose) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.assembled, SDG_ESTATE, "assemble first");
+    require(v && y, SDG_EINVAL, "null vector");
+    require(v != y, SDG_EINVAL, "v and y must not alias");
+    require(n_rhs == 1, SDG_EUNSUPPORTED, "batched right-hand sides are not built in this version");
+    check_prec(c, precision);
+    SDG_HIP(hipSetDevice(c.device));
+    apply_op(c, v, y, precision, transpose, (hipStream_t)stream);
+  });
+}
+
+int sdg_apply_velocity_operator(sdg_ctx* ctx, const double* v, double* y, int n_rhs, int precision, void* stream) {
+  return apply_common(ctx, v, y, n_rhs, precision, stream, false);
+}
+
+int sdg_apply_adjoint(sdg_ctx* ctx, const double* w, double* y, int n_rhs, int precision, void* stream) {
+  return apply_common(ctx, w, y, n_rhs, precision, stream, true);
+}
+
+int sdg_set_sources(sdg_ctx* ctx, int64_t n_src, const double* pos, const double* dir) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.assembled, SDG_ESTATE, "assemble first");
+    require(n_src >= 0, SDG_EINVAL, "negative source count");
+    require(n_src == 0 || (pos && dir), SDG_EINVAL, "null source arrays");
+    const HostSetup& hs = c.hs;
+    std::vector<int64_t> el(n_src);
+    std::vector<double> phi((size_t)n_src * hs.nphi), dr((size_t)n_src * hs.dim);
+    for (int64_t s = 0; s < n_src; ++s) {
+      int64_t e = locate_point(hs, pos + s * hs.dim);
+      require(e >= 0, SDG_EINVAL, "source " + std::to_string(s) + " lies outside the mesh");
+      eval_velocity_basis(hs, e, pos + s * hs.dim, &phi[s * hs.nphi], 1e-12);
+      el[s] = e;
+      for (int k = 0; k < hs.dim; ++k) dr[s * hs.dim + k] = dir[s * hs.dim + k];
+    }
+    SDG_HIP(hipSetDevice(c.device));
+    c.n_src = n_src;
+    c.src_elem = el;
+    c.src_phi = phi;
+    c.src_dir = dr;
+    c.d_src_elem.alloc(std::max<int64_t>(n_src, 1));
+    c.d_src_phi.alloc(std::max<size_t>(phi.size(), 1));
+    c.d_src_dir.alloc(std::max<size_t>(dr.size(), 1));
+    c.d_src_amp.alloc((size_t)std::max<int64_t>(n_src, 1) * hs.ng);
+    if (n_src) {
+      SDG_HIP(hipMemcpy(c.d_src_elem.p, el.data(), el.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+      SDG_HIP(hipMemcpy(c.d_src_phi.p, phi.data(), phi.size() * sizeof(double), hipMemcpyHostToDevice));
+      SDG_HIP(hipMemcpy(c.d_src_dir.p, dr.data(), dr.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+  });
+}
+
+int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const double* amp, int n_rhs,
+                   const sdg_solve_opts* opts, sdg_solve_info* info, double* v_slab, double* sigma_slab,
+                   void* stream) {
+  SolveResult res;
+  int rc = guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.assembled, SDG_ESTATE, "assemble first");
+    require(v_state && sigma_state && opts, SDG_EINVAL, "null argument");
+    require(n_rhs == 1, SDG_EUNSUPPORTED, "batched right-hand sides are not built in this version");
+    require(opts->rtol > 0 && opts->max_iter > 0, SDG_EINVAL, "rtol and max_iter must be positive");
+    const int prec = opts->precision == 0 ? SDG_PREC_F64 : opts->precision;
+    check_prec(c, SDG_PREC_F64);
+    if (prec == SDG_PREC_F32) check_prec(c, SDG_PREC_F32);
+    int solver = opts->solver;
+    if (solver == SDG_SOLVER_AUTO) solver = c.scheme == SDG_SCHEME_CN ? SDG_SOLVER_CG : SDG_SOLVER_GMRES;
+    require(solver == SDG_SOLVER_CG || solver == SDG_SOLVER_GMRES, SDG_EINVAL, "unknown solver");
+    require(solver != SDG_SOLVER_GMRES || c.d_V.p != nullptr, SDG_EINVAL,
+            "GMRES workspace is only allocated for the space-time scheme");
+    const int restart = opts->restart > 0 ? opts->restart : 30;
+    require(restart <= kMaxRestart, SDG_EINVAL, "restart must be <= 32");
+    SDG_HIP(hipSetDevice(c.device));
+    hipStream_t s = (hipStream_t)stream;
+    const HostSetup& hs = c.hs;
+    const int d = hs.dim, ng = hs.ng, nvs = d * hs.nphi;
+    const double dt = hs.dt;
+
+    // 1. right-hand side
+    if (c.scheme == SDG_SCHEME_CN) {
+      OpArgs a = base_args(c, SDG_PREC_F64);
+      a.v = v_state;
+      a.sig_in = sigma_state;
+      a.z = c.d_z.p;
+      a.y = c.d_b.p;
+      a.use_g = 1;
+      a.c.Cg[0] = -dt * dt / 4.0;
+      a.c.Cs[0] = dt;
+      a.c.Tm[0] = 1.0;
+      launch_face(d, hs.p, 1, SDG_PREC_F64, kScatter, a, s);
+      launch_elem(d, hs.p, 1, a, s);
+    } else {
+      std::vector<double> Ti = inverse(hs.T, ng);
+      OpArgs a = base_args(c, SDG_PREC_F64);
+      a.sig_in = sigma_state;
+      a.z = c.d_z.p;
+      a.use_g = 0;
+      a.c.Cs[0] = 1.0;
+      launch_face(d, hs.p, 1, SDG_PREC_F64, kScatter, a, s);
+      OpArgs e = base_args(c, SDG_PREC_F64);
+      e.v = v_state;
+      e.v_spatial = 1;
+      e.z = c.d_z.p;
+      e.y = c.d_b.p;
+      for (int aa = 0; aa < ng; ++aa) {
+        e.c.Tm[aa * ng] = hs.e0[aa];
+        double q = 0.0;
+        for (int b = 0; b < ng; ++b) q += Ti[aa * ng + b] * hs.e0[b];
+        e.c.Cs[aa] = dt * hs.w[aa] * q;
+      }
+      launch_elem(d, hs.p, ng, e, s);
+    }
+    SDG_HIP(hipGetLastError());
+    if (amp && c.n_src > 0) {
+      SDG_HIP(hipMemcpyAsync(c.d_src_amp.p, amp, c.n_src * ng * sizeof(double), hipMemcpyHostToDevice, s));
+      launch_add_sources(c, c.d_b.p, c.d_src_amp.p, s);
+    }
+
+    // 2. initial guess and Krylov solve
+    launch_broadcast_time(hs.n_elem, ng, nvs, v_state, c.d_x.p, s);
+    const int check = opts->check_every > 0 ? opts->check_every : 5;
+    auto inner = [&](const double* b, double* x, double tol, int maxit, int pr) {
+      return solver == SDG_SOLVER_CG ? solve_cg(c, b, x, tol, maxit, check, pr, s)
+                                     : solve_gmres(c, b, x, tol, maxit, restart, check, pr, s);
+    };
+    if (prec == SDG_PREC_F64) {
+      res = inner(c.d_b.p, c.d_x.p, opts->rtol, opts->max_iter, SDG_PREC_F64);
+    } else {
+      // FP32 operator inside FP64 iterative refinement
+      const int64_t n = c.n_slab;
+      const double inner_tol = opts->inner_rtol > 0 ? opts->inner_rtol : 1e-4;
+      const int max_ref = opts->max_refine > 0 ? opts->max_refine : 10;
+      double bnorm = std::sqrt(vec_dot_host(c, n, c.d_b.p, c.d_b.p, s));
+      res.bnorm = bnorm;
+      for (int k = 0; k <= max_ref; ++k) {
+        apply_op(c, c.d_x.p, c.d_t.p, SDG_PREC_F64, false, s);
+        ++res.matvecs;
+        vec_copy(n, c.d_b.p, c.d_d.p, s);
+        vec_axpby(n, -1.0, c.d_t.p, 1.0, c.d_d.p, s);  // d = b - A64 x
+        double rn = std::sqrt(vec_dot_host(c, n, c.d_d.p, c.d_d.p, s));
+        require(std::isfinite(rn), SDG_ENONFINITE, "non-finite residual");
+        res.rel_res = bnorm > 0 ? rn / bnorm : 0.0;
+        if (res.rel_res <= opts->rtol || k == max_ref || res.iters >= opts->max_iter) {
+          res.converged = res.rel_res <= opts->rtol;
+          break;
+        }
+        // correction: A32 e = d from a zero initial guess, then x += e
+        vec_fill(n, 0.0, c.d_e.p, s);
+        SolveResult in = inner(c.d_d.p, c.d_e.p, inner_tol, opts->max_iter - res.iters, SDG_PREC_F32);
+        res.iters += in.iters;
+        res.matvecs += in.matvecs;
+        ++res.refinements;
+        vec_axpby(n, 1.0, c.d_e.p, 1.0, c.d_x.p, s);
+      }
+    }
+
+    // 3. stress back-substitution and 4. end-of-slab state
+    if (c.scheme == SDG_SCHEME_CN) {
+      vec_copy(c.n_slab, v_state, c.d_t.p, s);
+      vec_axpby(c.n_slab, 1.0, c.d_x.p, 1.0, c.d_t.p, s);  // v^n + v^{n+1}
+      OpArgs a = base_args(c, SDG_PREC_F64);
+      a.v = c.d_t.p;
+      a.sig_in = sigma_state;
+      a.use_g = 1;
+      a.c.Cg[0] = -dt / 2.0;
+      a.c.Cs[0] = 1.0;
+      a.c.send[0] = 1.0;
+      a.s_out = sigma_slab;
+      a.s_end = c.d_tmp_sig.p;
+      launch_face(d, hs.p, 1, SDG_PREC_F64, kWriteStress, a, s);
+      SDG_HIP(hipGetLastError());
+      vec_copy(c.n_sig_state, c.d_tmp_sig.p, sigma_state, s);
+      if (v_slab) vec_copy(c.n_slab, c.d_x.p, v_slab, s);
+      vec_copy(c.n_state, c.d_x.p, v_state, s);
+    } else {
+      std::vector<double> Ti = inverse(hs.T, ng);
+      OpArgs a = base_args(c, SDG_PREC_F64);
+      a.v = c.d_x.p;
+      a.sig_in = sigma_state;
+      a.use_g = 1;
+      for (int aa = 0; aa < ng; ++aa) {
+        double q = 0.0;
+        for (int b = 0; b < ng; ++b) {
+          a.c.Cg[aa * ng + b] = -dt * Ti[aa * ng + b] * hs.w[b];
+          q += Ti[aa * ng + b] * hs.e0[b];
+        }
+        a.c.Cs[aa] = q;
+        a.c.send[aa] = hs.e1[aa];
+      }
+      a.s_out = sigma_slab;
+      a.s_end = c.d_tmp_sig.p;
+      launch_face(d, hs.p, ng, SDG_PREC_F64, kWriteStress, a, s);
+      SDG_HIP(hipGetLastError());
+      vec_copy(c.n_sig_state, c.d_tmp_sig.p, sigma_state, s);
+      if (v_slab) vec_copy(c.n_slab, c.d_x.p, v_slab, s);
+      launch_end_of_slab(hs.n_elem, ng, nvs, c.d_e1.p, c.d_x.p, v_state, s);
+    }
+    SDG_HIP(hipStreamSynchronize(s));
+    if (!res.converged) throw Error(SDG_ENOCONV, "Krylov solver did not reach rtol within max_iter");
+  });
+  if (info) {
+    info->iterations = res.iters;
+    info->matvecs = res.matvecs;
+    info->refinements = res.refinements;
+    info->converged = res.converged ? 1 : 0;
+    info->rel_residual = res.rel_res;
+    info->b_norm = res.bnorm;
+  }
+  return rc;
+}
+
+int sdg_energy(sdg_ctx* ctx, const double* v_state, const double* sigma_state, int n_rhs, double* out, void* stream) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.assembled, SDG_ESTATE, "assemble first");
+    require(v_state && sigma_state && out, SDG_EINVAL, "null argument");
+    require(n_rhs == 1, SDG_EUNSUPPORTED, "batched right-hand sides are not built in this version");
+    SDG_HIP(hipSetDevice(c.device));
+    hipStream_t s = (hipStream_t)stream;
+    launch_energy(c, v_state, sigma_state, &c.d_sc.p->dots[1], s);
+    SDG_HIP(hipMemcpyAsync(c.h_pinned, &c.d_sc.p->dots[1], sizeof(double), hipMemcpyDeviceToHost, s));
+    SDG_HIP(hipStreamSynchronize(s));
+    out[0] = c.h_pinned[0];
+  });
+}
+
+int sdg_sample_velocity(sdg_ctx* ctx, const double* v_state, int n_rhs, int64_t n_pts, const double* pts,
+                        double* out, void* stream) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.assembled, SDG_ESTATE, "assemble first");
+    require(n_rhs == 1, SDG_EUNSUPPORTED, "batched right-hand sides are not built in this version");
+    require(n_pts >= 0 && (n_pts == 0 || (v_state && pts && out)), SDG_EINVAL, "null argument");
+    if (n_pts == 0) return;
+    const HostSetup& hs = c.hs;
+    std::vector<int64_t> el(n_pts);
+    std::vector<double> phi(n_pts * hs.nphi);
+    for (int64_t q = 0; q < n_pts; ++q) {
+      el[q] = locate_point(hs, pts + q * hs.dim);
+      require(el[q] >= 0, SDG_EINVAL, "sample point outside the mesh");
+      eval_velocity_basis(hs, el[q], pts + q * hs.dim, &phi[q * hs.nphi], 1e-12);
+    }
+    SDG_HIP(hipSetDevice(c.device));
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<int64_t> de;
+    DevBuf<double> dp;
+    de.alloc(n_pts);
+    dp.alloc(phi.size());
+    SDG_HIP(hipMemcpy(de.p, el.data(), el.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    SDG_HIP(hipMemcpy(dp.p, phi.data(), phi.size() * sizeof(double), hipMemcpyHostToDevice));
+    launch_sample(n_pts, hs.nphi, hs.dim, de.p, dp.p, v_state, out, s);
+    SDG_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int sdg_eval_stress(sdg_ctx* ctx, const double* sigma_state, int n_rhs, int64_t n_pts, const double* pts,
+                    const int64_t* face, double* out, void* stream) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.assembled, SDG_ESTATE, "assemble first");
+    require(n_rhs == 1, SDG_EUNSUPPORTED, "batched right-hand sides are not built in this version");
+    require(n_pts >= 0 && (n_pts == 0 || (sigma_state && pts && face && out)), SDG_EINVAL, "null argument");
+    if (n_pts == 0) return;
+    const HostSetup& hs = c.hs;
+    std::vector<double> psi(n_pts * hs.npsi);
+    for (int64_t q = 0; q < n_pts; ++q) {
+      require(face[q] >= 0 && face[q] < hs.n_face, SDG_EINVAL, "face index out of range");
+      eval_dual_canonical(hs, c.elem.data(), face[q], 1, pts + q * hs.dim, &psi[q * hs.npsi]);
+    }
+    SDG_HIP(hipSetDevice(c.device));
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<int64_t> df;
+    DevBuf<double> dp;
+    df.alloc(n_pts);
+    dp.alloc(psi.size());
+    SDG_HIP(hipMemcpy(df.p, face, n_pts * sizeof(int64_t), hipMemcpyHostToDevice));
+    SDG_HIP(hipMemcpy(dp.p, psi.data(), psi.size() * sizeof(double), hipMemcpyHostToDevice));
+    launch_eval_stress(n_pts, hs.npsi, hs.nsig, df.p, dp.p, sigma_state, out, s);
+    SDG_HIP(hipStreamSynchronize(s));
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// Library context: host setup products, device copies of the operator and
+// every workspace the apply / solve entry points use (allocated once, at
+// assemble time).
+#pragma once
+
+#include "sdg_internal.hpp"
+
+namespace sdg {
+
+constexpr int kMaxRestart = 32;
+constexpr int kRedBlocks = 1024;  // grid size of the reduction kernels
+constexpr int kRedSlots = 40;     // partial-sum slots per reduction block
+
+// Device-resident scalars of the Krylov solvers.
+struct DevScalars {
+  double rr, pq, rr_new, alpha, beta;
+  double norm;          // last computed norm
+  double inv_norm;
+  double resid;         // GMRES residual estimate |g_{j+1}|
+  double H[(kMaxRestart + 1) * kMaxRestart];  // column-major, ld = kMaxRestart+1
+  double cs[kMaxRestart], sn[kMaxRestart];
+  double g[kMaxRestart + 1];
+  double h1[kMaxRestart + 1], h2[kMaxRestart + 1];
+  double y[kMaxRestart];
+  double dots[kRedSlots];
+  unsigned int ticket[4];
+};
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  void alloc(size_t count) {
+    free();
+    if (count == 0) return;
+    SDG_HIP(hipMalloc(&p, count * sizeof(T)));
+    n = count;
+  }
+  void free() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  ~DevBuf() { free(); }
+};
+
+struct Ctx {
+  int device = 0;
+  // inputs
+  int dim = 0;
+  std::vector<double> xyz;
+  std::vector<int64_t> elem;
+  std::vector<double> period;
+  bool have_mesh = false, have_disc = false, have_mat = false, assembled = false;
+  int p = 0, pg = 0, scheme = 0;
+  double dt = 0.0;
+  std::vector<double> lam, mu, rho;
+  unsigned precisions = 0;
+  int max_rhs = 1;
+
+  HostSetup hs;
+  int64_t n_slab = 0, n_state = 0, n_sig_state = 0;
+
+  // operator on device
+  DevBuf<FaceRec> d_faces;
+  DevBuf<double> d_Dt64;
+  DevBuf<float> d_Dt32;
+  DevBuf<double> d_face_lm, d_elem_w, d_Mref;
+  DevBuf<double> d_z;  // element face slots
+  Coefs op{}, adj{};   // operator and its transpose
+
+  // solver workspace
+  DevBuf<double> d_V;                   // (restart+1) * n_slab   (GMRES) or 4 * n_slab (CG)
+  DevBuf<double> d_x, d_b, d_r, d_w, d_t, d_d, d_e;
+  DevBuf<double> d_partials;            // kRedBlocks * kRedSlots
+  DevBuf<DevScalars> d_sc;
+  double* h_pinned = nullptr;           // pinned host copy of a few scalars
+  DevBuf<double> d_tmp_state, d_tmp_sig; // state-sized scratch (energy, back-substitution)
+
+  // sources
+  int64_t n_src = 0;
+  std::vector<int64_t> src_elem;
+  std::vector<double> src_phi, src_dir;
+  DevBuf<double> d_src_phi, d_src_dir, d_src_amp;
+  DevBuf<double> d_tw;  // time quadrature weights of the slab (CN: {1})
+  DevBuf<double> d_e1;  // end-of-slab weights gamma_a(1)
+  DevBuf<int64_t> d_src_elem;
+
+  ~Ctx() {
+    if (h_pinned) (void)hipHostFree(h_pinned);
+  }
+};
+
+// operator application on slab vectors (FP64 in / out)
+void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s);
+
+// vector kernels
+void vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
+void vec_copy(int64_t n, const double* x, double* y, hipStream_t s);
+void vec_fill(int64_t n, double value, double* y, hipStream_t s);
+double vec_dot_host(Ctx& c, int64_t n, const double* x, const double* y, hipStream_t s);
+
+// solvers: solve A x = b in place (x holds the initial guess)
+struct SolveResult {
+  int iters = 0, matvecs = 0, refinements = 0;
+  bool converged = false;
+  double rel_res = 0.0, bnorm = 0.0;
+};
+SolveResult solve_cg(Ctx& c, const double* b, double* x, double rtol, int max_iter, int check_every,
+                     int prec, hipStream_t s);
+SolveResult solve_gmres(Ctx& c, const double* b, double* x, double rtol, int max_iter, int restart,
+                        int check_every, int prec, hipStream_t s);
+
+// step pieces
+void launch_broadcast_time(int64_t n_elem, int ng, int nvs, const double* state, double* slab,
+                           hipStream_t s);
+void launch_end_of_slab(int64_t n_elem, int ng, int nvs, const double* w, const double* slab,
+                        double* state, hipStream_t s);
+void launch_add_sources(Ctx& c, double* b, const double* amp_dev, hipStream_t s);
+void launch_energy(Ctx& c, const double* v, const double* sig, double* out_dev, hipStream_t s);
+void launch_sample(int64_t n, int nphi, int dim, const int64_t* elem, const double* phi,
+                   const double* v, double* out, hipStream_t s);
+void launch_eval_stress(int64_t n, int npsi, int nsig, const int64_t* face, const double* psi,
+                        const double* sig, double* out, hipStream_t s);
+
+}  // namespace sdg

@@ -1,0 +1,195 @@
+// Per-step kernels around the Krylov solve: initial guess, end-of-slab
+// values, point sources (eq. MD_5_2), the energy of Section 5.2 and point
+// evaluation of velocity and stress.
+#include "context.hpp"
+
+namespace sdg {
+
+namespace {
+constexpr int kT = 256;
+unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kT - 1) / kT, 65535)); }
+
+// slab[e][a][q] = state[e][q] for every time node a
+__global__ void k_broadcast(int64_t n_elem, int ng, int nvs, const double* __restrict__ st, double* __restrict__ sl) {
+  const int64_t n = n_elem * ng * nvs;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i / (ng * nvs);
+    const int q = (int)(i % nvs);
+    sl[i] = st[e * nvs + q];
+  }
+}
+
+// state[e][q] = sum_a w[a] slab[e][a][q]
+__global__ void k_end(int64_t n_elem, int ng, int nvs, const double* __restrict__ w, const double* __restrict__ sl,
+                      double* __restrict__ st) {
+  const int64_t n = n_elem * nvs;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i / nvs;
+    const int q = (int)(i % nvs);
+    double acc = 0.0;
+    for (int a = 0; a < ng; ++a) acc += w[a] * sl[(e * ng + a) * nvs + q];
+    st[i] = acc;
+  }
+}
+
+// b[e][a][c][k] += dt w_a amp[s][a] dir[s][c] phi[s][k]; one thread per
+// (a, c, k) of each source, sources applied in order by one thread to keep
+// the sum deterministic.
+__global__ void k_sources(int64_t n_src, int ng, int dim, int nphi, double dt, const double* __restrict__ wq,
+                          const int64_t* __restrict__ elem, const double* __restrict__ phi,
+                          const double* __restrict__ dir, const double* __restrict__ amp, double* __restrict__ b) {
+  const int per = ng * dim * nphi;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= per) return;
+  const int k = t % nphi, c = (t / nphi) % dim, a = t / (nphi * dim);
+  for (int64_t s = 0; s < n_src; ++s) {
+    const int64_t e = elem[s];
+    b[((e * ng + a) * dim + c) * nphi + k] += dt * wq[a] * amp[s * ng + a] * dir[s * dim + c] * phi[s * nphi + k];
+  }
+}
+
+__device__ inline double wsum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Partial energies per block -> partials[block]; last block writes out.
+template <int D>
+__global__ void k_energy(int64_t n_elem, int64_t n_face, int nphi, int npsi, const double* __restrict__ Mref,
+                         const double* __restrict__ ew, const double* __restrict__ flm,
+                         const double* __restrict__ v, const double* __restrict__ sig, double* partials,
+                         double* out, unsigned int* ticket) {
+  constexpr int NS = D * (D + 1) / 2;
+  __shared__ double sh[16];
+  __shared__ bool last;
+  double acc = 0.0;
+  const int64_t nk = n_elem * D;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nk + n_face; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < nk) {
+      const int64_t e = i / D;
+      const double* vb = v + i * nphi;
+      double q = 0.0;
+      for (int k = 0; k < nphi; ++k) {
+        double mv = 0.0;
+        for (int kk = 0; kk < nphi; ++kk) mv += Mref[k * nphi + kk] * vb[kk];
+        q += vb[k] * mv;
+      }
+      acc += 0.5 * ew[e] * q;
+    } else {
+      const int64_t j = i - nk;
+      const double lam = flm[2 * j], mu = flm[2 * j + 1];
+      const double* sb = sig + j * NS * npsi;
+      double q = 0.0;
+      for (int m = 0; m < npsi; ++m) {
+        double s[NS];
+        for (int c = 0; c < NS; ++c) s[c] = sb[c * npsi + m];
+        if (D == 2) {
+          const double den = 4.0 * mu * (lam + mu);
+          const double a = (lam + 2.0 * mu) / den, b = -lam / den;
+          q += a * (s[0] * s[0] + s[1] * s[1]) + 2.0 * b * s[0] * s[1] + s[2] * s[2] / mu;
+        } else {
+          const double alpha = 3.0 * lam + 2.0 * mu;
+          const double f = 1.0 / (2.0 * mu * alpha);
+          const double dg = 2.0 * (lam + mu) * f, off = -lam * f;
+          q += dg * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2]) +
+               2.0 * off * (s[0] * s[1] + s[0] * s[2] + s[1] * s[2]) +
+               (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]) / mu;
+        }
+      }
+      acc += 0.5 * q;
+    }
+  }
+  acc = wsum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+    partials[blockIdx.x * kRedSlots] = s;
+    __threadfence();
+    last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    double s = 0.0;
+    for (unsigned b = 0; b < gridDim.x; ++b) s += partials[b * kRedSlots];
+    *out = s;
+    *ticket = 0u;
+  }
+}
+
+__global__ void k_sample(int64_t n, int nphi, int dim, const int64_t* __restrict__ elem, const double* __restrict__ phi,
+                         const double* __restrict__ v, double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * dim) return;
+  const int64_t pt = t / dim;
+  const int c = (int)(t % dim);
+  const double* vb = v + (elem[pt] * dim + c) * nphi;
+  double acc = 0.0;
+  for (int k = 0; k < nphi; ++k) acc += phi[pt * nphi + k] * vb[k];
+  out[t] = acc;
+}
+
+__global__ void k_eval_stress(int64_t n, int npsi, int nsig, const int64_t* __restrict__ face,
+                              const double* __restrict__ psi, const double* __restrict__ sig, double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nsig) return;
+  const int64_t pt = t / nsig;
+  const int s = (int)(t % nsig);
+  const double* sb = sig + (face[pt] * nsig + s) * npsi;
+  double acc = 0.0;
+  for (int m = 0; m < npsi; ++m) acc += psi[pt * npsi + m] * sb[m];
+  out[t] = acc;
+}
+}  // namespace
+
+void launch_broadcast_time(int64_t n_elem, int ng, int nvs, const double* state, double* slab, hipStream_t s) {
+  k_broadcast<<<grid_for(n_elem * ng * nvs), kT, 0, s>>>(n_elem, ng, nvs, state, slab);
+  SDG_HIP(hipGetLastError());
+}
+
+void launch_end_of_slab(int64_t n_elem, int ng, int nvs, const double* w, const double* slab, double* state,
+                        hipStream_t s) {
+  k_end<<<grid_for(n_elem * nvs), kT, 0, s>>>(n_elem, ng, nvs, w, slab, state);
+  SDG_HIP(hipGetLastError());
+}
+
+void launch_add_sources(Ctx& c, double* b, const double* amp_dev, hipStream_t s) {
+  if (c.n_src == 0) return;
+  const HostSetup& hs = c.hs;
+  const int per = hs.ng * hs.dim * hs.nphi;
+  // quadrature weights of the slab's time nodes (Crank-Nicolson: midpoint, weight 1)
+  k_sources<<<(per + kT - 1) / kT, kT, 0, s>>>(c.n_src, hs.ng, hs.dim, hs.nphi, hs.dt, c.d_tw.p,
+                                              c.d_src_elem.p, c.d_src_phi.p, c.d_src_dir.p, amp_dev, b);
+  SDG_HIP(hipGetLastError());
+}
+
+void launch_energy(Ctx& c, const double* v, const double* sig, double* out_dev, hipStream_t s) {
+  const HostSetup& hs = c.hs;
+  const int64_t n = hs.n_elem * hs.dim + hs.n_face;
+  unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kT - 1) / kT, kRedBlocks));
+  if (hs.dim == 2)
+    k_energy<2><<<g, kT, 0, s>>>(hs.n_elem, hs.n_face, hs.nphi, hs.npsi, c.d_Mref.p, c.d_elem_w.p, c.d_face_lm.p, v,
+                                 sig, c.d_partials.p, out_dev, &c.d_sc.p->ticket[3]);
+  else
+    k_energy<3><<<g, kT, 0, s>>>(hs.n_elem, hs.n_face, hs.nphi, hs.npsi, c.d_Mref.p, c.d_elem_w.p, c.d_face_lm.p, v,
+                                 sig, c.d_partials.p, out_dev, &c.d_sc.p->ticket[3]);
+  SDG_HIP(hipGetLastError());
+}
+
+void launch_sample(int64_t n, int nphi, int dim, const int64_t* elem, const double* phi, const double* v,
+                   double* out, hipStream_t s) {
+  if (n == 0) return;
+  k_sample<<<(unsigned)((n * dim + kT - 1) / kT), kT, 0, s>>>(n, nphi, dim, elem, phi, v, out);
+  SDG_HIP(hipGetLastError());
+}
+
+void launch_eval_stress(int64_t n, int npsi, int nsig, const int64_t* face, const double* psi, const double* sig,
+                        double* out, hipStream_t s) {
+  if (n == 0) return;
+  k_eval_stress<<<(unsigned)((n * nsig + kT - 1) / kT), kT, 0, s>>>(n, npsi, nsig, face, psi, sig, out);
+  SDG_HIP(hipGetLastError());
+}
+
+}  // namespace sdg

@@ -1,0 +1,127 @@
+// Internal declarations shared by the host setup, the HIP kernels and the
+// C-ABI layer of the staggered space-time DG elasticity library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/sdg.h"
+
+namespace sdg {
+
+// ---------------------------------------------------------------- errors
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define SDG_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      throw ::sdg::Error(SDG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline void require(bool ok, int code, const std::string& msg) {
+  if (!ok) throw Error(code, msg);
+}
+
+// ---------------------------------------------------------------- sizes
+
+constexpr int kMaxGamma = 4;   // N_gamma <= 4 (p_gamma <= 3)
+constexpr int kMaxRhs = 64;
+
+inline int n_phi_of(int dim, int p) {
+  return dim == 2 ? (p + 1) * (p + 2) / 2 : (p + 1) * (p + 2) * (p + 3) / 6;
+}
+inline int n_psi_of(int dim, int p) { return dim == 2 ? (p + 1) * (p + 1) : n_phi_of(3, p); }
+inline int n_sig_of(int dim) { return dim * (dim + 1) / 2; }
+
+// Per-face record used by the kernels.  right < 0 marks a free-surface face.
+struct FaceRec {
+  int32_t left, right;
+  int32_t lf, rf;   // local face index of the face in its left/right element
+};
+
+// ---------------------------------------------------------------- host setup products
+
+struct HostSetup {
+  int dim = 0, p = 0, pg = 0, scheme = SDG_SCHEME_STDG;
+  int nphi = 0, npsi = 0, ng = 1, nsig = 0;
+  int64_t n_elem = 0, n_face = 0, n_bface = 0;
+  double dt = 0.0;
+
+  std::vector<FaceRec> faces;           // n_face
+  std::vector<int32_t> elem_face;       // n_elem*(dim+1): face id of local face f
+  std::vector<double> Dt;               // n_face*2*nphi*dim*npsi, canonical dual basis
+  std::vector<double> face_lm;          // n_face*2: lambda_j, mu_j
+  std::vector<double> elem_w;           // n_elem: rho_i |det J_i|
+  std::vector<double> elem_detJ;        // n_elem
+  std::vector<double> elem_rho;         // n_elem
+  std::vector<double> Mref;             // nphi*nphi reference mass matrix
+  // unwrapped element vertices (n_elem*(dim+1)*dim) for point location
+  std::vector<double> elem_xyz;
+  // time basis
+  std::vector<double> tau, w, e0, e1, T;  // T is ng*ng row-major
+};
+
+// Build topology, geometry, bases and blocks.  Throws Error.
+void build_host_setup(HostSetup& hs, int dim, int64_t n_vert, const double* xyz, int64_t n_elem,
+                      const int64_t* elem, const double* period, int p, int pg, int scheme,
+                      double dt, const double* lam, const double* mu, const double* rho);
+
+// Nodal basis values of element e at physical point x (nphi values); returns
+// false if x is not in the closed element (tolerance tol in barycentric units).
+bool eval_velocity_basis(const HostSetup& hs, int64_t e, const double* x, double* phi, double tol);
+int64_t locate_point(const HostSetup& hs, const double* x);
+// Canonical dual basis functions of face j at n points x (n*dim) -> out (n*npsi).
+void eval_dual_canonical(const HostSetup& hs, const int64_t* elem, int64_t j, int64_t n,
+                         const double* x, double* out);
+
+// ---------------------------------------------------------------- kernel interface
+
+// Small coefficient matrices used by the operator kernels (row-major, N_gamma <= 4).
+struct Coefs {
+  double Tm[kMaxGamma * kMaxGamma];  // mass time matrix   [a][b]
+  double Cg[kMaxGamma * kMaxGamma];  // stress-from-gradient time matrix [a][b]
+  double Cs[kMaxGamma];              // stress-from-input-stress vector  [a]
+  double send[kMaxGamma];            // end-of-slab weights gamma_a(1) for the stress output
+};
+
+enum FaceMode : int {
+  kScatter = 0,   // z = D s written to the element slots
+  kWriteStress = 1  // s written out (slab and/or end-of-slab value)
+};
+
+struct OpArgs {
+  int64_t n_face, n_elem;
+  const FaceRec* faces;
+  const void* Dt;          // double or float blocks
+  const double* face_lm;
+  const double* elem_w;
+  const double* v;         // [elem][ng_in][d][nphi] (ng_in = NG, or 1 when v_spatial)
+  const double* sig_in;    // [face][nsig][npsi] or null
+  double* z;               // [elem][d+1][NG][d][nphi]  (kScatter)
+  double* s_out;           // [face][NG][nsig][npsi]    (kWriteStress, optional)
+  double* s_end;           // [face][nsig][npsi]        (kWriteStress, optional)
+  const double* y_add;     // element kernel: optional extra term added to y
+  double* y;               // element kernel output [elem][NG][d][nphi]
+  const double* Mref;      // nphi*nphi (device)
+  int use_g;               // 0: skip the gradient term (Cg == 0)
+  int v_spatial;           // element kernel: v has no time axis (mass applied with Tm[:,0])
+  double y_scale;          // element kernel: y = y_scale * (...) (reserved, 1.0)
+  Coefs c;
+};
+
+// Launch the face kernel and/or the element kernel for (dim, p, NG).
+// prec: SDG_PREC_F64 or SDG_PREC_F32.  Returns false if not compiled in.
+bool launch_face(int dim, int p, int ng, int prec, int mode, const OpArgs& a, hipStream_t s);
+bool launch_elem(int dim, int p, int ng, const OpArgs& a, hipStream_t s);
+bool have_kernels(int dim, int p, int ng);
+
+}  // namespace sdg

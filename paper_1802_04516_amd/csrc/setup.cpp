@@ -1,0 +1,760 @@
+// Host-side setup: topology, geometry, bases, exact quadrature and the
+// operator blocks of the staggered space-time DG scheme (Section 3 and
+// eqs. (MD_2)-(MD_6) of Section 4).  Runs once per mesh / material / dt.
+//
+// Blocks are stored per face and side in the canonical orthonormal dual
+// basis (Gram-Schmidt of the raw dual sequence over the dual element), so
+// the dual mass matrices are the identity and the Schur complement needs no
+// inverse mass:
+//   Dt[j][side][k][l][m] = int_{Gamma_j} phi_k psi_m (n_{i,j})_l
+//                          - int_{T_{i,j}} d_l phi_k psi_m,
+// with the face term dropped on free-surface faces (sigma.n = 0).
+#include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <thread>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "sdg_internal.hpp"
+
+namespace sdg {
+namespace {
+
+// ---------------------------------------------------------------- 1D rules
+
+// Gauss-Legendre nodes/weights on [0,1] by Newton iteration on the
+// three-term recurrence of the Legendre polynomials.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      if (n == 1) { p1 = z; p0 = 1.0; }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
+  }
+  // ascending order
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return x[a] < x[b]; });
+  std::vector<double> xs(n), ws(n);
+  for (int i = 0; i < n; ++i) { xs[i] = x[idx[i]]; ws[i] = w[idx[i]]; }
+  x = xs;
+  w = ws;
+}
+
+// Rule on an affine k-simplex embedded in d-space (k = rows-1), exact for
+// polynomials of total degree <= deg.  Collapsed (Duffy) coordinates with
+// Gauss-Legendre factors and the Jacobian written out:
+//   k=2: xi = u, eta = (1-u) v,                 J = (1-u)
+//   k=3: xi = u, eta = (1-u) v, zeta = (1-u)(1-v) w,  J = (1-u)^2 (1-v)
+struct Rule {
+  std::vector<double> x;  // npts*d
+  std::vector<double> w;
+  int d = 0;
+  int n() const { return (int)w.size(); }
+};
+
+Rule simplex_rule(const double* V, int k, int d, int deg) {
+  Rule r;
+  r.d = d;
+  int n = deg / 2 + 2;  // handles the extra Jacobian degrees
+  std::vector<double> gx, gw;
+  gauss_legendre(n, gx, gw);
+  // measure of the simplex relative to the reference one
+  double J[9] = {0};
+  for (int a = 0; a < k; ++a)
+    for (int c = 0; c < d; ++c) J[c * k + a] = V[(a + 1) * d + c] - V[c];
+  double vol;
+  if (k == d) {
+    if (d == 1) vol = std::fabs(J[0]);
+    else if (d == 2) vol = std::fabs(J[0] * J[3] - J[1] * J[2]);
+    else
+      vol = std::fabs(J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                      J[2] * (J[3] * J[7] - J[4] * J[6]));
+  } else if (k == 1) {
+    double s = 0;
+    for (int c = 0; c < d; ++c) s += J[c * k] * J[c * k];
+    vol = std::sqrt(s);
+  } else {  // k = 2 in 3D: |t1 x t2|
+    double t1[3] = {J[0], J[2], J[4]}, t2[3] = {J[1], J[3], J[5]};
+    double cx = t1[1] * t2[2] - t1[2] * t2[1], cy = t1[2] * t2[0] - t1[0] * t2[2],
+           cz = t1[0] * t2[1] - t1[1] * t2[0];
+    vol = std::sqrt(cx * cx + cy * cy + cz * cz);
+  }
+  auto push = [&](const double* ref, double wt) {
+    for (int c = 0; c < d; ++c) {
+      double s = V[c];
+      for (int a = 0; a < k; ++a) s += J[c * k + a] * ref[a];
+      r.x.push_back(s);
+    }
+    r.w.push_back(wt * vol);
+  };
+  if (k == 1) {
+    for (int i = 0; i < n; ++i) push(&gx[i], gw[i]);
+  } else if (k == 2) {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double ref[2] = {gx[i], (1.0 - gx[i]) * gx[j]};
+        push(ref, gw[i] * gw[j] * (1.0 - gx[i]));
+      }
+  } else {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        for (int l = 0; l < n; ++l) {
+          double u = gx[i], v = gx[j], t = gx[l];
+          double ref[3] = {u, (1.0 - u) * v, (1.0 - u) * (1.0 - v) * t};
+          push(ref, gw[i] * gw[j] * gw[l] * (1.0 - u) * (1.0 - u) * (1.0 - v));
+        }
+  }
+  return r;
+}
+
+// Dynamic parallel loop over [0, n) on the host cores.
+template <class F>
+void parallel_for(int64_t n, F&& fn) {
+  unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  if (n < 256) nt = 1;
+  std::atomic<int64_t> next{0};
+  auto worker = [&]() {
+    const int64_t chunk = 64;
+    for (;;) {
+      int64_t b = next.fetch_add(chunk);
+      if (b >= n) break;
+      int64_t e = std::min(n, b + chunk);
+      for (int64_t i = b; i < e; ++i) fn(i);
+    }
+  };
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nt; ++t) th.emplace_back(worker);
+  worker();
+  for (auto& t : th) t.join();
+}
+
+// ---------------------------------------------------------------- velocity basis
+
+// Equispaced Lagrange basis in Silvester's barycentric product form:
+// phi_alpha = prod_a R_{alpha_a}(lambda_a), R_m(z) = prod_{s<m} (p z - s)/(s+1).
+struct VelBasis {
+  int dim, p, n;
+  std::vector<std::array<int, 4>> alpha;  // barycentric multi-indices, pinned order
+
+  VelBasis(int d, int pp) : dim(d), p(pp) {
+    if (d == 2) {
+      for (int j = 0; j <= p; ++j)
+        for (int i = 0; i <= p - j; ++i) alpha.push_back({p - i - j, i, j, 0});
+    } else {
+      for (int kk = 0; kk <= p; ++kk)
+        for (int j = 0; j <= p - kk; ++j)
+          for (int i = 0; i <= p - kk - j; ++i) alpha.push_back({p - i - j - kk, i, j, kk});
+    }
+    n = (int)alpha.size();
+  }
+
+  static void R(int m, int p, double z, double& val, double& der) {
+    val = 1.0;
+    der = 0.0;
+    for (int s = 0; s < m; ++s) {
+      double f = (p * z - s) / (s + 1.0);
+      double df = p / (s + 1.0);
+      der = der * f + val * df;
+      val *= f;
+    }
+  }
+
+  // values (n) and reference gradients (n*dim, [k][b]) at reference point xi
+  void eval(const double* xi, double* val, double* grad) const {
+    double lam[4];
+    lam[0] = 1.0;
+    for (int b = 0; b < dim; ++b) { lam[b + 1] = xi[b]; lam[0] -= xi[b]; }
+    for (int k = 0; k < n; ++k) {
+      double rv[4], rd[4];
+      for (int a = 0; a <= dim; ++a) R(alpha[k][a], p, lam[a], rv[a], rd[a]);
+      double v = 1.0;
+      for (int a = 0; a <= dim; ++a) v *= rv[a];
+      val[k] = v;
+      if (grad) {
+        // d/dxi_b: lambda_0 decreases, lambda_{b+1} increases
+        for (int b = 0; b < dim; ++b) {
+          double t0 = rd[0], tb = rd[b + 1];
+          for (int a = 0; a <= dim; ++a) {
+            if (a != 0) t0 *= rv[a];
+            if (a != b + 1) tb *= rv[a];
+          }
+          grad[k * dim + b] = tb - t0;
+        }
+      }
+    }
+  }
+};
+
+// ---------------------------------------------------------------- small linear algebra
+
+// Solve A X = B in place (A n x n row-major, B n x m), partial pivoting.
+void solve_dense(std::vector<double> A, std::vector<double>& B, int n, int m) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    require(std::fabs(A[piv * n + c]) > 0.0, SDG_EMESH, "singular matrix in setup");
+    if (piv != c) {
+      for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[piv * n + k]);
+      for (int k = 0; k < m; ++k) std::swap(B[c * m + k], B[piv * m + k]);
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      double f = A[r * n + c] / A[c * n + c];
+      if (f == 0.0) continue;
+      for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+      for (int k = 0; k < m; ++k) B[r * m + k] -= f * B[c * m + k];
+    }
+  }
+  for (int r = 0; r < n; ++r)
+    for (int k = 0; k < m; ++k) B[r * m + k] /= A[r * n + r];
+}
+
+// Lower Cholesky factor of SPD G (n x n), returns L^{-1} (lower triangular).
+std::vector<double> cholesky_inverse(const std::vector<double>& G, int n) {
+  std::vector<double> L(n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = G[i * n + j];
+      for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
+      if (i == j) {
+        require(s > 0.0, SDG_EMESH, "dual Gram matrix not positive definite");
+        L[i * n + i] = std::sqrt(s);
+      } else {
+        L[i * n + j] = s / L[j * n + j];
+      }
+    }
+  std::vector<double> Li(n * n, 0.0);
+  for (int c = 0; c < n; ++c) {  // forward substitution of unit vectors
+    for (int i = 0; i < n; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) s -= L[i * n + k] * Li[k * n + c];
+      Li[i * n + c] = s / L[i * n + i];
+    }
+  }
+  return Li;
+}
+
+double legendre(int n, double x) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) return 1.0;
+  for (int k = 2; k <= n; ++k) {
+    double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = pk;
+  }
+  return p1;
+}
+
+// ---------------------------------------------------------------- dual basis
+
+// Raw dual basis of one face: 2D Legendre products in the quad frame
+// (lexicographic, a major); 3D Legendre products in scaled physical
+// coordinates ordered by total degree, then a, b descending.  Both share the
+// nested spans of the monomial sequences that define the canonical basis.
+struct DualBasis {
+  int dim, p, n;
+  std::vector<std::array<int, 3>> ex;
+  double origin[3];
+  double Ainv[9];  // frame coordinates = Ainv (x - origin)
+  std::vector<double> Linv;  // canonical = Linv * raw
+
+  DualBasis(int d, int pp) : dim(d), p(pp) {
+    if (d == 2) {
+      for (int a = 0; a <= p; ++a)
+        for (int b = 0; b <= p; ++b) ex.push_back({a, b, 0});
+    } else {
+      for (int deg = 0; deg <= p; ++deg)
+        for (int a = deg; a >= 0; --a)
+          for (int b = deg - a; b >= 0; --b) ex.push_back({a, b, deg - a - b});
+    }
+    n = (int)ex.size();
+  }
+
+  void raw(const double* x, double* out) const {
+    double y[3];
+    for (int r = 0; r < dim; ++r) {
+      double s = 0;
+      for (int c = 0; c < dim; ++c) s += Ainv[r * dim + c] * (x[c] - origin[c]);
+      y[r] = s;
+    }
+    if (dim == 2) { y[0] = 2.0 * y[0] - 1.0; y[1] = 2.0 * y[1] - 1.0; }
+    double L[3][8];
+    for (int r = 0; r < dim; ++r)
+      for (int q = 0; q <= p; ++q) L[r][q] = legendre(q, y[r]);
+    for (int m = 0; m < n; ++m) {
+      double v = 1.0;
+      for (int r = 0; r < dim; ++r) v *= L[r][ex[m][r]];
+      out[m] = v;
+    }
+  }
+
+  void canonical(const double* x, double* out) const {
+    double r[64];
+    raw(x, r);
+    for (int i = 0; i < n; ++i) {
+      double s = 0;
+      for (int k = 0; k <= i; ++k) s += Linv[i * n + k] * r[k];
+      out[i] = s;
+    }
+  }
+};
+
+// ---------------------------------------------------------------- helpers
+
+double det_and_inverse(const double* V, int d, double* Jinv) {
+  // J columns = V[a+1]-V[0]; returns det J and J^{-1} (row-major)
+  double J[9];
+  for (int c = 0; c < d; ++c)
+    for (int a = 0; a < d; ++a) J[c * d + a] = V[(a + 1) * d + c] - V[c];
+  if (d == 2) {
+    double det = J[0] * J[3] - J[1] * J[2];
+    Jinv[0] = J[3] / det; Jinv[1] = -J[1] / det;
+    Jinv[2] = -J[2] / det; Jinv[3] = J[0] / det;
+    return det;
+  }
+  double c00 = J[4] * J[8] - J[5] * J[7], c01 = J[5] * J[6] - J[3] * J[8], c02 = J[3] * J[7] - J[4] * J[6];
+  double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+  Jinv[0] = c00 / det; Jinv[1] = (J[2] * J[7] - J[1] * J[8]) / det; Jinv[2] = (J[1] * J[5] - J[2] * J[4]) / det;
+  Jinv[3] = c01 / det; Jinv[4] = (J[0] * J[8] - J[2] * J[6]) / det; Jinv[5] = (J[2] * J[3] - J[0] * J[5]) / det;
+  Jinv[6] = c02 / det; Jinv[7] = (J[1] * J[6] - J[0] * J[7]) / det; Jinv[8] = (J[0] * J[4] - J[1] * J[3]) / det;
+  return det;
+}
+
+// Physical basis values and gradients of an element with vertices V at x.
+void phys_eval(const VelBasis& vb, const double* V, const double* Jinv, const double* x,
+               double* val, double* grad /* n*dim, [k][l] */) {
+  int d = vb.dim;
+  double xi[3];
+  for (int b = 0; b < d; ++b) {
+    double s = 0;
+    for (int c = 0; c < d; ++c) s += Jinv[b * d + c] * (x[c] - V[c]);
+    xi[b] = s;
+  }
+  double gref[64 * 3];
+  vb.eval(xi, val, grad ? gref : nullptr);
+  if (grad)
+    for (int k = 0; k < vb.n; ++k)
+      for (int l = 0; l < d; ++l) {
+        double s = 0;
+        for (int b = 0; b < d; ++b) s += Jinv[b * d + l] * gref[k * d + b];
+        grad[k * d + l] = s;
+      }
+}
+
+// Geometry of face j in the frame of its left element.
+struct FaceGeom {
+  double X[9];            // face vertices, ordered by global vertex index
+  double Vl[12], Vr[12];  // left element, right element translated into the left frame
+  double bl[3], br[3];    // barycentres (br mirrored through the face on the boundary)
+  double nrm[3];          // unit normal from left to right
+  double Tsub[2][12];     // sub-simplices T_{l,j}, T_{r,j}
+};
+
+void face_geometry(const HostSetup& hs, const int64_t* elem, int64_t j, FaceGeom& g) {
+  const int d = hs.dim, nv = d + 1;
+  const FaceRec& fr = hs.faces[j];
+  const double* Vl = &hs.elem_xyz[(int64_t)fr.left * nv * d];
+  for (int a = 0; a < nv * d; ++a) g.Vl[a] = Vl[a];
+  int loc[3];
+  int q = 0;
+  for (int a = 0; a < nv; ++a)
+    if (a != fr.lf) loc[q++] = a;
+  std::sort(loc, loc + d, [&](int a, int b) {
+    return elem[(int64_t)fr.left * nv + a] < elem[(int64_t)fr.left * nv + b];
+  });
+  for (int a = 0; a < d; ++a)
+    for (int c = 0; c < d; ++c) g.X[a * d + c] = Vl[loc[a] * d + c];
+  for (int c = 0; c < d; ++c) { g.bl[c] = 0; g.br[c] = 0; }
+  for (int a = 0; a < nv; ++a)
+    for (int c = 0; c < d; ++c) g.bl[c] += Vl[a * d + c] / nv;
+  const bool interior = fr.right >= 0;
+  if (interior) {
+    const double* Vr0 = &hs.elem_xyz[(int64_t)fr.right * nv * d];
+    int64_t g0 = elem[(int64_t)fr.left * nv + loc[0]];
+    int ar = -1;
+    for (int a = 0; a < nv; ++a)
+      if (elem[(int64_t)fr.right * nv + a] == g0) ar = a;
+    require(ar >= 0, SDG_EMESH, "inconsistent face");
+    double shift[3];
+    for (int c = 0; c < d; ++c) shift[c] = g.X[c] - Vr0[ar * d + c];
+    for (int a = 0; a < nv; ++a)
+      for (int c = 0; c < d; ++c) g.Vr[a * d + c] = Vr0[a * d + c] + shift[c];
+    for (int a = 0; a < d; ++a) {
+      int64_t gv = elem[(int64_t)fr.left * nv + loc[a]];
+      for (int b = 0; b < nv; ++b)
+        if (elem[(int64_t)fr.right * nv + b] == gv)
+          for (int c = 0; c < d; ++c)
+            require(std::fabs(g.Vr[b * d + c] - g.X[a * d + c]) <= 1e-9 * (1.0 + std::fabs(g.X[a * d + c])),
+                    SDG_EMESH, "unmatched periodic face");
+    }
+    for (int a = 0; a < nv; ++a)
+      for (int c = 0; c < d; ++c) g.br[c] += g.Vr[a * d + c] / nv;
+  } else {
+    for (int c = 0; c < d; ++c) {
+      double mid = 0;
+      for (int a = 0; a < d; ++a) mid += g.X[a * d + c] / d;
+      g.br[c] = 2.0 * mid - g.bl[c];
+    }
+  }
+  if (d == 2) {
+    double t0 = g.X[2] - g.X[0], t1 = g.X[3] - g.X[1];
+    g.nrm[0] = t1; g.nrm[1] = -t0;
+  } else {
+    double t1[3] = {g.X[3] - g.X[0], g.X[4] - g.X[1], g.X[5] - g.X[2]};
+    double t2[3] = {g.X[6] - g.X[0], g.X[7] - g.X[1], g.X[8] - g.X[2]};
+    g.nrm[0] = t1[1] * t2[2] - t1[2] * t2[1];
+    g.nrm[1] = t1[2] * t2[0] - t1[0] * t2[2];
+    g.nrm[2] = t1[0] * t2[1] - t1[1] * t2[0];
+  }
+  double s = 0, dot = 0;
+  for (int c = 0; c < d; ++c) s += g.nrm[c] * g.nrm[c];
+  s = std::sqrt(s);
+  for (int c = 0; c < d; ++c) {
+    g.nrm[c] /= s;
+    double fc = 0;
+    for (int a = 0; a < d; ++a) fc += g.X[a * d + c] / d;
+    dot += g.nrm[c] * (fc - g.bl[c]);
+  }
+  if (dot < 0)
+    for (int c = 0; c < d; ++c) g.nrm[c] = -g.nrm[c];
+  for (int sd = 0; sd < 2; ++sd) {
+    for (int a = 0; a < d; ++a)
+      for (int c = 0; c < d; ++c) g.Tsub[sd][a * d + c] = g.X[a * d + c];
+    for (int c = 0; c < d; ++c) g.Tsub[sd][d * d + c] = sd == 0 ? g.bl[c] : g.br[c];
+  }
+}
+
+// Frame, Gram matrix and canonical orthonormalisation of the dual basis of
+// one face; vol receives |T_{l,j}| and |T_{r,j}| (0 on the boundary).
+void build_dual(const HostSetup& hs, int64_t j, const FaceGeom& g, DualBasis& db, double* vol) {
+  const int d = hs.dim, npsi = hs.npsi;
+  const int psi_deg = (d == 2) ? 2 * hs.p : hs.p;
+  const bool interior = hs.faces[j].right >= 0;
+  if (d == 2) {
+    double d1[2] = {g.X[2] - g.X[0], g.X[3] - g.X[1]};
+    double d2[2] = {g.br[0] - g.bl[0], g.br[1] - g.bl[1]};
+    double e1[2] = {0.5 * (d1[0] - d2[0]), 0.5 * (d1[1] - d2[1])};
+    double e2[2] = {0.5 * (d1[0] + d2[0]), 0.5 * (d1[1] + d2[1])};
+    double det = e1[0] * e2[1] - e2[0] * e1[1];
+    db.origin[0] = g.X[0];
+    db.origin[1] = g.X[1];
+    db.Ainv[0] = e2[1] / det; db.Ainv[1] = -e2[0] / det;
+    db.Ainv[2] = -e1[1] / det; db.Ainv[3] = e1[0] / det;
+  } else {
+    double c[3] = {0, 0, 0};
+    int cnt = 0;
+    for (int a = 0; a < 3; ++a, ++cnt)
+      for (int k = 0; k < 3; ++k) c[k] += g.X[a * 3 + k];
+    for (int k = 0; k < 3; ++k) c[k] += g.bl[k];
+    ++cnt;
+    if (interior) { for (int k = 0; k < 3; ++k) c[k] += g.br[k]; ++cnt; }
+    for (int k = 0; k < 3; ++k) c[k] /= cnt;
+    double h = 0;
+    for (int a = 0; a < 3; ++a) {
+      double sq = 0;
+      for (int k = 0; k < 3; ++k) sq += (g.X[a * 3 + k] - c[k]) * (g.X[a * 3 + k] - c[k]);
+      h = std::max(h, std::sqrt(sq));
+    }
+    for (int k = 0; k < 3; ++k) db.origin[k] = c[k];
+    for (int k = 0; k < 9; ++k) db.Ainv[k] = (k % 4 == 0) ? 1.0 / h : 0.0;
+  }
+  std::vector<double> G(npsi * npsi, 0.0), raw(npsi);
+  vol[0] = vol[1] = 0.0;
+  for (int s = 0; s < (interior ? 2 : 1); ++s) {
+    Rule r = simplex_rule(g.Tsub[s], d, d, 2 * psi_deg);
+    for (int q = 0; q < r.n(); ++q) {
+      db.raw(&r.x[q * d], raw.data());
+      vol[s] += r.w[q];
+      for (int a = 0; a < npsi; ++a)
+        for (int b = 0; b <= a; ++b) G[a * npsi + b] += r.w[q] * raw[a] * raw[b];
+    }
+  }
+  for (int a = 0; a < npsi; ++a)
+    for (int b = a + 1; b < npsi; ++b) G[a * npsi + b] = G[b * npsi + a];
+  db.Linv = cholesky_inverse(G, npsi);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- main builder
+
+void build_host_setup(HostSetup& hs, int dim, int64_t n_vert, const double* xyz, int64_t n_elem,
+                      const int64_t* elem, const double* period, int p, int pg, int scheme,
+                      double dt, const double* lam, const double* mu, const double* rho) {
+  require(dim == 2 || dim == 3, SDG_EINVAL, "dim must be 2 or 3");
+  require(n_elem > 0 && n_vert > 0, SDG_EINVAL, "empty mesh");
+  const int d = dim, nv = dim + 1;
+  hs.dim = d;
+  hs.p = p;
+  hs.pg = pg;
+  hs.scheme = scheme;
+  hs.nphi = n_phi_of(d, p);
+  hs.npsi = n_psi_of(d, p);
+  hs.nsig = n_sig_of(d);
+  hs.ng = pg + 1;
+  hs.dt = dt;
+  hs.n_elem = n_elem;
+
+  // --- unwrapped element vertices
+  hs.elem_xyz.assign(n_elem * nv * d, 0.0);
+  for (int64_t e = 0; e < n_elem; ++e) {
+    for (int a = 0; a < nv; ++a) {
+      int64_t g = elem[e * nv + a];
+      require(g >= 0 && g < n_vert, SDG_EMESH, "vertex index out of range");
+      for (int c = 0; c < d; ++c) {
+        double x = xyz[g * d + c];
+        if (period && a > 0) {
+          double x0 = hs.elem_xyz[(e * nv) * d + c];
+          x += period[c] * std::nearbyint((x0 - x) / period[c]);
+        }
+        hs.elem_xyz[(e * nv + a) * d + c] = x;
+      }
+    }
+  }
+  hs.elem_detJ.assign(n_elem, 0.0);
+  std::vector<double> Jinv_all(n_elem * d * d);
+  for (int64_t e = 0; e < n_elem; ++e) {
+    const double* V = &hs.elem_xyz[e * nv * d];
+    double det = det_and_inverse(V, d, &Jinv_all[e * d * d]);
+    double scale = 0;
+    for (int a = 1; a < nv; ++a)
+      for (int c = 0; c < d; ++c) scale = std::max(scale, std::fabs(V[a * d + c] - V[c]));
+    require(std::isfinite(det) && std::fabs(det) > 1e-12 * std::pow(scale, d), SDG_EMESH,
+            "degenerate element " + std::to_string(e));
+    hs.elem_detJ[e] = std::fabs(det);
+  }
+
+  // --- faces: sort (sorted vertex key, elem, local face)
+  struct Ent { int64_t k[3]; int64_t e; int f; };
+  std::vector<Ent> ents;
+  ents.reserve(n_elem * nv);
+  for (int64_t e = 0; e < n_elem; ++e)
+    for (int f = 0; f < nv; ++f) {
+      Ent t{{-1, -1, -1}, e, f};
+      int q = 0;
+      for (int a = 0; a < nv; ++a)
+        if (a != f) t.k[q++] = elem[e * nv + a];
+      std::sort(t.k, t.k + d);
+      ents.push_back(t);
+    }
+  std::sort(ents.begin(), ents.end(), [&](const Ent& a, const Ent& b) {
+    for (int q = 0; q < 3; ++q)
+      if (a.k[q] != b.k[q]) return a.k[q] < b.k[q];
+    return a.e < b.e;
+  });
+  hs.faces.clear();
+  for (size_t i = 0; i < ents.size();) {
+    size_t j = i + 1;
+    while (j < ents.size() && std::equal(ents[i].k, ents[i].k + 3, ents[j].k)) ++j;
+    require(j - i <= 2, SDG_EMESH, "face shared by more than two elements");
+    FaceRec r;
+    r.left = (int32_t)ents[i].e;
+    r.lf = ents[i].f;
+    if (j - i == 2) {
+      require(ents[i + 1].e != ents[i].e, SDG_EMESH, "element shares a face with itself");
+      r.right = (int32_t)ents[i + 1].e;
+      r.rf = ents[i + 1].f;
+    } else {
+      r.right = -1;
+      r.rf = -1;
+    }
+    hs.faces.push_back(r);
+    i = j;
+  }
+  std::sort(hs.faces.begin(), hs.faces.end(), [](const FaceRec& a, const FaceRec& b) {
+    return a.left != b.left ? a.left < b.left : a.lf < b.lf;
+  });
+  const int64_t nf = (int64_t)hs.faces.size();
+  hs.n_face = nf;
+  hs.n_bface = 0;
+  hs.elem_face.assign(n_elem * nv, -1);
+  for (int64_t j = 0; j < nf; ++j) {
+    const FaceRec& r = hs.faces[j];
+    hs.elem_face[(int64_t)r.left * nv + r.lf] = (int32_t)j;
+    if (r.right >= 0) hs.elem_face[(int64_t)r.right * nv + r.rf] = (int32_t)j;
+    else ++hs.n_bface;
+  }
+
+  // --- material and reference mass
+  hs.elem_rho.assign(rho, rho + n_elem);
+  hs.elem_w.resize(n_elem);
+  for (int64_t e = 0; e < n_elem; ++e) {
+    require(rho[e] > 0 && lam[e] >= 0 && mu[e] > 0, SDG_EINVAL, "material must be positive");
+    hs.elem_w[e] = rho[e] * hs.elem_detJ[e];
+  }
+  VelBasis vb(d, p);
+  {
+    std::vector<double> Vref(nv * d, 0.0);
+    for (int a = 0; a < d; ++a) Vref[(a + 1) * d + a] = 1.0;
+    Rule r = simplex_rule(Vref.data(), d, d, 2 * p);
+    hs.Mref.assign(hs.nphi * hs.nphi, 0.0);
+    std::vector<double> val(hs.nphi);
+    for (int q = 0; q < r.n(); ++q) {
+      vb.eval(&r.x[q * d], val.data(), nullptr);
+      for (int k = 0; k < hs.nphi; ++k)
+        for (int m = 0; m < hs.nphi; ++m) hs.Mref[k * hs.nphi + m] += r.w[q] * val[k] * val[m];
+    }
+  }
+
+  // --- time basis: Lagrange through the Gauss-Legendre points of [0,1]
+  {
+    const int ng = hs.ng;
+    gauss_legendre(ng, hs.tau, hs.w);
+    auto lag = [&](int a, double t, double* dval) {
+      double v = 1.0, dv = 0.0;
+      for (int b = 0; b < ng; ++b) {
+        if (b == a) continue;
+        double f = (t - hs.tau[b]) / (hs.tau[a] - hs.tau[b]);
+        dv = dv * f + v / (hs.tau[a] - hs.tau[b]);
+        v *= f;
+      }
+      if (dval) *dval = dv;
+      return v;
+    };
+    hs.e0.resize(ng);
+    hs.e1.resize(ng);
+    for (int a = 0; a < ng; ++a) { hs.e0[a] = lag(a, 0.0, nullptr); hs.e1[a] = lag(a, 1.0, nullptr); }
+    std::vector<double> qx, qw;
+    gauss_legendre(ng + 1, qx, qw);
+    hs.T.assign(ng * ng, 0.0);
+    for (int a = 0; a < ng; ++a)
+      for (int b = 0; b < ng; ++b) {
+        double s = hs.e1[a] * hs.e1[b];
+        for (int q = 0; q < (int)qx.size(); ++q) {
+          double da;
+          lag(a, qx[q], &da);
+          s -= qw[q] * da * lag(b, qx[q], nullptr);
+        }
+        hs.T[a * ng + b] = s;
+      }
+  }
+
+  // --- per-face blocks
+  const int nphi = hs.nphi, npsi = hs.npsi;
+  const int blk = nphi * d * npsi;
+  hs.Dt.assign((size_t)nf * 2 * blk, 0.0);
+  hs.face_lm.assign(nf * 2, 0.0);
+  const int psi_deg = (d == 2) ? 2 * p : p;
+  int err_code = 0;
+  std::string err_msg;
+
+  std::mutex err_mu;
+  parallel_for(nf, [&](int64_t j) {
+    std::vector<double> phi(nphi), gphi(nphi * d), psi(npsi);
+      try {
+        FaceGeom fg;
+        face_geometry(hs, elem, j, fg);
+        DualBasis db(d, p);
+        double vol[2];
+        build_dual(hs, j, fg, db, vol);
+        const FaceRec& fr = hs.faces[j];
+        const bool interior = fr.right >= 0;
+        const int nsides = interior ? 2 : 1;
+        for (int s = 0; s < nsides; ++s) {
+          const double* Ve = s == 0 ? fg.Vl : fg.Vr;
+          double Jinv[9];
+          det_and_inverse(Ve, d, Jinv);
+          double* out = &hs.Dt[((size_t)j * 2 + s) * blk];
+          Rule r = simplex_rule(fg.Tsub[s], d, d, std::max(p - 1, 0) + psi_deg);
+          for (int qq = 0; qq < r.n(); ++qq) {
+            const double* x = &r.x[qq * d];
+            phys_eval(vb, Ve, Jinv, x, phi.data(), gphi.data());
+            db.canonical(x, psi.data());
+            for (int k = 0; k < nphi; ++k)
+              for (int l = 0; l < d; ++l) {
+                double f = -r.w[qq] * gphi[k * d + l];
+                double* o = out + (k * d + l) * npsi;
+                for (int m = 0; m < npsi; ++m) o[m] += f * psi[m];
+              }
+          }
+          if (interior) {
+            double sgn = s == 0 ? 1.0 : -1.0;
+            Rule rf = simplex_rule(fg.X, d - 1, d, p + psi_deg);
+            for (int qq = 0; qq < rf.n(); ++qq) {
+              const double* x = &rf.x[qq * d];
+              phys_eval(vb, Ve, Jinv, x, phi.data(), nullptr);
+              db.canonical(x, psi.data());
+              for (int k = 0; k < nphi; ++k)
+                for (int l = 0; l < d; ++l) {
+                  double f = rf.w[qq] * phi[k] * sgn * fg.nrm[l];
+                  double* o = out + (k * d + l) * npsi;
+                  for (int m = 0; m < npsi; ++m) o[m] += f * psi[m];
+                }
+            }
+          }
+        }
+        // dual material: volume-weighted Lame parameters
+        if (interior) {
+          double vt = vol[0] + vol[1];
+          hs.face_lm[2 * j] = (vol[0] * lam[fr.left] + vol[1] * lam[fr.right]) / vt;
+          hs.face_lm[2 * j + 1] = (vol[0] * mu[fr.left] + vol[1] * mu[fr.right]) / vt;
+        } else {
+          hs.face_lm[2 * j] = lam[fr.left];
+          hs.face_lm[2 * j + 1] = mu[fr.left];
+        }
+      } catch (const Error& e) {
+        std::lock_guard<std::mutex> lk(err_mu);
+        if (!err_code) { err_code = e.code; err_msg = e.what(); }
+      }
+  });
+  if (err_code) throw Error(err_code, err_msg);
+}
+
+bool eval_velocity_basis(const HostSetup& hs, int64_t e, const double* x, double* phi, double tol) {
+  const int d = hs.dim, nv = d + 1;
+  const double* V = &hs.elem_xyz[e * nv * d];
+  double Jinv[9];
+  det_and_inverse(V, d, Jinv);
+  double xi[3], lam0 = 1.0;
+  for (int b = 0; b < d; ++b) {
+    double s = 0;
+    for (int c = 0; c < d; ++c) s += Jinv[b * d + c] * (x[c] - V[c]);
+    xi[b] = s;
+    lam0 -= s;
+    if (s < -tol) return false;
+  }
+  if (lam0 < -tol) return false;
+  if (phi) {
+    VelBasis vb(d, hs.p);
+    vb.eval(xi, phi, nullptr);
+  }
+  return true;
+}
+
+int64_t locate_point(const HostSetup& hs, const double* x) {
+  for (int64_t e = 0; e < hs.n_elem; ++e)
+    if (eval_velocity_basis(hs, e, x, nullptr, 1e-12)) return e;
+  return -1;
+}
+
+void eval_dual_canonical(const HostSetup& hs, const int64_t* elem, int64_t j, int64_t n,
+                         const double* x, double* out) {
+  FaceGeom fg;
+  face_geometry(hs, elem, j, fg);
+  DualBasis db(hs.dim, hs.p);
+  double vol[2];
+  build_dual(hs, j, fg, db, vol);
+  for (int64_t q = 0; q < n; ++q) db.canonical(x + q * hs.dim, out + q * hs.npsi);
+}
+
+}  // namespace sdg

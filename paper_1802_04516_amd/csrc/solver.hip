@@ -1,0 +1,454 @@
+// Krylov solvers and vector kernels for the velocity system (Section 4:
+// conjugate gradients for the symmetric positive definite Crank-Nicolson
+// system, matrix-free restarted GMRES for p_gamma > 0).
+//
+// All reductions are deterministic: each block writes a partial sum, and the
+// last block to finish (ticket counter) adds the partials in block order.
+// Scalars (alpha, beta, Hessenberg column, Givens rotations) stay in device
+// memory; the host reads one residual estimate every `check_every`
+// iterations.
+#include <cmath>
+#include <cstring>
+
+#include "context.hpp"
+
+namespace sdg {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline double warp_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Sum of `v` over the block; result valid in thread 0.
+__device__ inline double block_sum(double v, double* sh) {
+  v = warp_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+
+// Returns true in thread 0 of the last block to arrive.
+__device__ inline bool last_block(unsigned int* ticket) {
+  __shared__ bool am_last;
+  __threadfence();
+  if (threadIdx.x == 0) {
+    unsigned int t = atomicAdd(ticket, 1u);
+    am_last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  return am_last;
+}
+
+// Finish a reduction in the last block: out[slot] = sum_b partials[b][slot].
+__device__ inline void finish_sums(const double* partials, int nslots, double* out, unsigned int* ticket) {
+  __threadfence();
+  for (int sl = threadIdx.x; sl < nslots; sl += blockDim.x) {
+    double s = 0.0;
+    for (unsigned b = 0; b < gridDim.x; ++b) s += partials[(size_t)b * kRedSlots + sl];
+    out[sl] = s;
+  }
+  if (threadIdx.x == 0) *ticket = 0u;
+}
+
+unsigned red_grid(int64_t n) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, kRedBlocks));
+}
+
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
+}
+
+__global__ void k_fill(int64_t n, double v, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+
+__global__ void k_copy(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = x[i];
+}
+
+// out = x . y
+__global__ void k_dot(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                      double* partials, double* out, unsigned int* ticket) {
+  __shared__ double sh[16];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc += x[i] * y[i];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kRedSlots] = acc;
+  if (last_block(ticket)) finish_sums(partials, 1, out, ticket);
+}
+
+// ---------------------------------------------------------------- CG
+
+// x += alpha p, r -= alpha q, rr_new = r.r, with alpha = rr / pq; last block
+// sets beta = rr_new / rr and rr = rr_new.
+__global__ void k_cg_update(int64_t n, double* __restrict__ x, double* __restrict__ r,
+                            const double* __restrict__ p, const double* __restrict__ q,
+                            DevScalars* sc, double* partials) {
+  __shared__ double sh[16];
+  const double alpha = sc->rr / sc->pq;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kRedSlots] = acc;
+  if (last_block(&sc->ticket[0])) {
+    __threadfence();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (unsigned b = 0; b < gridDim.x; ++b) s += partials[(size_t)b * kRedSlots];
+      sc->alpha = alpha;
+      sc->beta = s / sc->rr;
+      sc->rr = s;
+      sc->ticket[0] = 0u;
+    }
+  }
+}
+
+__global__ void k_cg_p(int64_t n, double* __restrict__ p, const double* __restrict__ r, const DevScalars* sc) {
+  const double beta = sc->beta;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = r[i] + beta * p[i];
+}
+
+// ---------------------------------------------------------------- GMRES
+
+// h1[i] = V_i . w for i <= j (classical Gram-Schmidt projections)
+template <int MAXJ>
+__global__ void k_multidot(int64_t n, int nj, const double* __restrict__ V, const double* __restrict__ w,
+                           DevScalars* sc, double* partials) {
+  __shared__ double sh[16];
+  double acc[MAXJ];
+#pragma unroll
+  for (int i = 0; i < MAXJ; ++i) acc[i] = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const double wt = w[t];
+#pragma unroll
+    for (int i = 0; i < MAXJ; ++i)
+      if (i < nj) acc[i] += V[(size_t)i * n + t] * wt;
+  }
+#pragma unroll
+  for (int i = 0; i < MAXJ; ++i) {
+    if (i < nj) {
+      double s = block_sum(acc[i], sh);
+      if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kRedSlots + i] = s;
+    }
+  }
+  if (last_block(&sc->ticket[1])) finish_sums(partials, nj, sc->h1, &sc->ticket[1]);
+}
+
+// w -= V h1, then h2[i] = V_i . w (second Gram-Schmidt pass)
+template <int MAXJ>
+__global__ void k_cgs_pass(int64_t n, int nj, const double* __restrict__ V, double* __restrict__ w,
+                           DevScalars* sc, double* partials) {
+  __shared__ double sh[16];
+  __shared__ double hs[MAXJ];
+  if (threadIdx.x < nj) hs[threadIdx.x] = sc->h1[threadIdx.x];
+  __syncthreads();
+  double acc[MAXJ];
+#pragma unroll
+  for (int i = 0; i < MAXJ; ++i) acc[i] = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double vi[MAXJ];
+    double wt = w[t];
+#pragma unroll
+    for (int i = 0; i < MAXJ; ++i)
+      if (i < nj) { vi[i] = V[(size_t)i * n + t]; wt -= hs[i] * vi[i]; }
+    w[t] = wt;
+#pragma unroll
+    for (int i = 0; i < MAXJ; ++i)
+      if (i < nj) acc[i] += vi[i] * wt;
+  }
+#pragma unroll
+  for (int i = 0; i < MAXJ; ++i) {
+    if (i < nj) {
+      double s = block_sum(acc[i], sh);
+      if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kRedSlots + i] = s;
+    }
+  }
+  if (last_block(&sc->ticket[1])) finish_sums(partials, nj, sc->h2, &sc->ticket[1]);
+}
+
+// w -= V h2, norm^2 = w.w; the last block completes the Hessenberg column j,
+// applies the previous Givens rotations, forms the new one and updates g.
+template <int MAXJ>
+__global__ void k_cgs_final(int64_t n, int nj, const double* __restrict__ V, double* __restrict__ w,
+                            DevScalars* sc, double* partials) {
+  __shared__ double sh[16];
+  __shared__ double hs[MAXJ];
+  if (threadIdx.x < nj) hs[threadIdx.x] = sc->h2[threadIdx.x];
+  __syncthreads();
+  double acc = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double wt = w[t];
+#pragma unroll
+    for (int i = 0; i < MAXJ; ++i)
+      if (i < nj) wt -= hs[i] * V[(size_t)i * n + t];
+    w[t] = wt;
+    acc += wt * wt;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kRedSlots] = acc;
+  if (last_block(&sc->ticket[2])) {
+    __threadfence();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (unsigned b = 0; b < gridDim.x; ++b) s += partials[(size_t)b * kRedSlots];
+      const int j = nj - 1;
+      const int ld = kMaxRestart + 1;
+      double* Hc = sc->H + (size_t)j * ld;
+      for (int i = 0; i < nj; ++i) Hc[i] = sc->h1[i] + sc->h2[i];
+      const double nrm = sqrt(s);
+      Hc[j + 1] = nrm;
+      sc->norm = nrm;
+      sc->inv_norm = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      for (int i = 0; i < j; ++i) {
+        const double a = Hc[i], b = Hc[i + 1];
+        Hc[i] = sc->cs[i] * a + sc->sn[i] * b;
+        Hc[i + 1] = -sc->sn[i] * a + sc->cs[i] * b;
+      }
+      const double a = Hc[j], b = Hc[j + 1];
+      const double rad = hypot(a, b);
+      const double c = rad > 0.0 ? a / rad : 1.0, sn = rad > 0.0 ? b / rad : 0.0;
+      sc->cs[j] = c;
+      sc->sn[j] = sn;
+      Hc[j] = rad;
+      Hc[j + 1] = 0.0;
+      const double gj = sc->g[j];
+      sc->g[j] = c * gj;
+      sc->g[j + 1] = -sn * gj;
+      sc->resid = fabs(sc->g[j + 1]);
+      sc->ticket[2] = 0u;
+    }
+  }
+}
+
+__global__ void k_scale_into(int64_t n, const double* __restrict__ w, double* __restrict__ v, const double* scale) {
+  const double s = *scale;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = w[i] * s;
+}
+
+// Start of a cycle: g = (beta, 0, ...), V_0 = r / beta.
+__global__ void k_gmres_start(DevScalars* sc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double beta = sqrt(sc->dots[0]);
+    for (int i = 0; i <= kMaxRestart; ++i) sc->g[i] = 0.0;
+    sc->g[0] = beta;
+    sc->norm = beta;
+    sc->inv_norm = beta > 0.0 ? 1.0 / beta : 0.0;
+    sc->resid = beta;
+  }
+}
+
+// Back substitution R y = g for the leading k x k triangle.
+__global__ void k_gmres_trisolve(DevScalars* sc, int k) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int ld = kMaxRestart + 1;
+    for (int i = k - 1; i >= 0; --i) {
+      double s = sc->g[i];
+      for (int l = i + 1; l < k; ++l) s -= sc->H[(size_t)l * ld + i] * sc->y[l];
+      const double d = sc->H[(size_t)i * ld + i];
+      sc->y[i] = d != 0.0 ? s / d : 0.0;
+    }
+  }
+}
+
+// x += sum_i y_i V_i
+template <int MAXJ>
+__global__ void k_gmres_update(int64_t n, int k, const double* __restrict__ V, double* __restrict__ x,
+                               const DevScalars* sc) {
+  __shared__ double ys[MAXJ];
+  if (threadIdx.x < k) ys[threadIdx.x] = sc->y[threadIdx.x];
+  __syncthreads();
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double acc = x[t];
+#pragma unroll
+    for (int i = 0; i < MAXJ; ++i)
+      if (i < k) acc += ys[i] * V[(size_t)i * n + t];
+    x[t] = acc;
+  }
+}
+
+unsigned vgrid(int64_t n) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
+}
+
+void check_launch() { SDG_HIP(hipGetLastError()); }
+
+double read_scalar(Ctx& c, const double* dev, hipStream_t s) {
+  SDG_HIP(hipMemcpyAsync(c.h_pinned, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  SDG_HIP(hipStreamSynchronize(s));
+  return c.h_pinned[0];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- public helpers
+
+void vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
+  k_axpby<<<vgrid(n), kThreads, 0, s>>>(n, a, x, b, y);
+  check_launch();
+}
+
+void vec_fill(int64_t n, double value, double* y, hipStream_t s) {
+  k_fill<<<vgrid(n), kThreads, 0, s>>>(n, value, y);
+  check_launch();
+}
+
+void vec_copy(int64_t n, const double* x, double* y, hipStream_t s) {
+  k_copy<<<vgrid(n), kThreads, 0, s>>>(n, x, y);
+  check_launch();
+}
+
+static void dev_dot(Ctx& c, int64_t n, const double* x, const double* y, double* out, hipStream_t s) {
+  k_dot<<<red_grid(n), kThreads, 0, s>>>(n, x, y, c.d_partials.p, out, &c.d_sc.p->ticket[3]);
+  check_launch();
+}
+
+double vec_dot_host(Ctx& c, int64_t n, const double* x, const double* y, hipStream_t s) {
+  dev_dot(c, n, x, y, &c.d_sc.p->dots[0], s);
+  return read_scalar(c, &c.d_sc.p->dots[0], s);
+}
+
+// ---------------------------------------------------------------- CG
+
+SolveResult solve_cg(Ctx& c, const double* b, double* x, double rtol, int max_iter, int check_every,
+                     int prec, hipStream_t s) {
+  SolveResult res;
+  const int64_t n = c.n_slab;
+  double* r = c.d_r.p;
+  double* pv = c.d_w.p;
+  double* q = c.d_t.p;
+  DevScalars* sc = c.d_sc.p;
+  res.bnorm = std::sqrt(vec_dot_host(c, n, b, b, s));
+  if (res.bnorm == 0.0) {
+    vec_fill(n, 0.0, x, s);
+    res.converged = true;
+    return res;
+  }
+  require(std::isfinite(res.bnorm), SDG_ENONFINITE, "non-finite right-hand side");
+  // r = b - A x
+  apply_op(c, x, q, prec, false, s);
+  ++res.matvecs;
+  vec_copy(n, b, r, s);
+  vec_axpby(n, -1.0, q, 1.0, r, s);
+  vec_copy(n, r, pv, s);
+  dev_dot(c, n, r, r, &sc->rr, s);
+  check_every = std::max(1, check_every);
+  double rr = read_scalar(c, &sc->rr, s);
+  require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
+  if (std::sqrt(rr) <= rtol * res.bnorm) { res.converged = true; res.rel_res = std::sqrt(rr) / res.bnorm; return res; }
+  for (int it = 0; it < max_iter; ++it) {
+    apply_op(c, pv, q, prec, false, s);
+    ++res.matvecs;
+    dev_dot(c, n, pv, q, &sc->pq, s);
+    k_cg_update<<<red_grid(n), kThreads, 0, s>>>(n, x, r, pv, q, sc, c.d_partials.p);
+    check_launch();
+    k_cg_p<<<vgrid(n), kThreads, 0, s>>>(n, pv, r, sc);
+    check_launch();
+    ++res.iters;
+    if ((it + 1) % check_every == 0 || it + 1 == max_iter) {
+      rr = read_scalar(c, &sc->rr, s);
+      require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
+      if (std::sqrt(rr) <= rtol * res.bnorm) break;
+    }
+  }
+  // true residual
+  apply_op(c, x, q, prec, false, s);
+  ++res.matvecs;
+  vec_copy(n, b, r, s);
+  vec_axpby(n, -1.0, q, 1.0, r, s);
+  double tr = vec_dot_host(c, n, r, r, s);
+  require(std::isfinite(tr), SDG_ENONFINITE, "non-finite residual");
+  res.rel_res = std::sqrt(tr) / res.bnorm;
+  res.converged = res.rel_res <= rtol * 1.0000001 || std::sqrt(rr) <= rtol * res.bnorm;
+  return res;
+}
+
+// ---------------------------------------------------------------- GMRES
+
+SolveResult solve_gmres(Ctx& c, const double* b, double* x, double rtol, int max_iter, int restart,
+                        int check_every, int prec, hipStream_t s) {
+  SolveResult res;
+  const int64_t n = c.n_slab;
+  const int m = std::max(1, std::min(restart, kMaxRestart));
+  double* V = c.d_V.p;
+  double* r = c.d_r.p;
+  double* w = c.d_w.p;
+  DevScalars* sc = c.d_sc.p;
+  check_every = std::max(1, check_every);
+  res.bnorm = std::sqrt(vec_dot_host(c, n, b, b, s));
+  require(std::isfinite(res.bnorm), SDG_ENONFINITE, "non-finite right-hand side");
+  if (res.bnorm == 0.0) {
+    vec_fill(n, 0.0, x, s);
+    res.converged = true;
+    return res;
+  }
+  const unsigned rg = red_grid(n), vg = vgrid(n);
+  int total = 0;
+  for (;;) {
+    // r = b - A x, beta = ||r||
+    apply_op(c, x, r, prec, false, s);
+    ++res.matvecs;
+    vec_axpby(n, 1.0, b, -1.0, r, s);
+    dev_dot(c, n, r, r, &sc->dots[0], s);
+    double rr = read_scalar(c, &sc->dots[0], s);
+    require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
+    res.rel_res = std::sqrt(rr) / res.bnorm;
+    if (res.rel_res <= rtol) { res.converged = true; break; }
+    if (total >= max_iter) break;
+    k_gmres_start<<<1, 64, 0, s>>>(sc);
+    check_launch();
+    k_scale_into<<<vg, kThreads, 0, s>>>(n, r, V, &sc->inv_norm);
+    check_launch();
+    int k = 0;
+    for (int j = 0; j < m && total < max_iter; ++j) {
+      double* vj = V + (size_t)j * n;
+      apply_op(c, vj, w, prec, false, s);
+      ++res.matvecs;
+      k_multidot<kMaxRestart><<<rg, kThreads, 0, s>>>(n, j + 1, V, w, sc, c.d_partials.p);
+      check_launch();
+      k_cgs_pass<kMaxRestart><<<rg, kThreads, 0, s>>>(n, j + 1, V, w, sc, c.d_partials.p);
+      check_launch();
+      k_cgs_final<kMaxRestart><<<rg, kThreads, 0, s>>>(n, j + 1, V, w, sc, c.d_partials.p);
+      check_launch();
+      k_scale_into<<<vg, kThreads, 0, s>>>(n, w, V + (size_t)(j + 1) * n, &sc->inv_norm);
+      check_launch();
+      ++total;
+      ++res.iters;
+      k = j + 1;
+      if ((j + 1) % check_every == 0 || j + 1 == m) {
+        double est = read_scalar(c, &sc->resid, s);
+        require(std::isfinite(est), SDG_ENONFINITE, "non-finite residual estimate");
+        if (est <= rtol * res.bnorm) break;
+      }
+    }
+    k_gmres_trisolve<<<1, 64, 0, s>>>(sc, k);
+    check_launch();
+    k_gmres_update<kMaxRestart><<<vg, kThreads, 0, s>>>(n, k, V, x, sc);
+    check_launch();
+  }
+  return res;
+}
+
+}  // namespace sdg

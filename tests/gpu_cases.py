@@ -1,0 +1,48 @@
+"""Shared set-up for the GPU parity tests: the same seeded inputs are given
+to the HIP library and to the FP64 oracle."""
+import numpy as np
+
+import synth
+from oracle.assemble import Blocks
+from oracle.mesh import Topology
+from oracle.slab import Slab
+
+CASES = {
+    # name: (mesh builder, p, p_gamma, scheme, dt, material)
+    "c1": (lambda: synth.split_square(8, periodic=True), 1, 0, "cn", 0.01, "homog"),
+    "c2_8x8": (lambda: synth.split_square(8, jitter=0.2, seed=2001), 3, 3, "stdg", 2.5e-3, "layered"),
+    "p2pg2_free": (lambda: synth.split_square(6, jitter=0.15, seed=7), 2, 2, "stdg", 0.01, "lognormal"),
+    "p4pg1_periodic": (lambda: synth.split_square(4, periodic=True, jitter=0.1, seed=3), 4, 1, "stdg", 0.01, "lognormal"),
+    "3d_cn_p2": (lambda: synth.kuhn_cube(3, periodic=True), 2, 0, "cn", 0.01, "homog"),
+    "3d_free_p1pg2": (lambda: synth.kuhn_cube(2, periodic=False), 1, 2, "stdg", 0.02, "lognormal"),
+}
+
+
+def material(kind, mesh, seed=11):
+    if kind == "homog":
+        return synth.homogeneous_material(mesh.n_elem)
+    if kind == "layered":
+        return synth.layered_material(mesh.centroids(), sigma=0.1, seed=2002)
+    return synth.lognormal_material(mesh.n_elem, sigma=0.2, seed=seed)
+
+
+def build(name, precisions=None):
+    import paper_1802_04516_amd as sdg
+    mk, p, pg, scheme, dt, matkind = CASES[name]
+    mesh = mk()
+    lam, mu, rho = material(matkind, mesh)
+    ctx = sdg.Context(0)
+    sizes = ctx.setup(mesh.xyz, mesh.elem, mesh.period, p, pg,
+                      sdg.SDG_SCHEME_CN if scheme == "cn" else sdg.SDG_SCHEME_STDG, dt, lam, mu, rho,
+                      precisions or (sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32))
+    topo = Topology(mesh.xyz, mesh.elem, mesh.period)
+    B = Blocks(topo, p, lam, mu, rho)
+    slab = Slab(B, pg, dt, scheme)
+    return dict(mesh=mesh, ctx=ctx, sizes=sizes, B=B, slab=slab, p=p, pg=pg, scheme=scheme, dt=dt,
+                lam=lam, mu=mu, rho=rho)
+
+
+def rel(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))

@@ -1,0 +1,205 @@
+"""Parity of one implicit time step (right-hand side, Krylov solve, stress
+back-substitution; eqs. velocity.sys + NM26, or the Crank-Nicolson forms)
+between the HIP library and the oracle's sparse-LU solution of the coupled
+slab system, plus energy, point evaluation and failure handling.
+
+The spec bar is <= 1e-11 relative L2 per step; the GPU solves run at
+rtol 1e-13 so that the Krylov tolerance does not dominate.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_cases import build, rel
+from oracle import waves
+from oracle.assemble import locate
+
+pytestmark = pytest.mark.gpu
+
+
+def _to_gpu(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _canon(B, s_raw):
+    return np.stack([B.to_canonical(j, s_raw[j]) for j in range(B.topo.n_face)])
+
+
+def _opts(rtol=1e-13, precision=None, max_iter=2000, solver=0):
+    import paper_1802_04516_amd as sdg
+    return sdg.SolveOpts(solver, precision or sdg.SDG_PREC_F64, rtol, max_iter, 30, 5, 20, 1e-5)
+
+
+def _amp(case, n, f0=10.0, t_delay=0.1):
+    dt = case["dt"]
+    if case["scheme"] == "cn":
+        t = np.array([(n + 0.5) * dt])
+    else:
+        t = n * dt + case["slab"].tb.tau * dt
+    return synth.ricker(t, f0, t_delay)[None, :]
+
+
+def _run_pair(case, v0, s0_raw, nsteps, sources=None, precision=None, rtol=1e-13):
+    """Step both codes nsteps times from the same state; return max rel errors."""
+    import torch
+    B, slab, ctx = case["B"], case["slab"], case["ctx"]
+    vg = _to_gpu(v0)
+    sg = _to_gpu(_canon(B, s0_raw))
+    v, s = v0.copy(), s0_raw.copy()
+    if sources is not None:
+        ctx.set_sources(sources["pos"], sources["dir"])
+    errs = []
+    for n in range(nsteps):
+        amp = _amp(case, n) if sources is not None else None
+        info = ctx.step(vg, sg, amp, opts=_opts(rtol, precision))
+        src = dict(sources, amp=amp) if sources is not None else None
+        _, _, v, s = slab.step(v, s, src)
+        ev = rel(vg.cpu().numpy(), v)
+        es = rel(sg.cpu().numpy(), _canon(B, s))
+        errs.append((ev, es, info["iterations"], info["rel_residual"]))
+    torch.cuda.synchronize()
+    return errs
+
+
+def test_c1_crank_nicolson_plane_wave_10_steps():
+    case = build("c1")
+    wave = waves.PlaneWave2D(waves=("p",))
+    v0, s0 = waves.project(case["B"], wave, 0.0)
+    errs = _run_pair(case, v0, s0, 10)
+    for ev, es, it, rr in errs:
+        assert ev <= 1e-11 and es <= 1e-11, errs
+        assert rr <= 1e-13
+    case["ctx"].close()
+
+
+def test_c2_small_space_time_ricker_source():
+    case = build("c2_8x8")
+    src = dict(pos=np.array([[0.503, 0.497]]), dir=np.array([[0.0, 1.0]]))
+    nf, ns = case["B"].topo.n_elem, case["B"].topo.n_face
+    v0 = np.zeros((nf, 2, case["B"].nphi))
+    s0 = np.zeros((ns, 3, case["B"].npsi))
+    # start at t = 0.08 so the wavelet is non-negligible
+    errs = _run_pair(case, v0, s0, 6, sources=src)
+    for ev, es, it, rr in errs[1:]:
+        assert ev <= 1e-11 and es <= 1e-11, errs
+    case["ctx"].close()
+
+
+def test_space_time_p2_random_state_free_surface():
+    case = build("p2pg2_free")
+    rng = np.random.default_rng(21)
+    B = case["B"]
+    v0 = rng.standard_normal((B.topo.n_elem, 2, B.nphi))
+    s0 = 0.1 * rng.standard_normal((B.topo.n_face, 3, B.npsi))
+    errs = _run_pair(case, v0, s0, 3)
+    for ev, es, it, rr in errs:
+        assert ev <= 1e-11 and es <= 1e-11, errs
+    case["ctx"].close()
+
+
+def test_3d_crank_nicolson_shear_wave():
+    case = build("3d_cn_p2")
+    v0, s0 = waves.project(case["B"], waves.ShearWave3D(), 0.0)
+    errs = _run_pair(case, v0, s0, 3)
+    for ev, es, it, rr in errs:
+        assert ev <= 1e-11 and es <= 1e-11, errs
+    case["ctx"].close()
+
+
+def test_3d_space_time_free_surface():
+    case = build("3d_free_p1pg2")
+    rng = np.random.default_rng(4)
+    B = case["B"]
+    v0 = rng.standard_normal((B.topo.n_elem, 3, B.nphi))
+    s0 = 0.1 * rng.standard_normal((B.topo.n_face, 6, B.npsi))
+    errs = _run_pair(case, v0, s0, 2)
+    for ev, es, it, rr in errs:
+        assert ev <= 1e-11 and es <= 1e-11, errs
+    case["ctx"].close()
+
+
+def test_fp32_operator_with_fp64_refinement():
+    import paper_1802_04516_amd as sdg
+    case = build("c2_8x8")
+    rng = np.random.default_rng(8)
+    B = case["B"]
+    v0 = rng.standard_normal((B.topo.n_elem, 2, B.nphi))
+    s0 = 0.1 * rng.standard_normal((B.topo.n_face, 3, B.npsi))
+    errs = _run_pair(case, v0, s0, 2, precision=sdg.SDG_PREC_F32, rtol=1e-13)
+    for ev, es, it, rr in errs:
+        assert ev <= 1e-11 and es <= 1e-11, errs
+        assert rr <= 1e-13
+    case["ctx"].close()
+
+
+def test_energy_matches_oracle_and_cn_conserves():
+    import torch
+    case = build("c1")
+    B, slab, ctx = case["B"], case["slab"], case["ctx"]
+    v0, s0 = waves.project(B, waves.PlaneWave2D(waves=("p", "s")), 0.0)
+    vg, sg = _to_gpu(v0), _to_gpu(_canon(B, s0))
+    E0 = ctx.energy(vg, sg)
+    assert abs(E0 - slab.energy(v0, s0)) <= 1e-13 * E0
+    for _ in range(10):
+        ctx.step(vg, sg, None, opts=_opts(1e-15, max_iter=4000))
+    E1 = ctx.energy(vg, sg)
+    torch.cuda.synchronize()
+    assert abs(E1 - E0) <= 1e-12 * E0
+    ctx.close()
+
+
+def test_sample_velocity_and_eval_stress_against_oracle():
+    import torch
+    import paper_1802_04516_amd as sdg
+    case = build("p2pg2_free")
+    B, ctx = case["B"], case["ctx"]
+    rng = np.random.default_rng(2)
+    v = rng.standard_normal((B.topo.n_elem, 2, B.nphi))
+    s = rng.standard_normal((B.topo.n_face, 3, B.npsi))
+    pts = rng.uniform(0.01, 0.99, (17, 2))
+    out = torch.zeros(17 * 2, dtype=torch.float64, device="cuda")
+    sdg.sdg_sample_velocity(ctx.h, _to_gpu(v), pts, out)
+    ref = np.array([B.velocity_at(v[locate(B.topo, x)], locate(B.topo, x), x[None, :])[0] for x in pts])
+    assert np.allclose(out.cpu().numpy().reshape(17, 2), ref, atol=1e-12)
+    # stress at points of a few dual elements (canonical DOFs on the GPU side)
+    faces = np.array([0, 5, 9, 14, B.topo.n_face - 1])
+    xs = np.array([B.topo.sub_simplex(j, 0).mean(axis=0) for j in faces])
+    sc = _canon(B, s)
+    outs = torch.zeros(len(faces) * 3, dtype=torch.float64, device="cuda")
+    sdg.sdg_eval_stress(ctx.h, _to_gpu(sc), xs, faces, outs)
+    refs = np.array([B.stress_at(s[j], j, x[None, :])[0] for j, x in zip(faces, xs)])
+    assert np.allclose(outs.cpu().numpy().reshape(-1, 3), refs, atol=1e-11 * np.abs(refs).max())
+    ctx.close()
+
+
+def test_failure_injection_noconv_nonfinite_and_mesh():
+    import paper_1802_04516_amd as sdg
+    case = build("c1")
+    ctx, B = case["ctx"], case["B"]
+    rng = np.random.default_rng(0)
+    vg = _to_gpu(rng.standard_normal((B.topo.n_elem, 2, B.nphi)))
+    sg = _to_gpu(np.zeros((B.topo.n_face, 3, B.npsi)))
+    info = sdg.sdg_solve_step(ctx.h, vg, sg, None, opts=_opts(1e-14, max_iter=1), raise_on_noconv=False)
+    assert info["converged"] == 0 and info["iterations"] == 1 and info["rel_residual"] > 1e-14
+    with pytest.raises(sdg.SdgError) as ei:
+        ctx.step(vg, sg, None, opts=_opts(1e-14, max_iter=1))
+    assert ei.value.code == sdg.SDG_ENOCONV
+    bad = vg.clone()
+    bad[3] = float("nan")
+    with pytest.raises(sdg.SdgError) as ei:
+        ctx.step(bad, sg.clone(), None, opts=_opts())
+    assert ei.value.code == sdg.SDG_ENONFINITE
+    ctx.close()
+    # degenerate element
+    m = synth.split_square(3)
+    xyz = m.xyz.copy()
+    xyz[m.elem[4, 2]] = xyz[m.elem[4, 0]]
+    c2 = sdg.Context(0)
+    with pytest.raises(sdg.SdgError) as ei:
+        c2.setup(xyz, m.elem, None, 1, 0, sdg.SDG_SCHEME_CN, 0.01, *synth.homogeneous_material(m.n_elem))
+    assert ei.value.code == sdg.SDG_EMESH
+    with pytest.raises(sdg.SdgError) as ei:
+        c2.setup(m.xyz, m.elem, None, 9, 0, sdg.SDG_SCHEME_CN, 0.01, *synth.homogeneous_material(m.n_elem))
+    assert ei.value.code in (sdg.SDG_EINVAL, sdg.SDG_EUNSUPPORTED)
+    c2.close()
