@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--applies", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c2")
+    ap.add_argument("--precond", default="block", choices=["none", "mass", "block"])
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 1 GiB x 10 (scale for the rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
@@ -87,13 +90,24 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        nbytes = 1 << 30
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": nbytes, "copy_bytes_written_per_launch": nbytes,
+                          "launches": 10}), flush=True)
+        return
     w = synth.workload(args.workload)
     mesh = w["mesh"]
     scheme = sdg.SDG_SCHEME_CN if w["scheme"] == "cn" else sdg.SDG_SCHEME_STDG
     t0 = time.time()
     ctx = sdg.Context(0)
     sizes = ctx.setup(mesh.xyz, mesh.elem, mesh.period, w["p"], w["p_gamma"], scheme, w["dt"],
-                      w["lam"], w["mu"], w["rho"], sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32)
+                      w["lam"], w["mu"], w["rho"],
+                      sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND)
     log(f"setup {time.time() - t0:.1f}s: {sizes['n_elem']} elems, {sizes['n_face']} faces, "
         f"{sizes['n_vel_slab']} velocity DOFs, operator {sizes['op_bytes_f64'] / 1e6:.1f} MB")
     src = w["sources"]
@@ -110,8 +124,9 @@ def main():
 
     v = torch.zeros(sizes["n_vel_state"], dtype=torch.float64, device=dev)
     s = torch.zeros(sizes["n_stress_state"], dtype=torch.float64, device=dev)
-    opts64 = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F64, 1e-10, 5000, 30, 5, 10, 1e-4)
-    opts32 = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F32, 1e-10, 5000, 30, 5, 10, 1e-4)
+    pc = {"none": sdg.SDG_PRECOND_NONE, "mass": sdg.SDG_PRECOND_MASS, "block": sdg.SDG_PRECOND_BLOCK}[args.precond]
+    opts64 = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F64, 1e-10, 5000, 30, 5, 10, 1e-4, pc)
+    opts32 = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F32, 1e-10, 5000, 30, 5, 10, 1e-4, pc)
 
     # the source switches on around t_delay; start the run so that the timed
     # steps see the wavelet

@@ -80,7 +80,14 @@ enum {
 
 enum { SDG_SCHEME_STDG = 0, SDG_SCHEME_CN = 1 };
 enum { SDG_PREC_F64 = 1, SDG_PREC_F32 = 2 };
+/* extra sdg_assemble flag: also build the block preconditioner (eq. pre1) */
+enum { SDG_ASSEMBLE_BLOCK_PRECOND = 4 };
 enum { SDG_SOLVER_AUTO = 0, SDG_SOLVER_CG = 1, SDG_SOLVER_GMRES = 2 };
+/* Preconditioners (Appendix A discusses block-Jacobi preconditioning):
+ * MASS  = element block-Jacobi on the mass term, (T (x) rho Mbar_i)^-1, no storage;
+ * BLOCK = element block-Jacobi on the full diagonal block of the velocity
+ *         operator (eq. pre1), inverses stored at assemble time. */
+enum { SDG_PRECOND_NONE = 0, SDG_PRECOND_MASS = 1, SDG_PRECOND_BLOCK = 2 };
 
 typedef struct sdg_ctx sdg_ctx;
 
@@ -110,6 +117,8 @@ typedef struct {
   int32_t check_every; /* host convergence poll period in iterations                    */
   int32_t max_refine;  /* outer refinement sweeps for SDG_PREC_F32                      */
   double inner_rtol;   /* relative tolerance of each inner FP32 solve                   */
+  int32_t precond;     /* SDG_PRECOND_*: right preconditioner (GMRES) / PCG (CG)        */
+  int32_t pad;
 } sdg_solve_opts;
 
 typedef struct {
@@ -155,8 +164,10 @@ int sdg_set_material(sdg_ctx* ctx, const double* lambda, const double* mu, const
 
 /* Build topology, geometry, bases and the operator blocks on the host and
  * upload them.  precisions = SDG_PREC_F64 | SDG_PREC_F32 selects which
- * copies of the blocks are stored.  max_rhs (>= 1) sizes the workspaces for
- * batched applies and solves. */
+ * copies of the blocks are stored; OR in SDG_ASSEMBLE_BLOCK_PRECOND to also
+ * invert the element diagonal blocks of the velocity operator (eq. pre1,
+ * stored in FP32, (N_gamma d N_phi)^2 floats per element).  max_rhs (>= 1)
+ * sizes the workspaces for batched applies and solves. */
 int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs);
 
 int sdg_query(const sdg_ctx* ctx, sdg_sizes* out);

@@ -24,7 +24,9 @@ SDG_EINVAL, SDG_ENOMEM, SDG_EDEVICE, SDG_EMESH = -1, -2, -3, -4
 SDG_ENOCONV, SDG_ENONFINITE, SDG_EUNSUPPORTED, SDG_ESTATE = -5, -6, -7, -8
 SDG_SCHEME_STDG, SDG_SCHEME_CN = 0, 1
 SDG_PREC_F64, SDG_PREC_F32 = 1, 2
+SDG_ASSEMBLE_BLOCK_PRECOND = 4
 SDG_SOLVER_AUTO, SDG_SOLVER_CG, SDG_SOLVER_GMRES = 0, 1, 2
+SDG_PRECOND_NONE, SDG_PRECOND_MASS, SDG_PRECOND_BLOCK = 0, 1, 2
 
 _ERRNAMES = {SDG_EINVAL: "EINVAL", SDG_ENOMEM: "ENOMEM", SDG_EDEVICE: "EDEVICE", SDG_EMESH: "EMESH",
              SDG_ENOCONV: "ENOCONV", SDG_ENONFINITE: "ENONFINITE", SDG_EUNSUPPORTED: "EUNSUPPORTED",
@@ -56,7 +58,8 @@ class Sizes(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int32), ("precision", ctypes.c_int32), ("rtol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("max_refine", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
+                ("max_refine", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("precond", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -208,7 +211,7 @@ def sdg_set_sources(h, pos, direction):
 
 def sdg_solve_step(h, v_state, sigma_state, amp=None, n_rhs=1, opts: SolveOpts | None = None,
                    v_slab=None, sigma_slab=None, stream=None, raise_on_noconv=True):
-    opts = opts or SolveOpts(SDG_SOLVER_AUTO, SDG_PREC_F64, 1e-10, 1000, 30, 5, 10, 1e-4)
+    opts = opts or SolveOpts(SDG_SOLVER_AUTO, SDG_PREC_F64, 1e-10, 1000, 30, 5, 10, 1e-4, SDG_PRECOND_MASS)
     info = SolveInfo()
     a = _host(amp, np.float64) if amp is not None else None
     rc = lib().sdg_solve_step(h, _dev(v_state, name="v_state"), _dev(sigma_state, name="sigma_state"),

@@ -8,8 +8,10 @@
 
 namespace sdg {
 
-bool dispatch_2d(int which, int dim, int p, int ng, int prec, int mode, const OpArgs& a, hipStream_t s);
-bool dispatch_3d(int which, int dim, int p, int ng, int prec, int mode, const OpArgs& a, hipStream_t s);
+bool dispatch_2d(int which, int dim, int p, int ng, int prec, int mode, const OpArgs& a, hipStream_t s,
+                 const GradArgs* ga = nullptr);
+bool dispatch_3d(int which, int dim, int p, int ng, int prec, int mode, const OpArgs& a, hipStream_t s,
+                 const GradArgs* ga = nullptr);
 
 bool launch_face(int dim, int p, int ng, int prec, int mode, const OpArgs& a, hipStream_t s) {
   return dim == 2 ? dispatch_2d(0, dim, p, ng, prec, mode, a, s) : dispatch_3d(0, dim, p, ng, prec, mode, a, s);
@@ -17,6 +19,10 @@ bool launch_face(int dim, int p, int ng, int prec, int mode, const OpArgs& a, hi
 bool launch_elem(int dim, int p, int ng, const OpArgs& a, hipStream_t s) {
   return dim == 2 ? dispatch_2d(1, dim, p, ng, SDG_PREC_F64, 0, a, s)
                   : dispatch_3d(1, dim, p, ng, SDG_PREC_F64, 0, a, s);
+}
+bool launch_grad_face(int dim, int p, int ng, const GradArgs& g, hipStream_t s) {
+  OpArgs a{};
+  return dim == 2 ? dispatch_2d(3, dim, p, ng, SDG_PREC_F64, 0, a, s, &g) : dispatch_3d(3, dim, p, ng, SDG_PREC_F64, 0, a, s, &g);
 }
 bool have_kernels(int dim, int p, int ng) {
   OpArgs a{};
@@ -86,6 +92,7 @@ OpArgs base_args(Ctx& c, int prec) {
   a.elem_w = c.d_elem_w.p;
   a.Mref = c.d_Mref.p;
   a.y_scale = 1.0;
+  a.sig_in_ng = 1;
   return a;
 }
 
@@ -107,6 +114,25 @@ void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipS
   SDG_HIP(hipGetLastError());
   launch_elem(c.hs.dim, c.hs.p, c.hs.ng, a, s);
   SDG_HIP(hipGetLastError());
+}
+
+void apply_precond(Ctx& c, int kind, const double* x, double* y, bool transpose, hipStream_t s) {
+  const HostSetup& hs = c.hs;
+  if (kind == SDG_PRECOND_MASS) {
+    OpArgs a = base_args(c, SDG_PREC_F64);
+    a.Mref = c.d_Minv.p;
+    a.elem_w = c.d_winv.p;
+    a.v = x;
+    a.y = y;
+    a.c = transpose ? c.precA : c.precF;
+    launch_elem(hs.dim, hs.p, hs.ng, a, s);
+    SDG_HIP(hipGetLastError());
+  } else if (kind == SDG_PRECOND_BLOCK) {
+    require(c.d_Pblk.p != nullptr, SDG_ESTATE, "block preconditioner not assembled (pass SDG_ASSEMBLE_BLOCK_PRECOND)");
+    launch_block_apply(hs.n_elem, hs.ng * hs.dim * hs.nphi, c.d_Pblk.p, x, y, transpose, s);
+  } else {
+    vec_copy(c.n_slab, x, y, s);
+  }
 }
 
 }  // namespace sdg
@@ -204,8 +230,8 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
   return guard([&] {
     Ctx& c = ctx_of(ctx);
     require(c.have_mesh && c.have_disc && c.have_mat, SDG_ESTATE, "mesh, discretization and material must be set");
-    require((precisions & (SDG_PREC_F64 | SDG_PREC_F32)) != 0 && (precisions & ~3u) == 0, SDG_EINVAL,
-            "precisions must be a non-empty subset of SDG_PREC_F64 | SDG_PREC_F32");
+    require((precisions & (SDG_PREC_F64 | SDG_PREC_F32)) != 0 && (precisions & ~7u) == 0, SDG_EINVAL,
+            "precisions must be a non-empty subset of SDG_PREC_F64 | SDG_PREC_F32 (| SDG_ASSEMBLE_BLOCK_PRECOND)");
     require(max_rhs == 1, SDG_EUNSUPPORTED, "batched right-hand sides are not built in this version");
     SDG_HIP(hipSetDevice(c.device));
     c.assembled = false;
@@ -218,7 +244,7 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     c.n_slab = hs.n_elem * ng * d * nphi;
     c.n_state = hs.n_elem * d * nphi;
     c.n_sig_state = hs.n_face * hs.nsig * hs.npsi;
-    c.precisions = precisions;
+    c.precisions = precisions & 3u;
     c.max_rhs = max_rhs;
 
     // time coefficients
@@ -239,6 +265,31 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     if (c.scheme == SDG_SCHEME_CN) adj = op;
     c.op = op;
     c.adj = adj;
+    // mass block-Jacobi preconditioner: (Tm (x) w Mref)^-1 = Tm^-1 (x) w^-1 Mref^-1
+    {
+      Coefs pf{}, pa{};
+      std::vector<double> Tm(ng * ng);
+      for (int a = 0; a < ng * ng; ++a) Tm[a] = op.Tm[a];
+      std::vector<double> Ti = inverse(Tm, ng);
+      set_sq(pf.Tm, Ti, ng, false);
+      set_sq(pa.Tm, Ti, ng, true);
+      c.precF = pf;
+      c.precA = pa;
+      std::vector<double> Mi = inverse(hs.Mref, nphi);
+      c.d_Minv.alloc(Mi.size());
+      SDG_HIP(hipMemcpy(c.d_Minv.p, Mi.data(), Mi.size() * sizeof(double), hipMemcpyHostToDevice));
+      std::vector<double> wi(hs.n_elem);
+      for (int64_t e = 0; e < hs.n_elem; ++e) wi[e] = 1.0 / hs.elem_w[e];
+      c.d_winv.alloc(wi.size());
+      SDG_HIP(hipMemcpy(c.d_winv.p, wi.data(), wi.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (precisions & SDG_ASSEMBLE_BLOCK_PRECOND) {
+      std::vector<float> P = block_inverses(hs, op);
+      c.d_Pblk.alloc(P.size());
+      SDG_HIP(hipMemcpy(c.d_Pblk.p, P.data(), P.size() * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+      c.d_Pblk.free();
+    }
 
     // operator blocks
     c.d_faces.alloc(hs.n_face);
@@ -274,7 +325,7 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     // workspaces
     c.d_z.alloc((size_t)hs.n_elem * (d + 1) * ng * d * nphi);
     const size_t n = c.n_slab;
-    c.d_V.alloc(c.scheme == SDG_SCHEME_CN ? 0 : (size_t)(kMaxRestart + 1) * n);
+    c.d_V.alloc(c.scheme == SDG_SCHEME_CN ? n : (size_t)(kMaxRestart + 1) * n);
     c.d_x.alloc(n);
     c.d_b.alloc(n);
     c.d_r.alloc(n);
@@ -413,7 +464,7 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     int solver = opts->solver;
     if (solver == SDG_SOLVER_AUTO) solver = c.scheme == SDG_SCHEME_CN ? SDG_SOLVER_CG : SDG_SOLVER_GMRES;
     require(solver == SDG_SOLVER_CG || solver == SDG_SOLVER_GMRES, SDG_EINVAL, "unknown solver");
-    require(solver != SDG_SOLVER_GMRES || c.d_V.p != nullptr, SDG_EINVAL,
+    require(solver != SDG_SOLVER_GMRES || c.d_V.n >= (size_t)(kMaxRestart + 1) * c.n_slab, SDG_EINVAL,
             "GMRES workspace is only allocated for the space-time scheme");
     const int restart = opts->restart > 0 ? opts->restart : 30;
     require(restart <= kMaxRestart, SDG_EINVAL, "restart must be <= 32");
@@ -465,10 +516,17 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
 
     // 2. initial guess and Krylov solve
     launch_broadcast_time(hs.n_elem, ng, nvs, v_state, c.d_x.p, s);
-    const int check = opts->check_every > 0 ? opts->check_every : 5;
+    KrylovCfg kc;
+    kc.check_every = opts->check_every > 0 ? opts->check_every : 5;
+    kc.restart = restart;
+    kc.precond = opts->precond;
+    require(kc.precond >= SDG_PRECOND_NONE && kc.precond <= SDG_PRECOND_BLOCK, SDG_EINVAL, "unknown preconditioner");
     auto inner = [&](const double* b, double* x, double tol, int maxit, int pr) {
-      return solver == SDG_SOLVER_CG ? solve_cg(c, b, x, tol, maxit, check, pr, s)
-                                     : solve_gmres(c, b, x, tol, maxit, restart, check, pr, s);
+      KrylovCfg k2 = kc;
+      k2.rtol = tol;
+      k2.max_iter = maxit;
+      k2.prec = pr;
+      return solver == SDG_SOLVER_CG ? solve_cg(c, b, x, k2, s) : solve_gmres(c, b, x, k2, s);
     };
     if (prec == SDG_PREC_F64) {
       res = inner(c.d_b.p, c.d_x.p, opts->rtol, opts->max_iter, SDG_PREC_F64);

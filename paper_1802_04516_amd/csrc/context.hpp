@@ -68,6 +68,12 @@ struct Ctx {
   DevBuf<double> d_face_lm, d_elem_w, d_Mref;
   DevBuf<double> d_z;  // element face slots
   Coefs op{}, adj{};   // operator and its transpose
+  // preconditioners: mass block-Jacobi (reference mass inverse, 1/(rho|J|),
+  // T^-1) and the element diagonal-block inverses of eq. (pre1) in FP32,
+  // column-major per element
+  DevBuf<double> d_Minv, d_winv;
+  Coefs precF{}, precA{};
+  DevBuf<float> d_Pblk;
 
   // solver workspace
   DevBuf<double> d_V;                   // (restart+1) * n_slab   (GMRES) or 4 * n_slab (CG)
@@ -106,10 +112,19 @@ struct SolveResult {
   bool converged = false;
   double rel_res = 0.0, bnorm = 0.0;
 };
-SolveResult solve_cg(Ctx& c, const double* b, double* x, double rtol, int max_iter, int check_every,
-                     int prec, hipStream_t s);
-SolveResult solve_gmres(Ctx& c, const double* b, double* x, double rtol, int max_iter, int restart,
-                        int check_every, int prec, hipStream_t s);
+struct KrylovCfg {
+  double rtol = 1e-10;
+  int max_iter = 1000, restart = 30, check_every = 5;
+  int prec = SDG_PREC_F64;   // operator precision
+  int precond = SDG_PRECOND_NONE;
+  bool transpose = false;    // solve with A^T (adjoint)
+};
+SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s);
+SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s);
+// y = P^-1 x for the chosen preconditioner (transpose: P^-T)
+void apply_precond(Ctx& c, int kind, const double* x, double* y, bool transpose, hipStream_t s);
+void launch_block_apply(int64_t n_elem, int nv, const float* P, const double* x, double* y, bool transpose,
+                        hipStream_t s);
 
 // step pieces
 void launch_broadcast_time(int64_t n_elem, int ng, int nvs, const double* state, double* slab,

@@ -89,7 +89,7 @@ void eval_dual_canonical(const HostSetup& hs, const int64_t* elem, int64_t j, in
 struct Coefs {
   double Tm[kMaxGamma * kMaxGamma];  // mass time matrix   [a][b]
   double Cg[kMaxGamma * kMaxGamma];  // stress-from-gradient time matrix [a][b]
-  double Cs[kMaxGamma];              // stress-from-input-stress vector  [a]
+  double Cs[kMaxGamma * kMaxGamma];  // stress-from-input-stress matrix [a][q], q < sig_in_ng
   double send[kMaxGamma];            // end-of-slab weights gamma_a(1) for the stress output
 };
 
@@ -113,6 +113,11 @@ struct OpArgs {
   double* y;               // element kernel output [elem][NG][d][nphi]
   const double* Mref;      // nphi*nphi (device)
   int use_g;               // 0: skip the gradient term (Cg == 0)
+  int vsum;                // 1: replace the Hooke law by the Voigt sum (g_pq + g_qp), the
+                           //    transpose of the scatter's use of the stress
+  int sig_in_ng;           // time slots of sig_in (1 or NG); layout [face][q][s][m]
+  int sig_in_Et;           // 1: apply E^T (Voigt -> gradient space) to the input stress
+  int mass_identity;       // element kernel: y = Tm[a] v instead of Tm (x) w Mref v
   int v_spatial;           // element kernel: v has no time axis (mass applied with Tm[:,0])
   double y_scale;          // element kernel: y = y_scale * (...) (reserved, 1.0)
   Coefs c;
@@ -123,5 +128,25 @@ struct OpArgs {
 bool launch_face(int dim, int p, int ng, int prec, int mode, const OpArgs& a, hipStream_t s);
 bool launch_elem(int dim, int p, int ng, const OpArgs& a, hipStream_t s);
 bool have_kernels(int dim, int p, int ng);
+
+// Material-gradient pieces of the discrete adjoint (one time slab):
+//   face_out[2j]   += coef * sum_{a,m} wq[a] tr(g_a) sum_p Lam_s[a][pp][m]
+//   face_out[2j+1] += coef * sum_{a,m,s} wq[a] Lam_s[a][s][m] (g_pq + g_qp)_a[m]
+// with g = sum_sides Dt^T v (v: slab velocities [elem][a][c][k]).
+struct GradArgs {
+  int64_t n_face, n_elem;
+  const FaceRec* faces;
+  const double* Dt;
+  const double* v;        // forward slab velocity (or the CN sum v^n + v^{n+1})
+  const double* lam_s;    // adjoint stress slab [face][a][s][m]
+  double* face_out;       // [face][2]
+  double coef;            // -dt (space-time) or -dt/2 (Crank-Nicolson)
+  double wq[kMaxGamma];
+};
+bool launch_grad_face(int dim, int p, int ng, const GradArgs& a, hipStream_t s);
+
+// Inverses of the element diagonal blocks of the velocity operator (eq. pre1)
+// with time coefficients op (FP32, column-major per element).
+std::vector<float> block_inverses(const HostSetup& hs, const Coefs& op);
 
 }  // namespace sdg

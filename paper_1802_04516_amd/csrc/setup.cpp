@@ -757,4 +757,75 @@ void eval_dual_canonical(const HostSetup& hs, const int64_t* elem, int64_t j, in
   for (int64_t q = 0; q < n; ++q) db.canonical(x + q * hs.dim, out + q * hs.npsi);
 }
 
+// Element diagonal blocks of the velocity operator (eq. pre1),
+//   D_i = Tm (x) w_i Mref + Cg (x) K_ii,  K_ii = sum_f Dt_{i,f} E_j Dt_{i,f}^T,
+// inverted on the host; returned in FP32, column-major per element.
+std::vector<float> block_inverses(const HostSetup& hs, const Coefs& op) {
+  const int d = hs.dim, nphi = hs.nphi, npsi = hs.npsi, ng = hs.ng;
+  const int ns = d * nphi, nv = ng * ns, blk = nphi * d * npsi;
+  std::vector<float> out((size_t)hs.n_elem * nv * nv);
+  int err = 0;
+  parallel_for(hs.n_elem, [&](int64_t e) {
+    std::vector<double> K(ns * ns), Dm(nv * nv), Inv(nv * nv);
+    std::fill(K.begin(), K.end(), 0.0);
+    for (int f = 0; f <= d; ++f) {
+      const int32_t j = hs.elem_face[e * (d + 1) + f];
+      const FaceRec& fr = hs.faces[j];
+      const int side = fr.left == e ? 0 : 1;
+      const double* Db = &hs.Dt[((size_t)j * 2 + side) * blk];
+      const double lam = hs.face_lm[2 * j], mu = hs.face_lm[2 * j + 1];
+      // K[(c,k),(c2,k2)] = sum_{l,l2,m} Db[k][l][m] E_{cl,c2l2} Db[k2][l2][m]
+      for (int c = 0; c < d; ++c)
+        for (int l = 0; l < d; ++l)
+          for (int c2 = 0; c2 < d; ++c2)
+            for (int l2 = 0; l2 < d; ++l2) {
+              double E = mu * ((c == c2 && l == l2) + (c == l2 && l == c2)) + lam * (c == l && c2 == l2);
+              if (E == 0.0) continue;
+              for (int k = 0; k < nphi; ++k)
+                for (int k2 = 0; k2 < nphi; ++k2) {
+                  double sacc = 0.0;
+                  const double* a1 = Db + (k * d + l) * npsi;
+                  const double* a2 = Db + (k2 * d + l2) * npsi;
+                  for (int m = 0; m < npsi; ++m) sacc += a1[m] * a2[m];
+                  K[(c * nphi + k) * ns + c2 * nphi + k2] += E * sacc;
+                }
+            }
+    }
+    for (int a = 0; a < ng; ++a)
+      for (int b = 0; b < ng; ++b)
+        for (int i = 0; i < ns; ++i)
+          for (int i2 = 0; i2 < ns; ++i2) {
+            const int c = i / nphi, k = i % nphi, c2 = i2 / nphi, k2 = i2 % nphi;
+            double v = op.Cg[a * ng + b] * K[i * ns + i2];
+            if (c == c2) v += op.Tm[a * ng + b] * hs.elem_w[e] * hs.Mref[k * nphi + k2];
+            Dm[(a * ns + i) * nv + b * ns + i2] = v;
+          }
+    std::vector<double> M = Dm;
+    std::fill(Inv.begin(), Inv.end(), 0.0);
+    for (int i = 0; i < nv; ++i) Inv[i * nv + i] = 1.0;
+    for (int col = 0; col < nv; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < nv; ++r)
+        if (std::fabs(M[r * nv + col]) > std::fabs(M[piv * nv + col])) piv = r;
+      if (M[piv * nv + col] == 0.0) { err = 1; return; }
+      if (piv != col)
+        for (int k = 0; k < nv; ++k) { std::swap(M[col * nv + k], M[piv * nv + k]); std::swap(Inv[col * nv + k], Inv[piv * nv + k]); }
+      const double dinv = 1.0 / M[col * nv + col];
+      for (int k = 0; k < nv; ++k) { M[col * nv + k] *= dinv; Inv[col * nv + k] *= dinv; }
+      for (int r = 0; r < nv; ++r) {
+        if (r == col) continue;
+        const double f = M[r * nv + col];
+        if (f == 0.0) continue;
+        for (int k = 0; k < nv; ++k) { M[r * nv + k] -= f * M[col * nv + k]; Inv[r * nv + k] -= f * Inv[col * nv + k]; }
+      }
+    }
+    float* o = &out[(size_t)e * nv * nv];
+    for (int r = 0; r < nv; ++r)
+      for (int col = 0; col < nv; ++col) o[(size_t)col * nv + r] = (float)Inv[r * nv + col];
+  });
+  require(!err, SDG_EMESH, "singular diagonal block");
+  return out;
+}
+
+
 }  // namespace sdg

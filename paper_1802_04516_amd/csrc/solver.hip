@@ -8,6 +8,8 @@
 // memory; the host reads one residual estimate every `check_every`
 // iterations.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "context.hpp"
@@ -94,11 +96,12 @@ __global__ void k_dot(int64_t n, const double* __restrict__ x, const double* __r
 
 // ---------------------------------------------------------------- CG
 
-// x += alpha p, r -= alpha q, rr_new = r.r, with alpha = rr / pq; last block
-// sets beta = rr_new / rr and rr = rr_new.
+// x += alpha p, r -= alpha q with alpha = rz / pq; rr_new = r.r.  Without a
+// preconditioner (z = r) the last block also sets beta = rr_new / rz and
+// rz = rr_new.  sc->rr holds rz.
 __global__ void k_cg_update(int64_t n, double* __restrict__ x, double* __restrict__ r,
                             const double* __restrict__ p, const double* __restrict__ q,
-                            DevScalars* sc, double* partials) {
+                            DevScalars* sc, double* partials, int finish_beta) {
   __shared__ double sh[16];
   const double alpha = sc->rr / sc->pq;
   double acc = 0.0;
@@ -116,10 +119,55 @@ __global__ void k_cg_update(int64_t n, double* __restrict__ x, double* __restric
       double s = 0.0;
       for (unsigned b = 0; b < gridDim.x; ++b) s += partials[(size_t)b * kRedSlots];
       sc->alpha = alpha;
+      sc->rr_new = s;
+      if (finish_beta) {
+        sc->beta = s / sc->rr;
+        sc->rr = s;
+      }
+      sc->ticket[0] = 0u;
+    }
+  }
+}
+
+// rz_new = r . z; beta = rz_new / rz; rz = rz_new (preconditioned CG)
+__global__ void k_dot_beta(int64_t n, const double* __restrict__ r, const double* __restrict__ z, DevScalars* sc,
+                           double* partials) {
+  __shared__ double sh[16];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc += r[i] * z[i];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kRedSlots] = acc;
+  if (last_block(&sc->ticket[0])) {
+    __threadfence();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (unsigned b = 0; b < gridDim.x; ++b) s += partials[(size_t)b * kRedSlots];
       sc->beta = s / sc->rr;
       sc->rr = s;
       sc->ticket[0] = 0u;
     }
+  }
+}
+
+// y = P x for per-element dense blocks stored column-major in FP32
+// (P[e][col][row]); transpose applies P^T.
+__global__ void k_block_apply(int64_t n_elem, int nv, const float* __restrict__ P, const double* __restrict__ x,
+                              double* __restrict__ y, int transpose) {
+  extern __shared__ double sx[];
+  for (int64_t e = blockIdx.x; e < n_elem; e += gridDim.x) {
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) sx[i] = x[e * nv + i];
+    __syncthreads();
+    const float* Pe = P + (size_t)e * nv * nv;
+    for (int rrow = threadIdx.x; rrow < nv; rrow += blockDim.x) {
+      double acc = 0.0;
+      if (!transpose)
+        for (int col = 0; col < nv; ++col) acc += (double)Pe[(size_t)col * nv + rrow] * sx[col];
+      else
+        for (int col = 0; col < nv; ++col) acc += (double)Pe[(size_t)rrow * nv + col] * sx[col];
+      y[e * nv + rrow] = acc;
+    }
+    __syncthreads();
   }
 }
 
@@ -288,6 +336,11 @@ __global__ void k_gmres_update(int64_t n, int k, const double* __restrict__ V, d
   }
 }
 
+bool debug_krylov() {
+  static const bool on = std::getenv("SDG_DEBUG_KRYLOV") != nullptr;
+  return on;
+}
+
 unsigned vgrid(int64_t n) {
   int64_t b = (n + kThreads - 1) / kThreads;
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
@@ -330,73 +383,107 @@ double vec_dot_host(Ctx& c, int64_t n, const double* x, const double* y, hipStre
   return read_scalar(c, &c.d_sc.p->dots[0], s);
 }
 
+static double read_scalar_dot(Ctx& c, int64_t n, const double* r, hipStream_t s) {
+  return vec_dot_host(c, n, r, r, s);
+}
+
+void launch_block_apply(int64_t n_elem, int nv, const float* P, const double* x, double* y, bool transpose,
+                        hipStream_t s) {
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_elem, 65535));
+  const int t = nv <= 64 ? 64 : (nv <= 128 ? 128 : 256);
+  k_block_apply<<<g, t, nv * sizeof(double), s>>>(n_elem, nv, P, x, y, transpose ? 1 : 0);
+  check_launch();
+}
+
 // ---------------------------------------------------------------- CG
 
-SolveResult solve_cg(Ctx& c, const double* b, double* x, double rtol, int max_iter, int check_every,
-                     int prec, hipStream_t s) {
+// Preconditioned conjugate gradients (P = I for SDG_PRECOND_NONE):
+//   z = P^-1 r, p = z, rz = r.z;  per iteration
+//   q = A p; alpha = rz / p.q; x += alpha p; r -= alpha q; z = P^-1 r;
+//   beta = r.z_new / rz; p = z + beta p.
+SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s) {
   SolveResult res;
   const int64_t n = c.n_slab;
   double* r = c.d_r.p;
   double* pv = c.d_w.p;
   double* q = c.d_t.p;
+  double* z = c.d_V.p;  // first basis vector (always allocated) holds z = P^-1 r
   DevScalars* sc = c.d_sc.p;
+  const bool pre = k.precond != SDG_PRECOND_NONE;
+  const int check_every = std::max(1, k.check_every);
   res.bnorm = std::sqrt(vec_dot_host(c, n, b, b, s));
+  require(std::isfinite(res.bnorm), SDG_ENONFINITE, "non-finite right-hand side");
   if (res.bnorm == 0.0) {
     vec_fill(n, 0.0, x, s);
     res.converged = true;
     return res;
   }
-  require(std::isfinite(res.bnorm), SDG_ENONFINITE, "non-finite right-hand side");
-  // r = b - A x
-  apply_op(c, x, q, prec, false, s);
+  apply_op(c, x, q, k.prec, k.transpose, s);
   ++res.matvecs;
   vec_copy(n, b, r, s);
   vec_axpby(n, -1.0, q, 1.0, r, s);
-  vec_copy(n, r, pv, s);
-  dev_dot(c, n, r, r, &sc->rr, s);
-  check_every = std::max(1, check_every);
-  double rr = read_scalar(c, &sc->rr, s);
+  if (pre) {
+    apply_precond(c, k.precond, r, z, k.transpose, s);
+  } else {
+    z = r;
+  }
+  vec_copy(n, z, pv, s);
+  dev_dot(c, n, r, z, &sc->rr, s);  // rz
+  double rr = read_scalar_dot(c, n, r, s);
   require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
-  if (std::sqrt(rr) <= rtol * res.bnorm) { res.converged = true; res.rel_res = std::sqrt(rr) / res.bnorm; return res; }
-  for (int it = 0; it < max_iter; ++it) {
-    apply_op(c, pv, q, prec, false, s);
+  if (std::sqrt(rr) <= k.rtol * res.bnorm) {
+    res.converged = true;
+    res.rel_res = std::sqrt(rr) / res.bnorm;
+    return res;
+  }
+  for (int it = 0; it < k.max_iter; ++it) {
+    apply_op(c, pv, q, k.prec, k.transpose, s);
     ++res.matvecs;
     dev_dot(c, n, pv, q, &sc->pq, s);
-    k_cg_update<<<red_grid(n), kThreads, 0, s>>>(n, x, r, pv, q, sc, c.d_partials.p);
+    k_cg_update<<<red_grid(n), kThreads, 0, s>>>(n, x, r, pv, q, sc, c.d_partials.p, pre ? 0 : 1);
     check_launch();
-    k_cg_p<<<vgrid(n), kThreads, 0, s>>>(n, pv, r, sc);
+    if (pre) {
+      apply_precond(c, k.precond, r, z, k.transpose, s);
+      k_dot_beta<<<red_grid(n), kThreads, 0, s>>>(n, r, z, sc, c.d_partials.p);
+      check_launch();
+    }
+    k_cg_p<<<vgrid(n), kThreads, 0, s>>>(n, pv, z, sc);
     check_launch();
     ++res.iters;
-    if ((it + 1) % check_every == 0 || it + 1 == max_iter) {
-      rr = read_scalar(c, &sc->rr, s);
+    if ((it + 1) % check_every == 0 || it + 1 == k.max_iter) {
+      rr = read_scalar(c, &sc->rr_new, s);
       require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
-      if (std::sqrt(rr) <= rtol * res.bnorm) break;
+      if (std::sqrt(rr) <= k.rtol * res.bnorm) break;
     }
   }
   // true residual
-  apply_op(c, x, q, prec, false, s);
+  apply_op(c, x, q, k.prec, k.transpose, s);
   ++res.matvecs;
   vec_copy(n, b, r, s);
   vec_axpby(n, -1.0, q, 1.0, r, s);
   double tr = vec_dot_host(c, n, r, r, s);
   require(std::isfinite(tr), SDG_ENONFINITE, "non-finite residual");
   res.rel_res = std::sqrt(tr) / res.bnorm;
-  res.converged = res.rel_res <= rtol * 1.0000001 || std::sqrt(rr) <= rtol * res.bnorm;
+  res.converged = res.rel_res <= k.rtol;
   return res;
 }
 
 // ---------------------------------------------------------------- GMRES
 
-SolveResult solve_gmres(Ctx& c, const double* b, double* x, double rtol, int max_iter, int restart,
-                        int check_every, int prec, hipStream_t s) {
+// Restarted GMRES with right preconditioning (A P^-1 u = b, x = P^-1 u), so
+// the Arnoldi residual estimate is the true residual of the unpreconditioned
+// system.  Classical Gram-Schmidt with one reorthogonalisation.
+SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s) {
   SolveResult res;
   const int64_t n = c.n_slab;
-  const int m = std::max(1, std::min(restart, kMaxRestart));
+  const int m = std::max(1, std::min(k.restart, kMaxRestart));
   double* V = c.d_V.p;
   double* r = c.d_r.p;
   double* w = c.d_w.p;
+  double* t = c.d_t.p;
   DevScalars* sc = c.d_sc.p;
-  check_every = std::max(1, check_every);
+  const bool pre = k.precond != SDG_PRECOND_NONE;
+  const int check_every = std::max(1, k.check_every);
   res.bnorm = std::sqrt(vec_dot_host(c, n, b, b, s));
   require(std::isfinite(res.bnorm), SDG_ENONFINITE, "non-finite right-hand side");
   if (res.bnorm == 0.0) {
@@ -407,24 +494,29 @@ SolveResult solve_gmres(Ctx& c, const double* b, double* x, double rtol, int max
   const unsigned rg = red_grid(n), vg = vgrid(n);
   int total = 0;
   for (;;) {
-    // r = b - A x, beta = ||r||
-    apply_op(c, x, r, prec, false, s);
+    apply_op(c, x, r, k.prec, k.transpose, s);
     ++res.matvecs;
     vec_axpby(n, 1.0, b, -1.0, r, s);
     dev_dot(c, n, r, r, &sc->dots[0], s);
     double rr = read_scalar(c, &sc->dots[0], s);
     require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
     res.rel_res = std::sqrt(rr) / res.bnorm;
-    if (res.rel_res <= rtol) { res.converged = true; break; }
-    if (total >= max_iter) break;
+    if (debug_krylov()) std::fprintf(stderr, "[gmres] restart at it %d: true rel res %.3e\n", total, res.rel_res);
+    if (res.rel_res <= k.rtol) { res.converged = true; break; }
+    if (total >= k.max_iter) break;
     k_gmres_start<<<1, 64, 0, s>>>(sc);
     check_launch();
     k_scale_into<<<vg, kThreads, 0, s>>>(n, r, V, &sc->inv_norm);
     check_launch();
-    int k = 0;
-    for (int j = 0; j < m && total < max_iter; ++j) {
+    int kk = 0;
+    for (int j = 0; j < m && total < k.max_iter; ++j) {
       double* vj = V + (size_t)j * n;
-      apply_op(c, vj, w, prec, false, s);
+      if (pre) {
+        apply_precond(c, k.precond, vj, t, k.transpose, s);
+        apply_op(c, t, w, k.prec, k.transpose, s);
+      } else {
+        apply_op(c, vj, w, k.prec, k.transpose, s);
+      }
       ++res.matvecs;
       k_multidot<kMaxRestart><<<rg, kThreads, 0, s>>>(n, j + 1, V, w, sc, c.d_partials.p);
       check_launch();
@@ -436,17 +528,26 @@ SolveResult solve_gmres(Ctx& c, const double* b, double* x, double rtol, int max
       check_launch();
       ++total;
       ++res.iters;
-      k = j + 1;
+      kk = j + 1;
       if ((j + 1) % check_every == 0 || j + 1 == m) {
         double est = read_scalar(c, &sc->resid, s);
+        if (debug_krylov()) std::fprintf(stderr, "[gmres]   it %d est rel res %.3e\n", total, est / res.bnorm);
         require(std::isfinite(est), SDG_ENONFINITE, "non-finite residual estimate");
-        if (est <= rtol * res.bnorm) break;
+        if (est <= k.rtol * res.bnorm) break;
       }
     }
-    k_gmres_trisolve<<<1, 64, 0, s>>>(sc, k);
+    k_gmres_trisolve<<<1, 64, 0, s>>>(sc, kk);
     check_launch();
-    k_gmres_update<kMaxRestart><<<vg, kThreads, 0, s>>>(n, k, V, x, sc);
-    check_launch();
+    if (pre) {
+      vec_fill(n, 0.0, t, s);
+      k_gmres_update<kMaxRestart><<<vg, kThreads, 0, s>>>(n, kk, V, t, sc);
+      check_launch();
+      apply_precond(c, k.precond, t, w, k.transpose, s);
+      vec_axpby(n, 1.0, w, 1.0, x, s);
+    } else {
+      k_gmres_update<kMaxRestart><<<vg, kThreads, 0, s>>>(n, kk, V, x, sc);
+      check_launch();
+    }
   }
   return res;
 }

@@ -34,7 +34,7 @@ def build(name, precisions=None):
     ctx = sdg.Context(0)
     sizes = ctx.setup(mesh.xyz, mesh.elem, mesh.period, p, pg,
                       sdg.SDG_SCHEME_CN if scheme == "cn" else sdg.SDG_SCHEME_STDG, dt, lam, mu, rho,
-                      precisions or (sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32))
+                      precisions or (sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND))
     topo = Topology(mesh.xyz, mesh.elem, mesh.period)
     B = Blocks(topo, p, lam, mu, rho)
     slab = Slab(B, pg, dt, scheme)

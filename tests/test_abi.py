@@ -32,7 +32,7 @@ def test_struct_layouts_match_header():
     import ctypes
     # sdg_sizes: 8 int32, 7 int64, 1 double, 8 doubles, 2 int64, 2 int32
     assert ctypes.sizeof(sdg.Sizes) == 8 * 4 + 7 * 8 + 8 + 8 * 8 + 2 * 8 + 2 * 4
-    assert ctypes.sizeof(sdg.SolveOpts) == 4 + 4 + 8 + 4 * 4 + 8
+    assert ctypes.sizeof(sdg.SolveOpts) == 4 + 4 + 8 + 4 * 4 + 8 + 4 + 4
     assert ctypes.sizeof(sdg.SolveInfo) == 4 * 4 + 2 * 8
 
 
