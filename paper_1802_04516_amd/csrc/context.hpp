@@ -8,7 +8,7 @@
 namespace sdg {
 
 constexpr int kMaxRestart = 32;
-constexpr int kRedBlocks = 1024;  // grid size of the reduction kernels
+constexpr int kRedBlocks = 512;   // grid size of the reduction kernels
 constexpr int kRedSlots = 40;     // partial-sum slots per reduction block
 
 // Device-resident scalars of the Krylov solvers.
@@ -23,7 +23,6 @@ struct DevScalars {
   double h1[kMaxRestart + 1], h2[kMaxRestart + 1];
   double y[kMaxRestart];
   double dots[kRedSlots];
-  unsigned int ticket[4];
 };
 
 template <class T>
@@ -78,7 +77,7 @@ struct Ctx {
   // solver workspace
   DevBuf<double> d_V;                   // (restart+1) * n_slab   (GMRES) or 4 * n_slab (CG)
   DevBuf<double> d_x, d_b, d_r, d_w, d_t, d_d, d_e;
-  DevBuf<double> d_partials;            // kRedBlocks * kRedSlots
+  DevBuf<double> d_partials;            // kRedSlots * kRedBlocks, slot-major
   DevBuf<DevScalars> d_sc;
   double* h_pinned = nullptr;           // pinned host copy of a few scalars
   DevBuf<double> d_tmp_state, d_tmp_sig; // state-sized scratch (energy, back-substitution)

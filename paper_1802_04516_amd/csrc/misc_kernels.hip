@@ -53,15 +53,13 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
-// Partial energies per block -> partials[block]; last block writes out.
+// Partial energies per block -> partials[block]; k_energy_fin adds them.
 template <int D>
 __global__ void k_energy(int64_t n_elem, int64_t n_face, int nphi, int npsi, const double* __restrict__ Mref,
                          const double* __restrict__ ew, const double* __restrict__ flm,
-                         const double* __restrict__ v, const double* __restrict__ sig, double* partials,
-                         double* out, unsigned int* ticket) {
+                         const double* __restrict__ v, const double* __restrict__ sig, double* partials) {
   constexpr int NS = D * (D + 1) / 2;
   __shared__ double sh[16];
-  __shared__ bool last;
   double acc = 0.0;
   const int64_t nk = n_elem * D;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nk + n_face; i += (int64_t)gridDim.x * blockDim.x) {
@@ -105,17 +103,16 @@ __global__ void k_energy(int64_t n_elem, int64_t n_face, int nphi, int npsi, con
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
-    partials[blockIdx.x * kRedSlots] = s;
-    __threadfence();
-    last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    partials[blockIdx.x] = s;
   }
-  __syncthreads();
-  if (last && threadIdx.x == 0) {
-    __threadfence();
-    double s = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b) s += partials[b * kRedSlots];
-    *out = s;
-    *ticket = 0u;
+}
+
+__global__ void k_energy_fin(const double* partials, int nblocks, double* out) {
+  if (threadIdx.x < 64) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 64) v += partials[b];
+    v = wsum(v);
+    if (threadIdx.x == 0) *out = v;
   }
 }
 
@@ -171,10 +168,12 @@ void launch_energy(Ctx& c, const double* v, const double* sig, double* out_dev, 
   unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kT - 1) / kT, kRedBlocks));
   if (hs.dim == 2)
     k_energy<2><<<g, kT, 0, s>>>(hs.n_elem, hs.n_face, hs.nphi, hs.npsi, c.d_Mref.p, c.d_elem_w.p, c.d_face_lm.p, v,
-                                 sig, c.d_partials.p, out_dev, &c.d_sc.p->ticket[3]);
+                                 sig, c.d_partials.p);
   else
     k_energy<3><<<g, kT, 0, s>>>(hs.n_elem, hs.n_face, hs.nphi, hs.npsi, c.d_Mref.p, c.d_elem_w.p, c.d_face_lm.p, v,
-                                 sig, c.d_partials.p, out_dev, &c.d_sc.p->ticket[3]);
+                                 sig, c.d_partials.p);
+  SDG_HIP(hipGetLastError());
+  k_energy_fin<<<1, 64, 0, s>>>(c.d_partials.p, (int)g, out_dev);
   SDG_HIP(hipGetLastError());
 }
 

@@ -2,8 +2,8 @@
 // conjugate gradients for the symmetric positive definite Crank-Nicolson
 // system, matrix-free restarted GMRES for p_gamma > 0).
 //
-// All reductions are deterministic: each block writes a partial sum, and the
-// last block to finish (ticket counter) adds the partials in block order.
+// All reductions are deterministic: each block writes a partial sum and a
+// single-block finalize kernel adds the partials in a fixed order.
 // Scalars (alpha, beta, Hessenberg column, Givens rotations) stay in device
 // memory; the host reads one residual estimate every `check_every`
 // iterations.
@@ -39,32 +39,34 @@ __device__ inline double block_sum(double v, double* sh) {
   return r;
 }
 
-// Returns true in thread 0 of the last block to arrive.
-__device__ inline bool last_block(unsigned int* ticket) {
-  __shared__ bool am_last;
-  __threadfence();
-  if (threadIdx.x == 0) {
-    unsigned int t = atomicAdd(ticket, 1u);
-    am_last = (t == gridDim.x - 1);
+// Reductions are two launches: the producer kernel writes one partial sum
+// per block and slot, and a single-block finalize kernel adds them.  One
+// wavefront per slot: lane l adds blocks l, l+64, ..., then the wave adds the
+// 64 lane sums with a fixed shuffle tree, so results are deterministic and no
+// atomics are involved.
+__device__ inline void reduce_slots(const double* partials, int nblocks, int nslots, double* out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int sl = wid; sl < nslots; sl += nw) {
+    // slot-major layout: the wave's loads are contiguous and independent
+    const double* ps = partials + (size_t)sl * kRedBlocks;
+    double v0 = 0.0, v1 = 0.0;
+    int b = lane;
+    for (; b + 64 < nblocks; b += 128) { v0 += ps[b]; v1 += ps[b + 64]; }
+    if (b < nblocks) v0 += ps[b];
+    const double v = warp_sum(v0 + v1);
+    if (lane == 0) out[sl] = v;
   }
   __syncthreads();
-  return am_last;
-}
-
-// Finish a reduction in the last block: out[slot] = sum_b partials[b][slot].
-__device__ inline void finish_sums(const double* partials, int nslots, double* out, unsigned int* ticket) {
-  __threadfence();
-  for (int sl = threadIdx.x; sl < nslots; sl += blockDim.x) {
-    double s = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b) s += partials[(size_t)b * kRedSlots + sl];
-    out[sl] = s;
-  }
-  if (threadIdx.x == 0) *ticket = 0u;
 }
 
 unsigned red_grid(int64_t n) {
-  int64_t b = (n + kThreads - 1) / kThreads;
+  int64_t b = (n + 4 * kThreads - 1) / (4 * kThreads);
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, kRedBlocks));
+}
+
+// out[0..nslots) = sum of the producer's partials
+__global__ void k_finalize(const double* partials, int nblocks, int nslots, double* out) {
+  reduce_slots(partials, nblocks, nslots, out);
 }
 
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
@@ -83,25 +85,29 @@ __global__ void k_copy(int64_t n, const double* __restrict__ x, double* __restri
 }
 
 // out = x . y
-__global__ void k_dot(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
-                      double* partials, double* out, unsigned int* ticket) {
+__global__ void k_dot(int64_t n, const double* __restrict__ x, const double* __restrict__ y, double* partials) {
   __shared__ double sh[16];
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    acc += x[i] * y[i];
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kRedSlots] = acc;
-  if (last_block(ticket)) finish_sums(partials, 1, out, ticket);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    a0 += x[i] * y[i];
+    a1 += x[i + stride] * y[i + stride];
+    a2 += x[i + 2 * stride] * y[i + 2 * stride];
+    a3 += x[i + 3 * stride] * y[i + 3 * stride];
+  }
+  for (; i < n; i += stride) a0 += x[i] * y[i];
+  const double acc = block_sum((a0 + a1) + (a2 + a3), sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
 // ---------------------------------------------------------------- CG
 
-// x += alpha p, r -= alpha q with alpha = rz / pq; rr_new = r.r.  Without a
-// preconditioner (z = r) the last block also sets beta = rr_new / rz and
-// rz = rr_new.  sc->rr holds rz.
+// x += alpha p, r -= alpha q with alpha = rz / pq (sc->rr holds rz); the
+// partials of r.r go to slot 0.
 __global__ void k_cg_update(int64_t n, double* __restrict__ x, double* __restrict__ r,
                             const double* __restrict__ p, const double* __restrict__ q,
-                            DevScalars* sc, double* partials, int finish_beta) {
+                            const DevScalars* sc, double* partials) {
   __shared__ double sh[16];
   const double alpha = sc->rr / sc->pq;
   double acc = 0.0;
@@ -112,41 +118,66 @@ __global__ void k_cg_update(int64_t n, double* __restrict__ x, double* __restric
     acc += ri * ri;
   }
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kRedSlots] = acc;
-  if (last_block(&sc->ticket[0])) {
-    __threadfence();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (unsigned b = 0; b < gridDim.x; ++b) s += partials[(size_t)b * kRedSlots];
-      sc->alpha = alpha;
-      sc->rr_new = s;
-      if (finish_beta) {
-        sc->beta = s / sc->rr;
-        sc->rr = s;
-      }
-      sc->ticket[0] = 0u;
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+// rr_new = sum partials; without a preconditioner also beta = rr_new / rz and
+// rz = rr_new.
+__global__ void k_cg_update_fin(const double* partials, int nblocks, DevScalars* sc, int finish_beta) {
+  __shared__ double tot;
+  reduce_slots(partials, nblocks, 1, &tot);
+  if (threadIdx.x == 0) {
+    sc->alpha = sc->rr / sc->pq;
+    sc->rr_new = tot;
+    if (finish_beta) {
+      sc->beta = tot / sc->rr;
+      sc->rr = tot;
     }
   }
 }
 
-// rz_new = r . z; beta = rz_new / rz; rz = rz_new (preconditioned CG)
-__global__ void k_dot_beta(int64_t n, const double* __restrict__ r, const double* __restrict__ z, DevScalars* sc,
-                           double* partials) {
-  __shared__ double sh[16];
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    acc += r[i] * z[i];
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kRedSlots] = acc;
-  if (last_block(&sc->ticket[0])) {
-    __threadfence();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (unsigned b = 0; b < gridDim.x; ++b) s += partials[(size_t)b * kRedSlots];
-      sc->beta = s / sc->rr;
-      sc->rr = s;
-      sc->ticket[0] = 0u;
+// beta = (r . z)_new / rz and rz = (r . z)_new (preconditioned CG)
+__global__ void k_dot_beta_fin(const double* partials, int nblocks, DevScalars* sc) {
+  __shared__ double tot;
+  reduce_slots(partials, nblocks, 1, &tot);
+  if (threadIdx.x == 0) {
+    sc->beta = tot / sc->rr;
+    sc->rr = tot;
+  }
+}
+
+// y = P x, 4 consecutive rows per thread with 16-byte loads (nv % 4 == 0);
+// one workgroup holds several elements' x in LDS.
+__global__ __launch_bounds__(256) void k_block_apply4(int64_t n_elem, int nv, const float* __restrict__ P,
+                                                      const double* __restrict__ x, double* __restrict__ y) {
+  extern __shared__ double sx[];
+  const int tpe = nv / 4;              // threads per element
+  const int epb = blockDim.x / tpe;    // elements per workgroup pass
+  const int le = threadIdx.x / tpe, r4 = threadIdx.x % tpe;
+  for (int64_t e0 = (int64_t)blockIdx.x * epb; e0 < n_elem; e0 += (int64_t)gridDim.x * epb) {
+    const int ne = (int)min((int64_t)epb, n_elem - e0);
+    for (int i = threadIdx.x; i < ne * nv; i += blockDim.x) sx[i] = x[e0 * nv + i];
+    __syncthreads();
+    if (le < ne) {
+      const float4* Pe = reinterpret_cast<const float4*>(P + (size_t)(e0 + le) * nv * nv) + r4;
+      const double* xe = sx + le * nv;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 4
+      for (int col = 0; col < nv; ++col) {
+        const float4 p4 = Pe[(size_t)col * tpe];
+        const double xv = xe[col];
+        a0 += (double)p4.x * xv;
+        a1 += (double)p4.y * xv;
+        a2 += (double)p4.z * xv;
+        a3 += (double)p4.w * xv;
+      }
+      double* ye = y + (e0 + le) * nv + 4 * r4;
+      ye[0] = a0;
+      ye[1] = a1;
+      ye[2] = a2;
+      ye[3] = a3;
     }
+    __syncthreads();
   }
 }
 
@@ -182,7 +213,7 @@ __global__ void k_cg_p(int64_t n, double* __restrict__ p, const double* __restri
 // h1[i] = V_i . w for i <= j (classical Gram-Schmidt projections)
 template <int MAXJ>
 __global__ void k_multidot(int64_t n, int nj, const double* __restrict__ V, const double* __restrict__ w,
-                           DevScalars* sc, double* partials) {
+                           double* partials) {
   __shared__ double sh[16];
   double acc[MAXJ];
 #pragma unroll
@@ -197,16 +228,15 @@ __global__ void k_multidot(int64_t n, int nj, const double* __restrict__ V, cons
   for (int i = 0; i < MAXJ; ++i) {
     if (i < nj) {
       double s = block_sum(acc[i], sh);
-      if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kRedSlots + i] = s;
+      if (threadIdx.x == 0) partials[(size_t)i * kRedBlocks + blockIdx.x] = s;
     }
   }
-  if (last_block(&sc->ticket[1])) finish_sums(partials, nj, sc->h1, &sc->ticket[1]);
 }
 
 // w -= V h1, then h2[i] = V_i . w (second Gram-Schmidt pass)
 template <int MAXJ>
 __global__ void k_cgs_pass(int64_t n, int nj, const double* __restrict__ V, double* __restrict__ w,
-                           DevScalars* sc, double* partials) {
+                           const DevScalars* sc, double* partials) {
   __shared__ double sh[16];
   __shared__ double hs[MAXJ];
   if (threadIdx.x < nj) hs[threadIdx.x] = sc->h1[threadIdx.x];
@@ -229,17 +259,15 @@ __global__ void k_cgs_pass(int64_t n, int nj, const double* __restrict__ V, doub
   for (int i = 0; i < MAXJ; ++i) {
     if (i < nj) {
       double s = block_sum(acc[i], sh);
-      if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kRedSlots + i] = s;
+      if (threadIdx.x == 0) partials[(size_t)i * kRedBlocks + blockIdx.x] = s;
     }
   }
-  if (last_block(&sc->ticket[1])) finish_sums(partials, nj, sc->h2, &sc->ticket[1]);
 }
 
-// w -= V h2, norm^2 = w.w; the last block completes the Hessenberg column j,
-// applies the previous Givens rotations, forms the new one and updates g.
+// w -= V h2 and partials of w.w.
 template <int MAXJ>
 __global__ void k_cgs_final(int64_t n, int nj, const double* __restrict__ V, double* __restrict__ w,
-                            DevScalars* sc, double* partials) {
+                            const DevScalars* sc, double* partials) {
   __shared__ double sh[16];
   __shared__ double hs[MAXJ];
   if (threadIdx.x < nj) hs[threadIdx.x] = sc->h2[threadIdx.x];
@@ -254,38 +282,40 @@ __global__ void k_cgs_final(int64_t n, int nj, const double* __restrict__ V, dou
     acc += wt * wt;
   }
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kRedSlots] = acc;
-  if (last_block(&sc->ticket[2])) {
-    __threadfence();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (unsigned b = 0; b < gridDim.x; ++b) s += partials[(size_t)b * kRedSlots];
-      const int j = nj - 1;
-      const int ld = kMaxRestart + 1;
-      double* Hc = sc->H + (size_t)j * ld;
-      for (int i = 0; i < nj; ++i) Hc[i] = sc->h1[i] + sc->h2[i];
-      const double nrm = sqrt(s);
-      Hc[j + 1] = nrm;
-      sc->norm = nrm;
-      sc->inv_norm = nrm > 0.0 ? 1.0 / nrm : 0.0;
-      for (int i = 0; i < j; ++i) {
-        const double a = Hc[i], b = Hc[i + 1];
-        Hc[i] = sc->cs[i] * a + sc->sn[i] * b;
-        Hc[i + 1] = -sc->sn[i] * a + sc->cs[i] * b;
-      }
-      const double a = Hc[j], b = Hc[j + 1];
-      const double rad = hypot(a, b);
-      const double c = rad > 0.0 ? a / rad : 1.0, sn = rad > 0.0 ? b / rad : 0.0;
-      sc->cs[j] = c;
-      sc->sn[j] = sn;
-      Hc[j] = rad;
-      Hc[j + 1] = 0.0;
-      const double gj = sc->g[j];
-      sc->g[j] = c * gj;
-      sc->g[j + 1] = -sn * gj;
-      sc->resid = fabs(sc->g[j + 1]);
-      sc->ticket[2] = 0u;
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+// Completes the Hessenberg column j (h1 + h2 and the new norm), applies the
+// previous Givens rotations, forms the new one and updates g.
+__global__ void k_cgs_final_fin(const double* partials, int nblocks, int nj, DevScalars* sc) {
+  __shared__ double tot;
+  reduce_slots(partials, nblocks, 1, &tot);
+  if (threadIdx.x == 0) {
+    const double s = tot;
+    const int j = nj - 1;
+    const int ld = kMaxRestart + 1;
+    double* Hc = sc->H + (size_t)j * ld;
+    for (int i = 0; i < nj; ++i) Hc[i] = sc->h1[i] + sc->h2[i];
+    const double nrm = sqrt(s);
+    Hc[j + 1] = nrm;
+    sc->norm = nrm;
+    sc->inv_norm = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int i = 0; i < j; ++i) {
+      const double a = Hc[i], b = Hc[i + 1];
+      Hc[i] = sc->cs[i] * a + sc->sn[i] * b;
+      Hc[i + 1] = -sc->sn[i] * a + sc->cs[i] * b;
     }
+    const double a = Hc[j], b = Hc[j + 1];
+    const double rad = hypot(a, b);
+    const double c = rad > 0.0 ? a / rad : 1.0, sn = rad > 0.0 ? b / rad : 0.0;
+    sc->cs[j] = c;
+    sc->sn[j] = sn;
+    Hc[j] = rad;
+    Hc[j + 1] = 0.0;
+    const double gj = sc->g[j];
+    sc->g[j] = c * gj;
+    sc->g[j + 1] = -sn * gj;
+    sc->resid = fabs(sc->g[j + 1]);
   }
 }
 
@@ -374,7 +404,10 @@ void vec_copy(int64_t n, const double* x, double* y, hipStream_t s) {
 }
 
 static void dev_dot(Ctx& c, int64_t n, const double* x, const double* y, double* out, hipStream_t s) {
-  k_dot<<<red_grid(n), kThreads, 0, s>>>(n, x, y, c.d_partials.p, out, &c.d_sc.p->ticket[3]);
+  const unsigned g = red_grid(n);
+  k_dot<<<g, kThreads, 0, s>>>(n, x, y, c.d_partials.p);
+  check_launch();
+  k_finalize<<<1, 512, 0, s>>>(c.d_partials.p, (int)g, 1, out);
   check_launch();
 }
 
@@ -389,6 +422,14 @@ static double read_scalar_dot(Ctx& c, int64_t n, const double* r, hipStream_t s)
 
 void launch_block_apply(int64_t n_elem, int nv, const float* P, const double* x, double* y, bool transpose,
                         hipStream_t s) {
+  if (!transpose && nv % 4 == 0 && nv / 4 <= 256) {
+    const int epb = 256 / (nv / 4);
+    const int64_t groups = (n_elem + epb - 1) / epb;
+    const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 65535));
+    k_block_apply4<<<g, 256, (size_t)epb * nv * sizeof(double), s>>>(n_elem, nv, P, x, y);
+    check_launch();
+    return;
+  }
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_elem, 65535));
   const int t = nv <= 64 ? 64 : (nv <= 128 ? 128 : 256);
   k_block_apply<<<g, t, nv * sizeof(double), s>>>(n_elem, nv, P, x, y, transpose ? 1 : 0);
@@ -440,11 +481,16 @@ SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hip
     apply_op(c, pv, q, k.prec, k.transpose, s);
     ++res.matvecs;
     dev_dot(c, n, pv, q, &sc->pq, s);
-    k_cg_update<<<red_grid(n), kThreads, 0, s>>>(n, x, r, pv, q, sc, c.d_partials.p, pre ? 0 : 1);
+    const unsigned g = red_grid(n);
+    k_cg_update<<<g, kThreads, 0, s>>>(n, x, r, pv, q, sc, c.d_partials.p);
+    check_launch();
+    k_cg_update_fin<<<1, kThreads, 0, s>>>(c.d_partials.p, (int)g, sc, pre ? 0 : 1);
     check_launch();
     if (pre) {
       apply_precond(c, k.precond, r, z, k.transpose, s);
-      k_dot_beta<<<red_grid(n), kThreads, 0, s>>>(n, r, z, sc, c.d_partials.p);
+      k_dot<<<g, kThreads, 0, s>>>(n, r, z, c.d_partials.p);
+      check_launch();
+      k_dot_beta_fin<<<1, kThreads, 0, s>>>(c.d_partials.p, (int)g, sc);
       check_launch();
     }
     k_cg_p<<<vgrid(n), kThreads, 0, s>>>(n, pv, z, sc);
@@ -518,11 +564,17 @@ SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, 
         apply_op(c, vj, w, k.prec, k.transpose, s);
       }
       ++res.matvecs;
-      k_multidot<kMaxRestart><<<rg, kThreads, 0, s>>>(n, j + 1, V, w, sc, c.d_partials.p);
+      k_multidot<kMaxRestart><<<rg, kThreads, 0, s>>>(n, j + 1, V, w, c.d_partials.p);
+      check_launch();
+      k_finalize<<<1, 512, 0, s>>>(c.d_partials.p, (int)rg, j + 1, sc->h1);
       check_launch();
       k_cgs_pass<kMaxRestart><<<rg, kThreads, 0, s>>>(n, j + 1, V, w, sc, c.d_partials.p);
       check_launch();
+      k_finalize<<<1, 512, 0, s>>>(c.d_partials.p, (int)rg, j + 1, sc->h2);
+      check_launch();
       k_cgs_final<kMaxRestart><<<rg, kThreads, 0, s>>>(n, j + 1, V, w, sc, c.d_partials.p);
+      check_launch();
+      k_cgs_final_fin<<<1, kThreads, 0, s>>>(c.d_partials.p, (int)rg, j + 1, sc);
       check_launch();
       k_scale_into<<<vg, kThreads, 0, s>>>(n, w, V + (size_t)(j + 1) * n, &sc->inv_norm);
       check_launch();
