@@ -104,7 +104,11 @@ typedef struct {
   int64_t op_bytes_f64;   /* bytes of the stored FP64 operator blocks  */
   int64_t op_bytes_f32;
   int32_t max_rhs;        /* largest n_rhs accepted by the apply calls */
+  int32_t op_variant;     /* face-kernel variant in use for FP64 (see sdg_set_operator_variant) */
+  int32_t op_variant_f32;
   int32_t pad;
+  double tune_us_f64[3];  /* autotuner timings of the variants (microseconds per apply) */
+  double tune_us_f32[3];
 } sdg_sizes;
 
 typedef struct {
@@ -171,6 +175,14 @@ int sdg_set_material(sdg_ctx* ctx, const double* lambda, const double* mu, const
 int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs);
 
 int sdg_query(const sdg_ctx* ctx, sdg_sizes* out);
+
+/* Face-kernel variant of the operator apply: 0 = LDS kernel with flat
+ * loops, 1 = register-tiled kernel with the most faces per workgroup that
+ * fit in 64 KiB of LDS, 2 = register-tiled with half as many; -1 reruns the
+ * autotuner (sdg_assemble runs it: every variant is timed on the assembled
+ * operator and the fastest kept, per precision).  All variants compute the
+ * same operator. */
+int sdg_set_operator_variant(sdg_ctx* ctx, int variant);
 
 /* Face table in the library's face order (host arrays of n_face entries):
  * left element, its local face, right element (-1 on the boundary), its

@@ -1,6 +1,7 @@
 // C-ABI entry points (include/sdg.h): context lifecycle, assembly, operator
 // application, one implicit time step, energy and point evaluation.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -105,6 +106,7 @@ void check_prec(Ctx& c, int prec) {
 
 void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s) {
   OpArgs a = base_args(c, prec);
+  a.variant = prec == SDG_PREC_F32 ? c.variant32 : c.variant64;
   a.v = v;
   a.z = c.d_z.p;
   a.y = y;
@@ -114,6 +116,39 @@ void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipS
   SDG_HIP(hipGetLastError());
   launch_elem(c.hs.dim, c.hs.p, c.hs.ng, a, s);
   SDG_HIP(hipGetLastError());
+}
+
+// Time every face-kernel variant on the assembled operator and keep the
+// fastest per precision (the project's tile-shape autotuner).
+static void autotune(Ctx& c) {
+  hipStream_t s = nullptr;
+  hipEvent_t e0, e1;
+  SDG_HIP(hipEventCreate(&e0));
+  SDG_HIP(hipEventCreate(&e1));
+  vec_fill(c.n_slab, 1.0, c.d_x.p, s);
+  for (int pi = 0; pi < 2; ++pi) {
+    const int prec = pi == 0 ? SDG_PREC_F64 : SDG_PREC_F32;
+    if (!(c.precisions & prec)) continue;
+    int best = 0;
+    double best_t = 1e30;
+    for (int var = 0; var <= 2; ++var) {
+      if (pi == 0) c.variant64 = var; else c.variant32 = var;
+      for (int w = 0; w < 3; ++w) apply_op(c, c.d_x.p, c.d_r.p, prec, false, s);
+      SDG_HIP(hipEventRecord(e0, s));
+      const int reps = 10;
+      for (int w = 0; w < reps; ++w) apply_op(c, c.d_x.p, c.d_r.p, prec, false, s);
+      SDG_HIP(hipEventRecord(e1, s));
+      SDG_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      SDG_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const double us = 1e3 * ms / reps;
+      c.tune_us[pi][var] = us;
+      if (us < best_t) { best_t = us; best = var; }
+    }
+    if (pi == 0) c.variant64 = best; else c.variant32 = best;
+  }
+  SDG_HIP(hipEventDestroy(e0));
+  SDG_HIP(hipEventDestroy(e1));
 }
 
 void apply_precond(Ctx& c, int kind, const double* x, double* y, bool transpose, hipStream_t s) {
@@ -342,6 +377,23 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     c.d_src_amp.alloc((size_t)std::max<int64_t>(c.n_src, 1) * ng);
     SDG_HIP(hipDeviceSynchronize());
     c.assembled = true;
+    const char* forced = std::getenv("SDG_OP_VARIANT");
+    if (forced) {
+      c.variant64 = c.variant32 = std::max(0, std::min(2, std::atoi(forced)));
+    } else {
+      autotune(c);
+    }
+  });
+}
+
+int sdg_set_operator_variant(sdg_ctx* ctx, int variant) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.assembled, SDG_ESTATE, "assemble first");
+    require(variant >= -1 && variant <= 2, SDG_EINVAL, "variant must be -1 (autotune), 0, 1 or 2");
+    SDG_HIP(hipSetDevice(c.device));
+    if (variant < 0) autotune(c);
+    else c.variant64 = c.variant32 = variant;
   });
 }
 
@@ -375,6 +427,9 @@ int sdg_query(const sdg_ctx* ctx, sdg_sizes* out) {
     out->op_bytes_f64 = nblk * blk * 8;
     out->op_bytes_f32 = nblk * blk * 4;
     out->max_rhs = c.max_rhs;
+    out->op_variant = c.variant64;
+    out->op_variant_f32 = c.variant32;
+    for (int v = 0; v < 3; ++v) { out->tune_us_f64[v] = c.tune_us[0][v]; out->tune_us_f32[v] = c.tune_us[1][v]; }
   });
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -120,6 +121,8 @@ struct OpArgs {
   int mass_identity;       // element kernel: y = Tm[a] v instead of Tm (x) w Mref v
   int v_spatial;           // element kernel: v has no time axis (mass applied with Tm[:,0])
   double y_scale;          // element kernel: y = y_scale * (...) (reserved, 1.0)
+  int variant;             // operator face kernel: 0 = LDS flat loops, 1 = register-tiled
+                           // with the most faces per block, 2 = register-tiled, half of it
   Coefs c;
 };
 

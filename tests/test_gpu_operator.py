@@ -76,6 +76,26 @@ def test_apply_matches_oracle_schur(case):
     assert np.abs(per).max() <= 1e-12 * np.abs(ref).max() * 10
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_every_face_kernel_variant_matches_oracle(case, variant):
+    """Each face-kernel variant the autotuner may pick is held to the same
+    bar, in FP64 and FP32, on the forward operator and its transpose."""
+    import paper_1802_04516_amd as sdg
+    ctx = case["ctx"]
+    ctx.set_operator_variant(variant)
+    try:
+        rng = np.random.default_rng(99 + variant)
+        v = rng.standard_normal(case["slab"].nv)
+        ref = case["S"] @ v
+        assert rel(_apply(case, v), ref) <= 1e-12
+        assert rel(_apply(case, v, sdg.SDG_PREC_F32), ref) <= 2e-6
+        assert rel(_apply(case, v, adjoint=True), case["S"].T @ v) <= 1e-12
+    finally:
+        s = ctx.set_operator_variant(-1)
+    assert s["op_variant"] in (0, 1, 2) and s["op_variant_f32"] in (0, 1, 2)
+    assert all(t > 0 for t in s["tune_us_f64"])
+
+
 def test_apply_fp32_operator_error(case):
     import paper_1802_04516_amd as sdg
     rng = np.random.default_rng(99)
