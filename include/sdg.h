@@ -241,6 +241,41 @@ int sdg_sample_velocity(sdg_ctx* ctx, const double* v_state, int n_rhs, int64_t 
 int sdg_eval_stress(sdg_ctx* ctx, const double* sigma_state, int n_rhs, int64_t n_pts,
                     const double* pts, const int64_t* face, double* out, void* stream);
 
+/* Discrete adjoint of one implicit step (Lagrangian method applied to the
+ * slab system of eqs. NM25/NM26, or NM25.cn/NM26.cn).  Write the step as
+ *   A(theta) X = Bm(theta) u_old + F,   u_new = Ex X,
+ * with X the slab DOFs, u = (v, sigma) the states at t^{n,-} and t^{n+1,-},
+ * theta the per-element lambda, mu, rho.  Given the adjoint of the new state
+ * ubar_new = (vbar, sigma_bar) (device; velocity [elem][c][k], stress
+ * [face][s][m] in the canonical dual basis, i.e. dJ/du_new including the
+ * misfit terms at t^{n+1,-}), this call
+ *   1. forms the right-hand side Ex^T ubar_new of the transposed system
+ *      reduced to the velocity unknowns;
+ *   2. solves A_v^T L_v = b with the Krylov method of opts (FP64 only;
+ *      the velocity operator is the transpose of eq. (velocity.sys));
+ *   3. back-substitutes the stress multipliers L_s;
+ *   4. adds to grad (device, [3][n_elem]: lambda, mu, rho) the term
+ *      L^T (dBm/dtheta u_old - dA/dtheta X).  The face parameters are the
+ *      volume-weighted element parameters of the two sub-triangles of the
+ *      dual cell, so face gradients are passed to the elements with the
+ *      weights |T_{i,j}|/|R_j|;
+ *   5. overwrites vbar, sigma_bar with Bm^T L = the adjoint of u_old.
+ * v_old (device [elem][c][k]) is the forward state at t^{n,-} and v_slab
+ * (device [elem][a][c][k]) the forward velocity slab of the step, as
+ * returned in sdg_solve_step's v_slab.  The source term does not depend on
+ * theta.  On SDG_ENOCONV the outputs hold the values from the last iterate
+ * and *info is filled. */
+int sdg_adjoint_step(sdg_ctx* ctx, const double* v_old, const double* v_slab, double* vbar,
+                     double* sigma_bar, double* grad, const sdg_solve_opts* opts,
+                     sdg_solve_info* info, void* stream);
+
+/* Transpose of sdg_sample_velocity: vbar[e(x_q)][c][k] += phi_k(x_q)
+ * obs_bar[q][c] for the host points pts[n_pts*dim] (obs_bar device
+ * [pt][c], vbar device [elem][c][k]).  Points are processed in order, so the
+ * result is deterministic when several lie in one element. */
+int sdg_sample_velocity_adjoint(sdg_ctx* ctx, int n_rhs, int64_t n_pts, const double* pts,
+                                const double* obs_bar, double* vbar, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

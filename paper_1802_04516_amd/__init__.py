@@ -35,7 +35,8 @@ _ERRNAMES = {SDG_EINVAL: "EINVAL", SDG_ENOMEM: "ENOMEM", SDG_EDEVICE: "EDEVICE",
 EXPORTED = ("sdg_last_error", "sdg_create", "sdg_destroy", "sdg_set_mesh", "sdg_set_discretization",
             "sdg_set_material", "sdg_assemble", "sdg_query", "sdg_set_operator_variant", "sdg_face_table",
             "sdg_apply_velocity_operator", "sdg_apply_adjoint", "sdg_set_sources", "sdg_solve_step",
-            "sdg_energy", "sdg_sample_velocity", "sdg_eval_stress")
+            "sdg_energy", "sdg_sample_velocity", "sdg_eval_stress", "sdg_adjoint_step",
+            "sdg_sample_velocity_adjoint")
 
 
 class SdgError(RuntimeError):
@@ -103,6 +104,8 @@ def lib():
         "sdg_energy": ([_P, _P, _P, i, _DP, _P], i),
         "sdg_sample_velocity": ([_P, _P, i, ctypes.c_int64, _DP, _P, _P], i),
         "sdg_eval_stress": ([_P, _P, i, ctypes.c_int64, _DP, _I64P, _P, _P], i),
+        "sdg_adjoint_step": ([_P, _P, _P, _P, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P], i),
+        "sdg_sample_velocity_adjoint": ([_P, i, ctypes.c_int64, _DP, _P, _P, _P], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -235,6 +238,25 @@ def sdg_solve_step(h, v_state, sigma_state, amp=None, n_rhs=1, opts: SolveOpts |
     return res
 
 
+def sdg_adjoint_step(h, v_old, v_slab, vbar, sigma_bar, grad, opts: SolveOpts | None = None, stream=None):
+    """One backward step of the discrete adjoint; vbar, sigma_bar are
+    overwritten with the adjoint of the start-of-step state and grad
+    ([3, n_elem]: lambda, mu, rho) is accumulated."""
+    opts = opts or SolveOpts(SDG_SOLVER_AUTO, SDG_PREC_F64, 1e-12, 2000, 30, 5, 10, 1e-4, SDG_PRECOND_MASS)
+    info = SolveInfo()
+    _check(lib().sdg_adjoint_step(h, _dev(v_old, name="v_old"), _dev(v_slab, name="v_slab"), _dev(vbar, name="vbar"),
+                                  _dev(sigma_bar, name="sigma_bar"), _dev(grad, name="grad"), ctypes.byref(opts),
+                                  ctypes.byref(info), _stream(stream)))
+    return {f: getattr(info, f) for f, _ in SolveInfo._fields_}
+
+
+def sdg_sample_velocity_adjoint(h, pts, obs_bar, vbar, n_rhs=1, stream=None):
+    pts = _host(pts, np.float64)
+    _check(lib().sdg_sample_velocity_adjoint(h, n_rhs, pts.shape[0], _hp(pts, ctypes.c_double),
+                                             _dev(obs_bar, name="obs_bar"), _dev(vbar, name="vbar"),
+                                             _stream(stream)))
+
+
 def sdg_energy(h, v_state, sigma_state, n_rhs=1, stream=None):
     out = np.zeros(n_rhs)
     _check(lib().sdg_energy(h, _dev(v_state, name="v_state"), _dev(sigma_state, name="sigma_state"), n_rhs,
@@ -318,3 +340,17 @@ class Context:
 
     def energy(self, v_state, sigma_state):
         return float(sdg_energy(self.h, v_state, sigma_state)[0])
+
+    def adjoint_step(self, v_old, v_slab, vbar, sigma_bar, grad, opts=None, stream=None):
+        _dev(v_old, self._n("n_vel_state"), "v_old")
+        _dev(v_slab, self._n("n_vel_slab"), "v_slab")
+        _dev(vbar, self._n("n_vel_state"), "vbar")
+        _dev(sigma_bar, self._n("n_stress_state"), "sigma_bar")
+        _dev(grad, 3 * self._n("n_elem"), "grad")
+        return sdg_adjoint_step(self.h, v_old, v_slab, vbar, sigma_bar, grad, opts, stream)
+
+    def sample_adjoint(self, pts, obs_bar, vbar, stream=None):
+        pts = np.asarray(pts, np.float64)
+        _dev(obs_bar, pts.shape[0] * self._n("dim"), "obs_bar")
+        _dev(vbar, self._n("n_vel_state"), "vbar")
+        sdg_sample_velocity_adjoint(self.h, pts, obs_bar, vbar, stream=stream)

@@ -355,6 +355,34 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
       SDG_HIP(hipMemcpy(c.d_tw.p, tw.data(), ng * sizeof(double), hipMemcpyHostToDevice));
       c.d_e1.alloc(ng);
       SDG_HIP(hipMemcpy(c.d_e1.p, hs.e1.data(), ng * sizeof(double), hipMemcpyHostToDevice));
+      std::vector<double> e0(ng, 1.0);
+      if (c.scheme != SDG_SCHEME_CN) e0 = hs.e0;
+      c.d_e0.alloc(ng);
+      SDG_HIP(hipMemcpy(c.d_e0.p, e0.data(), ng * sizeof(double), hipMemcpyHostToDevice));
+    }
+    // adjoint: element -> face table with the volume fraction of the element
+    // in the dual cell of each of its faces
+    {
+      const int nfe = d + 1;
+      std::vector<double> wt((size_t)hs.n_elem * nfe, 0.0);
+      for (int64_t e = 0; e < hs.n_elem; ++e)
+        for (int f = 0; f < nfe; ++f) {
+          const int64_t j = hs.elem_face[e * nfe + f];
+          require(j >= 0 && j < hs.n_face, SDG_EMESH, "element face without a face record");
+          const FaceRec& fr = hs.faces[j];
+          if (fr.left == e && fr.lf == f) wt[e * nfe + f] = hs.face_wt[2 * j];
+          else if (fr.right == e && fr.rf == f) wt[e * nfe + f] = hs.face_wt[2 * j + 1];
+          else throw Error(SDG_EMESH, "element-face table is inconsistent");
+        }
+      c.d_ef_wt.alloc(wt.size());
+      SDG_HIP(hipMemcpy(c.d_ef_wt.p, wt.data(), wt.size() * sizeof(double), hipMemcpyHostToDevice));
+      c.d_elem_face.alloc(hs.elem_face.size());
+      SDG_HIP(hipMemcpy(c.d_elem_face.p, hs.elem_face.data(), hs.elem_face.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice));
+      c.d_detJ.alloc(hs.n_elem);
+      SDG_HIP(hipMemcpy(c.d_detJ.p, hs.elem_detJ.data(), hs.n_elem * sizeof(double), hipMemcpyHostToDevice));
+      c.d_lam_s.alloc((size_t)hs.n_face * ng * hs.nsig * hs.npsi);
+      c.d_face_grad.alloc((size_t)hs.n_face * 2);
     }
 
     // workspaces
@@ -667,6 +695,221 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     info->b_norm = res.bnorm;
   }
   return rc;
+}
+
+int sdg_adjoint_step(sdg_ctx* ctx, const double* v_old, const double* v_slab, double* vbar, double* sigma_bar,
+                     double* grad, const sdg_solve_opts* opts, sdg_solve_info* info, void* stream) {
+  SolveResult res;
+  int rc = guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.assembled, SDG_ESTATE, "assemble first");
+    require(v_old && v_slab && vbar && sigma_bar && grad && opts, SDG_EINVAL, "null argument");
+    require(opts->rtol > 0 && opts->max_iter > 0, SDG_EINVAL, "rtol and max_iter must be positive");
+    require(opts->precision == 0 || opts->precision == SDG_PREC_F64, SDG_EUNSUPPORTED,
+            "the adjoint step runs in FP64");
+    check_prec(c, SDG_PREC_F64);
+    int solver = opts->solver;
+    if (solver == SDG_SOLVER_AUTO) solver = c.scheme == SDG_SCHEME_CN ? SDG_SOLVER_CG : SDG_SOLVER_GMRES;
+    require(solver == SDG_SOLVER_CG || solver == SDG_SOLVER_GMRES, SDG_EINVAL, "unknown solver");
+    require(solver != SDG_SOLVER_GMRES || c.d_V.n >= (size_t)(kMaxRestart + 1) * c.n_slab, SDG_EINVAL,
+            "GMRES workspace is only allocated for the space-time scheme");
+    const int restart = opts->restart > 0 ? opts->restart : 30;
+    require(restart <= kMaxRestart, SDG_EINVAL, "restart must be <= 32");
+    require(opts->precond >= SDG_PRECOND_NONE && opts->precond <= SDG_PRECOND_BLOCK, SDG_EINVAL,
+            "unknown preconditioner");
+    SDG_HIP(hipSetDevice(c.device));
+    hipStream_t s = (hipStream_t)stream;
+    const HostSetup& hs = c.hs;
+    const int d = hs.dim, ng = hs.ng, nvs = d * hs.nphi;
+    const int64_t ne = hs.n_elem;
+    const double dt = hs.dt;
+    const bool cn = c.scheme == SDG_SCHEME_CN;
+    std::vector<double> TiT(ng * ng, 1.0);
+    if (!cn) {
+      std::vector<double> Ti = inverse(hs.T, ng);
+      for (int a = 0; a < ng; ++a)
+        for (int b = 0; b < ng; ++b) TiT[a * ng + b] = Ti[b * ng + a];
+    }
+    auto tite1 = [&](int a) {
+      double q = 0.0;
+      for (int b = 0; b < ng; ++b) q += TiT[a * ng + b] * hs.e1[b];
+      return q;
+    };
+
+    // 1. right-hand side of the transposed velocity system:
+    //    space-time  b_a = e1_a vbar - dt w_a (T^-T e1)_a D E^T sbar
+    //    Crank-Nicolson  b = vbar - dt/2 D E^T sbar
+    {
+      OpArgs f = base_args(c, SDG_PREC_F64);
+      f.sig_in = sigma_bar;
+      f.sig_in_Et = 1;
+      f.z = c.d_z.p;
+      f.use_g = 0;
+      f.c.Cs[0] = 1.0;
+      launch_face(d, hs.p, 1, SDG_PREC_F64, kScatter, f, s);
+      OpArgs e = base_args(c, SDG_PREC_F64);
+      e.v = vbar;
+      e.v_spatial = 1;
+      e.mass_identity = 1;
+      e.z = c.d_z.p;
+      e.y = c.d_b.p;
+      if (cn) {
+        e.c.Tm[0] = 1.0;
+        e.c.Cs[0] = -dt / 2.0;
+      } else {
+        for (int a = 0; a < ng; ++a) {
+          e.c.Tm[a * ng] = hs.e1[a];
+          e.c.Cs[a] = -dt * hs.w[a] * tite1(a);
+        }
+      }
+      launch_elem(d, hs.p, ng, e, s);
+      SDG_HIP(hipGetLastError());
+    }
+
+    // 2. Krylov solve of A^T L_v = b (zero initial guess)
+    vec_fill(c.n_slab, 0.0, c.d_x.p, s);
+    KrylovCfg kc;
+    kc.check_every = opts->check_every > 0 ? opts->check_every : 5;
+    kc.restart = restart;
+    kc.precond = opts->precond;
+    kc.rtol = opts->rtol;
+    kc.max_iter = opts->max_iter;
+    kc.prec = SDG_PREC_F64;
+    kc.transpose = true;
+    res = solver == SDG_SOLVER_CG ? solve_cg(c, c.d_b.p, c.d_x.p, kc, s) : solve_gmres(c, c.d_b.p, c.d_x.p, kc, s);
+
+    // 3. stress multipliers L_s and the new stress adjoint:
+    //    space-time  L_s = T^-T e1 (x) sbar + dt (T^-T W) (x) D^T L_v,  sbar' = e0^T L_s
+    //    Crank-Nicolson  L_s = sbar + dt/2 D^T L_v,  sbar' = 2 L_s - sbar
+    {
+      OpArgs a = base_args(c, SDG_PREC_F64);
+      a.v = c.d_x.p;
+      a.sig_in = sigma_bar;
+      a.use_g = 1;
+      a.vsum = 1;
+      a.s_out = c.d_lam_s.p;
+      if (cn) {
+        a.c.Cs[0] = 1.0;
+        a.c.Cg[0] = dt / 2.0;
+        a.c.send[0] = 1.0;
+      } else {
+        for (int aa = 0; aa < ng; ++aa) {
+          a.c.Cs[aa] = tite1(aa);
+          for (int b = 0; b < ng; ++b) a.c.Cg[aa * ng + b] = dt * TiT[aa * ng + b] * hs.w[b];
+          a.c.send[aa] = hs.e0[aa];
+        }
+        a.s_end = c.d_tmp_sig.p;
+      }
+      launch_face(d, hs.p, ng, SDG_PREC_F64, kWriteStress, a, s);
+      SDG_HIP(hipGetLastError());
+    }
+
+    // 4. material gradients
+    {
+      vec_fill(2 * hs.n_face, 0.0, c.d_face_grad.p, s);
+      GradArgs g{};
+      g.n_face = hs.n_face;
+      g.n_elem = ne;
+      g.faces = c.d_faces.p;
+      g.Dt = c.d_Dt64.p;
+      g.lam_s = c.d_lam_s.p;
+      g.face_out = c.d_face_grad.p;
+      RhoCoefs rcf{};
+      if (cn) {
+        vec_copy(c.n_slab, v_slab, c.d_t.p, s);
+        vec_axpby(c.n_slab, 1.0, v_old, 1.0, c.d_t.p, s);  // v^{n+1} + v^n
+        g.v = c.d_t.p;
+        g.coef = -dt / 2.0;
+        g.wq[0] = 1.0;
+        rcf.Bq[0] = -1.0;
+        rcf.Bo[0] = 1.0;
+      } else {
+        g.v = v_slab;
+        g.coef = -dt;
+        for (int b = 0; b < ng; ++b) g.wq[b] = hs.w[b];
+        for (int a = 0; a < ng; ++a) {
+          rcf.Bo[a] = hs.e0[a];
+          for (int b = 0; b < ng; ++b) rcf.Bq[a * ng + b] = -hs.T[a * ng + b];
+        }
+      }
+      launch_grad_face(d, hs.p, ng, g, s);
+      SDG_HIP(hipGetLastError());
+      launch_face_to_elem(ne, d + 1, c.d_elem_face.p, c.d_ef_wt.p, c.d_face_grad.p, grad, grad + ne, s);
+      launch_grad_rho(ne, ng, d, hs.nphi, rcf, c.d_Mref.p, c.d_detJ.p, c.d_x.p, v_slab, v_old, grad + 2 * ne, s);
+      SDG_HIP(hipGetLastError());
+    }
+
+    // 5. velocity adjoint at the start of the slab
+    if (cn) {
+      // vbar' = rho Mbar L_v - dt/2 D E^T L_s
+      OpArgs f = base_args(c, SDG_PREC_F64);
+      f.sig_in = c.d_lam_s.p;
+      f.sig_in_Et = 1;
+      f.z = c.d_z.p;
+      f.use_g = 0;
+      f.c.Cs[0] = -dt / 2.0;
+      launch_face(d, hs.p, 1, SDG_PREC_F64, kScatter, f, s);
+      OpArgs e = base_args(c, SDG_PREC_F64);
+      e.v = c.d_x.p;
+      e.z = c.d_z.p;
+      e.y = vbar;
+      e.c.Tm[0] = 1.0;
+      launch_elem(d, hs.p, 1, e, s);
+      vec_axpby(c.n_sig_state, 2.0, c.d_lam_s.p, -1.0, sigma_bar, s);
+    } else {
+      // vbar' = rho Mbar (e0^T L_v)
+      launch_end_of_slab(ne, ng, nvs, c.d_e0.p, c.d_x.p, c.d_tmp_state.p, s);
+      OpArgs e = base_args(c, SDG_PREC_F64);
+      e.v = c.d_tmp_state.p;
+      e.y = vbar;
+      e.c.Tm[0] = 1.0;
+      launch_elem(d, hs.p, 1, e, s);
+      vec_copy(c.n_sig_state, c.d_tmp_sig.p, sigma_bar, s);
+    }
+    SDG_HIP(hipGetLastError());
+    SDG_HIP(hipStreamSynchronize(s));
+    if (!res.converged) throw Error(SDG_ENOCONV, "Krylov solver did not reach rtol within max_iter");
+  });
+  if (info) {
+    info->iterations = res.iters;
+    info->matvecs = res.matvecs;
+    info->refinements = 0;
+    info->converged = res.converged ? 1 : 0;
+    info->rel_residual = res.rel_res;
+    info->b_norm = res.bnorm;
+  }
+  return rc;
+}
+
+int sdg_sample_velocity_adjoint(sdg_ctx* ctx, int n_rhs, int64_t n_pts, const double* pts, const double* obs_bar,
+                                double* vbar, void* stream) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.assembled, SDG_ESTATE, "assemble first");
+    require(n_rhs == 1, SDG_EUNSUPPORTED, "batched right-hand sides are not built in this version");
+    require(n_pts >= 0 && (n_pts == 0 || (vbar && pts && obs_bar)), SDG_EINVAL, "null argument");
+    if (n_pts == 0) return;
+    const HostSetup& hs = c.hs;
+    require(hs.dim * hs.nphi <= 256, SDG_EUNSUPPORTED, "element too large for the sampling transpose kernel");
+    std::vector<int64_t> el(n_pts);
+    std::vector<double> phi(n_pts * hs.nphi);
+    for (int64_t q = 0; q < n_pts; ++q) {
+      el[q] = locate_point(hs, pts + q * hs.dim);
+      require(el[q] >= 0, SDG_EINVAL, "sample point outside the mesh");
+      eval_velocity_basis(hs, el[q], pts + q * hs.dim, &phi[q * hs.nphi], 1e-12);
+    }
+    SDG_HIP(hipSetDevice(c.device));
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<int64_t> de;
+    DevBuf<double> dp;
+    de.alloc(n_pts);
+    dp.alloc(phi.size());
+    SDG_HIP(hipMemcpy(de.p, el.data(), el.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    SDG_HIP(hipMemcpy(dp.p, phi.data(), phi.size() * sizeof(double), hipMemcpyHostToDevice));
+    launch_sample_adjoint(n_pts, hs.nphi, hs.dim, de.p, dp.p, obs_bar, vbar, s);
+    SDG_HIP(hipGetLastError());
+    SDG_HIP(hipStreamSynchronize(s));
+  });
 }
 
 int sdg_energy(sdg_ctx* ctx, const double* v_state, const double* sigma_state, int n_rhs, double* out, void* stream) {

@@ -91,6 +91,12 @@ struct Ctx {
   DevBuf<double> d_src_phi, d_src_dir, d_src_amp;
   DevBuf<double> d_tw;  // time quadrature weights of the slab (CN: {1})
   DevBuf<double> d_e1;  // end-of-slab weights gamma_a(1)
+  DevBuf<double> d_e0;  // start-of-slab weights gamma_a(0)
+
+  // adjoint: stress multipliers of the slab, face gradients, element-face
+  // table with the volume fractions of the dual-cell material
+  DevBuf<double> d_lam_s, d_face_grad, d_detJ, d_ef_wt;
+  DevBuf<int32_t> d_elem_face;
   DevBuf<int64_t> d_src_elem;
 
   ~Ctx() {
@@ -134,6 +140,13 @@ void launch_end_of_slab(int64_t n_elem, int ng, int nvs, const double* w, const 
                         double* state, hipStream_t s);
 void launch_add_sources(Ctx& c, double* b, const double* amp_dev, hipStream_t s);
 void launch_energy(Ctx& c, const double* v, const double* sig, double* out_dev, hipStream_t s);
+void launch_grad_rho(int64_t n_elem, int ng, int dim, int nphi, const RhoCoefs& tc, const double* Mref,
+                     const double* detJ, const double* L, const double* X, const double* vold, double* g,
+                     hipStream_t s);
+void launch_face_to_elem(int64_t n_elem, int nfe, const int32_t* ef, const double* wt, const double* fg,
+                         double* g_lam, double* g_mu, hipStream_t s);
+void launch_sample_adjoint(int64_t n, int nphi, int dim, const int64_t* elem, const double* phi,
+                           const double* obar, double* vbar, hipStream_t s);
 void launch_sample(int64_t n, int nphi, int dim, const int64_t* elem, const double* phi,
                    const double* v, double* out, hipStream_t s);
 void launch_eval_stress(int64_t n, int npsi, int nsig, const int64_t* face, const double* psi,

@@ -1,6 +1,8 @@
 // Per-step kernels around the Krylov solve: initial guess, end-of-slab
-// values, point sources (eq. MD_5_2), the energy of Section 5.2 and point
-// evaluation of velocity and stress.
+// values, point sources (eq. MD_5_2), the energy of Section 5.2, point
+// evaluation of velocity and stress, and the element-level pieces of the
+// discrete adjoint (density gradient, face-to-element gradient gather,
+// transpose of the receiver sampling).
 #include "context.hpp"
 
 namespace sdg {
@@ -139,7 +141,77 @@ __global__ void k_eval_stress(int64_t n, int npsi, int nsig, const int64_t* __re
   for (int m = 0; m < npsi; ++m) acc += psi[pt * npsi + m] * sb[m];
   out[t] = acc;
 }
+// g[e] += |J_e| sum_{a,c,k} L[e][a][c][k] (Mref u_a)[c][k], with
+// u_a = sum_b Bq[a][b] X[e][b] + Bo[a] vold[e]: the derivative of the slab
+// system residual with respect to rho_e, contracted with the adjoint
+// multipliers.  One thread per element.
+__global__ void k_grad_rho(int64_t n_elem, int ng, int dim, int nphi, RhoCoefs tc, const double* __restrict__ Mref,
+                           const double* __restrict__ detJ, const double* __restrict__ L,
+                           const double* __restrict__ X, const double* __restrict__ vold, double* __restrict__ g) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_elem) return;
+  const int nvs = dim * nphi;
+  double acc = 0.0;
+  for (int a = 0; a < ng; ++a)
+    for (int c = 0; c < dim; ++c)
+      for (int kk = 0; kk < nphi; ++kk) {
+        // u_a[c][kk]
+        double u = tc.Bo[a] * vold[e * nvs + c * nphi + kk];
+        for (int b = 0; b < ng; ++b) u += tc.Bq[a * ng + b] * X[(e * ng + b) * nvs + c * nphi + kk];
+        double lm = 0.0;
+        const double* Lb = L + (e * ng + a) * nvs + c * nphi;
+        for (int k = 0; k < nphi; ++k) lm += Lb[k] * Mref[k * nphi + kk];
+        acc += lm * u;
+      }
+  g[e] += detJ[e] * acc;
+}
+
+// Per element: g_lam[e] += sum_f wt[e][f] fg[2 j(e,f)], g_mu likewise with
+// fg[2 j + 1]; the face gradients of the dual-cell Lame parameters are
+// distributed with the volume fractions that define them.
+__global__ void k_face_to_elem(int64_t n_elem, int nfe, const int32_t* __restrict__ ef, const double* __restrict__ wt,
+                               const double* __restrict__ fg, double* __restrict__ g_lam, double* __restrict__ g_mu) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_elem) return;
+  double sl = 0.0, sm = 0.0;
+  for (int f = 0; f < nfe; ++f) {
+    const int64_t j = ef[e * nfe + f];
+    const double w = wt[e * nfe + f];
+    sl += w * fg[2 * j];
+    sm += w * fg[2 * j + 1];
+  }
+  g_lam[e] += sl;
+  g_mu[e] += sm;
+}
+
+// Transpose of point sampling: vbar[e_q][c][k] += phi_q[k] obar[q][c], the
+// points taken in order so that the sum is deterministic.
+__global__ void k_sample_adjoint(int64_t n, int nphi, int dim, const int64_t* __restrict__ elem,
+                                 const double* __restrict__ phi, const double* __restrict__ obar,
+                                 double* __restrict__ vbar) {
+  const int t = threadIdx.x;
+  if (t >= dim * nphi) return;
+  const int c = t / nphi, k = t % nphi;
+  for (int64_t q = 0; q < n; ++q) vbar[elem[q] * dim * nphi + t] += phi[q * nphi + k] * obar[q * dim + c];
+}
+
 }  // namespace
+
+void launch_grad_rho(int64_t n_elem, int ng, int dim, int nphi, const RhoCoefs& tc, const double* Mref,
+                     const double* detJ, const double* L, const double* X, const double* vold, double* g,
+                     hipStream_t s) {
+  k_grad_rho<<<(unsigned)((n_elem + kT - 1) / kT), kT, 0, s>>>(n_elem, ng, dim, nphi, tc, Mref, detJ, L, X, vold, g);
+}
+
+void launch_face_to_elem(int64_t n_elem, int nfe, const int32_t* ef, const double* wt, const double* fg,
+                         double* g_lam, double* g_mu, hipStream_t s) {
+  k_face_to_elem<<<(unsigned)((n_elem + kT - 1) / kT), kT, 0, s>>>(n_elem, nfe, ef, wt, fg, g_lam, g_mu);
+}
+
+void launch_sample_adjoint(int64_t n, int nphi, int dim, const int64_t* elem, const double* phi,
+                           const double* obar, double* vbar, hipStream_t s) {
+  k_sample_adjoint<<<1, 256, 0, s>>>(n, nphi, dim, elem, phi, obar, vbar);
+}
 
 void launch_broadcast_time(int64_t n_elem, int ng, int nvs, const double* state, double* slab, hipStream_t s) {
   k_broadcast<<<grid_for(n_elem * ng * nvs), kT, 0, s>>>(n_elem, ng, nvs, state, slab);

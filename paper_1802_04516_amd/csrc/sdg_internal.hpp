@@ -61,6 +61,7 @@ struct HostSetup {
   std::vector<int32_t> elem_face;       // n_elem*(dim+1): face id of local face f
   std::vector<double> Dt;               // n_face*2*nphi*dim*npsi, canonical dual basis
   std::vector<double> face_lm;          // n_face*2: lambda_j, mu_j
+  std::vector<double> face_wt;          // n_face*2: |T_{left,j}|/|R_j|, |T_{right,j}|/|R_j| (1, 0 on the boundary)
   std::vector<double> elem_w;           // n_elem: rho_i |det J_i|
   std::vector<double> elem_detJ;        // n_elem
   std::vector<double> elem_rho;         // n_elem
@@ -147,6 +148,12 @@ struct GradArgs {
   double wq[kMaxGamma];
 };
 bool launch_grad_face(int dim, int p, int ng, const GradArgs& a, hipStream_t s);
+
+// Time coefficients of the density gradient (see launch_grad_rho).
+struct RhoCoefs {
+  double Bq[kMaxGamma * kMaxGamma];  // applied to the slab velocity
+  double Bo[kMaxGamma];              // applied to the start-of-slab velocity
+};
 
 // Inverses of the element diagonal blocks of the velocity operator (eq. pre1)
 // with time coefficients op (FP32, column-major per element).

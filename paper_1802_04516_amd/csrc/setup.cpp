@@ -654,6 +654,7 @@ void build_host_setup(HostSetup& hs, int dim, int64_t n_vert, const double* xyz,
   const int blk = nphi * d * npsi;
   hs.Dt.assign((size_t)nf * 2 * blk, 0.0);
   hs.face_lm.assign(nf * 2, 0.0);
+  hs.face_wt.assign(nf * 2, 0.0);
   const int psi_deg = (d == 2) ? 2 * p : p;
   int err_code = 0;
   std::string err_msg;
@@ -708,9 +709,12 @@ void build_host_setup(HostSetup& hs, int dim, int64_t n_vert, const double* xyz,
           double vt = vol[0] + vol[1];
           hs.face_lm[2 * j] = (vol[0] * lam[fr.left] + vol[1] * lam[fr.right]) / vt;
           hs.face_lm[2 * j + 1] = (vol[0] * mu[fr.left] + vol[1] * mu[fr.right]) / vt;
+          hs.face_wt[2 * j] = vol[0] / vt;
+          hs.face_wt[2 * j + 1] = vol[1] / vt;
         } else {
           hs.face_lm[2 * j] = lam[fr.left];
           hs.face_lm[2 * j + 1] = mu[fr.left];
+          hs.face_wt[2 * j] = 1.0;
         }
       } catch (const Error& e) {
         std::lock_guard<std::mutex> lk(err_mu);
