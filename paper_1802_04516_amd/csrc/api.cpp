@@ -163,8 +163,12 @@ void apply_precond(Ctx& c, int kind, const double* x, double* y, bool transpose,
     launch_elem(hs.dim, hs.p, hs.ng, a, s);
     SDG_HIP(hipGetLastError());
   } else if (kind == SDG_PRECOND_BLOCK) {
-    require(c.d_Pblk.p != nullptr, SDG_ESTATE, "block preconditioner not assembled (pass SDG_ASSEMBLE_BLOCK_PRECOND)");
-    launch_block_apply(hs.n_elem, hs.ng * hs.dim * hs.nphi, c.d_Pblk.p, x, y, transpose, s);
+    require(c.d_Pblk.p != nullptr || c.d_Pq.p != nullptr, SDG_ESTATE,
+            "block preconditioner not assembled (pass SDG_ASSEMBLE_BLOCK_PRECOND)");
+    if (c.pblk_factored)
+      launch_block_apply_fact(hs.n_elem, hs.ng, hs.dim * hs.nphi, c.d_Pq.p, c.d_Pb.p, x, y, transpose, s);
+    else
+      launch_block_apply(hs.n_elem, hs.ng * hs.dim * hs.nphi, c.d_Pblk.p, x, y, transpose, s);
   } else {
     vec_copy(c.n_slab, x, y, s);
   }
@@ -318,12 +322,22 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
       c.d_winv.alloc(wi.size());
       SDG_HIP(hipMemcpy(c.d_winv.p, wi.data(), wi.size() * sizeof(double), hipMemcpyHostToDevice));
     }
+    c.d_Pblk.free();
+    c.d_Pq.free();
+    c.d_Pb.free();
+    c.pblk_factored = false;
     if (precisions & SDG_ASSEMBLE_BLOCK_PRECOND) {
-      std::vector<float> P = block_inverses(hs, op);
-      c.d_Pblk.alloc(P.size());
-      SDG_HIP(hipMemcpy(c.d_Pblk.p, P.data(), P.size() * sizeof(float), hipMemcpyHostToDevice));
-    } else {
-      c.d_Pblk.free();
+      BlockPrecond bp = block_inverses(hs, op);
+      c.pblk_factored = bp.factored;
+      if (bp.factored) {
+        c.d_Pq.alloc(bp.Q.size());
+        SDG_HIP(hipMemcpy(c.d_Pq.p, bp.Q.data(), bp.Q.size() * sizeof(float), hipMemcpyHostToDevice));
+        c.d_Pb.alloc(bp.B.size());
+        SDG_HIP(hipMemcpy(c.d_Pb.p, bp.B.data(), bp.B.size() * sizeof(float), hipMemcpyHostToDevice));
+      } else {
+        c.d_Pblk.alloc(bp.P.size());
+        SDG_HIP(hipMemcpy(c.d_Pblk.p, bp.P.data(), bp.P.size() * sizeof(float), hipMemcpyHostToDevice));
+      }
     }
 
     // operator blocks

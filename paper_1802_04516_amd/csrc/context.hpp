@@ -74,7 +74,9 @@ struct Ctx {
   // column-major per element
   DevBuf<double> d_Minv, d_winv;
   Coefs precF{}, precA{};
-  DevBuf<float> d_Pblk;
+  DevBuf<float> d_Pblk;                 // explicit inverses (one time node)
+  DevBuf<float> d_Pq, d_Pb;             // factored inverses (several time nodes)
+  bool pblk_factored = false;
 
   // solver workspace
   DevBuf<double> d_V;                   // (restart+1) * n_slab   (GMRES) or 4 * n_slab (CG)
@@ -132,6 +134,8 @@ SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, 
 void apply_precond(Ctx& c, int kind, const double* x, double* y, bool transpose, hipStream_t s);
 void launch_block_apply(int64_t n_elem, int nv, const float* P, const double* x, double* y, bool transpose,
                         hipStream_t s);
+void launch_block_apply_fact(int64_t n_elem, int ng, int ns, const float* Q, const float* B, const double* x,
+                             double* y, bool transpose, hipStream_t s);
 
 // step pieces
 void launch_broadcast_time(int64_t n_elem, int ng, int nvs, const double* state, double* slab,

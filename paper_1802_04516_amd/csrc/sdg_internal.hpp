@@ -156,7 +156,16 @@ struct RhoCoefs {
 };
 
 // Inverses of the element diagonal blocks of the velocity operator (eq. pre1)
-// with time coefficients op (FP32, column-major per element).
-std::vector<float> block_inverses(const HostSetup& hs, const Coefs& op);
+// with time coefficients op, in FP32.  One time node: explicit inverses,
+// column-major per element (P).  Several: the factored form
+// (I (x) Q) blockdiag_i (Tm + lambda_i Cg)^-1 (I (x) Q^T) from the generalised
+// eigenvectors Q of the element stiffness and mass (Q [e][ck][i], B
+// [e][i][a][b]).
+struct BlockPrecond {
+  bool factored = false;
+  int ns = 0, ng = 0;
+  std::vector<float> P, Q, B;
+};
+BlockPrecond block_inverses(const HostSetup& hs, const Coefs& op);
 
 }  // namespace sdg

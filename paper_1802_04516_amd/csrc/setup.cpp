@@ -764,72 +764,208 @@ void eval_dual_canonical(const HostSetup& hs, const int64_t* elem, int64_t j, in
 // Element diagonal blocks of the velocity operator (eq. pre1),
 //   D_i = Tm (x) w_i Mref + Cg (x) K_ii,  K_ii = sum_f Dt_{i,f} E_j Dt_{i,f}^T,
 // inverted on the host; returned in FP32, column-major per element.
-std::vector<float> block_inverses(const HostSetup& hs, const Coefs& op) {
-  const int d = hs.dim, nphi = hs.nphi, npsi = hs.npsi, ng = hs.ng;
-  const int ns = d * nphi, nv = ng * ns, blk = nphi * d * npsi;
-  std::vector<float> out((size_t)hs.n_elem * nv * nv);
-  int err = 0;
-  parallel_for(hs.n_elem, [&](int64_t e) {
-    std::vector<double> K(ns * ns), Dm(nv * nv), Inv(nv * nv);
-    std::fill(K.begin(), K.end(), 0.0);
-    for (int f = 0; f <= d; ++f) {
-      const int32_t j = hs.elem_face[e * (d + 1) + f];
-      const FaceRec& fr = hs.faces[j];
-      const int side = fr.left == e ? 0 : 1;
-      const double* Db = &hs.Dt[((size_t)j * 2 + side) * blk];
-      const double lam = hs.face_lm[2 * j], mu = hs.face_lm[2 * j + 1];
-      // K[(c,k),(c2,k2)] = sum_{l,l2,m} Db[k][l][m] E_{cl,c2l2} Db[k2][l2][m]
-      for (int c = 0; c < d; ++c)
-        for (int l = 0; l < d; ++l)
-          for (int c2 = 0; c2 < d; ++c2)
-            for (int l2 = 0; l2 < d; ++l2) {
-              double E = mu * ((c == c2 && l == l2) + (c == l2 && l == c2)) + lam * (c == l && c2 == l2);
-              if (E == 0.0) continue;
-              for (int k = 0; k < nphi; ++k)
-                for (int k2 = 0; k2 < nphi; ++k2) {
-                  double sacc = 0.0;
-                  const double* a1 = Db + (k * d + l) * npsi;
-                  const double* a2 = Db + (k2 * d + l2) * npsi;
-                  for (int m = 0; m < npsi; ++m) sacc += a1[m] * a2[m];
-                  K[(c * nphi + k) * ns + c2 * nphi + k2] += E * sacc;
-                }
-            }
-    }
-    for (int a = 0; a < ng; ++a)
-      for (int b = 0; b < ng; ++b)
-        for (int i = 0; i < ns; ++i)
-          for (int i2 = 0; i2 < ns; ++i2) {
-            const int c = i / nphi, k = i % nphi, c2 = i2 / nphi, k2 = i2 % nphi;
-            double v = op.Cg[a * ng + b] * K[i * ns + i2];
-            if (c == c2) v += op.Tm[a * ng + b] * hs.elem_w[e] * hs.Mref[k * nphi + k2];
-            Dm[(a * ns + i) * nv + b * ns + i2] = v;
+namespace {
+
+// Element stiffness of the Schur operator restricted to element e (the
+// diagonal block of K): K[(c,k),(c2,k2)] = sum over the faces of e of
+// sum_{l,l2,m} Dt[k][l][m] E_{cl,c2l2} Dt[k2][l2][m].
+void element_stiffness(const HostSetup& hs, int64_t e, std::vector<double>& K) {
+  const int d = hs.dim, nphi = hs.nphi, npsi = hs.npsi;
+  const int ns = d * nphi, blk = nphi * d * npsi;
+  K.assign((size_t)ns * ns, 0.0);
+  for (int f = 0; f <= d; ++f) {
+    const int32_t j = hs.elem_face[e * (d + 1) + f];
+    const FaceRec& fr = hs.faces[j];
+    const int side = (fr.left == e && fr.lf == f) ? 0 : 1;
+    const double* Db = &hs.Dt[((size_t)j * 2 + side) * blk];
+    const double lam = hs.face_lm[2 * j], mu = hs.face_lm[2 * j + 1];
+    for (int c = 0; c < d; ++c)
+      for (int l = 0; l < d; ++l)
+        for (int c2 = 0; c2 < d; ++c2)
+          for (int l2 = 0; l2 < d; ++l2) {
+            double E = mu * ((c == c2 && l == l2) + (c == l2 && l == c2)) + lam * (c == l && c2 == l2);
+            if (E == 0.0) continue;
+            for (int k = 0; k < nphi; ++k)
+              for (int k2 = 0; k2 < nphi; ++k2) {
+                double sacc = 0.0;
+                const double* a1 = Db + (k * d + l) * npsi;
+                const double* a2 = Db + (k2 * d + l2) * npsi;
+                for (int m = 0; m < npsi; ++m) sacc += a1[m] * a2[m];
+                K[(c * nphi + k) * ns + c2 * nphi + k2] += E * sacc;
+              }
           }
-    std::vector<double> M = Dm;
-    std::fill(Inv.begin(), Inv.end(), 0.0);
-    for (int i = 0; i < nv; ++i) Inv[i * nv + i] = 1.0;
-    for (int col = 0; col < nv; ++col) {
-      int piv = col;
-      for (int r = col + 1; r < nv; ++r)
-        if (std::fabs(M[r * nv + col]) > std::fabs(M[piv * nv + col])) piv = r;
-      if (M[piv * nv + col] == 0.0) { err = 1; return; }
-      if (piv != col)
-        for (int k = 0; k < nv; ++k) { std::swap(M[col * nv + k], M[piv * nv + k]); std::swap(Inv[col * nv + k], Inv[piv * nv + k]); }
-      const double dinv = 1.0 / M[col * nv + col];
-      for (int k = 0; k < nv; ++k) { M[col * nv + k] *= dinv; Inv[col * nv + k] *= dinv; }
-      for (int r = 0; r < nv; ++r) {
-        if (r == col) continue;
-        const double f = M[r * nv + col];
-        if (f == 0.0) continue;
-        for (int k = 0; k < nv; ++k) { M[r * nv + k] -= f * M[col * nv + k]; Inv[r * nv + k] -= f * Inv[col * nv + k]; }
-      }
+  }
+}
+
+// Gauss-Jordan inverse with partial pivoting (row-major, n x n); false if singular.
+bool gj_inverse(std::vector<double> M, int n, std::vector<double>& Inv) {
+  Inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Inv[i * n + i] = 1.0;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(M[r * n + col]) > std::fabs(M[piv * n + col])) piv = r;
+    if (M[piv * n + col] == 0.0) return false;
+    if (piv != col)
+      for (int k = 0; k < n; ++k) { std::swap(M[col * n + k], M[piv * n + k]); std::swap(Inv[col * n + k], Inv[piv * n + k]); }
+    const double dinv = 1.0 / M[col * n + col];
+    for (int k = 0; k < n; ++k) { M[col * n + k] *= dinv; Inv[col * n + k] *= dinv; }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double f = M[r * n + col];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) { M[r * n + k] -= f * M[col * n + k]; Inv[r * n + k] -= f * Inv[col * n + k]; }
     }
-    float* o = &out[(size_t)e * nv * nv];
-    for (int r = 0; r < nv; ++r)
-      for (int col = 0; col < nv; ++col) o[(size_t)col * nv + r] = (float)Inv[r * nv + col];
+  }
+  return true;
+}
+
+// Cyclic Jacobi eigenvalue iteration for a symmetric matrix A (n x n,
+// row-major, destroyed): on return lam holds the eigenvalues and U (row-major,
+// columns = eigenvectors) satisfies A = U diag(lam) U^T.  Each rotation zeroes
+// one off-diagonal entry with the symmetric 2x2 Schur decomposition
+// (Golub and Van Loan, Matrix Computations, Sec. 8.5).
+void jacobi_eigen(std::vector<double>& A, int n, std::vector<double>& lam, std::vector<double>& U) {
+  U.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) U[i * n + i] = 1.0;
+  double scale = 0.0;
+  for (double v : A) scale += v * v;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += 2.0 * A[p * n + q] * A[p * n + q];
+    if (off <= 1e-30 * scale) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * n + q];
+        if (apq == 0.0) continue;
+        const double tau = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+        for (int k = 0; k < n; ++k) {  // A <- A J (columns p, q)
+          const double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - sn * akq;
+          A[k * n + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // A <- J^T A (rows p, q)
+          const double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - sn * aqk;
+          A[q * n + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {  // U <- U J
+          const double ukp = U[k * n + p], ukq = U[k * n + q];
+          U[k * n + p] = c * ukp - sn * ukq;
+          U[k * n + q] = sn * ukp + c * ukq;
+        }
+      }
+  }
+  lam.resize(n);
+  for (int i = 0; i < n; ++i) lam[i] = A[i * n + i];
+}
+
+}  // namespace
+
+BlockPrecond block_inverses(const HostSetup& hs, const Coefs& op) {
+  const int d = hs.dim, nphi = hs.nphi, ng = hs.ng;
+  const int ns = d * nphi, nv = ng * ns;
+  BlockPrecond out;
+  out.ns = ns;
+  out.ng = ng;
+  out.factored = ng > 1;
+  std::atomic<int> err{0};
+  if (!out.factored) {
+    // one time node: explicit inverse of rho|J| Tm Mbar + Cg K, column-major
+    out.P.resize((size_t)hs.n_elem * nv * nv);
+    parallel_for(hs.n_elem, [&](int64_t e) {
+      std::vector<double> K, Dm((size_t)nv * nv), Inv;
+      element_stiffness(hs, e, K);
+      for (int i = 0; i < ns; ++i)
+        for (int i2 = 0; i2 < ns; ++i2) {
+          const int c = i / nphi, k = i % nphi, c2 = i2 / nphi, k2 = i2 % nphi;
+          double v = op.Cg[0] * K[i * ns + i2];
+          if (c == c2) v += op.Tm[0] * hs.elem_w[e] * hs.Mref[k * nphi + k2];
+          Dm[i * nv + i2] = v;
+        }
+      if (!gj_inverse(Dm, nv, Inv)) { err = 1; return; }
+      float* o = &out.P[(size_t)e * nv * nv];
+      for (int r = 0; r < nv; ++r)
+        for (int col = 0; col < nv; ++col) o[(size_t)col * nv + r] = (float)Inv[r * nv + col];
+    });
+    require(!err, SDG_EMESH, "singular diagonal block");
+    return out;
+  }
+  // Several time nodes: the diagonal block is Tm (x) M_e + Cg (x) K_e with
+  // M_e = rho_e|J_e| (I (x) Mref).  With the generalised eigenvectors
+  // K_e Q = M_e Q Lambda, Q^T M_e Q = I, it factors as
+  //   (I (x) Q^-T) (Tm (x) I + Cg (x) Lambda) (I (x) Q^-1),
+  // whose inverse is (I (x) Q) blockdiag_i (Tm + lambda_i Cg)^-1 (I (x) Q^T).
+  // Stored per element: Q (ns x ns, row-major [ck][i]) and the ns inverses
+  // (ng x ng, row-major [a][b]).
+  std::vector<double> Lref((size_t)nphi * nphi, 0.0);
+  {
+    const std::vector<double>& M = hs.Mref;
+    for (int i = 0; i < nphi; ++i)
+      for (int j = 0; j <= i; ++j) {
+        double s = M[i * nphi + j];
+        for (int k = 0; k < j; ++k) s -= Lref[i * nphi + k] * Lref[j * nphi + k];
+        if (i == j) {
+          require(s > 0.0, SDG_EMESH, "reference mass matrix is not positive definite");
+          Lref[i * nphi + i] = std::sqrt(s);
+        } else {
+          Lref[i * nphi + j] = s / Lref[j * nphi + j];
+        }
+      }
+  }
+  std::vector<double> Linv;  // inverse of the lower-triangular factor
+  require(gj_inverse(Lref, nphi, Linv), SDG_EMESH, "reference mass matrix is singular");
+  out.Q.resize((size_t)hs.n_elem * ns * ns);
+  out.B.resize((size_t)hs.n_elem * ns * ng * ng);
+  parallel_for(hs.n_elem, [&](int64_t e) {
+    std::vector<double> K, C((size_t)ns * ns), lam, U, Bi((size_t)ng * ng), BiInv;
+    element_stiffness(hs, e, K);
+    const double w = hs.elem_w[e], sw = std::sqrt(w);
+    // C = L^-1 K L^-T with L = sqrt(w) (I (x) Lref)
+    auto Li = [&](int r, int col) {  // (I (x) Linv)[r][col]
+      const int c = r / nphi, k = r % nphi, c2 = col / nphi, k2 = col % nphi;
+      return c == c2 ? Linv[k * nphi + k2] : 0.0;
+    };
+    std::vector<double> T((size_t)ns * ns, 0.0);
+    for (int r = 0; r < ns; ++r)
+      for (int col = 0; col < ns; ++col) {
+        double s = 0.0;
+        for (int k = 0; k < ns; ++k) s += Li(r, k) * K[k * ns + col];
+        T[r * ns + col] = s;
+      }
+    for (int r = 0; r < ns; ++r)
+      for (int col = 0; col < ns; ++col) {
+        double s = 0.0;
+        for (int k = 0; k < ns; ++k) s += T[r * ns + k] * Li(col, k);
+        C[r * ns + col] = s / w;
+      }
+    for (int r = 0; r < ns; ++r)  // exact symmetry before the eigen-solve
+      for (int col = r + 1; col < ns; ++col) {
+        const double m = 0.5 * (C[r * ns + col] + C[col * ns + r]);
+        C[r * ns + col] = C[col * ns + r] = m;
+      }
+    jacobi_eigen(C, ns, lam, U);
+    // Q = L^-T U = (1/sqrt(w)) (I (x) Linv^T) U
+    float* Qe = &out.Q[(size_t)e * ns * ns];
+    for (int r = 0; r < ns; ++r)
+      for (int i = 0; i < ns; ++i) {
+        double s = 0.0;
+        for (int k = 0; k < ns; ++k) s += Li(k, r) * U[k * ns + i];
+        Qe[r * ns + i] = (float)(s / sw);
+      }
+    float* Be = &out.B[(size_t)e * ns * ng * ng];
+    for (int i = 0; i < ns; ++i) {
+      for (int a = 0; a < ng; ++a)
+        for (int b = 0; b < ng; ++b) Bi[a * ng + b] = op.Tm[a * ng + b] + lam[i] * op.Cg[a * ng + b];
+      if (!gj_inverse(Bi, ng, BiInv)) { err = 1; return; }
+      for (int a = 0; a < ng * ng; ++a) Be[i * ng * ng + a] = (float)BiInv[a];
+    }
   });
   require(!err, SDG_EMESH, "singular diagonal block");
   return out;
 }
-
 
 }  // namespace sdg

@@ -202,6 +202,50 @@ __global__ void k_block_apply(int64_t n_elem, int nv, const float* __restrict__ 
   }
 }
 
+// Factored element block inverse (several time nodes):
+//   y_e = (I (x) Q_e) blockdiag_i(B_{e,i}) (I (x) Q_e^T) x_e
+// (B^T for the transpose).  nv = ng*ns threads per element, several elements
+// per workgroup; x, u and w of an element are staged in LDS.
+__global__ __launch_bounds__(256) void k_block_apply_fact(int64_t n_elem, int ng, int ns, const float* __restrict__ Q,
+                                                          const float* __restrict__ B, const double* __restrict__ x,
+                                                          double* __restrict__ y, int transpose) {
+  extern __shared__ double sm[];
+  const int nv = ng * ns;
+  const int epb = blockDim.x / nv;
+  const int le = threadIdx.x / nv, r = threadIdx.x % nv;
+  const int a = r / ns, i = r % ns;
+  double* sx = sm + (size_t)min(le, epb - 1) * 2 * nv;
+  double* su = sx + nv;
+  for (int64_t e0 = (int64_t)blockIdx.x * epb; e0 < n_elem; e0 += (int64_t)gridDim.x * epb) {
+    const int64_t e = e0 + le;
+    const bool act = le < epb && e < n_elem;
+    const float* Qe = Q + (size_t)(act ? e : 0) * ns * ns;
+    if (act) sx[r] = x[e * nv + r];
+    __syncthreads();
+    if (act) {  // u[a][i] = sum_ck Q[ck][i] x[a][ck]
+      double acc = 0.0;
+      for (int ck = 0; ck < ns; ++ck) acc += (double)Qe[ck * ns + i] * sx[a * ns + ck];
+      su[r] = acc;
+    }
+    __syncthreads();
+    double wv = 0.0;
+    if (act) {  // w[a][i] = sum_b B_i[a][b] u[b][i]
+      const float* Be = B + ((size_t)e * ns + i) * ng * ng;
+      for (int b = 0; b < ng; ++b) wv += (double)(transpose ? Be[b * ng + a] : Be[a * ng + b]) * su[b * ns + i];
+    }
+    __syncthreads();
+    if (act) sx[r] = wv;
+    __syncthreads();
+    if (act) {  // y[a][ck] = sum_i Q[ck][i] w[a][i], here i plays ck
+      double acc = 0.0;
+      const float* Qr = Qe + (size_t)i * ns;
+      for (int ii = 0; ii < ns; ++ii) acc += (double)Qr[ii] * sx[a * ns + ii];
+      y[e * nv + r] = acc;
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void k_cg_p(int64_t n, double* __restrict__ p, const double* __restrict__ r, const DevScalars* sc) {
   const double beta = sc->beta;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -210,79 +254,131 @@ __global__ void k_cg_p(int64_t n, double* __restrict__ p, const double* __restri
 
 // ---------------------------------------------------------------- GMRES
 
-// h1[i] = V_i . w for i <= j (classical Gram-Schmidt projections)
-template <int MAXJ>
-__global__ void k_multidot(int64_t n, int nj, const double* __restrict__ V, const double* __restrict__ w,
-                           double* partials) {
-  __shared__ double sh[16];
-  double acc[MAXJ];
+// The Gram-Schmidt kernels take the number of basis vectors NJ as a template
+// parameter: every row's NJ loads are independent and unconditional, so a
+// wavefront keeps them all in flight.
+
+// Per-block sums of NJ accumulators -> partials[i][block] (slot-major).
+template <int NJ>
+__device__ inline void block_partials(const double (&acc)[NJ], double* sh, double* partials) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
-  for (int i = 0; i < MAXJ; ++i) acc[i] = 0.0;
+  for (int i = 0; i < NJ; ++i) {
+    const double v = warp_sum(acc[i]);
+    if (lane == 0) sh[wid * NJ + i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NJ) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[w * NJ + threadIdx.x];
+    partials[(size_t)threadIdx.x * kRedBlocks + blockIdx.x] = s;
+  }
+}
+
+// h1[i] = V_i . w for i < NJ (classical Gram-Schmidt projections)
+template <int NJ>
+__global__ __launch_bounds__(256) void k_multidot(int64_t n, const double* __restrict__ V,
+                                                  const double* __restrict__ w, double* partials) {
+  __shared__ double sh[4 * NJ];
+  double acc[NJ];
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) acc[i] = 0.0;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
     const double wt = w[t];
+    double vi[NJ];
 #pragma unroll
-    for (int i = 0; i < MAXJ; ++i)
-      if (i < nj) acc[i] += V[(size_t)i * n + t] * wt;
-  }
+    for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * n + t];
 #pragma unroll
-  for (int i = 0; i < MAXJ; ++i) {
-    if (i < nj) {
-      double s = block_sum(acc[i], sh);
-      if (threadIdx.x == 0) partials[(size_t)i * kRedBlocks + blockIdx.x] = s;
-    }
+    for (int i = 0; i < NJ; ++i) acc[i] += vi[i] * wt;
   }
+  block_partials<NJ>(acc, sh, partials);
 }
 
 // w -= V h1, then h2[i] = V_i . w (second Gram-Schmidt pass)
-template <int MAXJ>
-__global__ void k_cgs_pass(int64_t n, int nj, const double* __restrict__ V, double* __restrict__ w,
-                           const DevScalars* sc, double* partials) {
-  __shared__ double sh[16];
-  __shared__ double hs[MAXJ];
-  if (threadIdx.x < nj) hs[threadIdx.x] = sc->h1[threadIdx.x];
-  __syncthreads();
-  double acc[MAXJ];
+template <int NJ>
+__global__ __launch_bounds__(256) void k_cgs_pass(int64_t n, const double* __restrict__ V, double* __restrict__ w,
+                                                  const DevScalars* sc, double* partials) {
+  __shared__ double sh[4 * NJ];
+  double h[NJ], acc[NJ];
 #pragma unroll
-  for (int i = 0; i < MAXJ; ++i) acc[i] = 0.0;
+  for (int i = 0; i < NJ; ++i) { h[i] = sc->h1[i]; acc[i] = 0.0; }
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-    double vi[MAXJ];
+    double vi[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * n + t];
     double wt = w[t];
 #pragma unroll
-    for (int i = 0; i < MAXJ; ++i)
-      if (i < nj) { vi[i] = V[(size_t)i * n + t]; wt -= hs[i] * vi[i]; }
+    for (int i = 0; i < NJ; ++i) wt -= h[i] * vi[i];
     w[t] = wt;
 #pragma unroll
-    for (int i = 0; i < MAXJ; ++i)
-      if (i < nj) acc[i] += vi[i] * wt;
+    for (int i = 0; i < NJ; ++i) acc[i] += vi[i] * wt;
   }
-#pragma unroll
-  for (int i = 0; i < MAXJ; ++i) {
-    if (i < nj) {
-      double s = block_sum(acc[i], sh);
-      if (threadIdx.x == 0) partials[(size_t)i * kRedBlocks + blockIdx.x] = s;
-    }
-  }
+  block_partials<NJ>(acc, sh, partials);
 }
 
 // w -= V h2 and partials of w.w.
-template <int MAXJ>
-__global__ void k_cgs_final(int64_t n, int nj, const double* __restrict__ V, double* __restrict__ w,
-                            const DevScalars* sc, double* partials) {
-  __shared__ double sh[16];
-  __shared__ double hs[MAXJ];
-  if (threadIdx.x < nj) hs[threadIdx.x] = sc->h2[threadIdx.x];
-  __syncthreads();
-  double acc = 0.0;
+template <int NJ>
+__global__ __launch_bounds__(256) void k_cgs_final(int64_t n, const double* __restrict__ V, double* __restrict__ w,
+                                                   const DevScalars* sc, double* partials) {
+  __shared__ double sh[4];
+  double h[NJ];
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) h[i] = sc->h2[i];
+  double acc[1] = {0.0};
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double vi[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * n + t];
     double wt = w[t];
 #pragma unroll
-    for (int i = 0; i < MAXJ; ++i)
-      if (i < nj) wt -= hs[i] * V[(size_t)i * n + t];
+    for (int i = 0; i < NJ; ++i) wt -= h[i] * vi[i];
     w[t] = wt;
-    acc += wt * wt;
+    acc[0] += wt * wt;
   }
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+  block_partials<1>(acc, sh, partials);
+}
+
+// x += sum_i y_i V_i
+template <int NJ>
+__global__ __launch_bounds__(256) void k_gmres_update(int64_t n, const double* __restrict__ V, double* __restrict__ x,
+                                                      const DevScalars* sc) {
+  double ys[NJ];
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) ys[i] = sc->y[i];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double vi[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * n + t];
+    double acc = x[t];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) acc += ys[i] * vi[i];
+    x[t] = acc;
+  }
+}
+
+#define SDG_NJ_CASES(X)                                                                                    \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
+  X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+static_assert(kMaxRestart == 32, "the Gram-Schmidt dispatch covers 1..32 basis vectors");
+
+enum class Gs { Multidot, Pass, Final, Update };
+
+// Launch one of the Gram-Schmidt kernels for nj basis vectors.
+void launch_gs(Gs which, int nj, unsigned grid, hipStream_t s, int64_t n, const double* V, double* w,
+               const DevScalars* sc, double* partials) {
+  switch (nj) {
+#define SDG_GS_CASE(N)                                                                       \
+  case N:                                                                                    \
+    if (which == Gs::Multidot) k_multidot<N><<<grid, 256, 0, s>>>(n, V, w, partials);         \
+    else if (which == Gs::Pass) k_cgs_pass<N><<<grid, 256, 0, s>>>(n, V, w, sc, partials);    \
+    else if (which == Gs::Final) k_cgs_final<N><<<grid, 256, 0, s>>>(n, V, w, sc, partials);  \
+    else k_gmres_update<N><<<grid, 256, 0, s>>>(n, V, w, sc);                                 \
+    break;
+    SDG_NJ_CASES(SDG_GS_CASE)
+#undef SDG_GS_CASE
+    default:
+      throw Error(SDG_EINVAL, "Gram-Schmidt basis size out of range");
+  }
 }
 
 // Completes the Hessenberg column j (h1 + h2 and the new norm), applies the
@@ -436,6 +532,18 @@ void launch_block_apply(int64_t n_elem, int nv, const float* P, const double* x,
   check_launch();
 }
 
+void launch_block_apply_fact(int64_t n_elem, int ng, int ns, const float* Q, const float* B, const double* x,
+                             double* y, bool transpose, hipStream_t s) {
+  const int nv = ng * ns;
+  require(nv <= 256, SDG_EUNSUPPORTED, "element block too large for the factored preconditioner kernel");
+  const int epb = 256 / nv;
+  const int64_t groups = (n_elem + epb - 1) / epb;
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 65535));
+  k_block_apply_fact<<<g, epb * nv, (size_t)epb * 2 * nv * sizeof(double), s>>>(n_elem, ng, ns, Q, B, x, y,
+                                                                                transpose ? 1 : 0);
+  check_launch();
+}
+
 // ---------------------------------------------------------------- CG
 
 // Preconditioned conjugate gradients (P = I for SDG_PRECOND_NONE):
@@ -564,15 +672,15 @@ SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, 
         apply_op(c, vj, w, k.prec, k.transpose, s);
       }
       ++res.matvecs;
-      k_multidot<kMaxRestart><<<rg, kThreads, 0, s>>>(n, j + 1, V, w, c.d_partials.p);
+      launch_gs(Gs::Multidot, j + 1, rg, s, n, V, w, sc, c.d_partials.p);
       check_launch();
       k_finalize<<<1, 512, 0, s>>>(c.d_partials.p, (int)rg, j + 1, sc->h1);
       check_launch();
-      k_cgs_pass<kMaxRestart><<<rg, kThreads, 0, s>>>(n, j + 1, V, w, sc, c.d_partials.p);
+      launch_gs(Gs::Pass, j + 1, rg, s, n, V, w, sc, c.d_partials.p);
       check_launch();
       k_finalize<<<1, 512, 0, s>>>(c.d_partials.p, (int)rg, j + 1, sc->h2);
       check_launch();
-      k_cgs_final<kMaxRestart><<<rg, kThreads, 0, s>>>(n, j + 1, V, w, sc, c.d_partials.p);
+      launch_gs(Gs::Final, j + 1, rg, s, n, V, w, sc, c.d_partials.p);
       check_launch();
       k_cgs_final_fin<<<1, kThreads, 0, s>>>(c.d_partials.p, (int)rg, j + 1, sc);
       check_launch();
@@ -592,12 +700,12 @@ SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, 
     check_launch();
     if (pre) {
       vec_fill(n, 0.0, t, s);
-      k_gmres_update<kMaxRestart><<<vg, kThreads, 0, s>>>(n, kk, V, t, sc);
+      if (kk > 0) launch_gs(Gs::Update, kk, vg, s, n, V, t, sc, nullptr);
       check_launch();
       apply_precond(c, k.precond, t, w, k.transpose, s);
       vec_axpby(n, 1.0, w, 1.0, x, s);
     } else {
-      k_gmres_update<kMaxRestart><<<vg, kThreads, 0, s>>>(n, kk, V, x, sc);
+      if (kk > 0) launch_gs(Gs::Update, kk, vg, s, n, V, x, sc, nullptr);
       check_launch();
     }
   }

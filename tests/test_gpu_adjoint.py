@@ -36,15 +36,17 @@ def _oracle(lam, mu, rho, mesh, p, pg, scheme, dt, nsteps, data=None):
     return MisfitProblem(S, REC, SRC, list(amps), data)
 
 
-def _opts(rtol=1e-13):
+def _opts(rtol=1e-13, precond=None):
     import paper_1802_04516_amd as sdg
-    return sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F64, rtol, 4000, 30, 5, 10, 1e-4, sdg.SDG_PRECOND_MASS)
+    return sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F64, rtol, 4000, 30, 5, 10, 1e-4,
+                         sdg.SDG_PRECOND_MASS if precond is None else precond)
 
 
 CASES = {
-    # name: (n, p, p_gamma, scheme, dt, steps, checkpoint_every)
-    "stdg_p2pg2": (5, 2, 2, "stdg", 0.01, 7, 3),
-    "cn_p1": (5, 1, 0, "cn", 0.01, 6, 4),
+    # name: (n, p, p_gamma, scheme, dt, steps, checkpoint_every, preconditioner)
+    "stdg_p2pg2": (5, 2, 2, "stdg", 0.01, 7, 3, "block"),
+    "stdg_p1pg1_mass": (4, 1, 1, "stdg", 0.02, 5, 2, "mass"),
+    "cn_p1": (5, 1, 0, "cn", 0.01, 6, 4, "mass"),
 }
 
 
@@ -53,7 +55,7 @@ def problem(request):
     import torch
     import paper_1802_04516_amd as sdg
     from paper_1802_04516_amd.adjoint import Seismograms
-    n, p, pg, scheme, dt, nsteps, K = CASES[request.param]
+    n, p, pg, scheme, dt, nsteps, K, pc = CASES[request.param]
     mesh = synth.split_square(n, jitter=0.15, seed=3)
     lam, mu, rho = synth.lognormal_material(mesh.n_elem, sigma=0.2, seed=5)
     true = synth.lognormal_material(mesh.n_elem, sigma=0.2, seed=6)
@@ -65,7 +67,9 @@ def problem(request):
     P = _oracle(lam, mu, rho, mesh, p, pg, scheme, dt, nsteps, data)
     sim = Seismograms(mesh, p, pg, sdg.SDG_SCHEME_CN if scheme == "cn" else sdg.SDG_SCHEME_STDG, dt,
                       lam, mu, rho, SRC["pos"], SRC["dir"], _amps(scheme, S.tb.tau, dt, nsteps), REC,
-                      checkpoint_every=K, opts=_opts())
+                      checkpoint_every=K,
+                      opts=_opts(precond=sdg.SDG_PRECOND_BLOCK if pc == "block" else sdg.SDG_PRECOND_MASS),
+                      precisions=sdg.SDG_PREC_F64 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND)
     out = dict(name=request.param, mesh=mesh, lam=lam, mu=mu, rho=rho, P=P, v0=v0, s0=s0, data=data, sim=sim,
                data_t=torch.tensor(data, dtype=torch.float64, device="cuda"), nsteps=nsteps)
     yield out
