@@ -44,7 +44,10 @@
  *                                        3D: xx, yy, zz, yz, xz, xy,
  *                                        Section 2) and canonical dual basis
  *                                        function m.
- *   batched vectors  [...][r] with the right-hand-side index r innermost.
+ *   batched vectors  [r][...]: n_rhs right-hand sides stored one after
+ *                                        another (column r of a velocity slab
+ *                                        starts at r * n_vel_slab, of a state
+ *                                        at r * n_vel_state, ...).
  *   Faces are numbered by ascending (l(j), local face of l(j)) where the
  *   left element l(j) is the lower element index and local face f of a
  *   simplex is the one opposite its local vertex f.
@@ -160,6 +163,19 @@ int sdg_set_mesh(sdg_ctx* ctx, int dim, int64_t n_vert, const double* xyz,
  * or SDG_SCHEME_CN (eqs. NM25.cn-NM26.cn, requires p_gamma = 0), time step
  * dt > 0.  SDG_EUNSUPPORTED if the (dim, p, N_gamma) kernels are not
  * compiled in. */
+/* A batch of independent meshes of one dimension (Section 3 for each),
+ * solved together: mesh q has vertices xyz[vert_off[q]*dim ..
+ * vert_off[q+1]*dim) and elements elem[elem_off[q]*(dim+1) ..
+ * elem_off[q+1]*(dim+1)) whose vertex indices are local to the mesh (host
+ * arrays; offsets int64, n_mesh+1 entries starting at 0).  The library
+ * concatenates them into one mesh (meshes share no faces, no periodicity):
+ * elements, faces, materials and every state vector are laid out mesh after
+ * mesh in element order, and sdg_solve_step runs one Krylov process per mesh
+ * (own tolerance, segmented reductions) inside shared launches.  Replaces any
+ * earlier mesh. */
+int sdg_set_mesh_batch(sdg_ctx* ctx, int dim, int n_mesh, const int64_t* vert_off, const double* xyz,
+                       const int64_t* elem_off, const int64_t* elem);
+
 int sdg_set_discretization(sdg_ctx* ctx, int p, int p_gamma, int scheme, double dt);
 
 /* Per-element Lame parameters and density (host, n_elem each, > 0).
@@ -170,8 +186,11 @@ int sdg_set_material(sdg_ctx* ctx, const double* lambda, const double* mu, const
  * upload them.  precisions = SDG_PREC_F64 | SDG_PREC_F32 selects which
  * copies of the blocks are stored; OR in SDG_ASSEMBLE_BLOCK_PRECOND to also
  * invert the element diagonal blocks of the velocity operator (eq. pre1,
- * stored in FP32, (N_gamma d N_phi)^2 floats per element).  max_rhs (>= 1)
- * sizes the workspaces for batched applies and solves. */
+ * stored in FP32: (d N_phi)^2 floats per element for one time node; for
+ * several, the generalised eigenvectors of the element stiffness and mass
+ * and the N_gamma x N_gamma inverses per eigenvalue, (d N_phi)^2 +
+ * d N_phi N_gamma^2 floats).  max_rhs (1..1024) sizes the workspaces for
+ * batched applies and solves (every Krylov vector holds max_rhs columns). */
 int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs);
 
 int sdg_query(const sdg_ctx* ctx, sdg_sizes* out);
@@ -190,7 +209,8 @@ int sdg_set_operator_variant(sdg_ctx* ctx, int variant);
 int sdg_face_table(const sdg_ctx* ctx, int64_t* left, int32_t* left_face,
                    int64_t* right, int32_t* right_face);
 
-/* y = A v for n_rhs right-hand sides (device, slab layout, r innermost).
+/* y = A v for n_rhs right-hand sides (device, slab layout, column after
+ * column, n_rhs <= max_rhs), one launch of each kernel for all columns.
  * precision SDG_PREC_F64 or SDG_PREC_F32 (FP32 blocks and arithmetic, FP64
  * input/output).  v and y must not alias. */
 int sdg_apply_velocity_operator(sdg_ctx* ctx, const double* v, double* y, int n_rhs,
@@ -207,13 +227,21 @@ int sdg_apply_adjoint(sdg_ctx* ctx, const double* w, double* y, int n_rhs,
  * r % n_src only; with n_rhs = 1 all sources act together. */
 int sdg_set_sources(sdg_ctx* ctx, int64_t n_src, const double* pos, const double* dir);
 
+/* As sdg_set_sources on a mesh batch: source s is located in mesh mesh[s]
+ * (host int32) only; all sources act in one solve. */
+int sdg_set_mesh_sources(sdg_ctx* ctx, int64_t n_src, const double* pos, const double* dir,
+                         const int32_t* mesh);
+
 /* One implicit time step of n_rhs independent states:
  *   1. right-hand side of eq. (velocity.sys) (or velocity.sys.cn) from the
- *      old state v_state (device [elem][c][k][r]) and sigma_state (device
- *      [face][s][m][r]) plus the point sources with amplitudes
+ *      old state v_state (device [r][elem][c][k]) and sigma_state (device
+ *      [r][face][s][m]) plus the point sources with amplitudes
  *      amp[n_src*N_gamma] (host; S(t) at the slab's time nodes, the
  *      midpoint for Crank-Nicolson; NULL = no source);
- *   2. Krylov solve for the velocity slab (CG or restarted GMRES);
+ *   2. Krylov solve for the velocity slab (CG or restarted GMRES; with
+ *      n_rhs > 1 or on a mesh batch, GMRES with one Arnoldi process, one
+ *      tolerance and one convergence flag per column or mesh, sharing every
+ *      kernel launch; rtol then bounds every column's relative residual);
  *   3. stress back-substitution, eq. (NM26) or (NM26.cn);
  *   4. overwrite v_state and sigma_state with the end-of-slab values.
  * v_slab / sigma_slab (device, optional) receive the slab DOFs.
@@ -230,8 +258,9 @@ int sdg_energy(sdg_ctx* ctx, const double* v_state, const double* sigma_state, i
                double* out, void* stream);
 
 /* Velocity of a state at n_pts host points pts[n_pts*dim], written to
- * out[n_pts*dim*n_rhs] (device, [pt][c][r]).  Points outside the mesh give
- * SDG_EINVAL. */
+ * out[n_rhs*n_pts*dim] (device, [r][pt][c]).  Points outside the mesh give
+ * SDG_EINVAL.  The located elements of the last point set are kept, so
+ * repeated calls with the same points locate them once. */
 int sdg_sample_velocity(sdg_ctx* ctx, const double* v_state, int n_rhs, int64_t n_pts,
                         const double* pts, double* out, void* stream);
 

@@ -36,7 +36,7 @@ EXPORTED = ("sdg_last_error", "sdg_create", "sdg_destroy", "sdg_set_mesh", "sdg_
             "sdg_set_material", "sdg_assemble", "sdg_query", "sdg_set_operator_variant", "sdg_face_table",
             "sdg_apply_velocity_operator", "sdg_apply_adjoint", "sdg_set_sources", "sdg_solve_step",
             "sdg_energy", "sdg_sample_velocity", "sdg_eval_stress", "sdg_adjoint_step",
-            "sdg_sample_velocity_adjoint")
+            "sdg_sample_velocity_adjoint", "sdg_set_mesh_batch", "sdg_set_mesh_sources")
 
 
 class SdgError(RuntimeError):
@@ -106,6 +106,8 @@ def lib():
         "sdg_eval_stress": ([_P, _P, i, ctypes.c_int64, _DP, _I64P, _P, _P], i),
         "sdg_adjoint_step": ([_P, _P, _P, _P, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P], i),
         "sdg_sample_velocity_adjoint": ([_P, i, ctypes.c_int64, _DP, _P, _P, _P], i),
+        "sdg_set_mesh_batch": ([_P, i, i, _I64P, _DP, _I64P, _I64P], i),
+        "sdg_set_mesh_sources": ([_P, ctypes.c_int64, _DP, _DP, ctypes.POINTER(ctypes.c_int32)], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -166,6 +168,28 @@ def sdg_set_mesh(h, xyz, elem, period=None):
     per = _host(period, np.float64) if period is not None else None
     _check(lib().sdg_set_mesh(h, dim, xyz.shape[0], _hp(xyz, ctypes.c_double), elem.shape[0],
                               _hp(elem, ctypes.c_int64), _hp(per, ctypes.c_double)))
+
+
+def sdg_set_mesh_batch(h, meshes):
+    """meshes: sequence of (xyz (nv, dim), elem (ne, dim+1)) with local vertex indices."""
+    xyz = [_host(m[0], np.float64) for m in meshes]
+    elem = [_host(m[1], np.int64) for m in meshes]
+    dim = xyz[0].shape[1]
+    voff = np.concatenate([[0], np.cumsum([x.shape[0] for x in xyz])]).astype(np.int64)
+    eoff = np.concatenate([[0], np.cumsum([e.shape[0] for e in elem])]).astype(np.int64)
+    X = np.ascontiguousarray(np.concatenate(xyz, axis=0))
+    E = np.ascontiguousarray(np.concatenate(elem, axis=0))
+    _check(lib().sdg_set_mesh_batch(h, dim, len(meshes), _hp(voff, ctypes.c_int64), _hp(X, ctypes.c_double),
+                                    _hp(eoff, ctypes.c_int64), _hp(E, ctypes.c_int64)))
+    return voff, eoff
+
+
+def sdg_set_mesh_sources(h, pos, direction, mesh):
+    pos = _host(pos, np.float64)
+    d = _host(direction, np.float64)
+    mesh = _host(mesh, np.int32)
+    _check(lib().sdg_set_mesh_sources(h, pos.shape[0], _hp(pos, ctypes.c_double), _hp(d, ctypes.c_double),
+                                      _hp(mesh, ctypes.c_int32)))
 
 
 def sdg_set_discretization(h, p, p_gamma, scheme, dt):
@@ -308,21 +332,35 @@ class Context:
         self.sizes = sdg_query(self.h)
         return self.sizes
 
+    def setup_batch(self, meshes, p, p_gamma, scheme, dt, lam, mu, rho, precisions=SDG_PREC_F64 | SDG_PREC_F32):
+        """Several independent meshes (list of (xyz, elem)) solved together;
+        lam, mu, rho are concatenated mesh after mesh."""
+        voff, eoff = sdg_set_mesh_batch(self.h, meshes)
+        sdg_set_discretization(self.h, p, p_gamma, scheme, dt)
+        sdg_set_material(self.h, lam, mu, rho)
+        sdg_assemble(self.h, precisions, 1)
+        self.sizes = sdg_query(self.h)
+        self.mesh_elem_off = eoff
+        return self.sizes
+
+    def set_mesh_sources(self, pos, direction, mesh):
+        sdg_set_mesh_sources(self.h, pos, direction, mesh)
+
     def face_table(self):
         return sdg_face_table(self.h, self.sizes["n_face"])
 
     def _n(self, key):
         return self.sizes[key]
 
-    def apply(self, v, y, precision=SDG_PREC_F64, stream=None):
-        n = self._n("n_vel_slab")
+    def apply(self, v, y, precision=SDG_PREC_F64, stream=None, n_rhs=1):
+        n = self._n("n_vel_slab") * n_rhs
         _dev(v, n, "v"), _dev(y, n, "y")
-        sdg_apply_velocity_operator(self.h, v, y, 1, precision, stream)
+        sdg_apply_velocity_operator(self.h, v, y, n_rhs, precision, stream)
 
-    def apply_adjoint(self, w, y, precision=SDG_PREC_F64, stream=None):
-        n = self._n("n_vel_slab")
+    def apply_adjoint(self, w, y, precision=SDG_PREC_F64, stream=None, n_rhs=1):
+        n = self._n("n_vel_slab") * n_rhs
         _dev(w, n, "w"), _dev(y, n, "y")
-        sdg_apply_adjoint(self.h, w, y, 1, precision, stream)
+        sdg_apply_adjoint(self.h, w, y, n_rhs, precision, stream)
 
     def set_operator_variant(self, variant):
         """0/1/2 pins a face-kernel variant, -1 reruns the autotuner."""
@@ -333,13 +371,20 @@ class Context:
     def set_sources(self, pos, direction):
         sdg_set_sources(self.h, pos, direction)
 
-    def step(self, v_state, sigma_state, amp=None, **kw):
-        _dev(v_state, self._n("n_vel_state"), "v_state")
-        _dev(sigma_state, self._n("n_stress_state"), "sigma_state")
-        return sdg_solve_step(self.h, v_state, sigma_state, amp, **kw)
+    def step(self, v_state, sigma_state, amp=None, n_rhs=1, **kw):
+        _dev(v_state, self._n("n_vel_state") * n_rhs, "v_state")
+        _dev(sigma_state, self._n("n_stress_state") * n_rhs, "sigma_state")
+        if kw.get("v_slab") is not None:
+            _dev(kw["v_slab"], self._n("n_vel_slab") * n_rhs, "v_slab")
+        if kw.get("sigma_slab") is not None:
+            _dev(kw["sigma_slab"], self._n("n_stress_slab") * n_rhs, "sigma_slab")
+        return sdg_solve_step(self.h, v_state, sigma_state, amp, n_rhs=n_rhs, **kw)
 
-    def energy(self, v_state, sigma_state):
-        return float(sdg_energy(self.h, v_state, sigma_state)[0])
+    def energy(self, v_state, sigma_state, n_rhs=1):
+        _dev(v_state, self._n("n_vel_state") * n_rhs, "v_state")
+        _dev(sigma_state, self._n("n_stress_state") * n_rhs, "sigma_state")
+        e = sdg_energy(self.h, v_state, sigma_state, n_rhs)
+        return float(e[0]) if n_rhs == 1 else e
 
     def adjoint_step(self, v_old, v_slab, vbar, sigma_bar, grad, opts=None, stream=None):
         _dev(v_old, self._n("n_vel_state"), "v_old")

@@ -104,7 +104,7 @@ void check_prec(Ctx& c, int prec) {
 
 }  // namespace
 
-void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s) {
+void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s, int ncols) {
   OpArgs a = base_args(c, prec);
   a.variant = prec == SDG_PREC_F32 ? c.variant32 : c.variant64;
   a.v = v;
@@ -112,6 +112,9 @@ void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipS
   a.y = y;
   a.use_g = 1;
   a.c = transpose ? c.adj : c.op;
+  a.n_cols = ncols;
+  a.cs_v = a.cs_y = c.n_slab;
+  a.cs_z = c.z_col;
   launch_face(c.hs.dim, c.hs.p, c.hs.ng, prec, kScatter, a, s);
   SDG_HIP(hipGetLastError());
   launch_elem(c.hs.dim, c.hs.p, c.hs.ng, a, s);
@@ -151,7 +154,7 @@ static void autotune(Ctx& c) {
   SDG_HIP(hipEventDestroy(e1));
 }
 
-void apply_precond(Ctx& c, int kind, const double* x, double* y, bool transpose, hipStream_t s) {
+void apply_precond(Ctx& c, int kind, const double* x, double* y, bool transpose, hipStream_t s, int ncols) {
   const HostSetup& hs = c.hs;
   if (kind == SDG_PRECOND_MASS) {
     OpArgs a = base_args(c, SDG_PREC_F64);
@@ -160,18 +163,59 @@ void apply_precond(Ctx& c, int kind, const double* x, double* y, bool transpose,
     a.v = x;
     a.y = y;
     a.c = transpose ? c.precA : c.precF;
+    a.n_cols = ncols;
+    a.cs_v = a.cs_y = c.n_slab;
     launch_elem(hs.dim, hs.p, hs.ng, a, s);
     SDG_HIP(hipGetLastError());
   } else if (kind == SDG_PRECOND_BLOCK) {
     require(c.d_Pblk.p != nullptr || c.d_Pq.p != nullptr, SDG_ESTATE,
             "block preconditioner not assembled (pass SDG_ASSEMBLE_BLOCK_PRECOND)");
     if (c.pblk_factored)
-      launch_block_apply_fact(hs.n_elem, hs.ng, hs.dim * hs.nphi, c.d_Pq.p, c.d_Pb.p, x, y, transpose, s);
+      launch_block_apply_fact(hs.n_elem, hs.ng, hs.dim * hs.nphi, c.d_Pq.p, c.d_Pb.p, x, y, transpose, s, ncols,
+                              c.n_slab);
     else
-      launch_block_apply(hs.n_elem, hs.ng * hs.dim * hs.nphi, c.d_Pblk.p, x, y, transpose, s);
+      launch_block_apply(hs.n_elem, hs.ng * hs.dim * hs.nphi, c.d_Pblk.p, x, y, transpose, s, ncols, c.n_slab);
   } else {
-    vec_copy(c.n_slab, x, y, s);
+    vec_copy(c.n_slab * ncols, x, y, s);
   }
+}
+
+// Elements and nodal basis values of sampling points, located on the host and
+// kept on the device: repeated calls with the same points reuse them.
+void locate_points(Ctx& c, int64_t n_pts, const double* pts) {
+  const HostSetup& hs = c.hs;
+  const size_t nd = (size_t)n_pts * hs.dim;
+  if (c.samp_pts.size() == nd && std::equal(pts, pts + nd, c.samp_pts.begin()) && c.d_samp_elem.p) return;
+  std::vector<int64_t> el(n_pts);
+  std::vector<double> phi((size_t)n_pts * hs.nphi);
+  for (int64_t q = 0; q < n_pts; ++q) {
+    el[q] = locate_point(hs, pts + q * hs.dim);
+    require(el[q] >= 0, SDG_EINVAL, "sample point outside the mesh");
+    eval_velocity_basis(hs, el[q], pts + q * hs.dim, &phi[q * hs.nphi], 1e-12);
+  }
+  c.d_samp_elem.alloc(n_pts);
+  c.d_samp_phi.alloc(phi.size());
+  SDG_HIP(hipMemcpy(c.d_samp_elem.p, el.data(), el.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  SDG_HIP(hipMemcpy(c.d_samp_phi.p, phi.data(), phi.size() * sizeof(double), hipMemcpyHostToDevice));
+  c.samp_pts.assign(pts, pts + nd);
+}
+
+// Partition of the independent systems of a batched solve with ncols columns,
+// or of the meshes of a mesh batch (rebuilt when the column count changes).
+MultiSys& systems(Ctx& c, int ncols) {
+  const int key = c.n_mesh > 1 ? -1 : ncols;
+  if (c.msys_key != key) {
+    std::vector<int64_t> off;
+    if (c.n_mesh > 1) {
+      const int64_t per = (int64_t)c.hs.ng * c.hs.dim * c.hs.nphi;
+      for (int64_t e : c.mesh_elem_off) off.push_back(e * per);
+    } else {
+      for (int r = 0; r <= ncols; ++r) off.push_back((int64_t)r * c.n_slab);
+    }
+    c.msys.build(off);
+    c.msys_key = key;
+  }
+  return c.msys;
 }
 
 }  // namespace sdg
@@ -214,6 +258,9 @@ int sdg_set_mesh(sdg_ctx* ctx, int dim, int64_t n_vert, const double* xyz, int64
     c.dim = dim;
     c.xyz.assign(xyz, xyz + n_vert * dim);
     c.elem.assign(elem, elem + n_elem * (dim + 1));
+    c.n_mesh = 1;
+    c.mesh_vert_off = {0, n_vert};
+    c.mesh_elem_off = {0, n_elem};
     if (period) {
       c.period.assign(period, period + dim);
       for (double P : c.period) require(P > 0 && std::isfinite(P), SDG_EINVAL, "period must be positive");
@@ -221,6 +268,43 @@ int sdg_set_mesh(sdg_ctx* ctx, int dim, int64_t n_vert, const double* xyz, int64
       c.period.clear();
     }
     for (double x : c.xyz) require(std::isfinite(x), SDG_EINVAL, "non-finite vertex coordinate");
+    c.have_mesh = true;
+    c.assembled = false;
+  });
+}
+
+int sdg_set_mesh_batch(sdg_ctx* ctx, int dim, int n_mesh, const int64_t* vert_off, const double* xyz,
+                       const int64_t* elem_off, const int64_t* elem) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(dim == 2 || dim == 3, SDG_EINVAL, "dim must be 2 or 3");
+    require(n_mesh >= 1 && n_mesh <= kMaxSystems, SDG_EINVAL, "n_mesh must be in [1, 1024]");
+    require(vert_off && xyz && elem_off && elem, SDG_EINVAL, "null mesh array");
+    require(vert_off[0] == 0 && elem_off[0] == 0, SDG_EINVAL, "offsets must start at 0");
+    for (int q = 0; q < n_mesh; ++q)
+      require(vert_off[q + 1] > vert_off[q] && elem_off[q + 1] > elem_off[q], SDG_EINVAL,
+              "every mesh of the batch needs vertices and elements");
+    const int64_t nv = vert_off[n_mesh], ne = elem_off[n_mesh];
+    require(ne < (int64_t)1 << 31, SDG_EINVAL, "too many elements");
+    const int nvpe = dim + 1;
+    std::vector<int64_t> el((size_t)ne * nvpe);
+    for (int q = 0; q < n_mesh; ++q) {
+      const int64_t nvq = vert_off[q + 1] - vert_off[q];
+      for (int64_t e = elem_off[q]; e < elem_off[q + 1]; ++e)
+        for (int k = 0; k < nvpe; ++k) {
+          const int64_t v = elem[e * nvpe + k];
+          require(v >= 0 && v < nvq, SDG_EMESH, "vertex index outside its mesh");
+          el[e * nvpe + k] = v + vert_off[q];
+        }
+    }
+    c.dim = dim;
+    c.xyz.assign(xyz, xyz + nv * dim);
+    for (double x : c.xyz) require(std::isfinite(x), SDG_EINVAL, "non-finite vertex coordinate");
+    c.elem.swap(el);
+    c.period.clear();
+    c.n_mesh = n_mesh;
+    c.mesh_vert_off.assign(vert_off, vert_off + n_mesh + 1);
+    c.mesh_elem_off.assign(elem_off, elem_off + n_mesh + 1);
     c.have_mesh = true;
     c.assembled = false;
   });
@@ -271,9 +355,12 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     require(c.have_mesh && c.have_disc && c.have_mat, SDG_ESTATE, "mesh, discretization and material must be set");
     require((precisions & (SDG_PREC_F64 | SDG_PREC_F32)) != 0 && (precisions & ~7u) == 0, SDG_EINVAL,
             "precisions must be a non-empty subset of SDG_PREC_F64 | SDG_PREC_F32 (| SDG_ASSEMBLE_BLOCK_PRECOND)");
-    require(max_rhs == 1, SDG_EUNSUPPORTED, "batched right-hand sides are not built in this version");
+    require(max_rhs >= 1 && max_rhs <= kMaxSystems, SDG_EINVAL, "max_rhs must be in [1, 1024]");
+    require(max_rhs == 1 || c.n_mesh == 1, SDG_EUNSUPPORTED, "batched right-hand sides on a mesh batch");
     SDG_HIP(hipSetDevice(c.device));
     c.assembled = false;
+    c.msys_key = 0;
+    c.samp_pts.clear();
     HostSetup& hs = c.hs;
     const int64_t n_elem = (int64_t)(c.elem.size() / (c.dim + 1));
     const int64_t n_vert = (int64_t)(c.xyz.size() / c.dim);
@@ -399,10 +486,13 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
       c.d_face_grad.alloc((size_t)hs.n_face * 2);
     }
 
-    // workspaces
-    c.d_z.alloc((size_t)hs.n_elem * (d + 1) * ng * d * nphi);
-    const size_t n = c.n_slab;
-    c.d_V.alloc(c.scheme == SDG_SCHEME_CN ? n : (size_t)(kMaxRestart + 1) * n);
+    // workspaces (every solver vector holds max_rhs columns)
+    const size_t R = (size_t)max_rhs;
+    c.z_col = hs.n_elem * (d + 1) * ng * d * nphi;
+    c.d_z.alloc((size_t)c.z_col * R);
+    const size_t n = c.n_slab * R;
+    const bool multi = max_rhs > 1 || c.n_mesh > 1;
+    c.d_V.alloc(c.scheme == SDG_SCHEME_CN && !multi ? n : (size_t)(kMaxRestart + 1) * n);
     c.d_x.alloc(n);
     c.d_b.alloc(n);
     c.d_r.alloc(n);
@@ -414,8 +504,8 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     c.d_sc.alloc(1);
     SDG_HIP(hipMemset(c.d_sc.p, 0, sizeof(DevScalars)));
     if (!c.h_pinned) SDG_HIP(hipHostMalloc((void**)&c.h_pinned, 16 * sizeof(double), hipHostMallocDefault));
-    c.d_tmp_state.alloc(c.n_state);
-    c.d_tmp_sig.alloc(c.n_sig_state);
+    c.d_tmp_state.alloc(c.n_state * R);
+    c.d_tmp_sig.alloc(c.n_sig_state * R);
     c.d_src_amp.alloc((size_t)std::max<int64_t>(c.n_src, 1) * ng);
     SDG_HIP(hipDeviceSynchronize());
     c.assembled = true;
@@ -497,10 +587,10 @@ static int apply_common(sdg_ctx* ctx, const double* v, double* y, int n_rhs, int
     require(c.assembled, SDG_ESTATE, "assemble first");
     require(v && y, SDG_EINVAL, "null vector");
     require(v != y, SDG_EINVAL, "v and y must not alias");
-    require(n_rhs == 1, SDG_EUNSUPPORTED, "batched right-hand sides are not built in this version");
+    require(n_rhs >= 1 && n_rhs <= c.max_rhs, SDG_EINVAL, "n_rhs must be in [1, max_rhs of sdg_assemble]");
     check_prec(c, precision);
     SDG_HIP(hipSetDevice(c.device));
-    apply_op(c, v, y, precision, transpose, (hipStream_t)stream);
+    apply_op(c, v, y, precision, transpose, (hipStream_t)stream, n_rhs);
   });
 }
 
@@ -512,7 +602,7 @@ int sdg_apply_adjoint(sdg_ctx* ctx, const double* w, double* y, int n_rhs, int p
   return apply_common(ctx, w, y, n_rhs, precision, stream, true);
 }
 
-int sdg_set_sources(sdg_ctx* ctx, int64_t n_src, const double* pos, const double* dir) {
+static int set_sources_impl(sdg_ctx* ctx, int64_t n_src, const double* pos, const double* dir, const int32_t* mesh) {
   return guard([&] {
     Ctx& c = ctx_of(ctx);
     require(c.assembled, SDG_ESTATE, "assemble first");
@@ -522,7 +612,13 @@ int sdg_set_sources(sdg_ctx* ctx, int64_t n_src, const double* pos, const double
     std::vector<int64_t> el(n_src);
     std::vector<double> phi((size_t)n_src * hs.nphi), dr((size_t)n_src * hs.dim);
     for (int64_t s = 0; s < n_src; ++s) {
-      int64_t e = locate_point(hs, pos + s * hs.dim);
+      int64_t e0 = 0, e1 = -1;
+      if (mesh) {
+        require(mesh[s] >= 0 && mesh[s] < c.n_mesh, SDG_EINVAL, "source mesh index out of range");
+        e0 = c.mesh_elem_off[mesh[s]];
+        e1 = c.mesh_elem_off[mesh[s] + 1];
+      }
+      int64_t e = locate_point(hs, pos + s * hs.dim, e0, e1);
       require(e >= 0, SDG_EINVAL, "source " + std::to_string(s) + " lies outside the mesh");
       eval_velocity_basis(hs, e, pos + s * hs.dim, &phi[s * hs.nphi], 1e-12);
       el[s] = e;
@@ -545,6 +641,15 @@ int sdg_set_sources(sdg_ctx* ctx, int64_t n_src, const double* pos, const double
   });
 }
 
+int sdg_set_sources(sdg_ctx* ctx, int64_t n_src, const double* pos, const double* dir) {
+  return set_sources_impl(ctx, n_src, pos, dir, nullptr);
+}
+
+int sdg_set_mesh_sources(sdg_ctx* ctx, int64_t n_src, const double* pos, const double* dir, const int32_t* mesh) {
+  if (!mesh && n_src > 0) return guard([] { throw Error(SDG_EINVAL, "null mesh index array"); });
+  return set_sources_impl(ctx, n_src, pos, dir, mesh);
+}
+
 int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const double* amp, int n_rhs,
                    const sdg_solve_opts* opts, sdg_solve_info* info, double* v_slab, double* sigma_slab,
                    void* stream) {
@@ -553,16 +658,20 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     Ctx& c = ctx_of(ctx);
     require(c.assembled, SDG_ESTATE, "assemble first");
     require(v_state && sigma_state && opts, SDG_EINVAL, "null argument");
-    require(n_rhs == 1, SDG_EUNSUPPORTED, "batched right-hand sides are not built in this version");
+    require(n_rhs >= 1 && n_rhs <= c.max_rhs, SDG_EINVAL, "n_rhs must be in [1, max_rhs of sdg_assemble]");
     require(opts->rtol > 0 && opts->max_iter > 0, SDG_EINVAL, "rtol and max_iter must be positive");
     const int prec = opts->precision == 0 ? SDG_PREC_F64 : opts->precision;
     check_prec(c, SDG_PREC_F64);
     if (prec == SDG_PREC_F32) check_prec(c, SDG_PREC_F32);
+    const int R = n_rhs;
+    const bool multi = R > 1 || c.n_mesh > 1;
     int solver = opts->solver;
-    if (solver == SDG_SOLVER_AUTO) solver = c.scheme == SDG_SCHEME_CN ? SDG_SOLVER_CG : SDG_SOLVER_GMRES;
+    if (solver == SDG_SOLVER_AUTO) solver = c.scheme == SDG_SCHEME_CN && !multi ? SDG_SOLVER_CG : SDG_SOLVER_GMRES;
     require(solver == SDG_SOLVER_CG || solver == SDG_SOLVER_GMRES, SDG_EINVAL, "unknown solver");
-    require(solver != SDG_SOLVER_GMRES || c.d_V.n >= (size_t)(kMaxRestart + 1) * c.n_slab, SDG_EINVAL,
-            "GMRES workspace is only allocated for the space-time scheme");
+    require(!multi || solver == SDG_SOLVER_GMRES, SDG_EUNSUPPORTED,
+            "batched and mesh-batch solves use GMRES (SDG_SOLVER_GMRES or AUTO)");
+    require(solver != SDG_SOLVER_GMRES || c.d_V.n >= (size_t)(kMaxRestart + 1) * c.n_slab * R, SDG_EINVAL,
+            "GMRES workspace is only allocated for the space-time scheme or batched solves");
     const int restart = opts->restart > 0 ? opts->restart : 30;
     require(restart <= kMaxRestart, SDG_EINVAL, "restart must be <= 32");
     SDG_HIP(hipSetDevice(c.device));
@@ -570,8 +679,10 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     const HostSetup& hs = c.hs;
     const int d = hs.dim, ng = hs.ng, nvs = d * hs.nphi;
     const double dt = hs.dt;
+    const int64_t N = c.n_slab * R;
+    const int64_t sig_slab_col = hs.n_face * ng * hs.nsig * hs.npsi;
 
-    // 1. right-hand side
+    // 1. right-hand side (one launch for all columns)
     if (c.scheme == SDG_SCHEME_CN) {
       OpArgs a = base_args(c, SDG_PREC_F64);
       a.v = v_state;
@@ -582,6 +693,11 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
       a.c.Cg[0] = -dt * dt / 4.0;
       a.c.Cs[0] = dt;
       a.c.Tm[0] = 1.0;
+      a.n_cols = R;
+      a.cs_v = c.n_state;
+      a.cs_sig_in = c.n_sig_state;
+      a.cs_z = c.z_col;
+      a.cs_y = c.n_slab;
       launch_face(d, hs.p, 1, SDG_PREC_F64, kScatter, a, s);
       launch_elem(d, hs.p, 1, a, s);
     } else {
@@ -591,12 +707,19 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
       a.z = c.d_z.p;
       a.use_g = 0;
       a.c.Cs[0] = 1.0;
+      a.n_cols = R;
+      a.cs_sig_in = c.n_sig_state;
+      a.cs_z = c.z_col;
       launch_face(d, hs.p, 1, SDG_PREC_F64, kScatter, a, s);
       OpArgs e = base_args(c, SDG_PREC_F64);
       e.v = v_state;
       e.v_spatial = 1;
       e.z = c.d_z.p;
       e.y = c.d_b.p;
+      e.n_cols = R;
+      e.cs_v = c.n_state;
+      e.cs_z = c.z_col;
+      e.cs_y = c.n_slab;
       for (int aa = 0; aa < ng; ++aa) {
         e.c.Tm[aa * ng] = hs.e0[aa];
         double q = 0.0;
@@ -608,11 +731,11 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     SDG_HIP(hipGetLastError());
     if (amp && c.n_src > 0) {
       SDG_HIP(hipMemcpyAsync(c.d_src_amp.p, amp, c.n_src * ng * sizeof(double), hipMemcpyHostToDevice, s));
-      launch_add_sources(c, c.d_b.p, c.d_src_amp.p, s);
+      launch_add_sources(c, c.d_b.p, c.d_src_amp.p, s, R);
     }
 
-    // 2. initial guess and Krylov solve
-    launch_broadcast_time(hs.n_elem, ng, nvs, v_state, c.d_x.p, s);
+    // 2. initial guess (old state at every time node) and Krylov solve
+    launch_broadcast_time(hs.n_elem * R, ng, nvs, v_state, c.d_x.p, s);
     KrylovCfg kc;
     kc.check_every = opts->check_every > 0 ? opts->check_every : 5;
     kc.restart = restart;
@@ -623,63 +746,83 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
       k2.rtol = tol;
       k2.max_iter = maxit;
       k2.prec = pr;
-      return solver == SDG_SOLVER_CG ? solve_cg(c, b, x, k2, s) : solve_gmres(c, b, x, k2, s);
+      if (!multi) return solver == SDG_SOLVER_CG ? solve_cg(c, b, x, k2, s) : solve_gmres(c, b, x, k2, s);
+      MultiSys& m = systems(c, R);
+      std::function<void(const double*, double*)> op = [&](const double* in, double* out) {
+        apply_op(c, in, out, pr, false, s, R);
+      };
+      std::function<void(const double*, double*)> pre = [&](const double* in, double* out) {
+        apply_precond(c, k2.precond, in, out, false, s, R);
+      };
+      return solve_gmres_multi(m, b, x, k2, s, op, k2.precond != SDG_PRECOND_NONE ? &pre : nullptr, c.d_V.p,
+                               c.d_r.p, c.d_w.p, c.d_t.p);
     };
     if (prec == SDG_PREC_F64) {
       res = inner(c.d_b.p, c.d_x.p, opts->rtol, opts->max_iter, SDG_PREC_F64);
     } else {
       // FP32 operator inside FP64 iterative refinement
-      const int64_t n = c.n_slab;
       const double inner_tol = opts->inner_rtol > 0 ? opts->inner_rtol : 1e-4;
       const int max_ref = opts->max_refine > 0 ? opts->max_refine : 10;
-      double bnorm = std::sqrt(vec_dot_host(c, n, c.d_b.p, c.d_b.p, s));
-      res.bnorm = bnorm;
-      for (int k = 0; k <= max_ref; ++k) {
-        apply_op(c, c.d_x.p, c.d_t.p, SDG_PREC_F64, false, s);
+      auto rel_residual = [&](double* bnorm_out) {
+        // d = b - A64 x and the worst relative residual over the systems
+        apply_op(c, c.d_x.p, c.d_t.p, SDG_PREC_F64, false, s, R);
         ++res.matvecs;
-        vec_copy(n, c.d_b.p, c.d_d.p, s);
-        vec_axpby(n, -1.0, c.d_t.p, 1.0, c.d_d.p, s);  // d = b - A64 x
-        double rn = std::sqrt(vec_dot_host(c, n, c.d_d.p, c.d_d.p, s));
-        require(std::isfinite(rn), SDG_ENONFINITE, "non-finite residual");
-        res.rel_res = bnorm > 0 ? rn / bnorm : 0.0;
-        if (res.rel_res <= opts->rtol || k == max_ref || res.iters >= opts->max_iter) {
-          res.converged = res.rel_res <= opts->rtol;
+        vec_copy(N, c.d_b.p, c.d_d.p, s);
+        vec_axpby(N, -1.0, c.d_t.p, 1.0, c.d_d.p, s);
+        if (!multi) {
+          const double bn = std::sqrt(vec_dot_host(c, N, c.d_b.p, c.d_b.p, s));
+          const double rn = std::sqrt(vec_dot_host(c, N, c.d_d.p, c.d_d.p, s));
+          *bnorm_out = bn;
+          return bn > 0 ? rn / bn : rn;
+        }
+        return multi_rel_residual(systems(c, R), c.d_b.p, c.d_d.p, s, bnorm_out);
+      };
+      for (int k = 0; k <= max_ref; ++k) {
+        double bnorm = 0.0;
+        const double rr = rel_residual(&bnorm);
+        require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
+        res.rel_res = rr;
+        res.bnorm = bnorm;
+        if (rr <= opts->rtol || k == max_ref || res.iters >= opts->max_iter) {
+          res.converged = rr <= opts->rtol;
           break;
         }
         // correction: A32 e = d from a zero initial guess, then x += e
-        vec_fill(n, 0.0, c.d_e.p, s);
+        vec_fill(N, 0.0, c.d_e.p, s);
         SolveResult in = inner(c.d_d.p, c.d_e.p, inner_tol, opts->max_iter - res.iters, SDG_PREC_F32);
         res.iters += in.iters;
         res.matvecs += in.matvecs;
         ++res.refinements;
-        vec_axpby(n, 1.0, c.d_e.p, 1.0, c.d_x.p, s);
+        vec_axpby(N, 1.0, c.d_e.p, 1.0, c.d_x.p, s);
       }
     }
 
     // 3. stress back-substitution and 4. end-of-slab state
+    OpArgs a = base_args(c, SDG_PREC_F64);
+    a.sig_in = sigma_state;
+    a.use_g = 1;
+    a.s_out = sigma_slab;
+    a.s_end = c.d_tmp_sig.p;
+    a.n_cols = R;
+    a.cs_v = c.n_slab;
+    a.cs_sig_in = c.n_sig_state;
+    a.cs_s_out = sig_slab_col;
+    a.cs_s_end = c.n_sig_state;
     if (c.scheme == SDG_SCHEME_CN) {
-      vec_copy(c.n_slab, v_state, c.d_t.p, s);
-      vec_axpby(c.n_slab, 1.0, c.d_x.p, 1.0, c.d_t.p, s);  // v^n + v^{n+1}
-      OpArgs a = base_args(c, SDG_PREC_F64);
+      vec_copy(N, v_state, c.d_t.p, s);
+      vec_axpby(N, 1.0, c.d_x.p, 1.0, c.d_t.p, s);  // v^n + v^{n+1}
       a.v = c.d_t.p;
-      a.sig_in = sigma_state;
-      a.use_g = 1;
       a.c.Cg[0] = -dt / 2.0;
       a.c.Cs[0] = 1.0;
       a.c.send[0] = 1.0;
-      a.s_out = sigma_slab;
-      a.s_end = c.d_tmp_sig.p;
       launch_face(d, hs.p, 1, SDG_PREC_F64, kWriteStress, a, s);
       SDG_HIP(hipGetLastError());
-      vec_copy(c.n_sig_state, c.d_tmp_sig.p, sigma_state, s);
-      if (v_slab) vec_copy(c.n_slab, c.d_x.p, v_slab, s);
-      vec_copy(c.n_state, c.d_x.p, v_state, s);
+      vec_copy(c.n_sig_state * R, c.d_tmp_sig.p, sigma_state, s);
+      if (v_slab) vec_copy(N, c.d_x.p, v_slab, s);
+      vec_copy(c.n_state * R, c.d_x.p, v_state, s);
     } else {
       std::vector<double> Ti = inverse(hs.T, ng);
-      OpArgs a = base_args(c, SDG_PREC_F64);
       a.v = c.d_x.p;
-      a.sig_in = sigma_state;
-      a.use_g = 1;
       for (int aa = 0; aa < ng; ++aa) {
         double q = 0.0;
         for (int b = 0; b < ng; ++b) {
@@ -689,13 +832,11 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
         a.c.Cs[aa] = q;
         a.c.send[aa] = hs.e1[aa];
       }
-      a.s_out = sigma_slab;
-      a.s_end = c.d_tmp_sig.p;
       launch_face(d, hs.p, ng, SDG_PREC_F64, kWriteStress, a, s);
       SDG_HIP(hipGetLastError());
-      vec_copy(c.n_sig_state, c.d_tmp_sig.p, sigma_state, s);
-      if (v_slab) vec_copy(c.n_slab, c.d_x.p, v_slab, s);
-      launch_end_of_slab(hs.n_elem, ng, nvs, c.d_e1.p, c.d_x.p, v_state, s);
+      vec_copy(c.n_sig_state * R, c.d_tmp_sig.p, sigma_state, s);
+      if (v_slab) vec_copy(N, c.d_x.p, v_slab, s);
+      launch_end_of_slab(hs.n_elem * R, ng, nvs, c.d_e1.p, c.d_x.p, v_state, s);
     }
     SDG_HIP(hipStreamSynchronize(s));
     if (!res.converged) throw Error(SDG_ENOCONV, "Krylov solver did not reach rtol within max_iter");
@@ -900,27 +1041,15 @@ int sdg_sample_velocity_adjoint(sdg_ctx* ctx, int n_rhs, int64_t n_pts, const do
   return guard([&] {
     Ctx& c = ctx_of(ctx);
     require(c.assembled, SDG_ESTATE, "assemble first");
-    require(n_rhs == 1, SDG_EUNSUPPORTED, "batched right-hand sides are not built in this version");
+    require(n_rhs == 1, SDG_EUNSUPPORTED, "the sampling transpose takes one right-hand side");
     require(n_pts >= 0 && (n_pts == 0 || (vbar && pts && obs_bar)), SDG_EINVAL, "null argument");
     if (n_pts == 0) return;
     const HostSetup& hs = c.hs;
     require(hs.dim * hs.nphi <= 256, SDG_EUNSUPPORTED, "element too large for the sampling transpose kernel");
-    std::vector<int64_t> el(n_pts);
-    std::vector<double> phi(n_pts * hs.nphi);
-    for (int64_t q = 0; q < n_pts; ++q) {
-      el[q] = locate_point(hs, pts + q * hs.dim);
-      require(el[q] >= 0, SDG_EINVAL, "sample point outside the mesh");
-      eval_velocity_basis(hs, el[q], pts + q * hs.dim, &phi[q * hs.nphi], 1e-12);
-    }
     SDG_HIP(hipSetDevice(c.device));
     hipStream_t s = (hipStream_t)stream;
-    DevBuf<int64_t> de;
-    DevBuf<double> dp;
-    de.alloc(n_pts);
-    dp.alloc(phi.size());
-    SDG_HIP(hipMemcpy(de.p, el.data(), el.size() * sizeof(int64_t), hipMemcpyHostToDevice));
-    SDG_HIP(hipMemcpy(dp.p, phi.data(), phi.size() * sizeof(double), hipMemcpyHostToDevice));
-    launch_sample_adjoint(n_pts, hs.nphi, hs.dim, de.p, dp.p, obs_bar, vbar, s);
+    locate_points(c, n_pts, pts);
+    launch_sample_adjoint(n_pts, hs.nphi, hs.dim, c.d_samp_elem.p, c.d_samp_phi.p, obs_bar, vbar, s);
     SDG_HIP(hipGetLastError());
     SDG_HIP(hipStreamSynchronize(s));
   });
@@ -931,13 +1060,16 @@ int sdg_energy(sdg_ctx* ctx, const double* v_state, const double* sigma_state, i
     Ctx& c = ctx_of(ctx);
     require(c.assembled, SDG_ESTATE, "assemble first");
     require(v_state && sigma_state && out, SDG_EINVAL, "null argument");
-    require(n_rhs == 1, SDG_EUNSUPPORTED, "batched right-hand sides are not built in this version");
+    require(n_rhs >= 1 && n_rhs <= c.max_rhs, SDG_EINVAL, "n_rhs must be in [1, max_rhs of sdg_assemble]");
     SDG_HIP(hipSetDevice(c.device));
     hipStream_t s = (hipStream_t)stream;
-    launch_energy(c, v_state, sigma_state, &c.d_sc.p->dots[1], s);
-    SDG_HIP(hipMemcpyAsync(c.h_pinned, &c.d_sc.p->dots[1], sizeof(double), hipMemcpyDeviceToHost, s));
-    SDG_HIP(hipStreamSynchronize(s));
-    out[0] = c.h_pinned[0];
+    for (int r = 0; r < n_rhs; ++r) {
+      launch_energy(c, v_state + (int64_t)r * c.n_state, sigma_state + (int64_t)r * c.n_sig_state,
+                    &c.d_sc.p->dots[1], s);
+      SDG_HIP(hipMemcpyAsync(c.h_pinned, &c.d_sc.p->dots[1], sizeof(double), hipMemcpyDeviceToHost, s));
+      SDG_HIP(hipStreamSynchronize(s));
+      out[r] = c.h_pinned[0];
+    }
   });
 }
 
@@ -946,26 +1078,17 @@ int sdg_sample_velocity(sdg_ctx* ctx, const double* v_state, int n_rhs, int64_t 
   return guard([&] {
     Ctx& c = ctx_of(ctx);
     require(c.assembled, SDG_ESTATE, "assemble first");
-    require(n_rhs == 1, SDG_EUNSUPPORTED, "batched right-hand sides are not built in this version");
+    require(n_rhs >= 1 && n_rhs <= c.max_rhs, SDG_EINVAL, "n_rhs must be in [1, max_rhs of sdg_assemble]");
     require(n_pts >= 0 && (n_pts == 0 || (v_state && pts && out)), SDG_EINVAL, "null argument");
     if (n_pts == 0) return;
-    const HostSetup& hs = c.hs;
-    std::vector<int64_t> el(n_pts);
-    std::vector<double> phi(n_pts * hs.nphi);
-    for (int64_t q = 0; q < n_pts; ++q) {
-      el[q] = locate_point(hs, pts + q * hs.dim);
-      require(el[q] >= 0, SDG_EINVAL, "sample point outside the mesh");
-      eval_velocity_basis(hs, el[q], pts + q * hs.dim, &phi[q * hs.nphi], 1e-12);
-    }
     SDG_HIP(hipSetDevice(c.device));
     hipStream_t s = (hipStream_t)stream;
-    DevBuf<int64_t> de;
-    DevBuf<double> dp;
-    de.alloc(n_pts);
-    dp.alloc(phi.size());
-    SDG_HIP(hipMemcpy(de.p, el.data(), el.size() * sizeof(int64_t), hipMemcpyHostToDevice));
-    SDG_HIP(hipMemcpy(dp.p, phi.data(), phi.size() * sizeof(double), hipMemcpyHostToDevice));
-    launch_sample(n_pts, hs.nphi, hs.dim, de.p, dp.p, v_state, out, s);
+    locate_points(c, n_pts, pts);
+    const HostSetup& hs = c.hs;
+    for (int r = 0; r < n_rhs; ++r)
+      launch_sample(n_pts, hs.nphi, hs.dim, c.d_samp_elem.p, c.d_samp_phi.p, v_state + (int64_t)r * c.n_state,
+                    out + (int64_t)r * n_pts * hs.dim, s);
+    SDG_HIP(hipGetLastError());
     SDG_HIP(hipStreamSynchronize(s));
   });
 }

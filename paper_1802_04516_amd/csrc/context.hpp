@@ -3,6 +3,8 @@
 // assemble time).
 #pragma once
 
+#include <functional>
+
 #include "sdg_internal.hpp"
 
 namespace sdg {
@@ -25,6 +27,18 @@ struct DevScalars {
   double dots[kRedSlots];
 };
 
+// Scalars of one system of a multi-system Krylov solve.
+struct SysScalars {
+  double H[(kMaxRestart + 1) * kMaxRestart];  // column-major, ld = kMaxRestart+1
+  double cs[kMaxRestart], sn[kMaxRestart];
+  double g[kMaxRestart + 1];
+  double h1[kMaxRestart + 1], h2[kMaxRestart + 1];
+  double y[kMaxRestart];
+  double dot, norm, inv_norm, resid, tol_abs, bnorm, rnorm;
+  int32_t active, k;
+};
+constexpr int kMaxSystems = 1024;
+
 template <class T>
 struct DevBuf {
   T* p = nullptr;
@@ -41,6 +55,27 @@ struct DevBuf {
     n = 0;
   }
   ~DevBuf() { free(); }
+};
+
+// Independent systems as contiguous segments [off[s], off[s+1]) of one
+// vector, with the reduction-block partition used by the segmented kernels.
+struct MultiSys {
+  int S = 0;
+  int64_t n_total = 0;
+  int n_blocks = 0;
+  std::vector<int64_t> off;
+  DevBuf<int> d_blk_seg, d_seg_blk0;
+  DevBuf<int64_t> d_blk_beg, d_blk_end;
+  DevBuf<SysScalars> d_ss;
+  DevBuf<double> d_partials;
+  DevBuf<int> d_nactive;
+  int* h_pinned = nullptr;
+  void build(const std::vector<int64_t>& offsets);
+  void read_scalars(std::vector<SysScalars>& out, hipStream_t s) const;
+  MultiSys() = default;
+  MultiSys(const MultiSys&) = delete;
+  MultiSys& operator=(const MultiSys&) = delete;
+  ~MultiSys();
 };
 
 struct Ctx {
@@ -101,13 +136,26 @@ struct Ctx {
   DevBuf<int32_t> d_elem_face;
   DevBuf<int64_t> d_src_elem;
 
+  // several independent systems: batched columns or a mesh batch
+  int n_mesh = 1;
+  std::vector<int64_t> mesh_vert_off, mesh_elem_off;  // n_mesh + 1 each
+  MultiSys msys;
+  int msys_key = 0;        // columns the partition was built for (-1: mesh batch)
+  int64_t z_col = 0;       // face-slot workspace per column
+
+  // located sampling points of the last call
+  std::vector<double> samp_pts;
+  DevBuf<int64_t> d_samp_elem;
+  DevBuf<double> d_samp_phi;
+
   ~Ctx() {
     if (h_pinned) (void)hipHostFree(h_pinned);
   }
 };
 
 // operator application on slab vectors (FP64 in / out)
-void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s);
+// ncols > 1: ncols independent columns stored one after another (stride n_slab)
+void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s, int ncols = 1);
 
 // vector kernels
 void vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
@@ -130,19 +178,29 @@ struct KrylovCfg {
 };
 SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s);
 SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s);
+// Largest ||r_s|| / ||b_s|| over the systems of m (bnorm_max: largest ||b_s||).
+double multi_rel_residual(MultiSys& m, const double* b, const double* r, hipStream_t s, double* bnorm_max);
+MultiSys& systems(Ctx& c, int ncols);
+void locate_points(Ctx& c, int64_t n_pts, const double* pts);
+// Restarted GMRES on the independent systems of m (right preconditioning
+// with *pre when given); V holds (restart+1) basis vectors of m.n_total.
+SolveResult solve_gmres_multi(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
+                              const std::function<void(const double*, double*)>& op,
+                              const std::function<void(const double*, double*)>* pre, double* V, double* r,
+                              double* w, double* t);
 // y = P^-1 x for the chosen preconditioner (transpose: P^-T)
-void apply_precond(Ctx& c, int kind, const double* x, double* y, bool transpose, hipStream_t s);
+void apply_precond(Ctx& c, int kind, const double* x, double* y, bool transpose, hipStream_t s, int ncols = 1);
 void launch_block_apply(int64_t n_elem, int nv, const float* P, const double* x, double* y, bool transpose,
-                        hipStream_t s);
+                        hipStream_t s, int ncols = 1, int64_t cstride = 0);
 void launch_block_apply_fact(int64_t n_elem, int ng, int ns, const float* Q, const float* B, const double* x,
-                             double* y, bool transpose, hipStream_t s);
+                             double* y, bool transpose, hipStream_t s, int ncols = 1, int64_t cstride = 0);
 
 // step pieces
 void launch_broadcast_time(int64_t n_elem, int ng, int nvs, const double* state, double* slab,
                            hipStream_t s);
 void launch_end_of_slab(int64_t n_elem, int ng, int nvs, const double* w, const double* slab,
                         double* state, hipStream_t s);
-void launch_add_sources(Ctx& c, double* b, const double* amp_dev, hipStream_t s);
+void launch_add_sources(Ctx& c, double* b, const double* amp_dev, hipStream_t s, int ncols = 1);
 void launch_energy(Ctx& c, const double* v, const double* sig, double* out_dev, hipStream_t s);
 void launch_grad_rho(int64_t n_elem, int ng, int dim, int nphi, const RhoCoefs& tc, const double* Mref,
                      const double* detJ, const double* L, const double* X, const double* vold, double* g,

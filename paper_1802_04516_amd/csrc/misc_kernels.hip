@@ -50,6 +50,22 @@ __global__ void k_sources(int64_t n_src, int ng, int dim, int nphi, double dt, c
   }
 }
 
+// Batched right-hand sides: column r (grid y) carries source r % n_src only.
+__global__ void k_sources_cols(int64_t n_src, int ng, int dim, int nphi, double dt, const double* __restrict__ wq,
+                               const int64_t* __restrict__ elem, const double* __restrict__ phi,
+                               const double* __restrict__ dir, const double* __restrict__ amp, double* __restrict__ b,
+                               int64_t cstride) {
+  const int per = ng * dim * nphi;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= per) return;
+  const int64_t r = blockIdx.y;
+  const int64_t s = r % n_src;
+  const int k = t % nphi, c = (t / nphi) % dim, a = t / (nphi * dim);
+  const int64_t e = elem[s];
+  b[r * cstride + ((e * ng + a) * dim + c) * nphi + k] +=
+      dt * wq[a] * amp[s * ng + a] * dir[s * dim + c] * phi[s * nphi + k];
+}
+
 __device__ inline double wsum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   return v;
@@ -224,10 +240,17 @@ void launch_end_of_slab(int64_t n_elem, int ng, int nvs, const double* w, const 
   SDG_HIP(hipGetLastError());
 }
 
-void launch_add_sources(Ctx& c, double* b, const double* amp_dev, hipStream_t s) {
+void launch_add_sources(Ctx& c, double* b, const double* amp_dev, hipStream_t s, int ncols) {
   if (c.n_src == 0) return;
   const HostSetup& hs = c.hs;
   const int per = hs.ng * hs.dim * hs.nphi;
+  if (ncols > 1) {
+    k_sources_cols<<<dim3((per + kT - 1) / kT, ncols), kT, 0, s>>>(c.n_src, hs.ng, hs.dim, hs.nphi, hs.dt, c.d_tw.p,
+                                                                   c.d_src_elem.p, c.d_src_phi.p, c.d_src_dir.p,
+                                                                   amp_dev, b, c.n_slab);
+    SDG_HIP(hipGetLastError());
+    return;
+  }
   // quadrature weights of the slab's time nodes (Crank-Nicolson: midpoint, weight 1)
   k_sources<<<(per + kT - 1) / kT, kT, 0, s>>>(c.n_src, hs.ng, hs.dim, hs.nphi, hs.dt, c.d_tw.p,
                                               c.d_src_elem.p, c.d_src_phi.p, c.d_src_dir.p, amp_dev, b);

@@ -1,0 +1,495 @@
+// Restarted GMRES for several independent systems sharing every launch.
+//
+// The systems are contiguous segments [off_s, off_{s+1}) of one long vector:
+// the columns of a batched solve (several right-hand sides on one mesh,
+// stored column after column) or the meshes of a ragged batch (one
+// concatenated mesh whose element ranges are the meshes).  Each system has
+// its own Arnoldi process, Hessenberg matrix, Givens rotations, tolerance and
+// convergence flag; the operator and preconditioner are applied to all
+// segments in one launch, and every reduction is segmented: each reduction
+// block covers rows of a single system, and the per-system sums are formed
+// in a fixed order by a finalize kernel, so results are deterministic and a
+// system's iterates do not depend on the others.
+//
+// A system whose residual estimate reaches its tolerance is switched off on
+// the device (its Gram-Schmidt work is skipped); its correction is applied at
+// the end of the cycle with the Arnoldi steps it took.  The host polls the
+// device count of active systems every check_every iterations.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <functional>
+
+#include "context.hpp"
+
+namespace sdg {
+
+namespace {
+
+constexpr int kT = 256;
+
+__device__ inline double wsum64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+template <int NJ>
+__device__ inline void block_partials_m(const double (&acc)[NJ], double* sh, double* partials, int nblocks) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    const double v = wsum64(acc[i]);
+    if (lane == 0) sh[wid * NJ + i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NJ) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[w * NJ + threadIdx.x];
+    partials[(size_t)threadIdx.x * nblocks + blockIdx.x] = s;
+  }
+}
+
+struct BlockMap {
+  const int* seg;        // block -> system
+  const int64_t* beg;    // first row of the block
+  const int64_t* end;    // one past the last row
+  int nblocks;
+};
+
+// h1[s][i] partials: V_i . w over the block's rows (i < NJ); all = 1 also
+// covers inactive systems
+template <int NJ>
+__global__ __launch_bounds__(kT) void km_multidot(BlockMap bm, int64_t ld, const double* __restrict__ V,
+                                                  const double* __restrict__ w, const SysScalars* ss,
+                                                  double* partials, int all) {
+  __shared__ double sh[4 * NJ];
+  const int sys = bm.seg[blockIdx.x];
+  if (!all && !ss[sys].active) return;
+  double acc[NJ];
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) acc[i] = 0.0;
+  const int64_t e = bm.end[blockIdx.x];
+  for (int64_t t = bm.beg[blockIdx.x] + threadIdx.x; t < e; t += kT) {
+    const double wt = w[t];
+    double vi[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * ld + t];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) acc[i] += vi[i] * wt;
+  }
+  block_partials_m<NJ>(acc, sh, partials, bm.nblocks);
+}
+
+// w -= V h1[s]; partials of h2 = V . w
+template <int NJ>
+__global__ __launch_bounds__(kT) void km_cgs_pass(BlockMap bm, int64_t ld, const double* __restrict__ V,
+                                                  double* __restrict__ w, const SysScalars* ss, double* partials) {
+  __shared__ double sh[4 * NJ];
+  const int sys = bm.seg[blockIdx.x];
+  if (!ss[sys].active) return;
+  double h[NJ], acc[NJ];
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) { h[i] = ss[sys].h1[i]; acc[i] = 0.0; }
+  const int64_t e = bm.end[blockIdx.x];
+  for (int64_t t = bm.beg[blockIdx.x] + threadIdx.x; t < e; t += kT) {
+    double vi[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * ld + t];
+    double wt = w[t];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) wt -= h[i] * vi[i];
+    w[t] = wt;
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) acc[i] += vi[i] * wt;
+  }
+  block_partials_m<NJ>(acc, sh, partials, bm.nblocks);
+}
+
+// w -= V h2[s]; partials of w . w
+template <int NJ>
+__global__ __launch_bounds__(kT) void km_cgs_final(BlockMap bm, int64_t ld, const double* __restrict__ V,
+                                                   double* __restrict__ w, const SysScalars* ss, double* partials) {
+  __shared__ double sh[4];
+  const int sys = bm.seg[blockIdx.x];
+  if (!ss[sys].active) return;
+  double h[NJ];
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) h[i] = ss[sys].h2[i];
+  double acc[1] = {0.0};
+  const int64_t e = bm.end[blockIdx.x];
+  for (int64_t t = bm.beg[blockIdx.x] + threadIdx.x; t < e; t += kT) {
+    double vi[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * ld + t];
+    double wt = w[t];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) wt -= h[i] * vi[i];
+    w[t] = wt;
+    acc[0] += wt * wt;
+  }
+  block_partials_m<1>(acc, sh, partials, bm.nblocks);
+}
+
+// x += sum_{i < k_s} y[s][i] V_i (y beyond k_s is zero)
+template <int NJ>
+__global__ __launch_bounds__(kT) void km_update(BlockMap bm, int64_t ld, const double* __restrict__ V,
+                                                double* __restrict__ x, const SysScalars* ss) {
+  const int sys = bm.seg[blockIdx.x];
+  if (ss[sys].k == 0) return;
+  double ys[NJ];
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) ys[i] = ss[sys].y[i];
+  const int64_t e = bm.end[blockIdx.x];
+  for (int64_t t = bm.beg[blockIdx.x] + threadIdx.x; t < e; t += kT) {
+    double vi[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * ld + t];
+    double acc = x[t];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) acc += ys[i] * vi[i];
+    x[t] = acc;
+  }
+}
+
+// v = w * inv_norm[s] on the rows of active systems
+__global__ __launch_bounds__(kT) void km_scale(BlockMap bm, const double* __restrict__ w, double* __restrict__ v,
+                                               const SysScalars* ss, int only_active) {
+  const int sys = bm.seg[blockIdx.x];
+  if (only_active && !ss[sys].active) return;
+  const double sc = ss[sys].inv_norm;
+  const int64_t e = bm.end[blockIdx.x];
+  for (int64_t t = bm.beg[blockIdx.x] + threadIdx.x; t < e; t += kT) v[t] = w[t] * sc;
+}
+
+// x = 0 on the rows of systems with a zero right-hand side
+__global__ __launch_bounds__(kT) void km_zero_null(BlockMap bm, double* __restrict__ x, const SysScalars* ss) {
+  const int sys = bm.seg[blockIdx.x];
+  if (ss[sys].bnorm != 0.0) return;
+  const int64_t e = bm.end[blockIdx.x];
+  for (int64_t t = bm.beg[blockIdx.x] + threadIdx.x; t < e; t += kT) x[t] = 0.0;
+}
+
+// Per-system sums of partials[i][blocks of s] for i < nslots; one wavefront
+// per (system, slot).  dst selects the field written.
+enum Dst { kH1 = 0, kH2 = 1, kDot = 2 };
+__global__ void km_finalize(const double* partials, int nblocks, const int* seg_blk0, int S, int nslots,
+                            SysScalars* ss, int dst, int all) {
+  const int lane = threadIdx.x & 63;
+  const int wv = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (wv >= S * nslots) return;
+  const int s = wv / nslots, i = wv % nslots;
+  if (!all && !ss[s].active) return;
+  const int b0 = seg_blk0[s], b1 = seg_blk0[s + 1];
+  double v = 0.0;
+  for (int b = b0 + lane; b < b1; b += 64) v += partials[(size_t)i * nblocks + b];
+  v = wsum64(v);
+  if (lane == 0) {
+    if (dst == kH1) ss[s].h1[i] = v;
+    else if (dst == kH2) ss[s].h2[i] = v;
+    else ss[s].dot = v;
+  }
+}
+
+// Block-wide count of flags (one block of up to 1024 threads).
+__device__ inline int block_count(int flag, int* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  int v = flag;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  int r = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nw; ++i) r += sh[i];
+  return r;
+}
+
+// Norm of w per system, Hessenberg column j, Givens rotations, residual
+// estimate, convergence flag; one thread per system.
+__global__ void km_arnoldi_fin(const double* partials, int nblocks, const int* seg_blk0, int S, int j,
+                               SysScalars* ss, int* nactive) {
+  __shared__ int sh[16];
+  const int s = threadIdx.x;
+  int act = 0;
+  if (s < S && ss[s].active) {
+    SysScalars& q = ss[s];
+    double tot = 0.0;
+    for (int b = seg_blk0[s]; b < seg_blk0[s + 1]; ++b) tot += partials[b];
+    const int ld = kMaxRestart + 1;
+    double* Hc = q.H + (size_t)j * ld;
+    for (int i = 0; i <= j; ++i) Hc[i] = q.h1[i] + q.h2[i];
+    const double nrm = sqrt(tot);
+    Hc[j + 1] = nrm;
+    q.norm = nrm;
+    q.inv_norm = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int i = 0; i < j; ++i) {
+      const double a = Hc[i], b = Hc[i + 1];
+      Hc[i] = q.cs[i] * a + q.sn[i] * b;
+      Hc[i + 1] = -q.sn[i] * a + q.cs[i] * b;
+    }
+    const double a = Hc[j], b = Hc[j + 1];
+    const double rad = hypot(a, b);
+    const double c = rad > 0.0 ? a / rad : 1.0, sn = rad > 0.0 ? b / rad : 0.0;
+    q.cs[j] = c;
+    q.sn[j] = sn;
+    Hc[j] = rad;
+    Hc[j + 1] = 0.0;
+    const double gj = q.g[j];
+    q.g[j] = c * gj;
+    q.g[j + 1] = -sn * gj;
+    q.resid = fabs(q.g[j + 1]);
+    q.k = j + 1;
+    if (q.resid <= q.tol_abs || nrm == 0.0) q.active = 0;
+    act = q.active;
+  }
+  const int n = block_count(act, sh);
+  if (threadIdx.x == 0) *nactive = n;
+}
+
+// Start of a cycle from the per-system r.r in ss.dot.
+__global__ void km_cycle_start(int S, SysScalars* ss, int* nactive) {
+  __shared__ int sh[16];
+  const int s = threadIdx.x;
+  int act = 0;
+  if (s < S) {
+    SysScalars& q = ss[s];
+    const double beta = sqrt(q.dot);
+    q.rnorm = beta;
+    for (int i = 0; i <= kMaxRestart; ++i) q.g[i] = 0.0;
+    for (int i = 0; i < kMaxRestart; ++i) q.y[i] = 0.0;
+    q.g[0] = beta;
+    q.norm = beta;
+    q.inv_norm = beta > 0.0 ? 1.0 / beta : 0.0;
+    q.resid = beta;
+    q.k = 0;
+    q.active = (beta > q.tol_abs) ? 1 : 0;
+    act = q.active;
+  }
+  const int n = block_count(act, sh);
+  if (threadIdx.x == 0) *nactive = n;
+}
+
+// bnorm and tolerance per system from ss.dot = b.b
+__global__ void km_set_tol(int S, SysScalars* ss, double rtol) {
+  const int s = threadIdx.x;
+  if (s < S) {
+    ss[s].bnorm = sqrt(ss[s].dot);
+    ss[s].tol_abs = rtol * ss[s].bnorm;
+    ss[s].active = 1;
+    ss[s].k = 0;
+  }
+}
+
+// Back substitution R y = g per system with its k.
+__global__ void km_trisolve(int S, SysScalars* ss) {
+  const int s = threadIdx.x;
+  if (s >= S) return;
+  SysScalars& q = ss[s];
+  const int ld = kMaxRestart + 1;
+  for (int i = 0; i < kMaxRestart; ++i) q.y[i] = 0.0;
+  for (int i = q.k - 1; i >= 0; --i) {
+    double sum = q.g[i];
+    for (int l = i + 1; l < q.k; ++l) sum -= q.H[(size_t)l * ld + i] * q.y[l];
+    const double d = q.H[(size_t)i * ld + i];
+    q.y[i] = d != 0.0 ? sum / d : 0.0;
+  }
+}
+
+#define SDG_MNJ_CASES(X)                                                                                   \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
+  X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+
+enum class Op { Multidot, Pass, Final, Update };
+
+void launch_m(Op op, int nj, const BlockMap& bm, hipStream_t s, int64_t ld, const double* V, double* w,
+              SysScalars* ss, double* partials) {
+  const unsigned g = (unsigned)bm.nblocks;
+  switch (nj) {
+#define SDG_M_CASE(N)                                                                          \
+  case N:                                                                                      \
+    if (op == Op::Multidot) km_multidot<N><<<g, kT, 0, s>>>(bm, ld, V, w, ss, partials, 0);     \
+    else if (op == Op::Pass) km_cgs_pass<N><<<g, kT, 0, s>>>(bm, ld, V, w, ss, partials);       \
+    else if (op == Op::Final) km_cgs_final<N><<<g, kT, 0, s>>>(bm, ld, V, w, ss, partials);     \
+    else km_update<N><<<g, kT, 0, s>>>(bm, ld, V, w, ss);                                       \
+    break;
+    SDG_MNJ_CASES(SDG_M_CASE)
+#undef SDG_M_CASE
+    default:
+      throw Error(SDG_EINVAL, "Gram-Schmidt basis size out of range");
+  }
+  SDG_HIP(hipGetLastError());
+}
+
+BlockMap map_of(const MultiSys& m) {
+  return BlockMap{m.d_blk_seg.p, m.d_blk_beg.p, m.d_blk_end.p, m.n_blocks};
+}
+
+void finalize(const MultiSys& m, int nslots, int dst, int all, hipStream_t s) {
+  const int waves = m.S * nslots;
+  const unsigned blocks = (unsigned)((waves * 64 + kT - 1) / kT);
+  km_finalize<<<blocks, kT, 0, s>>>(m.d_partials.p, m.n_blocks, m.d_seg_blk0.p, m.S, nslots, m.d_ss.p, dst, all);
+  SDG_HIP(hipGetLastError());
+}
+
+// per-system x . x into ss.dot (all systems)
+void seg_norm2(const MultiSys& m, const double* x, hipStream_t s) {
+  km_multidot<1><<<(unsigned)m.n_blocks, kT, 0, s>>>(map_of(m), m.n_total, x, x, m.d_ss.p, m.d_partials.p, 1);
+  SDG_HIP(hipGetLastError());
+  finalize(m, 1, kDot, 1, s);
+}
+
+unsigned sys_threads(int S) { return (unsigned)std::max(64, ((S + 63) / 64) * 64); }
+
+int read_int(int* dev, int* pinned, hipStream_t s) {
+  SDG_HIP(hipMemcpyAsync(pinned, dev, sizeof(int), hipMemcpyDeviceToHost, s));
+  SDG_HIP(hipStreamSynchronize(s));
+  return *pinned;
+}
+
+}  // namespace
+
+void MultiSys::build(const std::vector<int64_t>& offsets) {
+  require(offsets.size() >= 2, SDG_EINVAL, "at least one system");
+  S = (int)offsets.size() - 1;
+  require(S <= kMaxSystems, SDG_EUNSUPPORTED, "too many independent systems in one solve");
+  off = offsets;
+  n_total = off[S];
+  const int64_t rpb = std::max<int64_t>(4 * kT, (n_total + 2047) / 2048);
+  std::vector<int> seg, blk0(S + 1);
+  std::vector<int64_t> beg, end;
+  for (int q = 0; q < S; ++q) {
+    blk0[q] = (int)seg.size();
+    const int64_t len = off[q + 1] - off[q];
+    require(len >= 0, SDG_EINVAL, "system offsets must be non-decreasing");
+    const int64_t nb = std::max<int64_t>(1, (len + rpb - 1) / rpb);
+    for (int64_t b = 0; b < nb; ++b) {
+      seg.push_back(q);
+      beg.push_back(off[q] + std::min(len, b * rpb));
+      end.push_back(off[q] + std::min(len, (b + 1) * rpb));
+    }
+  }
+  blk0[S] = (int)seg.size();
+  n_blocks = (int)seg.size();
+  d_blk_seg.alloc(seg.size());
+  SDG_HIP(hipMemcpy(d_blk_seg.p, seg.data(), seg.size() * sizeof(int), hipMemcpyHostToDevice));
+  d_seg_blk0.alloc(blk0.size());
+  SDG_HIP(hipMemcpy(d_seg_blk0.p, blk0.data(), blk0.size() * sizeof(int), hipMemcpyHostToDevice));
+  d_blk_beg.alloc(beg.size());
+  SDG_HIP(hipMemcpy(d_blk_beg.p, beg.data(), beg.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  d_blk_end.alloc(end.size());
+  SDG_HIP(hipMemcpy(d_blk_end.p, end.data(), end.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  d_ss.alloc(S);
+  SDG_HIP(hipMemset(d_ss.p, 0, S * sizeof(SysScalars)));
+  d_partials.alloc((size_t)(kMaxRestart + 1) * n_blocks);
+  d_nactive.alloc(1);
+  if (!h_pinned) SDG_HIP(hipHostMalloc((void**)&h_pinned, 16 * sizeof(int), hipHostMallocDefault));
+}
+
+MultiSys::~MultiSys() {
+  if (h_pinned) (void)hipHostFree(h_pinned);
+}
+
+void MultiSys::read_scalars(std::vector<SysScalars>& out, hipStream_t s) const {
+  out.resize(S);
+  SDG_HIP(hipMemcpyAsync(out.data(), d_ss.p, S * sizeof(SysScalars), hipMemcpyDeviceToHost, s));
+  SDG_HIP(hipStreamSynchronize(s));
+}
+
+double multi_rel_residual(MultiSys& m, const double* b, const double* r, hipStream_t s, double* bnorm_max) {
+  std::vector<SysScalars> h;
+  seg_norm2(m, b, s);
+  m.read_scalars(h, s);
+  std::vector<double> bn(m.S);
+  for (int q = 0; q < m.S; ++q) bn[q] = std::sqrt(h[q].dot);
+  seg_norm2(m, r, s);
+  m.read_scalars(h, s);
+  double worst = 0.0, bmax = 0.0;
+  for (int q = 0; q < m.S; ++q) {
+    const double rn = std::sqrt(h[q].dot);
+    worst = std::max(worst, bn[q] > 0.0 ? rn / bn[q] : rn);
+    bmax = std::max(bmax, bn[q]);
+  }
+  if (bnorm_max) *bnorm_max = bmax;
+  return worst;
+}
+
+SolveResult solve_gmres_multi(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
+                              const std::function<void(const double*, double*)>& op,
+                              const std::function<void(const double*, double*)>* pre, double* V, double* r,
+                              double* w, double* t) {
+  SolveResult res;
+  const int64_t n = m.n_total;
+  const BlockMap bm = map_of(m);
+  SysScalars* ss = m.d_ss.p;
+  const unsigned st = sys_threads(m.S);
+  const int mres = k.restart;
+  const int check_every = std::max(1, k.check_every);
+  seg_norm2(m, b, s);
+  km_set_tol<<<1, st, 0, s>>>(m.S, ss, k.rtol);
+  km_zero_null<<<(unsigned)m.n_blocks, kT, 0, s>>>(bm, x, ss);
+  SDG_HIP(hipGetLastError());
+  int total = 0;
+  for (;;) {
+    op(x, r);
+    ++res.matvecs;
+    vec_axpby(n, 1.0, b, -1.0, r, s);
+    seg_norm2(m, r, s);
+    km_cycle_start<<<1, st, 0, s>>>(m.S, ss, m.d_nactive.p);
+    SDG_HIP(hipGetLastError());
+    const int nact = read_int(m.d_nactive.p, m.h_pinned, s);
+    if (nact == 0) { res.converged = true; break; }
+    if (total >= k.max_iter) break;
+    km_scale<<<(unsigned)m.n_blocks, kT, 0, s>>>(bm, r, V, ss, 1);
+    SDG_HIP(hipGetLastError());
+    int kk = 0;
+    for (int j = 0; j < mres && total < k.max_iter; ++j) {
+      double* vj = V + (size_t)j * n;
+      if (pre) {
+        (*pre)(vj, t);
+        op(t, w);
+      } else {
+        op(vj, w);
+      }
+      ++res.matvecs;
+      launch_m(Op::Multidot, j + 1, bm, s, n, V, w, ss, m.d_partials.p);
+      finalize(m, j + 1, kH1, 0, s);
+      launch_m(Op::Pass, j + 1, bm, s, n, V, w, ss, m.d_partials.p);
+      finalize(m, j + 1, kH2, 0, s);
+      launch_m(Op::Final, j + 1, bm, s, n, V, w, ss, m.d_partials.p);
+      km_arnoldi_fin<<<1, st, 0, s>>>(m.d_partials.p, m.n_blocks, m.d_seg_blk0.p, m.S, j, ss, m.d_nactive.p);
+      SDG_HIP(hipGetLastError());
+      km_scale<<<(unsigned)m.n_blocks, kT, 0, s>>>(bm, w, V + (size_t)(j + 1) * n, ss, 1);
+      SDG_HIP(hipGetLastError());
+      ++total;
+      ++res.iters;
+      kk = j + 1;
+      if ((j + 1) % check_every == 0 || j + 1 == mres) {
+        if (read_int(m.d_nactive.p, m.h_pinned, s) == 0) break;
+      }
+    }
+    km_trisolve<<<1, st, 0, s>>>(m.S, ss);
+    SDG_HIP(hipGetLastError());
+    if (pre) {
+      vec_fill(n, 0.0, t, s);
+      launch_m(Op::Update, kk, bm, s, n, V, t, ss, nullptr);
+      (*pre)(t, w);
+      vec_axpby(n, 1.0, w, 1.0, x, s);
+    } else {
+      launch_m(Op::Update, kk, bm, s, n, V, x, ss, nullptr);
+    }
+  }
+  std::vector<SysScalars> h;
+  m.read_scalars(h, s);
+  double worst = 0.0, bmax = 0.0;
+  for (const SysScalars& q : h) {
+    if (q.bnorm > 0.0) worst = std::max(worst, q.rnorm / q.bnorm);
+    bmax = std::max(bmax, q.bnorm);
+  }
+  res.rel_res = worst;
+  res.bnorm = bmax;
+  require(std::isfinite(worst), SDG_ENONFINITE, "non-finite residual");
+  return res;
+}
+
+}  // namespace sdg

@@ -80,7 +80,8 @@ void build_host_setup(HostSetup& hs, int dim, int64_t n_vert, const double* xyz,
 // Nodal basis values of element e at physical point x (nphi values); returns
 // false if x is not in the closed element (tolerance tol in barycentric units).
 bool eval_velocity_basis(const HostSetup& hs, int64_t e, const double* x, double* phi, double tol);
-int64_t locate_point(const HostSetup& hs, const double* x);
+// First element (in [e_begin, e_end), default all) containing x, or -1.
+int64_t locate_point(const HostSetup& hs, const double* x, int64_t e_begin = 0, int64_t e_end = -1);
 // Canonical dual basis functions of face j at n points x (n*dim) -> out (n*npsi).
 void eval_dual_canonical(const HostSetup& hs, const int64_t* elem, int64_t j, int64_t n,
                          const double* x, double* out);
@@ -124,6 +125,11 @@ struct OpArgs {
   double y_scale;          // element kernel: y = y_scale * (...) (reserved, 1.0)
   int variant;             // operator face kernel: 0 = LDS flat loops, 1 = register-tiled
                            // with the most faces per block, 2 = register-tiled, half of it
+  // Several independent columns (right-hand sides) of the same mesh: the
+  // launch grid's y index is the column and every per-column array is offset
+  // by column * its stride (0 = shared by all columns).
+  int n_cols;
+  int64_t cs_v, cs_y, cs_z, cs_sig_in, cs_s_out, cs_s_end, cs_y_add;
   Coefs c;
 };
 

@@ -745,8 +745,9 @@ bool eval_velocity_basis(const HostSetup& hs, int64_t e, const double* x, double
   return true;
 }
 
-int64_t locate_point(const HostSetup& hs, const double* x) {
-  for (int64_t e = 0; e < hs.n_elem; ++e)
+int64_t locate_point(const HostSetup& hs, const double* x, int64_t e_begin, int64_t e_end) {
+  if (e_end < 0) e_end = hs.n_elem;
+  for (int64_t e = std::max<int64_t>(0, e_begin); e < std::min<int64_t>(e_end, hs.n_elem); ++e)
     if (eval_velocity_basis(hs, e, x, nullptr, 1e-12)) return e;
   return -1;
 }

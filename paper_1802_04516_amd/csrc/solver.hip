@@ -149,8 +149,11 @@ __global__ void k_dot_beta_fin(const double* partials, int nblocks, DevScalars* 
 // y = P x, 4 consecutive rows per thread with 16-byte loads (nv % 4 == 0);
 // one workgroup holds several elements' x in LDS.
 __global__ __launch_bounds__(256) void k_block_apply4(int64_t n_elem, int nv, const float* __restrict__ P,
-                                                      const double* __restrict__ x, double* __restrict__ y) {
+                                                      const double* __restrict__ x, double* __restrict__ y,
+                                                      int64_t cstride) {
   extern __shared__ double sx[];
+  x += blockIdx.y * cstride;
+  y += blockIdx.y * cstride;
   const int tpe = nv / 4;              // threads per element
   const int epb = blockDim.x / tpe;    // elements per workgroup pass
   const int le = threadIdx.x / tpe, r4 = threadIdx.x % tpe;
@@ -184,8 +187,10 @@ __global__ __launch_bounds__(256) void k_block_apply4(int64_t n_elem, int nv, co
 // y = P x for per-element dense blocks stored column-major in FP32
 // (P[e][col][row]); transpose applies P^T.
 __global__ void k_block_apply(int64_t n_elem, int nv, const float* __restrict__ P, const double* __restrict__ x,
-                              double* __restrict__ y, int transpose) {
+                              double* __restrict__ y, int transpose, int64_t cstride) {
   extern __shared__ double sx[];
+  x += blockIdx.y * cstride;
+  y += blockIdx.y * cstride;
   for (int64_t e = blockIdx.x; e < n_elem; e += gridDim.x) {
     for (int i = threadIdx.x; i < nv; i += blockDim.x) sx[i] = x[e * nv + i];
     __syncthreads();
@@ -208,8 +213,10 @@ __global__ void k_block_apply(int64_t n_elem, int nv, const float* __restrict__ 
 // per workgroup; x, u and w of an element are staged in LDS.
 __global__ __launch_bounds__(256) void k_block_apply_fact(int64_t n_elem, int ng, int ns, const float* __restrict__ Q,
                                                           const float* __restrict__ B, const double* __restrict__ x,
-                                                          double* __restrict__ y, int transpose) {
+                                                          double* __restrict__ y, int transpose, int64_t cstride) {
   extern __shared__ double sm[];
+  x += blockIdx.y * cstride;
+  y += blockIdx.y * cstride;
   const int nv = ng * ns;
   const int epb = blockDim.x / nv;
   const int le = threadIdx.x / nv, r = threadIdx.x % nv;
@@ -517,30 +524,31 @@ static double read_scalar_dot(Ctx& c, int64_t n, const double* r, hipStream_t s)
 }
 
 void launch_block_apply(int64_t n_elem, int nv, const float* P, const double* x, double* y, bool transpose,
-                        hipStream_t s) {
+                        hipStream_t s, int ncols, int64_t cstride) {
+  const unsigned gy = (unsigned)std::max(1, ncols);
   if (!transpose && nv % 4 == 0 && nv / 4 <= 256) {
     const int epb = 256 / (nv / 4);
     const int64_t groups = (n_elem + epb - 1) / epb;
     const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 65535));
-    k_block_apply4<<<g, 256, (size_t)epb * nv * sizeof(double), s>>>(n_elem, nv, P, x, y);
+    k_block_apply4<<<dim3(g, gy), 256, (size_t)epb * nv * sizeof(double), s>>>(n_elem, nv, P, x, y, cstride);
     check_launch();
     return;
   }
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_elem, 65535));
   const int t = nv <= 64 ? 64 : (nv <= 128 ? 128 : 256);
-  k_block_apply<<<g, t, nv * sizeof(double), s>>>(n_elem, nv, P, x, y, transpose ? 1 : 0);
+  k_block_apply<<<dim3(g, gy), t, nv * sizeof(double), s>>>(n_elem, nv, P, x, y, transpose ? 1 : 0, cstride);
   check_launch();
 }
 
 void launch_block_apply_fact(int64_t n_elem, int ng, int ns, const float* Q, const float* B, const double* x,
-                             double* y, bool transpose, hipStream_t s) {
+                             double* y, bool transpose, hipStream_t s, int ncols, int64_t cstride) {
   const int nv = ng * ns;
   require(nv <= 256, SDG_EUNSUPPORTED, "element block too large for the factored preconditioner kernel");
   const int epb = 256 / nv;
   const int64_t groups = (n_elem + epb - 1) / epb;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 65535));
-  k_block_apply_fact<<<g, epb * nv, (size_t)epb * 2 * nv * sizeof(double), s>>>(n_elem, ng, ns, Q, B, x, y,
-                                                                                transpose ? 1 : 0);
+  k_block_apply_fact<<<dim3(g, (unsigned)std::max(1, ncols)), epb * nv, (size_t)epb * 2 * nv * sizeof(double), s>>>(
+      n_elem, ng, ns, Q, B, x, y, transpose ? 1 : 0, cstride);
   check_launch();
 }
 

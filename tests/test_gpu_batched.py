@@ -1,0 +1,205 @@
+"""Batched right-hand sides and mesh batches: several independent systems
+solved in shared launches, each held to the single-system oracle bar.
+
+Batched columns: column r of a batched step carries source r % n_src and its
+own old state; each column is compared with the oracle's step of that
+column alone (<= 1e-11 relative L2, Krylov rtol 1e-13), and the batched
+operator apply with the single-column apply (bit for bit: the same kernels
+on offset pointers) and with the oracle's Schur complement.
+
+Mesh batches: ragged meshes concatenated by the library, one Krylov process
+per mesh; each mesh's part of the state is compared with the oracle on that
+mesh alone.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_cases import material, rel
+from oracle.assemble import Blocks
+from oracle.mesh import Topology
+from oracle.slab import Slab
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _canon(B, s_raw):
+    return np.stack([B.to_canonical(j, s_raw[j]) for j in range(B.topo.n_face)])
+
+
+def _opts(rtol=1e-13, precision=None, precond=None, max_iter=3000):
+    import paper_1802_04516_amd as sdg
+    return sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, precision or sdg.SDG_PREC_F64, rtol, max_iter, 30, 5, 20, 1e-5,
+                         sdg.SDG_PRECOND_MASS if precond is None else precond)
+
+
+def _amps(slab, scheme, dt, n, n_src, scale):
+    t = np.array([(n + 0.5) * dt]) if scheme == "cn" else n * dt + slab.tb.tau * dt
+    return np.stack([scale[s] * synth.ricker(t, 10.0, 0.02) for s in range(n_src)])
+
+
+BATCH_CASES = {
+    # name: (mesh, p, p_gamma, scheme, dt, material, columns, preconditioner)
+    "stdg_p3pg3": (lambda: synth.split_square(6, jitter=0.2, seed=2001), 3, 3, "stdg", 2.5e-3, "layered", 5, "block"),
+    "stdg_p2pg1": (lambda: synth.split_square(5, jitter=0.1, seed=9), 2, 1, "stdg", 0.01, "lognormal", 3, "mass"),
+    "cn_p2": (lambda: synth.split_square(5, periodic=True, jitter=0.1, seed=4), 2, 0, "cn", 0.01, "lognormal", 4,
+              "mass"),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(BATCH_CASES))
+def bcase(request):
+    import paper_1802_04516_amd as sdg
+    mk, p, pg, scheme, dt, matkind, R, pc = BATCH_CASES[request.param]
+    mesh = mk()
+    lam, mu, rho = material(matkind, mesh)
+    ctx = sdg.Context(0)
+    sizes = ctx.setup(mesh.xyz, mesh.elem, mesh.period, p, pg,
+                      sdg.SDG_SCHEME_CN if scheme == "cn" else sdg.SDG_SCHEME_STDG, dt, lam, mu, rho,
+                      sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND, max_rhs=R)
+    B = Blocks(Topology(mesh.xyz, mesh.elem, mesh.period), p, lam, mu, rho)
+    slab = Slab(B, pg, dt, scheme)
+    yield dict(name=request.param, mesh=mesh, ctx=ctx, sizes=sizes, B=B, slab=slab, scheme=scheme, dt=dt, R=R,
+               precond=sdg.SDG_PRECOND_BLOCK if pc == "block" else sdg.SDG_PRECOND_MASS)
+    ctx.close()
+
+
+def test_batched_apply_matches_columns_and_oracle(bcase):
+    import torch
+    import paper_1802_04516_amd as sdg
+    ctx, R, n = bcase["ctx"], bcase["R"], bcase["sizes"]["n_vel_slab"]
+    S = bcase["slab"].schur()
+    rng = np.random.default_rng(77)
+    V = rng.standard_normal((R, n))
+    for prec, tol in ((sdg.SDG_PREC_F64, 1e-12), (sdg.SDG_PREC_F32, 2e-6)):
+        vb, yb = _gpu(V), torch.empty(R * n, dtype=torch.float64, device="cuda")
+        ctx.apply(vb, yb, prec, n_rhs=R)
+        ys = torch.empty(n, dtype=torch.float64, device="cuda")
+        for r in range(R):
+            ctx.apply(_gpu(V[r]), ys, prec)
+            assert torch.equal(ys, yb[r * n:(r + 1) * n]), f"column {r} differs from the single apply"
+            assert rel(ys.cpu().numpy(), S @ V[r]) <= tol
+    yt = torch.empty(R * n, dtype=torch.float64, device="cuda")
+    ctx.apply_adjoint(_gpu(V), yt, n_rhs=R)
+    for r in range(R):
+        assert rel(yt[r * n:(r + 1) * n].cpu().numpy(), S.T @ V[r]) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32ir"])
+def test_batched_steps_match_oracle_per_column(bcase, precision):
+    import paper_1802_04516_amd as sdg
+    ctx, R, B, slab = bcase["ctx"], bcase["R"], bcase["B"], bcase["slab"]
+    ne, nf = B.topo.n_elem, B.topo.n_face
+    rng = np.random.default_rng(5 + R)
+    n_src = 2
+    pos = np.array([[0.31, 0.42], [0.67, 0.58]])
+    dirs = np.array([[0.0, 1.0], [0.6, 0.8]])
+    ctx.set_sources(pos, dirs)
+    scale = np.array([1.0, -0.7])
+    # column states: random for r < R-1, the last column starts at rest
+    v0 = [0.3 * rng.standard_normal((ne, 2, B.nphi)) for _ in range(R - 1)] + [np.zeros((ne, 2, B.nphi))]
+    s0 = [0.1 * rng.standard_normal((nf, 3, B.npsi)) for _ in range(R - 1)] + [np.zeros((nf, 3, B.npsi))]
+    vg = _gpu(np.stack(v0))
+    sg = _gpu(np.stack([_canon(B, s) for s in s0]))
+    prec = sdg.SDG_PREC_F64 if precision == "f64" else sdg.SDG_PREC_F32
+    vo, so = [v.copy() for v in v0], [s.copy() for s in s0]
+    for n in range(3):
+        amps = _amps(slab, bcase["scheme"], bcase["dt"], n, n_src, scale)
+        info = ctx.step(vg, sg, amps.ravel(), n_rhs=R, opts=_opts(precision=prec, precond=bcase["precond"]))
+        V = vg.cpu().numpy().reshape(R, -1)
+        Sg = sg.cpu().numpy().reshape(R, -1)
+        worst = 0.0
+        for r in range(R):
+            src = dict(pos=pos[r % n_src:r % n_src + 1], dir=dirs[r % n_src:r % n_src + 1],
+                       amp=amps[r % n_src:r % n_src + 1])
+            _, _, vo[r], so[r] = slab.step(vo[r], so[r], src)
+            worst = max(worst, rel(V[r], vo[r]), rel(Sg[r], _canon(B, so[r])))
+        print(f"{bcase['name']} {precision} step {n}: worst column err {worst:.2e} iters {info['iterations']} "
+              f"refinements {info['refinements']} rel res {info['rel_residual']:.2e}")
+        assert worst <= 1e-11
+
+
+def test_batched_energy_and_limits(bcase):
+    import torch
+    import paper_1802_04516_amd as sdg
+    ctx, R, B = bcase["ctx"], bcase["R"], bcase["B"]
+    rng = np.random.default_rng(3)
+    ne, nf = B.topo.n_elem, B.topo.n_face
+    v = rng.standard_normal((R, ne, 2, B.nphi))
+    s = rng.standard_normal((R, nf, 3, B.npsi))
+    e = ctx.energy(_gpu(v), _gpu(s), n_rhs=R)
+    for r in range(R):
+        e1 = ctx.energy(_gpu(v[r]), _gpu(s[r]))
+        assert e[r] == e1
+    n = bcase["sizes"]["n_vel_slab"]
+    L = sdg.lib()
+    x = torch.zeros((R + 1) * n, dtype=torch.float64, device="cuda")
+    y = torch.zeros_like(x)
+    rc = L.sdg_apply_velocity_operator(ctx.h, sdg._dev(x), sdg._dev(y), R + 1, sdg.SDG_PREC_F64, None)
+    assert rc == sdg.SDG_EINVAL
+
+
+MESH_BATCH = [
+    # ragged sizes: 18, 50, 32 triangles
+    (lambda: synth.split_square(3, jitter=0.1, seed=41), 0.02),
+    (lambda: synth.split_square(5, jitter=0.2, seed=42), 0.01),
+    (lambda: synth.split_square(4, seed=43), 0.0),
+]
+
+
+@pytest.mark.parametrize("scheme,p,pg,precision", [("stdg", 2, 2, "f64"), ("stdg", 3, 1, "f32ir"),
+                                                    ("cn", 2, 0, "f64")])
+def test_mesh_batch_step_matches_oracle_per_mesh(scheme, p, pg, precision):
+    import paper_1802_04516_amd as sdg
+    meshes = [mk() for mk, _ in MESH_BATCH]
+    mats = [synth.lognormal_material(m.n_elem, sigma=0.2, seed=100 + q) for q, m in enumerate(meshes)]
+    lam, mu, rho = (np.concatenate([mt[i] for mt in mats]) for i in range(3))
+    dt = 0.01
+    ctx = sdg.Context(0)
+    sizes = ctx.setup_batch([(m.xyz, m.elem) for m in meshes], p, pg,
+                            sdg.SDG_SCHEME_CN if scheme == "cn" else sdg.SDG_SCHEME_STDG, dt, lam, mu, rho,
+                            sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND)
+    slabs = [Slab(Blocks(Topology(m.xyz, m.elem, None), p, *mt), pg, dt, scheme) for m, mt in zip(meshes, mats)]
+    # faces of the concatenated mesh are contiguous per mesh, in each mesh's own order
+    left = ctx.face_table()[0]
+    eoff = ctx.mesh_elem_off
+    foff = np.searchsorted(left, eoff)
+    for q, S in enumerate(slabs):
+        assert foff[q + 1] - foff[q] == S.nf
+    pos = np.array([[0.37, 0.61], [0.52, 0.44], [0.7, 0.3]])
+    dirs = np.array([[0.0, 1.0], [1.0, 0.0], [0.6, 0.8]])
+    scale = np.array([1.0, 0.5, -0.8])
+    ctx.set_mesh_sources(pos, dirs, np.arange(3, dtype=np.int32))
+    rng = np.random.default_rng(8)
+    v0 = [0.2 * rng.standard_normal((m.n_elem, 2, S.nphi)) * (q != 2) for q, (m, S) in enumerate(zip(meshes, slabs))]
+    s0 = [np.zeros((S.nf, 3, S.npsi)) for S in slabs]
+    vg = _gpu(np.concatenate([v.ravel() for v in v0]))
+    sg = _gpu(np.concatenate([np.stack([S.B.to_canonical(j, s[j]) for j in range(S.nf)]).ravel()
+                              for S, s in zip(slabs, s0)]))
+    prec = sdg.SDG_PREC_F64 if precision == "f64" else sdg.SDG_PREC_F32
+    ng = pg + 1
+    vo, so = [v.copy() for v in v0], [s.copy() for s in s0]
+    nvs = 2 * slabs[0].nphi
+    nss = 3 * slabs[0].npsi
+    for n in range(3):
+        amps = _amps(slabs[0], scheme, dt, n, 3, scale)
+        info = ctx.step(vg, sg, amps.ravel(), opts=_opts(precision=prec, precond=sdg.SDG_PRECOND_BLOCK))
+        V = vg.cpu().numpy()
+        Sg = sg.cpu().numpy()
+        worst = 0.0
+        for q, S in enumerate(slabs):
+            src = dict(pos=pos[q:q + 1], dir=dirs[q:q + 1], amp=amps[q:q + 1])
+            _, _, vo[q], so[q] = S.step(vo[q], so[q], src)
+            vq = V[eoff[q] * nvs:eoff[q + 1] * nvs]
+            sq = Sg[foff[q] * nss:foff[q + 1] * nss]
+            worst = max(worst, rel(vq, vo[q]), rel(sq, np.stack([S.B.to_canonical(j, so[q][j]) for j in range(S.nf)])))
+        print(f"mesh batch {scheme} p={p} pg={pg} {precision} step {n}: worst mesh err {worst:.2e} "
+              f"iters {info['iterations']} rel res {info['rel_residual']:.2e}")
+        assert worst <= 1e-11
+    assert sizes["n_elem"] == sum(m.n_elem for m in meshes)
+    ctx.close()
