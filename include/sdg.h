@@ -91,6 +91,7 @@ enum { SDG_SOLVER_AUTO = 0, SDG_SOLVER_CG = 1, SDG_SOLVER_GMRES = 2 };
  * BLOCK = element block-Jacobi on the full diagonal block of the velocity
  *         operator (eq. pre1), inverses stored at assemble time. */
 enum { SDG_PRECOND_NONE = 0, SDG_PRECOND_MASS = 1, SDG_PRECOND_BLOCK = 2 };
+enum { SDG_SOLVE_GRAPH = 1 };
 
 typedef struct sdg_ctx sdg_ctx;
 
@@ -125,7 +126,7 @@ typedef struct {
   int32_t max_refine;  /* outer refinement sweeps for SDG_PREC_F32                      */
   double inner_rtol;   /* relative tolerance of each inner FP32 solve                   */
   int32_t precond;     /* SDG_PRECOND_*: right preconditioner (GMRES) / PCG (CG)        */
-  int32_t pad;
+  int32_t flags;       /* SDG_SOLVE_GRAPH: record the step in HIP graphs (see below)    */
 } sdg_solve_opts;
 
 typedef struct {
@@ -247,7 +248,17 @@ int sdg_set_mesh_sources(sdg_ctx* ctx, int64_t n_src, const double* pos, const d
  * v_slab / sigma_slab (device, optional) receive the slab DOFs.
  * The initial guess is the old state copied to every time node.
  * On SDG_ENOCONV the states hold the step computed from the last iterate
- * and *info is filled. */
+ * and *info is filled.
+ * With opts->flags & SDG_SOLVE_GRAPH (FP64, GMRES) the step's launches are
+ * recorded once into HIP graphs (right-hand side + first restart cycle, one
+ * restart cycle, residual check, back-substitution) and replayed; the host
+ * only reads the device count of unconverged systems between replays, and
+ * every cycle runs its full restart length (converged systems are masked
+ * on the device).  The graphs are kept while the state, slab and amplitude
+ * pointers, n_rhs and the solver options stay the same; they are rebuilt
+ * otherwise and dropped by sdg_assemble, sdg_set_sources and
+ * sdg_set_operator_variant.  The call synchronises `stream` before the
+ * replays, which run on a stream of the context. */
 int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const double* amp,
                    int n_rhs, const sdg_solve_opts* opts, sdg_solve_info* info,
                    double* v_slab, double* sigma_slab, void* stream);

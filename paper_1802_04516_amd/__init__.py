@@ -27,6 +27,7 @@ SDG_PREC_F64, SDG_PREC_F32 = 1, 2
 SDG_ASSEMBLE_BLOCK_PRECOND = 4
 SDG_SOLVER_AUTO, SDG_SOLVER_CG, SDG_SOLVER_GMRES = 0, 1, 2
 SDG_PRECOND_NONE, SDG_PRECOND_MASS, SDG_PRECOND_BLOCK = 0, 1, 2
+SDG_SOLVE_GRAPH = 1
 
 _ERRNAMES = {SDG_EINVAL: "EINVAL", SDG_ENOMEM: "ENOMEM", SDG_EDEVICE: "EDEVICE", SDG_EMESH: "EMESH",
              SDG_ENOCONV: "ENOCONV", SDG_ENONFINITE: "ENONFINITE", SDG_EUNSUPPORTED: "EUNSUPPORTED",
@@ -62,7 +63,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int32), ("precision", ctypes.c_int32), ("rtol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("precond", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("flags", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

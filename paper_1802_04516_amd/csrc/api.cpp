@@ -200,6 +200,113 @@ void locate_points(Ctx& c, int64_t n_pts, const double* pts) {
   c.samp_pts.assign(pts, pts + nd);
 }
 
+// Right-hand side of eq. (velocity.sys) (or velocity.sys.cn) for R columns
+// into d_b (point sources from d_src_amp when src), and the initial guess
+// (old state at every time node) into d_x.
+void step_rhs(Ctx& c, const double* v_state, const double* sigma_state, int R, bool src, hipStream_t s) {
+  const HostSetup& hs = c.hs;
+  const int d = hs.dim, ng = hs.ng, nvs = d * hs.nphi;
+  const double dt = hs.dt;
+  if (c.scheme == SDG_SCHEME_CN) {
+    OpArgs a = base_args(c, SDG_PREC_F64);
+    a.v = v_state;
+    a.sig_in = sigma_state;
+    a.z = c.d_z.p;
+    a.y = c.d_b.p;
+    a.use_g = 1;
+    a.c.Cg[0] = -dt * dt / 4.0;
+    a.c.Cs[0] = dt;
+    a.c.Tm[0] = 1.0;
+    a.n_cols = R;
+    a.cs_v = c.n_state;
+    a.cs_sig_in = c.n_sig_state;
+    a.cs_z = c.z_col;
+    a.cs_y = c.n_slab;
+    launch_face(d, hs.p, 1, SDG_PREC_F64, kScatter, a, s);
+    launch_elem(d, hs.p, 1, a, s);
+  } else {
+    std::vector<double> Ti = inverse(hs.T, ng);
+    OpArgs a = base_args(c, SDG_PREC_F64);
+    a.sig_in = sigma_state;
+    a.z = c.d_z.p;
+    a.use_g = 0;
+    a.c.Cs[0] = 1.0;
+    a.n_cols = R;
+    a.cs_sig_in = c.n_sig_state;
+    a.cs_z = c.z_col;
+    launch_face(d, hs.p, 1, SDG_PREC_F64, kScatter, a, s);
+    OpArgs e = base_args(c, SDG_PREC_F64);
+    e.v = v_state;
+    e.v_spatial = 1;
+    e.z = c.d_z.p;
+    e.y = c.d_b.p;
+    e.n_cols = R;
+    e.cs_v = c.n_state;
+    e.cs_z = c.z_col;
+    e.cs_y = c.n_slab;
+    for (int aa = 0; aa < ng; ++aa) {
+      e.c.Tm[aa * ng] = hs.e0[aa];
+      double q = 0.0;
+      for (int b = 0; b < ng; ++b) q += Ti[aa * ng + b] * hs.e0[b];
+      e.c.Cs[aa] = dt * hs.w[aa] * q;
+    }
+    launch_elem(d, hs.p, ng, e, s);
+  }
+  SDG_HIP(hipGetLastError());
+  if (src) launch_add_sources(c, c.d_b.p, c.d_src_amp.p, s, R);
+  launch_broadcast_time(hs.n_elem * R, ng, nvs, v_state, c.d_x.p, s);
+}
+
+// Stress back-substitution (eq. NM26 or NM26.cn) from the velocity slab in
+// d_x, then the end-of-slab state, for R columns.
+void step_backsub(Ctx& c, double* v_state, double* sigma_state, double* v_slab, double* sigma_slab, int R,
+                  hipStream_t s) {
+  const HostSetup& hs = c.hs;
+  const int d = hs.dim, ng = hs.ng, nvs = d * hs.nphi;
+  const double dt = hs.dt;
+  const int64_t N = c.n_slab * R;
+  OpArgs a = base_args(c, SDG_PREC_F64);
+  a.sig_in = sigma_state;
+  a.use_g = 1;
+  a.s_out = sigma_slab;
+  a.s_end = c.d_tmp_sig.p;
+  a.n_cols = R;
+  a.cs_v = c.n_slab;
+  a.cs_sig_in = c.n_sig_state;
+  a.cs_s_out = hs.n_face * ng * hs.nsig * hs.npsi;
+  a.cs_s_end = c.n_sig_state;
+  if (c.scheme == SDG_SCHEME_CN) {
+    vec_copy(N, v_state, c.d_t.p, s);
+    vec_axpby(N, 1.0, c.d_x.p, 1.0, c.d_t.p, s);  // v^n + v^{n+1}
+    a.v = c.d_t.p;
+    a.c.Cg[0] = -dt / 2.0;
+    a.c.Cs[0] = 1.0;
+    a.c.send[0] = 1.0;
+    launch_face(d, hs.p, 1, SDG_PREC_F64, kWriteStress, a, s);
+    SDG_HIP(hipGetLastError());
+    vec_copy(c.n_sig_state * R, c.d_tmp_sig.p, sigma_state, s);
+    if (v_slab) vec_copy(N, c.d_x.p, v_slab, s);
+    vec_copy(c.n_state * R, c.d_x.p, v_state, s);
+  } else {
+    std::vector<double> Ti = inverse(hs.T, ng);
+    a.v = c.d_x.p;
+    for (int aa = 0; aa < ng; ++aa) {
+      double q = 0.0;
+      for (int b = 0; b < ng; ++b) {
+        a.c.Cg[aa * ng + b] = -dt * Ti[aa * ng + b] * hs.w[b];
+        q += Ti[aa * ng + b] * hs.e0[b];
+      }
+      a.c.Cs[aa] = q;
+      a.c.send[aa] = hs.e1[aa];
+    }
+    launch_face(d, hs.p, ng, SDG_PREC_F64, kWriteStress, a, s);
+    SDG_HIP(hipGetLastError());
+    vec_copy(c.n_sig_state * R, c.d_tmp_sig.p, sigma_state, s);
+    if (v_slab) vec_copy(N, c.d_x.p, v_slab, s);
+    launch_end_of_slab(hs.n_elem * R, ng, nvs, c.d_e1.p, c.d_x.p, v_state, s);
+  }
+}
+
 // Partition of the independent systems of a batched solve with ncols columns,
 // or of the meshes of a mesh batch (rebuilt when the column count changes).
 MultiSys& systems(Ctx& c, int ncols) {
@@ -212,6 +319,7 @@ MultiSys& systems(Ctx& c, int ncols) {
     } else {
       for (int r = 0; r <= ncols; ++r) off.push_back((int64_t)r * c.n_slab);
     }
+    c.graphs.clear();  // recorded graphs point into the old partition
     c.msys.build(off);
     c.msys_key = key;
   }
@@ -361,6 +469,7 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     c.assembled = false;
     c.msys_key = 0;
     c.samp_pts.clear();
+    c.graphs.clear();
     HostSetup& hs = c.hs;
     const int64_t n_elem = (int64_t)(c.elem.size() / (c.dim + 1));
     const int64_t n_vert = (int64_t)(c.xyz.size() / c.dim);
@@ -524,6 +633,7 @@ int sdg_set_operator_variant(sdg_ctx* ctx, int variant) {
     require(c.assembled, SDG_ESTATE, "assemble first");
     require(variant >= -1 && variant <= 2, SDG_EINVAL, "variant must be -1 (autotune), 0, 1 or 2");
     SDG_HIP(hipSetDevice(c.device));
+    c.graphs.clear();
     if (variant < 0) autotune(c);
     else c.variant64 = c.variant32 = variant;
   });
@@ -625,6 +735,7 @@ static int set_sources_impl(sdg_ctx* ctx, int64_t n_src, const double* pos, cons
       for (int k = 0; k < hs.dim; ++k) dr[s * hs.dim + k] = dir[s * hs.dim + k];
     }
     SDG_HIP(hipSetDevice(c.device));
+    c.graphs.clear();
     c.n_src = n_src;
     c.src_elem = el;
     c.src_phi = phi;
@@ -660,87 +771,127 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     require(v_state && sigma_state && opts, SDG_EINVAL, "null argument");
     require(n_rhs >= 1 && n_rhs <= c.max_rhs, SDG_EINVAL, "n_rhs must be in [1, max_rhs of sdg_assemble]");
     require(opts->rtol > 0 && opts->max_iter > 0, SDG_EINVAL, "rtol and max_iter must be positive");
+    require((opts->flags & ~SDG_SOLVE_GRAPH) == 0, SDG_EINVAL, "unknown solve flags");
     const int prec = opts->precision == 0 ? SDG_PREC_F64 : opts->precision;
     check_prec(c, SDG_PREC_F64);
     if (prec == SDG_PREC_F32) check_prec(c, SDG_PREC_F32);
     const int R = n_rhs;
-    const bool multi = R > 1 || c.n_mesh > 1;
+    const bool graph = (opts->flags & SDG_SOLVE_GRAPH) != 0;
+    const bool multi = R > 1 || c.n_mesh > 1 || graph;
     int solver = opts->solver;
     if (solver == SDG_SOLVER_AUTO) solver = c.scheme == SDG_SCHEME_CN && !multi ? SDG_SOLVER_CG : SDG_SOLVER_GMRES;
     require(solver == SDG_SOLVER_CG || solver == SDG_SOLVER_GMRES, SDG_EINVAL, "unknown solver");
     require(!multi || solver == SDG_SOLVER_GMRES, SDG_EUNSUPPORTED,
-            "batched and mesh-batch solves use GMRES (SDG_SOLVER_GMRES or AUTO)");
+            "batched, mesh-batch and graph solves use GMRES (SDG_SOLVER_GMRES or AUTO)");
+    require(!graph || prec == SDG_PREC_F64, SDG_EUNSUPPORTED, "graph mode runs the FP64 solve");
     require(solver != SDG_SOLVER_GMRES || c.d_V.n >= (size_t)(kMaxRestart + 1) * c.n_slab * R, SDG_EINVAL,
             "GMRES workspace is only allocated for the space-time scheme or batched solves");
     const int restart = opts->restart > 0 ? opts->restart : 30;
     require(restart <= kMaxRestart, SDG_EINVAL, "restart must be <= 32");
+    require(opts->precond >= SDG_PRECOND_NONE && opts->precond <= SDG_PRECOND_BLOCK, SDG_EINVAL,
+            "unknown preconditioner");
     SDG_HIP(hipSetDevice(c.device));
     hipStream_t s = (hipStream_t)stream;
-    const HostSetup& hs = c.hs;
-    const int d = hs.dim, ng = hs.ng, nvs = d * hs.nphi;
-    const double dt = hs.dt;
     const int64_t N = c.n_slab * R;
-    const int64_t sig_slab_col = hs.n_face * ng * hs.nsig * hs.npsi;
-
-    // 1. right-hand side (one launch for all columns)
-    if (c.scheme == SDG_SCHEME_CN) {
-      OpArgs a = base_args(c, SDG_PREC_F64);
-      a.v = v_state;
-      a.sig_in = sigma_state;
-      a.z = c.d_z.p;
-      a.y = c.d_b.p;
-      a.use_g = 1;
-      a.c.Cg[0] = -dt * dt / 4.0;
-      a.c.Cs[0] = dt;
-      a.c.Tm[0] = 1.0;
-      a.n_cols = R;
-      a.cs_v = c.n_state;
-      a.cs_sig_in = c.n_sig_state;
-      a.cs_z = c.z_col;
-      a.cs_y = c.n_slab;
-      launch_face(d, hs.p, 1, SDG_PREC_F64, kScatter, a, s);
-      launch_elem(d, hs.p, 1, a, s);
-    } else {
-      std::vector<double> Ti = inverse(hs.T, ng);
-      OpArgs a = base_args(c, SDG_PREC_F64);
-      a.sig_in = sigma_state;
-      a.z = c.d_z.p;
-      a.use_g = 0;
-      a.c.Cs[0] = 1.0;
-      a.n_cols = R;
-      a.cs_sig_in = c.n_sig_state;
-      a.cs_z = c.z_col;
-      launch_face(d, hs.p, 1, SDG_PREC_F64, kScatter, a, s);
-      OpArgs e = base_args(c, SDG_PREC_F64);
-      e.v = v_state;
-      e.v_spatial = 1;
-      e.z = c.d_z.p;
-      e.y = c.d_b.p;
-      e.n_cols = R;
-      e.cs_v = c.n_state;
-      e.cs_z = c.z_col;
-      e.cs_y = c.n_slab;
-      for (int aa = 0; aa < ng; ++aa) {
-        e.c.Tm[aa * ng] = hs.e0[aa];
-        double q = 0.0;
-        for (int b = 0; b < ng; ++b) q += Ti[aa * ng + b] * hs.e0[b];
-        e.c.Cs[aa] = dt * hs.w[aa] * q;
-      }
-      launch_elem(d, hs.p, ng, e, s);
-    }
-    SDG_HIP(hipGetLastError());
-    if (amp && c.n_src > 0) {
-      SDG_HIP(hipMemcpyAsync(c.d_src_amp.p, amp, c.n_src * ng * sizeof(double), hipMemcpyHostToDevice, s));
-      launch_add_sources(c, c.d_b.p, c.d_src_amp.p, s, R);
-    }
-
-    // 2. initial guess (old state at every time node) and Krylov solve
-    launch_broadcast_time(hs.n_elem * R, ng, nvs, v_state, c.d_x.p, s);
     KrylovCfg kc;
     kc.check_every = opts->check_every > 0 ? opts->check_every : 5;
     kc.restart = restart;
     kc.precond = opts->precond;
-    require(kc.precond >= SDG_PRECOND_NONE && kc.precond <= SDG_PRECOND_BLOCK, SDG_EINVAL, "unknown preconditioner");
+    kc.rtol = opts->rtol;
+    kc.max_iter = opts->max_iter;
+
+    if (graph) {
+      MultiSys& m = systems(c, R);
+      StepGraphs& G = c.graphs;
+      if (!G.stream) SDG_HIP(hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
+      hipStream_t gs = G.stream;
+      std::function<void(const double*, double*)> op = [&c, R, gs](const double* in, double* out) {
+        apply_op(c, in, out, SDG_PREC_F64, false, gs, R);
+      };
+      std::function<void(const double*, double*)> pre = [&c, R, gs, kc](const double* in, double* out) {
+        apply_precond(c, kc.precond, in, out, false, gs, R);
+      };
+      const std::function<void(const double*, double*)>* pp = kc.precond != SDG_PRECOND_NONE ? &pre : nullptr;
+      const bool src = amp && c.n_src > 0;
+      const bool same = G.head && G.v == v_state && G.sig == sigma_state && G.vslab == v_slab &&
+                        G.sslab == sigma_slab && G.R == R && G.precond == kc.precond && G.restart == restart &&
+                        G.rtol == kc.rtol && G.src == src;
+      if (!same) {
+        G.clear();
+        auto record = [&](auto&& body) {
+          SDG_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed));
+          hipGraph_t g = nullptr;
+          try {
+            body();
+          } catch (...) {
+            (void)hipStreamEndCapture(gs, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+          }
+          SDG_HIP(hipStreamEndCapture(gs, &g));
+          hipGraphExec_t e = nullptr;
+          const hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(g);
+          SDG_HIP(err);
+          return e;
+        };
+        int mv = 0;
+        bool done = false;
+        G.head = record([&] {
+          step_rhs(c, v_state, sigma_state, R, src, gs);
+          multi_setup(m, c.d_b.p, c.d_x.p, kc.rtol, gs);
+          multi_cycle(m, c.d_b.p, c.d_x.p, kc, gs, op, pp, c.d_V.p, c.d_r.p, c.d_w.p, c.d_t.p, false, restart, &mv,
+                      &done);
+        });
+        G.cycle = record([&] {
+          multi_cycle(m, c.d_b.p, c.d_x.p, kc, gs, op, pp, c.d_V.p, c.d_r.p, c.d_w.p, c.d_t.p, false, restart, &mv,
+                      &done);
+        });
+        G.verify = record([&] { multi_residual(m, c.d_b.p, c.d_x.p, gs, op, c.d_r.p); });
+        G.tail = record([&] { step_backsub(c, v_state, sigma_state, v_slab, sigma_slab, R, gs); });
+        G.v = v_state;
+        G.sig = sigma_state;
+        G.vslab = v_slab;
+        G.sslab = sigma_slab;
+        G.R = R;
+        G.precond = kc.precond;
+        G.restart = restart;
+        G.rtol = kc.rtol;
+        G.src = src;
+      }
+      SDG_HIP(hipStreamSynchronize(s));
+      if (src)
+        SDG_HIP(hipMemcpyAsync(c.d_src_amp.p, amp, c.n_src * c.hs.ng * sizeof(double), hipMemcpyHostToDevice, gs));
+      SDG_HIP(hipGraphLaunch(G.head, gs));
+      res.iters = restart;
+      res.matvecs = restart + 1;
+      for (;;) {
+        if (multi_nactive(m, gs) == 0) {
+          SDG_HIP(hipGraphLaunch(G.verify, gs));
+          ++res.matvecs;
+          if (multi_nactive(m, gs) == 0) {
+            res.converged = true;
+            break;
+          }
+        }
+        if (res.iters >= kc.max_iter) break;
+        SDG_HIP(hipGraphLaunch(G.cycle, gs));
+        res.iters += restart;
+        res.matvecs += restart + 1;
+      }
+      SDG_HIP(hipGraphLaunch(G.tail, gs));
+      multi_result(m, gs, res);
+      SDG_HIP(hipStreamSynchronize(gs));
+      if (!res.converged) throw Error(SDG_ENOCONV, "Krylov solver did not reach rtol within max_iter");
+      return;
+    }
+
+    // 1. right-hand side (one launch for all columns)
+    const bool src = amp && c.n_src > 0;
+    if (src) SDG_HIP(hipMemcpyAsync(c.d_src_amp.p, amp, c.n_src * c.hs.ng * sizeof(double), hipMemcpyHostToDevice, s));
+    step_rhs(c, v_state, sigma_state, R, src, s);
+
+    // 2. Krylov solve from the old state copied to every time node
     auto inner = [&](const double* b, double* x, double tol, int maxit, int pr) {
       KrylovCfg k2 = kc;
       k2.rtol = tol;
@@ -798,46 +949,7 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     }
 
     // 3. stress back-substitution and 4. end-of-slab state
-    OpArgs a = base_args(c, SDG_PREC_F64);
-    a.sig_in = sigma_state;
-    a.use_g = 1;
-    a.s_out = sigma_slab;
-    a.s_end = c.d_tmp_sig.p;
-    a.n_cols = R;
-    a.cs_v = c.n_slab;
-    a.cs_sig_in = c.n_sig_state;
-    a.cs_s_out = sig_slab_col;
-    a.cs_s_end = c.n_sig_state;
-    if (c.scheme == SDG_SCHEME_CN) {
-      vec_copy(N, v_state, c.d_t.p, s);
-      vec_axpby(N, 1.0, c.d_x.p, 1.0, c.d_t.p, s);  // v^n + v^{n+1}
-      a.v = c.d_t.p;
-      a.c.Cg[0] = -dt / 2.0;
-      a.c.Cs[0] = 1.0;
-      a.c.send[0] = 1.0;
-      launch_face(d, hs.p, 1, SDG_PREC_F64, kWriteStress, a, s);
-      SDG_HIP(hipGetLastError());
-      vec_copy(c.n_sig_state * R, c.d_tmp_sig.p, sigma_state, s);
-      if (v_slab) vec_copy(N, c.d_x.p, v_slab, s);
-      vec_copy(c.n_state * R, c.d_x.p, v_state, s);
-    } else {
-      std::vector<double> Ti = inverse(hs.T, ng);
-      a.v = c.d_x.p;
-      for (int aa = 0; aa < ng; ++aa) {
-        double q = 0.0;
-        for (int b = 0; b < ng; ++b) {
-          a.c.Cg[aa * ng + b] = -dt * Ti[aa * ng + b] * hs.w[b];
-          q += Ti[aa * ng + b] * hs.e0[b];
-        }
-        a.c.Cs[aa] = q;
-        a.c.send[aa] = hs.e1[aa];
-      }
-      launch_face(d, hs.p, ng, SDG_PREC_F64, kWriteStress, a, s);
-      SDG_HIP(hipGetLastError());
-      vec_copy(c.n_sig_state * R, c.d_tmp_sig.p, sigma_state, s);
-      if (v_slab) vec_copy(N, c.d_x.p, v_slab, s);
-      launch_end_of_slab(hs.n_elem * R, ng, nvs, c.d_e1.p, c.d_x.p, v_state, s);
-    }
+    step_backsub(c, v_state, sigma_state, v_slab, sigma_slab, R, s);
     SDG_HIP(hipStreamSynchronize(s));
     if (!res.converged) throw Error(SDG_ENOCONV, "Krylov solver did not reach rtol within max_iter");
   });

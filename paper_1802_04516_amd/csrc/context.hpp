@@ -78,6 +78,24 @@ struct MultiSys {
   ~MultiSys();
 };
 
+// Step recorded in HIP graphs, with the arguments it was recorded for.
+struct StepGraphs {
+  hipGraphExec_t head = nullptr, cycle = nullptr, verify = nullptr, tail = nullptr;
+  hipStream_t stream = nullptr;
+  const void *v = nullptr, *sig = nullptr, *vslab = nullptr, *sslab = nullptr;
+  int R = 0, precond = 0, restart = 0, max_iter = 0, check_every = 0;
+  double rtol = 0.0;
+  bool src = false;
+  void clear() {
+    for (hipGraphExec_t* g : {&head, &cycle, &verify, &tail})
+      if (*g) { (void)hipGraphExecDestroy(*g); *g = nullptr; }
+  }
+  ~StepGraphs() {
+    clear();
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
 struct Ctx {
   int device = 0;
   // inputs
@@ -143,6 +161,8 @@ struct Ctx {
   int msys_key = 0;        // columns the partition was built for (-1: mesh batch)
   int64_t z_col = 0;       // face-slot workspace per column
 
+  StepGraphs graphs;
+
   // located sampling points of the last call
   std::vector<double> samp_pts;
   DevBuf<int64_t> d_samp_elem;
@@ -178,6 +198,21 @@ struct KrylovCfg {
 };
 SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s);
 SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s);
+// Pieces of the multi-system GMRES, also used to record the step in HIP
+// graphs (poll = false: no host synchronisation inside):
+//   multi_setup     per-system ||b||, tolerances, x = 0 where b = 0;
+//   multi_residual  r = b - A x, per-system ||r||, activity flags;
+//   multi_cycle     residual + one restart cycle of at most max_steps Arnoldi
+//                   steps with device-side masks, then the correction.
+void multi_setup(MultiSys& m, const double* b, double* x, double rtol, hipStream_t s);
+void multi_residual(MultiSys& m, const double* b, const double* x, hipStream_t s,
+                    const std::function<void(const double*, double*)>& op, double* r);
+int multi_cycle(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
+                const std::function<void(const double*, double*)>& op,
+                const std::function<void(const double*, double*)>* pre, double* V, double* r, double* w, double* t,
+                bool poll, int max_steps, int* matvecs, bool* all_converged);
+int multi_nactive(MultiSys& m, hipStream_t s);
+void multi_result(MultiSys& m, hipStream_t s, SolveResult& res);
 // Largest ||r_s|| / ||b_s|| over the systems of m (bnorm_max: largest ||b_s||).
 double multi_rel_residual(MultiSys& m, const double* b, const double* r, hipStream_t s, double* bnorm_max);
 MultiSys& systems(Ctx& c, int ncols);

@@ -414,71 +414,83 @@ double multi_rel_residual(MultiSys& m, const double* b, const double* r, hipStre
   return worst;
 }
 
-SolveResult solve_gmres_multi(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
-                              const std::function<void(const double*, double*)>& op,
-                              const std::function<void(const double*, double*)>* pre, double* V, double* r,
-                              double* w, double* t) {
-  SolveResult res;
+void multi_setup(MultiSys& m, const double* b, double* x, double rtol, hipStream_t s) {
+  seg_norm2(m, b, s);
+  km_set_tol<<<1, sys_threads(m.S), 0, s>>>(m.S, m.d_ss.p, rtol);
+  km_zero_null<<<(unsigned)m.n_blocks, kT, 0, s>>>(map_of(m), x, m.d_ss.p);
+  SDG_HIP(hipGetLastError());
+}
+
+void multi_residual(MultiSys& m, const double* b, const double* x, hipStream_t s,
+                    const std::function<void(const double*, double*)>& op, double* r) {
+  op(x, r);
+  vec_axpby(m.n_total, 1.0, b, -1.0, r, s);
+  seg_norm2(m, r, s);
+  km_cycle_start<<<1, sys_threads(m.S), 0, s>>>(m.S, m.d_ss.p, m.d_nactive.p);
+  SDG_HIP(hipGetLastError());
+}
+
+int multi_cycle(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
+                const std::function<void(const double*, double*)>& op,
+                const std::function<void(const double*, double*)>* pre, double* V, double* r, double* w, double* t,
+                bool poll, int max_steps, int* matvecs, bool* all_converged) {
   const int64_t n = m.n_total;
   const BlockMap bm = map_of(m);
   SysScalars* ss = m.d_ss.p;
   const unsigned st = sys_threads(m.S);
-  const int mres = k.restart;
   const int check_every = std::max(1, k.check_every);
-  seg_norm2(m, b, s);
-  km_set_tol<<<1, st, 0, s>>>(m.S, ss, k.rtol);
-  km_zero_null<<<(unsigned)m.n_blocks, kT, 0, s>>>(bm, x, ss);
-  SDG_HIP(hipGetLastError());
-  int total = 0;
-  for (;;) {
-    op(x, r);
-    ++res.matvecs;
-    vec_axpby(n, 1.0, b, -1.0, r, s);
-    seg_norm2(m, r, s);
-    km_cycle_start<<<1, st, 0, s>>>(m.S, ss, m.d_nactive.p);
-    SDG_HIP(hipGetLastError());
-    const int nact = read_int(m.d_nactive.p, m.h_pinned, s);
-    if (nact == 0) { res.converged = true; break; }
-    if (total >= k.max_iter) break;
-    km_scale<<<(unsigned)m.n_blocks, kT, 0, s>>>(bm, r, V, ss, 1);
-    SDG_HIP(hipGetLastError());
-    int kk = 0;
-    for (int j = 0; j < mres && total < k.max_iter; ++j) {
-      double* vj = V + (size_t)j * n;
-      if (pre) {
-        (*pre)(vj, t);
-        op(t, w);
-      } else {
-        op(vj, w);
-      }
-      ++res.matvecs;
-      launch_m(Op::Multidot, j + 1, bm, s, n, V, w, ss, m.d_partials.p);
-      finalize(m, j + 1, kH1, 0, s);
-      launch_m(Op::Pass, j + 1, bm, s, n, V, w, ss, m.d_partials.p);
-      finalize(m, j + 1, kH2, 0, s);
-      launch_m(Op::Final, j + 1, bm, s, n, V, w, ss, m.d_partials.p);
-      km_arnoldi_fin<<<1, st, 0, s>>>(m.d_partials.p, m.n_blocks, m.d_seg_blk0.p, m.S, j, ss, m.d_nactive.p);
-      SDG_HIP(hipGetLastError());
-      km_scale<<<(unsigned)m.n_blocks, kT, 0, s>>>(bm, w, V + (size_t)(j + 1) * n, ss, 1);
-      SDG_HIP(hipGetLastError());
-      ++total;
-      ++res.iters;
-      kk = j + 1;
-      if ((j + 1) % check_every == 0 || j + 1 == mres) {
-        if (read_int(m.d_nactive.p, m.h_pinned, s) == 0) break;
-      }
+  *all_converged = false;
+  multi_residual(m, b, x, s, op, r);
+  ++*matvecs;
+  if (poll) {
+    if (read_int(m.d_nactive.p, m.h_pinned, s) == 0) {
+      *all_converged = true;
+      return 0;
     }
-    km_trisolve<<<1, st, 0, s>>>(m.S, ss);
-    SDG_HIP(hipGetLastError());
+    if (max_steps <= 0) return 0;
+  }
+  km_scale<<<(unsigned)m.n_blocks, kT, 0, s>>>(bm, r, V, ss, 1);
+  SDG_HIP(hipGetLastError());
+  int kk = 0;
+  for (int j = 0; j < k.restart && j < max_steps; ++j) {
+    double* vj = V + (size_t)j * n;
     if (pre) {
-      vec_fill(n, 0.0, t, s);
-      launch_m(Op::Update, kk, bm, s, n, V, t, ss, nullptr);
-      (*pre)(t, w);
-      vec_axpby(n, 1.0, w, 1.0, x, s);
+      (*pre)(vj, t);
+      op(t, w);
     } else {
-      launch_m(Op::Update, kk, bm, s, n, V, x, ss, nullptr);
+      op(vj, w);
+    }
+    ++*matvecs;
+    launch_m(Op::Multidot, j + 1, bm, s, n, V, w, ss, m.d_partials.p);
+    finalize(m, j + 1, kH1, 0, s);
+    launch_m(Op::Pass, j + 1, bm, s, n, V, w, ss, m.d_partials.p);
+    finalize(m, j + 1, kH2, 0, s);
+    launch_m(Op::Final, j + 1, bm, s, n, V, w, ss, m.d_partials.p);
+    km_arnoldi_fin<<<1, st, 0, s>>>(m.d_partials.p, m.n_blocks, m.d_seg_blk0.p, m.S, j, ss, m.d_nactive.p);
+    SDG_HIP(hipGetLastError());
+    km_scale<<<(unsigned)m.n_blocks, kT, 0, s>>>(bm, w, V + (size_t)(j + 1) * n, ss, 1);
+    SDG_HIP(hipGetLastError());
+    kk = j + 1;
+    if (poll && ((j + 1) % check_every == 0 || j + 1 == k.restart)) {
+      if (read_int(m.d_nactive.p, m.h_pinned, s) == 0) break;
     }
   }
+  km_trisolve<<<1, st, 0, s>>>(m.S, ss);
+  SDG_HIP(hipGetLastError());
+  if (pre) {
+    vec_fill(n, 0.0, t, s);
+    launch_m(Op::Update, kk, bm, s, n, V, t, ss, nullptr);
+    (*pre)(t, w);
+    vec_axpby(n, 1.0, w, 1.0, x, s);
+  } else {
+    launch_m(Op::Update, kk, bm, s, n, V, x, ss, nullptr);
+  }
+  return kk;
+}
+
+int multi_nactive(MultiSys& m, hipStream_t s) { return read_int(m.d_nactive.p, m.h_pinned, s); }
+
+void multi_result(MultiSys& m, hipStream_t s, SolveResult& res) {
   std::vector<SysScalars> h;
   m.read_scalars(h, s);
   double worst = 0.0, bmax = 0.0;
@@ -489,6 +501,28 @@ SolveResult solve_gmres_multi(MultiSys& m, const double* b, double* x, const Kry
   res.rel_res = worst;
   res.bnorm = bmax;
   require(std::isfinite(worst), SDG_ENONFINITE, "non-finite residual");
+}
+
+SolveResult solve_gmres_multi(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
+                              const std::function<void(const double*, double*)>& op,
+                              const std::function<void(const double*, double*)>* pre, double* V, double* r,
+                              double* w, double* t) {
+  SolveResult res;
+  multi_setup(m, b, x, k.rtol, s);
+  for (;;) {
+    bool done = false;
+    const int it = multi_cycle(m, b, x, k, s, op, pre, V, r, w, t, true, k.max_iter - res.iters, &res.matvecs, &done);
+    res.iters += it;
+    if (done) { res.converged = true; break; }
+    if (it == 0 || res.iters >= k.max_iter) {
+      // one more residual evaluation to report the final state
+      bool d2 = false;
+      multi_cycle(m, b, x, k, s, op, pre, V, r, w, t, true, 0, &res.matvecs, &d2);
+      res.converged = d2;
+      break;
+    }
+  }
+  multi_result(m, s, res);
   return res;
 }
 

@@ -203,3 +203,94 @@ def test_mesh_batch_step_matches_oracle_per_mesh(scheme, p, pg, precision):
         assert worst <= 1e-11
     assert sizes["n_elem"] == sum(m.n_elem for m in meshes)
     ctx.close()
+
+
+GRAPH_CASES = {
+    # name: (meshes, p, p_gamma, scheme, columns)
+    "mesh_batch_stdg": ([m for m, _ in MESH_BATCH], 2, 2, "stdg", 1),
+    "single_stdg_p3": ([lambda: synth.split_square(6, jitter=0.2, seed=2001)], 3, 3, "stdg", 1),
+    "batched_cn": ([lambda: synth.split_square(5, jitter=0.1, seed=4)], 2, 0, "cn", 3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(GRAPH_CASES))
+def test_graph_replays_match_eager_steps_and_oracle(name):
+    """The step recorded in HIP graphs is replayed for several steps with
+    other work and synchronisations in between; every replayed step is
+    checked against the same step run eagerly and against the oracle."""
+    import torch
+    import paper_1802_04516_amd as sdg
+    mks, p, pg, scheme, R = GRAPH_CASES[name]
+    meshes = [mk() for mk in mks]
+    mats = [synth.lognormal_material(m.n_elem, sigma=0.2, seed=200 + q) for q, m in enumerate(meshes)]
+    lam, mu, rho = (np.concatenate([mt[i] for mt in mats]) for i in range(3))
+    dt = 0.01
+    sch = sdg.SDG_SCHEME_CN if scheme == "cn" else sdg.SDG_SCHEME_STDG
+    prc = sdg.SDG_PREC_F64 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND
+    ctx = sdg.Context(0)
+    if len(meshes) > 1:
+        ctx.setup_batch([(m.xyz, m.elem) for m in meshes], p, pg, sch, dt, lam, mu, rho, prc)
+        ctx.set_mesh_sources(np.array([[0.37, 0.61], [0.52, 0.44], [0.7, 0.3]]), np.array([[0.0, 1.0]] * 3),
+                             np.arange(3, dtype=np.int32))
+        n_src = 3
+    else:
+        ctx.setup(meshes[0].xyz, meshes[0].elem, None, p, pg, sch, dt, lam, mu, rho, prc, max_rhs=R)
+        ctx.set_sources(np.array([[0.41, 0.57], [0.6, 0.35], [0.25, 0.3]][:R]), np.array([[0.0, 1.0]] * R))
+        n_src = R
+    slabs = [Slab(Blocks(Topology(m.xyz, m.elem, None), p, *mt), pg, dt, scheme) for m, mt in zip(meshes, mats)]
+    sz = ctx.sizes
+    rng = np.random.default_rng(13)
+    v0 = 0.2 * rng.standard_normal(sz["n_vel_state"] * R)
+    s0 = np.zeros(sz["n_stress_state"] * R)
+    vg, sg = _gpu(v0), _gpu(s0)          # graph-mode state
+    ve, se = _gpu(v0), _gpu(s0)          # eager state
+    opts_g = _opts(precond=sdg.SDG_PRECOND_BLOCK)
+    opts_g.flags = sdg.SDG_SOLVE_GRAPH
+    opts_e = _opts(precond=sdg.SDG_PRECOND_BLOCK)
+    scratch_v = torch.randn(sz["n_vel_slab"], dtype=torch.float64, device="cuda")
+    scratch_y = torch.empty_like(scratch_v)
+    for n in range(4):
+        amps = _amps(slabs[0], scheme, dt, n, n_src, np.linspace(1.0, -0.5, n_src))
+        # the eager step starts from the graph path's state so both see the same input
+        ve.copy_(vg)
+        se.copy_(sg)
+        vin = vg.cpu().numpy()
+        sin = sg.cpu().numpy()
+        info_g = ctx.step(vg, sg, amps.ravel(), n_rhs=R, opts=opts_g)
+        ctx.apply(scratch_v, scratch_y)          # eager work between replays
+        torch.cuda.synchronize()
+        info_e = ctx.step(ve, se, amps.ravel(), n_rhs=R, opts=opts_e)
+        d_ge = max(rel(vg.cpu().numpy(), ve.cpu().numpy()), rel(sg.cpu().numpy(), se.cpu().numpy()))
+        # oracle, per mesh / column, from the same input
+        worst = 0.0
+        if len(meshes) > 1:
+            nvs, nss = 2 * slabs[0].nphi, 3 * slabs[0].npsi
+            eoff = ctx.mesh_elem_off
+            left = ctx.face_table()[0]
+            foff = np.searchsorted(left, eoff)
+            for q, S in enumerate(slabs):
+                vq = vin[eoff[q] * nvs:eoff[q + 1] * nvs].reshape(S.ne, S.d, S.nphi)
+                sq = sin[foff[q] * nss:foff[q + 1] * nss].reshape(S.nf, S.nsig, S.npsi)
+                sraw = np.stack([S.B.from_canonical(j, sq[j]) for j in range(S.nf)])
+                src = dict(pos=np.array([[0.37, 0.61], [0.52, 0.44], [0.7, 0.3]])[q:q + 1],
+                           dir=np.array([[0.0, 1.0]]), amp=amps[q:q + 1])
+                _, _, v1, s1 = S.step(vq, sraw, src)
+                worst = max(worst, rel(vg.cpu().numpy()[eoff[q] * nvs:eoff[q + 1] * nvs], v1),
+                            rel(sg.cpu().numpy()[foff[q] * nss:foff[q + 1] * nss],
+                                np.stack([S.B.to_canonical(j, s1[j]) for j in range(S.nf)])))
+        else:
+            S = slabs[0]
+            pos = np.array([[0.41, 0.57], [0.6, 0.35], [0.25, 0.3]])
+            for r in range(R):
+                vq = vin.reshape(R, -1)[r].reshape(S.ne, S.d, S.nphi)
+                sq = sin.reshape(R, -1)[r].reshape(S.nf, S.nsig, S.npsi)
+                sraw = np.stack([S.B.from_canonical(j, sq[j]) for j in range(S.nf)])
+                src = dict(pos=pos[r:r + 1], dir=np.array([[0.0, 1.0]]), amp=amps[r:r + 1])
+                _, _, v1, s1 = S.step(vq, sraw, src)
+                worst = max(worst, rel(vg.cpu().numpy().reshape(R, -1)[r], v1),
+                            rel(sg.cpu().numpy().reshape(R, -1)[r],
+                                np.stack([S.B.to_canonical(j, s1[j]) for j in range(S.nf)])))
+        print(f"{name} step {n}: graph vs eager {d_ge:.2e}, vs oracle {worst:.2e}, iters graph "
+              f"{info_g['iterations']} eager {info_e['iterations']}")
+        assert d_ge <= 1e-11 and worst <= 1e-11
+    ctx.close()
