@@ -66,6 +66,171 @@ def cpu_baseline(seconds=10.0):
                       f"{slab.nv} DOF, nnz {S.nnz}) version of the workload recipe, {reps} applies in {dt:.1f}s"}
 
 
+def _solve_opts(sdg, precision, pc, flags=0, solver=None):
+    o = sdg.SolveOpts(solver if solver is not None else sdg.SDG_SOLVER_AUTO, precision, 1e-10, 5000, 30, 5, 10,
+                      1e-4, pc)
+    o.flags = flags
+    return o
+
+
+def bench_batched(args, t_single_fp64):
+    """64 Ricker point sources at seeded random positions (seed 4001) on the
+    workload's mesh and material, one right-hand side each, solved in one
+    batched step (shared launches, per-column GMRES)."""
+    import numpy as np
+    import torch
+
+    import paper_1802_04516_amd as sdg
+    import synth
+    R = 64
+    w = synth.workload("c2")
+    mesh = w["mesh"]
+    ctx = sdg.Context(0)
+    sizes = ctx.setup(mesh.xyz, mesh.elem, mesh.period, w["p"], w["p_gamma"], sdg.SDG_SCHEME_STDG, w["dt"],
+                      w["lam"], w["mu"], w["rho"],
+                      sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND, max_rhs=R)
+    pos = np.random.default_rng(4001).uniform(0.05, 0.95, size=(R, 2))
+    ctx.set_sources(pos, np.tile([[0.0, 1.0]], (R, 1)))
+    tau = np.array(sizes["tau"])
+    dt = w["dt"]
+    step0 = int(0.05 / dt)
+
+    def amps(k):
+        t = (step0 + k) * dt + tau * dt
+        return np.tile(synth.ricker(t, 10.0, 0.1)[None, :], (R, 1)).ravel()
+
+    n = sizes["n_vel_slab"]
+    res = {"n_rhs": R, "velocity_dofs": n * R}
+    for name, prec in (("fp64", sdg.SDG_PREC_F64), ("fp32_operator_fp64_refinement", sdg.SDG_PREC_F32)):
+        v = torch.zeros(sizes["n_vel_state"] * R, dtype=torch.float64, device="cuda")
+        s = torch.zeros(sizes["n_stress_state"] * R, dtype=torch.float64, device="cuda")
+        o = _solve_opts(sdg, prec, sdg.SDG_PRECOND_BLOCK)
+        ctx.step(v, s, amps(0), n_rhs=R, opts=o)
+        torch.cuda.synchronize()
+        steps = 2
+        t0 = time.perf_counter()
+        mv = it = 0
+        for k in range(steps):
+            info = ctx.step(v, s, amps(1 + k), n_rhs=R, opts=o)
+            mv += info["matvecs"]
+            it += info["iterations"]
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        res[name] = {"s_per_step": t, "s_per_step_per_rhs": t / R, "iterations_per_step": it / steps,
+                     "gdofs": n * R * (mv / steps) / t / 1e9}
+        log(f"batched {R} sources {name}: {t * 1e3:.1f} ms/step ({t / R * 1e3:.2f} ms per source), {it / steps:.0f} it")
+    x = torch.randn(n * R, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for prec, key in ((sdg.SDG_PREC_F64, "apply_fp64_us"), (sdg.SDG_PREC_F32, "apply_fp32_us")):
+        for _ in range(3):
+            ctx.apply(x, y, prec, n_rhs=R)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            ctx.apply(x, y, prec, n_rhs=R)
+        e1.record()
+        e1.synchronize()
+        res[key] = e0.elapsed_time(e1) * 1e3 / 10
+    res["single_rhs_fp64_s_per_step"] = t_single_fp64
+    res["speedup_vs_64_single_fp64_steps"] = R * t_single_fp64 / res["fp64"]["s_per_step"]
+    log(f"batched apply FP64 {res['apply_fp64_us']:.0f} us, FP32 {res['apply_fp32_us']:.0f} us for {R} columns")
+    ctx.close()
+    return res
+
+
+def bench_mesh_batch(args):
+    """16 meshes with log-uniform sizes in [512, 16384] triangles (seed
+    4002), jitter seeds 4100+k, layered lognormal media seeds 4200+k, one
+    Ricker source each, one step of all meshes (HIP graphs and eager)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_1802_04516_amd as sdg
+    import synth
+    rng = np.random.default_rng(4002)
+    meshes, mats = [], []
+    for k in range(16):
+        Nk = math.exp(rng.uniform(math.log(512), math.log(16384)))
+        nx = max(1, round(math.sqrt(Nk / 2)))
+        ny = max(1, round(Nk / (2 * nx)))
+        m = synth.split_square(nx, ny, jitter=0.2, seed=4100 + k)
+        meshes.append(m)
+        mats.append(synth.layered_material(m.centroids(), sigma=0.1, seed=4200 + k))
+    lam, mu, rho = (np.concatenate([mt[i] for mt in mats]) for i in range(3))
+    ctx = sdg.Context(0)
+    dt = 2.5e-3
+    sizes = ctx.setup_batch([(m.xyz, m.elem) for m in meshes], 3, 3, sdg.SDG_SCHEME_STDG, dt, lam, mu, rho,
+                            sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND)
+    ctx.set_mesh_sources(np.tile([[0.503, 0.497]], (16, 1)), np.tile([[0.0, 1.0]], (16, 1)),
+                         np.arange(16, dtype=np.int32))
+    tau = np.array(sizes["tau"])
+    step0 = int(0.05 / dt)
+
+    def amps(k):
+        t = (step0 + k) * dt + tau * dt
+        return np.tile(synth.ricker(t, 10.0, 0.1)[None, :], (16, 1)).ravel()
+
+    res = {"n_mesh": 16, "elements": [m.n_elem for m in meshes], "velocity_dofs": sizes["n_vel_slab"]}
+    for name, flags in (("fp64_hip_graph", sdg.SDG_SOLVE_GRAPH), ("fp64_eager", 0)):
+        v = torch.zeros(sizes["n_vel_state"], dtype=torch.float64, device="cuda")
+        s = torch.zeros(sizes["n_stress_state"], dtype=torch.float64, device="cuda")
+        o = _solve_opts(sdg, sdg.SDG_PREC_F64, sdg.SDG_PRECOND_BLOCK, flags, sdg.SDG_SOLVER_GMRES)
+        ctx.step(v, s, amps(0), opts=o)  # warm-up (records the graphs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = ctx.step(v, s, amps(1), opts=o)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        res[name] = {"s_per_step": t, "iterations": info["iterations"], "matvecs": info["matvecs"],
+                     "gdofs": sizes["n_vel_slab"] * info["matvecs"] / t / 1e9}
+        log(f"mesh batch 16 ({sizes['n_elem']} elems) {name}: {t * 1e3:.1f} ms/step, {info['iterations']} it")
+    ctx.close()
+    return res
+
+
+def bench_3d_operator(args):
+    """3D operator on the 32^3 periodic Kuhn cube (196,608 tetrahedra, p=2,
+    Crank-Nicolson, homogeneous): the stored blocks (about 2 GB FP64) exceed
+    the last-level cache, so this apply runs from HBM."""
+    import torch
+
+    import paper_1802_04516_amd as sdg
+    import synth
+    w = synth.workload("c3")
+    mesh = w["mesh"]
+    t0 = time.time()
+    ctx = sdg.Context(0)
+    sizes = ctx.setup(mesh.xyz, mesh.elem, mesh.period, 2, 0, sdg.SDG_SCHEME_CN, w["dt"], w["lam"], w["mu"],
+                      w["rho"], sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32)
+    log(f"3D setup {time.time() - t0:.1f}s: {sizes['n_elem']} tets, operator {sizes['op_bytes_f64'] / 1e9:.2f} GB; "
+        f"autotune f64 {sizes['tune_us_f64']} -> {sizes['op_variant']}")
+    n = sizes["n_vel_slab"]
+    x = torch.randn(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    res = {"elements": sizes["n_elem"], "velocity_dofs": n, "operator_bytes_f64": sizes["op_bytes_f64"]}
+    for prec, key, ob in ((sdg.SDG_PREC_F64, "fp64", sizes["op_bytes_f64"]),
+                          (sdg.SDG_PREC_F32, "fp32", sizes["op_bytes_f32"])):
+        for _ in range(3):
+            ctx.apply(x, y, prec)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        reps = 20
+        for _ in range(reps):
+            ctx.apply(x, y, prec)
+        e1.record()
+        e1.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / reps
+        b_alg = ob + 2 * n * 8 + sizes["n_face"] * 32 + sizes["n_elem"] * 8
+        res[key] = {"apply_us": t * 1e6, "gdofs": n / t / 1e9, "algorithmic_gbs": b_alg / t / 1e9,
+                    "hbm_frac": b_alg / t / 1e9 / HBM_PEAK_GBS}
+        log(f"3D apply {key}: {t * 1e6:.0f} us, {n / t / 1e9:.2f} GDOF/s, {b_alg / t / 1e9:.0f} GB/s "
+            f"({100 * b_alg / t / 1e9 / HBM_PEAK_GBS:.1f}% of HBM peak)")
+    ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +240,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precond", default="block", choices=["none", "mass", "block"])
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched (64 sources), mesh-batch (16 meshes) and 3D operator measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB x 10 (scale for the rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -168,6 +335,26 @@ def main():
     log(f"FP32+IR: {args.steps} steps in {t32:.3f}s, {it32 / args.steps:.1f} inner it/step, "
         f"rel diff to FP64 {err32:.2e}")
 
+    # ---- FP64 steps recorded in HIP graphs
+    v.copy_(v_save)
+    s.copy_(s_save)
+    optsg = sdg.SolveOpts(sdg.SDG_SOLVER_GMRES, sdg.SDG_PREC_F64, 1e-10, 5000, 30, 5, 10, 1e-4, pc)
+    optsg.flags = sdg.SDG_SOLVE_GRAPH
+    ctx.step(v, s, amp_at(step0 + args.warmup), opts=optsg)  # records the graphs
+    v.copy_(v_save)
+    s.copy_(s_save)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    itg = 0
+    for k in range(args.steps):
+        info = ctx.step(v, s, amp_at(step0 + args.warmup + k), opts=optsg)
+        itg += info["iterations"]
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    errg = float((v - v64).norm() / max(float(v64.norm()), 1e-300))
+    log(f"FP64 graph: {args.steps} steps in {tg:.3f}s, {itg / args.steps:.1f} it/step (full cycles), "
+        f"rel diff to FP64 {errg:.2e}")
+
     # ---- operator apply timing (HIP events on the launch stream)
     x = torch.randn(n, dtype=torch.float64, device=dev)
     y = torch.empty_like(x)
@@ -218,8 +405,11 @@ def main():
         "config": {"workload": "2D 64x64 jittered split square (8192 tris), p=3, p_gamma=3, layered "
                                "lognormal media, 10 Hz Ricker source, dt=2.5e-3, GMRES(30) to 1e-10",
                    "n_elem": n_elem, "velocity_dofs_per_slab": n, "parallelism": "single GPU"},
-        "s_per_step": {"fp64": t64 / args.steps, "fp32_operator_fp64_refinement": t32 / args.steps},
-        "iterations_per_step": {"fp64": iters / args.steps, "fp32_ir_inner": it32 / args.steps},
+        "s_per_step": {"fp64": t64 / args.steps, "fp32_operator_fp64_refinement": t32 / args.steps,
+                       "fp64_hip_graph": tg / args.steps},
+        "iterations_per_step": {"fp64": iters / args.steps, "fp32_ir_inner": it32 / args.steps,
+                                "fp64_hip_graph": itg / args.steps},
+        "fp64_hip_graph_rel_diff_vs_fp64": errg,
         "matvec_kernel": {"fp64_us": ta64 * 1e6, "fp64_gdofs": n / ta64 / 1e9,
                           "fp32_us": ta32 * 1e6, "fp32_gdofs": n / ta32 / 1e9},
         "fp32_ir_rel_diff_vs_fp64": err32,
@@ -229,6 +419,11 @@ def main():
                      "bytes_per_launch": balg64},
         "cpu_baseline": cpu,
     }
+    ctx.close()
+    if not args.no_extras:
+        out["batched_64_sources"] = bench_batched(args, t64 / args.steps)
+        out["mesh_batch_16"] = bench_mesh_batch(args)
+        out["operator_3d"] = bench_3d_operator(args)
     print(json.dumps(out), flush=True)
     ctx.close()
 

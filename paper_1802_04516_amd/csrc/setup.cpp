@@ -15,6 +15,7 @@
 #include <thread>
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -130,6 +131,10 @@ Rule simplex_rule(const double* V, int k, int d, int deg) {
 template <class F>
 void parallel_for(int64_t n, F&& fn) {
   unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  if (const char* omp = std::getenv("OMP_NUM_THREADS")) {
+    const int k = std::atoi(omp);
+    if (k > 0) nt = std::min(nt, (unsigned)k);
+  }
   if (n < 256) nt = 1;
   std::atomic<int64_t> next{0};
   auto worker = [&]() {
