@@ -66,6 +66,72 @@ def cpu_baseline(seconds=10.0):
                       f"{slab.nv} DOF, nnz {S.nnz}) version of the workload recipe, {reps} applies in {dt:.1f}s"}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_traffic.json")
+
+
+def kernel_source_hash():
+    """Hash of the operator kernel sources the traffic counters describe."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("op_kernels.inc", "shapes.hpp"):
+        with open(os.path.join(ROOT, "paper_1802_04516_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, variant):
+    """HBM bytes per operator apply (face + element kernel) from the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded in profiles/, scaled by
+    the same counters' readings for a plain copy; None when the kernels have
+    changed since the counters were taken or no record exists."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    wl = rec.get(workload, {})
+    v = wl.get("variants", {}).get(str(variant))
+    e = wl.get("elem")
+    if v is None or e is None:
+        return None
+    ff, wf = rec["copy_calibration"]["fetch_factor"], rec["copy_calibration"]["write_factor"]
+    kib = (v["fetch_kib"] + e["fetch_kib"]) * ff + (v["write_kib"] + e["write_kib"]) * wf
+    return kib * 1024.0
+
+
+def apply_probe(args):
+    """Operator applies only (for counter runs under rocprofv3)."""
+    import torch
+
+    import paper_1802_04516_amd as sdg
+    import synth
+    if args.variant >= 0:
+        os.environ["SDG_OP_VARIANT"] = str(args.variant)
+    w = synth.workload(args.workload)
+    m = w["mesh"]
+    sch = sdg.SDG_SCHEME_CN if w["scheme"] == "cn" else sdg.SDG_SCHEME_STDG
+    prec = sdg.SDG_PREC_F64 if args.prec == "f64" else sdg.SDG_PREC_F32
+    ctx = sdg.Context(0)
+    sz = ctx.setup(m.xyz, m.elem, m.period, w["p"], w["p_gamma"], sch, w["dt"], w["lam"], w["mu"], w["rho"], prec)
+    n = sz["n_vel_slab"]
+    x = torch.randn(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    ctx.apply(x, y, prec)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.reps):
+        ctx.apply(x, y, prec)
+    e1.record()
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / args.reps
+    print(json.dumps({"workload": args.workload, "variant": sz["op_variant"] if prec == sdg.SDG_PREC_F64
+                      else sz["op_variant_f32"], "precision": args.prec, "apply_us": t * 1e6}), flush=True)
+    ctx.close()
+
+
 def _solve_opts(sdg, precision, pc, flags=0, solver=None):
     o = sdg.SolveOpts(solver if solver is not None else sdg.SDG_SOLVER_AUTO, precision, 1e-10, 5000, 30, 5, 10,
                       1e-4, pc)
@@ -205,7 +271,7 @@ def bench_3d_operator(args):
     sizes = ctx.setup(mesh.xyz, mesh.elem, mesh.period, 2, 0, sdg.SDG_SCHEME_CN, w["dt"], w["lam"], w["mu"],
                       w["rho"], sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32)
     log(f"3D setup {time.time() - t0:.1f}s: {sizes['n_elem']} tets, operator {sizes['op_bytes_f64'] / 1e9:.2f} GB; "
-        f"autotune f64 {sizes['tune_us_f64']} -> {sizes['op_variant']}")
+        f"autotune f64 {[round(x, 1) for x in sizes['tune_us_f64']]} -> {sizes['op_variant']}")
     n = sizes["n_vel_slab"]
     x = torch.randn(n, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
@@ -242,6 +308,12 @@ def main():
     ap.add_argument("--precond", default="block", choices=["none", "mass", "block"])
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (64 sources), mesh-batch (16 meshes) and 3D operator measurements")
+    ap.add_argument("--apply-probe", action="store_true",
+                    help="only run --reps operator applies of --workload (c2 or c3) with face-kernel --variant "
+                         "(-1: autotuned) in --prec, for rocprofv3 counter runs")
+    ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB x 10 (scale for the rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -267,6 +339,9 @@ def main():
         print(json.dumps({"copy_bytes_read_per_launch": nbytes, "copy_bytes_written_per_launch": nbytes,
                           "launches": 10}), flush=True)
         return
+    if args.apply_probe:
+        apply_probe(args)
+        return
     w = synth.workload(args.workload)
     mesh = w["mesh"]
     scheme = sdg.SDG_SCHEME_CN if w["scheme"] == "cn" else sdg.SDG_SCHEME_STDG
@@ -277,8 +352,8 @@ def main():
                       sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND)
     log(f"setup {time.time() - t0:.1f}s: {sizes['n_elem']} elems, {sizes['n_face']} faces, "
         f"{sizes['n_vel_slab']} velocity DOFs, operator {sizes['op_bytes_f64'] / 1e6:.1f} MB")
-    log(f"face-kernel autotune (us/apply, variants 0/1/2): f64 {sizes['tune_us_f64']} -> {sizes['op_variant']}, "
-        f"f32 {sizes['tune_us_f32']} -> {sizes['op_variant_f32']}")
+    log(f"face-kernel autotune (us/apply, variants 0..6): f64 {[round(x, 1) for x in sizes['tune_us_f64']]} -> {sizes['op_variant']}, "
+        f"f32 {[round(x, 1) for x in sizes['tune_us_f32']]} -> {sizes['op_variant_f32']}")
     src = w["sources"]
     if src is not None:
         ctx.set_sources(src["pos"], src["dir"])
@@ -414,8 +489,10 @@ def main():
                           "fp32_us": ta32 * 1e6, "fp32_gdofs": n / ta32 / 1e9},
         "fp32_ir_rel_diff_vs_fp64": err32,
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "velocity operator apply (face_kernel + elem_kernel), FP64",
+                     "frac": ach / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("c2", sizes["op_variant"]),
+                     "kernel": f"velocity operator apply (face kernel variant {sizes['op_variant']} + element "
+                               f"kernel), FP64",
                      "bytes_per_launch": balg64},
         "cpu_baseline": cpu,
     }

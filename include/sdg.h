@@ -111,8 +111,8 @@ typedef struct {
   int32_t op_variant;     /* face-kernel variant in use for FP64 (see sdg_set_operator_variant) */
   int32_t op_variant_f32;
   int32_t pad;
-  double tune_us_f64[3];  /* autotuner timings of the variants (microseconds per apply) */
-  double tune_us_f32[3];
+  double tune_us_f64[8];  /* autotuner timings of the variants (microseconds per apply) */
+  double tune_us_f32[8];
 } sdg_sizes;
 
 typedef struct {
@@ -196,12 +196,16 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs);
 
 int sdg_query(const sdg_ctx* ctx, sdg_sizes* out);
 
-/* Face-kernel variant of the operator apply: 0 = LDS kernel with flat
- * loops, 1 = register-tiled kernel with the most faces per workgroup that
- * fit in 64 KiB of LDS, 2 = register-tiled with half as many; -1 reruns the
- * autotuner (sdg_assemble runs it: every variant is timed on the assembled
- * operator and the fastest kept, per precision).  All variants compute the
- * same operator. */
+/* Face-kernel variant (tile shape) of the operator apply: 0 = LDS kernel
+ * with flat loops, 1 = register-tiled kernel with the most faces per
+ * workgroup that fit in 64 KiB of LDS, 2 = register-tiled with half as many,
+ * 3 = column-parallel kernel (one thread per face and stress column, at
+ * most 256/(d N_psi) faces per workgroup within 64 KiB of LDS), 4 = the
+ * same with half as many faces, 5 and 6 = column-parallel kernels that read
+ * the blocks from HBM straight into registers (about 256/(d N_psi) faces
+ * per workgroup, or twice as many); -1 reruns the autotuner (sdg_assemble runs it: every variant is
+ * timed on the assembled operator and the fastest kept, per precision).  All
+ * variants compute the same operator. */
 int sdg_set_operator_variant(sdg_ctx* ctx, int variant);
 
 /* Face table in the library's face order (host arrays of n_face entries):

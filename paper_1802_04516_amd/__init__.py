@@ -56,7 +56,7 @@ class Sizes(ctypes.Structure):
                 ("dt", ctypes.c_double), ("tau", ctypes.c_double * 8), ("op_bytes_f64", ctypes.c_int64),
                 ("op_bytes_f32", ctypes.c_int64), ("max_rhs", ctypes.c_int32), ("op_variant", ctypes.c_int32),
                 ("op_variant_f32", ctypes.c_int32), ("pad", ctypes.c_int32),
-                ("tune_us_f64", ctypes.c_double * 3), ("tune_us_f32", ctypes.c_double * 3)]
+                ("tune_us_f64", ctypes.c_double * 8), ("tune_us_f32", ctypes.c_double * 8)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -212,8 +212,8 @@ def sdg_query(h) -> dict:
     _check(lib().sdg_query(h, ctypes.byref(s)))
     out = {f: getattr(s, f) for f, _ in Sizes._fields_ if f not in ("tau", "pad", "tune_us_f64", "tune_us_f32")}
     out["tau"] = [s.tau[a] for a in range(s.n_gamma)]
-    out["tune_us_f64"] = list(s.tune_us_f64)
-    out["tune_us_f32"] = list(s.tune_us_f32)
+    out["tune_us_f64"] = [x for x in s.tune_us_f64][:7]
+    out["tune_us_f32"] = [x for x in s.tune_us_f32][:7]
     return out
 
 
@@ -364,7 +364,7 @@ class Context:
         sdg_apply_adjoint(self.h, w, y, n_rhs, precision, stream)
 
     def set_operator_variant(self, variant):
-        """0/1/2 pins a face-kernel variant, -1 reruns the autotuner."""
+        """0..6 pins a face-kernel variant, -1 reruns the autotuner."""
         sdg_set_operator_variant(self.h, variant)
         self.sizes = sdg_query(self.h)
         return self.sizes

@@ -134,7 +134,7 @@ static void autotune(Ctx& c) {
     if (!(c.precisions & prec)) continue;
     int best = 0;
     double best_t = 1e30;
-    for (int var = 0; var <= 2; ++var) {
+    for (int var = 0; var < kNumVariants; ++var) {
       if (pi == 0) c.variant64 = var; else c.variant32 = var;
       for (int w = 0; w < 3; ++w) apply_op(c, c.d_x.p, c.d_r.p, prec, false, s);
       SDG_HIP(hipEventRecord(e0, s));
@@ -620,7 +620,7 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     c.assembled = true;
     const char* forced = std::getenv("SDG_OP_VARIANT");
     if (forced) {
-      c.variant64 = c.variant32 = std::max(0, std::min(2, std::atoi(forced)));
+      c.variant64 = c.variant32 = std::max(0, std::min(kNumVariants - 1, std::atoi(forced)));
     } else {
       autotune(c);
     }
@@ -631,7 +631,7 @@ int sdg_set_operator_variant(sdg_ctx* ctx, int variant) {
   return guard([&] {
     Ctx& c = ctx_of(ctx);
     require(c.assembled, SDG_ESTATE, "assemble first");
-    require(variant >= -1 && variant <= 2, SDG_EINVAL, "variant must be -1 (autotune), 0, 1 or 2");
+    require(variant >= -1 && variant < kNumVariants, SDG_EINVAL, "variant must be -1 (autotune) or 0..6");
     SDG_HIP(hipSetDevice(c.device));
     c.graphs.clear();
     if (variant < 0) autotune(c);
@@ -671,7 +671,7 @@ int sdg_query(const sdg_ctx* ctx, sdg_sizes* out) {
     out->max_rhs = c.max_rhs;
     out->op_variant = c.variant64;
     out->op_variant_f32 = c.variant32;
-    for (int v = 0; v < 3; ++v) { out->tune_us_f64[v] = c.tune_us[0][v]; out->tune_us_f32[v] = c.tune_us[1][v]; }
+    for (int v = 0; v < kNumVariants; ++v) { out->tune_us_f64[v] = c.tune_us[0][v]; out->tune_us_f32[v] = c.tune_us[1][v]; }
   });
 }
 

@@ -121,7 +121,7 @@ struct Ctx {
   DevBuf<double> d_z;  // element face slots
   Coefs op{}, adj{};   // operator and its transpose
   int variant64 = 0, variant32 = 0;   // face-kernel variant per precision (autotuned)
-  double tune_us[2][3] = {{0}};       // measured apply times [prec][variant]
+  double tune_us[2][8] = {{0}};  // measured apply times [prec][variant]
   // preconditioners: mass block-Jacobi (reference mass inverse, 1/(rho|J|),
   // T^-1) and the element diagonal-block inverses of eq. (pre1) in FP32,
   // column-major per element

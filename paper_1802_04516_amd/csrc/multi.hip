@@ -206,45 +206,53 @@ __device__ inline int block_count(int flag, int* sh) {
 }
 
 // Norm of w per system, Hessenberg column j, Givens rotations, residual
-// estimate, convergence flag; one thread per system.
-__global__ void km_arnoldi_fin(const double* partials, int nblocks, const int* seg_blk0, int S, int j,
-                               SysScalars* ss, int* nactive) {
-  __shared__ int sh[16];
-  const int s = threadIdx.x;
-  int act = 0;
-  if (s < S && ss[s].active) {
-    SysScalars& q = ss[s];
-    double tot = 0.0;
-    for (int b = seg_blk0[s]; b < seg_blk0[s + 1]; ++b) tot += partials[b];
-    const int ld = kMaxRestart + 1;
-    double* Hc = q.H + (size_t)j * ld;
-    for (int i = 0; i <= j; ++i) Hc[i] = q.h1[i] + q.h2[i];
-    const double nrm = sqrt(tot);
-    Hc[j + 1] = nrm;
-    q.norm = nrm;
-    q.inv_norm = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    for (int i = 0; i < j; ++i) {
-      const double a = Hc[i], b = Hc[i + 1];
-      Hc[i] = q.cs[i] * a + q.sn[i] * b;
-      Hc[i + 1] = -q.sn[i] * a + q.cs[i] * b;
+// estimate, convergence flag.  One workgroup of 1024 threads: wavefront w
+// handles systems w, w+16, ...; its lanes add the system's block partials
+// (fixed order), lane 0 updates the system's scalars; then the workgroup
+// counts the active systems.
+__global__ __launch_bounds__(1024) void km_arnoldi_fin(const double* partials, int nblocks, const int* seg_blk0,
+                                                       int S, int j, SysScalars* ss, int* nactive) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int s = wv; s < S; s += nw) {
+    if (!ss[s].active) continue;
+    double v = 0.0;
+    for (int b = seg_blk0[s] + lane; b < seg_blk0[s + 1]; b += 64) v += partials[b];
+    const double tot = wsum64(v);
+    if (lane == 0) {
+      SysScalars& q = ss[s];
+      const int ld = kMaxRestart + 1;
+      double* Hc = q.H + (size_t)j * ld;
+      for (int i = 0; i <= j; ++i) Hc[i] = q.h1[i] + q.h2[i];
+      const double nrm = sqrt(tot);
+      Hc[j + 1] = nrm;
+      q.norm = nrm;
+      q.inv_norm = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      for (int i = 0; i < j; ++i) {
+        const double a = Hc[i], b = Hc[i + 1];
+        Hc[i] = q.cs[i] * a + q.sn[i] * b;
+        Hc[i + 1] = -q.sn[i] * a + q.cs[i] * b;
+      }
+      const double a = Hc[j], b = Hc[j + 1];
+      const double rad = hypot(a, b);
+      const double c = rad > 0.0 ? a / rad : 1.0, sn = rad > 0.0 ? b / rad : 0.0;
+      q.cs[j] = c;
+      q.sn[j] = sn;
+      Hc[j] = rad;
+      Hc[j + 1] = 0.0;
+      const double gj = q.g[j];
+      q.g[j] = c * gj;
+      q.g[j + 1] = -sn * gj;
+      q.resid = fabs(q.g[j + 1]);
+      q.k = j + 1;
+      if (q.resid <= q.tol_abs || nrm == 0.0) q.active = 0;
+      atomicAdd(&cnt, q.active);  // integer count in LDS: order-independent
     }
-    const double a = Hc[j], b = Hc[j + 1];
-    const double rad = hypot(a, b);
-    const double c = rad > 0.0 ? a / rad : 1.0, sn = rad > 0.0 ? b / rad : 0.0;
-    q.cs[j] = c;
-    q.sn[j] = sn;
-    Hc[j] = rad;
-    Hc[j + 1] = 0.0;
-    const double gj = q.g[j];
-    q.g[j] = c * gj;
-    q.g[j + 1] = -sn * gj;
-    q.resid = fabs(q.g[j + 1]);
-    q.k = j + 1;
-    if (q.resid <= q.tol_abs || nrm == 0.0) q.active = 0;
-    act = q.active;
   }
-  const int n = block_count(act, sh);
-  if (threadIdx.x == 0) *nactive = n;
+  __syncthreads();
+  if (threadIdx.x == 0) *nactive = cnt;
 }
 
 // Start of a cycle from the per-system r.r in ss.dot.
@@ -466,7 +474,7 @@ int multi_cycle(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hip
     launch_m(Op::Pass, j + 1, bm, s, n, V, w, ss, m.d_partials.p);
     finalize(m, j + 1, kH2, 0, s);
     launch_m(Op::Final, j + 1, bm, s, n, V, w, ss, m.d_partials.p);
-    km_arnoldi_fin<<<1, st, 0, s>>>(m.d_partials.p, m.n_blocks, m.d_seg_blk0.p, m.S, j, ss, m.d_nactive.p);
+    km_arnoldi_fin<<<1, 1024, 0, s>>>(m.d_partials.p, m.n_blocks, m.d_seg_blk0.p, m.S, j, ss, m.d_nactive.p);
     SDG_HIP(hipGetLastError());
     km_scale<<<(unsigned)m.n_blocks, kT, 0, s>>>(bm, w, V + (size_t)(j + 1) * n, ss, 1);
     SDG_HIP(hipGetLastError());

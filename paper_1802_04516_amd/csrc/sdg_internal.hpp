@@ -34,6 +34,7 @@ inline void require(bool ok, int code, const std::string& msg) {
 
 // ---------------------------------------------------------------- sizes
 
+constexpr int kNumVariants = 7;
 constexpr int kMaxGamma = 4;   // N_gamma <= 4 (p_gamma <= 3)
 constexpr int kMaxRhs = 64;
 
@@ -124,7 +125,9 @@ struct OpArgs {
   int v_spatial;           // element kernel: v has no time axis (mass applied with Tm[:,0])
   double y_scale;          // element kernel: y = y_scale * (...) (reserved, 1.0)
   int variant;             // operator face kernel: 0 = LDS flat loops, 1 = register-tiled
-                           // with the most faces per block, 2 = register-tiled, half of it
+                           // with the most faces per block, 2 = register-tiled, half of it,
+                           // 3 = column-parallel (most faces that fit), 4 = half of it,
+                           // 5, 6 = column-parallel reading blocks from HBM into registers
   // Several independent columns (right-hand sides) of the same mesh: the
   // launch grid's y index is the column and every per-column array is offset
   // by column * its stride (0 = shared by all columns).

@@ -209,45 +209,57 @@ __global__ void k_block_apply(int64_t n_elem, int nv, const float* __restrict__ 
 
 // Factored element block inverse (several time nodes):
 //   y_e = (I (x) Q_e) blockdiag_i(B_{e,i}) (I (x) Q_e^T) x_e
-// (B^T for the transpose).  nv = ng*ns threads per element, several elements
-// per workgroup; x, u and w of an element are staged in LDS.
-__global__ __launch_bounds__(256) void k_block_apply_fact(int64_t n_elem, int ng, int ns, const float* __restrict__ Q,
+// (B^T for the transpose).  NV = NG*NS threads per element, several elements
+// per workgroup; x, u and w of an element are staged in LDS.  The sizes are
+// compile-time so that every loop unrolls and its loads are in flight
+// together.
+template <int NG, int NS>
+__global__ __launch_bounds__(256) void k_block_apply_fact(int64_t n_elem, const float* __restrict__ Q,
                                                           const float* __restrict__ B, const double* __restrict__ x,
                                                           double* __restrict__ y, int transpose, int64_t cstride) {
-  extern __shared__ double sm[];
+  constexpr int NV = NG * NS;
+  constexpr int EPB = 256 / NV;
+  __shared__ double sm[EPB * 2 * NV];
   x += blockIdx.y * cstride;
   y += blockIdx.y * cstride;
-  const int nv = ng * ns;
-  const int epb = blockDim.x / nv;
-  const int le = threadIdx.x / nv, r = threadIdx.x % nv;
-  const int a = r / ns, i = r % ns;
-  double* sx = sm + (size_t)min(le, epb - 1) * 2 * nv;
-  double* su = sx + nv;
-  for (int64_t e0 = (int64_t)blockIdx.x * epb; e0 < n_elem; e0 += (int64_t)gridDim.x * epb) {
+  const int le = threadIdx.x / NV, r = threadIdx.x % NV;
+  const int a = r / NS, i = r % NS;
+  double* sx = sm + (size_t)min(le, EPB - 1) * 2 * NV;
+  double* su = sx + NV;
+  for (int64_t e0 = (int64_t)blockIdx.x * EPB; e0 < n_elem; e0 += (int64_t)gridDim.x * EPB) {
     const int64_t e = e0 + le;
-    const bool act = le < epb && e < n_elem;
-    const float* Qe = Q + (size_t)(act ? e : 0) * ns * ns;
-    if (act) sx[r] = x[e * nv + r];
+    const bool act = le < EPB && e < n_elem;
+    const float* Qe = Q + (size_t)(act ? e : 0) * NS * NS;
+    if (act) sx[r] = x[e * NV + r];
     __syncthreads();
     if (act) {  // u[a][i] = sum_ck Q[ck][i] x[a][ck]
+      float qc[NS];
+#pragma unroll
+      for (int ck = 0; ck < NS; ++ck) qc[ck] = Qe[ck * NS + i];
       double acc = 0.0;
-      for (int ck = 0; ck < ns; ++ck) acc += (double)Qe[ck * ns + i] * sx[a * ns + ck];
+#pragma unroll
+      for (int ck = 0; ck < NS; ++ck) acc += (double)qc[ck] * sx[a * NS + ck];
       su[r] = acc;
     }
     __syncthreads();
     double wv = 0.0;
     if (act) {  // w[a][i] = sum_b B_i[a][b] u[b][i]
-      const float* Be = B + ((size_t)e * ns + i) * ng * ng;
-      for (int b = 0; b < ng; ++b) wv += (double)(transpose ? Be[b * ng + a] : Be[a * ng + b]) * su[b * ns + i];
+      const float* Be = B + ((size_t)e * NS + i) * NG * NG;
+#pragma unroll
+      for (int b = 0; b < NG; ++b) wv += (double)(transpose ? Be[b * NG + a] : Be[a * NG + b]) * su[b * NS + i];
     }
     __syncthreads();
     if (act) sx[r] = wv;
     __syncthreads();
     if (act) {  // y[a][ck] = sum_i Q[ck][i] w[a][i], here i plays ck
+      const float* Qr = Qe + (size_t)i * NS;
+      float qr[NS];
+#pragma unroll
+      for (int ii = 0; ii < NS; ++ii) qr[ii] = Qr[ii];
       double acc = 0.0;
-      const float* Qr = Qe + (size_t)i * ns;
-      for (int ii = 0; ii < ns; ++ii) acc += (double)Qr[ii] * sx[a * ns + ii];
-      y[e * nv + r] = acc;
+#pragma unroll
+      for (int ii = 0; ii < NS; ++ii) acc += (double)qr[ii] * sx[a * NS + ii];
+      y[e * NV + r] = acc;
     }
     __syncthreads();
   }
@@ -542,14 +554,21 @@ void launch_block_apply(int64_t n_elem, int nv, const float* P, const double* x,
 
 void launch_block_apply_fact(int64_t n_elem, int ng, int ns, const float* Q, const float* B, const double* x,
                              double* y, bool transpose, hipStream_t s, int ncols, int64_t cstride) {
-  const int nv = ng * ns;
-  require(nv <= 256, SDG_EUNSUPPORTED, "element block too large for the factored preconditioner kernel");
-  const int epb = 256 / nv;
-  const int64_t groups = (n_elem + epb - 1) / epb;
-  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 65535));
-  k_block_apply_fact<<<dim3(g, (unsigned)std::max(1, ncols)), epb * nv, (size_t)epb * 2 * nv * sizeof(double), s>>>(
-      n_elem, ng, ns, Q, B, x, y, transpose ? 1 : 0, cstride);
-  check_launch();
+  const unsigned gy = (unsigned)std::max(1, ncols);
+  auto go = [&](auto kernel, int nv) {
+    const int epb = 256 / nv;
+    const int64_t groups = (n_elem + epb - 1) / epb;
+    const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 65535));
+    kernel<<<dim3(g, gy), epb * nv, 0, s>>>(n_elem, Q, B, x, y, transpose ? 1 : 0, cstride);
+  };
+#define SDG_FACT(NG_, NS_) \
+  if (ng == NG_ && ns == NS_) { go(k_block_apply_fact<NG_, NS_>, NG_ * NS_); check_launch(); return; }
+#define SDG_FACT_NS(NS_) SDG_FACT(2, NS_) SDG_FACT(3, NS_) SDG_FACT(4, NS_)
+  // d N_phi for 2D p = 1..4 and 3D p = 1..3
+  SDG_FACT_NS(6) SDG_FACT_NS(12) SDG_FACT_NS(20) SDG_FACT_NS(30) SDG_FACT_NS(60)
+#undef SDG_FACT_NS
+#undef SDG_FACT
+  throw Error(SDG_EUNSUPPORTED, "no factored block-preconditioner kernel for this element size");
 }
 
 // ---------------------------------------------------------------- CG
