@@ -110,9 +110,10 @@ typedef struct {
   int32_t max_rhs;        /* largest n_rhs accepted by the apply calls */
   int32_t op_variant;     /* face-kernel variant in use for FP64 (see sdg_set_operator_variant) */
   int32_t op_variant_f32;
-  int32_t pad;
+  int32_t op_bvariant;    /* batched FP64 apply (see sdg_set_batched_variant) */
   double tune_us_f64[8];  /* autotuner timings of the variants (microseconds per apply) */
   double tune_us_f32[8];
+  double tune_us_batched[3]; /* batched applies of max_rhs columns per batched variant */
 } sdg_sizes;
 
 typedef struct {
@@ -207,6 +208,15 @@ int sdg_query(const sdg_ctx* ctx, sdg_sizes* out);
  * timed on the assembled operator and the fastest kept, per precision).  All
  * variants compute the same operator. */
 int sdg_set_operator_variant(sdg_ctx* ctx, int variant);
+
+/* Kernel of the batched FP64 operator apply (n_rhs > 1): 0 = the face
+ * kernel variant above launched once per column (column grid), 1 and 2 =
+ * the matrix-core kernel (v_mfma_f64_16x16x4: the face gradient and the
+ * scatter of each face become GEMMs over the columns) with 8 or 16 columns
+ * per workgroup.  sdg_assemble picks the fastest for max_rhs columns when
+ * max_rhs > 1; shapes the matrix-core kernel does not cover (N_gamma d not
+ * dividing 16, or N_phi > 16) use the column grid whatever is set. */
+int sdg_set_batched_variant(sdg_ctx* ctx, int bvariant);
 
 /* Face table in the library's face order (host arrays of n_face entries):
  * left element, its local face, right element (-1 on the boundary), its

@@ -34,7 +34,7 @@ _ERRNAMES = {SDG_EINVAL: "EINVAL", SDG_ENOMEM: "ENOMEM", SDG_EDEVICE: "EDEVICE",
              SDG_ESTATE: "ESTATE"}
 
 EXPORTED = ("sdg_last_error", "sdg_create", "sdg_destroy", "sdg_set_mesh", "sdg_set_discretization",
-            "sdg_set_material", "sdg_assemble", "sdg_query", "sdg_set_operator_variant", "sdg_face_table",
+            "sdg_set_material", "sdg_assemble", "sdg_query", "sdg_set_operator_variant", "sdg_set_batched_variant", "sdg_face_table",
             "sdg_apply_velocity_operator", "sdg_apply_adjoint", "sdg_set_sources", "sdg_solve_step",
             "sdg_energy", "sdg_sample_velocity", "sdg_eval_stress", "sdg_adjoint_step",
             "sdg_sample_velocity_adjoint", "sdg_set_mesh_batch", "sdg_set_mesh_sources")
@@ -55,8 +55,9 @@ class Sizes(ctypes.Structure):
                 ("n_stress_state", ctypes.c_int64), ("n_stress_slab", ctypes.c_int64),
                 ("dt", ctypes.c_double), ("tau", ctypes.c_double * 8), ("op_bytes_f64", ctypes.c_int64),
                 ("op_bytes_f32", ctypes.c_int64), ("max_rhs", ctypes.c_int32), ("op_variant", ctypes.c_int32),
-                ("op_variant_f32", ctypes.c_int32), ("pad", ctypes.c_int32),
-                ("tune_us_f64", ctypes.c_double * 8), ("tune_us_f32", ctypes.c_double * 8)]
+                ("op_variant_f32", ctypes.c_int32), ("op_bvariant", ctypes.c_int32),
+                ("tune_us_f64", ctypes.c_double * 8), ("tune_us_f32", ctypes.c_double * 8),
+                ("tune_us_batched", ctypes.c_double * 3)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -97,6 +98,7 @@ def lib():
         "sdg_assemble": ([_P, ctypes.c_uint, i], i),
         "sdg_query": ([_P, ctypes.POINTER(Sizes)], i),
         "sdg_set_operator_variant": ([_P, i], i),
+        "sdg_set_batched_variant": ([_P, i], i),
         "sdg_face_table": ([_P, _I64P, _I32P, _I64P, _I32P], i),
         "sdg_apply_velocity_operator": ([_P, _P, _P, i, i, _P], i),
         "sdg_apply_adjoint": ([_P, _P, _P, i, i, _P], i),
@@ -210,10 +212,12 @@ def sdg_assemble(h, precisions=SDG_PREC_F64 | SDG_PREC_F32, max_rhs=1):
 def sdg_query(h) -> dict:
     s = Sizes()
     _check(lib().sdg_query(h, ctypes.byref(s)))
-    out = {f: getattr(s, f) for f, _ in Sizes._fields_ if f not in ("tau", "pad", "tune_us_f64", "tune_us_f32")}
+    out = {f: getattr(s, f) for f, _ in Sizes._fields_
+           if f not in ("tau", "tune_us_f64", "tune_us_f32", "tune_us_batched")}
     out["tau"] = [s.tau[a] for a in range(s.n_gamma)]
     out["tune_us_f64"] = [x for x in s.tune_us_f64][:7]
     out["tune_us_f32"] = [x for x in s.tune_us_f32][:7]
+    out["tune_us_batched"] = list(s.tune_us_batched)
     return out
 
 
@@ -366,6 +370,12 @@ class Context:
     def set_operator_variant(self, variant):
         """0..6 pins a face-kernel variant, -1 reruns the autotuner."""
         sdg_set_operator_variant(self.h, variant)
+        self.sizes = sdg_query(self.h)
+        return self.sizes
+
+    def set_batched_variant(self, bvariant):
+        """0: column grid, 1/2: matrix-core kernel with 8/16 columns per workgroup."""
+        _check(lib().sdg_set_batched_variant(self.h, bvariant))
         self.sizes = sdg_query(self.h)
         return self.sizes
 

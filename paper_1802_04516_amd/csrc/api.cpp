@@ -113,6 +113,7 @@ void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipS
   a.use_g = 1;
   a.c = transpose ? c.adj : c.op;
   a.n_cols = ncols;
+  a.bvariant = c.bvariant;
   a.cs_v = a.cs_y = c.n_slab;
   a.cs_z = c.z_col;
   launch_face(c.hs.dim, c.hs.p, c.hs.ng, prec, kScatter, a, s);
@@ -149,6 +150,28 @@ static void autotune(Ctx& c) {
       if (us < best_t) { best_t = us; best = var; }
     }
     if (pi == 0) c.variant64 = best; else c.variant32 = best;
+  }
+  // batched FP64 applies: column grid against the matrix-core tile widths
+  c.bvariant = 0;
+  if (c.max_rhs > 1 && (c.precisions & SDG_PREC_F64)) {
+    const int R = c.max_rhs;
+    vec_fill(c.n_slab * R, 1.0, c.d_x.p, s);
+    int best = 0;
+    double best_t = 1e30;
+    for (int bv = 0; bv < 3; ++bv) {
+      c.bvariant = bv;
+      apply_op(c, c.d_x.p, c.d_r.p, SDG_PREC_F64, false, s, R);
+      SDG_HIP(hipEventRecord(e0, s));
+      const int reps = 3;
+      for (int w = 0; w < reps; ++w) apply_op(c, c.d_x.p, c.d_r.p, SDG_PREC_F64, false, s, R);
+      SDG_HIP(hipEventRecord(e1, s));
+      SDG_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      SDG_HIP(hipEventElapsedTime(&ms, e0, e1));
+      c.tune_b_us[bv] = 1e3 * ms / reps;
+      if (c.tune_b_us[bv] < best_t) { best_t = c.tune_b_us[bv]; best = bv; }
+    }
+    c.bvariant = best;
   }
   SDG_HIP(hipEventDestroy(e0));
   SDG_HIP(hipEventDestroy(e1));
@@ -639,6 +662,16 @@ int sdg_set_operator_variant(sdg_ctx* ctx, int variant) {
   });
 }
 
+int sdg_set_batched_variant(sdg_ctx* ctx, int bvariant) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.assembled, SDG_ESTATE, "assemble first");
+    require(bvariant >= 0 && bvariant <= 2, SDG_EINVAL, "batched variant must be 0, 1 or 2");
+    c.graphs.clear();
+    c.bvariant = bvariant;
+  });
+}
+
 int sdg_query(const sdg_ctx* ctx, sdg_sizes* out) {
   return guard([&] {
     require(ctx && out, SDG_EINVAL, "null argument");
@@ -671,6 +704,8 @@ int sdg_query(const sdg_ctx* ctx, sdg_sizes* out) {
     out->max_rhs = c.max_rhs;
     out->op_variant = c.variant64;
     out->op_variant_f32 = c.variant32;
+    out->op_bvariant = c.bvariant;
+    for (int v = 0; v < 3; ++v) out->tune_us_batched[v] = c.tune_b_us[v];
     for (int v = 0; v < kNumVariants; ++v) { out->tune_us_f64[v] = c.tune_us[0][v]; out->tune_us_f32[v] = c.tune_us[1][v]; }
   });
 }

@@ -122,6 +122,8 @@ struct Ctx {
   Coefs op{}, adj{};   // operator and its transpose
   int variant64 = 0, variant32 = 0;   // face-kernel variant per precision (autotuned)
   double tune_us[2][8] = {{0}};  // measured apply times [prec][variant]
+  int bvariant = 0;              // batched FP64 apply: 0 column grid, 1/2 matrix-core kernel
+  double tune_b_us[3] = {0};     // measured batched applies (max_rhs columns) per bvariant
   // preconditioners: mass block-Jacobi (reference mass inverse, 1/(rho|J|),
   // T^-1) and the element diagonal-block inverses of eq. (pre1) in FP32,
   // column-major per element
