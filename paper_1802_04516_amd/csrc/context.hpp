@@ -25,6 +25,8 @@ struct DevScalars {
   double h1[kMaxRestart + 1], h2[kMaxRestart + 1];
   double y[kMaxRestart];
   double dots[kRedSlots];
+  double reorth;        // 1 when the current Arnoldi step needs a second projection
+  double n_reorth;      // count of second projections (diagnostics)
 };
 
 // Scalars of one system of a multi-system Krylov solve.

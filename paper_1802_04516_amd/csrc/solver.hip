@@ -294,14 +294,15 @@ __device__ inline void block_partials(const double (&acc)[NJ], double* sh, doubl
   }
 }
 
-// h1[i] = V_i . w for i < NJ (classical Gram-Schmidt projections)
+// h1[i] = V_i . w for i < NJ (classical Gram-Schmidt projections) and, in
+// slot NJ, w . w
 template <int NJ>
 __global__ __launch_bounds__(256) void k_multidot(int64_t n, const double* __restrict__ V,
                                                   const double* __restrict__ w, double* partials) {
-  __shared__ double sh[4 * NJ];
-  double acc[NJ];
+  __shared__ double sh[4 * (NJ + 1)];
+  double acc[NJ + 1];
 #pragma unroll
-  for (int i = 0; i < NJ; ++i) acc[i] = 0.0;
+  for (int i = 0; i <= NJ; ++i) acc[i] = 0.0;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
     const double wt = w[t];
     double vi[NJ];
@@ -309,37 +310,58 @@ __global__ __launch_bounds__(256) void k_multidot(int64_t n, const double* __res
     for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * n + t];
 #pragma unroll
     for (int i = 0; i < NJ; ++i) acc[i] += vi[i] * wt;
+    acc[NJ] += wt * wt;
   }
-  block_partials<NJ>(acc, sh, partials);
+  block_partials<NJ + 1>(acc, sh, partials);
 }
 
-// w -= V h1, then h2[i] = V_i . w (second Gram-Schmidt pass)
+// w -= V h1.  When the step needs a second projection (sc->reorth), the
+// partials of h2 = V . w follow; otherwise the partials of w . w (slot 0).
 template <int NJ>
 __global__ __launch_bounds__(256) void k_cgs_pass(int64_t n, const double* __restrict__ V, double* __restrict__ w,
                                                   const DevScalars* sc, double* partials) {
   __shared__ double sh[4 * NJ];
-  double h[NJ], acc[NJ];
+  double h[NJ];
 #pragma unroll
-  for (int i = 0; i < NJ; ++i) { h[i] = sc->h1[i]; acc[i] = 0.0; }
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-    double vi[NJ];
+  for (int i = 0; i < NJ; ++i) h[i] = sc->h1[i];
+  if (sc->reorth != 0.0) {
+    double acc[NJ];
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * n + t];
-    double wt = w[t];
+    for (int i = 0; i < NJ; ++i) acc[i] = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+      double vi[NJ];
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) wt -= h[i] * vi[i];
-    w[t] = wt;
+      for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * n + t];
+      double wt = w[t];
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) acc[i] += vi[i] * wt;
+      for (int i = 0; i < NJ; ++i) wt -= h[i] * vi[i];
+      w[t] = wt;
+#pragma unroll
+      for (int i = 0; i < NJ; ++i) acc[i] += vi[i] * wt;
+    }
+    block_partials<NJ>(acc, sh, partials);
+  } else {
+    double acc[1] = {0.0};
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+      double vi[NJ];
+#pragma unroll
+      for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * n + t];
+      double wt = w[t];
+#pragma unroll
+      for (int i = 0; i < NJ; ++i) wt -= h[i] * vi[i];
+      w[t] = wt;
+      acc[0] += wt * wt;
+    }
+    block_partials<1>(acc, sh, partials);
   }
-  block_partials<NJ>(acc, sh, partials);
 }
 
-// w -= V h2 and partials of w.w.
+// Second projection (only when sc->reorth): w -= V h2 and partials of w.w.
 template <int NJ>
 __global__ __launch_bounds__(256) void k_cgs_final(int64_t n, const double* __restrict__ V, double* __restrict__ w,
                                                    const DevScalars* sc, double* partials) {
   __shared__ double sh[4];
+  if (sc->reorth == 0.0) return;
   double h[NJ];
 #pragma unroll
   for (int i = 0; i < NJ; ++i) h[i] = sc->h2[i];
@@ -397,6 +419,33 @@ void launch_gs(Gs which, int nj, unsigned grid, hipStream_t s, int64_t n, const 
 #undef SDG_GS_CASE
     default:
       throw Error(SDG_EINVAL, "Gram-Schmidt basis size out of range");
+  }
+}
+
+// h1 from the first projection's partials, and the decision whether this
+// step needs a second projection: the "twice is enough" test of Daniel,
+// Gragg, Kaufman and Stewart (1976), reorthogonalise when
+// ||w - V h1||^2 = ||w||^2 - ||h1||^2 < ||w||^2 / 2.  When the test passes,
+// the Pythagorean value is accurate to rounding, so no loss of
+// orthogonality is missed.
+__global__ void k_h1_fin(const double* partials, int nblocks, int nj, DevScalars* sc) {
+  reduce_slots(partials, nblocks, nj + 1, sc->h1);
+  if (threadIdx.x == 0) {
+    const double ww = sc->h1[nj];
+    double hh = 0.0;
+    for (int i = 0; i < nj; ++i) hh += sc->h1[i] * sc->h1[i];
+    const double r = (ww - hh < 0.5 * ww) ? 1.0 : 0.0;
+    sc->reorth = r;
+    sc->n_reorth += r;
+  }
+}
+
+// h2 from the second projection's partials, or zero without one.
+__global__ void k_h2_fin(const double* partials, int nblocks, int nj, DevScalars* sc) {
+  if (sc->reorth != 0.0) {
+    reduce_slots(partials, nblocks, nj, sc->h2);
+  } else {
+    for (int i = threadIdx.x; i < nj; i += blockDim.x) sc->h2[i] = 0.0;
   }
 }
 
@@ -701,11 +750,11 @@ SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, 
       ++res.matvecs;
       launch_gs(Gs::Multidot, j + 1, rg, s, n, V, w, sc, c.d_partials.p);
       check_launch();
-      k_finalize<<<1, 512, 0, s>>>(c.d_partials.p, (int)rg, j + 1, sc->h1);
+      k_h1_fin<<<1, 512, 0, s>>>(c.d_partials.p, (int)rg, j + 1, sc);
       check_launch();
       launch_gs(Gs::Pass, j + 1, rg, s, n, V, w, sc, c.d_partials.p);
       check_launch();
-      k_finalize<<<1, 512, 0, s>>>(c.d_partials.p, (int)rg, j + 1, sc->h2);
+      k_h2_fin<<<1, 512, 0, s>>>(c.d_partials.p, (int)rg, j + 1, sc);
       check_launch();
       launch_gs(Gs::Final, j + 1, rg, s, n, V, w, sc, c.d_partials.p);
       check_launch();
@@ -735,6 +784,12 @@ SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, 
       if (kk > 0) launch_gs(Gs::Update, kk, vg, s, n, V, x, sc, nullptr);
       check_launch();
     }
+  }
+  if (debug_krylov()) {
+    double nr = 0.0;
+    SDG_HIP(hipMemcpyAsync(&nr, &c.d_sc.p->n_reorth, sizeof(double), hipMemcpyDeviceToHost, s));
+    SDG_HIP(hipStreamSynchronize(s));
+    std::fprintf(stderr, "[gmres] second projections so far: %.0f\n", nr);
   }
   return res;
 }

@@ -12,6 +12,7 @@ CASES = {
     "c1": (lambda: synth.split_square(8, periodic=True), 1, 0, "cn", 0.01, "homog"),
     "c2_8x8": (lambda: synth.split_square(8, jitter=0.2, seed=2001), 3, 3, "stdg", 2.5e-3, "layered"),
     "p2pg2_free": (lambda: synth.split_square(6, jitter=0.15, seed=7), 2, 2, "stdg", 0.01, "lognormal"),
+    "p3pg0_free": (lambda: synth.split_square(5, jitter=0.2, seed=11), 3, 0, "stdg", 0.005, "layered"),
     "p4pg1_periodic": (lambda: synth.split_square(4, periodic=True, jitter=0.1, seed=3), 4, 1, "stdg", 0.01, "lognormal"),
     "3d_cn_p2": (lambda: synth.kuhn_cube(3, periodic=True), 2, 0, "cn", 0.01, "homog"),
     "3d_free_p1pg2": (lambda: synth.kuhn_cube(2, periodic=False), 1, 2, "stdg", 0.02, "lognormal"),

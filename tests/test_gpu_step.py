@@ -102,6 +102,21 @@ def test_space_time_p2_random_state_free_surface():
     case["ctx"].close()
 
 
+def test_space_time_p_gamma_0_implicit_euler_like():
+    """p_gamma = 0 in the space-time scheme: one time node per slab (the
+    lowest-order member of the family, an implicit Euler-like step), solved
+    with GMRES like every space-time slab."""
+    case = build("p3pg0_free")
+    rng = np.random.default_rng(31)
+    B = case["B"]
+    v0 = rng.standard_normal((B.topo.n_elem, 2, B.nphi))
+    s0 = 0.1 * rng.standard_normal((B.topo.n_face, 3, B.npsi))
+    errs = _run_pair(case, v0, s0, 3)
+    for ev, es, it, rr in errs:
+        assert ev <= 1e-11 and es <= 1e-11, errs
+    case["ctx"].close()
+
+
 @pytest.mark.parametrize("precond", [0, 1, 2])
 def test_preconditioners_agree_and_rank(precond):
     """Unpreconditioned, mass block-Jacobi and diagonal-block (eq. pre1) right
