@@ -3,7 +3,7 @@ back-substitution; eqs. velocity.sys + NM26, or the Crank-Nicolson forms)
 between the HIP library and the oracle's sparse-LU solution of the coupled
 slab system, plus energy, point evaluation and failure handling.
 
-The spec bar is <= 1e-11 relative L2 per step; the GPU solves run at
+The parity bar is <= 1e-11 relative L2 per step; the GPU solves run at
 rtol 1e-12 (CG: 1e-13) so that the Krylov tolerance stays below it.  GMRES(30)
 in FP64 stagnates near 1e-13 on these systems, so that is not asked of it.
 """
