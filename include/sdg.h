@@ -91,7 +91,7 @@ enum { SDG_SOLVER_AUTO = 0, SDG_SOLVER_CG = 1, SDG_SOLVER_GMRES = 2 };
  * BLOCK = element block-Jacobi on the full diagonal block of the velocity
  *         operator (eq. pre1), inverses stored at assemble time. */
 enum { SDG_PRECOND_NONE = 0, SDG_PRECOND_MASS = 1, SDG_PRECOND_BLOCK = 2 };
-enum { SDG_SOLVE_GRAPH = 1 };
+enum { SDG_SOLVE_GRAPH = 1, SDG_SOLVE_EXTRAPOLATE = 2 };
 
 typedef struct sdg_ctx sdg_ctx;
 
@@ -127,7 +127,7 @@ typedef struct {
   int32_t max_refine;  /* outer refinement sweeps for SDG_PREC_F32                      */
   double inner_rtol;   /* relative tolerance of each inner FP32 solve                   */
   int32_t precond;     /* SDG_PRECOND_*: right preconditioner (GMRES) / PCG (CG)        */
-  int32_t flags;       /* SDG_SOLVE_GRAPH: record the step in HIP graphs (see below)    */
+  int32_t flags;       /* SDG_SOLVE_GRAPH | SDG_SOLVE_EXTRAPOLATE (see sdg_solve_step)  */
 } sdg_solve_opts;
 
 typedef struct {
@@ -260,7 +260,12 @@ int sdg_set_mesh_sources(sdg_ctx* ctx, int64_t n_src, const double* pos, const d
  *   3. stress back-substitution, eq. (NM26) or (NM26.cn);
  *   4. overwrite v_state and sigma_state with the end-of-slab values.
  * v_slab / sigma_slab (device, optional) receive the slab DOFs.
- * The initial guess is the old state copied to every time node.
+ * The initial guess is the old state copied to every time node; with
+ * opts->flags & SDG_SOLVE_EXTRAPOLATE it is the previous step's velocity
+ * slab (kept by the context) continued to the new slab's time nodes, which
+ * is meant for consecutive steps of one trajectory: the first such step,
+ * or one after a step without the flag or with another n_rhs, starts from
+ * the old state as usual.  Both guesses converge to the same tolerance.
  * On SDG_ENOCONV the states hold the step computed from the last iterate
  * and *info is filled.
  * With opts->flags & SDG_SOLVE_GRAPH (FP64, GMRES) the step's launches are

@@ -226,7 +226,8 @@ void locate_points(Ctx& c, int64_t n_pts, const double* pts) {
 // Right-hand side of eq. (velocity.sys) (or velocity.sys.cn) for R columns
 // into d_b (point sources from d_src_amp when src), and the initial guess
 // (old state at every time node) into d_x.
-void step_rhs(Ctx& c, const double* v_state, const double* sigma_state, int R, bool src, hipStream_t s) {
+void step_rhs(Ctx& c, const double* v_state, const double* sigma_state, int R, bool src, hipStream_t s,
+              bool extrap) {
   const HostSetup& hs = c.hs;
   const int d = hs.dim, ng = hs.ng, nvs = d * hs.nphi;
   const double dt = hs.dt;
@@ -277,13 +278,16 @@ void step_rhs(Ctx& c, const double* v_state, const double* sigma_state, int R, b
   }
   SDG_HIP(hipGetLastError());
   if (src) launch_add_sources(c, c.d_b.p, c.d_src_amp.p, s, R);
-  launch_broadcast_time(hs.n_elem * R, ng, nvs, v_state, c.d_x.p, s);
+  if (extrap)
+    launch_time_map(hs.n_elem * R, ng, nvs, hs.Ext.data(), c.d_prev.p, c.d_x.p, s);
+  else
+    launch_broadcast_time(hs.n_elem * R, ng, nvs, v_state, c.d_x.p, s);
 }
 
 // Stress back-substitution (eq. NM26 or NM26.cn) from the velocity slab in
 // d_x, then the end-of-slab state, for R columns.
 void step_backsub(Ctx& c, double* v_state, double* sigma_state, double* v_slab, double* sigma_slab, int R,
-                  hipStream_t s) {
+                  hipStream_t s, bool extrap) {
   const HostSetup& hs = c.hs;
   const int d = hs.dim, ng = hs.ng, nvs = d * hs.nphi;
   const double dt = hs.dt;
@@ -328,6 +332,7 @@ void step_backsub(Ctx& c, double* v_state, double* sigma_state, double* v_slab, 
     if (v_slab) vec_copy(N, c.d_x.p, v_slab, s);
     launch_end_of_slab(hs.n_elem * R, ng, nvs, c.d_e1.p, c.d_x.p, v_state, s);
   }
+  if (extrap) vec_copy(N, c.d_x.p, c.d_prev.p, s);
 }
 
 // Partition of the independent systems of a batched solve with ncols columns,
@@ -637,6 +642,8 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     SDG_HIP(hipMemset(c.d_sc.p, 0, sizeof(DevScalars)));
     if (!c.h_pinned) SDG_HIP(hipHostMalloc((void**)&c.h_pinned, 16 * sizeof(double), hipHostMallocDefault));
     c.d_tmp_state.alloc(c.n_state * R);
+    c.d_prev.alloc(n);
+    c.prev_valid = false;
     c.d_tmp_sig.alloc(c.n_sig_state * R);
     c.d_src_amp.alloc((size_t)std::max<int64_t>(c.n_src, 1) * ng);
     SDG_HIP(hipDeviceSynchronize());
@@ -806,7 +813,7 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     require(v_state && sigma_state && opts, SDG_EINVAL, "null argument");
     require(n_rhs >= 1 && n_rhs <= c.max_rhs, SDG_EINVAL, "n_rhs must be in [1, max_rhs of sdg_assemble]");
     require(opts->rtol > 0 && opts->max_iter > 0, SDG_EINVAL, "rtol and max_iter must be positive");
-    require((opts->flags & ~SDG_SOLVE_GRAPH) == 0, SDG_EINVAL, "unknown solve flags");
+    require((opts->flags & ~(SDG_SOLVE_GRAPH | SDG_SOLVE_EXTRAPOLATE)) == 0, SDG_EINVAL, "unknown solve flags");
     const int prec = opts->precision == 0 ? SDG_PREC_F64 : opts->precision;
     check_prec(c, SDG_PREC_F64);
     if (prec == SDG_PREC_F32) check_prec(c, SDG_PREC_F32);
@@ -834,6 +841,14 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     kc.precond = opts->precond;
     kc.rtol = opts->rtol;
     kc.max_iter = opts->max_iter;
+    // extrapolated initial guess: the previous slab continued in time; without
+    // a previous slab of this width, seed it with the old state at every node
+    // (the continuation of a constant is the constant)
+    const bool extrap = (opts->flags & SDG_SOLVE_EXTRAPOLATE) != 0;
+    if (extrap && (!c.prev_valid || c.prev_R != R))
+      launch_broadcast_time(c.hs.n_elem * R, c.hs.ng, c.hs.dim * c.hs.nphi, v_state, c.d_prev.p, s);
+    c.prev_valid = extrap;
+    c.prev_R = R;
 
     if (graph) {
       MultiSys& m = systems(c, R);
@@ -850,7 +865,7 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
       const bool src = amp && c.n_src > 0;
       const bool same = G.head && G.v == v_state && G.sig == sigma_state && G.vslab == v_slab &&
                         G.sslab == sigma_slab && G.R == R && G.precond == kc.precond && G.restart == restart &&
-                        G.rtol == kc.rtol && G.src == src;
+                        G.rtol == kc.rtol && G.src == src && G.flags == opts->flags;
       if (!same) {
         G.clear();
         auto record = [&](auto&& body) {
@@ -873,7 +888,7 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
         int mv = 0;
         bool done = false;
         G.head = record([&] {
-          step_rhs(c, v_state, sigma_state, R, src, gs);
+          step_rhs(c, v_state, sigma_state, R, src, gs, extrap);
           multi_setup(m, c.d_b.p, c.d_x.p, kc.rtol, gs);
           multi_cycle(m, c.d_b.p, c.d_x.p, kc, gs, op, pp, c.d_V.p, c.d_r.p, c.d_w.p, c.d_t.p, false, restart, &mv,
                       &done);
@@ -883,7 +898,7 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
                       &done);
         });
         G.verify = record([&] { multi_residual(m, c.d_b.p, c.d_x.p, gs, op, c.d_r.p); });
-        G.tail = record([&] { step_backsub(c, v_state, sigma_state, v_slab, sigma_slab, R, gs); });
+        G.tail = record([&] { step_backsub(c, v_state, sigma_state, v_slab, sigma_slab, R, gs, extrap); });
         G.v = v_state;
         G.sig = sigma_state;
         G.vslab = v_slab;
@@ -893,6 +908,7 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
         G.restart = restart;
         G.rtol = kc.rtol;
         G.src = src;
+        G.flags = opts->flags;
       }
       SDG_HIP(hipStreamSynchronize(s));
       if (src)
@@ -924,7 +940,7 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     // 1. right-hand side (one launch for all columns)
     const bool src = amp && c.n_src > 0;
     if (src) SDG_HIP(hipMemcpyAsync(c.d_src_amp.p, amp, c.n_src * c.hs.ng * sizeof(double), hipMemcpyHostToDevice, s));
-    step_rhs(c, v_state, sigma_state, R, src, s);
+    step_rhs(c, v_state, sigma_state, R, src, s, extrap);
 
     // 2. Krylov solve from the old state copied to every time node
     auto inner = [&](const double* b, double* x, double tol, int maxit, int pr) {
@@ -984,7 +1000,7 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     }
 
     // 3. stress back-substitution and 4. end-of-slab state
-    step_backsub(c, v_state, sigma_state, v_slab, sigma_slab, R, s);
+    step_backsub(c, v_state, sigma_state, v_slab, sigma_slab, R, s, extrap);
     SDG_HIP(hipStreamSynchronize(s));
     if (!res.converged) throw Error(SDG_ENOCONV, "Krylov solver did not reach rtol within max_iter");
   });

@@ -85,7 +85,7 @@ struct StepGraphs {
   hipGraphExec_t head = nullptr, cycle = nullptr, verify = nullptr, tail = nullptr;
   hipStream_t stream = nullptr;
   const void *v = nullptr, *sig = nullptr, *vslab = nullptr, *sslab = nullptr;
-  int R = 0, precond = 0, restart = 0, max_iter = 0, check_every = 0;
+  int R = 0, precond = 0, restart = 0, max_iter = 0, check_every = 0, flags = 0;
   double rtol = 0.0;
   bool src = false;
   void clear() {
@@ -166,6 +166,10 @@ struct Ctx {
   int64_t z_col = 0;       // face-slot workspace per column
 
   StepGraphs graphs;
+  // previous slab solution, for the extrapolated initial guess
+  DevBuf<double> d_prev;
+  bool prev_valid = false;
+  int prev_R = 0;
 
   // located sampling points of the last call
   std::vector<double> samp_pts;
@@ -237,6 +241,8 @@ void launch_block_apply_fact(int64_t n_elem, int ng, int ns, const float* Q, con
 // step pieces
 void launch_broadcast_time(int64_t n_elem, int ng, int nvs, const double* state, double* slab,
                            hipStream_t s);
+void launch_time_map(int64_t n_elem, int ng, int nvs, const double* Mt, const double* in, double* out,
+                     hipStream_t s);
 void launch_end_of_slab(int64_t n_elem, int ng, int nvs, const double* w, const double* slab,
                         double* state, hipStream_t s);
 void launch_add_sources(Ctx& c, double* b, const double* amp_dev, hipStream_t s, int ncols = 1);

@@ -21,6 +21,21 @@ __global__ void k_broadcast(int64_t n_elem, int ng, int nvs, const double* __res
   }
 }
 
+// out[e][a][q] = sum_b Mt[a][b] in[e][b][q] (time-node mixing of a slab)
+struct TimeMat { double m[kMaxGamma * kMaxGamma]; };
+__global__ void k_time_map(int64_t n_elem, int ng, int nvs, TimeMat Mt, const double* __restrict__ in,
+                           double* __restrict__ out) {
+  const int64_t n = n_elem * ng * nvs;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i / (ng * nvs);
+    const int r = (int)(i % (ng * nvs)), a = r / nvs, q = r % nvs;
+    const double* ib = in + e * ng * nvs + q;
+    double acc = 0.0;
+    for (int b = 0; b < ng; ++b) acc += Mt.m[a * ng + b] * ib[b * nvs];
+    out[i] = acc;
+  }
+}
+
 // state[e][q] = sum_a w[a] slab[e][a][q]
 __global__ void k_end(int64_t n_elem, int ng, int nvs, const double* __restrict__ w, const double* __restrict__ sl,
                       double* __restrict__ st) {
@@ -227,6 +242,15 @@ void launch_face_to_elem(int64_t n_elem, int nfe, const int32_t* ef, const doubl
 void launch_sample_adjoint(int64_t n, int nphi, int dim, const int64_t* elem, const double* phi,
                            const double* obar, double* vbar, hipStream_t s) {
   k_sample_adjoint<<<1, 256, 0, s>>>(n, nphi, dim, elem, phi, obar, vbar);
+}
+
+void launch_time_map(int64_t n_elem, int ng, int nvs, const double* Mt, const double* in, double* out,
+                     hipStream_t s) {
+  TimeMat t{};
+  for (int i = 0; i < ng * ng; ++i) t.m[i] = Mt[i];
+  const int64_t n = n_elem * ng * nvs;
+  k_time_map<<<grid_for(n), kT, 0, s>>>(n_elem, ng, nvs, t, in, out);
+  SDG_HIP(hipGetLastError());
 }
 
 void launch_broadcast_time(int64_t n_elem, int ng, int nvs, const double* state, double* slab, hipStream_t s) {

@@ -71,6 +71,7 @@ struct HostSetup {
   std::vector<double> elem_xyz;
   // time basis
   std::vector<double> tau, w, e0, e1, T;  // T is ng*ng row-major
+  std::vector<double> Ext;                 // ng*ng: time basis of the slab evaluated on the next slab
 };
 
 // Build topology, geometry, bases and blocks.  Throws Error.

@@ -639,6 +639,10 @@ void build_host_setup(HostSetup& hs, int dim, int64_t n_vert, const double* xyz,
     hs.e0.resize(ng);
     hs.e1.resize(ng);
     for (int a = 0; a < ng; ++a) { hs.e0[a] = lag(a, 0.0, nullptr); hs.e1[a] = lag(a, 1.0, nullptr); }
+    // the slab polynomial continued to the next slab: Ext[a][b] = gamma_b(1 + tau_a)
+    hs.Ext.assign(ng * ng, 0.0);
+    for (int a = 0; a < ng; ++a)
+      for (int b = 0; b < ng; ++b) hs.Ext[a * ng + b] = lag(b, 1.0 + hs.tau[a], nullptr);
     std::vector<double> qx, qw;
     gauss_legendre(ng + 1, qx, qw);
     hs.T.assign(ng * ng, 0.0);

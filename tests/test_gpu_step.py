@@ -42,7 +42,7 @@ def _amp(case, n, f0=10.0, t_delay=0.1):
     return synth.ricker(t, f0, t_delay)[None, :]
 
 
-def _run_pair(case, v0, s0_raw, nsteps, sources=None, precision=None, rtol=1e-12, precond=None):
+def _run_pair(case, v0, s0_raw, nsteps, sources=None, precision=None, rtol=1e-12, precond=None, flags=0):
     """Step both codes nsteps times from the same state; return max rel errors."""
     import torch
     B, slab, ctx = case["B"], case["slab"], case["ctx"]
@@ -54,7 +54,9 @@ def _run_pair(case, v0, s0_raw, nsteps, sources=None, precision=None, rtol=1e-12
     errs = []
     for n in range(nsteps):
         amp = _amp(case, n) if sources is not None else None
-        info = ctx.step(vg, sg, amp, opts=_opts(rtol, precision, precond=precond))
+        o = _opts(rtol, precision, precond=precond)
+        o.flags = flags
+        info = ctx.step(vg, sg, amp, opts=o)
         src = dict(sources, amp=amp) if sources is not None else None
         _, _, v, s = slab.step(v, s, src)
         ev = rel(vg.cpu().numpy(), v)
@@ -100,6 +102,29 @@ def test_space_time_p2_random_state_free_surface():
     for ev, es, it, rr in errs:
         assert ev <= 1e-11 and es <= 1e-11, errs
     case["ctx"].close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_extrapolated_initial_guess_same_solution_fewer_iterations(graph):
+    """The previous slab continued in time as initial guess: the steps still
+    match the oracle and need no more iterations than from the old state (on
+    this small mesh both converge within two convergence polls)."""
+    import paper_1802_04516_amd as sdg
+    case = build("c2_8x8")
+    src = dict(pos=np.array([[0.503, 0.497]]), dir=np.array([[0.0, 1.0]]))
+    B = case["B"]
+    v0 = np.zeros((B.topo.n_elem, 2, B.nphi))
+    s0 = np.zeros((B.topo.n_face, 3, B.npsi))
+    fl = sdg.SDG_SOLVE_EXTRAPOLATE | (sdg.SDG_SOLVE_GRAPH if graph else 0)
+    errs = _run_pair(case, v0, s0, 6, sources=src, flags=fl, precond=sdg.SDG_PRECOND_BLOCK)
+    for ev, es, it, rr in errs[1:]:
+        assert ev <= 1e-11 and es <= 1e-11, errs
+    case["ctx"].close()
+    case2 = build("c2_8x8")
+    base = _run_pair(case2, v0, s0, 6, sources=src, precond=sdg.SDG_PRECOND_BLOCK)
+    case2["ctx"].close()
+    if not graph:
+        assert sum(e[2] for e in errs[2:]) <= sum(e[2] for e in base[2:])
 
 
 def test_space_time_p_gamma_0_implicit_euler_like():
