@@ -352,7 +352,7 @@ def main():
                       sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND)
     log(f"setup {time.time() - t0:.1f}s: {sizes['n_elem']} elems, {sizes['n_face']} faces, "
         f"{sizes['n_vel_slab']} velocity DOFs, operator {sizes['op_bytes_f64'] / 1e6:.1f} MB")
-    log(f"face-kernel autotune (us/apply, variants 0..6): f64 {[round(x, 1) for x in sizes['tune_us_f64']]} -> {sizes['op_variant']}, "
+    log(f"face-kernel autotune (us/apply, variants 0..7): f64 {[round(x, 1) for x in sizes['tune_us_f64']]} -> {sizes['op_variant']}, "
         f"f32 {[round(x, 1) for x in sizes['tune_us_f32']]} -> {sizes['op_variant_f32']}")
     src = w["sources"]
     if src is not None:

@@ -204,7 +204,10 @@ int sdg_query(const sdg_ctx* ctx, sdg_sizes* out);
  * most 256/(d N_psi) faces per workgroup within 64 KiB of LDS), 4 = the
  * same with half as many faces, 5 and 6 = column-parallel kernels that read
  * the blocks from HBM straight into registers (about 256/(d N_psi) faces
- * per workgroup, or twice as many); -1 reruns the autotuner (sdg_assemble runs it: every variant is
+ * per workgroup, or twice as many), 7 = one face per wavefront on the FP64
+ * matrix cores (the face gradient and scatter as 16x16x4 MFMA sequences,
+ * the rows padded to 16; in FP32, or where N_gamma d > 16 or N_phi > 16,
+ * variant 5); -1 reruns the autotuner (sdg_assemble runs it: every variant is
  * timed on the assembled operator and the fastest kept, per precision).  All
  * variants compute the same operator. */
 int sdg_set_operator_variant(sdg_ctx* ctx, int variant);

@@ -216,8 +216,8 @@ def sdg_query(h) -> dict:
     out = {f: getattr(s, f) for f, _ in Sizes._fields_
            if f not in ("tau", "tune_us_f64", "tune_us_f32", "tune_us_batched")}
     out["tau"] = [s.tau[a] for a in range(s.n_gamma)]
-    out["tune_us_f64"] = [x for x in s.tune_us_f64][:7]
-    out["tune_us_f32"] = [x for x in s.tune_us_f32][:7]
+    out["tune_us_f64"] = [x for x in s.tune_us_f64][:8]
+    out["tune_us_f32"] = [x for x in s.tune_us_f32][:8]
     out["tune_us_batched"] = list(s.tune_us_batched)
     return out
 
@@ -369,7 +369,7 @@ class Context:
         sdg_apply_adjoint(self.h, w, y, n_rhs, precision, stream)
 
     def set_operator_variant(self, variant):
-        """0..6 pins a face-kernel variant, -1 reruns the autotuner."""
+        """0..7 pins a face-kernel variant, -1 reruns the autotuner."""
         sdg_set_operator_variant(self.h, variant)
         self.sizes = sdg_query(self.h)
         return self.sizes

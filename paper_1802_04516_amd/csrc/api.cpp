@@ -661,7 +661,7 @@ int sdg_set_operator_variant(sdg_ctx* ctx, int variant) {
   return guard([&] {
     Ctx& c = ctx_of(ctx);
     require(c.assembled, SDG_ESTATE, "assemble first");
-    require(variant >= -1 && variant < kNumVariants, SDG_EINVAL, "variant must be -1 (autotune) or 0..6");
+    require(variant >= -1 && variant < kNumVariants, SDG_EINVAL, "variant must be -1 (autotune) or 0..7");
     SDG_HIP(hipSetDevice(c.device));
     c.graphs.clear();
     if (variant < 0) autotune(c);

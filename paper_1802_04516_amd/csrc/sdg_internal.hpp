@@ -34,7 +34,7 @@ inline void require(bool ok, int code, const std::string& msg) {
 
 // ---------------------------------------------------------------- sizes
 
-constexpr int kNumVariants = 7;
+constexpr int kNumVariants = 8;
 constexpr int kMaxGamma = 4;   // N_gamma <= 4 (p_gamma <= 3)
 constexpr int kMaxRhs = 64;
 
@@ -128,7 +128,8 @@ struct OpArgs {
   int variant;             // operator face kernel: 0 = LDS flat loops, 1 = register-tiled
                            // with the most faces per block, 2 = register-tiled, half of it,
                            // 3 = column-parallel (most faces that fit), 4 = half of it,
-                           // 5, 6 = column-parallel reading blocks from HBM into registers
+                           // 5, 6 = column-parallel reading blocks from HBM into registers,
+                           // 7 = one face per wavefront on the FP64 matrix cores
   // Several independent columns (right-hand sides) of the same mesh: the
   // launch grid's y index is the column and every per-column array is offset
   // by column * its stride (0 = shared by all columns).

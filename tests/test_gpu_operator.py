@@ -76,7 +76,7 @@ def test_apply_matches_oracle_schur(case):
     assert np.abs(per).max() <= 1e-12 * np.abs(ref).max() * 10
 
 
-@pytest.mark.parametrize("variant", list(range(7)))
+@pytest.mark.parametrize("variant", list(range(8)))
 def test_every_face_kernel_variant_matches_oracle(case, variant):
     """Each face-kernel variant the autotuner may pick is held to the same
     bar, in FP64 and FP32, on the forward operator and its transpose."""
@@ -92,7 +92,7 @@ def test_every_face_kernel_variant_matches_oracle(case, variant):
         assert rel(_apply(case, v, adjoint=True), case["S"].T @ v) <= 1e-12
     finally:
         s = ctx.set_operator_variant(-1)
-    assert s["op_variant"] in range(7) and s["op_variant_f32"] in range(7)
+    assert s["op_variant"] in range(8) and s["op_variant_f32"] in range(8)
     assert all(t > 0 for t in s["tune_us_f64"])
 
 
