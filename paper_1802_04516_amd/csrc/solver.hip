@@ -449,21 +449,41 @@ __global__ void k_h2_fin(const double* partials, int nblocks, int nj, DevScalars
   }
 }
 
-// Completes the Hessenberg column j (h1 + h2 and the new norm), applies the
-// previous Givens rotations, forms the new one and updates g.
-__global__ void k_cgs_final_fin(const double* partials, int nblocks, int nj, DevScalars* sc) {
-  __shared__ double tot;
-  reduce_slots(partials, nblocks, 1, &tot);
-  if (threadIdx.x == 0) {
-    const double s = tot;
+// Completes Arnoldi step j and writes the next basis vector:
+//   every block adds the ||w||^2 partials (slot 0) in the same fixed order,
+//   so all blocks hold the same norm, and scales its rows of w into v;
+//   block 0 also completes the Hessenberg column j (h1 + h2 and the norm),
+//   applies the previous Givens rotations, forms the new one and updates g.
+// The partials are read by every block (nblocks doubles each) instead of
+// being reduced by a separate single-block launch.
+__global__ __launch_bounds__(256) void k_arnoldi_scale(int64_t n, const double* partials, int nblocks, int nj,
+                                                       DevScalars* sc, const double* __restrict__ w,
+                                                       double* __restrict__ v) {
+  __shared__ double tot_sh;
+  {
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 64) {
+      double a0 = 0.0, a1 = 0.0;
+      int b = lane;
+      for (; b + 64 < nblocks; b += 128) { a0 += partials[b]; a1 += partials[b + 64]; }
+      if (b < nblocks) a0 += partials[b];
+      const double t = warp_sum(a0 + a1);
+      if (lane == 0) tot_sh = t;
+    }
+    __syncthreads();
+  }
+  const double nrm = sqrt(tot_sh);
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = w[i] * inv;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     const int j = nj - 1;
     const int ld = kMaxRestart + 1;
     double* Hc = sc->H + (size_t)j * ld;
     for (int i = 0; i < nj; ++i) Hc[i] = sc->h1[i] + sc->h2[i];
-    const double nrm = sqrt(s);
     Hc[j + 1] = nrm;
     sc->norm = nrm;
-    sc->inv_norm = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    sc->inv_norm = inv;
     for (int i = 0; i < j; ++i) {
       const double a = Hc[i], b = Hc[i + 1];
       Hc[i] = sc->cs[i] * a + sc->sn[i] * b;
@@ -758,9 +778,7 @@ SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, 
       check_launch();
       launch_gs(Gs::Final, j + 1, rg, s, n, V, w, sc, c.d_partials.p);
       check_launch();
-      k_cgs_final_fin<<<1, kThreads, 0, s>>>(c.d_partials.p, (int)rg, j + 1, sc);
-      check_launch();
-      k_scale_into<<<vg, kThreads, 0, s>>>(n, w, V + (size_t)(j + 1) * n, &sc->inv_norm);
+      k_arnoldi_scale<<<rg, kThreads, 0, s>>>(n, c.d_partials.p, (int)rg, j + 1, sc, w, V + (size_t)(j + 1) * n);
       check_launch();
       ++total;
       ++res.iters;
