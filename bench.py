@@ -256,10 +256,29 @@ def bench_mesh_batch(args):
     return res
 
 
+def nodal_points(mesh, p):
+    """Physical coordinates of the velocity nodes, (n_elem, N_phi, dim), in
+    the library's node order (equispaced nodes (i, j[, k]) / p, i fastest)."""
+    import numpy as np
+    V = mesh.unwrapped_vertices()
+    d = V.shape[2]
+    if d == 2:
+        ref = [(i / p, j / p) for j in range(p + 1) for i in range(p + 1 - j)]
+    else:
+        ref = [(i / p, j / p, k / p) for k in range(p + 1) for j in range(p + 1 - k) for i in range(p + 1 - k - j)]
+    ref = np.array(ref)
+    E = V[:, 1:, :] - V[:, :1, :]                       # (n_elem, d, d): edge vectors
+    return V[:, :1, :] + np.einsum("nl,eld->end", ref, E)
+
+
 def bench_3d_operator(args):
     """3D operator on the 32^3 periodic Kuhn cube (196,608 tetrahedra, p=2,
     Crank-Nicolson, homogeneous): the stored blocks (about 2 GB FP64) exceed
-    the last-level cache, so this apply runs from HBM."""
+    the last-level cache, so this apply runs from HBM.  Then five implicit
+    steps (preconditioned CG to 1e-10) from a plane S-wave velocity, FP64 and
+    FP32 operator + FP64 refinement, with the energy drift (the scheme
+    conserves energy exactly in this setting, Section 5)."""
+    import numpy as np
     import torch
 
     import paper_1802_04516_amd as sdg
@@ -269,13 +288,14 @@ def bench_3d_operator(args):
     t0 = time.time()
     ctx = sdg.Context(0)
     sizes = ctx.setup(mesh.xyz, mesh.elem, mesh.period, 2, 0, sdg.SDG_SCHEME_CN, w["dt"], w["lam"], w["mu"],
-                      w["rho"], sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32)
+                      w["rho"], sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND)
     log(f"3D setup {time.time() - t0:.1f}s: {sizes['n_elem']} tets, operator {sizes['op_bytes_f64'] / 1e9:.2f} GB; "
         f"autotune f64 {[round(x, 1) for x in sizes['tune_us_f64']]} -> {sizes['op_variant']}")
     n = sizes["n_vel_slab"]
     x = torch.randn(n, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
-    res = {"elements": sizes["n_elem"], "velocity_dofs": n, "operator_bytes_f64": sizes["op_bytes_f64"]}
+    res = {"elements": sizes["n_elem"], "velocity_dofs": n, "operator_bytes_f64": sizes["op_bytes_f64"],
+           "face_kernel_variant": sizes["op_variant"]}
     for prec, key, ob in ((sdg.SDG_PREC_F64, "fp64", sizes["op_bytes_f64"]),
                           (sdg.SDG_PREC_F32, "fp32", sizes["op_bytes_f32"])):
         for _ in range(3):
@@ -293,9 +313,35 @@ def bench_3d_operator(args):
                     "hbm_frac": b_alg / t / 1e9 / HBM_PEAK_GBS}
         log(f"3D apply {key}: {t * 1e6:.0f} us, {n / t / 1e9:.2f} GDOF/s, {b_alg / t / 1e9:.0f} GB/s "
             f"({100 * b_alg / t / 1e9 / HBM_PEAK_GBS:.1f}% of HBM peak)")
+    res["traffic_per_apply_bytes"] = measured_traffic("c3", sizes["op_variant"])
+
+    # plane S-wave velocity: direction (1,1,1)/sqrt(3), polarisation (1,-1,0)/sqrt(2), alpha 0.1, c_s 1
+    X = nodal_points(mesh, 2)                                # (n_elem, N_phi, 3)
+    pol = np.array([1.0, -1.0, 0.0]) / np.sqrt(2.0)
+    phase = 2.0 * np.pi * X.sum(axis=2)                      # k.x with k = 2 pi (1, 1, 1)
+    v0 = 0.1 * pol[None, :, None] * np.sin(phase)[:, None, :]  # (n_elem, 3, N_phi)
+    steps = 5
+    for name, prec in (("fp64_steps", sdg.SDG_PREC_F64), ("fp32_operator_fp64_refinement_steps", sdg.SDG_PREC_F32)):
+        v = torch.tensor(np.ascontiguousarray(v0).ravel(), dtype=torch.float64, device="cuda")
+        s = torch.zeros(sizes["n_stress_state"], dtype=torch.float64, device="cuda")
+        opts = _solve_opts(sdg, prec, sdg.SDG_PRECOND_BLOCK)
+        E0 = ctx.energy(v, s)
+        drift = 0.0
+        its = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = ctx.step(v, s, None, opts=opts)
+            its += info["iterations"]
+            drift = max(drift, abs(ctx.energy(v, s) - E0) / E0)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        res[name] = {"s_per_step": t, "iterations_per_step": its / steps, "max_rel_energy_drift": drift,
+                     "note": "wall time includes one energy evaluation per step"}
+        log(f"3D Crank-Nicolson {name}: {t * 1e3:.1f} ms/step, {its / steps:.1f} CG it/step, "
+            f"energy drift {drift:.2e}")
     ctx.close()
     return res
-
 
 def main():
     ap = argparse.ArgumentParser()

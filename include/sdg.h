@@ -286,7 +286,8 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
                    double* v_slab, double* sigma_slab, void* stream);
 
 /* Total energy 1/2 sum_i rho_i int |v|^2 + 1/2 sum_j int sigma : E_j^-1 sigma
- * (Section 5.2) of a state, FP64, written to out[n_rhs] (host). */
+ * (Section 5.2) of a state, FP64, written to out[n_rhs] (host), one value
+ * per column; on a mesh batch (n_rhs = 1) out[n_mesh], one value per mesh. */
 int sdg_energy(sdg_ctx* ctx, const double* v_state, const double* sigma_state, int n_rhs,
                double* out, void* stream);
 

@@ -287,8 +287,8 @@ def sdg_sample_velocity_adjoint(h, pts, obs_bar, vbar, n_rhs=1, stream=None):
                                              _stream(stream)))
 
 
-def sdg_energy(h, v_state, sigma_state, n_rhs=1, stream=None):
-    out = np.zeros(n_rhs)
+def sdg_energy(h, v_state, sigma_state, n_rhs=1, stream=None, n_out=None):
+    out = np.zeros(max(n_rhs, n_out or 1))
     _check(lib().sdg_energy(h, _dev(v_state, name="v_state"), _dev(sigma_state, name="sigma_state"), n_rhs,
                             _hp(out, ctypes.c_double), _stream(stream)))
     return out
@@ -317,6 +317,7 @@ class Context:
         self.h = sdg_create(device)
         self.device = device
         self.sizes = None
+        self.mesh_elem_off = None
 
     def close(self):
         if self.h:
@@ -332,6 +333,7 @@ class Context:
     def setup(self, mesh_xyz, elem, period, p, p_gamma, scheme, dt, lam, mu, rho,
               precisions=SDG_PREC_F64 | SDG_PREC_F32, max_rhs=1):
         sdg_set_mesh(self.h, mesh_xyz, elem, period)
+        self.mesh_elem_off = None
         sdg_set_discretization(self.h, p, p_gamma, scheme, dt)
         sdg_set_material(self.h, lam, mu, rho)
         sdg_assemble(self.h, precisions, max_rhs)
@@ -395,7 +397,10 @@ class Context:
     def energy(self, v_state, sigma_state, n_rhs=1):
         _dev(v_state, self._n("n_vel_state") * n_rhs, "v_state")
         _dev(sigma_state, self._n("n_stress_state") * n_rhs, "sigma_state")
-        e = sdg_energy(self.h, v_state, sigma_state, n_rhs)
+        n_mesh = len(self.mesh_elem_off) - 1 if getattr(self, "mesh_elem_off", None) is not None else 1
+        e = sdg_energy(self.h, v_state, sigma_state, n_rhs, n_out=n_mesh)
+        if n_mesh > 1:
+            return e
         return float(e[0]) if n_rhs == 1 else e
 
     def adjoint_step(self, v_old, v_slab, vbar, sigma_bar, grad, opts=None, stream=None):

@@ -504,6 +504,15 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     build_host_setup(hs, c.dim, n_vert, c.xyz.data(), n_elem, c.elem.data(), c.period.empty() ? nullptr : c.period.data(),
                      c.p, c.pg, c.scheme, c.dt, c.lam.data(), c.mu.data(), c.rho.data());
     const int d = hs.dim, ng = hs.ng, nphi = hs.nphi;
+    c.mesh_face_off.assign(c.n_mesh + 1, hs.n_face);
+    {
+      // faces are ordered by left element and never join two meshes
+      int64_t j = 0;
+      for (int q = 0; q < c.n_mesh; ++q) {
+        while (j < hs.n_face && hs.faces[j].left < c.mesh_elem_off[q]) ++j;
+        c.mesh_face_off[q] = j;
+      }
+    }
     c.n_slab = hs.n_elem * ng * d * nphi;
     c.n_state = hs.n_elem * d * nphi;
     c.n_sig_state = hs.n_face * hs.nsig * hs.npsi;
@@ -1226,6 +1235,19 @@ int sdg_energy(sdg_ctx* ctx, const double* v_state, const double* sigma_state, i
     require(n_rhs >= 1 && n_rhs <= c.max_rhs, SDG_EINVAL, "n_rhs must be in [1, max_rhs of sdg_assemble]");
     SDG_HIP(hipSetDevice(c.device));
     hipStream_t s = (hipStream_t)stream;
+    if (c.n_mesh > 1) {
+      // one value per mesh of the batch: its element and face ranges
+      require(n_rhs == 1, SDG_EUNSUPPORTED, "batched right-hand sides on a mesh batch");
+      for (int q = 0; q < c.n_mesh; ++q) {
+        launch_energy(c, v_state, sigma_state, &c.d_sc.p->dots[1], s, c.mesh_elem_off[q],
+                      c.mesh_elem_off[q + 1] - c.mesh_elem_off[q], c.mesh_face_off[q],
+                      c.mesh_face_off[q + 1] - c.mesh_face_off[q]);
+        SDG_HIP(hipMemcpyAsync(c.h_pinned, &c.d_sc.p->dots[1], sizeof(double), hipMemcpyDeviceToHost, s));
+        SDG_HIP(hipStreamSynchronize(s));
+        out[q] = c.h_pinned[0];
+      }
+      return;
+    }
     for (int r = 0; r < n_rhs; ++r) {
       launch_energy(c, v_state + (int64_t)r * c.n_state, sigma_state + (int64_t)r * c.n_sig_state,
                     &c.d_sc.p->dots[1], s);

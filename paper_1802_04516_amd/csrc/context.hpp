@@ -161,6 +161,7 @@ struct Ctx {
   // several independent systems: batched columns or a mesh batch
   int n_mesh = 1;
   std::vector<int64_t> mesh_vert_off, mesh_elem_off;  // n_mesh + 1 each
+  std::vector<int64_t> mesh_face_off;                  // n_mesh + 1, set by sdg_assemble
   MultiSys msys;
   int msys_key = 0;        // columns the partition was built for (-1: mesh batch)
   int64_t z_col = 0;       // face-slot workspace per column
@@ -246,7 +247,9 @@ void launch_time_map(int64_t n_elem, int ng, int nvs, const double* Mt, const do
 void launch_end_of_slab(int64_t n_elem, int ng, int nvs, const double* w, const double* slab,
                         double* state, hipStream_t s);
 void launch_add_sources(Ctx& c, double* b, const double* amp_dev, hipStream_t s, int ncols = 1);
-void launch_energy(Ctx& c, const double* v, const double* sig, double* out_dev, hipStream_t s);
+// energy of elements [e0, e0+ne) and faces [f0, f0+nf) (negative counts: to the end)
+void launch_energy(Ctx& c, const double* v, const double* sig, double* out_dev, hipStream_t s, int64_t e0 = 0,
+                   int64_t ne = -1, int64_t f0 = 0, int64_t nf = -1);
 void launch_grad_rho(int64_t n_elem, int ng, int dim, int nphi, const RhoCoefs& tc, const double* Mref,
                      const double* detJ, const double* L, const double* X, const double* vold, double* g,
                      hipStream_t s);

@@ -281,16 +281,21 @@ void launch_add_sources(Ctx& c, double* b, const double* amp_dev, hipStream_t s,
   SDG_HIP(hipGetLastError());
 }
 
-void launch_energy(Ctx& c, const double* v, const double* sig, double* out_dev, hipStream_t s) {
+void launch_energy(Ctx& c, const double* v, const double* sig, double* out_dev, hipStream_t s, int64_t e0,
+                   int64_t ne, int64_t f0, int64_t nf) {
   const HostSetup& hs = c.hs;
-  const int64_t n = hs.n_elem * hs.dim + hs.n_face;
+  if (ne < 0) ne = hs.n_elem - e0;
+  if (nf < 0) nf = hs.n_face - f0;
+  const int64_t n = ne * hs.dim + nf;
   unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kT - 1) / kT, kRedBlocks));
+  const double* vv = v + e0 * hs.dim * hs.nphi;
+  const double* ss = sig + f0 * hs.nsig * hs.npsi;
   if (hs.dim == 2)
-    k_energy<2><<<g, kT, 0, s>>>(hs.n_elem, hs.n_face, hs.nphi, hs.npsi, c.d_Mref.p, c.d_elem_w.p, c.d_face_lm.p, v,
-                                 sig, c.d_partials.p);
+    k_energy<2><<<g, kT, 0, s>>>(ne, nf, hs.nphi, hs.npsi, c.d_Mref.p, c.d_elem_w.p + e0, c.d_face_lm.p + 2 * f0, vv,
+                                 ss, c.d_partials.p);
   else
-    k_energy<3><<<g, kT, 0, s>>>(hs.n_elem, hs.n_face, hs.nphi, hs.npsi, c.d_Mref.p, c.d_elem_w.p, c.d_face_lm.p, v,
-                                 sig, c.d_partials.p);
+    k_energy<3><<<g, kT, 0, s>>>(ne, nf, hs.nphi, hs.npsi, c.d_Mref.p, c.d_elem_w.p + e0, c.d_face_lm.p + 2 * f0, vv,
+                                 ss, c.d_partials.p);
   SDG_HIP(hipGetLastError());
   k_energy_fin<<<1, 64, 0, s>>>(c.d_partials.p, (int)g, out_dev);
   SDG_HIP(hipGetLastError());

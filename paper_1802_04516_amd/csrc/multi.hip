@@ -216,40 +216,51 @@ __global__ __launch_bounds__(1024) void km_arnoldi_fin(const double* partials, i
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // per wavefront: the system's Hessenberg column and rotations in LDS
+  __shared__ double hcs[16][kMaxRestart + 1], css[16][kMaxRestart], sns[16][kMaxRestart];
+  double* hc = hcs[wv];
+  double* cs = css[wv];
+  double* sn = sns[wv];
   for (int s = wv; s < S; s += nw) {
     if (!ss[s].active) continue;
+    SysScalars& q = ss[s];
     double v = 0.0;
     for (int b = seg_blk0[s] + lane; b < seg_blk0[s + 1]; b += 64) v += partials[b];
     const double tot = wsum64(v);
+    if (lane <= j) hc[lane] = q.h1[lane] + q.h2[lane];
+    if (lane < j) { cs[lane] = q.cs[lane]; sn[lane] = q.sn[lane]; }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (lane == 0) {
-      SysScalars& q = ss[s];
-      const int ld = kMaxRestart + 1;
-      double* Hc = q.H + (size_t)j * ld;
-      for (int i = 0; i <= j; ++i) Hc[i] = q.h1[i] + q.h2[i];
       const double nrm = sqrt(tot);
-      Hc[j + 1] = nrm;
+      hc[j + 1] = nrm;
       q.norm = nrm;
       q.inv_norm = nrm > 0.0 ? 1.0 / nrm : 0.0;
       for (int i = 0; i < j; ++i) {
-        const double a = Hc[i], b = Hc[i + 1];
-        Hc[i] = q.cs[i] * a + q.sn[i] * b;
-        Hc[i + 1] = -q.sn[i] * a + q.cs[i] * b;
+        const double a = hc[i], b = hc[i + 1];
+        hc[i] = cs[i] * a + sn[i] * b;
+        hc[i + 1] = -sn[i] * a + cs[i] * b;
       }
-      const double a = Hc[j], b = Hc[j + 1];
+      const double a = hc[j], b = hc[j + 1];
       const double rad = hypot(a, b);
-      const double c = rad > 0.0 ? a / rad : 1.0, sn = rad > 0.0 ? b / rad : 0.0;
+      const double c = rad > 0.0 ? a / rad : 1.0, sg = rad > 0.0 ? b / rad : 0.0;
       q.cs[j] = c;
-      q.sn[j] = sn;
-      Hc[j] = rad;
-      Hc[j + 1] = 0.0;
+      q.sn[j] = sg;
+      hc[j] = rad;
+      hc[j + 1] = 0.0;
       const double gj = q.g[j];
       q.g[j] = c * gj;
-      q.g[j + 1] = -sn * gj;
+      q.g[j + 1] = -sg * gj;
       q.resid = fabs(q.g[j + 1]);
       q.k = j + 1;
       if (q.resid <= q.tol_abs || nrm == 0.0) q.active = 0;
       atomicAdd(&cnt, q.active);  // integer count in LDS: order-independent
     }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    double* Hc = q.H + (size_t)j * (kMaxRestart + 1);
+    if (lane <= j + 1) Hc[lane] = hc[lane];
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
   if (threadIdx.x == 0) *nactive = cnt;

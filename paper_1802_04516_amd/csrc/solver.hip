@@ -476,30 +476,40 @@ __global__ __launch_bounds__(256) void k_arnoldi_scale(int64_t n, const double* 
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     v[i] = w[i] * inv;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0) {
+    // Hessenberg column and rotations staged in LDS with parallel loads, so
+    // the serial rotation loop runs from LDS
+    __shared__ double hc[kMaxRestart + 1], cs[kMaxRestart], sn[kMaxRestart];
     const int j = nj - 1;
-    const int ld = kMaxRestart + 1;
-    double* Hc = sc->H + (size_t)j * ld;
-    for (int i = 0; i < nj; ++i) Hc[i] = sc->h1[i] + sc->h2[i];
-    Hc[j + 1] = nrm;
-    sc->norm = nrm;
-    sc->inv_norm = inv;
-    for (int i = 0; i < j; ++i) {
-      const double a = Hc[i], b = Hc[i + 1];
-      Hc[i] = sc->cs[i] * a + sc->sn[i] * b;
-      Hc[i + 1] = -sc->sn[i] * a + sc->cs[i] * b;
+    for (int i = threadIdx.x; i < nj; i += blockDim.x) {
+      hc[i] = sc->h1[i] + sc->h2[i];
+      if (i < j) { cs[i] = sc->cs[i]; sn[i] = sc->sn[i]; }
     }
-    const double a = Hc[j], b = Hc[j + 1];
-    const double rad = hypot(a, b);
-    const double c = rad > 0.0 ? a / rad : 1.0, sn = rad > 0.0 ? b / rad : 0.0;
-    sc->cs[j] = c;
-    sc->sn[j] = sn;
-    Hc[j] = rad;
-    Hc[j + 1] = 0.0;
-    const double gj = sc->g[j];
-    sc->g[j] = c * gj;
-    sc->g[j + 1] = -sn * gj;
-    sc->resid = fabs(sc->g[j + 1]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      hc[j + 1] = nrm;
+      sc->norm = nrm;
+      sc->inv_norm = inv;
+      for (int i = 0; i < j; ++i) {
+        const double a = hc[i], b = hc[i + 1];
+        hc[i] = cs[i] * a + sn[i] * b;
+        hc[i + 1] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = hc[j], b = hc[j + 1];
+      const double rad = hypot(a, b);
+      const double c = rad > 0.0 ? a / rad : 1.0, s = rad > 0.0 ? b / rad : 0.0;
+      sc->cs[j] = c;
+      sc->sn[j] = s;
+      hc[j] = rad;
+      hc[j + 1] = 0.0;
+      const double gj = sc->g[j];
+      sc->g[j] = c * gj;
+      sc->g[j + 1] = -s * gj;
+      sc->resid = fabs(sc->g[j + 1]);
+    }
+    __syncthreads();
+    double* Hc = sc->H + (size_t)j * (kMaxRestart + 1);
+    for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) Hc[i] = hc[i];
   }
 }
 

@@ -222,6 +222,12 @@ def test_mesh_batch_step_matches_oracle_per_mesh(scheme, p, pg, precision):
               f"iters {info['iterations']} rel res {info['rel_residual']:.2e}")
         assert worst <= 1e-11
     assert sizes["n_elem"] == sum(m.n_elem for m in meshes)
+    # energy of the batch: one value per mesh (Section 5.2)
+    e = ctx.energy(vg, sg)
+    assert len(e) == len(meshes)
+    for q, S in enumerate(slabs):
+        eo = S.energy(vo[q], so[q])
+        assert abs(e[q] - eo) <= 1e-11 * abs(eo), (q, e[q], eo)
     ctx.close()
 
 
