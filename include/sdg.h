@@ -91,7 +91,17 @@ enum { SDG_SOLVER_AUTO = 0, SDG_SOLVER_CG = 1, SDG_SOLVER_GMRES = 2 };
  * BLOCK = element block-Jacobi on the full diagonal block of the velocity
  *         operator (eq. pre1), inverses stored at assemble time. */
 enum { SDG_PRECOND_NONE = 0, SDG_PRECOND_MASS = 1, SDG_PRECOND_BLOCK = 2 };
-enum { SDG_SOLVE_GRAPH = 1, SDG_SOLVE_EXTRAPOLATE = 2 };
+/* Solve flags (sdg_solve_opts.flags):
+ * GRAPH        replay the step from HIP graphs (see sdg_solve_step);
+ * EXTRAPOLATE  initial guess continued from the previous slab (sdg_solve_step);
+ * CGS2         single-system GMRES orthogonalises each new basis vector within
+ *              its own step (classical Gram-Schmidt, a second projection when
+ *              the test of Daniel, Gragg, Kaufman and Stewart asks for it: three
+ *              sweeps over the basis).  The default delays the second projection
+ *              of a vector to the next step (Swirydowicz et al. 2020, Bielich et
+ *              al. 2022): one reduction and two sweeps per step; the residual
+ *              estimate polled every check_every steps then lags by one step. */
+enum { SDG_SOLVE_GRAPH = 1, SDG_SOLVE_EXTRAPOLATE = 2, SDG_SOLVE_CGS2 = 4 };
 
 typedef struct sdg_ctx sdg_ctx;
 
@@ -122,12 +132,12 @@ typedef struct {
                           iterative refinement (dots, residuals, updates stay FP64)     */
   double rtol;         /* stop when ||b - A v||_2 <= rtol ||b||_2                       */
   int32_t max_iter;    /* total Krylov iterations (inner iterations for FP32)          */
-  int32_t restart;     /* GMRES restart length (<= 64)                                  */
+  int32_t restart;     /* GMRES restart length (<= 32)                                  */
   int32_t check_every; /* host convergence poll period in iterations                    */
   int32_t max_refine;  /* outer refinement sweeps for SDG_PREC_F32                      */
   double inner_rtol;   /* relative tolerance of each inner FP32 solve                   */
   int32_t precond;     /* SDG_PRECOND_*: right preconditioner (GMRES) / PCG (CG)        */
-  int32_t flags;       /* SDG_SOLVE_GRAPH | SDG_SOLVE_EXTRAPOLATE (see sdg_solve_step)  */
+  int32_t flags;       /* SDG_SOLVE_GRAPH | SDG_SOLVE_EXTRAPOLATE | SDG_SOLVE_CGS2      */
 } sdg_solve_opts;
 
 typedef struct {

@@ -29,6 +29,7 @@ SDG_SOLVER_AUTO, SDG_SOLVER_CG, SDG_SOLVER_GMRES = 0, 1, 2
 SDG_PRECOND_NONE, SDG_PRECOND_MASS, SDG_PRECOND_BLOCK = 0, 1, 2
 SDG_SOLVE_GRAPH = 1
 SDG_SOLVE_EXTRAPOLATE = 2
+SDG_SOLVE_CGS2 = 4
 
 _ERRNAMES = {SDG_EINVAL: "EINVAL", SDG_ENOMEM: "ENOMEM", SDG_EDEVICE: "EDEVICE", SDG_EMESH: "EMESH",
              SDG_ENOCONV: "ENOCONV", SDG_ENONFINITE: "ENONFINITE", SDG_EUNSUPPORTED: "EUNSUPPORTED",

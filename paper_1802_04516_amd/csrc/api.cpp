@@ -822,7 +822,8 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     require(v_state && sigma_state && opts, SDG_EINVAL, "null argument");
     require(n_rhs >= 1 && n_rhs <= c.max_rhs, SDG_EINVAL, "n_rhs must be in [1, max_rhs of sdg_assemble]");
     require(opts->rtol > 0 && opts->max_iter > 0, SDG_EINVAL, "rtol and max_iter must be positive");
-    require((opts->flags & ~(SDG_SOLVE_GRAPH | SDG_SOLVE_EXTRAPOLATE)) == 0, SDG_EINVAL, "unknown solve flags");
+    require((opts->flags & ~(SDG_SOLVE_GRAPH | SDG_SOLVE_EXTRAPOLATE | SDG_SOLVE_CGS2)) == 0, SDG_EINVAL,
+            "unknown solve flags");
     const int prec = opts->precision == 0 ? SDG_PREC_F64 : opts->precision;
     check_prec(c, SDG_PREC_F64);
     if (prec == SDG_PREC_F32) check_prec(c, SDG_PREC_F32);
@@ -850,6 +851,7 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     kc.precond = opts->precond;
     kc.rtol = opts->rtol;
     kc.max_iter = opts->max_iter;
+    kc.delayed = (opts->flags & SDG_SOLVE_CGS2) == 0;
     // extrapolated initial guess: the previous slab continued in time; without
     // a previous slab of this width, seed it with the old state at every node
     // (the continuation of a constant is the constant)
@@ -1103,6 +1105,7 @@ int sdg_adjoint_step(sdg_ctx* ctx, const double* v_old, const double* v_slab, do
     kc.max_iter = opts->max_iter;
     kc.prec = SDG_PREC_F64;
     kc.transpose = true;
+    kc.delayed = (opts->flags & SDG_SOLVE_CGS2) == 0;
     res = solver == SDG_SOLVER_CG ? solve_cg(c, c.d_b.p, c.d_x.p, kc, s) : solve_gmres(c, c.d_b.p, c.d_x.p, kc, s);
 
     // 3. stress multipliers L_s and the new stress adjoint:

@@ -11,7 +11,7 @@ namespace sdg {
 
 constexpr int kMaxRestart = 32;
 constexpr int kRedBlocks = 512;   // grid size of the reduction kernels
-constexpr int kRedSlots = 40;     // partial-sum slots per reduction block
+constexpr int kRedSlots = 2 * kMaxRestart + 2;  // partial-sum slots per reduction block
 
 // Device-resident scalars of the Krylov solvers.
 struct DevScalars {
@@ -27,6 +27,12 @@ struct DevScalars {
   double dots[kRedSlots];
   double reorth;        // 1 when the current Arnoldi step needs a second projection
   double n_reorth;      // count of second projections (diagnostics)
+  // delayed reorthogonalisation: the Hessenberg matrix before the Givens
+  // rotations (column-major, ld = kMaxRestart+1) and the coefficients of the
+  // update sweep (h2 holds the reorthogonalisation coefficients b)
+  double Hu[(kMaxRestart + 1) * kMaxRestart];
+  double f[kMaxRestart + 1];
+  double e;
 };
 
 // Scalars of one system of a multi-system Krylov solve.
@@ -204,6 +210,7 @@ struct KrylovCfg {
   int prec = SDG_PREC_F64;   // operator precision
   int precond = SDG_PRECOND_NONE;
   bool transpose = false;    // solve with A^T (adjoint)
+  bool delayed = true;       // GMRES: delayed reorthogonalisation (one reduction per step)
 };
 SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s);
 SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s);

@@ -48,13 +48,48 @@ __device__ inline void reduce_slots(const double* partials, int nblocks, int nsl
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int sl = wid; sl < nslots; sl += nw) {
     // slot-major layout: the wave's loads are contiguous and independent
+    // all of the lane's loads (at most kRedBlocks / 64) in flight at once
     const double* ps = partials + (size_t)sl * kRedBlocks;
-    double v0 = 0.0, v1 = 0.0;
-    int b = lane;
-    for (; b + 64 < nblocks; b += 128) { v0 += ps[b]; v1 += ps[b + 64]; }
-    if (b < nblocks) v0 += ps[b];
-    const double v = warp_sum(v0 + v1);
+    constexpr int PER = kRedBlocks / 64;
+    double pv[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) pv[q] = lane + 64 * q < nblocks ? ps[lane + 64 * q] : 0.0;
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) v += pv[q];
+    v = warp_sum(v);
     if (lane == 0) out[sl] = v;
+  }
+  __syncthreads();
+}
+
+// Sums of NS slots of partials (nblocks <= kRedBlocks per slot) by one
+// workgroup of NW wavefronts, every load in flight at once: wave w adds the
+// slots w, w + NW, ..., lane l the blocks l, l + 64, ... of each, then a
+// fixed shuffle tree per slot.  Result in out[0..NS) (LDS), valid after the
+// call.
+template <int NS, int NW = 4>
+__device__ inline void reduce_slots_wg(const double* partials, int nblocks, double* out) {
+  constexpr int SPW = (NS + NW - 1) / NW, PER = kRedBlocks / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double v[SPW][PER];
+#pragma unroll
+  for (int i = 0; i < SPW; ++i) {
+    const int sl = wid + NW * i;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int b = lane + 64 * q;
+      v[i][q] = (sl < NS && b < nblocks) ? partials[(size_t)sl * kRedBlocks + b] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < SPW; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) t += v[i][q];
+    t = warp_sum(t);
+    const int sl = wid + NW * i;
+    if (lane == 0 && sl < NS) out[sl] = t;
   }
   __syncthreads();
 }
@@ -277,20 +312,57 @@ __global__ void k_cg_p(int64_t n, double* __restrict__ p, const double* __restri
 // parameter: every row's NJ loads are independent and unconditional, so a
 // wavefront keeps them all in flight.
 
-// Per-block sums of NJ accumulators -> partials[i][block] (slot-major).
-template <int NJ>
-__device__ inline void block_partials(const double (&acc)[NJ], double* sh, double* partials) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+constexpr int pow2ceil(int x) { return x <= 1 ? 1 : 2 * pow2ceil((x + 1) / 2); }
+
+// One butterfly exchange of a wavefront reduce-scatter (offset O, CNT
+// accumulators left): a lane keeps one half of its accumulators, sends the
+// other half to lane ^ O and adds what it receives; lanes with bit O set
+// keep the upper half (their slot base moves up by CNT / 2).  With one
+// accumulator left the exchange is a plain butterfly sum.
+template <int CNT, int O>
+__device__ inline void bfly(double* v, int lane, int& base) {
+  if constexpr (O > 0) {
+    if constexpr (CNT > 1) {
+      constexpr int H = CNT / 2;
+      const bool up = (lane & O) != 0;
 #pragma unroll
-  for (int i = 0; i < NJ; ++i) {
-    const double v = warp_sum(acc[i]);
-    if (lane == 0) sh[wid * NJ + i] = v;
+      for (int i = 0; i < H; ++i) {
+        const double send = up ? v[i] : v[i + H];
+        const double keep = up ? v[i + H] : v[i];
+        v[i] = keep + __shfl_xor(send, O, 64);
+      }
+      if (up) base += H;
+      bfly<H, O / 2>(v, lane, base);
+    } else {
+      v[0] += __shfl_xor(v[0], O, 64);
+      bfly<1, O / 2>(v, lane, base);
+    }
   }
+}
+
+// Per-block sums of NS (<= 64) accumulators -> partials[i][block]
+// (slot-major).  Within a wavefront a butterfly reduce-scatter over the six
+// lane offsets 32 .. 1 moves about NSP values per lane (NSP = NS rounded up
+// to a power of two) instead of 6 NS for one shuffle tree per slot; lane l
+// ends with the wave sum of slot l / (64 / NSP).  The waves' sums are then
+// added in wave order, so the result is deterministic.
+template <int NS>
+__device__ inline void block_partials(const double (&acc)[NS], double* partials) {
+  constexpr int NSP = pow2ceil(NS), REP = 64 / NSP;
+  static_assert(NSP <= 64, "at most 64 accumulators per block reduction");
+  __shared__ double shp[16 * NSP];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double v[NSP];
+#pragma unroll
+  for (int i = 0; i < NSP; ++i) v[i] = i < NS ? acc[i] : 0.0;
+  int base = 0;
+  bfly<NSP, 32>(v, lane, base);
+  if (lane % REP == 0 && base < NS) shp[wid * NSP + base] = v[0];
   __syncthreads();
-  if (threadIdx.x < NJ) {
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += sh[w * NJ + threadIdx.x];
-    partials[(size_t)threadIdx.x * kRedBlocks + blockIdx.x] = s;
+  if (threadIdx.x < NS) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += shp[w * NSP + threadIdx.x];
+    partials[(size_t)threadIdx.x * kRedBlocks + blockIdx.x] = t;
   }
 }
 
@@ -299,7 +371,6 @@ __device__ inline void block_partials(const double (&acc)[NJ], double* sh, doubl
 template <int NJ>
 __global__ __launch_bounds__(256) void k_multidot(int64_t n, const double* __restrict__ V,
                                                   const double* __restrict__ w, double* partials) {
-  __shared__ double sh[4 * (NJ + 1)];
   double acc[NJ + 1];
 #pragma unroll
   for (int i = 0; i <= NJ; ++i) acc[i] = 0.0;
@@ -312,7 +383,254 @@ __global__ __launch_bounds__(256) void k_multidot(int64_t n, const double* __res
     for (int i = 0; i < NJ; ++i) acc[i] += vi[i] * wt;
     acc[NJ] += wt * wt;
   }
-  block_partials<NJ + 1>(acc, sh, partials);
+  block_partials<NJ + 1>(acc, partials);
+}
+
+// ---- Arnoldi with delayed reorthogonalisation (one reduction per step).
+// The low-synchronisation classical Gram-Schmidt with a lagged second
+// projection of Swirydowicz, Langou, Ananthan, Yang and Thomas (2020) and
+// Bielich, Langou, Thomas, Swirydowicz, Yamazaki and Boman (2022),
+// restated here.  Step j holds the final orthonormal q_0..q_{j-1} (Q), the
+// once-projected, unnormalised u_j in slot j of V and z = A P^-1 u_j.  One
+// sweep forms b = Q^T u_j, c = Q^T z, u_j.u_j and u_j.z; then
+//   nu = ||u_j - Q b|| = sqrt(u.u - b.b),  q_j = (u_j - Q b) / nu,
+//   Hessenberg column j-1 = (a_{j-1} + b, nu)       (a: first projection),
+//   w_j = A P^-1 q_j = (z - Q_j Hb) / nu,  Hb = H[0:j+1, 0:j] b
+//         (the Arnoldi relation A P^-1 Q = Q_j H applied to b),
+//   a_j = Q_j^T w_j:  a_j[i] = (c_i - Hb_i) / nu (i < j),
+//                     a_j[j] = ((u.z - b.c) / nu - Hb_j) / nu,
+// and one update sweep writes q_j over u_j and the next once-projected
+//   u_{j+1} = w_j - Q_j a_j = z / nu - e u_j - Q f,
+//   d = Hb / nu + a_j,  e = d_j / nu,  f_i = d_i - e b_i.
+// The Hessenberg column of step j is complete one step later; the last
+// column of a cycle is completed by a sweep without z.
+
+// Slots [0, NJ) = Q^T u, [NJ, 2NJ) = Q^T z, 2NJ = u.u, 2NJ+1 = u.z, with
+// Q = V[0..NJ), u = V[NJ]; without z (HZ false) [0, NJ) = Q^T u, NJ = u.u.
+template <int NJ, bool HZ>
+__global__ __launch_bounds__(256) void k_dmultidot(int64_t n, const double* __restrict__ V,
+                                                   const double* __restrict__ z, double* partials) {
+  constexpr int NS = HZ ? 2 * NJ + 2 : NJ + 1, IA = HZ ? 2 * NJ : NJ;
+  double acc[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) acc[i] = 0.0;
+  const double* __restrict__ u = V + (size_t)NJ * n;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const double ut = u[t];
+    const double zt = HZ ? z[t] : 0.0;
+    double vi[NJ > 0 ? NJ : 1];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * n + t];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+      acc[i] += vi[i] * ut;
+      if (HZ) acc[NJ + i] += vi[i] * zt;
+    }
+    acc[IA] += ut * ut;
+    if (HZ) acc[2 * NJ + 1] += ut * zt;
+  }
+  block_partials<NS>(acc, partials);
+}
+
+// Finalize of step NJ (one 1024-thread block): nu, Hessenberg column NJ-1
+// (unrotated in Hu, rotated in H), its Givens rotation, g and the residual
+// estimate; with HZ also a_NJ (into h1) and the update coefficients b (h2),
+// f, e and 1/nu (inv_norm).  Step 0 sets g[0] = nu = ||r||.
+template <int NJ, bool HZ>
+__global__ __launch_bounds__(1024) void k_dfin(const double* partials, int nblocks, DevScalars* sc) {
+  constexpr int NS = HZ ? 2 * NJ + 2 : NJ + 1, IA = HZ ? 2 * NJ : NJ, ld = kMaxRestart + 1,
+                NC = NJ > 0 ? NJ : 1;
+  __shared__ double sv[NS];
+  __shared__ double sHu[(NJ + 1) * NC];  // columns 0..NJ-1, ld NJ+1
+  __shared__ double sHb[NJ + 1];
+  __shared__ double sa[NC], scs[NC], ssn[NC], sgj;
+  __shared__ double sc_[4];  // nu, 1/nu, e
+  const int tid = threadIdx.x;
+  // everything the serial part reads, staged in LDS with parallel loads that
+  // are in flight together with the partials' loads
+  for (int i = tid; i < (NJ + 1) * NJ; i += blockDim.x) {
+    const int col = i / (NJ + 1), row = i % (NJ + 1);
+    sHu[i] = col + 1 < NJ && row <= col + 1 ? sc->Hu[(size_t)col * ld + row] : 0.0;
+  }
+  if (tid < NJ) {
+    sa[tid] = sc->h1[tid];
+    if (tid + 1 < NJ) {
+      scs[tid] = sc->cs[tid];
+      ssn[tid] = sc->sn[tid];
+    }
+  }
+  if (NJ > 0 && tid == 64) sgj = sc->g[NJ > 0 ? NJ - 1 : 0];
+  reduce_slots_wg<NS, 16>(partials, nblocks, sv);  // ends with a barrier
+  if (tid == 0) {
+    double bb = 0.0;
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) bb += sv[i] * sv[i];
+    const double nu2 = sv[IA] - bb;
+    const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+    const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
+    sc_[0] = nu;
+    sc_[1] = inv;
+    sc->norm = nu;
+    if (NJ == 0) {
+      sc->g[0] = nu;
+      sc->resid = nu;
+    } else {
+      // complete column NJ-1, then rotate it
+      double hc[NJ + 1];
+#pragma unroll
+      for (int i = 0; i < NJ; ++i) hc[i] = sa[i] + sv[i];
+      hc[NJ] = nu;
+#pragma unroll
+      for (int i = 0; i <= NJ; ++i) sHu[(NJ - 1) * (NJ + 1) + i] = hc[i];
+#pragma unroll
+      for (int i = 0; i + 1 < NJ; ++i) {
+        const double a = hc[i], b = hc[i + 1];
+        hc[i] = scs[i] * a + ssn[i] * b;
+        hc[i + 1] = -ssn[i] * a + scs[i] * b;
+      }
+      const double a = hc[NJ - 1], b = hc[NJ];
+      const double rad = hypot(a, b);
+      const double cr = rad > 0.0 ? a / rad : 1.0, sr = rad > 0.0 ? b / rad : 0.0;
+      sc->cs[NJ - 1] = cr;
+      sc->sn[NJ - 1] = sr;
+      hc[NJ - 1] = rad;
+      hc[NJ] = 0.0;
+      double* Hc = sc->H + (size_t)(NJ - 1) * ld;
+#pragma unroll
+      for (int i = 0; i <= NJ; ++i) Hc[i] = hc[i];
+      sc->g[NJ - 1] = cr * sgj;
+      sc->g[NJ] = -sr * sgj;
+      sc->resid = fabs(sr * sgj);
+    }
+  }
+  if (NJ == 0 && tid > 0 && tid <= kMaxRestart) sc->g[tid] = 0.0;
+  __syncthreads();
+  if (NJ > 0 && tid <= NJ) sc->Hu[(size_t)(NJ - 1) * ld + tid] = sHu[(NJ - 1) * (NJ + 1) + tid];
+  if (!HZ) return;
+  // Hb = H[0:NJ+1, 0:NJ] b
+  if (tid <= NJ) {
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) acc += sHu[i * (NJ + 1) + tid] * sv[i];  // zero below the subdiagonal
+    sHb[tid] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double inv = sc_[1];
+    double bc = 0.0;
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) bc += sv[i] * sv[NJ + i];
+    const double aj = ((sv[2 * NJ + 1] - bc) * inv - sHb[NJ]) * inv;
+    const double dj = sHb[NJ] * inv + aj;
+    const double e = dj * inv;
+    sc->h1[NJ] = aj;
+    sc->e = e;
+    sc->inv_norm = inv;
+    sc_[2] = e;
+  }
+  __syncthreads();
+  if (tid < NJ) {
+    const double inv = sc_[1], e = sc_[2];
+    const double ai = (sv[NJ + tid] - sHb[tid]) * inv;
+    const double di = sHb[tid] * inv + ai;
+    sc->h1[tid] = ai;
+    sc->h2[tid] = sv[tid];
+    sc->f[tid] = di - e * sv[tid];
+  }
+}
+
+// Update sweep of step NJ: q_NJ = (u - Q b) / nu over slot NJ of V, and the
+// next once-projected vector u_{NJ+1} = z / nu - e u - Q f into slot NJ+1.
+template <int NJ>
+__global__ __launch_bounds__(256) void k_dupdate(int64_t n, double* V, const double* __restrict__ z,
+                                                 const DevScalars* sc) {
+  double bq[NJ > 0 ? NJ : 1], fq[NJ > 0 ? NJ : 1];
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) { bq[i] = sc->h2[i]; fq[i] = sc->f[i]; }
+  const double inv = sc->inv_norm, e = sc->e;
+  const double* __restrict__ Q = V;
+  double* __restrict__ u = V + (size_t)NJ * n;
+  double* __restrict__ un = V + (size_t)(NJ + 1) * n;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double vi[NJ > 0 ? NJ : 1];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) vi[i] = Q[(size_t)i * n + t];
+    const double ut = u[t];
+    double q = ut, w = z[t] * inv - e * ut;
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+      q -= bq[i] * vi[i];
+      w -= fq[i] * vi[i];
+    }
+    u[t] = q * inv;
+    un[t] = w;
+  }
+}
+
+#define SDG_NJ0_CASES(X)                                                                                        \
+  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
+  X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+
+enum class Dg { Multidot, MultidotU, Fin, FinU, Update };
+
+// Launch a kernel of the delayed scheme for step nj (MultidotU / FinU: the
+// completion of the last column, without z; Fin / FinU take the producer's
+// grid size as `grid`).
+void launch_dgs(Dg which, int nj, unsigned grid, hipStream_t s, int64_t n, double* V, const double* z,
+                DevScalars* sc, double* partials) {
+  // a step with z has at most kMaxRestart - 1 final vectors before it
+  require(nj < kMaxRestart || which == Dg::MultidotU || which == Dg::FinU, SDG_EINVAL,
+          "Gram-Schmidt basis size out of range");
+  switch (nj) {
+#define SDG_DG_Z(N) (N < kMaxRestart ? N : kMaxRestart - 1)
+#define SDG_DG_CASE(N)                                                                                      \
+  case N:                                                                                                   \
+    if (which == Dg::Multidot) k_dmultidot<SDG_DG_Z(N), true><<<grid, 256, 0, s>>>(n, V, z, partials);      \
+    else if (which == Dg::MultidotU) k_dmultidot<N, false><<<grid, 256, 0, s>>>(n, V, nullptr, partials);    \
+    else if (which == Dg::Fin) k_dfin<SDG_DG_Z(N), true><<<1, 1024, 0, s>>>(partials, (int)grid, sc);        \
+    else if (which == Dg::FinU) k_dfin<N, false><<<1, 1024, 0, s>>>(partials, (int)grid, sc);                 \
+    else k_dupdate<SDG_DG_Z(N)><<<grid, 256, 0, s>>>(n, V, z, sc);                                          \
+    break;
+    SDG_NJ0_CASES(SDG_DG_CASE)
+#undef SDG_DG_CASE
+#undef SDG_DG_Z
+    default:
+      throw Error(SDG_EINVAL, "Gram-Schmidt basis size out of range");
+  }
+}
+
+// h1 from the first projection's partials, and the decision whether this
+// step needs a second projection: the "twice is enough" test of Daniel,
+// Gragg, Kaufman and Stewart (1976), reorthogonalise when
+// ||w - V h1||^2 = ||w||^2 - ||h1||^2 < ||w||^2 / 2.  When the test passes,
+// the Pythagorean value is accurate to rounding, so no loss of
+// orthogonality is missed.  One 256-thread block.
+template <int NJ>
+__global__ __launch_bounds__(256) void k_h1_fin(const double* partials, int nblocks, DevScalars* sc) {
+  __shared__ double hs[NJ + 1];
+  reduce_slots_wg<NJ + 1>(partials, nblocks, hs);
+  if (threadIdx.x <= NJ) sc->h1[threadIdx.x] = hs[threadIdx.x];
+  if (threadIdx.x == 0) {
+    const double ww = hs[NJ];
+    double hh = 0.0;
+    for (int i = 0; i < NJ; ++i) hh += hs[i] * hs[i];
+    const double r = (ww - hh < 0.5 * ww) ? 1.0 : 0.0;
+    sc->reorth = r;
+    sc->n_reorth += r;
+  }
+}
+
+// h2 from the second projection's partials, or zero without one.  One
+// 256-thread block.
+template <int NJ>
+__global__ __launch_bounds__(256) void k_h2_fin(const double* partials, int nblocks, DevScalars* sc) {
+  if (sc->reorth != 0.0) {
+    __shared__ double hs[NJ];
+    reduce_slots_wg<NJ>(partials, nblocks, hs);
+    if (threadIdx.x < NJ) sc->h2[threadIdx.x] = hs[threadIdx.x];
+  } else if (threadIdx.x < NJ) {
+    sc->h2[threadIdx.x] = 0.0;
+  }
 }
 
 // w -= V h1.  When the step needs a second projection (sc->reorth), the
@@ -320,7 +638,6 @@ __global__ __launch_bounds__(256) void k_multidot(int64_t n, const double* __res
 template <int NJ>
 __global__ __launch_bounds__(256) void k_cgs_pass(int64_t n, const double* __restrict__ V, double* __restrict__ w,
                                                   const DevScalars* sc, double* partials) {
-  __shared__ double sh[4 * NJ];
   double h[NJ];
 #pragma unroll
   for (int i = 0; i < NJ; ++i) h[i] = sc->h1[i];
@@ -339,7 +656,7 @@ __global__ __launch_bounds__(256) void k_cgs_pass(int64_t n, const double* __res
 #pragma unroll
       for (int i = 0; i < NJ; ++i) acc[i] += vi[i] * wt;
     }
-    block_partials<NJ>(acc, sh, partials);
+    block_partials<NJ>(acc, partials);
   } else {
     double acc[1] = {0.0};
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
@@ -352,7 +669,7 @@ __global__ __launch_bounds__(256) void k_cgs_pass(int64_t n, const double* __res
       w[t] = wt;
       acc[0] += wt * wt;
     }
-    block_partials<1>(acc, sh, partials);
+    block_partials<1>(acc, partials);
   }
 }
 
@@ -360,7 +677,6 @@ __global__ __launch_bounds__(256) void k_cgs_pass(int64_t n, const double* __res
 template <int NJ>
 __global__ __launch_bounds__(256) void k_cgs_final(int64_t n, const double* __restrict__ V, double* __restrict__ w,
                                                    const DevScalars* sc, double* partials) {
-  __shared__ double sh[4];
   if (sc->reorth == 0.0) return;
   double h[NJ];
 #pragma unroll
@@ -376,7 +692,7 @@ __global__ __launch_bounds__(256) void k_cgs_final(int64_t n, const double* __re
     w[t] = wt;
     acc[0] += wt * wt;
   }
-  block_partials<1>(acc, sh, partials);
+  block_partials<1>(acc, partials);
 }
 
 // x += sum_i y_i V_i
@@ -402,50 +718,26 @@ __global__ __launch_bounds__(256) void k_gmres_update(int64_t n, const double* _
   X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
 static_assert(kMaxRestart == 32, "the Gram-Schmidt dispatch covers 1..32 basis vectors");
 
-enum class Gs { Multidot, Pass, Final, Update };
+enum class Gs { Multidot, Pass, Final, Update, H1Fin, H2Fin };
 
-// Launch one of the Gram-Schmidt kernels for nj basis vectors.
+// Launch one of the Gram-Schmidt kernels for nj basis vectors (the
+// finalize kernels H1Fin / H2Fin take the producer's grid size as `grid`).
 void launch_gs(Gs which, int nj, unsigned grid, hipStream_t s, int64_t n, const double* V, double* w,
-               const DevScalars* sc, double* partials) {
+               DevScalars* sc, double* partials) {
   switch (nj) {
 #define SDG_GS_CASE(N)                                                                       \
   case N:                                                                                    \
     if (which == Gs::Multidot) k_multidot<N><<<grid, 256, 0, s>>>(n, V, w, partials);         \
     else if (which == Gs::Pass) k_cgs_pass<N><<<grid, 256, 0, s>>>(n, V, w, sc, partials);    \
     else if (which == Gs::Final) k_cgs_final<N><<<grid, 256, 0, s>>>(n, V, w, sc, partials);  \
+    else if (which == Gs::H1Fin) k_h1_fin<N><<<1, 256, 0, s>>>(partials, (int)grid, sc);       \
+    else if (which == Gs::H2Fin) k_h2_fin<N><<<1, 256, 0, s>>>(partials, (int)grid, sc);       \
     else k_gmres_update<N><<<grid, 256, 0, s>>>(n, V, w, sc);                                 \
     break;
     SDG_NJ_CASES(SDG_GS_CASE)
 #undef SDG_GS_CASE
     default:
       throw Error(SDG_EINVAL, "Gram-Schmidt basis size out of range");
-  }
-}
-
-// h1 from the first projection's partials, and the decision whether this
-// step needs a second projection: the "twice is enough" test of Daniel,
-// Gragg, Kaufman and Stewart (1976), reorthogonalise when
-// ||w - V h1||^2 = ||w||^2 - ||h1||^2 < ||w||^2 / 2.  When the test passes,
-// the Pythagorean value is accurate to rounding, so no loss of
-// orthogonality is missed.
-__global__ void k_h1_fin(const double* partials, int nblocks, int nj, DevScalars* sc) {
-  reduce_slots(partials, nblocks, nj + 1, sc->h1);
-  if (threadIdx.x == 0) {
-    const double ww = sc->h1[nj];
-    double hh = 0.0;
-    for (int i = 0; i < nj; ++i) hh += sc->h1[i] * sc->h1[i];
-    const double r = (ww - hh < 0.5 * ww) ? 1.0 : 0.0;
-    sc->reorth = r;
-    sc->n_reorth += r;
-  }
-}
-
-// h2 from the second projection's partials, or zero without one.
-__global__ void k_h2_fin(const double* partials, int nblocks, int nj, DevScalars* sc) {
-  if (sc->reorth != 0.0) {
-    reduce_slots(partials, nblocks, nj, sc->h2);
-  } else {
-    for (int i = threadIdx.x; i < nj; i += blockDim.x) sc->h2[i] = 0.0;
   }
 }
 
@@ -463,11 +755,14 @@ __global__ __launch_bounds__(256) void k_arnoldi_scale(int64_t n, const double* 
   {
     const int lane = threadIdx.x & 63;
     if (threadIdx.x < 64) {
-      double a0 = 0.0, a1 = 0.0;
-      int b = lane;
-      for (; b + 64 < nblocks; b += 128) { a0 += partials[b]; a1 += partials[b + 64]; }
-      if (b < nblocks) a0 += partials[b];
-      const double t = warp_sum(a0 + a1);
+      constexpr int PER = kRedBlocks / 64;
+      double pv[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) pv[q] = lane + 64 * q < nblocks ? partials[lane + 64 * q] : 0.0;
+      double a = 0.0;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) a += pv[q];
+      const double t = warp_sum(a);
       if (lane == 0) tot_sh = t;
     }
     __syncthreads();
@@ -730,10 +1025,109 @@ SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hip
 
 // ---------------------------------------------------------------- GMRES
 
+// x += P^-1 V[0..kk) y after the triangular solve of a restart cycle.
+static void gmres_correction(Ctx& c, int kk, double* x, const KrylovCfg& k, hipStream_t s) {
+  const int64_t n = c.n_slab;
+  const unsigned vg = vgrid(n);
+  double* V = c.d_V.p;
+  double* w = c.d_w.p;
+  double* t = c.d_t.p;
+  DevScalars* sc = c.d_sc.p;
+  k_gmres_trisolve<<<1, 64, 0, s>>>(sc, kk);
+  check_launch();
+  if (k.precond != SDG_PRECOND_NONE) {
+    vec_fill(n, 0.0, t, s);
+    if (kk > 0) launch_gs(Gs::Update, kk, vg, s, n, V, t, sc, nullptr);
+    check_launch();
+    apply_precond(c, k.precond, t, w, k.transpose, s);
+    vec_axpby(n, 1.0, w, 1.0, x, s);
+  } else {
+    if (kk > 0) launch_gs(Gs::Update, kk, vg, s, n, V, x, sc, nullptr);
+    check_launch();
+  }
+}
+
+// Restarted GMRES with right preconditioning and delayed
+// reorthogonalisation (one reduction and two sweeps over the basis per
+// step; see k_dmultidot).  Step j completes Hessenberg column j-1, so the
+// residual estimate read every `check_every` steps lags by one step.
+static SolveResult solve_gmres_delayed(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s) {
+  SolveResult res;
+  const int64_t n = c.n_slab;
+  const int m = std::max(1, std::min(k.restart, kMaxRestart));
+  double* V = c.d_V.p;
+  double* w = c.d_w.p;
+  double* t = c.d_t.p;
+  DevScalars* sc = c.d_sc.p;
+  const bool pre = k.precond != SDG_PRECOND_NONE;
+  const int check_every = std::max(1, k.check_every);
+  res.bnorm = std::sqrt(vec_dot_host(c, n, b, b, s));
+  require(std::isfinite(res.bnorm), SDG_ENONFINITE, "non-finite right-hand side");
+  if (res.bnorm == 0.0) {
+    vec_fill(n, 0.0, x, s);
+    res.converged = true;
+    return res;
+  }
+  const unsigned rg = red_grid(n), vg = vgrid(n);
+  int total = 0;
+  for (;;) {
+    // r = b - A x is the first (unnormalised) basis vector of the cycle
+    apply_op(c, x, V, k.prec, k.transpose, s);
+    ++res.matvecs;
+    vec_axpby(n, 1.0, b, -1.0, V, s);
+    dev_dot(c, n, V, V, &sc->dots[0], s);
+    double rr = read_scalar(c, &sc->dots[0], s);
+    require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
+    res.rel_res = std::sqrt(rr) / res.bnorm;
+    if (debug_krylov()) std::fprintf(stderr, "[gmres] restart at it %d: true rel res %.3e\n", total, res.rel_res);
+    if (res.rel_res <= k.rtol) { res.converged = true; break; }
+    if (total >= k.max_iter) break;
+    int j = 0, kk = -1;
+    for (; j < m && total < k.max_iter; ++j) {
+      double* uj = V + (size_t)j * n;
+      if (pre) {
+        apply_precond(c, k.precond, uj, t, k.transpose, s);
+        apply_op(c, t, w, k.prec, k.transpose, s);
+      } else {
+        apply_op(c, uj, w, k.prec, k.transpose, s);
+      }
+      ++res.matvecs;
+      launch_dgs(Dg::Multidot, j, rg, s, n, V, w, sc, c.d_partials.p);
+      check_launch();
+      launch_dgs(Dg::Fin, j, rg, s, n, V, w, sc, c.d_partials.p);
+      check_launch();
+      launch_dgs(Dg::Update, j, vg, s, n, V, w, sc, c.d_partials.p);
+      check_launch();
+      ++total;
+      ++res.iters;
+      if (j > 0 && j % check_every == 0) {
+        // columns 0..j-1 are complete
+        double est = read_scalar(c, &sc->resid, s);
+        if (debug_krylov()) std::fprintf(stderr, "[gmres]   it %d est rel res %.3e\n", total, est / res.bnorm);
+        require(std::isfinite(est), SDG_ENONFINITE, "non-finite residual estimate");
+        if (est <= k.rtol * res.bnorm) { kk = j; break; }
+      }
+    }
+    if (kk < 0) {
+      // j steps taken: complete column j-1 from u_j (slot j)
+      launch_dgs(Dg::MultidotU, j, rg, s, n, V, nullptr, sc, c.d_partials.p);
+      check_launch();
+      launch_dgs(Dg::FinU, j, rg, s, n, V, nullptr, sc, c.d_partials.p);
+      check_launch();
+      kk = j;
+    }
+    gmres_correction(c, kk, x, k, s);
+  }
+  return res;
+}
+
 // Restarted GMRES with right preconditioning (A P^-1 u = b, x = P^-1 u), so
 // the Arnoldi residual estimate is the true residual of the unpreconditioned
-// system.  Classical Gram-Schmidt with one reorthogonalisation.
+// system.  By default the delayed scheme above; otherwise classical
+// Gram-Schmidt with a second projection in the same step when the DGKS test
+// asks for it.
 SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s) {
+  if (k.delayed) return solve_gmres_delayed(c, b, x, k, s);
   SolveResult res;
   const int64_t n = c.n_slab;
   const int m = std::max(1, std::min(k.restart, kMaxRestart));
@@ -780,11 +1174,11 @@ SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, 
       ++res.matvecs;
       launch_gs(Gs::Multidot, j + 1, rg, s, n, V, w, sc, c.d_partials.p);
       check_launch();
-      k_h1_fin<<<1, 512, 0, s>>>(c.d_partials.p, (int)rg, j + 1, sc);
+      launch_gs(Gs::H1Fin, j + 1, rg, s, n, V, w, sc, c.d_partials.p);
       check_launch();
       launch_gs(Gs::Pass, j + 1, rg, s, n, V, w, sc, c.d_partials.p);
       check_launch();
-      k_h2_fin<<<1, 512, 0, s>>>(c.d_partials.p, (int)rg, j + 1, sc);
+      launch_gs(Gs::H2Fin, j + 1, rg, s, n, V, w, sc, c.d_partials.p);
       check_launch();
       launch_gs(Gs::Final, j + 1, rg, s, n, V, w, sc, c.d_partials.p);
       check_launch();
@@ -800,18 +1194,7 @@ SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, 
         if (est <= k.rtol * res.bnorm) break;
       }
     }
-    k_gmres_trisolve<<<1, 64, 0, s>>>(sc, kk);
-    check_launch();
-    if (pre) {
-      vec_fill(n, 0.0, t, s);
-      if (kk > 0) launch_gs(Gs::Update, kk, vg, s, n, V, t, sc, nullptr);
-      check_launch();
-      apply_precond(c, k.precond, t, w, k.transpose, s);
-      vec_axpby(n, 1.0, w, 1.0, x, s);
-    } else {
-      if (kk > 0) launch_gs(Gs::Update, kk, vg, s, n, V, x, sc, nullptr);
-      check_launch();
-    }
+    gmres_correction(c, kk, x, k, s);
   }
   if (debug_krylov()) {
     double nr = 0.0;

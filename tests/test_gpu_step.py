@@ -127,6 +127,38 @@ def test_extrapolated_initial_guess_same_solution_fewer_iterations(graph):
         assert sum(e[2] for e in errs[2:]) <= sum(e[2] for e in base[2:])
 
 
+@pytest.mark.parametrize("restart,check_every", [(30, 5), (4, 1), (7, 3)])
+@pytest.mark.parametrize("cgs2", [False, True])
+def test_gmres_orthogonalisation_schemes(cgs2, restart, check_every):
+    """Both Arnoldi orthogonalisations of the single-system GMRES (default:
+    the second projection of a basis vector delayed to the next step, one
+    reduction per step; SDG_SOLVE_CGS2: within the step) reach the oracle's
+    step at the parity bar.  Short restarts exercise the completion of the
+    last Hessenberg column of a cycle; check_every = 1 the lagged residual
+    estimate at every step."""
+    import paper_1802_04516_amd as sdg
+    case = build("p2pg2_free")
+    rng = np.random.default_rng(33)
+    B, slab, ctx = case["B"], case["slab"], case["ctx"]
+    v0 = rng.standard_normal((B.topo.n_elem, 2, B.nphi))
+    s0 = 0.1 * rng.standard_normal((B.topo.n_face, 3, B.npsi))
+    vg, sg = _to_gpu(v0), _to_gpu(_canon(B, s0))
+    for precond in (sdg.SDG_PRECOND_MASS, sdg.SDG_PRECOND_BLOCK):
+        o = sdg.SolveOpts(sdg.SDG_SOLVER_GMRES, sdg.SDG_PREC_F64, 2e-13, 4000, restart, check_every, 20, 1e-5,
+                          precond)
+        o.flags = sdg.SDG_SOLVE_CGS2 if cgs2 else 0
+        v1, s1 = vg.clone(), sg.clone()
+        info = ctx.step(v1, s1, None, opts=o)
+        _, _, v, s = slab.step(v0, s0, None)
+        ev = rel(v1.cpu().numpy(), v)
+        es = rel(s1.cpu().numpy(), _canon(B, s))
+        print(f"cgs2={cgs2} restart={restart} precond={precond}: v {ev:.2e} s {es:.2e} "
+              f"iters {info['iterations']} res {info['rel_residual']:.2e}")
+        assert info["converged"] and info["rel_residual"] <= 2e-13
+        assert ev <= 1e-11 and es <= 1e-11
+    ctx.close()
+
+
 def test_space_time_p_gamma_0_implicit_euler_like():
     """p_gamma = 0 in the space-time scheme: one time node per slab (the
     lowest-order member of the family, an implicit Euler-like step), solved
