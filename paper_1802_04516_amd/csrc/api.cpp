@@ -650,6 +650,12 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     c.d_sc.alloc(1);
     SDG_HIP(hipMemset(c.d_sc.p, 0, sizeof(DevScalars)));
     if (!c.h_pinned) SDG_HIP(hipHostMalloc((void**)&c.h_pinned, 16 * sizeof(double), hipHostMallocDefault));
+    if (!c.h_poll) {
+      SDG_HIP(hipHostMalloc((void**)&c.h_poll, (kMaxRestart + 1) * sizeof(double),
+                            hipHostMallocCoherent | hipHostMallocMapped));
+      for (int i = 0; i <= kMaxRestart; ++i) c.h_poll[i] = 0.0;
+      SDG_HIP(hipHostGetDevicePointer((void**)&c.d_poll, c.h_poll, 0));
+    }
     c.d_tmp_state.alloc(c.n_state * R);
     c.d_prev.alloc(n);
     c.prev_valid = false;

@@ -147,6 +147,12 @@ struct Ctx {
   DevBuf<double> d_partials;            // kRedSlots * kRedBlocks, slot-major
   DevBuf<DevScalars> d_sc;
   double* h_pinned = nullptr;           // pinned host copy of a few scalars
+  // convergence poll of the delayed GMRES: {latest stamp, estimate of step
+  // 0, 1, ... of the cycle} written by the device into coherent pinned
+  // memory; stamps increase over the context's lifetime
+  double* h_poll = nullptr;
+  double* d_poll = nullptr;             // device address of h_poll
+  double poll_seq = 0.0;
   DevBuf<double> d_tmp_state, d_tmp_sig; // state-sized scratch (energy, back-substitution)
 
   // sources
@@ -185,6 +191,7 @@ struct Ctx {
 
   ~Ctx() {
     if (h_pinned) (void)hipHostFree(h_pinned);
+    if (h_poll) (void)hipHostFree(h_poll);
   }
 };
 

@@ -301,18 +301,31 @@ __global__ void km_set_tol(int S, SysScalars* ss, double rtol) {
 }
 
 // Back substitution R y = g per system with its k.
-__global__ void km_trisolve(int S, SysScalars* ss) {
-  const int s = threadIdx.x;
+// Per system y = R^-1 g (R: the k x k upper triangle of its rotated
+// Hessenberg matrix), one wavefront per system: lane l holds row l of R and
+// the running right-hand side; column by column from the last, y_i is
+// broadcast and the lanes above subtract R_li y_i.
+__global__ __launch_bounds__(256) void km_trisolve(int S, SysScalars* ss) {
+  const int s = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), l = threadIdx.x & 63;
   if (s >= S) return;
   SysScalars& q = ss[s];
-  const int ld = kMaxRestart + 1;
-  for (int i = 0; i < kMaxRestart; ++i) q.y[i] = 0.0;
-  for (int i = q.k - 1; i >= 0; --i) {
-    double sum = q.g[i];
-    for (int l = i + 1; l < q.k; ++l) sum -= q.H[(size_t)l * ld + i] * q.y[l];
-    const double d = q.H[(size_t)i * ld + i];
-    q.y[i] = d != 0.0 ? sum / d : 0.0;
+  constexpr int ld = kMaxRestart + 1;
+  const int k = q.k;
+  double hrow[kMaxRestart];
+#pragma unroll
+  for (int i = 0; i < kMaxRestart; ++i) hrow[i] = (l < k && i < k) ? q.H[(size_t)i * ld + l] : 0.0;
+  double r = l < k ? q.g[l] : 0.0, y = 0.0;
+#pragma unroll
+  for (int i = kMaxRestart - 1; i >= 0; --i) {
+    if (i < k) {
+      const double ri = __shfl(r, i, 64);
+      const double d = __shfl(hrow[i], i, 64);
+      const double yi = d != 0.0 ? ri / d : 0.0;
+      if (l == i) y = yi;
+      if (l < i) r -= hrow[i] * yi;
+    }
   }
+  if (l < kMaxRestart) q.y[l] = y;
 }
 
 #define SDG_MNJ_CASES(X)                                                                                   \
@@ -494,7 +507,7 @@ int multi_cycle(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hip
       if (read_int(m.d_nactive.p, m.h_pinned, s) == 0) break;
     }
   }
-  km_trisolve<<<1, st, 0, s>>>(m.S, ss);
+  km_trisolve<<<(unsigned)((m.S * 64 + 255) / 256), 256, 0, s>>>(m.S, ss);
   SDG_HIP(hipGetLastError());
   if (pre) {
     vec_fill(n, 0.0, t, s);

@@ -403,41 +403,45 @@ __global__ __launch_bounds__(256) void k_multidot(int64_t n, const double* __res
 //   u_{j+1} = w_j - Q_j a_j = z / nu - e u_j - Q f,
 //   d = Hb / nu + a_j,  e = d_j / nu,  f_i = d_i - e b_i.
 // The Hessenberg column of step j is complete one step later; the last
-// column of a cycle is completed by a sweep without z.
+// column of a cycle is completed from dot products that the last step's
+// update sweep forms.
 
 // Slots [0, NJ) = Q^T u, [NJ, 2NJ) = Q^T z, 2NJ = u.u, 2NJ+1 = u.z, with
-// Q = V[0..NJ), u = V[NJ]; without z (HZ false) [0, NJ) = Q^T u, NJ = u.u.
-template <int NJ, bool HZ>
+// Q = V[0..NJ), u = V[NJ].
+template <int NJ>
 __global__ __launch_bounds__(256) void k_dmultidot(int64_t n, const double* __restrict__ V,
                                                    const double* __restrict__ z, double* partials) {
-  constexpr int NS = HZ ? 2 * NJ + 2 : NJ + 1, IA = HZ ? 2 * NJ : NJ;
+  constexpr int NS = 2 * NJ + 2;
   double acc[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) acc[i] = 0.0;
   const double* __restrict__ u = V + (size_t)NJ * n;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
     const double ut = u[t];
-    const double zt = HZ ? z[t] : 0.0;
+    const double zt = z[t];
     double vi[NJ > 0 ? NJ : 1];
 #pragma unroll
     for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * n + t];
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
       acc[i] += vi[i] * ut;
-      if (HZ) acc[NJ + i] += vi[i] * zt;
+      acc[NJ + i] += vi[i] * zt;
     }
-    acc[IA] += ut * ut;
-    if (HZ) acc[2 * NJ + 1] += ut * zt;
+    acc[2 * NJ] += ut * ut;
+    acc[2 * NJ + 1] += ut * zt;
   }
   block_partials<NS>(acc, partials);
 }
 
 // Finalize of step NJ (one 1024-thread block): nu, Hessenberg column NJ-1
 // (unrotated in Hu, rotated in H), its Givens rotation, g and the residual
-// estimate; with HZ also a_NJ (into h1) and the update coefficients b (h2),
-// f, e and 1/nu (inv_norm).  Step 0 sets g[0] = nu = ||r||.
+// estimate; with HZ (a step with z, partials of k_dmultidot) also a_NJ (into
+// h1) and the update coefficients b (h2), f, e and 1/nu (inv_norm); without
+// (the completion of a cycle's last column) the partials are Q^T u in slots
+// [0, NJ) and u.u in slot NJ.  Step 0 sets g[0] = nu = ||r||.
 template <int NJ, bool HZ>
-__global__ __launch_bounds__(1024) void k_dfin(const double* partials, int nblocks, DevScalars* sc) {
+__global__ __launch_bounds__(1024) void k_dfin(const double* partials, int nblocks, DevScalars* sc, double* poll,
+                                               double stamp) {
   constexpr int NS = HZ ? 2 * NJ + 2 : NJ + 1, IA = HZ ? 2 * NJ : NJ, ld = kMaxRestart + 1,
                 NC = NJ > 0 ? NJ : 1;
   __shared__ double sv[NS];
@@ -471,6 +475,7 @@ __global__ __launch_bounds__(1024) void k_dfin(const double* partials, int nbloc
     sc_[0] = nu;
     sc_[1] = inv;
     sc->norm = nu;
+    double est = nu;
     if (NJ == 0) {
       sc->g[0] = nu;
       sc->resid = nu;
@@ -500,7 +505,14 @@ __global__ __launch_bounds__(1024) void k_dfin(const double* partials, int nbloc
       for (int i = 0; i <= NJ; ++i) Hc[i] = hc[i];
       sc->g[NJ - 1] = cr * sgj;
       sc->g[NJ] = -sr * sgj;
-      sc->resid = fabs(sr * sgj);
+      est = fabs(sr * sgj);
+      sc->resid = est;
+    }
+    if (poll) {
+      // residual estimate of this step, then its stamp, to coherent pinned
+      // host memory
+      __hip_atomic_store(&poll[1 + NJ], est, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&poll[0], stamp, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
   if (NJ == 0 && tid > 0 && tid <= kMaxRestart) sc->g[tid] = 0.0;
@@ -541,9 +553,12 @@ __global__ __launch_bounds__(1024) void k_dfin(const double* partials, int nbloc
 
 // Update sweep of step NJ: q_NJ = (u - Q b) / nu over slot NJ of V, and the
 // next once-projected vector u_{NJ+1} = z / nu - e u - Q f into slot NJ+1.
-template <int NJ>
+// With DOTS (the last step of a cycle) the sweep also forms the partials of
+// the completion of column NJ: q_i . u_{NJ+1} for i <= NJ and
+// u_{NJ+1} . u_{NJ+1}: slots [0, NJ] and NJ + 1.
+template <int NJ, bool DOTS = false>
 __global__ __launch_bounds__(256) void k_dupdate(int64_t n, double* V, const double* __restrict__ z,
-                                                 const DevScalars* sc) {
+                                                 const DevScalars* sc, double* partials) {
   double bq[NJ > 0 ? NJ : 1], fq[NJ > 0 ? NJ : 1];
 #pragma unroll
   for (int i = 0; i < NJ; ++i) { bq[i] = sc->h2[i]; fq[i] = sc->f[i]; }
@@ -551,6 +566,9 @@ __global__ __launch_bounds__(256) void k_dupdate(int64_t n, double* V, const dou
   const double* __restrict__ Q = V;
   double* __restrict__ u = V + (size_t)NJ * n;
   double* __restrict__ un = V + (size_t)(NJ + 1) * n;
+  double acc[DOTS ? NJ + 2 : 1];
+#pragma unroll
+  for (int i = 0; i < (DOTS ? NJ + 2 : 1); ++i) acc[i] = 0.0;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
     double vi[NJ > 0 ? NJ : 1];
 #pragma unroll
@@ -562,34 +580,42 @@ __global__ __launch_bounds__(256) void k_dupdate(int64_t n, double* V, const dou
       q -= bq[i] * vi[i];
       w -= fq[i] * vi[i];
     }
-    u[t] = q * inv;
+    q *= inv;
+    u[t] = q;
     un[t] = w;
+    if constexpr (DOTS) {
+#pragma unroll
+      for (int i = 0; i < NJ; ++i) acc[i] += vi[i] * w;
+      acc[NJ] += q * w;
+      acc[NJ + 1] += w * w;
+    }
   }
+  if constexpr (DOTS) block_partials<NJ + 2>(acc, partials);
 }
 
 #define SDG_NJ0_CASES(X)                                                                                        \
   X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
   X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
 
-enum class Dg { Multidot, MultidotU, Fin, FinU, Update };
+enum class Dg { Multidot, Fin, FinU, Update, UpdateDots };
 
-// Launch a kernel of the delayed scheme for step nj (MultidotU / FinU: the
-// completion of the last column, without z; Fin / FinU take the producer's
-// grid size as `grid`).
+// Launch a kernel of the delayed scheme for step nj (FinU: the completion
+// of the last column of a cycle, from the partials of UpdateDots; Fin / FinU
+// take the producer's grid size as `grid`).
 void launch_dgs(Dg which, int nj, unsigned grid, hipStream_t s, int64_t n, double* V, const double* z,
-                DevScalars* sc, double* partials) {
+                DevScalars* sc, double* partials, double* poll = nullptr, double stamp = 0.0) {
   // a step with z has at most kMaxRestart - 1 final vectors before it
-  require(nj < kMaxRestart || which == Dg::MultidotU || which == Dg::FinU, SDG_EINVAL,
+  require(nj < kMaxRestart || which == Dg::FinU, SDG_EINVAL,
           "Gram-Schmidt basis size out of range");
   switch (nj) {
 #define SDG_DG_Z(N) (N < kMaxRestart ? N : kMaxRestart - 1)
 #define SDG_DG_CASE(N)                                                                                      \
   case N:                                                                                                   \
-    if (which == Dg::Multidot) k_dmultidot<SDG_DG_Z(N), true><<<grid, 256, 0, s>>>(n, V, z, partials);      \
-    else if (which == Dg::MultidotU) k_dmultidot<N, false><<<grid, 256, 0, s>>>(n, V, nullptr, partials);    \
-    else if (which == Dg::Fin) k_dfin<SDG_DG_Z(N), true><<<1, 1024, 0, s>>>(partials, (int)grid, sc);        \
-    else if (which == Dg::FinU) k_dfin<N, false><<<1, 1024, 0, s>>>(partials, (int)grid, sc);                 \
-    else k_dupdate<SDG_DG_Z(N)><<<grid, 256, 0, s>>>(n, V, z, sc);                                          \
+    if (which == Dg::Multidot) k_dmultidot<SDG_DG_Z(N)><<<grid, 256, 0, s>>>(n, V, z, partials);            \
+    else if (which == Dg::Fin) k_dfin<SDG_DG_Z(N), true><<<1, 1024, 0, s>>>(partials, (int)grid, sc, poll, stamp); \
+    else if (which == Dg::FinU) k_dfin<N, false><<<1, 1024, 0, s>>>(partials, (int)grid, sc, nullptr, 0.0); \
+    else if (which == Dg::UpdateDots) k_dupdate<SDG_DG_Z(N), true><<<grid, 256, 0, s>>>(n, V, z, sc, partials); \
+    else k_dupdate<SDG_DG_Z(N)><<<grid, 256, 0, s>>>(n, V, z, sc, nullptr);                                 \
     break;
     SDG_NJ0_CASES(SDG_DG_CASE)
 #undef SDG_DG_CASE
@@ -695,8 +721,8 @@ __global__ __launch_bounds__(256) void k_cgs_final(int64_t n, const double* __re
   block_partials<1>(acc, partials);
 }
 
-// x += sum_i y_i V_i
-template <int NJ>
+// x += sum_i y_i V_i, or x = sum_i y_i V_i (SET)
+template <int NJ, bool SET = false>
 __global__ __launch_bounds__(256) void k_gmres_update(int64_t n, const double* __restrict__ V, double* __restrict__ x,
                                                       const DevScalars* sc) {
   double ys[NJ];
@@ -706,7 +732,7 @@ __global__ __launch_bounds__(256) void k_gmres_update(int64_t n, const double* _
     double vi[NJ];
 #pragma unroll
     for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * n + t];
-    double acc = x[t];
+    double acc = SET ? 0.0 : x[t];
 #pragma unroll
     for (int i = 0; i < NJ; ++i) acc += ys[i] * vi[i];
     x[t] = acc;
@@ -718,7 +744,7 @@ __global__ __launch_bounds__(256) void k_gmres_update(int64_t n, const double* _
   X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
 static_assert(kMaxRestart == 32, "the Gram-Schmidt dispatch covers 1..32 basis vectors");
 
-enum class Gs { Multidot, Pass, Final, Update, H1Fin, H2Fin };
+enum class Gs { Multidot, Pass, Final, Update, UpdateSet, H1Fin, H2Fin };
 
 // Launch one of the Gram-Schmidt kernels for nj basis vectors (the
 // finalize kernels H1Fin / H2Fin take the producer's grid size as `grid`).
@@ -732,6 +758,7 @@ void launch_gs(Gs which, int nj, unsigned grid, hipStream_t s, int64_t n, const 
     else if (which == Gs::Final) k_cgs_final<N><<<grid, 256, 0, s>>>(n, V, w, sc, partials);  \
     else if (which == Gs::H1Fin) k_h1_fin<N><<<1, 256, 0, s>>>(partials, (int)grid, sc);       \
     else if (which == Gs::H2Fin) k_h2_fin<N><<<1, 256, 0, s>>>(partials, (int)grid, sc);       \
+    else if (which == Gs::UpdateSet) k_gmres_update<N, true><<<grid, 256, 0, s>>>(n, V, w, sc); \
     else k_gmres_update<N><<<grid, 256, 0, s>>>(n, V, w, sc);                                 \
     break;
     SDG_NJ_CASES(SDG_GS_CASE)
@@ -827,32 +854,28 @@ __global__ void k_gmres_start(DevScalars* sc) {
 }
 
 // Back substitution R y = g for the leading k x k triangle.
-__global__ void k_gmres_trisolve(DevScalars* sc, int k) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const int ld = kMaxRestart + 1;
-    for (int i = k - 1; i >= 0; --i) {
-      double s = sc->g[i];
-      for (int l = i + 1; l < k; ++l) s -= sc->H[(size_t)l * ld + i] * sc->y[l];
-      const double d = sc->H[(size_t)i * ld + i];
-      sc->y[i] = d != 0.0 ? s / d : 0.0;
+// y = R^-1 g for the k x k upper triangle R of the rotated Hessenberg
+// matrix, one wavefront: lane l holds row l of R and the running right-hand
+// side r_l; column by column from the last, y_i = r_i / R_ii is broadcast
+// and the lanes above subtract R_li y_i.
+__global__ __launch_bounds__(64) void k_gmres_trisolve(DevScalars* sc, int k) {
+  constexpr int ld = kMaxRestart + 1;
+  const int l = threadIdx.x;
+  double hrow[kMaxRestart];
+#pragma unroll
+  for (int i = 0; i < kMaxRestart; ++i) hrow[i] = (l < k && i < k) ? sc->H[(size_t)i * ld + l] : 0.0;
+  double r = l < k ? sc->g[l] : 0.0, y = 0.0;
+#pragma unroll
+  for (int i = kMaxRestart - 1; i >= 0; --i) {
+    if (i < k) {
+      const double ri = __shfl(r, i, 64);
+      const double d = __shfl(hrow[i], i, 64);
+      const double yi = d != 0.0 ? ri / d : 0.0;
+      if (l == i) y = yi;
+      if (l < i) r -= hrow[i] * yi;
     }
   }
-}
-
-// x += sum_i y_i V_i
-template <int MAXJ>
-__global__ void k_gmres_update(int64_t n, int k, const double* __restrict__ V, double* __restrict__ x,
-                               const DevScalars* sc) {
-  __shared__ double ys[MAXJ];
-  if (threadIdx.x < k) ys[threadIdx.x] = sc->y[threadIdx.x];
-  __syncthreads();
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-    double acc = x[t];
-#pragma unroll
-    for (int i = 0; i < MAXJ; ++i)
-      if (i < k) acc += ys[i] * V[(size_t)i * n + t];
-    x[t] = acc;
-  }
+  if (l < k) sc->y[l] = y;
 }
 
 bool debug_krylov() {
@@ -1036,8 +1059,8 @@ static void gmres_correction(Ctx& c, int kk, double* x, const KrylovCfg& k, hipS
   k_gmres_trisolve<<<1, 64, 0, s>>>(sc, kk);
   check_launch();
   if (k.precond != SDG_PRECOND_NONE) {
-    vec_fill(n, 0.0, t, s);
-    if (kk > 0) launch_gs(Gs::Update, kk, vg, s, n, V, t, sc, nullptr);
+    if (kk > 0) launch_gs(Gs::UpdateSet, kk, vg, s, n, V, t, sc, nullptr);
+    else vec_fill(n, 0.0, t, s);
     check_launch();
     apply_precond(c, k.precond, t, w, k.transpose, s);
     vec_axpby(n, 1.0, w, 1.0, x, s);
@@ -1047,10 +1070,39 @@ static void gmres_correction(Ctx& c, int kk, double* x, const KrylovCfg& k, hipS
   }
 }
 
+// Residual estimate of step j of the current delayed-GMRES cycle, whose
+// finalize carried `stamp`: the device writes the estimate of step j into
+// slot 1 + j and then the stamp into slot 0 of coherent pinned memory, so the
+// host waits for that step without draining the stream and decides on that
+// step's value alone (the same decision on every run).  Device errors end
+// the wait.
+static double load_acquire(const double* p) {
+  const uint64_t bits = __atomic_load_n(reinterpret_cast<const uint64_t*>(p), __ATOMIC_ACQUIRE);
+  double d;
+  std::memcpy(&d, &bits, sizeof d);
+  return d;
+}
+
+static double wait_poll(Ctx& c, int j, double stamp, hipStream_t s) {
+  for (long spin = 1;; ++spin) {
+    if (load_acquire(&c.h_poll[0]) >= stamp) return load_acquire(&c.h_poll[1 + j]);
+    if (spin % 4096 == 0) {
+      const hipError_t e = hipStreamQuery(s);
+      if (e == hipSuccess) {
+        require(load_acquire(&c.h_poll[0]) >= stamp, SDG_EDEVICE, "convergence poll: estimate not written");
+        return load_acquire(&c.h_poll[1 + j]);
+      }
+      if (e != hipErrorNotReady) SDG_HIP(e);
+    }
+  }
+}
+
 // Restarted GMRES with right preconditioning and delayed
 // reorthogonalisation (one reduction and two sweeps over the basis per
-// step; see k_dmultidot).  Step j completes Hessenberg column j-1, so the
-// residual estimate read every `check_every` steps lags by one step.
+// step; see k_dmultidot).  Step j completes Hessenberg column j-1.  Every
+// `check_every` steps the host reads the residual estimate of the step two
+// steps back (wait_poll), so the device always has queued work while the
+// host decides; a converged cycle ends with all columns complete so far.
 static SolveResult solve_gmres_delayed(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s) {
   SolveResult res;
   const int64_t n = c.n_slab;
@@ -1083,6 +1135,7 @@ static SolveResult solve_gmres_delayed(Ctx& c, const double* b, double* x, const
     if (res.rel_res <= k.rtol) { res.converged = true; break; }
     if (total >= k.max_iter) break;
     int j = 0, kk = -1;
+    double stamps[kMaxRestart];
     for (; j < m && total < k.max_iter; ++j) {
       double* uj = V + (size_t)j * n;
       if (pre) {
@@ -1094,24 +1147,27 @@ static SolveResult solve_gmres_delayed(Ctx& c, const double* b, double* x, const
       ++res.matvecs;
       launch_dgs(Dg::Multidot, j, rg, s, n, V, w, sc, c.d_partials.p);
       check_launch();
-      launch_dgs(Dg::Fin, j, rg, s, n, V, w, sc, c.d_partials.p);
+      stamps[j] = ++c.poll_seq;
+      launch_dgs(Dg::Fin, j, rg, s, n, V, w, sc, c.d_partials.p, c.d_poll, stamps[j]);
       check_launch();
-      launch_dgs(Dg::Update, j, vg, s, n, V, w, sc, c.d_partials.p);
+      // the last step of a cycle also forms the partials that complete its column
+      const bool last = j + 1 == m || total + 1 >= k.max_iter;
+      if (last) launch_dgs(Dg::UpdateDots, j, rg, s, n, V, w, sc, c.d_partials.p);
+      else launch_dgs(Dg::Update, j, vg, s, n, V, w, sc, c.d_partials.p);
       check_launch();
       ++total;
       ++res.iters;
-      if (j > 0 && j % check_every == 0) {
-        // columns 0..j-1 are complete
-        double est = read_scalar(c, &sc->resid, s);
+      if (j >= 2 && j % check_every == 0) {
+        // estimate of step j-2; after this step columns 0..j-1 are complete
+        const double est = wait_poll(c, j - 2, stamps[j - 2], s);
         if (debug_krylov()) std::fprintf(stderr, "[gmres]   it %d est rel res %.3e\n", total, est / res.bnorm);
         require(std::isfinite(est), SDG_ENONFINITE, "non-finite residual estimate");
         if (est <= k.rtol * res.bnorm) { kk = j; break; }
       }
     }
     if (kk < 0) {
-      // j steps taken: complete column j-1 from u_j (slot j)
-      launch_dgs(Dg::MultidotU, j, rg, s, n, V, nullptr, sc, c.d_partials.p);
-      check_launch();
+      // j steps taken: complete column j-1 from u_j (slot j), whose partials
+      // the last step's update sweep formed
       launch_dgs(Dg::FinU, j, rg, s, n, V, nullptr, sc, c.d_partials.p);
       check_launch();
       kk = j;
