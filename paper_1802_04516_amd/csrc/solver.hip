@@ -245,58 +245,60 @@ __global__ void k_block_apply(int64_t n_elem, int nv, const float* __restrict__ 
 // Factored element block inverse (several time nodes):
 //   y_e = (I (x) Q_e) blockdiag_i(B_{e,i}) (I (x) Q_e^T) x_e
 // (B^T for the transpose).  NV = NG*NS threads per element, several elements
-// per workgroup; x, u and w of an element are staged in LDS.  The sizes are
-// compile-time so that every loop unrolls and its loads are in flight
-// together.
+// per workgroup, one element per thread group; every global load of the
+// element (x, the column and the row of Q_e, the row of B_{e,i}) is issued
+// first so that they are all in flight together, then x, u and w pass
+// through LDS.
 template <int NG, int NS>
 __global__ __launch_bounds__(256) void k_block_apply_fact(int64_t n_elem, const float* __restrict__ Q,
                                                           const float* __restrict__ B, const double* __restrict__ x,
                                                           double* __restrict__ y, int transpose, int64_t cstride) {
   constexpr int NV = NG * NS;
   constexpr int EPB = 256 / NV;
-  __shared__ double sm[EPB * 2 * NV];
+  __shared__ double sx[EPB * NV], su[EPB * NV];
   x += blockIdx.y * cstride;
   y += blockIdx.y * cstride;
   const int le = threadIdx.x / NV, r = threadIdx.x % NV;
   const int a = r / NS, i = r % NS;
-  double* sx = sm + (size_t)min(le, EPB - 1) * 2 * NV;
-  double* su = sx + NV;
-  for (int64_t e0 = (int64_t)blockIdx.x * EPB; e0 < n_elem; e0 += (int64_t)gridDim.x * EPB) {
-    const int64_t e = e0 + le;
-    const bool act = le < EPB && e < n_elem;
-    const float* Qe = Q + (size_t)(act ? e : 0) * NS * NS;
-    if (act) sx[r] = x[e * NV + r];
-    __syncthreads();
-    if (act) {  // u[a][i] = sum_ck Q[ck][i] x[a][ck]
-      float qc[NS];
+  const int64_t e = (int64_t)blockIdx.x * EPB + le;
+  const bool act = le < EPB && e < n_elem;
+  float qc[NS], qr[NS], bq[NG];
+  double xv = 0.0;
+  if (act) {
+    const float* Qe = Q + (size_t)e * NS * NS;
+    const float* Be = B + ((size_t)e * NS + i) * NG * NG;
+    xv = x[e * NV + r];
 #pragma unroll
-      for (int ck = 0; ck < NS; ++ck) qc[ck] = Qe[ck * NS + i];
-      double acc = 0.0;
+    for (int ck = 0; ck < NS; ++ck) qc[ck] = Qe[ck * NS + i];
 #pragma unroll
-      for (int ck = 0; ck < NS; ++ck) acc += (double)qc[ck] * sx[a * NS + ck];
-      su[r] = acc;
-    }
-    __syncthreads();
-    double wv = 0.0;
-    if (act) {  // w[a][i] = sum_b B_i[a][b] u[b][i]
-      const float* Be = B + ((size_t)e * NS + i) * NG * NG;
+    for (int ii = 0; ii < NS; ++ii) qr[ii] = Qe[i * NS + ii];
 #pragma unroll
-      for (int b = 0; b < NG; ++b) wv += (double)(transpose ? Be[b * NG + a] : Be[a * NG + b]) * su[b * NS + i];
-    }
-    __syncthreads();
-    if (act) sx[r] = wv;
-    __syncthreads();
-    if (act) {  // y[a][ck] = sum_i Q[ck][i] w[a][i], here i plays ck
-      const float* Qr = Qe + (size_t)i * NS;
-      float qr[NS];
+    for (int b = 0; b < NG; ++b) bq[b] = transpose ? Be[b * NG + a] : Be[a * NG + b];
+  }
+  const int ls = le < EPB ? le : EPB - 1;
+  double* sxe = sx + ls * NV;
+  double* sue = su + ls * NV;
+  if (act) sxe[r] = xv;
+  __syncthreads();
+  if (act) {  // u[a][i] = sum_ck Q[ck][i] x[a][ck]
+    double acc = 0.0;
 #pragma unroll
-      for (int ii = 0; ii < NS; ++ii) qr[ii] = Qr[ii];
-      double acc = 0.0;
+    for (int ck = 0; ck < NS; ++ck) acc += (double)qc[ck] * sxe[a * NS + ck];
+    sue[r] = acc;
+  }
+  __syncthreads();
+  double wv = 0.0;
+  if (act) {  // w[a][i] = sum_b B_i[a][b] u[b][i]
 #pragma unroll
-      for (int ii = 0; ii < NS; ++ii) acc += (double)qr[ii] * sx[a * NS + ii];
-      y[e * NV + r] = acc;
-    }
-    __syncthreads();
+    for (int b = 0; b < NG; ++b) wv += (double)bq[b] * sue[b * NS + i];
+  }
+  if (act) sxe[r] = wv;  // every read of x happened before the last barrier
+  __syncthreads();
+  if (act) {  // y[a][i] = sum_ii Q[i][ii] w[a][ii]
+    double acc = 0.0;
+#pragma unroll
+    for (int ii = 0; ii < NS; ++ii) acc += (double)qr[ii] * sxe[a * NS + ii];
+    y[e * NV + r] = acc;
   }
 }
 
@@ -955,8 +957,9 @@ void launch_block_apply_fact(int64_t n_elem, int ng, int ns, const float* Q, con
   auto go = [&](auto kernel, int nv) {
     const int epb = 256 / nv;
     const int64_t groups = (n_elem + epb - 1) / epb;
-    const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 65535));
-    kernel<<<dim3(g, gy), epb * nv, 0, s>>>(n_elem, Q, B, x, y, transpose ? 1 : 0, cstride);
+    require(groups <= 0x7fffffff, SDG_EINVAL, "too many elements for the block preconditioner grid");
+    kernel<<<dim3((unsigned)std::max<int64_t>(1, groups), gy), epb * nv, 0, s>>>(n_elem, Q, B, x, y,
+                                                                                transpose ? 1 : 0, cstride);
   };
 #define SDG_FACT(NG_, NS_) \
   if (ng == NG_ && ns == NS_) { go(k_block_apply_fact<NG_, NS_>, NG_ * NS_); check_launch(); return; }
