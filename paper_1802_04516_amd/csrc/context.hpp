@@ -44,6 +44,10 @@ struct SysScalars {
   double y[kMaxRestart];
   double dot, norm, inv_norm, resid, tol_abs, bnorm, rnorm;
   int32_t active, k;
+  // delayed reorthogonalisation (as DevScalars)
+  double Hu[(kMaxRestart + 1) * kMaxRestart];
+  double f[kMaxRestart + 1];
+  double e;
 };
 constexpr int kMaxSystems = 1024;
 

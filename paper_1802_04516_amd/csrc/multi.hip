@@ -14,13 +14,17 @@
 // A system whose residual estimate reaches its tolerance is switched off on
 // the device (its Gram-Schmidt work is skipped); its correction is applied at
 // the end of the cycle with the Arnoldi steps it took.  The host polls the
-// device count of active systems every check_every iterations.
+// device count of active systems every check_every iterations.  By default
+// the Arnoldi steps delay each vector's second projection to the next step
+// (as the single-system solver); with SDG_SOLVE_CGS2 both projections run
+// within the step.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <functional>
 
 #include "context.hpp"
+#include "reduce.hpp"
 
 namespace sdg {
 
@@ -328,6 +332,252 @@ __global__ __launch_bounds__(256) void km_trisolve(int S, SysScalars* ss) {
   if (l < kMaxRestart) q.y[l] = y;
 }
 
+// ---- Delayed reorthogonalisation for every system (the scheme of the
+// single-system solver: one segmented reduction and two sweeps per step).
+
+// Slots [0, NJ) = Q^T u, [NJ, 2NJ) = Q^T z, 2NJ = u.u, 2NJ+1 = u.z per block
+// of an active system, Q = V[0..NJ), u = V[NJ].  Block 0 also clears the
+// count of active systems that the following finalize forms.
+template <int NJ>
+__global__ __launch_bounds__(kT) void km_dmultidot(BlockMap bm, int64_t ld, const double* __restrict__ V,
+                                                   const double* __restrict__ z, const SysScalars* ss,
+                                                   double* partials, int* nactive) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *nactive = 0;
+  const int sys = bm.seg[blockIdx.x];
+  if (!ss[sys].active) return;
+  constexpr int NS = 2 * NJ + 2;
+  double acc[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) acc[i] = 0.0;
+  const double* __restrict__ u = V + (size_t)NJ * ld;
+  const int64_t e = bm.end[blockIdx.x];
+  for (int64_t t = bm.beg[blockIdx.x] + threadIdx.x; t < e; t += kT) {
+    const double ut = u[t], zt = z[t];
+    double vi[NJ > 0 ? NJ : 1];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * ld + t];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+      acc[i] += vi[i] * ut;
+      acc[NJ + i] += vi[i] * zt;
+    }
+    acc[2 * NJ] += ut * ut;
+    acc[2 * NJ + 1] += ut * zt;
+  }
+  block_partials_to<NS>(acc, partials, bm.nblocks);
+}
+
+// Finalize of step NJ, one workgroup per active system: its four
+// wavefronts add the system's block partials of every slot (thread = block,
+// then a butterfly reduce-scatter over the slots per wavefront and the
+// wavefronts' sums in wave order), then wavefront 0 forms nu, Hessenberg
+// column NJ-1 (unrotated and rotated), its Givens rotation, g, the residual
+// estimate and k = NJ; with HZ also a_NJ, b, f, e, 1/nu, the convergence flag
+// and the count of active systems; without (the completion of a cycle's
+// last column, slots [0, NJ) = Q^T u and NJ = u.u) only the column.
+template <int NJ, bool HZ>
+__global__ __launch_bounds__(kT) void km_dfin(const double* partials, int nblocks, const int* seg_blk0, int S,
+                                              SysScalars* ss, int* nactive) {
+  constexpr int NS = HZ ? 2 * NJ + 2 : NJ + 1, IA = HZ ? 2 * NJ : NJ, ld = kMaxRestart + 1;
+  constexpr int NC = NJ > 0 ? NJ : 1, NSP = pow2ceil(NS);
+  __shared__ double sw[kT / 64][NSP];
+  __shared__ double sv[NS];
+  __shared__ double sHu[(NJ + 1) * NC];
+  __shared__ double sHb[NJ + 1];
+  __shared__ double scx[4];
+  __shared__ double sa[NC], scs[NC], ssn[NC], sgj;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int s = blockIdx.x;
+  if (s >= S || !ss[s].active) return;  // uniform over the workgroup
+  SysScalars& q = ss[s];
+  for (int i = threadIdx.x; i < (NJ + 1) * NJ; i += kT) {
+    const int col = i / (NJ + 1), row = i % (NJ + 1);
+    sHu[i] = col + 1 < NJ && row <= col + 1 ? q.Hu[(size_t)col * ld + row] : 0.0;
+  }
+  // what the serial part reads, staged with parallel loads
+  if (threadIdx.x < NJ) {
+    sa[threadIdx.x] = q.h1[threadIdx.x];
+    if (threadIdx.x + 1 < NJ) {
+      scs[threadIdx.x] = q.cs[threadIdx.x];
+      ssn[threadIdx.x] = q.sn[threadIdx.x];
+    }
+  }
+  if (NJ > 0 && threadIdx.x == 64) sgj = q.g[NJ > 0 ? NJ - 1 : 0];
+  {
+    double acc[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) acc[i] = 0.0;
+    const int b0 = seg_blk0[s], nb = seg_blk0[s + 1] - b0;
+    for (int b = threadIdx.x; b < nb; b += kT) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) acc[i] += partials[(size_t)i * nblocks + b0 + b];
+    }
+    int slot;
+    bool first;
+    const double v = wave_reduce_scatter<NS>(acc, lane, slot, first);
+    if (first) sw[wv][slot] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NS) {
+    double t = 0.0;
+    for (int w = 0; w < kT / 64; ++w) t += sw[w][threadIdx.x];
+    sv[threadIdx.x] = t;
+  }
+  __syncthreads();
+  if (wv != 0) return;
+  if (lane == 0) {
+    double bb = 0.0;
+    for (int i = 0; i < NJ; ++i) bb += sv[i] * sv[i];
+    const double nu2 = sv[IA] - bb;
+    const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+    const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
+    scx[0] = nu;
+    scx[1] = inv;
+    q.norm = nu;
+    if (NJ == 0) {
+      q.g[0] = nu;
+      q.resid = nu;
+    } else {
+      double hc[NJ + 1];
+      for (int i = 0; i < NJ; ++i) hc[i] = sa[i] + sv[i];
+      hc[NJ] = nu;
+      for (int i = 0; i <= NJ; ++i) sHu[(NJ - 1) * (NJ + 1) + i] = hc[i];
+      for (int i = 0; i + 1 < NJ; ++i) {
+        const double a = hc[i], b = hc[i + 1];
+        hc[i] = scs[i] * a + ssn[i] * b;
+        hc[i + 1] = -ssn[i] * a + scs[i] * b;
+      }
+      const double a = hc[NJ - 1], b = hc[NJ];
+      const double rad = hypot(a, b);
+      const double cr = rad > 0.0 ? a / rad : 1.0, sr = rad > 0.0 ? b / rad : 0.0;
+      q.cs[NJ - 1] = cr;
+      q.sn[NJ - 1] = sr;
+      hc[NJ - 1] = rad;
+      hc[NJ] = 0.0;
+      double* Hc = q.H + (size_t)(NJ - 1) * ld;
+      for (int i = 0; i <= NJ; ++i) Hc[i] = hc[i];
+      q.g[NJ - 1] = cr * sgj;
+      q.g[NJ] = -sr * sgj;
+      q.resid = fabs(sr * sgj);
+    }
+    q.k = NJ;
+    if (HZ && NJ > 0 && (q.resid <= q.tol_abs || nu == 0.0)) q.active = 0;
+    if (HZ) atomicAdd(nactive, q.active);  // integer count: order-independent
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (NJ > 0 && lane <= NJ) q.Hu[(size_t)(NJ - 1) * ld + lane] = sHu[(NJ - 1) * (NJ + 1) + lane];
+  if (!HZ) return;
+  if (lane <= NJ) {
+    double acc = 0.0;
+    for (int i = 0; i < NJ; ++i) acc += sHu[i * (NJ + 1) + lane] * sv[i];  // zero below the subdiagonal
+    sHb[lane] = acc;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const double inv = scx[1];
+  double e = 0.0;
+  if (lane == 0) {
+    double bc = 0.0;
+    for (int i = 0; i < NJ; ++i) bc += sv[i] * sv[NJ + i];
+    const double aj = ((sv[2 * NJ + 1] - bc) * inv - sHb[NJ]) * inv;
+    const double dj = sHb[NJ] * inv + aj;
+    e = dj * inv;
+    q.h1[NJ] = aj;
+    q.e = e;
+    q.inv_norm = inv;
+  }
+  e = __shfl(e, 0, 64);
+  if (lane < NJ) {
+    const double ai = (sv[NJ + lane] - sHb[lane]) * inv;
+    const double di = sHb[lane] * inv + ai;
+    q.h1[lane] = ai;
+    q.h2[lane] = sv[lane];
+    q.f[lane] = di - e * sv[lane];
+  }
+}
+
+// Update sweep of step NJ for the active systems: q_NJ = (u - Q b) / nu
+// over slot NJ, u_{NJ+1} = z / nu - e u - Q f into slot NJ+1; with DOTS the
+// partials of the completion of column NJ (q_i . u_{NJ+1}, i <= NJ, and
+// u_{NJ+1} . u_{NJ+1}).
+template <int NJ, bool DOTS>
+__global__ __launch_bounds__(kT) void km_dupdate(BlockMap bm, int64_t ld, double* V, const double* __restrict__ z,
+                                                 const SysScalars* ss, double* partials) {
+  const int sys = bm.seg[blockIdx.x];
+  if (!ss[sys].active) return;
+  const SysScalars& q = ss[sys];
+  double bq[NJ > 0 ? NJ : 1], fq[NJ > 0 ? NJ : 1];
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) { bq[i] = q.h2[i]; fq[i] = q.f[i]; }
+  const double inv = q.inv_norm, e = q.e;
+  const double* __restrict__ Q = V;
+  double* __restrict__ u = V + (size_t)NJ * ld;
+  double* __restrict__ un = V + (size_t)(NJ + 1) * ld;
+  double acc[DOTS ? NJ + 2 : 1];
+#pragma unroll
+  for (int i = 0; i < (DOTS ? NJ + 2 : 1); ++i) acc[i] = 0.0;
+  const int64_t end = bm.end[blockIdx.x];
+  for (int64_t t = bm.beg[blockIdx.x] + threadIdx.x; t < end; t += kT) {
+    double vi[NJ > 0 ? NJ : 1];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) vi[i] = Q[(size_t)i * ld + t];
+    const double ut = u[t];
+    double qv = ut, w = z[t] * inv - e * ut;
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+      qv -= bq[i] * vi[i];
+      w -= fq[i] * vi[i];
+    }
+    qv *= inv;
+    u[t] = qv;
+    un[t] = w;
+    if constexpr (DOTS) {
+#pragma unroll
+      for (int i = 0; i < NJ; ++i) acc[i] += vi[i] * w;
+      acc[NJ] += qv * w;
+      acc[NJ + 1] += w * w;
+    }
+  }
+  if constexpr (DOTS) block_partials_to<NJ + 2>(acc, partials, bm.nblocks);
+}
+
+#define SDG_MNJ0_CASES(X)                                                                                       \
+  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
+  X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+
+enum class Dm { Multidot, Fin, FinU, Update, UpdateDots };
+
+void launch_dm(Dm op, int nj, const MultiSys& m, const BlockMap& bm, hipStream_t s, double* V, const double* z) {
+  require(nj < kMaxRestart || op == Dm::FinU, SDG_EINVAL, "Gram-Schmidt basis size out of range");
+  const unsigned g = (unsigned)bm.nblocks;
+  const unsigned gs = (unsigned)m.S;
+  const int64_t ld = m.n_total;
+  SysScalars* ss = m.d_ss.p;
+  double* pt = m.d_partials.p;
+  switch (nj) {
+#define SDG_DM_Z(N) (N < kMaxRestart ? N : kMaxRestart - 1)
+#define SDG_DM_CASE(N)                                                                                            \
+  case N:                                                                                                         \
+    if (op == Dm::Multidot) km_dmultidot<SDG_DM_Z(N)><<<g, kT, 0, s>>>(bm, ld, V, z, ss, pt, m.d_nactive.p);     \
+    else if (op == Dm::Fin)                                                                                       \
+      km_dfin<SDG_DM_Z(N), true><<<gs, kT, 0, s>>>(pt, bm.nblocks, m.d_seg_blk0.p, m.S, ss, m.d_nactive.p);       \
+    else if (op == Dm::FinU)                                                                                      \
+      km_dfin<N, false><<<gs, kT, 0, s>>>(pt, bm.nblocks, m.d_seg_blk0.p, m.S, ss, m.d_nactive.p);               \
+    else if (op == Dm::UpdateDots) km_dupdate<SDG_DM_Z(N), true><<<g, kT, 0, s>>>(bm, ld, V, z, ss, pt);           \
+    else km_dupdate<SDG_DM_Z(N), false><<<g, kT, 0, s>>>(bm, ld, V, z, ss, pt);                                 \
+    break;
+    SDG_MNJ0_CASES(SDG_DM_CASE)
+#undef SDG_DM_CASE
+#undef SDG_DM_Z
+    default:
+      throw Error(SDG_EINVAL, "Gram-Schmidt basis size out of range");
+  }
+  SDG_HIP(hipGetLastError());
+}
+
 #define SDG_MNJ_CASES(X)                                                                                   \
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
   X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
@@ -413,7 +663,7 @@ void MultiSys::build(const std::vector<int64_t>& offsets) {
   SDG_HIP(hipMemcpy(d_blk_end.p, end.data(), end.size() * sizeof(int64_t), hipMemcpyHostToDevice));
   d_ss.alloc(S);
   SDG_HIP(hipMemset(d_ss.p, 0, S * sizeof(SysScalars)));
-  d_partials.alloc((size_t)(kMaxRestart + 1) * n_blocks);
+  d_partials.alloc((size_t)(2 * kMaxRestart + 2) * n_blocks);
   d_nactive.alloc(1);
   if (!h_pinned) SDG_HIP(hipHostMalloc((void**)&h_pinned, 16 * sizeof(int), hipHostMallocDefault));
 }
@@ -462,10 +712,72 @@ void multi_residual(MultiSys& m, const double* b, const double* x, hipStream_t s
   SDG_HIP(hipGetLastError());
 }
 
+// One restart cycle with delayed reorthogonalisation for every system.  The
+// residual r = b - A x goes straight into slot 0 of V as the first,
+// unnormalised basis vector; step j completes each system's Hessenberg
+// column j-1 and switches systems whose estimate has converged off; the last
+// step's update sweep forms the dots that complete the last column.
+static int multi_cycle_delayed(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
+                               const std::function<void(const double*, double*)>& op,
+                               const std::function<void(const double*, double*)>* pre, double* V, double* w,
+                               double* t, bool poll, int max_steps, int* matvecs, bool* all_converged) {
+  const int64_t n = m.n_total;
+  const BlockMap bm = map_of(m);
+  SysScalars* ss = m.d_ss.p;
+  const int check_every = std::max(1, k.check_every);
+  *all_converged = false;
+  multi_residual(m, b, x, s, op, V);
+  ++*matvecs;
+  if (poll) {
+    if (read_int(m.d_nactive.p, m.h_pinned, s) == 0) {
+      *all_converged = true;
+      return 0;
+    }
+    if (max_steps <= 0) return 0;
+  }
+  const int steps = std::min(k.restart, max_steps);
+  int j = 0;
+  bool done = false;
+  for (; j < steps; ++j) {
+    double* vj = V + (size_t)j * n;
+    if (pre) {
+      (*pre)(vj, t);
+      op(t, w);
+    } else {
+      op(vj, w);
+    }
+    ++*matvecs;
+    const bool last = j + 1 == steps;
+    launch_dm(Dm::Multidot, j, m, bm, s, V, w);
+    launch_dm(Dm::Fin, j, m, bm, s, V, w);
+    launch_dm(last ? Dm::UpdateDots : Dm::Update, j, m, bm, s, V, w);
+    if (poll && !last && (j + 1) % check_every == 0) {
+      if (read_int(m.d_nactive.p, m.h_pinned, s) == 0) {
+        done = true;
+        ++j;
+        break;
+      }
+    }
+  }
+  if (!done) launch_dm(Dm::FinU, j, m, bm, s, V, nullptr);
+  km_trisolve<<<(unsigned)((m.S * 64 + 255) / 256), 256, 0, s>>>(m.S, ss);
+  SDG_HIP(hipGetLastError());
+  if (pre) {
+    vec_fill(n, 0.0, t, s);
+    launch_m(Op::Update, j, bm, s, n, V, t, ss, nullptr);
+    (*pre)(t, w);
+    vec_axpby(n, 1.0, w, 1.0, x, s);
+  } else {
+    launch_m(Op::Update, j, bm, s, n, V, x, ss, nullptr);
+  }
+  return j;
+}
+
 int multi_cycle(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
                 const std::function<void(const double*, double*)>& op,
                 const std::function<void(const double*, double*)>* pre, double* V, double* r, double* w, double* t,
                 bool poll, int max_steps, int* matvecs, bool* all_converged) {
+  if (k.delayed) return multi_cycle_delayed(m, b, x, k, s, op, pre, V, w, t, poll, max_steps, matvecs, all_converged);
   const int64_t n = m.n_total;
   const BlockMap bm = map_of(m);
   SysScalars* ss = m.d_ss.p;

@@ -13,6 +13,7 @@
 #include <cstring>
 
 #include "context.hpp"
+#include "reduce.hpp"
 
 namespace sdg {
 
@@ -314,58 +315,9 @@ __global__ void k_cg_p(int64_t n, double* __restrict__ p, const double* __restri
 // parameter: every row's NJ loads are independent and unconditional, so a
 // wavefront keeps them all in flight.
 
-constexpr int pow2ceil(int x) { return x <= 1 ? 1 : 2 * pow2ceil((x + 1) / 2); }
-
-// One butterfly exchange of a wavefront reduce-scatter (offset O, CNT
-// accumulators left): a lane keeps one half of its accumulators, sends the
-// other half to lane ^ O and adds what it receives; lanes with bit O set
-// keep the upper half (their slot base moves up by CNT / 2).  With one
-// accumulator left the exchange is a plain butterfly sum.
-template <int CNT, int O>
-__device__ inline void bfly(double* v, int lane, int& base) {
-  if constexpr (O > 0) {
-    if constexpr (CNT > 1) {
-      constexpr int H = CNT / 2;
-      const bool up = (lane & O) != 0;
-#pragma unroll
-      for (int i = 0; i < H; ++i) {
-        const double send = up ? v[i] : v[i + H];
-        const double keep = up ? v[i + H] : v[i];
-        v[i] = keep + __shfl_xor(send, O, 64);
-      }
-      if (up) base += H;
-      bfly<H, O / 2>(v, lane, base);
-    } else {
-      v[0] += __shfl_xor(v[0], O, 64);
-      bfly<1, O / 2>(v, lane, base);
-    }
-  }
-}
-
-// Per-block sums of NS (<= 64) accumulators -> partials[i][block]
-// (slot-major).  Within a wavefront a butterfly reduce-scatter over the six
-// lane offsets 32 .. 1 moves about NSP values per lane (NSP = NS rounded up
-// to a power of two) instead of 6 NS for one shuffle tree per slot; lane l
-// ends with the wave sum of slot l / (64 / NSP).  The waves' sums are then
-// added in wave order, so the result is deterministic.
 template <int NS>
 __device__ inline void block_partials(const double (&acc)[NS], double* partials) {
-  constexpr int NSP = pow2ceil(NS), REP = 64 / NSP;
-  static_assert(NSP <= 64, "at most 64 accumulators per block reduction");
-  __shared__ double shp[16 * NSP];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  double v[NSP];
-#pragma unroll
-  for (int i = 0; i < NSP; ++i) v[i] = i < NS ? acc[i] : 0.0;
-  int base = 0;
-  bfly<NSP, 32>(v, lane, base);
-  if (lane % REP == 0 && base < NS) shp[wid * NSP + base] = v[0];
-  __syncthreads();
-  if (threadIdx.x < NS) {
-    double t = 0.0;
-    for (int w = 0; w < nw; ++w) t += shp[w * NSP + threadIdx.x];
-    partials[(size_t)threadIdx.x * kRedBlocks + blockIdx.x] = t;
-  }
+  block_partials_to<NS>(acc, partials, kRedBlocks);
 }
 
 // h1[i] = V_i . w for i < NJ (classical Gram-Schmidt projections) and, in

@@ -110,8 +110,11 @@ def test_batched_apply_matches_columns_and_oracle(bcase, bvariant):
         ctx.set_batched_variant(old)
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32ir"])
+@pytest.mark.parametrize("precision", ["f64", "f32ir", "f64_cgs2"])
 def test_batched_steps_match_oracle_per_column(bcase, precision):
+    """Batched columns against the oracle column by column; f64_cgs2 runs the
+    multi-system GMRES with both Gram-Schmidt projections within the step
+    (SDG_SOLVE_CGS2) instead of the default delayed one."""
     import paper_1802_04516_amd as sdg
     ctx, R, B, slab = bcase["ctx"], bcase["R"], bcase["B"], bcase["slab"]
     ne, nf = B.topo.n_elem, B.topo.n_face
@@ -126,11 +129,14 @@ def test_batched_steps_match_oracle_per_column(bcase, precision):
     s0 = [0.1 * rng.standard_normal((nf, 3, B.npsi)) for _ in range(R - 1)] + [np.zeros((nf, 3, B.npsi))]
     vg = _gpu(np.stack(v0))
     sg = _gpu(np.stack([_canon(B, s) for s in s0]))
-    prec = sdg.SDG_PREC_F64 if precision == "f64" else sdg.SDG_PREC_F32
+    prec = sdg.SDG_PREC_F32 if precision == "f32ir" else sdg.SDG_PREC_F64
     vo, so = [v.copy() for v in v0], [s.copy() for s in s0]
     for n in range(3):
         amps = _amps(slab, bcase["scheme"], bcase["dt"], n, n_src, scale)
-        info = ctx.step(vg, sg, amps.ravel(), n_rhs=R, opts=_opts(precision=prec, precond=bcase["precond"]))
+        o = _opts(precision=prec, precond=bcase["precond"])
+        if precision == "f64_cgs2":
+            o.flags = sdg.SDG_SOLVE_CGS2
+        info = ctx.step(vg, sg, amps.ravel(), n_rhs=R, opts=o)
         V = vg.cpu().numpy().reshape(R, -1)
         Sg = sg.cpu().numpy().reshape(R, -1)
         worst = 0.0
