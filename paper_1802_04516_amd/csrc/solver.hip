@@ -903,6 +903,115 @@ void launch_block_apply(int64_t n_elem, int nv, const float* P, const double* x,
   check_launch();
 }
 
+// Update sweep of a delayed-GMRES step fused with the factored block
+// preconditioner of the next basis vector: per element (NV = NG*NS rows,
+// several elements per workgroup) q_nj = (u - Q b) / nu over slot nj of V and
+// u_{nj+1} = z / nu - e u - Q f into slot nj+1, as k_dupdate, then
+// t = P^-1 u_{nj+1} from LDS, as k_block_apply_fact, with the same
+// arithmetic in the same order.  nj is a runtime count; the basis loads go
+// in chunks of 8 with every load of a chunk in flight.
+template <int NG, int NS>
+__global__ __launch_bounds__(256) void k_dupdate_pre(int64_t n_elem, int nj, int64_t n, double* V,
+                                                     const double* __restrict__ z, const DevScalars* sc,
+                                                     const float* __restrict__ Qf, const float* __restrict__ Bf,
+                                                     double* __restrict__ tout, int transpose) {
+  constexpr int NV = NG * NS;
+  constexpr int EPB = 256 / NV;
+  __shared__ double sb[kMaxRestart], sf[kMaxRestart];
+  __shared__ double sx[EPB * NV], su[EPB * NV];
+  const int le = threadIdx.x / NV, r = threadIdx.x % NV;
+  const int a = r / NS, i = r % NS;
+  const int64_t e = (int64_t)blockIdx.x * EPB + le;
+  const bool act = le < EPB && e < n_elem;
+  const int64_t row = e * NV + r;
+  if (threadIdx.x < nj) {
+    sb[threadIdx.x] = sc->h2[threadIdx.x];
+    sf[threadIdx.x] = sc->f[threadIdx.x];
+  }
+  const double inv = sc->inv_norm, ee = sc->e;
+  float qc[NS], qr[NS], bq[NG];
+  double ut = 0.0, zt = 0.0;
+  if (act) {
+    const float* Qe = Qf + (size_t)e * NS * NS;
+    const float* Be = Bf + ((size_t)e * NS + i) * NG * NG;
+    ut = V[(size_t)nj * n + row];
+    zt = z[row];
+#pragma unroll
+    for (int ck = 0; ck < NS; ++ck) qc[ck] = Qe[ck * NS + i];
+#pragma unroll
+    for (int ii = 0; ii < NS; ++ii) qr[ii] = Qe[i * NS + ii];
+#pragma unroll
+    for (int b = 0; b < NG; ++b) bq[b] = transpose ? Be[b * NG + a] : Be[a * NG + b];
+  }
+  __syncthreads();
+  double w = 0.0;
+  if (act) {
+    double q = ut;
+    w = zt * inv - ee * ut;
+    for (int i0 = 0; i0 < nj; i0 += 8) {
+      double vi[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) vi[k] = i0 + k < nj ? V[(size_t)(i0 + k) * n + row] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (i0 + k < nj) {
+          q -= sb[i0 + k] * vi[k];
+          w -= sf[i0 + k] * vi[k];
+        }
+      }
+    }
+    V[(size_t)nj * n + row] = q * inv;
+    V[(size_t)(nj + 1) * n + row] = w;
+  }
+  const int ls = le < EPB ? le : EPB - 1;
+  double* sxe = sx + ls * NV;
+  double* sue = su + ls * NV;
+  if (act) sxe[r] = w;
+  __syncthreads();
+  if (act) {  // u[a][i] = sum_ck Q[ck][i] x[a][ck]
+    double acc = 0.0;
+#pragma unroll
+    for (int ck = 0; ck < NS; ++ck) acc += (double)qc[ck] * sxe[a * NS + ck];
+    sue[r] = acc;
+  }
+  __syncthreads();
+  double wv = 0.0;
+  if (act) {  // w[a][i] = sum_b B_i[a][b] u[b][i]
+#pragma unroll
+    for (int b = 0; b < NG; ++b) wv += (double)bq[b] * sue[b * NS + i];
+  }
+  if (act) sxe[r] = wv;
+  __syncthreads();
+  if (act) {  // y[a][i] = sum_ii Q[i][ii] w[a][ii]
+    double acc = 0.0;
+#pragma unroll
+    for (int ii = 0; ii < NS; ++ii) acc += (double)qr[ii] * sxe[a * NS + ii];
+    tout[row] = acc;
+  }
+}
+
+// The fused update + preconditioner above for (ng, ns); false where no
+// factored kernel exists for the element size.
+bool launch_dupdate_pre(int64_t n_elem, int ng, int ns, int nj, int64_t n, double* V, const double* z,
+                        const DevScalars* sc, const float* Q, const float* B, double* t, bool transpose,
+                        hipStream_t s) {
+  auto go = [&](auto kernel, int nv) {
+    const int epb = 256 / nv;
+    const int64_t groups = (n_elem + epb - 1) / epb;
+    require(groups <= 0x7fffffff, SDG_EINVAL, "too many elements for the block preconditioner grid");
+    kernel<<<(unsigned)std::max<int64_t>(1, groups), epb * nv, 0, s>>>(n_elem, nj, n, V, z, sc, Q, B, t,
+                                                                      transpose ? 1 : 0);
+    check_launch();
+  };
+#define SDG_DPRE(NG_, NS_) \
+  if (ng == NG_ && ns == NS_) { go(k_dupdate_pre<NG_, NS_>, NG_ * NS_); return true; }
+#define SDG_DPRE_NS(NS_) SDG_DPRE(2, NS_) SDG_DPRE(3, NS_) SDG_DPRE(4, NS_)
+  SDG_DPRE_NS(6) SDG_DPRE_NS(12) SDG_DPRE_NS(20) SDG_DPRE_NS(30) SDG_DPRE_NS(60)
+#undef SDG_DPRE_NS
+#undef SDG_DPRE
+  return false;
+}
+
 void launch_block_apply_fact(int64_t n_elem, int ng, int ns, const float* Q, const float* B, const double* x,
                              double* y, bool transpose, hipStream_t s, int ncols, int64_t cstride) {
   const unsigned gy = (unsigned)std::max(1, ncols);
@@ -1076,6 +1185,8 @@ static SolveResult solve_gmres_delayed(Ctx& c, const double* b, double* x, const
     return res;
   }
   const unsigned rg = red_grid(n), vg = vgrid(n);
+  // the factored block preconditioner is fused into the update sweep
+  const bool fuse_pre = k.precond == SDG_PRECOND_BLOCK && c.pblk_factored && c.d_Pq.p != nullptr;
   int total = 0;
   for (;;) {
     // r = b - A x is the first (unnormalised) basis vector of the cycle
@@ -1091,14 +1202,16 @@ static SolveResult solve_gmres_delayed(Ctx& c, const double* b, double* x, const
     if (total >= k.max_iter) break;
     int j = 0, kk = -1;
     double stamps[kMaxRestart];
+    bool t_ready = false;  // t already holds P^-1 of slot j (fused into the previous update)
     for (; j < m && total < k.max_iter; ++j) {
       double* uj = V + (size_t)j * n;
       if (pre) {
-        apply_precond(c, k.precond, uj, t, k.transpose, s);
+        if (!t_ready) apply_precond(c, k.precond, uj, t, k.transpose, s);
         apply_op(c, t, w, k.prec, k.transpose, s);
       } else {
         apply_op(c, uj, w, k.prec, k.transpose, s);
       }
+      t_ready = false;
       ++res.matvecs;
       launch_dgs(Dg::Multidot, j, rg, s, n, V, w, sc, c.d_partials.p);
       check_launch();
@@ -1107,8 +1220,16 @@ static SolveResult solve_gmres_delayed(Ctx& c, const double* b, double* x, const
       check_launch();
       // the last step of a cycle also forms the partials that complete its column
       const bool last = j + 1 == m || total + 1 >= k.max_iter;
-      if (last) launch_dgs(Dg::UpdateDots, j, rg, s, n, V, w, sc, c.d_partials.p);
-      else launch_dgs(Dg::Update, j, vg, s, n, V, w, sc, c.d_partials.p);
+      if (last) {
+        launch_dgs(Dg::UpdateDots, j, rg, s, n, V, w, sc, c.d_partials.p);
+      } else if (fuse_pre) {
+        // the next basis vector and its preconditioned image in one pass
+        t_ready = launch_dupdate_pre(c.hs.n_elem, c.hs.ng, c.hs.dim * c.hs.nphi, j, n, V, w, sc, c.d_Pq.p,
+                                     c.d_Pb.p, t, k.transpose, s);
+        if (!t_ready) launch_dgs(Dg::Update, j, vg, s, n, V, w, sc, c.d_partials.p);
+      } else {
+        launch_dgs(Dg::Update, j, vg, s, n, V, w, sc, c.d_partials.p);
+      }
       check_launch();
       ++total;
       ++res.iters;
