@@ -886,9 +886,61 @@ static double read_scalar_dot(Ctx& c, int64_t n, const double* r, hipStream_t s)
   return vec_dot_host(c, n, r, r, s);
 }
 
+// Explicit element block inverse y_e = P_e x_e (P_e^T for the transpose),
+// P_e column-major FP32, for a compile-time block size NV: one thread per row,
+// several elements per workgroup; every load of the row (x and the NV
+// entries of P_e) is issued first, then x passes through LDS.
+template <int NV>
+__global__ __launch_bounds__(256) void k_block_apply_nv(int64_t n_elem, const float* __restrict__ P,
+                                                        const double* __restrict__ x, double* __restrict__ y,
+                                                        int transpose, int64_t cstride) {
+  constexpr int EPB = 256 / NV;
+  __shared__ double sx[EPB * NV];
+  x += blockIdx.y * cstride;
+  y += blockIdx.y * cstride;
+  const int le = threadIdx.x / NV, r = threadIdx.x % NV;
+  const int64_t e = (int64_t)blockIdx.x * EPB + le;
+  const bool act = le < EPB && e < n_elem;
+  float pc[NV];
+  double xv = 0.0;
+  if (act) {
+    const float* Pe = P + (size_t)e * NV * NV;
+    xv = x[e * NV + r];
+    if (!transpose) {
+#pragma unroll
+      for (int col = 0; col < NV; ++col) pc[col] = Pe[(size_t)col * NV + r];
+    } else {
+#pragma unroll
+      for (int col = 0; col < NV; ++col) pc[col] = Pe[(size_t)r * NV + col];
+    }
+  }
+  const int ls = le < EPB ? le : EPB - 1;
+  if (act) sx[ls * NV + r] = xv;
+  __syncthreads();
+  if (act) {
+    double acc = 0.0;
+#pragma unroll
+    for (int col = 0; col < NV; ++col) acc += (double)pc[col] * sx[ls * NV + col];
+    y[e * NV + r] = acc;
+  }
+}
+
 void launch_block_apply(int64_t n_elem, int nv, const float* P, const double* x, double* y, bool transpose,
                         hipStream_t s, int ncols, int64_t cstride) {
   const unsigned gy = (unsigned)std::max(1, ncols);
+  // d N_phi for 2D p = 1..4 and 3D p = 1..3 (one time node)
+#define SDG_BLK_NV(NV_)                                                                                      \
+  if (nv == NV_) {                                                                                           \
+    constexpr int epb = 256 / NV_;                                                                           \
+    const int64_t groups = (n_elem + epb - 1) / epb;                                                         \
+    require(groups <= 0x7fffffff, SDG_EINVAL, "too many elements for the block preconditioner grid");        \
+    k_block_apply_nv<NV_><<<dim3((unsigned)std::max<int64_t>(1, groups), gy), epb * NV_, 0, s>>>(             \
+        n_elem, P, x, y, transpose ? 1 : 0, cstride);                                                        \
+    check_launch();                                                                                          \
+    return;                                                                                                  \
+  }
+  SDG_BLK_NV(6) SDG_BLK_NV(12) SDG_BLK_NV(20) SDG_BLK_NV(30) SDG_BLK_NV(60)
+#undef SDG_BLK_NV
   if (!transpose && nv % 4 == 0 && nv / 4 <= 256) {
     const int epb = 256 / (nv / 4);
     const int64_t groups = (n_elem + epb - 1) / epb;
