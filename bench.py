@@ -137,11 +137,17 @@ def apply_probe(args):
 # sweep over restart lengths 10..32 gave 12.3 ms/step at 10-15 against
 # 13.6 ms/step at 30 (149 against 144 iterations at 15).
 GMRES_RESTART = 15
+# Relative tolerance of each inner FP32 solve of the FP32 operator + FP64
+# refinement path.  Two refinement sweeps reach 1e-10; a sweep on C2
+# (restart 15, 20 steps) gave 12.7 / 14.3 / 13.3 / 10.5 / 11.2 / 12.1 /
+# 12.7 / 13.8 ms/step for 3e-4 / 1e-4 / 3e-5 / 2e-5 / 1e-5 / 5e-6 / 3e-6 /
+# 1e-6 against 11.6 ms/step for FP64.
+IR_INNER_RTOL = 2e-5
 
 
 def _solve_opts(sdg, precision, pc, flags=0, solver=None):
     o = sdg.SolveOpts(solver if solver is not None else sdg.SDG_SOLVER_AUTO, precision, 1e-10, 5000,
-                      GMRES_RESTART, 5, 10, 1e-4, pc)
+                      GMRES_RESTART, 5, 10, IR_INNER_RTOL, pc)
     o.flags = flags
     return o
 
@@ -423,7 +429,8 @@ def main():
     s = torch.zeros(sizes["n_stress_state"], dtype=torch.float64, device=dev)
     pc = {"none": sdg.SDG_PRECOND_NONE, "mass": sdg.SDG_PRECOND_MASS, "block": sdg.SDG_PRECOND_BLOCK}[args.precond]
     opts64 = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F64, 1e-10, 5000, GMRES_RESTART, 5, 10, 1e-4, pc)
-    opts32 = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F32, 1e-10, 5000, GMRES_RESTART, 5, 10, 1e-4, pc)
+    opts32 = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F32, 1e-10, 5000, GMRES_RESTART, 5, 10, IR_INNER_RTOL,
+                           pc)
 
     # the source switches on around t_delay; start the run so that the timed
     # steps see the wavelet
@@ -551,10 +558,14 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "2D 64x64 jittered split square (8192 tris), p=3, p_gamma=3, layered "
-                               "lognormal media, 10 Hz Ricker source, dt=2.5e-3, GMRES(30) to 1e-10",
+                               "lognormal media, 10 Hz Ricker source, dt=2.5e-3, GMRES(15) with the element "
+                               "block preconditioner to 1e-10",
                    "n_elem": n_elem, "velocity_dofs_per_slab": n, "parallelism": "single GPU"},
         "s_per_step": {"fp64": t64 / args.steps, "fp32_operator_fp64_refinement": t32 / args.steps,
                        "fp64_hip_graph": tg / args.steps, "fp64_extrapolated_guess": tx / args.steps},
+        "chosen": min(({"path": "fp64", "s_per_step": t64 / args.steps},
+                       {"path": "fp32_operator_fp64_refinement", "s_per_step": t32 / args.steps}),
+                      key=lambda d: d["s_per_step"]),
         "iterations_per_step": {"fp64": iters / args.steps, "fp32_ir_inner": it32 / args.steps,
                                 "fp64_hip_graph": itg / args.steps, "fp64_extrapolated_guess": itx / args.steps},
         "fp64_extrapolated_rel_diff_vs_fp64": errx,
