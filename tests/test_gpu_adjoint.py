@@ -47,6 +47,9 @@ CASES = {
     "stdg_p2pg2": (5, 2, 2, "stdg", 0.01, 7, 3, "block"),
     "stdg_p1pg1_mass": (4, 1, 1, "stdg", 0.02, 5, 2, "mass"),
     "cn_p1": (5, 1, 0, "cn", 0.01, 6, 4, "mass"),
+    # Crank-Nicolson with the explicit element block inverse (its transposed
+    # application in the adjoint solves)
+    "cn_p1_block": (5, 1, 0, "cn", 0.01, 6, 3, "block"),
 }
 
 
