@@ -141,7 +141,7 @@ struct Ctx {
   // column-major per element
   DevBuf<double> d_Minv, d_winv;
   Coefs precF{}, precA{};
-  DevBuf<float> d_Pblk;                 // explicit inverses (one time node)
+  DevBuf<float> d_Pblk;                 // explicit inverses (one time node), packed upper triangles
   DevBuf<float> d_Pq, d_Pb;             // factored inverses (several time nodes)
   bool pblk_factored = false;
 

@@ -884,8 +884,12 @@ BlockPrecond block_inverses(const HostSetup& hs, const Coefs& op) {
   out.factored = ng > 1;
   std::atomic<int> err{0};
   if (!out.factored) {
-    // one time node: explicit inverse of rho|J| Tm Mbar + Cg K, column-major
-    out.P.resize((size_t)hs.n_elem * nv * nv);
+    // one time node: explicit inverse of rho|J| Tm Mbar + Cg K.  The block is
+    // symmetric (K and Mbar are), so only its upper triangle is kept,
+    // packed column by column: entry (r, c), r <= c, at c (c + 1) / 2 + r,
+    // symmetrised from the two computed entries
+    const size_t np = (size_t)nv * (nv + 1) / 2;
+    out.P.resize((size_t)hs.n_elem * np);
     parallel_for(hs.n_elem, [&](int64_t e) {
       std::vector<double> K, Dm((size_t)nv * nv), Inv;
       element_stiffness(hs, e, K);
@@ -897,9 +901,10 @@ BlockPrecond block_inverses(const HostSetup& hs, const Coefs& op) {
           Dm[i * nv + i2] = v;
         }
       if (!gj_inverse(Dm, nv, Inv)) { err = 1; return; }
-      float* o = &out.P[(size_t)e * nv * nv];
-      for (int r = 0; r < nv; ++r)
-        for (int col = 0; col < nv; ++col) o[(size_t)col * nv + r] = (float)Inv[r * nv + col];
+      float* o = &out.P[(size_t)e * np];
+      for (int col = 0; col < nv; ++col)
+        for (int r = 0; r <= col; ++r)
+          o[(size_t)col * (col + 1) / 2 + r] = (float)(0.5 * (Inv[r * nv + col] + Inv[col * nv + r]));
     });
     require(!err, SDG_EMESH, "singular diagonal block");
     return out;

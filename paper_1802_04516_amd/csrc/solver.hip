@@ -182,67 +182,6 @@ __global__ void k_dot_beta_fin(const double* partials, int nblocks, DevScalars* 
   }
 }
 
-// y = P x, 4 consecutive rows per thread with 16-byte loads (nv % 4 == 0);
-// one workgroup holds several elements' x in LDS.
-__global__ __launch_bounds__(256) void k_block_apply4(int64_t n_elem, int nv, const float* __restrict__ P,
-                                                      const double* __restrict__ x, double* __restrict__ y,
-                                                      int64_t cstride) {
-  extern __shared__ double sx[];
-  x += blockIdx.y * cstride;
-  y += blockIdx.y * cstride;
-  const int tpe = nv / 4;              // threads per element
-  const int epb = blockDim.x / tpe;    // elements per workgroup pass
-  const int le = threadIdx.x / tpe, r4 = threadIdx.x % tpe;
-  for (int64_t e0 = (int64_t)blockIdx.x * epb; e0 < n_elem; e0 += (int64_t)gridDim.x * epb) {
-    const int ne = (int)min((int64_t)epb, n_elem - e0);
-    for (int i = threadIdx.x; i < ne * nv; i += blockDim.x) sx[i] = x[e0 * nv + i];
-    __syncthreads();
-    if (le < ne) {
-      const float4* Pe = reinterpret_cast<const float4*>(P + (size_t)(e0 + le) * nv * nv) + r4;
-      const double* xe = sx + le * nv;
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-#pragma unroll 4
-      for (int col = 0; col < nv; ++col) {
-        const float4 p4 = Pe[(size_t)col * tpe];
-        const double xv = xe[col];
-        a0 += (double)p4.x * xv;
-        a1 += (double)p4.y * xv;
-        a2 += (double)p4.z * xv;
-        a3 += (double)p4.w * xv;
-      }
-      double* ye = y + (e0 + le) * nv + 4 * r4;
-      ye[0] = a0;
-      ye[1] = a1;
-      ye[2] = a2;
-      ye[3] = a3;
-    }
-    __syncthreads();
-  }
-}
-
-// y = P x for per-element dense blocks stored column-major in FP32
-// (P[e][col][row]); transpose applies P^T.
-__global__ void k_block_apply(int64_t n_elem, int nv, const float* __restrict__ P, const double* __restrict__ x,
-                              double* __restrict__ y, int transpose, int64_t cstride) {
-  extern __shared__ double sx[];
-  x += blockIdx.y * cstride;
-  y += blockIdx.y * cstride;
-  for (int64_t e = blockIdx.x; e < n_elem; e += gridDim.x) {
-    for (int i = threadIdx.x; i < nv; i += blockDim.x) sx[i] = x[e * nv + i];
-    __syncthreads();
-    const float* Pe = P + (size_t)e * nv * nv;
-    for (int rrow = threadIdx.x; rrow < nv; rrow += blockDim.x) {
-      double acc = 0.0;
-      if (!transpose)
-        for (int col = 0; col < nv; ++col) acc += (double)Pe[(size_t)col * nv + rrow] * sx[col];
-      else
-        for (int col = 0; col < nv; ++col) acc += (double)Pe[(size_t)rrow * nv + col] * sx[col];
-      y[e * nv + rrow] = acc;
-    }
-    __syncthreads();
-  }
-}
-
 // Factored element block inverse (several time nodes):
 //   y_e = (I (x) Q_e) blockdiag_i(B_{e,i}) (I (x) Q_e^T) x_e
 // (B^T for the transpose).  NV = NG*NS threads per element, several elements
@@ -886,15 +825,17 @@ static double read_scalar_dot(Ctx& c, int64_t n, const double* r, hipStream_t s)
   return vec_dot_host(c, n, r, r, s);
 }
 
-// Explicit element block inverse y_e = P_e x_e (P_e^T for the transpose),
-// P_e column-major FP32, for a compile-time block size NV: one thread per row,
-// several elements per workgroup; every load of the row (x and the NV
-// entries of P_e) is issued first, then x passes through LDS.
+// Explicit element block inverse y_e = P_e x_e for a compile-time block size
+// NV.  P_e is symmetric and stored as its packed upper triangle (entry (r, c),
+// r <= c, at c (c + 1) / 2 + r, FP32), so the transpose is the same product.
+// One thread per row, several elements per workgroup; every load of the row
+// (x and the NV entries of row r of P_e) is issued first, then x passes
+// through LDS.
 template <int NV>
-__global__ __launch_bounds__(256) void k_block_apply_nv(int64_t n_elem, const float* __restrict__ P,
-                                                        const double* __restrict__ x, double* __restrict__ y,
-                                                        int transpose, int64_t cstride) {
-  constexpr int EPB = 256 / NV;
+__global__ __launch_bounds__(256) void k_block_apply_sym(int64_t n_elem, const float* __restrict__ P,
+                                                         const double* __restrict__ x, double* __restrict__ y,
+                                                         int64_t cstride) {
+  constexpr int EPB = 256 / NV, NP = NV * (NV + 1) / 2;
   __shared__ double sx[EPB * NV];
   x += blockIdx.y * cstride;
   y += blockIdx.y * cstride;
@@ -904,15 +845,11 @@ __global__ __launch_bounds__(256) void k_block_apply_nv(int64_t n_elem, const fl
   float pc[NV];
   double xv = 0.0;
   if (act) {
-    const float* Pe = P + (size_t)e * NV * NV;
+    const float* Pe = P + (size_t)e * NP;
     xv = x[e * NV + r];
-    if (!transpose) {
+    const int rr = r * (r + 1) / 2;
 #pragma unroll
-      for (int col = 0; col < NV; ++col) pc[col] = Pe[(size_t)col * NV + r];
-    } else {
-#pragma unroll
-      for (int col = 0; col < NV; ++col) pc[col] = Pe[(size_t)r * NV + col];
-    }
+    for (int col = 0; col < NV; ++col) pc[col] = Pe[r <= col ? col * (col + 1) / 2 + r : rr + col];
   }
   const int ls = le < EPB ? le : EPB - 1;
   if (act) sx[ls * NV + r] = xv;
@@ -927,6 +864,7 @@ __global__ __launch_bounds__(256) void k_block_apply_nv(int64_t n_elem, const fl
 
 void launch_block_apply(int64_t n_elem, int nv, const float* P, const double* x, double* y, bool transpose,
                         hipStream_t s, int ncols, int64_t cstride) {
+  (void)transpose;  // symmetric blocks
   const unsigned gy = (unsigned)std::max(1, ncols);
   // d N_phi for 2D p = 1..4 and 3D p = 1..3 (one time node)
 #define SDG_BLK_NV(NV_)                                                                                      \
@@ -934,25 +872,14 @@ void launch_block_apply(int64_t n_elem, int nv, const float* P, const double* x,
     constexpr int epb = 256 / NV_;                                                                           \
     const int64_t groups = (n_elem + epb - 1) / epb;                                                         \
     require(groups <= 0x7fffffff, SDG_EINVAL, "too many elements for the block preconditioner grid");        \
-    k_block_apply_nv<NV_><<<dim3((unsigned)std::max<int64_t>(1, groups), gy), epb * NV_, 0, s>>>(             \
-        n_elem, P, x, y, transpose ? 1 : 0, cstride);                                                        \
+    k_block_apply_sym<NV_><<<dim3((unsigned)std::max<int64_t>(1, groups), gy), epb * NV_, 0, s>>>(            \
+        n_elem, P, x, y, cstride);                                                                           \
     check_launch();                                                                                          \
     return;                                                                                                  \
   }
   SDG_BLK_NV(6) SDG_BLK_NV(12) SDG_BLK_NV(20) SDG_BLK_NV(30) SDG_BLK_NV(60)
 #undef SDG_BLK_NV
-  if (!transpose && nv % 4 == 0 && nv / 4 <= 256) {
-    const int epb = 256 / (nv / 4);
-    const int64_t groups = (n_elem + epb - 1) / epb;
-    const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 65535));
-    k_block_apply4<<<dim3(g, gy), 256, (size_t)epb * nv * sizeof(double), s>>>(n_elem, nv, P, x, y, cstride);
-    check_launch();
-    return;
-  }
-  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_elem, 65535));
-  const int t = nv <= 64 ? 64 : (nv <= 128 ? 128 : 256);
-  k_block_apply<<<dim3(g, gy), t, nv * sizeof(double), s>>>(n_elem, nv, P, x, y, transpose ? 1 : 0, cstride);
-  check_launch();
+  throw Error(SDG_EUNSUPPORTED, "no block-preconditioner kernel for this element size");
 }
 
 // Update sweep of a delayed-GMRES step fused with the factored block
