@@ -828,36 +828,48 @@ static double read_scalar_dot(Ctx& c, int64_t n, const double* r, hipStream_t s)
 // Explicit element block inverse y_e = P_e x_e for a compile-time block size
 // NV.  P_e is symmetric and stored as its packed upper triangle (entry (r, c),
 // r <= c, at c (c + 1) / 2 + r, FP32), so the transpose is the same product.
-// One thread per row, several elements per workgroup; every load of the row
-// (x and the NV entries of row r of P_e) is issued first, then x passes
-// through LDS.
+// The packed blocks of a workgroup's elements are contiguous: they are
+// copied to LDS with coalesced loads (issued together with the x loads),
+// then one thread per row forms y from LDS.  Launched with EPB * NV threads.
 template <int NV>
 __global__ __launch_bounds__(256) void k_block_apply_sym(int64_t n_elem, const float* __restrict__ P,
                                                          const double* __restrict__ x, double* __restrict__ y,
                                                          int64_t cstride) {
-  constexpr int EPB = 256 / NV, NP = NV * (NV + 1) / 2;
+  constexpr int EPB = 256 / NV, NP = NV * (NV + 1) / 2, NT = EPB * NV;  // NT threads per workgroup
+  constexpr int PPT = (EPB * NP + NT - 1) / NT;  // packed values copied per thread
   __shared__ double sx[EPB * NV];
+  __shared__ float sP[EPB * NP];
   x += blockIdx.y * cstride;
   y += blockIdx.y * cstride;
   const int le = threadIdx.x / NV, r = threadIdx.x % NV;
-  const int64_t e = (int64_t)blockIdx.x * EPB + le;
-  const bool act = le < EPB && e < n_elem;
-  float pc[NV];
-  double xv = 0.0;
-  if (act) {
-    const float* Pe = P + (size_t)e * NP;
-    xv = x[e * NV + r];
-    const int rr = r * (r + 1) / 2;
+  const int64_t e0 = (int64_t)blockIdx.x * EPB;
+  const int ne = (int)min((int64_t)EPB, n_elem - e0);
+  const int64_t e = e0 + le;
+  const bool act = le < ne;
+  {
+    const float* Pg = P + (size_t)e0 * NP;
+    float pv[PPT];
 #pragma unroll
-    for (int col = 0; col < NV; ++col) pc[col] = Pe[r <= col ? col * (col + 1) / 2 + r : rr + col];
+    for (int u = 0; u < PPT; ++u) {
+      const int i = threadIdx.x + u * NT;
+      pv[u] = i < ne * NP ? Pg[i] : 0.0f;
+    }
+    const double xv = act ? x[e * NV + r] : 0.0;
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      const int i = threadIdx.x + u * NT;
+      if (i < ne * NP) sP[i] = pv[u];
+    }
+    if (act) sx[le * NV + r] = xv;
   }
-  const int ls = le < EPB ? le : EPB - 1;
-  if (act) sx[ls * NV + r] = xv;
   __syncthreads();
   if (act) {
+    const float* Pe = sP + le * NP;
+    const int rr = r * (r + 1) / 2;
     double acc = 0.0;
 #pragma unroll
-    for (int col = 0; col < NV; ++col) acc += (double)pc[col] * sx[ls * NV + col];
+    for (int col = 0; col < NV; ++col)
+      acc += (double)Pe[r <= col ? col * (col + 1) / 2 + r : rr + col] * sx[le * NV + col];
     y[e * NV + r] = acc;
   }
 }
