@@ -5,8 +5,10 @@
 // All reductions are deterministic: each block writes a partial sum and a
 // single-block finalize kernel adds the partials in a fixed order.
 // Scalars (alpha, beta, Hessenberg column, Givens rotations) stay in device
-// memory; the host reads one residual estimate every `check_every`
-// iterations.
+// memory.  CG and the GMRES with SDG_SOLVE_CGS2 read one residual estimate
+// every `check_every` iterations (a stream synchronisation); the default
+// GMRES reads the estimate that its finalize kernel wrote into coherent
+// pinned host memory, without draining the stream.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
