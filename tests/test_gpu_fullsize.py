@@ -1,0 +1,163 @@
+"""Parity at the benchmarked sizes, in the launch configuration the benchmark
+times (the autotuned face-kernel variant, the same assembly flags and solver
+options):
+
+  2D: 64x64 split square (8192 triangles), +-20% jitter, free surface,
+      p = 3, p_gamma = 3, layered lognormal material, dt = 2.5e-3;
+  3D: 32^3 periodic Kuhn cube (196,608 tetrahedra), p = 2, Crank-Nicolson,
+      homogeneous material, dt = 0.01.
+
+The oracle cannot assemble these meshes whole, so it is evaluated on the
+patch of each sampled element and its face neighbours, whose Schur rows and
+columns are exactly those of the whole mesh (tests/patch.py, pinned by
+tests/test_oracle_patch.py).  The sample holds the first and last elements
+(the last one sits in the ragged last tile of every kernel), boundary
+elements and seeded random ones.
+
+The implicit step is checked through a property that holds at any size: on
+the momentum rows of each sampled element and the stress rows of its faces
+the coupled slab system (eqs. NM25, NM26, or their Crank-Nicolson forms) is
+satisfied by the step's slab DOFs.  The stress back-substitution is exact
+per face (bar 1e-11 relative to the face's right-hand side); the momentum
+residual of an element is a part of the velocity system's residual, so it is
+bounded by rtol (1e-10) times ||b|| = ||A v|| (1 + rtol), with A v from the
+FP64 apply pinned above.
+"""
+import numpy as np
+import pytest
+
+import synth
+from patch import Patch, face_codes
+
+pytestmark = pytest.mark.gpu
+
+N_RANDOM = 10
+# FP64 bar on the sampled rows (relative L2 over the sample; each element is
+# held to the per-result bar 1e-11).
+F64_BAR = {"c2": 1e-12, "c3": 1e-11}
+
+
+@pytest.fixture(scope="module", params=["c2", "c3"])
+def big(request):
+    import paper_1802_04516_amd as sdg
+    w = synth.workload(request.param)
+    mesh = w["mesh"]
+    ctx = sdg.Context(0)
+    sizes = ctx.setup(mesh.xyz, mesh.elem, mesh.period, w["p"], w["p_gamma"],
+                      sdg.SDG_SCHEME_CN if w["scheme"] == "cn" else sdg.SDG_SCHEME_STDG, w["dt"],
+                      w["lam"], w["mu"], w["rho"],
+                      sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND)
+    ne = mesh.n_elem
+    rng = np.random.default_rng(8080)
+    sample = {0, ne - 1, ne // 2, *rng.choice(ne, N_RANDOM, replace=False).tolist()}
+    if mesh.period is None:
+        # elements with a free-surface face (fewer than d + 1 neighbours)
+        elem = np.asarray(mesh.elem)
+        cand = rng.choice(ne, 400, replace=False)
+        d = elem.shape[1] - 1
+        bnd = [int(e) for e in cand if (np.isin(elem, elem[e]).sum(axis=1) >= d).sum() - 1 < d + 1]
+        sample.update(bnd[:3])
+    patches = {}
+    for i in sorted(sample):
+        patches[i] = Patch(mesh, i, w["p"], w["p_gamma"], w["dt"], w["scheme"], w["lam"], w["mu"], w["rho"])
+    print(f"{request.param}: {ne} elements, face-kernel variant f64 {sizes['op_variant']} "
+          f"f32 {sizes['op_variant_f32']}, {len(patches)} sampled elements")
+    yield dict(name=request.param, w=w, ctx=ctx, sizes=sizes, patches=patches,
+               S={i: P.slab.schur() for i, P in patches.items()})
+    ctx.close()
+
+
+def _apply(big, v, precision, adjoint=False):
+    import torch
+    vt = torch.tensor(v, dtype=torch.float64, device="cuda")
+    yt = torch.empty_like(vt)
+    if adjoint:
+        big["ctx"].apply_adjoint(vt, yt, precision)
+    else:
+        big["ctx"].apply(vt, yt, precision)
+    torch.cuda.synchronize()
+    return yt.cpu().numpy()
+
+
+def _compare(big, y, v, adjoint, tol_all, tol_elem, label):
+    num = den = worst = 0.0
+    for i, P in big["patches"].items():
+        S = big["S"][i]
+        ref = P.schur_col(v, S) if adjoint else P.schur_row(v, S)
+        got = y.reshape(-1, P.blk)[i]
+        e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        worst = max(worst, e)
+        assert e <= tol_elem, (label, i, e)
+        num += np.linalg.norm(got - ref) ** 2
+        den += np.linalg.norm(ref) ** 2
+    print(f"{big['name']} {label}: sampled rel L2 {np.sqrt(num / den):.2e}, worst element {worst:.2e}")
+    assert np.sqrt(num / den) <= tol_all
+
+
+def test_fullsize_apply_sampled_rows(big):
+    import paper_1802_04516_amd as sdg
+    n = big["sizes"]["n_vel_slab"]
+    v = np.random.default_rng(8081).standard_normal(n)
+    bar = F64_BAR[big["name"]]
+    _compare(big, _apply(big, v, sdg.SDG_PREC_F64), v, False, bar, 1e-11, "f64 apply")
+    _compare(big, _apply(big, v, sdg.SDG_PREC_F32), v, False, 2e-6, 1e-5, "f32 apply")
+    _compare(big, _apply(big, v, sdg.SDG_PREC_F64, adjoint=True), v, True, bar, 1e-11, "f64 adjoint")
+
+
+def test_fullsize_every_face_kernel_variant(big):
+    """The autotuner may pick another variant on another run: each one is
+    held to the bar at full size."""
+    import paper_1802_04516_amd as sdg
+    ctx = big["ctx"]
+    n = big["sizes"]["n_vel_slab"]
+    v = np.random.default_rng(8082).standard_normal(n)
+    try:
+        for variant in range(8):
+            ctx.set_operator_variant(variant)
+            _compare(big, _apply(big, v, sdg.SDG_PREC_F64), v, False, F64_BAR[big["name"]], 1e-11,
+                     f"variant {variant} f64")
+            _compare(big, _apply(big, v, sdg.SDG_PREC_F32), v, False, 2e-6, 1e-5, f"variant {variant} f32")
+    finally:
+        ctx.set_operator_variant(-1)
+
+
+@pytest.mark.parametrize("chosen", [False, True], ids=["fp64", "fp32_ir"])
+def test_fullsize_step_sampled_local_residual(big, chosen):
+    import torch
+    import paper_1802_04516_amd as sdg
+    from bench import GMRES_RESTART, IR_INNER_RTOL
+    sz, ctx = big["sizes"], big["ctx"]
+    rtol = 1e-10
+    if chosen:
+        opts = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F32, rtol, 5000, GMRES_RESTART, 5, 10,
+                             IR_INNER_RTOL if big["name"] == "c2" else 1e-4, sdg.SDG_PRECOND_BLOCK)
+    else:
+        opts = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F64, rtol, 5000, GMRES_RESTART, 5, 10, 1e-4,
+                             sdg.SDG_PRECOND_BLOCK)
+    rng = np.random.default_rng(8083)
+    v_old = rng.standard_normal(sz["n_vel_state"])
+    s_old = rng.standard_normal(sz["n_stress_state"])
+    dev = dict(dtype=torch.float64, device="cuda")
+    vg, sg = torch.tensor(v_old, **dev), torch.tensor(s_old, **dev)
+    v_slab = torch.empty(sz["n_vel_slab"], **dev)
+    s_slab = torch.empty(sz["n_stress_slab"], **dev)
+    info = ctx.step(vg, sg, None, opts=opts, v_slab=v_slab, sigma_slab=s_slab)
+    torch.cuda.synchronize()
+    assert info["converged"] and info["rel_residual"] <= rtol
+    vs, ss = v_slab.cpu().numpy(), s_slab.cpu().numpy()
+    b_norm = np.linalg.norm(_apply(big, vs, sdg.SDG_PREC_F64)) * (1 + rtol)
+    codes = face_codes(big["w"]["mesh"].elem)
+    assert len(codes) == sz["n_face"]
+    r2 = 0.0
+    worst_face = 0.0
+    for i, P in big["patches"].items():
+        rv, bv, faces = P.coupled_residual(vs, ss, v_old, s_old, codes)
+        r2 += np.linalg.norm(rv) ** 2
+        for rs, bs in faces:
+            e = np.linalg.norm(rs) / np.linalg.norm(bs)
+            worst_face = max(worst_face, e)
+            assert e <= 1e-11, (i, e)
+    print(f"{big['name']} {'fp32+IR' if chosen else 'fp64'} step: {info['iterations']} iterations, "
+          f"{info['matvecs']} matvecs, rel res {info['rel_residual']:.2e}; sampled momentum residual "
+          f"{np.sqrt(r2) / b_norm:.2e} of ||b||, worst stress row {worst_face:.2e}")
+    assert np.sqrt(r2) <= rtol * b_norm
