@@ -234,26 +234,57 @@ void solve_dense(std::vector<double> A, std::vector<double>& B, int n, int m) {
     for (int k = 0; k < m; ++k) B[r * m + k] /= A[r * n + r];
 }
 
-// Lower Cholesky factor of SPD G (n x n), returns L^{-1} (lower triangular).
-std::vector<double> cholesky_inverse(const std::vector<double>& G, int n) {
-  std::vector<double> L(n * n, 0.0);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j <= i; ++j) {
-      double s = G[i * n + j];
-      for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
-      if (i == j) {
-        require(s > 0.0, SDG_EMESH, "dual Gram matrix not positive definite");
-        L[i * n + i] = std::sqrt(s);
-      } else {
-        L[i * n + j] = s / L[j * n + j];
+// Orthonormalisation of the raw dual sequence from its values: A (nq x n,
+// row-major) holds sqrt(w_q) raw_k(x_q) for an exact rule, so A^T A is the
+// Gram matrix.  Householder QR, A = Q R with diag(R) > 0, gives the
+// canonical functions raw R^{-1}; returns Li = R^{-T} (lower triangular,
+// canonical_i = sum_{k<=i} Li[i][k] raw_k).  Same result as Gram-Schmidt of
+// the sequence (hence as the Cholesky factor of A^T A) in exact arithmetic,
+// but the orthonormality error of the computed functions is eps cond(A)
+// instead of eps cond(A)^2.
+std::vector<double> orthonormaliser(std::vector<double> A, int nq, int n) {
+  require(nq >= n, SDG_EMESH, "dual Gram rule has too few points");
+  std::vector<double> v(nq);
+  for (int j = 0; j < n; ++j) {
+    double nrm = 0.0, scale = 0.0;
+    for (int i = j; i < nq; ++i) scale = std::max(scale, std::fabs(A[i * n + j]));
+    require(scale > 0.0, SDG_EMESH, "dual basis functions are linearly dependent");
+    for (int i = j; i < nq; ++i) {
+      double t = A[i * n + j] / scale;
+      nrm += t * t;
+    }
+    nrm = scale * std::sqrt(nrm);
+    const double alpha = A[j * n + j] > 0 ? -nrm : nrm;
+    double vv = 0.0;
+    for (int i = j; i < nq; ++i) {
+      v[i] = A[i * n + j] - (i == j ? alpha : 0.0);
+      vv += v[i] * v[i];
+    }
+    if (vv > 0.0) {
+      for (int k = j; k < n; ++k) {
+        double s = 0.0;
+        for (int i = j; i < nq; ++i) s += v[i] * A[i * n + k];
+        s *= 2.0 / vv;
+        for (int i = j; i < nq; ++i) A[i * n + k] -= s * v[i];
       }
     }
+  }
+  // R = upper triangle of A with rows scaled to a positive diagonal
+  std::vector<double> R(n * n, 0.0);
+  double rmax = 0.0;
+  for (int j = 0; j < n; ++j) rmax = std::max(rmax, std::fabs(A[j * n + j]));
+  for (int j = 0; j < n; ++j) {
+    const double sg = A[j * n + j] < 0 ? -1.0 : 1.0;
+    require(std::fabs(A[j * n + j]) > 1e-14 * rmax, SDG_EMESH, "dual Gram matrix not positive definite");
+    for (int k = j; k < n; ++k) R[j * n + k] = sg * A[j * n + k];
+  }
   std::vector<double> Li(n * n, 0.0);
-  for (int c = 0; c < n; ++c) {  // forward substitution of unit vectors
-    for (int i = 0; i < n; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int k = 0; k < i; ++k) s -= L[i * n + k] * Li[k * n + c];
-      Li[i * n + c] = s / L[i * n + i];
+  for (int c = 0; c < n; ++c) {  // column c of R^{-1} by back substitution = row c of Li
+    Li[c * n + c] = 1.0 / R[c * n + c];
+    for (int i = c - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int k = i + 1; k <= c; ++k) s += R[i * n + k] * Li[c * n + k];
+      Li[c * n + i] = -s / R[i * n + i];
     }
   }
   return Li;
@@ -449,7 +480,7 @@ void face_geometry(const HostSetup& hs, const int64_t* elem, int64_t j, FaceGeom
   }
 }
 
-// Frame, Gram matrix and canonical orthonormalisation of the dual basis of
+// Frame and canonical orthonormalisation of the dual basis of
 // one face; vol receives |T_{l,j}| and |T_{r,j}| (0 on the boundary).
 void build_dual(const HostSetup& hs, int64_t j, const FaceGeom& g, DualBasis& db, double* vol) {
   const int d = hs.dim, npsi = hs.npsi;
@@ -483,20 +514,19 @@ void build_dual(const HostSetup& hs, int64_t j, const FaceGeom& g, DualBasis& db
     for (int k = 0; k < 3; ++k) db.origin[k] = c[k];
     for (int k = 0; k < 9; ++k) db.Ainv[k] = (k % 4 == 0) ? 1.0 / h : 0.0;
   }
-  std::vector<double> G(npsi * npsi, 0.0), raw(npsi);
+  std::vector<double> A, raw(npsi);
   vol[0] = vol[1] = 0.0;
+  int nq = 0;
   for (int s = 0; s < (interior ? 2 : 1); ++s) {
     Rule r = simplex_rule(g.Tsub[s], d, d, 2 * psi_deg);
-    for (int q = 0; q < r.n(); ++q) {
+    for (int q = 0; q < r.n(); ++q, ++nq) {
       db.raw(&r.x[q * d], raw.data());
       vol[s] += r.w[q];
-      for (int a = 0; a < npsi; ++a)
-        for (int b = 0; b <= a; ++b) G[a * npsi + b] += r.w[q] * raw[a] * raw[b];
+      const double sw = std::sqrt(r.w[q]);
+      for (int a = 0; a < npsi; ++a) A.push_back(sw * raw[a]);
     }
   }
-  for (int a = 0; a < npsi; ++a)
-    for (int b = a + 1; b < npsi; ++b) G[a * npsi + b] = G[b * npsi + a];
-  db.Linv = cholesky_inverse(G, npsi);
+  db.Linv = orthonormaliser(std::move(A), nq, npsi);
 }
 
 }  // namespace
