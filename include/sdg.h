@@ -210,9 +210,10 @@ int sdg_query(const sdg_ctx* ctx, sdg_sizes* out);
 /* Face-kernel variant (tile shape) of the operator apply: 0 = LDS kernel
  * with flat loops, 1 = register-tiled kernel with the most faces per
  * workgroup that fit in 64 KiB of LDS, 2 = register-tiled with half as many,
- * 3 = column-parallel kernel (one thread per face and stress column, at
- * most 256/(d N_psi) faces per workgroup within 64 KiB of LDS), 4 = the
- * same with half as many faces, 5 and 6 = column-parallel kernels that read
+ * 4 = column-parallel kernel (one thread per face and stress column, half
+ * of the at most 256/(d N_psi) faces per workgroup that fit in 64 KiB of
+ * LDS), 3 = the same kernel persistent (one workgroup per resident slot),
+ * loading the next chunk's blocks while computing the current one, 5 and 6 = column-parallel kernels that read
  * the blocks from HBM straight into registers (about 256/(d N_psi) faces
  * per workgroup, or twice as many), 7 = one face per wavefront on the FP64
  * matrix cores (the face gradient and scatter as 16x16x4 MFMA sequences,

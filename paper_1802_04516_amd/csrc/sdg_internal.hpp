@@ -127,7 +127,7 @@ struct OpArgs {
   double y_scale;          // element kernel: y = y_scale * (...) (reserved, 1.0)
   int variant;             // operator face kernel: 0 = LDS flat loops, 1 = register-tiled
                            // with the most faces per block, 2 = register-tiled, half of it,
-                           // 3 = column-parallel (most faces that fit), 4 = half of it,
+                           // 3 = column-parallel, persistent and pipelined, 4 = column-parallel,
                            // 5, 6 = column-parallel reading blocks from HBM into registers,
                            // 7 = one face per wavefront on the FP64 matrix cores
   // Several independent columns (right-hand sides) of the same mesh: the
