@@ -207,20 +207,26 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs);
 
 int sdg_query(const sdg_ctx* ctx, sdg_sizes* out);
 
-/* Face-kernel variant (tile shape) of the operator apply: 0 = LDS kernel
- * with flat loops, 1 = register-tiled kernel with the most faces per
- * workgroup that fit in 64 KiB of LDS, 2 = register-tiled with half as many,
- * 4 = column-parallel kernel (one thread per face and stress column, half
- * of the at most 256/(d N_psi) faces per workgroup that fit in 64 KiB of
- * LDS), 3 = the same kernel persistent (one workgroup per resident slot),
- * loading the next chunk's blocks while computing the current one, 5 and 6 = column-parallel kernels that read
- * the blocks from HBM straight into registers (about 256/(d N_psi) faces
- * per workgroup, or twice as many), 7 = one face per wavefront on the FP64
- * matrix cores (the face gradient and scatter as 16x16x4 MFMA sequences,
- * the rows padded to 16; in FP32, or where N_gamma d > 16 or N_phi > 16,
- * variant 5); -1 reruns the autotuner (sdg_assemble runs it: every variant is
- * timed on the assembled operator and the fastest kept, per precision).  All
- * variants compute the same operator. */
+/* Face-kernel variant (tile shape) of the operator apply:
+ *   0 = LDS kernel with flat loops;
+ *   1 = register-tiled kernel with the most faces per workgroup that fit in
+ *       64 KiB of LDS; 2 = the same with half as many;
+ *   4 = column-parallel kernel (one thread per face and stress column, half
+ *       of the at most 256/(d N_psi) faces per workgroup that fit in 64 KiB
+ *       of LDS); 3 = the same kernel persistent (one workgroup per resident
+ *       slot), loading the next chunk's blocks while computing the current
+ *       one;
+ *   5 = column-parallel kernel that reads the blocks from HBM straight into
+ *       registers (about 256/(d N_psi) faces per workgroup); 6 = the same
+ *       with the scatter summed across the face's lanes from the block
+ *       columns already in registers (d N_psi rounded up to a power of two
+ *       lanes per face; where that exceeds 64, variant 5);
+ *   7 = one face per wavefront on the FP64 matrix cores (the face gradient
+ *       and scatter as 16x16x4 MFMA sequences, the rows padded to 16; in
+ *       FP32, or where N_gamma d > 16 or N_phi > 16, variant 5);
+ *  -1 reruns the autotuner (sdg_assemble runs it: every variant is timed on
+ *       the assembled operator and the fastest kept, per precision).
+ * All variants compute the same operator. */
 int sdg_set_operator_variant(sdg_ctx* ctx, int variant);
 
 /* Kernel of the batched FP64 operator apply (n_rhs > 1): 0 = the face

@@ -128,7 +128,8 @@ struct OpArgs {
   int variant;             // operator face kernel: 0 = LDS flat loops, 1 = register-tiled
                            // with the most faces per block, 2 = register-tiled, half of it,
                            // 3 = column-parallel, persistent and pipelined, 4 = column-parallel,
-                           // 5, 6 = column-parallel reading blocks from HBM into registers,
+                           // 5 = column-parallel reading blocks from HBM into registers,
+                           // 6 = the same with the scatter summed across the face's lanes,
                            // 7 = one face per wavefront on the FP64 matrix cores
   // Several independent columns (right-hand sides) of the same mesh: the
   // launch grid's y index is the column and every per-column array is offset
