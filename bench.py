@@ -288,8 +288,8 @@ def nodal_points(mesh, p):
 def bench_3d_operator(args):
     """3D operator on the 32^3 periodic Kuhn cube (196,608 tetrahedra, p=2,
     Crank-Nicolson, homogeneous): the stored blocks (about 2 GB FP64) exceed
-    the last-level cache, so this apply runs from HBM.  Then five implicit
-    steps (preconditioned CG to 1e-10) from a plane S-wave velocity, FP64 and
+    the last-level cache, so this apply runs from HBM.  Then the workload's 50
+    implicit steps (preconditioned CG to 1e-10) from a plane S-wave velocity, FP64 and
     FP32 operator + FP64 refinement, with the energy drift (the scheme
     conserves energy exactly in this setting, Section 5)."""
     import numpy as np
@@ -334,7 +334,7 @@ def bench_3d_operator(args):
     pol = np.array([1.0, -1.0, 0.0]) / np.sqrt(2.0)
     phase = 2.0 * np.pi * X.sum(axis=2)                      # k.x with k = 2 pi (1, 1, 1)
     v0 = 0.1 * pol[None, :, None] * np.sin(phase)[:, None, :]  # (n_elem, 3, N_phi)
-    steps = 5
+    steps = w["steps"]  # 50
     for name, prec in (("fp64_steps", sdg.SDG_PREC_F64), ("fp32_operator_fp64_refinement_steps", sdg.SDG_PREC_F32)):
         v = torch.tensor(np.ascontiguousarray(v0).ravel(), dtype=torch.float64, device="cuda")
         s = torch.zeros(sizes["n_stress_state"], dtype=torch.float64, device="cuda")
