@@ -110,6 +110,31 @@ def test_batched_apply_matches_columns_and_oracle(bcase, bvariant):
         ctx.set_batched_variant(old)
 
 
+@pytest.mark.parametrize("variant", [3, 6])
+def test_column_grid_with_persistent_and_lane_reduced_face_kernels(bcase, variant):
+    """The column grid (grid y = column) of the persistent face kernel
+    (variant 3, whose x grid walks chunks) and of the lane-reduced one
+    (variant 6) gives every column bit for bit its single-column apply."""
+    import torch
+    import paper_1802_04516_amd as sdg
+    ctx, R, n = bcase["ctx"], bcase["R"], bcase["sizes"]["n_vel_slab"]
+    V = np.random.default_rng(78).standard_normal((R, n))
+    old = ctx.sizes["op_bvariant"]
+    ctx.set_batched_variant(0)
+    ctx.set_operator_variant(variant)
+    try:
+        for prec in (sdg.SDG_PREC_F64, sdg.SDG_PREC_F32):
+            yb = torch.empty(R * n, dtype=torch.float64, device="cuda")
+            ctx.apply(_gpu(V), yb, prec, n_rhs=R)
+            ys = torch.empty(n, dtype=torch.float64, device="cuda")
+            for r in range(R):
+                ctx.apply(_gpu(V[r]), ys, prec)
+                assert torch.equal(ys, yb[r * n:(r + 1) * n]), f"column {r} differs from the single apply"
+    finally:
+        ctx.set_operator_variant(-1)
+        ctx.set_batched_variant(old)
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32ir", "f64_cgs2"])
 def test_batched_steps_match_oracle_per_column(bcase, precision):
     """Batched columns against the oracle column by column; f64_cgs2 runs the

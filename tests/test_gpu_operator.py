@@ -96,6 +96,23 @@ def test_every_face_kernel_variant_matches_oracle(case, variant):
     assert all(t > 0 for t in s["tune_us_f64"])
 
 
+def test_pipelined_face_kernel_is_bitwise_the_plain_one(case):
+    """Variant 3 runs the arithmetic of variant 4 in a persistent, prefetching
+    loop: the results must agree bit for bit, in FP64 and FP32."""
+    import paper_1802_04516_amd as sdg
+    ctx = case["ctx"]
+    v = np.random.default_rng(77).standard_normal(case["slab"].nv)
+    out = {}
+    try:
+        for variant in (3, 4):
+            ctx.set_operator_variant(variant)
+            out[variant] = (_apply(case, v), _apply(case, v, sdg.SDG_PREC_F32))
+    finally:
+        ctx.set_operator_variant(-1)
+    assert np.array_equal(out[3][0], out[4][0])
+    assert np.array_equal(out[3][1], out[4][1])
+
+
 def test_apply_fp32_operator_error(case):
     import paper_1802_04516_amd as sdg
     rng = np.random.default_rng(99)
