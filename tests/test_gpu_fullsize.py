@@ -125,12 +125,12 @@ def test_fullsize_every_face_kernel_variant(big):
 def test_fullsize_step_sampled_local_residual(big, chosen):
     import torch
     import paper_1802_04516_amd as sdg
-    from bench import GMRES_RESTART, IR_INNER_RTOL
+    from bench import GMRES_RESTART, IR_INNER_RTOL, IR_INNER_RTOL_3D
     sz, ctx = big["sizes"], big["ctx"]
     rtol = 1e-10
     if chosen:
         opts = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F32, rtol, 5000, GMRES_RESTART, 5, 10,
-                             IR_INNER_RTOL if big["name"] == "c2" else 1e-4, sdg.SDG_PRECOND_BLOCK)
+                             IR_INNER_RTOL if big["name"] == "c2" else IR_INNER_RTOL_3D, sdg.SDG_PRECOND_BLOCK)
     else:
         opts = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F64, rtol, 5000, GMRES_RESTART, 5, 10, 1e-4,
                              sdg.SDG_PRECOND_BLOCK)
