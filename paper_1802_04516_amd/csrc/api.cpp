@@ -960,11 +960,12 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     step_rhs(c, v_state, sigma_state, R, src, s, extrap);
 
     // 2. Krylov solve from the old state copied to every time node
-    auto inner = [&](const double* b, double* x, double tol, int maxit, int pr) {
+    auto inner = [&](const double* b, double* x, double tol, int maxit, int pr, bool x_zero) {
       KrylovCfg k2 = kc;
       k2.rtol = tol;
       k2.max_iter = maxit;
       k2.prec = pr;
+      k2.x_zero = x_zero && !multi;
       if (!multi) return solver == SDG_SOLVER_CG ? solve_cg(c, b, x, k2, s) : solve_gmres(c, b, x, k2, s);
       MultiSys& m = systems(c, R);
       std::function<void(const double*, double*)> op = [&](const double* in, double* out) {
@@ -977,7 +978,7 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
                                c.d_r.p, c.d_w.p, c.d_t.p);
     };
     if (prec == SDG_PREC_F64) {
-      res = inner(c.d_b.p, c.d_x.p, opts->rtol, opts->max_iter, SDG_PREC_F64);
+      res = inner(c.d_b.p, c.d_x.p, opts->rtol, opts->max_iter, SDG_PREC_F64, false);
     } else {
       // FP32 operator inside FP64 iterative refinement
       const double inner_tol = opts->inner_rtol > 0 ? opts->inner_rtol : 1e-4;
@@ -1008,7 +1009,7 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
         }
         // correction: A32 e = d from a zero initial guess, then x += e
         vec_fill(N, 0.0, c.d_e.p, s);
-        SolveResult in = inner(c.d_d.p, c.d_e.p, inner_tol, opts->max_iter - res.iters, SDG_PREC_F32);
+        SolveResult in = inner(c.d_d.p, c.d_e.p, inner_tol, opts->max_iter - res.iters, SDG_PREC_F32, true);
         res.iters += in.iters;
         res.matvecs += in.matvecs;
         ++res.refinements;
@@ -1112,6 +1113,7 @@ int sdg_adjoint_step(sdg_ctx* ctx, const double* v_old, const double* v_slab, do
     kc.prec = SDG_PREC_F64;
     kc.transpose = true;
     kc.delayed = (opts->flags & SDG_SOLVE_CGS2) == 0;
+    kc.x_zero = true;
     res = solver == SDG_SOLVER_CG ? solve_cg(c, c.d_b.p, c.d_x.p, kc, s) : solve_gmres(c, c.d_b.p, c.d_x.p, kc, s);
 
     // 3. stress multipliers L_s and the new stress adjoint:

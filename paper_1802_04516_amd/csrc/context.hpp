@@ -222,6 +222,7 @@ struct KrylovCfg {
   int precond = SDG_PRECOND_NONE;
   bool transpose = false;    // solve with A^T (adjoint)
   bool delayed = true;       // GMRES: delayed reorthogonalisation (one reduction per step)
+  bool x_zero = false;       // x is zero on entry: the first residual is b itself (no operator apply)
 };
 SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s);
 SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s);

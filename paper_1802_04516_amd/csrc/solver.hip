@@ -1048,10 +1048,12 @@ SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hip
     res.converged = true;
     return res;
   }
-  apply_op(c, x, q, k.prec, k.transpose, s);
-  ++res.matvecs;
   vec_copy(n, b, r, s);
-  vec_axpby(n, -1.0, q, 1.0, r, s);
+  if (!k.x_zero) {  // with x = 0 the residual is b exactly
+    apply_op(c, x, q, k.prec, k.transpose, s);
+    ++res.matvecs;
+    vec_axpby(n, -1.0, q, 1.0, r, s);
+  }
   if (pre) {
     apply_precond(c, k.precond, r, z, k.transpose, s);
   } else {
@@ -1181,11 +1183,18 @@ static SolveResult solve_gmres_delayed(Ctx& c, const double* b, double* x, const
   // the factored block preconditioner is fused into the update sweep
   const bool fuse_pre = k.precond == SDG_PRECOND_BLOCK && c.pblk_factored && c.d_Pq.p != nullptr;
   int total = 0;
+  bool x_zero = k.x_zero;
   for (;;) {
-    // r = b - A x is the first (unnormalised) basis vector of the cycle
-    apply_op(c, x, V, k.prec, k.transpose, s);
-    ++res.matvecs;
-    vec_axpby(n, 1.0, b, -1.0, V, s);
+    // r = b - A x is the first (unnormalised) basis vector of the cycle (b
+    // itself while x is still the zero initial guess)
+    if (x_zero) {
+      vec_copy(n, b, V, s);
+      x_zero = false;
+    } else {
+      apply_op(c, x, V, k.prec, k.transpose, s);
+      ++res.matvecs;
+      vec_axpby(n, 1.0, b, -1.0, V, s);
+    }
     dev_dot(c, n, V, V, &sc->dots[0], s);
     double rr = read_scalar(c, &sc->dots[0], s);
     require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
@@ -1272,10 +1281,16 @@ SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, 
   }
   const unsigned rg = red_grid(n), vg = vgrid(n);
   int total = 0;
+  bool x_zero = k.x_zero;
   for (;;) {
-    apply_op(c, x, r, k.prec, k.transpose, s);
-    ++res.matvecs;
-    vec_axpby(n, 1.0, b, -1.0, r, s);
+    if (x_zero) {  // b - A 0 = b
+      vec_copy(n, b, r, s);
+      x_zero = false;
+    } else {
+      apply_op(c, x, r, k.prec, k.transpose, s);
+      ++res.matvecs;
+      vec_axpby(n, 1.0, b, -1.0, r, s);
+    }
     dev_dot(c, n, r, r, &sc->dots[0], s);
     double rr = read_scalar(c, &sc->dots[0], s);
     require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
