@@ -116,6 +116,7 @@ void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipS
   a.bvariant = c.bvariant;
   a.cs_v = a.cs_y = c.n_slab;
   a.cs_z = c.z_col;
+  a.z_f32 = prec == SDG_PREC_F32;
   launch_face(c.hs.dim, c.hs.p, c.hs.ng, prec, kScatter, a, s);
   SDG_HIP(hipGetLastError());
   launch_elem(c.hs.dim, c.hs.p, c.hs.ng, a, s);

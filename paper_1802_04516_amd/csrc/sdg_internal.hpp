@@ -135,6 +135,8 @@ struct OpArgs {
   // launch grid's y index is the column and every per-column array is offset
   // by column * its stride (0 = shared by all columns).
   int n_cols;
+  int z_f32 = 0;           // face slots z in FP32 (written by the FP32 face kernels of the
+                           // operator apply, read by its element kernel); else FP64
   int bvariant;            // batched FP64 operator: 0 = column grid of the variant above,
                            // 1, 2 = matrix-core kernel with 8 or 16 columns per workgroup
   int64_t cs_v, cs_y, cs_z, cs_sig_in, cs_s_out, cs_s_end, cs_y_add;
