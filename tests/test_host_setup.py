@@ -1,0 +1,80 @@
+"""Host-side set-up code of the library (no GPU), against the oracle.
+
+tests/host/dual_basis.cpp compiles the library's set-up source on the host
+and writes the canonical dual basis of every face at given points.  The
+canonical basis is the Gram-Schmidt orthonormalisation over the dual element
+of the raw sequence (Section 3, the stress basis of the dual mesh): the
+library builds it from Legendre products by Householder QR, the oracle from
+monomials by a Cholesky factor of the Gram matrix.  Both span the same
+nested spaces with positive leading coefficients, so the functions must
+agree; a wrong frame, ordering or orthonormalisation in either shows up.
+"""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.assemble import Blocks
+from oracle.mesh import Topology
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HIP_INCLUDE = "/opt/rocm/include"
+
+MESHES = {
+    "2d_free_p3": (lambda: synth.split_square(3, jitter=0.2, seed=5), 3, False),
+    "2d_periodic_p2": (lambda: synth.split_square(4, periodic=True, jitter=0.1, seed=6), 2, True),
+    "3d_free_p2": (lambda: synth.kuhn_cube(2, periodic=False), 2, False),
+    "3d_periodic_p1": (lambda: synth.kuhn_cube(3, periodic=True), 1, True),
+}
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None or not os.path.exists(os.path.join(HIP_INCLUDE, "hip", "hip_runtime.h")):
+        pytest.skip("needs g++ and the HIP headers")
+    exe = str(tmp_path_factory.mktemp("host") / "dual_basis")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", f"-I{HIP_INCLUDE}", "-w",
+                    os.path.join(HERE, "host", "dual_basis.cpp"), "-o", exe, "-lpthread"], check=True)
+    return exe
+
+
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_library_dual_basis_equals_oracle_gram_schmidt(harness, tmp_path, name):
+    mk, p, periodic = MESHES[name]
+    mesh = mk()
+    elem = np.asarray(mesh.elem, dtype=np.int64)
+    xyz = np.asarray(mesh.xyz, dtype=np.float64)
+    d = elem.shape[1] - 1
+    mfile, pfile, ofile = tmp_path / "mesh.bin", tmp_path / "pts.bin", tmp_path / "out.bin"
+    with open(mfile, "wb") as f:
+        np.array([d, xyz.shape[0], elem.shape[0], p, int(periodic)], dtype=np.int64).tofile(f)
+        xyz.tofile(f)
+        elem.tofile(f)
+    topo = Topology(mesh.xyz, mesh.elem, mesh.period)
+    n = elem.shape[0]
+    B = Blocks(topo, p, np.full(n, 2.0), np.full(n, 1.0), np.full(n, 1.0))
+    # points: the centroids of the two sub-simplices and of the face
+    pts = []
+    for j, F in enumerate(topo.faces):
+        tl = topo.sub_simplex(j, 0).mean(axis=0)
+        tr = topo.sub_simplex(j, 1).mean(axis=0) if F.right >= 0 else 0.5 * (tl + F.X.mean(axis=0))
+        pts.append([tl, tr, F.X.mean(axis=0)])
+    pts = np.asarray(pts, dtype=np.float64)
+    K = pts.shape[1]
+    with open(pfile, "wb") as f:
+        np.array([K], dtype=np.int64).tofile(f)
+        pts.tofile(f)
+    subprocess.run([harness, str(mfile), str(pfile), str(ofile)], check=True)
+    got = np.fromfile(ofile, dtype=np.float64).reshape(topo.n_face, K, B.npsi)
+    worst = 0.0
+    for j in range(topo.n_face):
+        raw = B.duals[j].eval(pts[j])                       # (K, npsi)
+        ref = np.linalg.solve(B.L[j], raw.T).T              # canonical = L^-1 raw
+        err = np.abs(got[j] - ref).max() / np.abs(ref).max()
+        worst = max(worst, err)
+    print(f"{name}: {topo.n_face} faces, worst relative difference {worst:.2e}")
+    assert worst <= 1e-9
