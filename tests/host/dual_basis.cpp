@@ -3,11 +3,13 @@
 // evaluated at given points, so that a test can compare it with the
 // oracle's Gram-Schmidt basis.
 //
-//   dual_basis MESH POINTS OUT
+//   dual_basis MESH POINTS OUT [FACES]
 // MESH:   int64 dim, n_vert, n_elem, p, periodic; double xyz[n_vert][dim];
 //         int64 elem[n_elem][dim + 1] (periodic: unit period in every axis)
 // POINTS: int64 K; double x[n_face][K][dim] (in the left element's frame)
 // OUT:    double psi[n_face][K][n_psi]
+// FACES:  int32 [n_face][4] = left, local face in left, right (-1 on the
+//         boundary), local face in right
 #include "../../paper_1802_04516_amd/csrc/setup.cpp"
 
 #include <cstdio>
@@ -17,8 +19,8 @@ using namespace sdg;
 static bool read_all(FILE* f, void* p, size_t bytes) { return std::fread(p, 1, bytes, f) == bytes; }
 
 int main(int argc, char** argv) {
-  if (argc != 4) {
-    std::fprintf(stderr, "usage: dual_basis MESH POINTS OUT\n");
+  if (argc != 4 && argc != 5) {
+    std::fprintf(stderr, "usage: dual_basis MESH POINTS OUT [FACES]\n");
     return 2;
   }
   FILE* fm = std::fopen(argv[1], "rb");
@@ -59,7 +61,16 @@ int main(int argc, char** argv) {
   }
   FILE* fo = std::fopen(argv[3], "wb");
   if (!fo) return 3;
-  const bool ok = std::fwrite(out.data(), 8, out.size(), fo) == out.size();
+  bool ok = std::fwrite(out.data(), 8, out.size(), fo) == out.size();
   std::fclose(fo);
+  if (ok && argc == 5) {
+    FILE* ff = std::fopen(argv[4], "wb");
+    if (!ff) return 3;
+    for (const FaceRec& r : hs.faces) {
+      const int32_t rec[4] = {r.left, r.lf, r.right, r.rf};
+      ok = ok && std::fwrite(rec, 4, 4, ff) == 4;
+    }
+    std::fclose(ff);
+  }
   return ok ? 0 : 3;
 }

@@ -8,6 +8,8 @@ library builds it from Legendre products by Householder QR, the oracle from
 monomials by a Cholesky factor of the Gram matrix.  Both span the same
 nested spaces with positive leading coefficients, so the functions must
 agree; a wrong frame, ordering or orthonormalisation in either shows up.
+The harness also writes the library's face table, which must follow the
+oracle's face numbering.
 """
 import os
 import shutil
@@ -68,7 +70,11 @@ def test_library_dual_basis_equals_oracle_gram_schmidt(harness, tmp_path, name):
     with open(pfile, "wb") as f:
         np.array([K], dtype=np.int64).tofile(f)
         pts.tofile(f)
-    subprocess.run([harness, str(mfile), str(pfile), str(ofile)], check=True)
+    ffile = tmp_path / "faces.bin"
+    subprocess.run([harness, str(mfile), str(pfile), str(ofile), str(ffile)], check=True)
+    # the face table (numbering by left element and local face, sides)
+    faces = np.fromfile(ffile, dtype=np.int32).reshape(-1, 4)
+    assert np.array_equal(faces, [[F.left, F.lf, F.right, F.rf] for F in topo.faces])
     got = np.fromfile(ofile, dtype=np.float64).reshape(topo.n_face, K, B.npsi)
     worst = 0.0
     for j in range(topo.n_face):
