@@ -3,13 +3,15 @@
 // evaluated at given points, so that a test can compare it with the
 // oracle's Gram-Schmidt basis.
 //
-//   dual_basis MESH POINTS OUT [FACES]
+//   dual_basis MESH POINTS OUT [FACES BLOCKS]
 // MESH:   int64 dim, n_vert, n_elem, p, periodic; double xyz[n_vert][dim];
 //         int64 elem[n_elem][dim + 1] (periodic: unit period in every axis)
 // POINTS: int64 K; double x[n_face][K][dim] (in the left element's frame)
 // OUT:    double psi[n_face][K][n_psi]
 // FACES:  int32 [n_face][4] = left, local face in left, right (-1 on the
 //         boundary), local face in right
+// BLOCKS: double Dt[n_face][2][N_phi][d][N_psi] (canonical dual basis; zero
+//         for the missing side of a boundary face)
 #include "../../paper_1802_04516_amd/csrc/setup.cpp"
 
 #include <cstdio>
@@ -19,8 +21,8 @@ using namespace sdg;
 static bool read_all(FILE* f, void* p, size_t bytes) { return std::fread(p, 1, bytes, f) == bytes; }
 
 int main(int argc, char** argv) {
-  if (argc != 4 && argc != 5) {
-    std::fprintf(stderr, "usage: dual_basis MESH POINTS OUT [FACES]\n");
+  if (argc != 4 && argc != 6) {
+    std::fprintf(stderr, "usage: dual_basis MESH POINTS OUT [FACES BLOCKS]\n");
     return 2;
   }
   FILE* fm = std::fopen(argv[1], "rb");
@@ -63,7 +65,7 @@ int main(int argc, char** argv) {
   if (!fo) return 3;
   bool ok = std::fwrite(out.data(), 8, out.size(), fo) == out.size();
   std::fclose(fo);
-  if (ok && argc == 5) {
+  if (ok && argc == 6) {
     FILE* ff = std::fopen(argv[4], "wb");
     if (!ff) return 3;
     for (const FaceRec& r : hs.faces) {
@@ -71,6 +73,10 @@ int main(int argc, char** argv) {
       ok = ok && std::fwrite(rec, 4, 4, ff) == 4;
     }
     std::fclose(ff);
+    FILE* fb = std::fopen(argv[5], "wb");
+    if (!fb) return 3;
+    ok = ok && std::fwrite(hs.Dt.data(), 8, hs.Dt.size(), fb) == hs.Dt.size();
+    std::fclose(fb);
   }
   return ok ? 0 : 3;
 }

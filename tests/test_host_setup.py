@@ -9,7 +9,8 @@ monomials by a Cholesky factor of the Gram matrix.  Both span the same
 nested spaces with positive leading coefficients, so the functions must
 agree; a wrong frame, ordering or orthonormalisation in either shows up.
 The harness also writes the library's face table, which must follow the
-oracle's face numbering.
+oracle's face numbering, and its coupling blocks, which must be the
+oracle's D (eq. MD_3) mapped to the canonical basis.
 """
 import os
 import shutil
@@ -70,8 +71,8 @@ def test_library_dual_basis_equals_oracle_gram_schmidt(harness, tmp_path, name):
     with open(pfile, "wb") as f:
         np.array([K], dtype=np.int64).tofile(f)
         pts.tofile(f)
-    ffile = tmp_path / "faces.bin"
-    subprocess.run([harness, str(mfile), str(pfile), str(ofile), str(ffile)], check=True)
+    ffile, bfile = tmp_path / "faces.bin", tmp_path / "blocks.bin"
+    subprocess.run([harness, str(mfile), str(pfile), str(ofile), str(ffile), str(bfile)], check=True)
     # the face table (numbering by left element and local face, sides)
     faces = np.fromfile(ffile, dtype=np.int32).reshape(-1, 4)
     assert np.array_equal(faces, [[F.left, F.lf, F.right, F.rf] for F in topo.faces])
@@ -84,3 +85,15 @@ def test_library_dual_basis_equals_oracle_gram_schmidt(harness, tmp_path, name):
         worst = max(worst, err)
     print(f"{name}: {topo.n_face} faces, worst relative difference {worst:.2e}")
     assert worst <= 1e-9
+    # the coupling blocks D (eq. MD_3) in the canonical basis: D_can = D_raw L^-T
+    Dt = np.fromfile(bfile, dtype=np.float64).reshape(topo.n_face, 2, B.nphi, d, B.npsi)
+    worst_d = 0.0
+    for j, F in enumerate(topo.faces):
+        for side in range(2):
+            if side == 1 and F.right < 0:
+                assert not Dt[j, 1].any()
+                continue
+            ref = np.linalg.solve(B.L[j], B.D[j][side].reshape(-1, B.npsi).T).T.reshape(B.nphi, d, B.npsi)
+            worst_d = max(worst_d, np.abs(Dt[j, side] - ref).max() / np.abs(ref).max())
+    print(f"{name}: worst relative difference of the coupling blocks {worst_d:.2e}")
+    assert worst_d <= 1e-11
