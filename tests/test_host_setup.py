@@ -9,8 +9,9 @@ monomials by a Cholesky factor of the Gram matrix.  Both span the same
 nested spaces with positive leading coefficients, so the functions must
 agree; a wrong frame, ordering or orthonormalisation in either shows up.
 The harness also writes the library's face table, which must follow the
-oracle's face numbering, and its coupling blocks, which must be the
-oracle's D (eq. MD_3) mapped to the canonical basis.
+oracle's face numbering, its coupling blocks, which must be the oracle's D
+(eq. MD_3) mapped to the canonical basis, and its dual material, element
+mass and time basis.
 """
 import os
 import shutil
@@ -21,16 +22,18 @@ import pytest
 
 import synth
 from oracle.assemble import Blocks
+from oracle.basis import TimeBasis
 from oracle.mesh import Topology
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 HIP_INCLUDE = "/opt/rocm/include"
 
 MESHES = {
-    "2d_free_p3": (lambda: synth.split_square(3, jitter=0.2, seed=5), 3, False),
-    "2d_periodic_p2": (lambda: synth.split_square(4, periodic=True, jitter=0.1, seed=6), 2, True),
-    "3d_free_p2": (lambda: synth.kuhn_cube(2, periodic=False), 2, False),
-    "3d_periodic_p1": (lambda: synth.kuhn_cube(3, periodic=True), 1, True),
+    # name: (mesh, p, periodic, p_gamma)
+    "2d_free_p3": (lambda: synth.split_square(3, jitter=0.2, seed=5), 3, False, 3),
+    "2d_periodic_p2": (lambda: synth.split_square(4, periodic=True, jitter=0.1, seed=6), 2, True, 1),
+    "3d_free_p2": (lambda: synth.kuhn_cube(2, periodic=False), 2, False, 2),
+    "3d_periodic_p1": (lambda: synth.kuhn_cube(3, periodic=True), 1, True, 0),
 }
 
 
@@ -47,19 +50,21 @@ def harness(tmp_path_factory):
 
 @pytest.mark.parametrize("name", sorted(MESHES))
 def test_library_dual_basis_equals_oracle_gram_schmidt(harness, tmp_path, name):
-    mk, p, periodic = MESHES[name]
+    mk, p, periodic, pg = MESHES[name]
     mesh = mk()
     elem = np.asarray(mesh.elem, dtype=np.int64)
     xyz = np.asarray(mesh.xyz, dtype=np.float64)
     d = elem.shape[1] - 1
+    lam, mu, rho = synth.lognormal_material(elem.shape[0], sigma=0.3, seed=31)
     mfile, pfile, ofile = tmp_path / "mesh.bin", tmp_path / "pts.bin", tmp_path / "out.bin"
     with open(mfile, "wb") as f:
-        np.array([d, xyz.shape[0], elem.shape[0], p, int(periodic)], dtype=np.int64).tofile(f)
+        np.array([d, xyz.shape[0], elem.shape[0], p, int(periodic), pg], dtype=np.int64).tofile(f)
         xyz.tofile(f)
         elem.tofile(f)
+        for a in (lam, mu, rho):
+            np.asarray(a, dtype=np.float64).tofile(f)
     topo = Topology(mesh.xyz, mesh.elem, mesh.period)
-    n = elem.shape[0]
-    B = Blocks(topo, p, np.full(n, 2.0), np.full(n, 1.0), np.full(n, 1.0))
+    B = Blocks(topo, p, lam, mu, rho)
     # points: the centroids of the two sub-simplices and of the face
     pts = []
     for j, F in enumerate(topo.faces):
@@ -71,8 +76,8 @@ def test_library_dual_basis_equals_oracle_gram_schmidt(harness, tmp_path, name):
     with open(pfile, "wb") as f:
         np.array([K], dtype=np.int64).tofile(f)
         pts.tofile(f)
-    ffile, bfile = tmp_path / "faces.bin", tmp_path / "blocks.bin"
-    subprocess.run([harness, str(mfile), str(pfile), str(ofile), str(ffile), str(bfile)], check=True)
+    ffile, bfile, dfile = tmp_path / "faces.bin", tmp_path / "blocks.bin", tmp_path / "data.bin"
+    subprocess.run([harness, str(mfile), str(pfile), str(ofile), str(ffile), str(bfile), str(dfile)], check=True)
     # the face table (numbering by left element and local face, sides)
     faces = np.fromfile(ffile, dtype=np.int32).reshape(-1, 4)
     assert np.array_equal(faces, [[F.left, F.lf, F.right, F.rf] for F in topo.faces])
@@ -97,3 +102,20 @@ def test_library_dual_basis_equals_oracle_gram_schmidt(harness, tmp_path, name):
             worst_d = max(worst_d, np.abs(Dt[j, side] - ref).max() / np.abs(ref).max())
     print(f"{name}: worst relative difference of the coupling blocks {worst_d:.2e}")
     assert worst_d <= 1e-11
+    # dual material (volume-weighted Lame parameters), element mass rho |J| M_ref
+    # against the oracle's rho M_bar, and the time basis (Section 4)
+    nf, ne, nphi, ng = topo.n_face, topo.n_elem, B.nphi, pg + 1
+    data = np.fromfile(dfile, dtype=np.float64)
+    sizes = [2 * nf, ne, nphi * nphi, ng, ng, ng, ng, ng * ng]
+    assert data.size == sum(sizes)
+    face_lm, elem_w, Mref, tau, w, e0, e1, T = np.split(data, np.cumsum(sizes)[:-1])
+    face_lm = face_lm.reshape(nf, 2)
+    assert np.allclose(face_lm[:, 0], B.lam_j, rtol=1e-13, atol=0)
+    assert np.allclose(face_lm[:, 1], B.mu_j, rtol=1e-13, atol=0)
+    Mref = Mref.reshape(nphi, nphi)
+    for e in range(ne):
+        ref = B.rho[e] * B.Mbar[e]
+        assert np.abs(elem_w[e] * Mref - ref).max() <= 1e-12 * np.abs(ref).max(), e
+    tb = TimeBasis(pg)
+    for got_, ref_ in ((tau, tb.tau), (w, tb.w), (e0, tb.e0), (e1, tb.e1), (T, tb.T.ravel())):
+        assert np.allclose(got_, ref_, rtol=0, atol=1e-13)
