@@ -1,13 +1,16 @@
 """Benchmark of the velocity Schur-complement operator and the implicit time
 step on one MI355X.
 
-Workload (synthetic, shaped like the paper's 2D runs): 64x64 split-square
-mesh of the unit square (8192 triangles) with +-20% vertex jitter, free
-surface, p = 3 in space and p_gamma = 3 in time (space-time DG), three
-lognormal layers, a 10 Hz Ricker point source, dt = 2.5e-3.
+Headline workload (synthetic, shaped like the paper's 3D runs): the unit
+cube cut into 32^3 cubes of 6 Kuhn tetrahedra (196,608 tetrahedra),
+periodic, p = 2, Crank-Nicolson in time, homogeneous (rho, lambda, mu) =
+(1, 2, 1), dt = 0.01, starting from the L2 projection of the plane S-wave
+along (1,1,1)/sqrt(3) with polarisation (1,-1,0)/sqrt(2).  Its stored
+operator blocks (1.9 GB in FP64) exceed the 256 MB last-level cache, so the
+operator apply streams from HBM.
 
 A "step" is one implicit time step of the whole hot path: right-hand side,
-restarted GMRES on the velocity system to relative residual 1e-10, stress
+preconditioned CG on the velocity system to relative residual 1e-10, stress
 back-substitution and end-of-slab update, all in the library's kernels on
 inputs resident in HBM.
 
@@ -16,9 +19,14 @@ inputs resident in HBM.
 Prints one JSON line.  `value` is the matvec-equivalent throughput of the
 timed FP64 steps (velocity DOFs x operator applications / wall time);
 `roofline` reports the operator apply (face + element kernels) against the
-HBM peak from HIP-event timing of back-to-back applies; `cpu_baseline` is
-the FP64 oracle's explicit Schur CSR mat-vec on a bounded 12x12 sample of
-the same recipe.
+HBM peak from HIP-event timing of back-to-back applies on the launch stream;
+`cpu_baseline` is the FP64 oracle on the 16^3 version of the same recipe
+(24,576 tetrahedra), timed on one host core in a separate process while the
+GPU part runs: explicit Schur CSR mat-vec and one Schur-complement CG step to
+1e-10, with the per-DOF extrapolation to the full mesh stated.  Extra
+objects: the 2D space-time workload (64x64 jittered split square, p = 3,
+p_gamma = 3; its 63 MB operator is cache-resident), 64 batched point
+sources, and 16 meshes of uneven size in one step.
 """
 from __future__ import annotations
 
@@ -32,38 +40,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "velocity-matvec GDOF/s + s per implicit step to 1e-10 residual, FP64 vs chosen"
+# the oracle's sample of the headline recipe: 16^3 Kuhn cubes
+CPU_SAMPLE_N = 16
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def cpu_baseline(seconds=10.0):
-    """The oracle, as it stands, timed on the host: explicit Schur CSR SpMV
-    (SciPy, single-threaded) on the 12x12 version of the workload recipe."""
-    import numpy as np
-    from threadpoolctl import threadpool_limits
-
-    import synth
-    from oracle.assemble import Blocks
-    from oracle.mesh import Topology
-    from oracle.slab import Slab
-    w = synth.workload("c2", scale=12)
-    m = w["mesh"]
-    with threadpool_limits(limits=1):
-        B = Blocks(Topology(m.xyz, m.elem, m.period), w["p"], w["lam"], w["mu"], w["rho"])
-        slab = Slab(B, w["p_gamma"], w["dt"], "stdg")
-        S = slab.schur()
-        v = np.random.default_rng(0).standard_normal(slab.nv)
-        reps = 0
-        t0 = time.perf_counter()
-        while time.perf_counter() - t0 < seconds:
-            S @ v
-            reps += 1
-        dt = time.perf_counter() - t0
-    return {"value": slab.nv * reps / dt / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"scipy CSR mat-vec of the explicit FP64 Schur complement on the 12x12 (288-triangle, "
-                      f"{slab.nv} DOF, nnz {S.nnz}) version of the workload recipe, {reps} applies in {dt:.1f}s"}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_traffic.json")
@@ -290,13 +273,196 @@ def nodal_points(mesh, p):
     return V[:, :1, :] + np.einsum("nl,eld->end", ref, E)
 
 
-def bench_3d_operator(args):
-    """3D operator on the 32^3 periodic Kuhn cube (196,608 tetrahedra, p=2,
-    Crank-Nicolson, homogeneous): the stored blocks (about 2 GB FP64) exceed
-    the last-level cache, so this apply runs from HBM.  Then the workload's 50
-    implicit steps (preconditioned CG to 1e-10) from a plane S-wave velocity, FP64 and
-    FP32 operator + FP64 refinement, with the energy drift (the scheme
-    conserves energy exactly in this setting, Section 5)."""
+
+
+def swave_3d():
+    """The plane S-wave of the headline workload at t = 0 as point functions
+    (data only): direction n = (1,1,1)/sqrt(3), k = 2 pi (1,1,1), polarisation
+    a = (1,-1,0)/sqrt(2), amplitude 0.1, mu = rho = 1 (c_s = 1):
+    v = 0.1 c_s a sin(k.x), sigma = -0.1 mu (a n^T + n a^T) sin(k.x), Voigt
+    order (xx, yy, zz, yz, xz, xy)."""
+    import numpy as np
+    a = np.array([1.0, -1.0, 0.0]) / np.sqrt(2.0)
+    nn = np.ones(3) / np.sqrt(3.0)
+    S = -0.1 * (np.outer(a, nn) + np.outer(nn, a))
+    sv = np.array([S[0, 0], S[1, 1], S[2, 2], S[1, 2], S[0, 2], S[0, 1]])
+
+    def phase(x):
+        return np.sin(2.0 * np.pi * np.asarray(x).sum(axis=1))
+
+    return (lambda x: 0.1 * np.outer(phase(x), a)), (lambda x: np.outer(phase(x), sv))
+
+
+def host_info():
+    """Host CPU model, core count and memory for the cpu_baseline record."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    mem_gb = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    mem_gb = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "cpus_available": avail, "ram_gib": mem_gb}
+
+
+def oracle_worker(conn, n):
+    """Child process of the cpu_baseline leg (no GPU): builds the oracle on
+    the n^3 version of the headline recipe, then, on request, times it on
+    one core and compares the GPU's step results with the oracle's."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle.assemble import Blocks
+    from oracle.mesh import Topology
+    from oracle.slab import Slab
+    try:
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            w = synth.workload("c3", scale=n)
+            m = w["mesh"]
+            B = Blocks(Topology(m.xyz, m.elem, m.period), w["p"], w["lam"], w["mu"], w["rho"])
+            log(f"oracle sample: blocks of {m.n_elem} tets built ({time.perf_counter() - t0:.0f} s)")
+            slab = Slab(B, 0, w["dt"], "cn")
+            log(f"oracle sample: coupled slab matrix assembled ({time.perf_counter() - t0:.0f} s)")
+            S = slab.schur()
+            build_s = time.perf_counter() - t0
+            log(f"oracle sample: Schur complement formed, nnz {S.nnz} ({build_s:.0f} s)")
+            conn.send(("ready", build_s))
+            msg = conn.recv()
+            if msg[0] != "go":
+                return
+            v0, s0_can, gpu = msg[1], msg[2], msg[3]
+            nf = B.topo.n_face
+            s0 = np.stack([B.from_canonical(j, s0_can[j]) for j in range(nf)])
+            # explicit Schur CSR mat-vec
+            x = np.random.default_rng(0).standard_normal(slab.nv)
+            reps = 0
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < 5.0:
+                S @ x
+                reps += 1
+            t_spmv = (time.perf_counter() - t0) / reps
+            log(f"oracle sample: Schur mat-vec {t_spmv * 1e3:.1f} ms")
+            # one step: right-hand side, CG on the Schur complement to 1e-10, back-substitution
+            t0 = time.perf_counter()
+            _, _, v1, s1, its = slab.step_schur(v0, s0, rtol=1e-10)
+            t_step = time.perf_counter() - t0
+            log(f"oracle sample: CG step to 1e-10 in {t_step:.1f} s ({its} iterations)")
+            # reference step for the GPU's per-result errors: CG to 1e-13
+            _, _, vr, sr, _ = slab.step_schur(v0, s0, rtol=1e-13)
+            sr_can = np.stack([B.to_canonical(j, sr[j]) for j in range(nf)])
+            errs = {}
+            for name, (vg, sg) in gpu.items():
+                errs[name] = {"velocity_rel_l2": float(np.linalg.norm(vg - vr) / np.linalg.norm(vr)),
+                              "stress_rel_l2": float(np.linalg.norm(sg - sr_can) / np.linalg.norm(sr_can))}
+            conn.send(("done", dict(n=n, n_elem=m.n_elem, nv=slab.nv, nnz=int(S.nnz), build_s=build_s,
+                                    t_spmv=t_spmv, spmv_reps=reps, t_step=t_step, iters=int(its), errors=errs)))
+    except Exception as e:  # reported in the bench line instead of a baseline
+        try:
+            conn.send(("error", repr(e)))
+        except Exception:
+            pass
+
+
+def start_oracle(n):
+    """Start the oracle child process.  Called before anything touches the
+    GPU, so the child is a fresh interpreter started from a process with no
+    GPU state."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    parent, child = ctx.Pipe()
+    proc = ctx.Process(target=oracle_worker, args=(child, n), daemon=True)
+    proc.start()
+    return proc, parent
+
+
+def finish_oracle(proc, conn, v0, s0, gpu_results, full_elems, timeout=1800):
+    """Hand the sample state and the GPU's results to the oracle child, wait
+    for its timings and errors, and build the cpu_baseline record."""
+    log("waiting for the oracle sample (cpu_baseline) ...")
+    if not conn.poll(timeout):
+        proc.kill()
+        return None, None
+    msg = conn.recv()
+    if msg[0] != "ready":
+        log(f"oracle sample failed: {msg[1]}")
+        return None, None
+    conn.send(("go", v0, s0, gpu_results))
+    if not conn.poll(timeout):
+        proc.kill()
+        return None, None
+    msg = conn.recv()
+    proc.join(timeout=60)
+    if msg[0] != "done":
+        log(f"oracle sample failed: {msg[1]}")
+        return None, None
+    r = msg[1]
+    mv = r["iters"] + 1
+    scale = full_elems / r["n_elem"]
+    cpu = {"value": r["nv"] * mv / r["t_step"] / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+           "sample": (f"FP64 oracle (SciPy, one thread) on the {r['n']}^3 version of the workload recipe "
+                      f"({r['n_elem']} tetrahedra, {r['nv']} velocity DOFs, Schur CSR nnz {r['nnz']}): one "
+                      f"step = right-hand side + unpreconditioned CG on the explicit Schur complement to 1e-10 "
+                      f"({r['iters']} iterations) + stress back-substitution in {r['t_step']:.2f} s; value = "
+                      f"velocity DOFs x (iterations + 1) / step time.  Built in {r['build_s']:.0f} s in a "
+                      f"separate process while the GPU part ran (not timed)."),
+           "s_per_step_sample": r["t_step"],
+           "s_per_step_extrapolated_full_mesh": r["t_step"] * scale,
+           "extrapolation": f"per DOF (x{scale:.0f}) at the sample's iteration count",
+           "schur_spmv": {"s_per_apply": r["t_spmv"], "gdofs": r["nv"] / r["t_spmv"] / 1e9, "reps": r["spmv_reps"]},
+           "host": host_info()}
+    return cpu, r["errors"]
+
+
+
+
+def time_applies(ctx, n, prec, reps, ncols=1):
+    """Mean time of back-to-back operator applies from HIP events recorded on
+    the stream the kernels are launched on (torch's current stream, which
+    the binding passes to the library)."""
+    import torch
+    x = torch.randn(n * ncols, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(max(3, reps // 10)):
+        ctx.apply(x, y, prec, stream=stream, n_rhs=ncols)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        ctx.apply(x, y, prec, stream=stream, n_rhs=ncols)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def b_alg(sizes, prec_bytes_key="op_bytes_f64"):
+    """Algorithmic bytes of one apply: the stored blocks read once, v in and
+    y out (FP64), the face records and dual material, the element weights."""
+    n = sizes["n_vel_slab"]
+    return sizes[prec_bytes_key] + 2 * n * 8 + sizes["n_face"] * (16 + 16) + sizes["n_elem"] * 8
+
+
+def bench_c3(args):
+    """The headline workload: applies, then W warmup and K timed implicit
+    steps in FP64 and with the FP32 operator inside FP64 refinement, from the
+    projected plane S-wave; energy drift over the workload's 50 steps."""
     import numpy as np
     import torch
 
@@ -306,80 +472,193 @@ def bench_3d_operator(args):
     mesh = w["mesh"]
     t0 = time.time()
     ctx = sdg.Context(0)
-    sizes = ctx.setup(mesh.xyz, mesh.elem, mesh.period, 2, 0, sdg.SDG_SCHEME_CN, w["dt"], w["lam"], w["mu"],
-                      w["rho"], sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND)
-    log(f"3D setup {time.time() - t0:.1f}s: {sizes['n_elem']} tets, operator {sizes['op_bytes_f64'] / 1e9:.2f} GB; "
-        f"autotune f64 {[round(x, 1) for x in sizes['tune_us_f64']]} -> {sizes['op_variant']}")
+    sizes = ctx.setup(mesh.xyz, mesh.elem, mesh.period, w["p"], w["p_gamma"], sdg.SDG_SCHEME_CN, w["dt"],
+                      w["lam"], w["mu"], w["rho"], sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND)
+    log(f"C3 setup {time.time() - t0:.1f}s: {sizes['n_elem']} tets, {sizes['n_face']} faces, operator "
+        f"{sizes['op_bytes_f64'] / 1e9:.2f} GB; autotune f64 {[round(x, 1) for x in sizes['tune_us_f64']]} -> "
+        f"{sizes['op_variant']}, f32 {[round(x, 1) for x in sizes['tune_us_f32']]} -> {sizes['op_variant_f32']}")
     n = sizes["n_vel_slab"]
-    x = torch.randn(n, dtype=torch.float64, device="cuda")
-    y = torch.empty_like(x)
-    res = {"elements": sizes["n_elem"], "velocity_dofs": n, "operator_bytes_f64": sizes["op_bytes_f64"],
-           "face_kernel_variant": sizes["op_variant"]}
-    for prec, key, ob in ((sdg.SDG_PREC_F64, "fp64", sizes["op_bytes_f64"]),
-                          (sdg.SDG_PREC_F32, "fp32", sizes["op_bytes_f32"])):
-        for _ in range(3):
-            ctx.apply(x, y, prec)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        reps = 20
-        for _ in range(reps):
-            ctx.apply(x, y, prec)
-        e1.record()
-        e1.synchronize()
-        t = e0.elapsed_time(e1) / 1e3 / reps
-        b_alg = ob + 2 * n * 8 + sizes["n_face"] * 32 + sizes["n_elem"] * 8
-        res[key] = {"apply_us": t * 1e6, "gdofs": n / t / 1e9, "algorithmic_gbs": b_alg / t / 1e9,
-                    "hbm_frac": b_alg / t / 1e9 / HBM_PEAK_GBS}
-        log(f"3D apply {key}: {t * 1e6:.0f} us, {n / t / 1e9:.2f} GDOF/s, {b_alg / t / 1e9:.0f} GB/s "
-            f"({100 * b_alg / t / 1e9 / HBM_PEAK_GBS:.1f}% of HBM peak)")
-    res["traffic_per_apply_bytes"] = measured_traffic("c3", sizes["op_variant"])
+    ta64 = time_applies(ctx, n, sdg.SDG_PREC_F64, args.applies)
+    ta32 = time_applies(ctx, n, sdg.SDG_PREC_F32, args.applies)
+    ba64, ba32 = b_alg(sizes), b_alg(sizes, "op_bytes_f32")
+    log(f"C3 apply FP64 {ta64 * 1e6:.1f} us ({n / ta64 / 1e9:.2f} GDOF/s, {ba64 / ta64 / 1e9:.0f} GB/s "
+        f"algorithmic, {ba64 / ta64 / 1e9 / HBM_PEAK_GBS:.3f} of HBM); FP32 {ta32 * 1e6:.1f} us "
+        f"({n / ta32 / 1e9:.2f} GDOF/s, {ba32 / ta32 / 1e9:.0f} GB/s)")
 
-    # plane S-wave velocity: direction (1,1,1)/sqrt(3), polarisation (1,-1,0)/sqrt(2), alpha 0.1, c_s 1
-    X = nodal_points(mesh, 2)                                # (n_elem, N_phi, 3)
-    pol = np.array([1.0, -1.0, 0.0]) / np.sqrt(2.0)
-    phase = 2.0 * np.pi * X.sum(axis=2)                      # k.x with k = 2 pi (1, 1, 1)
-    v0 = 0.1 * pol[None, :, None] * np.sin(phase)[:, None, :]  # (n_elem, 3, N_phi)
-    steps = w["steps"]  # 50
-    for name, prec in (("fp64_steps", sdg.SDG_PREC_F64), ("fp32_operator_fp64_refinement_steps", sdg.SDG_PREC_F32)):
-        v = torch.tensor(np.ascontiguousarray(v0).ravel(), dtype=torch.float64, device="cuda")
-        s = torch.zeros(sizes["n_stress_state"], dtype=torch.float64, device="cuda")
-        opts = _solve_opts(sdg, prec, sdg.SDG_PRECOND_BLOCK)
-        if prec == sdg.SDG_PREC_F32:
-            opts.inner_rtol = IR_INNER_RTOL_3D
-        E0 = ctx.energy(v, s)
-        drift = 0.0
-        its = 0
+    t0 = time.time()
+    vel_fn, sig_fn = swave_3d()
+    v, s = ctx.project_state(vel_fn, sig_fn)
+    log(f"C3 initial state: L2 projection of the plane S-wave in {time.time() - t0:.1f}s")
+    opts64 = _solve_opts(sdg, sdg.SDG_PREC_F64, sdg.SDG_PRECOND_BLOCK)
+    opts32 = _solve_opts(sdg, sdg.SDG_PREC_F32, sdg.SDG_PRECOND_BLOCK)
+    opts32.inner_rtol = IR_INNER_RTOL_3D
+    E0 = ctx.energy(v, s)
+    drift = 0.0
+    for _ in range(args.warmup):
+        ctx.step(v, s, None, opts=opts64)
+        drift = max(drift, abs(ctx.energy(v, s) - E0) / E0)
+    log(f"C3 warmup {args.warmup} steps done")
+    v_save, s_save = v.clone(), s.clone()
+    res = {}
+    for name, opts in (("fp64", opts64), ("fp32_operator_fp64_refinement", opts32)):
+        v.copy_(v_save)
+        s.copy_(s_save)
+        Ea = ctx.energy(v, s)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        mv = it = 0
+        for _ in range(args.steps):
             info = ctx.step(v, s, None, opts=opts)
-            its += info["iterations"]
-            drift = max(drift, abs(ctx.energy(v, s) - E0) / E0)
+            mv += info["matvecs"]
+            it += info["iterations"]
         torch.cuda.synchronize()
-        t = (time.perf_counter() - t0) / steps
-        res[name] = {"s_per_step": t, "iterations_per_step": its / steps, "max_rel_energy_drift": drift,
-                     "note": "wall time includes one energy evaluation per step"}
-        log(f"3D Crank-Nicolson {name}: {t * 1e3:.1f} ms/step, {its / steps:.1f} CG it/step, "
-            f"energy drift {drift:.2e}")
-    fast = min(("fp64_steps", "fp32_operator_fp64_refinement_steps"), key=lambda k: res[k]["s_per_step"])
-    res["chosen"] = {"path": fast, "s_per_step": res[fast]["s_per_step"]}
+        t = time.perf_counter() - t0
+        res[name] = {"s_per_step": t / args.steps, "matvecs_per_step": mv / args.steps,
+                     "iterations_per_step": it / args.steps, "gdofs": n * mv / t / 1e9,
+                     "rel_energy_change_over_timed_steps": abs(ctx.energy(v, s) - Ea) / Ea,
+                     "state": (v.clone(), s.clone())}
+        log(f"C3 {name}: {args.steps} steps in {t:.3f}s ({t / args.steps * 1e3:.2f} ms/step), "
+            f"{it / args.steps:.1f} CG it/step, {mv / args.steps:.1f} matvecs/step")
+    (v64, s64), (v32, s32) = res["fp64"].pop("state"), res["fp32_operator_fp64_refinement"].pop("state")
+    diff32 = {"velocity_rel_l2": float((v32 - v64).norm() / v64.norm()),
+              "stress_rel_l2": float((s32 - s64).norm() / s64.norm())}
+    # the rest of the workload's 50 steps (FP64, untimed): energy drift from t = 0
+    v.copy_(v64)
+    s.copy_(s64)
+    drift = max(drift, abs(ctx.energy(v, s) - E0) / E0)
+    for _ in range(max(0, w["steps"] - args.warmup - args.steps)):
+        ctx.step(v, s, None, opts=opts64)
+        drift = max(drift, abs(ctx.energy(v, s) - E0) / E0)
+    log(f"C3 energy: largest relative drift over the {max(w['steps'], args.warmup + args.steps)} steps "
+        f"{drift:.2e}")
+    out = dict(sizes=sizes, n=n, ta64=ta64, ta32=ta32, ba64=ba64, ba32=ba32, steps=res, diff32=diff32,
+               drift=drift, n_steps_drift=max(w["steps"], args.warmup + args.steps))
+    ctx.close()
+    return out
+
+
+def bench_c3_sample(n_cubes):
+    """The headline recipe on n^3 cubes for the per-result errors against the
+    oracle: one FP64 step and one FP32-operator + FP64-refinement step at the
+    benchmark's solver options from a seeded random state (velocity slab
+    state and canonical stress DOFs).  Returns host arrays."""
+    import numpy as np
+    import torch
+
+    import paper_1802_04516_amd as sdg
+    import synth
+    w = synth.workload("c3", scale=n_cubes)
+    mesh = w["mesh"]
+    ctx = sdg.Context(0)
+    sz = ctx.setup(mesh.xyz, mesh.elem, mesh.period, w["p"], w["p_gamma"], sdg.SDG_SCHEME_CN, w["dt"],
+                   w["lam"], w["mu"], w["rho"], sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND)
+    rng = np.random.default_rng(9301)
+    v0 = rng.standard_normal((sz["n_elem"], 3, sz["n_phi"]))
+    s0 = 0.1 * rng.standard_normal((sz["n_face"], 6, sz["n_psi"]))
+    opts64 = _solve_opts(sdg, sdg.SDG_PREC_F64, sdg.SDG_PRECOND_BLOCK)
+    opts32 = _solve_opts(sdg, sdg.SDG_PREC_F32, sdg.SDG_PRECOND_BLOCK)
+    opts32.inner_rtol = IR_INNER_RTOL_3D
+    out = {}
+    for name, o in (("fp64", opts64), ("fp32_operator_fp64_refinement", opts32)):
+        v = torch.tensor(v0.ravel(), dtype=torch.float64, device="cuda")
+        s = torch.tensor(s0.ravel(), dtype=torch.float64, device="cuda")
+        ctx.step(v, s, None, opts=o)
+        torch.cuda.synchronize()
+        out[name] = (v.cpu().numpy().reshape(v0.shape), s.cpu().numpy().reshape(s0.shape))
+    ctx.close()
+    return v0, s0, out
+
+
+def bench_c2(args):
+    """The 2D space-time workload (64x64 jittered split square, 8192
+    triangles, p = 3, p_gamma = 3, layered lognormal media, 10 Hz Ricker
+    source, dt = 2.5e-3, GMRES(15) with the element block preconditioner to
+    1e-10).  Its operator (63 MB) is resident in the 256 MB last-level cache
+    after the first apply."""
+    import numpy as np
+    import torch
+
+    import paper_1802_04516_amd as sdg
+    import synth
+    w = synth.workload("c2")
+    mesh = w["mesh"]
+    ctx = sdg.Context(0)
+    sizes = ctx.setup(mesh.xyz, mesh.elem, mesh.period, w["p"], w["p_gamma"], sdg.SDG_SCHEME_STDG, w["dt"],
+                      w["lam"], w["mu"], w["rho"], sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND)
+    log(f"C2 autotune f64 {[round(x, 1) for x in sizes['tune_us_f64']]} -> {sizes['op_variant']}, "
+        f"f32 {[round(x, 1) for x in sizes['tune_us_f32']]} -> {sizes['op_variant_f32']}")
+    src = w["sources"]
+    ctx.set_sources(src["pos"], src["dir"])
+    n = sizes["n_vel_slab"]
+    tau = np.array(sizes["tau"])
+
+    def amp_at(step):
+        t = step * w["dt"] + tau * w["dt"]
+        return synth.ricker(t, src["f0"], src["t_delay"])[None, :]
+
+    v = torch.zeros(sizes["n_vel_state"], dtype=torch.float64, device="cuda")
+    s = torch.zeros(sizes["n_stress_state"], dtype=torch.float64, device="cuda")
+    step0 = int(0.05 / w["dt"])  # the source switches on around t_delay
+    o64 = _solve_opts(sdg, sdg.SDG_PREC_F64, sdg.SDG_PRECOND_BLOCK)
+    o32 = _solve_opts(sdg, sdg.SDG_PREC_F32, sdg.SDG_PRECOND_BLOCK)
+    o32.inner_rtol = IR_INNER_RTOL
+    ox = _solve_opts(sdg, sdg.SDG_PREC_F64, sdg.SDG_PRECOND_BLOCK, sdg.SDG_SOLVE_EXTRAPOLATE)
+    og = _solve_opts(sdg, sdg.SDG_PREC_F64, sdg.SDG_PRECOND_BLOCK, sdg.SDG_SOLVE_GRAPH, sdg.SDG_SOLVER_GMRES)
+    for k in range(args.warmup):
+        ctx.step(v, s, amp_at(step0 + k), opts=o64)
+    v_save, s_save = v.clone(), s.clone()
+    res = {"n_elem": sizes["n_elem"], "velocity_dofs_per_slab": n, "cache_resident": True}
+    ref = None
+    for name, o in (("fp64", o64), ("fp32_operator_fp64_refinement", o32), ("fp64_extrapolated_guess", ox),
+                    ("fp64_hip_graph", og)):
+        v.copy_(v_save)
+        s.copy_(s_save)
+        if o.flags:  # seeds the previous slab / records the graphs
+            ctx.step(v, s, amp_at(step0 + args.warmup - 1), opts=o)
+            v.copy_(v_save)
+            s.copy_(s_save)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mv = it = 0
+        for k in range(args.steps):
+            info = ctx.step(v, s, amp_at(step0 + args.warmup + k), opts=o)
+            mv += info["matvecs"]
+            it += info["iterations"]
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        if ref is None:
+            ref = v.clone()
+        res[name] = {"s_per_step": t / args.steps, "iterations_per_step": it / args.steps,
+                     "gdofs": n * mv / t / 1e9,
+                     "rel_diff_vs_fp64": float((v - ref).norm() / max(float(ref.norm()), 1e-300))}
+        log(f"C2 {name}: {t / args.steps * 1e3:.2f} ms/step, {it / args.steps:.1f} it/step")
+    ta64 = time_applies(ctx, n, sdg.SDG_PREC_F64, args.applies)
+    ta32 = time_applies(ctx, n, sdg.SDG_PREC_F32, args.applies)
+    ba = b_alg(sizes)
+    res["apply"] = {"fp64_us": ta64 * 1e6, "fp32_us": ta32 * 1e6, "fp64_gdofs": n / ta64 / 1e9,
+                    "algorithmic_gbs_fp64": ba / ta64 / 1e9, "frac_of_hbm_peak_fp64": ba / ta64 / 1e9 / HBM_PEAK_GBS,
+                    "face_kernel_variant_fp64": sizes["op_variant"],
+                    "traffic_per_apply_bytes": measured_traffic("c2", sizes["op_variant"])}
+    res["chosen"] = min(({"path": k, "s_per_step": res[k]["s_per_step"]}
+                         for k in ("fp64", "fp32_operator_fp64_refinement")), key=lambda d: d["s_per_step"])
+    log(f"C2 apply FP64 {ta64 * 1e6:.1f} us, FP32 {ta32 * 1e6:.1f} us")
     ctx.close()
     return res
+
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--applies", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--applies", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2")
-    ap.add_argument("--precond", default="block", choices=["none", "mass", "block"])
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched (64 sources), mesh-batch (16 meshes) and 3D operator measurements")
+                    help="skip the 2D workload, batched (64 sources) and mesh-batch (16 meshes) measurements")
     ap.add_argument("--apply-probe", action="store_true",
                     help="only run --reps operator applies of --workload (c2 or c3) with face-kernel --variant "
                          "(-1: autotuned) in --prec, for rocprofv3 counter runs")
+    ap.add_argument("--workload", default="c3")
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--prec", default="f64", choices=["f64", "f32"])
@@ -387,20 +666,21 @@ def main():
                     help="only run a plain device copy of 1 GiB x 10 (scale for the rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); more GPUs are not part of this build",
               file=sys.stderr)
         sys.exit(2)
+    oracle = None
+    if not (args.no_cpu_baseline or args.apply_probe or args.calibrate_copy):
+        # before anything touches the GPU: the oracle child starts from a
+        # process without GPU state
+        oracle = start_oracle(CPU_SAMPLE_N)
+        log(f"oracle sample ({CPU_SAMPLE_N}^3) building in process {oracle[0].pid}")
 
-    import numpy as np
     import torch
 
-    import paper_1802_04516_amd as sdg
-    import synth
-
-    dev = torch.device("cuda:0")
     if args.calibrate_copy:
         nbytes = 1 << 30
-        a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
         for _ in range(10):
             b.copy_(a)
@@ -411,193 +691,66 @@ def main():
     if args.apply_probe:
         apply_probe(args)
         return
-    w = synth.workload(args.workload)
-    mesh = w["mesh"]
-    scheme = sdg.SDG_SCHEME_CN if w["scheme"] == "cn" else sdg.SDG_SCHEME_STDG
-    t0 = time.time()
-    ctx = sdg.Context(0)
-    sizes = ctx.setup(mesh.xyz, mesh.elem, mesh.period, w["p"], w["p_gamma"], scheme, w["dt"],
-                      w["lam"], w["mu"], w["rho"],
-                      sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND)
-    log(f"setup {time.time() - t0:.1f}s: {sizes['n_elem']} elems, {sizes['n_face']} faces, "
-        f"{sizes['n_vel_slab']} velocity DOFs, operator {sizes['op_bytes_f64'] / 1e6:.1f} MB")
-    log(f"face-kernel autotune (us/apply, variants 0..7): f64 {[round(x, 1) for x in sizes['tune_us_f64']]} -> {sizes['op_variant']}, "
-        f"f32 {[round(x, 1) for x in sizes['tune_us_f32']]} -> {sizes['op_variant_f32']}")
-    src = w["sources"]
-    if src is not None:
-        ctx.set_sources(src["pos"], src["dir"])
-    n = sizes["n_vel_slab"]
-    tau = np.array(sizes["tau"])
 
-    def amp_at(step):
-        if src is None:
-            return None
-        t = step * w["dt"] + tau * w["dt"]
-        return synth.ricker(t, src["f0"], src["t_delay"])[None, :]
-
-    v = torch.zeros(sizes["n_vel_state"], dtype=torch.float64, device=dev)
-    s = torch.zeros(sizes["n_stress_state"], dtype=torch.float64, device=dev)
-    pc = {"none": sdg.SDG_PRECOND_NONE, "mass": sdg.SDG_PRECOND_MASS, "block": sdg.SDG_PRECOND_BLOCK}[args.precond]
-    opts64 = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F64, 1e-10, 5000, GMRES_RESTART, 5, 10, 1e-4, pc)
-    opts32 = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F32, 1e-10, 5000, GMRES_RESTART, 5, 10, IR_INNER_RTOL,
-                           pc)
-
-    # the source switches on around t_delay; start the run so that the timed
-    # steps see the wavelet
-    step0 = int(0.05 / w["dt"]) if src is not None else 0
-    for k in range(args.warmup):
-        ctx.step(v, s, amp_at(step0 + k), opts=opts64)
-    log(f"warmup {args.warmup} steps done")
-    v_save, s_save = v.clone(), s.clone()
-
-    # ---- timed FP64 steps
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    matvecs = iters = 0
-    for k in range(args.steps):
-        info = ctx.step(v, s, amp_at(step0 + args.warmup + k), opts=opts64)
-        matvecs += info["matvecs"]
-        iters += info["iterations"]
-    torch.cuda.synchronize()
-    t64 = time.perf_counter() - t0
-    log(f"FP64: {args.steps} steps in {t64:.3f}s, {iters / args.steps:.1f} GMRES it/step, "
-        f"{matvecs / args.steps:.1f} matvecs/step")
-    v64 = v.clone()
-
-    # ---- the chosen path: FP32 operator inside FP64 iterative refinement
-    v.copy_(v_save)
-    s.copy_(s_save)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    it32 = mv32 = 0
-    for k in range(args.steps):
-        info = ctx.step(v, s, amp_at(step0 + args.warmup + k), opts=opts32)
-        it32 += info["iterations"]
-        mv32 += info["matvecs"]
-    torch.cuda.synchronize()
-    t32 = time.perf_counter() - t0
-    err32 = float((v - v64).norm() / max(float(v64.norm()), 1e-300))
-    log(f"FP32+IR: {args.steps} steps in {t32:.3f}s, {it32 / args.steps:.1f} inner it/step, "
-        f"rel diff to FP64 {err32:.2e}")
-
-    # ---- FP64 steps with the extrapolated initial guess
-    v.copy_(v_save)
-    s.copy_(s_save)
-    optsx = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F64, 1e-10, 5000, GMRES_RESTART, 5, 10, 1e-4, pc)
-    optsx.flags = sdg.SDG_SOLVE_EXTRAPOLATE
-    ctx.step(v, s, amp_at(step0 + args.warmup - 1), opts=optsx)  # seeds the previous slab
-    v.copy_(v_save)
-    s.copy_(s_save)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    itx = 0
-    for k in range(args.steps):
-        info = ctx.step(v, s, amp_at(step0 + args.warmup + k), opts=optsx)
-        itx += info["iterations"]
-    torch.cuda.synchronize()
-    tx = time.perf_counter() - t0
-    errx = float((v - v64).norm() / max(float(v64.norm()), 1e-300))
-    log(f"FP64 extrapolated guess: {args.steps} steps in {tx:.3f}s, {itx / args.steps:.1f} it/step, "
-        f"rel diff to FP64 {errx:.2e}")
-
-    # ---- FP64 steps recorded in HIP graphs
-    v.copy_(v_save)
-    s.copy_(s_save)
-    optsg = sdg.SolveOpts(sdg.SDG_SOLVER_GMRES, sdg.SDG_PREC_F64, 1e-10, 5000, GMRES_RESTART, 5, 10, 1e-4, pc)
-    optsg.flags = sdg.SDG_SOLVE_GRAPH
-    ctx.step(v, s, amp_at(step0 + args.warmup), opts=optsg)  # records the graphs
-    v.copy_(v_save)
-    s.copy_(s_save)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    itg = 0
-    for k in range(args.steps):
-        info = ctx.step(v, s, amp_at(step0 + args.warmup + k), opts=optsg)
-        itg += info["iterations"]
-    torch.cuda.synchronize()
-    tg = time.perf_counter() - t0
-    errg = float((v - v64).norm() / max(float(v64.norm()), 1e-300))
-    log(f"FP64 graph: {args.steps} steps in {tg:.3f}s, {itg / args.steps:.1f} it/step (full cycles), "
-        f"rel diff to FP64 {errg:.2e}")
-
-    # ---- operator apply timing (HIP events on the launch stream)
-    x = torch.randn(n, dtype=torch.float64, device=dev)
-    y = torch.empty_like(x)
-    stream = torch.cuda.current_stream()
-
-    def time_applies(prec):
-        for _ in range(20):
-            ctx.apply(x, y, prec)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.applies):
-            ctx.apply(x, y, prec)
-        e1.record(stream)
-        e1.synchronize()
-        return e0.elapsed_time(e1) / 1e3 / args.applies
-
-    ta64 = time_applies(sdg.SDG_PREC_F64)
-    ta32 = time_applies(sdg.SDG_PREC_F32)
-    n_elem, n_face = sizes["n_elem"], sizes["n_face"]
-    small = n_face * (16 + 16) + n_elem * 8
-    balg64 = sizes["op_bytes_f64"] + 2 * n * 8 + small
-    balg32 = sizes["op_bytes_f32"] + 2 * n * 8 + small
-    ach = balg64 / ta64 / 1e9
-    log(f"apply FP64 {ta64 * 1e6:.1f} us ({n / ta64 / 1e9:.2f} GDOF/s, {ach:.0f} GB/s algorithmic); "
-        f"FP32 {ta32 * 1e6:.1f} us ({n / ta32 / 1e9:.2f} GDOF/s, {balg32 / ta32 / 1e9:.0f} GB/s)")
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("timing the oracle on the host (cpu_baseline) ...")
-        cpu = cpu_baseline()
-        log(f"cpu_baseline {cpu['value']:.4f} GDOF/s")
-
-    value = n * matvecs / t64 / 1e9
+    c3 = bench_c3(args)
+    sz = c3["sizes"]
+    st = c3["steps"]
+    t64 = st["fp64"]["s_per_step"]
+    ach = c3["ba64"] / c3["ta64"] / 1e9
     out = {
-        "metric": "velocity-matvec GDOF/s + s per implicit step to 1e-10 residual, FP64 vs chosen",
-        "value": value,
+        "metric": METRIC,
+        "value": st["fp64"]["gdofs"],
         "unit": "GDOF/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": t64 / args.steps * 1e3,
+        "ms_per_step": t64 * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "2D 64x64 jittered split square (8192 tris), p=3, p_gamma=3, layered "
-                               "lognormal media, 10 Hz Ricker source, dt=2.5e-3, GMRES(15) with the element "
-                               "block preconditioner to 1e-10",
-                   "n_elem": n_elem, "velocity_dofs_per_slab": n, "parallelism": "single GPU"},
-        "s_per_step": {"fp64": t64 / args.steps, "fp32_operator_fp64_refinement": t32 / args.steps,
-                       "fp64_hip_graph": tg / args.steps, "fp64_extrapolated_guess": tx / args.steps},
-        "chosen": min(({"path": "fp64", "s_per_step": t64 / args.steps},
-                       {"path": "fp32_operator_fp64_refinement", "s_per_step": t32 / args.steps}),
-                      key=lambda d: d["s_per_step"]),
-        "iterations_per_step": {"fp64": iters / args.steps, "fp32_ir_inner": it32 / args.steps,
-                                "fp64_hip_graph": itg / args.steps, "fp64_extrapolated_guess": itx / args.steps},
-        "fp64_extrapolated_rel_diff_vs_fp64": errx,
-        "fp64_hip_graph_rel_diff_vs_fp64": errg,
-        "matvec_kernel": {"fp64_us": ta64 * 1e6, "fp64_gdofs": n / ta64 / 1e9,
-                          "fp32_us": ta32 * 1e6, "fp32_gdofs": n / ta32 / 1e9},
-        "fp32_ir_rel_diff_vs_fp64": err32,
+        "config": {"workload": "3D unit cube, 32^3 cubes x 6 Kuhn tetrahedra (196,608 tets), periodic, p=2, "
+                               "Crank-Nicolson, homogeneous (rho, lambda, mu) = (1, 2, 1), dt=0.01, plane S-wave "
+                               "initial data (L2 projection), CG with the element block preconditioner to 1e-10",
+                   "n_elem": sz["n_elem"], "n_face": sz["n_face"], "velocity_dofs_per_slab": c3["n"],
+                   "operator_bytes_fp64": sz["op_bytes_f64"], "parallelism": "single GPU"},
+        "s_per_step": {"fp64": t64, "fp32_operator_fp64_refinement": st["fp32_operator_fp64_refinement"]["s_per_step"]},
+        "chosen": min(({"path": k, "s_per_step": st[k]["s_per_step"]}
+                       for k in ("fp64", "fp32_operator_fp64_refinement")), key=lambda d: d["s_per_step"]),
+        "steps_detail": st,
+        "fp32_ir_diff_vs_fp64_after_timed_steps": c3["diff32"],
+        "energy": {"max_rel_drift": c3["drift"], "steps": c3["n_steps_drift"],
+                   "note": "Crank-Nicolson conserves the discrete energy exactly here (Section 5); the drift "
+                           "is the solver tolerance's"},
+        "matvec_kernel": {"fp64_us": c3["ta64"] * 1e6, "fp64_gdofs": c3["n"] / c3["ta64"] / 1e9,
+                          "fp32_us": c3["ta32"] * 1e6, "fp32_gdofs": c3["n"] / c3["ta32"] / 1e9,
+                          "fp32_algorithmic_gbs": c3["ba32"] / c3["ta32"] / 1e9,
+                          "face_kernel_variant": {"fp64": sz["op_variant"], "fp32": sz["op_variant_f32"]}},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("c2", sizes["op_variant"]),
-                     "kernel": f"velocity operator apply (face kernel variant {sizes['op_variant']} + element "
-                               f"kernel), FP64",
-                     "bytes_per_launch": balg64},
-        "cpu_baseline": cpu,
+                     "traffic": measured_traffic("c3", sz["op_variant"]),
+                     "kernel": f"velocity operator apply (face kernel variant {sz['op_variant']} + element kernel), "
+                               f"FP64",
+                     "bytes_per_launch": c3["ba64"]},
+        "cpu_baseline": None,
     }
-    ctx.close()
     if not args.no_extras:
-        out["batched_64_sources"] = bench_batched(args, t64 / args.steps)
+        out["workload_2d_space_time"] = bench_c2(args)
+        out["batched_64_sources"] = bench_batched(args, out["workload_2d_space_time"]["fp64"]["s_per_step"])
         out["mesh_batch_16"] = bench_mesh_batch(args)
-        out["operator_3d"] = bench_3d_operator(args)
+    if oracle is not None:
+        v0, s0, gpu = bench_c3_sample(CPU_SAMPLE_N)
+        cpu, errs = finish_oracle(oracle[0], oracle[1], v0, s0, gpu, sz["n_elem"])
+        out["cpu_baseline"] = cpu
+        out["error_vs_oracle_per_step"] = {
+            "sample": f"{CPU_SAMPLE_N}^3 version of the workload recipe, one step from a seeded random state at "
+                      f"the benchmark's solver options; oracle: Schur-complement CG to 1e-13",
+            **(errs or {})}
+        if cpu:
+            log(f"cpu_baseline {cpu['value']:.4f} GDOF/s, {cpu['s_per_step_sample']:.2f} s/step on the sample; "
+                f"errors vs oracle {errs}")
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -163,18 +163,19 @@ void sdg_destroy(sdg_ctx* ctx);
  * elem[n_elem*(dim+1)] (host, vertex indices).  period (host, dim doubles)
  * or NULL: on a periodic mesh vertices on opposite sides are identified and
  * each element is unwrapped by the minimum-image rule relative to its first
- * vertex.  Faces with a single element are free-surface boundaries.
+ * vertex.  Boundary conditions (Section 6): the paper's tests use periodic
+ * boundaries (given by `period`) and the free surface sigma . n = 0; a face
+ * with a single element is a free-surface face, so no per-face boundary tag
+ * is taken (an interior face cannot be free surface, and a one-sided face
+ * has no other condition to carry).  The dual element of a free-surface face
+ * is T_{l,j} alone and the face integral of eq. (MD_3) is dropped there
+ * (natural traction-free condition).
  * Returns SDG_EMESH for a degenerate element, a face shared by more than
- * two elements or an unmatched periodic face. */
+ * two elements or an unmatched periodic face.  Replaces any earlier mesh
+ * and drops the point sources of sdg_set_sources. */
 int sdg_set_mesh(sdg_ctx* ctx, int dim, int64_t n_vert, const double* xyz,
                  int64_t n_elem, const int64_t* elem, const double* period);
 
-/* Space degree p (Section 3: N_phi = C(p+dim, dim) velocity functions,
- * N_psi = (p+1)^2 in 2D and N_phi in 3D stress functions), time degree
- * p_gamma (N_gamma = p_gamma + 1), scheme SDG_SCHEME_STDG (eqs. NM25-NM26)
- * or SDG_SCHEME_CN (eqs. NM25.cn-NM26.cn, requires p_gamma = 0), time step
- * dt > 0.  SDG_EUNSUPPORTED if the (dim, p, N_gamma) kernels are not
- * compiled in. */
 /* A batch of independent meshes of one dimension (Section 3 for each),
  * solved together: mesh q has vertices xyz[vert_off[q]*dim ..
  * vert_off[q+1]*dim) and elements elem[elem_off[q]*(dim+1) ..
@@ -183,19 +184,38 @@ int sdg_set_mesh(sdg_ctx* ctx, int dim, int64_t n_vert, const double* xyz,
  * concatenates them into one mesh (meshes share no faces, no periodicity):
  * elements, faces, materials and every state vector are laid out mesh after
  * mesh in element order, and sdg_solve_step runs one Krylov process per mesh
- * (own tolerance, segmented reductions) inside shared launches.  Replaces any
- * earlier mesh. */
+ * (own tolerance, segmented reductions) inside shared launches.  Boundary
+ * faces are free surface as in sdg_set_mesh.  Replaces any earlier mesh and
+ * drops the point sources. */
 int sdg_set_mesh_batch(sdg_ctx* ctx, int dim, int n_mesh, const int64_t* vert_off, const double* xyz,
                        const int64_t* elem_off, const int64_t* elem);
 
+/* Space degree p (Section 3: N_phi = C(p+dim, dim) velocity functions,
+ * N_psi = (p+1)^2 in 2D and N_phi in 3D stress functions), time degree
+ * p_gamma (N_gamma = p_gamma + 1), scheme SDG_SCHEME_STDG (eqs. NM25-NM26)
+ * or SDG_SCHEME_CN (eqs. NM25.cn-NM26.cn, requires p_gamma = 0), time step
+ * dt > 0.  SDG_EUNSUPPORTED if the (dim, p, N_gamma) kernels are not
+ * compiled in.  A new p drops the point sources of sdg_set_sources (their
+ * basis values belong to the old degree). */
 int sdg_set_discretization(sdg_ctx* ctx, int p, int p_gamma, int scheme, double dt);
 
-/* Per-element Lame parameters and density (host, n_elem each, > 0).
- * E_j is constant per dual element with volume-weighted lambda, mu. */
+/* Per-element Lame parameters and density (host, n_elem each; lambda >= 0,
+ * mu > 0, rho > 0).  The density is discretised on the main grid and the
+ * stiffness on the dual grid (Section 4, eq. NM1); rho_i is taken constant
+ * per element and E_j, the isotropic Hooke law of eq. (1.1b), constant per
+ * dual element R_j with the volume-weighted lambda_j = (|T_{l,j}| lambda_l +
+ * |T_{r,j}| lambda_r) / |R_j| and likewise mu_j (the L2 projection of the
+ * piecewise-constant element values onto constants on R_j).  SDG_EINVAL for
+ * a non-finite or out-of-range value. */
 int sdg_set_material(sdg_ctx* ctx, const double* lambda, const double* mu, const double* rho);
 
 /* Build topology, geometry, bases and the operator blocks on the host and
- * upload them.  precisions = SDG_PREC_F64 | SDG_PREC_F32 selects which
+ * upload them: the element mass Mbar_i and time matrices of eqs. (MD_2) to
+ * (MD_2_3), the coupling blocks D_{i,j} of eq. (MD_3) in the canonical dual
+ * basis (where M_j = I, and Q_{i,j} of eq. (MD_6) equals -D_{i,j}^T by the
+ * identity of Section 5), and the dual material.  SDG_ESTATE unless mesh,
+ * discretization and material are set; SDG_EMESH for a mesh the set-up
+ * rejects.  precisions = SDG_PREC_F64 | SDG_PREC_F32 selects which
  * copies of the blocks are stored; OR in SDG_ASSEMBLE_BLOCK_PRECOND to also
  * invert the element diagonal blocks of the velocity operator (eq. pre1,
  * stored in FP32: (d N_phi)^2 floats per element for one time node; for
@@ -205,6 +225,10 @@ int sdg_set_material(sdg_ctx* ctx, const double* lambda, const double* mu, const
  * batched applies and solves (every Krylov vector holds max_rhs columns). */
 int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs);
 
+/* Sizes of the assembled discretization (Section 3: N_phi, N_psi, N_gamma
+ * and the unknown counts of eqs. NM25-NM26), the stored operator bytes and
+ * the autotuner's choices and timings, copied to *out (host).  SDG_ESTATE
+ * before sdg_assemble. */
 int sdg_query(const sdg_ctx* ctx, sdg_sizes* out);
 
 /* Face-kernel variant (tile shape) of the operator apply:
@@ -238,7 +262,9 @@ int sdg_set_operator_variant(sdg_ctx* ctx, int variant);
  * dividing 16, or N_phi > 16) use the column grid whatever is set. */
 int sdg_set_batched_variant(sdg_ctx* ctx, int bvariant);
 
-/* Face table in the library's face order (host arrays of n_face entries):
+/* Face table in the library's face order (Section 3: each face Gamma_j has a
+ * left element l(j) and, off the boundary, a right element r(j); host arrays
+ * of n_face entries):
  * left element, its local face, right element (-1 on the boundary), its
  * local face (-1 on the boundary).  Any pointer may be NULL. */
 int sdg_face_table(const sdg_ctx* ctx, int64_t* left, int32_t* left_face,
@@ -251,7 +277,10 @@ int sdg_face_table(const sdg_ctx* ctx, int64_t* left, int32_t* left_face,
 int sdg_apply_velocity_operator(sdg_ctx* ctx, const double* v, double* y, int n_rhs,
                                 int precision, void* stream);
 
-/* y = A^T w, A^T = T^T (x) rho Mbar + dt^2 (W T^-T W) (x) K (K symmetric). */
+/* y = A^T w: the transpose of the velocity operator of eq. (velocity.sys),
+ * A^T = T^T (x) rho Mbar + dt^2 (W T^-T W) (x) K (K is symmetric, Section 5),
+ * used by the discrete adjoint.  Same arguments, layouts and errors as
+ * sdg_apply_velocity_operator. */
 int sdg_apply_adjoint(sdg_ctx* ctx, const double* w, double* y, int n_rhs,
                       int precision, void* stream);
 
@@ -309,17 +338,47 @@ int sdg_energy(sdg_ctx* ctx, const double* v_state, const double* sigma_state, i
                double* out, void* stream);
 
 /* Velocity of a state at n_pts host points pts[n_pts*dim], written to
- * out[n_rhs*n_pts*dim] (device, [r][pt][c]).  Points outside the mesh give
- * SDG_EINVAL.  The located elements of the last point set are kept, so
+ * out[n_rhs*n_pts*dim] (device, [r][pt][c]): the expansion of eq. (NM1),
+ * v_h(x) = sum_k phi_k^(i)(x) v_{k,i} in the element i containing x (the
+ * receivers of Section 6).  Points outside the mesh give SDG_EINVAL; a point
+ * on a shared boundary takes the lowest element index.  The located elements of the last point set are kept, so
  * repeated calls with the same points locate them once. */
 int sdg_sample_velocity(sdg_ctx* ctx, const double* v_state, int n_rhs, int64_t n_pts,
                         const double* pts, double* out, void* stream);
 
-/* Stress of a state at points: pts[n_pts*dim] (host) with the face index
- * face[n_pts] (host) of the dual element each point lies in; out
- * [pt][s][r] (device). */
+/* Stress of a state at points: the expansion of eq. (NM1) on the dual grid,
+ * sigma_h(x) = sum_m psi_m^(j)(x) sigma_{m,j} in the canonical dual basis of
+ * face j.  pts[n_pts*dim] (host) with the face index face[n_pts] (host) of
+ * the dual element each point lies in; out [pt][s][r] (device).  SDG_EINVAL
+ * for a face index out of range. */
 int sdg_eval_stress(sdg_ctx* ctx, const double* sigma_state, int n_rhs, int64_t n_pts,
                     const double* pts, const int64_t* face, double* out, void* stream);
+
+/* L2 projection of initial data onto the discrete spaces: the state at
+ * t^{0,-} (the paper fixes no initial projection; this is the L2 projection
+ * onto the velocity space of Section 3 per element, and onto the dual space
+ * per dual element R_j in the canonical dual basis, where the dual mass is
+ * the identity).  which = 0: elements, which = 1: dual elements.  degree:
+ * the projection rule integrates polynomials of total degree <= degree
+ * exactly; it must lie in [dmin, dmin + 16] with dmin = 2p for elements and
+ * psi_deg + p for dual elements (psi_deg = 2p in 2D, p in 3D), so that the
+ * mass of the discrete space is exact; larger degrees integrate
+ * non-polynomial data more accurately.
+ * sdg_projection_points writes the number of rule points per cell to
+ * *n_per_cell and, when pts is not NULL, the points pts[cell][q][dim] and
+ * weights wts[cell][q] (host; wts may be NULL).  On a periodic mesh the
+ * points of a cell lie in its unwrapped frame (possibly outside the periodic
+ * box).  A free-surface dual element is T_{l,j} alone: the second half of its
+ * points repeats the first with zero weights.
+ * sdg_project_state takes the caller's data at those points, values
+ * [cell][q][comp] (host; comp = dim velocity components, or n_sigma Voigt
+ * stresses), and writes the projected state to out (device; velocity state
+ * [elem][c][k] or stress state [face][s][m]).  Synchronises `stream`.
+ * SDG_ENONFINITE for a non-finite value, SDG_EINVAL for a degree out of
+ * range. */
+int sdg_projection_points(const sdg_ctx* ctx, int which, int degree, int64_t* n_per_cell, double* pts,
+                          double* wts);
+int sdg_project_state(sdg_ctx* ctx, int which, int degree, const double* values, double* out, void* stream);
 
 /* Discrete adjoint of one implicit step (Lagrangian method applied to the
  * slab system of eqs. NM25/NM26, or NM25.cn/NM26.cn).  Write the step as
@@ -349,9 +408,11 @@ int sdg_adjoint_step(sdg_ctx* ctx, const double* v_old, const double* v_slab, do
                      double* sigma_bar, double* grad, const sdg_solve_opts* opts,
                      sdg_solve_info* info, void* stream);
 
-/* Transpose of sdg_sample_velocity: vbar[e(x_q)][c][k] += phi_k(x_q)
+/* Transpose of sdg_sample_velocity (the point evaluation of eq. NM1), for
+ * the adjoint of a receiver misfit: vbar[e(x_q)][c][k] += phi_k(x_q)
  * obs_bar[q][c] for the host points pts[n_pts*dim] (obs_bar device
- * [pt][c], vbar device [elem][c][k]).  Points are processed in order, so the
+ * [pt][c], vbar device [elem][c][k]).  SDG_EINVAL for a point outside the
+ * mesh.  Points are processed in order, so the
  * result is deterministic when several lie in one element. */
 int sdg_sample_velocity_adjoint(sdg_ctx* ctx, int n_rhs, int64_t n_pts, const double* pts,
                                 const double* obs_bar, double* vbar, void* stream);

@@ -106,57 +106,48 @@ class MisfitProblem:
         return J, np.array(obs), states, slabs
 
     # ------------------------------------------------------------- adjoint
-    def gradient(self, v0, s0):
-        """dJ/d(lambda_e, mu_e, rho_e) by the discrete adjoint."""
+    def adjoint_step(self, v_old, s_old, X, vbar, sbar, lu_T=None):
+        """One backward step of the recursion above: given the adjoint of the
+        new state ubar_{n+1} = (vbar, sbar) (raw stress basis), the old state
+        u_n and the slab DOFs X_n, return ubar_n = Bm^T Lam_n and the
+        gradient increment Lam_n^T (dBm/dtheta u_n - dA/dtheta X_n) on the
+        dual-element and element parameters: (vbar_n, sbar_n, g_lam_j,
+        g_mu_j, g_rho)."""
+        S = self.S
+        nv, ns = S.nv, S.ns
+        face_rows = np.arange(ns) // (S.ng * S.nsig * S.npsi)
+        elem_rows = np.arange(nv) // (S.ng * S.d * S.nphi)
+        # Xbar = Ex^T ubar
+        if S.scheme == "cn":
+            xv = vbar.reshape(S.ne, 1, S.d, S.nphi)
+            xs = sbar.reshape(S.nf, 1, S.nsig, S.npsi)
+        else:
+            xv = np.einsum("a,eck->eack", S.tb.e1, vbar)
+            xs = np.einsum("a,jsm->jasm", S.tb.e1, sbar)
+        Xbar = np.concatenate([xv.ravel(), xs.ravel()])
+        Lam = (lu_T or spla.splu(S.A.T.tocsc())).solve(Xbar)
+        Lv, Ls = Lam[:nv], Lam[nv:]
+        Xv = X[:nv]
+        # dA/dtheta X terms
+        g_lam_j = -np.bincount(face_rows, weights=Ls * (self.A_lam @ Xv), minlength=S.nf)
+        g_mu_j = -np.bincount(face_rows, weights=Ls * (self.A_mu @ Xv), minlength=S.nf)
+        g_rho = -np.bincount(elem_rows, weights=Lv * (self.A_rho @ Xv), minlength=S.ne)
+        # dBm/drho u_n: the old-state momentum term is linear in rho
+        b_unit = self._rho_unit_rhs(v_old, s_old)
+        g_rho += np.bincount(elem_rows, weights=Lv * b_unit, minlength=S.ne)
+        if S.scheme == "cn":
+            # CN: the explicit coupling halves also depend on lambda, mu
+            vo = v_old.reshape(-1)
+            g_lam_j += np.bincount(face_rows, weights=Ls * (-(self.A_lam @ vo)), minlength=S.nf)
+            g_mu_j += np.bincount(face_rows, weights=Ls * (-(self.A_mu @ vo)), minlength=S.nf)
+        vb, sb = self._bm_transpose(Lam)
+        return vb, sb, g_lam_j, g_mu_j, g_rho
+
+    def faces_to_elements(self, g_lam_j, g_mu_j):
+        """Face-parameter gradients passed to the elements with the volume
+        weights d lambda_j / d lambda_e = |T_{e,j}| / |R_j|."""
         S = self.S
         B = S.B
-        J, obs, states, slabs = self.forward(v0, s0)
-        N = len(slabs)
-        nv, ns = S.nv, S.ns
-        lu_T = spla.splu(S.A.T.tocsc())
-        g_lam_j = np.zeros(S.nf)
-        g_mu_j = np.zeros(S.nf)
-        g_rho = np.zeros(S.ne)
-        # ubar as arrays shaped like the state
-        vbar = np.zeros((S.ne, S.d, S.nphi))
-        sbar = np.zeros((S.nf, S.nsig, S.npsi))
-        face_rows = (np.arange(ns) // (S.ng * S.nsig * S.npsi))
-        elem_rows = (np.arange(nv) // (S.ng * S.d * S.nphi))
-        for n in range(N - 1, -1, -1):
-            # misfit at t^{n+1,-} acts on state n+1
-            resid = obs[n] - self.data[n]
-            for r, (e, phi) in enumerate(zip(self.rec_elem, self.rec_phi)):
-                vbar[e] += 2.0 * np.outer(resid[r], phi)
-            # Xbar = Ex^T ubar
-            if S.scheme == "cn":
-                xv = vbar.reshape(S.ne, 1, S.d, S.nphi)
-                xs = sbar.reshape(S.nf, 1, S.nsig, S.npsi)
-            else:
-                xv = np.einsum("a,eck->eack", S.tb.e1, vbar)
-                xs = np.einsum("a,jsm->jasm", S.tb.e1, sbar)
-            Xbar = np.concatenate([xv.ravel(), xs.ravel()])
-            Lam = lu_T.solve(Xbar)
-            Lv, Ls = Lam[:nv], Lam[nv:]
-            X = slabs[n]
-            Xv = X[:nv]
-            v_old, s_old = states[n]
-            # dA/dtheta X terms
-            g_lam_j -= np.bincount(face_rows, weights=Ls * (self.A_lam @ Xv), minlength=S.nf)
-            g_mu_j -= np.bincount(face_rows, weights=Ls * (self.A_mu @ Xv), minlength=S.nf)
-            g_rho -= np.bincount(elem_rows, weights=Lv * (self.A_rho @ Xv), minlength=S.ne)
-            # dBm/drho u_n: the old-state momentum term is linear in rho
-            b_unit = self._rho_unit_rhs(v_old, s_old)
-            g_rho += np.bincount(elem_rows, weights=Lv * b_unit, minlength=S.ne)
-            if S.scheme == "cn":
-                # CN: the explicit coupling halves also depend on lambda, mu
-                s_vec = s_old.reshape(-1)
-                vo = v_old.reshape(-1)
-                g_lam_j += np.bincount(face_rows, weights=Ls * (-(self.A_lam @ vo)), minlength=S.nf)
-                g_mu_j += np.bincount(face_rows, weights=Ls * (-(self.A_mu @ vo)), minlength=S.nf)
-            # ubar_n = Bm^T Lam
-            ub = self._bm_transpose(Lam)
-            vbar, sbar = ub
-        # face -> element with volume weights
         g_lam = np.zeros(S.ne)
         g_mu = np.zeros(S.ne)
         for j, F in enumerate(B.topo.faces):
@@ -170,6 +161,35 @@ class MisfitProblem:
             else:
                 g_lam[F.left] += g_lam_j[j]
                 g_mu[F.left] += g_mu_j[j]
+        return g_lam, g_mu
+
+    def gradient(self, v0, s0, increments=None):
+        """dJ/d(lambda_e, mu_e, rho_e) by the discrete adjoint.  With a list
+        for ``increments``, each step's element increments (g_lam, g_mu,
+        g_rho) are appended to it."""
+        S = self.S
+        J, obs, states, slabs = self.forward(v0, s0)
+        N = len(slabs)
+        lu_T = spla.splu(S.A.T.tocsc())
+        g_lam_j = np.zeros(S.nf)
+        g_mu_j = np.zeros(S.nf)
+        g_rho = np.zeros(S.ne)
+        # ubar as arrays shaped like the state
+        vbar = np.zeros((S.ne, S.d, S.nphi))
+        sbar = np.zeros((S.nf, S.nsig, S.npsi))
+        for n in range(N - 1, -1, -1):
+            # misfit at t^{n+1,-} acts on state n+1
+            resid = obs[n] - self.data[n]
+            for r, (e, phi) in enumerate(zip(self.rec_elem, self.rec_phi)):
+                vbar[e] += 2.0 * np.outer(resid[r], phi)
+            v_old, s_old = states[n]
+            vbar, sbar, gl, gm, gr = self.adjoint_step(v_old, s_old, slabs[n], vbar, sbar, lu_T)
+            if increments is not None:
+                increments.append((*self.faces_to_elements(gl, gm), gr))
+            g_lam_j += gl
+            g_mu_j += gm
+            g_rho += gr
+        g_lam, g_mu = self.faces_to_elements(g_lam_j, g_mu_j)
         return J, g_lam, g_mu, g_rho
 
     def _rho_unit_rhs(self, v_old, s_old):

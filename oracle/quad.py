@@ -9,6 +9,8 @@ Section 3.
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 from scipy.special import roots_jacobi
 
@@ -29,9 +31,18 @@ def n_points(degree: int) -> int:
     return max(1, (degree + 2) // 2)
 
 
+@functools.lru_cache(maxsize=None)
 def reference_rule(dim: int, degree: int):
     """Points (npts, dim) and weights on the reference simplex
-    {x_i >= 0, sum x_i <= 1}; exact for total degree <= ``degree``."""
+    {x_i >= 0, sum x_i <= 1}; exact for total degree <= ``degree``.
+    Built once per (dim, degree); the returned arrays are read-only."""
+    pts, w = _reference_rule(dim, degree)
+    pts.setflags(write=False)
+    w.setflags(write=False)
+    return pts, w
+
+
+def _reference_rule(dim: int, degree: int):
     n = n_points(degree)
     if dim == 1:
         x, w = gauss_legendre_01(n)

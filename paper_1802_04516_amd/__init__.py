@@ -39,7 +39,8 @@ EXPORTED = ("sdg_last_error", "sdg_create", "sdg_destroy", "sdg_set_mesh", "sdg_
             "sdg_set_material", "sdg_assemble", "sdg_query", "sdg_set_operator_variant", "sdg_set_batched_variant", "sdg_face_table",
             "sdg_apply_velocity_operator", "sdg_apply_adjoint", "sdg_set_sources", "sdg_solve_step",
             "sdg_energy", "sdg_sample_velocity", "sdg_eval_stress", "sdg_adjoint_step",
-            "sdg_sample_velocity_adjoint", "sdg_set_mesh_batch", "sdg_set_mesh_sources")
+            "sdg_sample_velocity_adjoint", "sdg_set_mesh_batch", "sdg_set_mesh_sources",
+            "sdg_projection_points", "sdg_project_state")
 
 
 class SdgError(RuntimeError):
@@ -113,6 +114,8 @@ def lib():
         "sdg_sample_velocity_adjoint": ([_P, i, ctypes.c_int64, _DP, _P, _P, _P], i),
         "sdg_set_mesh_batch": ([_P, i, i, _I64P, _DP, _I64P, _I64P], i),
         "sdg_set_mesh_sources": ([_P, ctypes.c_int64, _DP, _DP, ctypes.POINTER(ctypes.c_int32)], i),
+        "sdg_projection_points": ([_P, i, i, _I64P, _DP, _DP], i),
+        "sdg_project_state": ([_P, i, i, _DP, _P, _P], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -309,6 +312,30 @@ def sdg_eval_stress(h, sigma_state, pts, face, out, n_rhs=1, stream=None):
                                  _stream(stream)))
 
 
+def projection_min_degree(dim, p, which):
+    """Lowest projection rule degree accepted for elements (0) or dual
+    elements (1)."""
+    return 2 * p if which == 0 else (2 * p if dim == 2 else p) + p
+
+
+def sdg_projection_points(h, which, degree, n_cells, dim):
+    """Points (n_cells, nq, dim) and weights (n_cells, nq) of the projection
+    rule of elements (which = 0) or dual elements (which = 1)."""
+    nq = ctypes.c_int64(0)
+    _check(lib().sdg_projection_points(h, which, degree, ctypes.byref(nq), None, None))
+    pts = np.empty((n_cells, nq.value, dim))
+    wts = np.empty((n_cells, nq.value))
+    _check(lib().sdg_projection_points(h, which, degree, ctypes.byref(nq), _hp(pts, ctypes.c_double),
+                                       _hp(wts, ctypes.c_double)))
+    return pts, wts
+
+
+def sdg_project_state(h, which, degree, values, out, stream=None):
+    values = _host(values, np.float64)
+    _check(lib().sdg_project_state(h, which, degree, _hp(values, ctypes.c_double), _dev(out, name="out"),
+                                   _stream(stream)))
+
+
 # ---------------------------------------------------------------- convenience wrapper
 
 class Context:
@@ -411,6 +438,30 @@ class Context:
         _dev(sigma_bar, self._n("n_stress_state"), "sigma_bar")
         _dev(grad, 3 * self._n("n_elem"), "grad")
         return sdg_adjoint_step(self.h, v_old, v_slab, vbar, sigma_bar, grad, opts, stream)
+
+    def projection_points(self, which, extra_degree=0):
+        """Rule points and weights of the L2 projection of initial data on
+        elements (which = 0) or dual elements (which = 1), with a rule exact
+        to the lowest accepted degree plus extra_degree."""
+        n = self._n("n_elem") if which == 0 else self._n("n_face")
+        deg = projection_min_degree(self._n("dim"), self._n("p"), which) + extra_degree
+        return sdg_projection_points(self.h, which, deg, n, self._n("dim"))
+
+    def project_state(self, velocity_fn, stress_fn, extra_degree=0, stream=None):
+        """Projected initial state (v, sigma) as device tensors from point
+        functions velocity_fn(x) -> (n, dim) and stress_fn(x) -> (n, n_sigma)
+        (Voigt order), evaluated at the library's rule points."""
+        import torch
+        out = []
+        for which, fn, key in ((0, velocity_fn, "n_vel_state"), (1, stress_fn, "n_stress_state")):
+            pts, _ = self.projection_points(which, extra_degree)
+            vals = np.asarray(fn(pts.reshape(-1, pts.shape[-1])), np.float64)
+            del pts
+            t = torch.empty(self._n(key), dtype=torch.float64, device=f"cuda:{self.device}")
+            deg = projection_min_degree(self._n("dim"), self._n("p"), which) + extra_degree
+            sdg_project_state(self.h, which, deg, vals, t, stream)
+            out.append(t)
+        return out[0], out[1]
 
     def sample_adjoint(self, pts, obs_bar, vbar, stream=None):
         pts = np.asarray(pts, np.float64)

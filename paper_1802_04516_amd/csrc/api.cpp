@@ -338,6 +338,20 @@ void step_backsub(Ctx& c, double* v_state, double* sigma_state, double* v_slab, 
 
 // Partition of the independent systems of a batched solve with ncols columns,
 // or of the meshes of a mesh batch (rebuilt when the column count changes).
+// Sources are located on one mesh with one velocity basis; a new mesh or
+// degree makes their element indices and basis values meaningless.
+void clear_sources(Ctx& c) {
+  c.n_src = 0;
+  c.p_src = 0;
+  c.src_elem.clear();
+  c.src_phi.clear();
+  c.src_dir.clear();
+  c.d_src_elem.free();
+  c.d_src_phi.free();
+  c.d_src_dir.free();
+  c.graphs.clear();
+}
+
 MultiSys& systems(Ctx& c, int ncols) {
   const int key = c.n_mesh > 1 ? -1 : ncols;
   if (c.msys_key != key) {
@@ -405,6 +419,7 @@ int sdg_set_mesh(sdg_ctx* ctx, int dim, int64_t n_vert, const double* xyz, int64
       c.period.clear();
     }
     for (double x : c.xyz) require(std::isfinite(x), SDG_EINVAL, "non-finite vertex coordinate");
+    clear_sources(c);
     c.have_mesh = true;
     c.assembled = false;
   });
@@ -442,6 +457,7 @@ int sdg_set_mesh_batch(sdg_ctx* ctx, int dim, int n_mesh, const int64_t* vert_of
     c.n_mesh = n_mesh;
     c.mesh_vert_off.assign(vert_off, vert_off + n_mesh + 1);
     c.mesh_elem_off.assign(elem_off, elem_off + n_mesh + 1);
+    clear_sources(c);
     c.have_mesh = true;
     c.assembled = false;
   });
@@ -463,6 +479,7 @@ int sdg_set_discretization(sdg_ctx* ctx, int p, int p_gamma, int scheme, double 
     c.pg = p_gamma;
     c.scheme = scheme;
     c.dt = dt;
+    if (p != c.p_src) clear_sources(c);
     c.have_disc = true;
     c.assembled = false;
   });
@@ -795,6 +812,7 @@ static int set_sources_impl(sdg_ctx* ctx, int64_t n_src, const double* pos, cons
     SDG_HIP(hipSetDevice(c.device));
     c.graphs.clear();
     c.n_src = n_src;
+    c.p_src = c.p;
     c.src_elem = el;
     c.src_phi = phi;
     c.src_dir = dr;
@@ -1313,6 +1331,47 @@ int sdg_eval_stress(sdg_ctx* ctx, const double* sigma_state, int n_rhs, int64_t 
     SDG_HIP(hipMemcpy(df.p, face, n_pts * sizeof(int64_t), hipMemcpyHostToDevice));
     SDG_HIP(hipMemcpy(dp.p, psi.data(), psi.size() * sizeof(double), hipMemcpyHostToDevice));
     launch_eval_stress(n_pts, hs.npsi, hs.nsig, df.p, dp.p, sigma_state, out, s);
+    SDG_HIP(hipStreamSynchronize(s));
+  });
+}
+
+static void check_projection(const Ctx& c, int which, int degree) {
+  require(c.assembled, SDG_ESTATE, "assemble first");
+  require(which == 0 || which == 1, SDG_EINVAL, "which must be 0 (elements) or 1 (dual elements)");
+  const int lo = projection_min_degree(c.hs, which);
+  require(degree >= lo && degree <= lo + 16, SDG_EINVAL,
+          "projection degree must be in [" + std::to_string(lo) + ", " + std::to_string(lo + 16) + "]");
+}
+
+int sdg_projection_points(const sdg_ctx* ctx, int which, int degree, int64_t* n_per_cell, double* pts,
+                          double* wts) {
+  return guard([&] {
+    require(ctx != nullptr, SDG_EINVAL, "null context");
+    const Ctx& c = *reinterpret_cast<const Ctx*>(ctx);
+    check_projection(c, which, degree);
+    const HostSetup& hs = c.hs;
+    const int nq = projection_rule_size(hs, which, degree);
+    if (n_per_cell) *n_per_cell = nq;
+    if (pts) projection_points(hs, c.elem.data(), which, degree, pts, wts);
+    else require(wts == nullptr, SDG_EINVAL, "weights are written together with the points");
+  });
+}
+
+int sdg_project_state(sdg_ctx* ctx, int which, int degree, const double* values, double* out, void* stream) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    check_projection(c, which, degree);
+    require(values && out, SDG_EINVAL, "null argument");
+    const HostSetup& hs = c.hs;
+    const int64_t n = which == 0 ? c.n_state : c.n_sig_state;
+    const int64_t nval =
+        (which == 0 ? hs.n_elem * hs.dim : hs.n_face * hs.nsig) * projection_rule_size(hs, which, degree);
+    for (int64_t i = 0; i < nval; ++i) require(std::isfinite(values[i]), SDG_ENONFINITE, "non-finite value");
+    std::vector<double> host(n);
+    project_values(hs, c.elem.data(), which, degree, values, host.data());
+    SDG_HIP(hipSetDevice(c.device));
+    hipStream_t s = (hipStream_t)stream;
+    SDG_HIP(hipMemcpyAsync(out, host.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
     SDG_HIP(hipStreamSynchronize(s));
   });
 }

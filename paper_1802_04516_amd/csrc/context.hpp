@@ -159,8 +159,9 @@ struct Ctx {
   double poll_seq = 0.0;
   DevBuf<double> d_tmp_state, d_tmp_sig; // state-sized scratch (energy, back-substitution)
 
-  // sources
+  // sources (located for degree p_src on the current mesh)
   int64_t n_src = 0;
+  int p_src = 0;
   std::vector<int64_t> src_elem;
   std::vector<double> src_phi, src_dir;
   DevBuf<double> d_src_phi, d_src_dir, d_src_amp;

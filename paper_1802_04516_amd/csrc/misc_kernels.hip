@@ -267,6 +267,11 @@ void launch_end_of_slab(int64_t n_elem, int ng, int nvs, const double* w, const 
 void launch_add_sources(Ctx& c, double* b, const double* amp_dev, hipStream_t s, int ncols) {
   if (c.n_src == 0) return;
   const HostSetup& hs = c.hs;
+  require(c.p_src == c.p && (int64_t)c.src_elem.size() == c.n_src &&
+              c.src_phi.size() == (size_t)c.n_src * hs.nphi,
+          SDG_ESTATE, "sources were located for another mesh or degree; set them again");
+  for (int64_t e : c.src_elem)
+    require(e >= 0 && e < hs.n_elem, SDG_ESTATE, "source element outside the mesh; set the sources again");
   const int per = hs.ng * hs.dim * hs.nphi;
   if (ncols > 1) {
     k_sources_cols<<<dim3((per + kT - 1) / kT, ncols), kT, 0, s>>>(c.n_src, hs.ng, hs.dim, hs.nphi, hs.dt, c.d_tw.p,

@@ -88,6 +88,19 @@ int64_t locate_point(const HostSetup& hs, const double* x, int64_t e_begin = 0, 
 void eval_dual_canonical(const HostSetup& hs, const int64_t* elem, int64_t j, int64_t n,
                          const double* x, double* out);
 
+// L2 projection of initial data (the state at t^{0,-}) onto the velocity
+// space (which = 0, per element) or the dual space (which = 1, per face, in
+// the canonical dual basis) with a rule exact to total degree `degree`
+// (>= projection_min_degree): the points of the rule per cell, their
+// weights, and the projection of the caller's values at those points
+// (values [cell][q][comp], comp = dim or n_sigma; out [cell][comp][basis]).
+int projection_min_degree(const HostSetup& hs, int which);
+int projection_rule_size(const HostSetup& hs, int which, int degree);
+void projection_points(const HostSetup& hs, const int64_t* elem, int which, int degree, double* pts,
+                       double* wts);
+void project_values(const HostSetup& hs, const int64_t* elem, int which, int degree, const double* values,
+                    double* out);
+
 // ---------------------------------------------------------------- kernel interface
 
 // Small coefficient matrices used by the operator kernels (row-major, N_gamma <= 4).

@@ -801,6 +801,105 @@ void eval_dual_canonical(const HostSetup& hs, const int64_t* elem, int64_t j, in
   for (int64_t q = 0; q < n; ++q) db.canonical(x + q * hs.dim, out + q * hs.npsi);
 }
 
+// ---------------------------------------------------------------- projection of data
+
+// Lowest rule degree of the L2 projection of initial data (the state at
+// t^{0,-}) that integrates the mass of the discrete space exactly: velocity
+// functions have degree p, dual functions degree psi_deg (2p for the 2D
+// tensor products), and the projected data is at least of degree p.
+int projection_min_degree(const HostSetup& hs, int which) {
+  const int psi_deg = hs.dim == 2 ? 2 * hs.p : hs.p;
+  return which == 0 ? 2 * hs.p : psi_deg + hs.p;
+}
+
+int projection_rule_size(const HostSetup& hs, int which, int degree) {
+  std::vector<double> Vref((hs.dim + 1) * hs.dim, 0.0);
+  for (int a = 0; a < hs.dim; ++a) Vref[(a + 1) * hs.dim + a] = 1.0;
+  const int nq = simplex_rule(Vref.data(), hs.dim, hs.dim, degree).n();
+  return which == 0 ? nq : 2 * nq;
+}
+
+void projection_points(const HostSetup& hs, const int64_t* elem, int which, int degree, double* pts,
+                       double* wts) {
+  const int d = hs.dim, nv = d + 1;
+  const int nq = projection_rule_size(hs, which, degree);
+  if (which == 0) {
+    parallel_for(hs.n_elem, [&](int64_t e) {
+      Rule r = simplex_rule(&hs.elem_xyz[e * nv * d], d, d, degree);
+      for (int q = 0; q < nq; ++q) {
+        for (int c = 0; c < d; ++c) pts[(e * nq + q) * d + c] = r.x[q * d + c];
+        if (wts) wts[e * nq + q] = r.w[q];
+      }
+    });
+    return;
+  }
+  const int half = nq / 2;
+  parallel_for(hs.n_face, [&](int64_t j) {
+    FaceGeom fg;
+    face_geometry(hs, elem, j, fg);
+    const bool interior = hs.faces[j].right >= 0;
+    for (int s = 0; s < 2; ++s) {
+      // a free-surface dual element is T_{l,j} alone: its second half of
+      // points repeats the first with zero weights
+      Rule r = simplex_rule(fg.Tsub[interior ? s : 0], d, d, degree);
+      for (int q = 0; q < half; ++q) {
+        const int64_t o = j * nq + s * half + q;
+        for (int c = 0; c < d; ++c) pts[o * d + c] = r.x[q * d + c];
+        if (wts) wts[o] = (interior || s == 0) ? r.w[q] : 0.0;
+      }
+    }
+  });
+}
+
+void project_values(const HostSetup& hs, const int64_t* elem, int which, int degree, const double* values,
+                    double* out) {
+  const int d = hs.dim, nv = d + 1, nphi = hs.nphi, npsi = hs.npsi, nsig = hs.nsig;
+  const int nq = projection_rule_size(hs, which, degree);
+  if (which == 0) {
+    // v_e = Mbar_e^-1 int_{T_e} phi f = Mref^-1 sum_q w_q phi(xi_q) f(x_q) / |J_e|, computed
+    // on the reference element with the same points the caller evaluated f at
+    std::vector<double> Vref(nv * d, 0.0);
+    for (int a = 0; a < d; ++a) Vref[(a + 1) * d + a] = 1.0;
+    Rule r = simplex_rule(Vref.data(), d, d, degree);
+    VelBasis vb(d, hs.p);
+    std::vector<double> Phi((size_t)nq * nphi);
+    for (int q = 0; q < nq; ++q) vb.eval(&r.x[q * d], &Phi[(size_t)q * nphi], nullptr);
+    parallel_for(hs.n_elem, [&](int64_t e) {
+      std::vector<double> B((size_t)nphi * d, 0.0);  // [k][c]
+      for (int q = 0; q < nq; ++q) {
+        const double* f = values + (e * nq + q) * d;
+        for (int k = 0; k < nphi; ++k)
+          for (int c = 0; c < d; ++c) B[k * d + c] += r.w[q] * Phi[(size_t)q * nphi + k] * f[c];
+      }
+      solve_dense(hs.Mref, B, nphi, d);
+      for (int c = 0; c < d; ++c)
+        for (int k = 0; k < nphi; ++k) out[(e * d + c) * nphi + k] = B[k * d + c];
+    });
+    return;
+  }
+  // sigma_j[s][m] = int_{R_j} psi_m f_s: the canonical dual basis is orthonormal
+  std::vector<double> pts((size_t)hs.n_face * nq * d), wts((size_t)hs.n_face * nq);
+  projection_points(hs, elem, 1, degree, pts.data(), wts.data());
+  parallel_for(hs.n_face, [&](int64_t j) {
+    FaceGeom fg;
+    face_geometry(hs, elem, j, fg);
+    DualBasis db(d, hs.p);
+    double vol[2];
+    build_dual(hs, j, fg, db, vol);
+    std::vector<double> psi(npsi);
+    double* o = out + j * nsig * npsi;
+    for (int a = 0; a < nsig * npsi; ++a) o[a] = 0.0;
+    for (int q = 0; q < nq; ++q) {
+      const double w = wts[j * nq + q];
+      if (w == 0.0) continue;
+      db.canonical(&pts[(j * nq + q) * d], psi.data());
+      const double* f = values + (j * nq + q) * nsig;
+      for (int sv = 0; sv < nsig; ++sv)
+        for (int m = 0; m < npsi; ++m) o[sv * npsi + m] += w * psi[m] * f[sv];
+    }
+  });
+}
+
 // Element diagonal blocks of the velocity operator (eq. pre1),
 //   D_i = Tm (x) w_i Mref + Cg (x) K_ii,  K_ii = sum_f Dt_{i,f} E_j Dt_{i,f}^T,
 // inverted on the host; returned in FP32, column-major per element.

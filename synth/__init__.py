@@ -87,13 +87,15 @@ class Mesh:
 
 def split_square(n: int, m: int | None = None, *, jitter: float = 0.0,
                  seed: int | None = None, periodic: bool = False,
-                 lo=(0.0, 0.0), hi=(1.0, 1.0)) -> Mesh:
-    """n x m squares on [lo, hi], each split along the '/' diagonal.
+                 lo=(0.0, 0.0), hi=(1.0, 1.0), diagonal: str = "/") -> Mesh:
+    """n x m squares on [lo, hi], each split along the '/' diagonal (or the
+    '\\' one with ``diagonal="\\"``).
 
     Vertices are numbered row-major with x fastest.  Square (i, j) with
     corners v00=(i,j), v10=(i+1,j), v11=(i+1,j+1), v01=(i,j+1) gives the two
     counter-clockwise triangles (v00, v10, v11) and (v00, v11, v01), in that
-    order; squares are visited with i fastest.
+    order ('\\': (v00, v10, v01) and (v10, v11, v01)); squares are visited
+    with i fastest.
 
     ``jitter`` moves every free vertex by i.i.d. U(-jitter, jitter) times the
     local spacing in each coordinate (boundary vertices stay fixed on a
@@ -102,6 +104,8 @@ def split_square(n: int, m: int | None = None, *, jitter: float = 0.0,
     depend on which vertices are boundary ones.
     """
     m = n if m is None else m
+    if diagonal not in ("/", "\\"):
+        raise ValueError(f"diagonal must be '/' or '\\', not {diagonal!r}")
     lo = np.asarray(lo, float)
     hi = np.asarray(hi, float)
     hx, hy = (hi[0] - lo[0]) / n, (hi[1] - lo[1]) / m
@@ -128,13 +132,17 @@ def split_square(n: int, m: int | None = None, *, jitter: float = 0.0,
     for j in range(m):
         for i in range(n):
             v00, v10, v11, v01 = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)
-            elem[e] = (v00, v10, v11)
-            elem[e + 1] = (v00, v11, v01)
+            if diagonal == "/":
+                elem[e] = (v00, v10, v11)
+                elem[e + 1] = (v00, v11, v01)
+            else:
+                elem[e] = (v00, v10, v01)
+                elem[e + 1] = (v10, v11, v01)
             e += 2
     period = (hi - lo) if periodic else None
     return Mesh(xyz=xyz, elem=elem, period=period,
                 meta=dict(kind="split_square", n=n, m=m, jitter=jitter, seed=seed,
-                          periodic=periodic))
+                          periodic=periodic, diagonal=diagonal))
 
 
 def kuhn_cube(n: int, *, periodic: bool = True, lo=(0.0, 0.0, 0.0),

@@ -18,10 +18,10 @@ The implicit step is checked through a property that holds at any size: on
 the momentum rows of each sampled element and the stress rows of its faces
 the coupled slab system (eqs. NM25, NM26, or their Crank-Nicolson forms) is
 satisfied by the step's slab DOFs.  The stress back-substitution is exact
-per face (bar 1e-11 relative to the face's right-hand side); the momentum
-residual of an element is a part of the velocity system's residual, so it is
-bounded by rtol (1e-10) times ||b|| = ||A v|| (1 + rtol), with A v from the
-FP64 apply pinned above.
+per face (bar 1e-11 relative to the face's right-hand side).  Solved to
+1e-12, every sampled element's momentum residual is held to 1e-10 of its
+own right-hand side; at the benchmark's 1e-10 the sample's residual is held
+to the global bound rtol ||b||, the only bound the tolerance gives.
 """
 import numpy as np
 import pytest
@@ -121,20 +121,13 @@ def test_fullsize_every_face_kernel_variant(big):
         ctx.set_operator_variant(-1)
 
 
-@pytest.mark.parametrize("chosen", [False, True], ids=["fp64", "fp32_ir"])
-def test_fullsize_step_sampled_local_residual(big, chosen):
+def _step_local_residuals(big, opts, rtol, seed):
+    """One step at full size from a seeded random state; returns per sampled
+    element (momentum residual norm, momentum right-hand-side norm) of the
+    coupled slab system and the worst relative stress-row residual."""
     import torch
-    import paper_1802_04516_amd as sdg
-    from bench import GMRES_RESTART, IR_INNER_RTOL, IR_INNER_RTOL_3D
     sz, ctx = big["sizes"], big["ctx"]
-    rtol = 1e-10
-    if chosen:
-        opts = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F32, rtol, 5000, GMRES_RESTART, 5, 10,
-                             IR_INNER_RTOL if big["name"] == "c2" else IR_INNER_RTOL_3D, sdg.SDG_PRECOND_BLOCK)
-    else:
-        opts = sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F64, rtol, 5000, GMRES_RESTART, 5, 10, 1e-4,
-                             sdg.SDG_PRECOND_BLOCK)
-    rng = np.random.default_rng(8083)
+    rng = np.random.default_rng(seed)
     v_old = rng.standard_normal(sz["n_vel_state"])
     s_old = rng.standard_normal(sz["n_stress_state"])
     dev = dict(dtype=torch.float64, device="cuda")
@@ -145,22 +138,62 @@ def test_fullsize_step_sampled_local_residual(big, chosen):
     torch.cuda.synchronize()
     assert info["converged"] and info["rel_residual"] <= rtol
     vs, ss = v_slab.cpu().numpy(), s_slab.cpu().numpy()
-    b_norm = np.linalg.norm(_apply(big, vs, sdg.SDG_PREC_F64)) * (1 + rtol)
     codes = face_codes(big["w"]["mesh"].elem)
     assert len(codes) == sz["n_face"]
-    r2 = 0.0
-    worst_face = 0.0
+    rows, worst_face = {}, 0.0
     for i, P in big["patches"].items():
         rv, bv, faces = P.coupled_residual(vs, ss, v_old, s_old, codes)
-        r2 += np.linalg.norm(rv) ** 2
+        rows[i] = (np.linalg.norm(rv), np.linalg.norm(bv))
         for rs, bs in faces:
-            e = np.linalg.norm(rs) / np.linalg.norm(bs)
-            worst_face = max(worst_face, e)
-            assert e <= 1e-11, (i, e)
-    print(f"{big['name']} {'fp32+IR' if chosen else 'fp64'} step: {info['iterations']} iterations, "
-          f"{info['matvecs']} matvecs, rel res {info['rel_residual']:.2e}; sampled momentum residual "
-          f"{np.sqrt(r2) / b_norm:.2e} of ||b||, worst stress row {worst_face:.2e}")
-    assert np.sqrt(r2) <= rtol * b_norm
+            worst_face = max(worst_face, np.linalg.norm(rs) / np.linalg.norm(bs))
+    return info, rows, worst_face, vs
+
+
+def _opts_for(big, chosen, rtol):
+    import paper_1802_04516_amd as sdg
+    from bench import GMRES_RESTART, IR_INNER_RTOL, IR_INNER_RTOL_3D
+    if chosen:
+        return sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F32, rtol, 5000, GMRES_RESTART, 5, 20,
+                             IR_INNER_RTOL if big["name"] == "c2" else IR_INNER_RTOL_3D, sdg.SDG_PRECOND_BLOCK)
+    return sdg.SolveOpts(sdg.SDG_SOLVER_AUTO, sdg.SDG_PREC_F64, rtol, 5000, GMRES_RESTART, 5, 10, 1e-4,
+                         sdg.SDG_PRECOND_BLOCK)
+
+
+@pytest.mark.parametrize("chosen", [False, True], ids=["fp64", "fp32_ir"])
+def test_fullsize_step_sampled_local_residual(big, chosen):
+    """Each sampled element's momentum rows and each of its faces' stress
+    rows of the coupled slab system, against that element's (face's) own
+    right-hand side.  The Krylov tolerance bounds only the global residual,
+    so the step is solved to 1e-12 here and each element is held to 1e-10
+    of its own rows (room for a residual that is not spread evenly over the
+    mesh); the stress back-substitution is exact per face (1e-11)."""
+    rtol = 1e-12
+    info, rows, worst_face, _ = _step_local_residuals(big, _opts_for(big, chosen, rtol), rtol, 8083)
+    ratios = {i: r / b for i, (r, b) in rows.items()}
+    worst_i = max(ratios, key=ratios.get)
+    print(f"{big['name']} {'fp32+IR' if chosen else 'fp64'} step to {rtol:g}: {info['iterations']} iterations, "
+          f"rel res {info['rel_residual']:.2e}; worst element momentum residual {ratios[worst_i]:.2e} of its "
+          f"own right-hand side (element {worst_i}), worst stress rows {worst_face:.2e}")
+    assert worst_face <= 1e-11
+    for i, r in ratios.items():
+        assert r <= 1e-10, (i, r)
+
+
+def test_fullsize_step_at_benchmark_tolerance(big):
+    """The step at the benchmark's options (rtol 1e-10): the sampled
+    elements' momentum residual lies within the global bound
+    rtol ||b|| (||b|| = ||A v|| (1 + rtol), A v from the FP64 apply pinned
+    above); the per-element ratio to the element's own rows is printed."""
+    import paper_1802_04516_amd as sdg
+    rtol = 1e-10
+    info, rows, worst_face, vs = _step_local_residuals(big, _opts_for(big, False, rtol), rtol, 8084)
+    b_norm = np.linalg.norm(_apply(big, vs, sdg.SDG_PREC_F64)) * (1 + rtol)
+    r_s = np.sqrt(sum(r * r for r, _ in rows.values()))
+    b_s = np.sqrt(sum(b * b for _, b in rows.values()))
+    print(f"{big['name']} step at 1e-10: sampled momentum residual {r_s / b_norm:.2e} of the global ||b||, "
+          f"{r_s / b_s:.2e} of the sample's own rows; worst stress rows {worst_face:.2e}")
+    assert worst_face <= 1e-11
+    assert r_s <= rtol * b_norm
 
 
 def test_fullsize_crank_nicolson_conserves_energy(big):

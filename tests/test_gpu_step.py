@@ -306,3 +306,81 @@ def test_failure_injection_noconv_nonfinite_and_mesh():
         c2.setup(m.xyz, m.elem, None, 9, 0, sdg.SDG_SCHEME_CN, 0.01, *synth.homogeneous_material(m.n_elem))
     assert ei.value.code in (sdg.SDG_EINVAL, sdg.SDG_EUNSUPPORTED)
     c2.close()
+
+
+def test_sources_dropped_on_new_mesh_or_degree():
+    """Point sources are located on one mesh with one velocity basis: a new
+    mesh (or a new degree) drops them, so a step with amplitudes afterwards
+    carries no source at all (it equals the source-free step bit for bit),
+    and sources set again on the new mesh act as usual."""
+    import torch
+    import paper_1802_04516_amd as sdg
+    big = synth.split_square(6, jitter=0.2, seed=2001)
+    small = synth.split_square(3, jitter=0.2, seed=2001)
+    ctx = sdg.Context(0)
+    prec = sdg.SDG_PREC_F64 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND
+    ctx.setup(big.xyz, big.elem, None, 3, 1, sdg.SDG_SCHEME_STDG, 2.5e-3,
+              *synth.layered_material(big.centroids(), seed=2002), prec)
+    # a source in the last element of the larger mesh (index beyond the smaller mesh)
+    ctx.set_sources(big.centroids()[-1:], [[0.0, 1.0]])
+    amp = np.array([[1.0, 0.5]])
+    for mesh, p in ((small, 3), (small, 2)):
+        sz = ctx.setup(mesh.xyz, mesh.elem, None, p, 1, sdg.SDG_SCHEME_STDG, 2.5e-3,
+                       *synth.layered_material(mesh.centroids(), seed=2002), prec)
+        rng = np.random.default_rng(3)
+        v0 = _to_gpu(rng.standard_normal(sz["n_vel_state"]))
+        s0 = _to_gpu(rng.standard_normal(sz["n_stress_state"]))
+        v1, s1, v2, s2 = v0.clone(), s0.clone(), v0.clone(), s0.clone()
+        o = _opts(1e-12, solver=sdg.SDG_SOLVER_GMRES, precond=sdg.SDG_PRECOND_BLOCK)
+        ctx.step(v1, s1, amp, opts=o)
+        ctx.step(v2, s2, None, opts=o)
+        torch.cuda.synchronize()
+        assert torch.equal(v1, v2) and torch.equal(s1, s2)
+    # sources set on the current mesh act again
+    ctx.set_sources(small.centroids()[:1], [[0.0, 1.0]])
+    v3, s3 = v0.clone(), s0.clone()
+    ctx.step(v3, s3, amp, opts=o)
+    torch.cuda.synchronize()
+    assert not torch.equal(v3, v2)
+    ctx.close()
+
+
+class _PolyField:
+    """Random polynomial velocity and Voigt stress fields of total degree q."""
+
+    def __init__(self, dim, q, seed):
+        rng = np.random.default_rng(seed)
+        self.exps = [e for e in np.ndindex(*([q + 1] * dim)) if sum(e) <= q]
+        self.cv = rng.standard_normal((len(self.exps), dim))
+        self.cs = rng.standard_normal((len(self.exps), dim * (dim + 1) // 2))
+
+    def _mono(self, x):
+        x = np.atleast_2d(x)
+        return np.stack([np.prod(x ** np.array(e)[None, :], axis=1) for e in self.exps], axis=1)
+
+    def velocity(self, x, t=0.0):
+        return self._mono(x) @ self.cv
+
+    def stress_voigt(self, x, t=0.0):
+        return self._mono(x) @ self.cs
+
+
+@pytest.mark.parametrize("case", ["3d_cn_p2", "p2pg2_free", "c2_8x8"])
+def test_projection_of_initial_data_matches_oracle(case):
+    """sdg_project_state (the L2 projection of the initial state onto the
+    velocity space and, in the canonical basis, onto the dual space) against
+    the oracle's projection of the same data: polynomial fields of degree
+    p + 1, which lie outside the discrete spaces and which both rules
+    integrate exactly at one degree above the lowest accepted one."""
+    import torch
+    c = build(case)
+    B, ctx = c["B"], c["ctx"]
+    field = _PolyField(B.dim, c["p"] + 1, seed=12)
+    v_ref, s_raw = waves.project(B, field, 0.0)
+    s_ref = _canon(B, s_raw)
+    v, s = ctx.project_state(field.velocity, field.stress_voigt, extra_degree=1)
+    torch.cuda.synchronize()
+    ev, es = rel(v.cpu().numpy(), v_ref), rel(s.cpu().numpy(), s_ref)
+    print(f"{case}: projection v {ev:.2e} sigma {es:.2e}")
+    assert ev <= 1e-12 and es <= 1e-12
+    ctx.close()

@@ -119,3 +119,83 @@ def test_library_dual_basis_equals_oracle_gram_schmidt(harness, tmp_path, name):
     tb = TimeBasis(pg)
     for got_, ref_ in ((tau, tb.tau), (w, tb.w), (e0, tb.e0), (e1, tb.e1), (T, tb.T.ravel())):
         assert np.allclose(got_, ref_, rtol=0, atol=1e-13)
+
+
+@pytest.fixture(scope="module")
+def proj_harness(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None or not os.path.exists(os.path.join(HIP_INCLUDE, "hip", "hip_runtime.h")):
+        pytest.skip("needs g++ and the HIP headers")
+    exe = str(tmp_path_factory.mktemp("host") / "projection")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", f"-I{HIP_INCLUDE}", "-w",
+                    os.path.join(HERE, "host", "projection.cpp"), "-o", exe, "-lpthread"], check=True)
+    return exe
+
+
+class _PolyField:
+    """A random polynomial field of total degree q: velocity (dim components)
+    and Voigt stress (n_sigma components)."""
+
+    def __init__(self, dim, q, seed):
+        rng = np.random.default_rng(seed)
+        self.exps = [e for e in np.ndindex(*([q + 1] * dim)) if sum(e) <= q]
+        self.cv = rng.standard_normal((len(self.exps), dim))
+        self.cs = rng.standard_normal((len(self.exps), dim * (dim + 1) // 2))
+
+    def _mono(self, x):
+        x = np.atleast_2d(x)
+        return np.stack([np.prod(x ** np.array(e)[None, :], axis=1) for e in self.exps], axis=1)
+
+    def velocity(self, x, t=0.0):
+        return self._mono(x) @ self.cv
+
+    def stress_voigt(self, x, t=0.0):
+        return self._mono(x) @ self.cs
+
+
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_library_projection_of_initial_data_equals_oracle(proj_harness, tmp_path, name):
+    """The library's L2 projection of initial data (velocity per element,
+    stress per dual element in the canonical basis) equals the oracle's, for
+    polynomial data of degree p + 1 (outside the discrete spaces, integrated
+    exactly by both rules).  On a free-surface dual element only T_{l,j}
+    carries weight."""
+    from oracle import waves
+    mk, p, periodic, pg = MESHES[name]
+    mesh = mk()
+    elem = np.asarray(mesh.elem, dtype=np.int64)
+    xyz = np.asarray(mesh.xyz, dtype=np.float64)
+    d = elem.shape[1] - 1
+    lam, mu, rho = synth.lognormal_material(elem.shape[0], sigma=0.3, seed=31)
+    mfile = tmp_path / "mesh.bin"
+    with open(mfile, "wb") as f:
+        np.array([d, xyz.shape[0], elem.shape[0], p, int(periodic), pg], dtype=np.int64).tofile(f)
+        xyz.tofile(f)
+        elem.tofile(f)
+        for a in (lam, mu, rho):
+            np.asarray(a, dtype=np.float64).tofile(f)
+    topo = Topology(mesh.xyz, mesh.elem, mesh.period)
+    B = Blocks(topo, p, lam, mu, rho)
+    field = _PolyField(d, p + 1, seed=5)
+    v_ref, s_raw = waves.project(B, field, 0.0)
+    s_ref = np.stack([B.to_canonical(j, s_raw[j]) for j in range(topo.n_face)])
+    psi_deg = 2 * p if d == 2 else p
+    for which, ref, fn in ((0, v_ref, field.velocity), (1, s_ref, field.stress_voigt)):
+        pfile, vfile, ofile = tmp_path / f"p{which}.bin", tmp_path / f"v{which}.bin", tmp_path / f"o{which}.bin"
+        # exact for the data of degree p + 1 times a basis function: one above the lowest degree
+        deg = str((2 * p if which == 0 else psi_deg + p) + 1)
+        subprocess.run([proj_harness, str(mfile), "0", str(which), deg, str(pfile)], check=True)
+        raw = np.fromfile(pfile, dtype=np.float64)
+        nq = int(np.frombuffer(raw[:1].tobytes(), dtype=np.int64)[0])
+        ncell = topo.n_elem if which == 0 else topo.n_face
+        pts = raw[1:1 + ncell * nq * d].reshape(ncell, nq, d)
+        wts = raw[1 + ncell * nq * d:].reshape(ncell, nq)
+        # the weights integrate the cell volumes: |T_e|, or |R_j| = |T_{l,j}| + |T_{r,j}|
+        vol = np.array([topo.volume(e) for e in range(ncell)]) if which == 0 else B.vol_sub.sum(axis=1)
+        assert np.allclose(wts.sum(axis=1), vol, rtol=1e-13, atol=0)
+        np.ascontiguousarray(fn(pts.reshape(-1, d))).tofile(vfile)
+        subprocess.run([proj_harness, str(mfile), "1", str(which), deg, str(vfile), str(ofile)], check=True)
+        got = np.fromfile(ofile, dtype=np.float64).reshape(ref.shape)
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"{name} which={which}: {nq} points per cell, max rel difference {err:.2e}")
+        assert err <= 1e-11

@@ -81,14 +81,62 @@ def test_time_matrix_closed_forms(pg):
     assert np.all(np.linalg.eigvals(tb.T).real > 0)
 
 
-@pytest.mark.parametrize("dim,p", [(2, 2), (3, 2)])
-def test_canonical_dual_basis_orthonormal(dim, p):
-    mesh = synth.split_square(3, jitter=0.2, seed=3) if dim == 2 else synth.kuhn_cube(3)
+def _split_simplex(V):
+    """The 2^k simplices of one midpoint (red) refinement of the simplex with
+    vertex rows V: corner pieces plus the interior ones (k = 2: 4 triangles,
+    k = 3: 8 tetrahedra via the 0-5 diagonal of the inner octahedron)."""
+    V = np.asarray(V, float)
+    k = V.shape[0] - 1
+    mid = {(a, b): 0.5 * (V[a] + V[b]) for a in range(k + 1) for b in range(k + 1)}
+    P = lambda a, b: mid[(min(a, b), max(a, b))]
+    if k == 2:
+        return [np.array([V[0], P(0, 1), P(0, 2)]), np.array([V[1], P(0, 1), P(1, 2)]),
+                np.array([V[2], P(0, 2), P(1, 2)]), np.array([P(0, 1), P(1, 2), P(0, 2)])]
+    m01, m02, m03, m12, m13, m23 = P(0, 1), P(0, 2), P(0, 3), P(1, 2), P(1, 3), P(2, 3)
+    return [np.array([V[0], m01, m02, m03]), np.array([V[1], m01, m12, m13]),
+            np.array([V[2], m02, m12, m23]), np.array([V[3], m03, m13, m23]),
+            np.array([m01, m02, m03, m23]), np.array([m01, m02, m12, m23]),
+            np.array([m01, m03, m13, m23]), np.array([m01, m12, m13, m23])]
+
+
+@pytest.mark.parametrize("case", ["2d_free_jitter", "2d_periodic", "3d_free", "3d_periodic"])
+def test_canonical_dual_basis_is_gram_schmidt_of_raw_sequence(case):
+    """The canonical dual basis (raw monomials times the inverse transposed
+    Cholesky factor of the oracle's Gram matrix M_j) equals modified
+    Gram-Schmidt of the raw sequence, run on its own inner product: a
+    quadrature over a midpoint refinement of each sub-simplex T_{i,j} of the
+    dual element, with a rule of another degree.  A Gram matrix that missed a
+    sub-simplex, a transposed or non-inverted factor, or a wrong raw order
+    fails this."""
+    p = 2
+    mesh = {"2d_free_jitter": lambda: synth.split_square(3, jitter=0.2, seed=3),
+            "2d_periodic": lambda: synth.split_square(3, periodic=True, jitter=0.1, seed=4),
+            "3d_free": lambda: synth.kuhn_cube(2, periodic=False),
+            "3d_periodic": lambda: synth.kuhn_cube(3)}[case]()
     B = _blocks(mesh, p)
-    for j in range(min(B.topo.n_face, 40)):
-        Li = np.linalg.inv(B.L[j])
-        assert np.allclose(Li @ B.M[j] @ Li.T, np.eye(B.npsi), atol=1e-10)
-        assert B.npsi == ((p + 1) ** 2 if dim == 2 else math.comb(p + 3, 3))
+    psi_deg = 2 * p if B.dim == 2 else p
+    rng = np.random.default_rng(0)
+    faces = rng.choice(B.topo.n_face, size=min(B.topo.n_face, 12), replace=False)
+    for j in faces:
+        F = B.topo.faces[j]
+        pts, wts = [], []
+        for side in ([0] if F.right < 0 else [0, 1]):
+            for piece in _split_simplex(B.topo.sub_simplex(j, side)):
+                x, w = quad.simplex_rule(piece, 2 * psi_deg + 3)
+                pts.append(x)
+                wts.append(w)
+        x, w = np.vstack(pts), np.concatenate(wts)
+        raw = B.duals[j].eval(x)
+        Q = np.zeros_like(raw)
+        for m in range(B.npsi):
+            f = raw[:, m].copy()
+            for k in range(m):
+                f -= np.sum(w * f * Q[:, k]) * Q[:, k]
+            Q[:, m] = f / np.sqrt(np.sum(w * f * f))
+        canon = raw @ np.linalg.inv(B.L[j]).T
+        scale = np.abs(Q).max()
+        assert np.abs(canon - Q).max() <= 1e-9 * scale, (case, j, np.abs(canon - Q).max())
+        assert B.npsi == ((p + 1) ** 2 if B.dim == 2 else math.comb(p + 3, 3))
 
 
 # ------------------------------------------------------------------ blocks
@@ -364,3 +412,27 @@ def test_point_source_location_and_partition_of_unity():
     # the nodal basis sums to one, so the DOFs of component y add up to dt w_a S_a
     assert np.allclose(b[e, :, 1].sum(axis=1), 0.01 * S.tb.w * [2.0, 3.0], atol=1e-15)
     assert np.all(b[e, :, 0] == 0)
+
+
+@pytest.mark.parametrize("case", ["cn_2d", "stdg_2d", "cn_3d"])
+def test_schur_krylov_step_equals_coupled_lu_step(case):
+    """The oracle's Schur-complement Krylov step (eliminate the stress, CG or
+    GMRES on the velocity system, back-substitute) reaches the coupled
+    sparse-LU step: the solution of eqs. NM25/NM26 is unique (Section 4), so
+    the two agree to the Krylov tolerance."""
+    if case == "cn_2d":
+        mesh, p, pg, sch = synth.split_square(4, periodic=True), 2, 0, "cn"
+    elif case == "stdg_2d":
+        mesh, p, pg, sch = synth.split_square(4, jitter=0.2, seed=5), 2, 1, "stdg"
+    else:
+        mesh, p, pg, sch = synth.kuhn_cube(2, periodic=False), 2, 0, "cn"
+    B = _blocks(mesh, p, synth.lognormal_material(mesh.n_elem, seed=9))
+    slab = Slab(B, pg, 0.02, sch)
+    rng = np.random.default_rng(7)
+    v0 = rng.standard_normal((B.topo.n_elem, B.dim, B.nphi))
+    s0 = rng.standard_normal((B.topo.n_face, B.nsig, B.npsi))
+    _, _, v1, s1 = slab.step(v0, s0)
+    _, _, v2, s2, its = slab.step_schur(v0, s0, rtol=1e-13)
+    assert its > 0
+    assert np.linalg.norm(v2 - v1) <= 1e-10 * np.linalg.norm(v1)
+    assert np.linalg.norm(s2 - s1) <= 1e-10 * np.linalg.norm(s1)
