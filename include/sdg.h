@@ -277,6 +277,21 @@ int sdg_face_table(const sdg_ctx* ctx, int64_t* left, int32_t* left_face,
 int sdg_apply_velocity_operator(sdg_ctx* ctx, const double* v, double* y, int n_rhs,
                                 int precision, void* stream);
 
+/* Allocation-free form of sdg_apply_velocity_operator, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, layouts, result
+ * (bit for bit) and errors, with one more limit: the face-slot workspace,
+ * (dim+1) N_gamma dim N_phi FP64 values per element and column, lives in a
+ * file-scope device array of 256 MiB per GPU (resolved by sdg_create, held
+ * until the process ends) instead of the context's workspace; a larger
+ * n_elem * n_rhs gives SDG_EINVAL.  The call makes no allocation.  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (concurrent streams or threads, any context) race and give undefined
+ * results.  Every slot is written before it is read within a call, so
+ * nothing from an earlier call carries over. */
+int sdg_apply_velocity_operator_noalloc(sdg_ctx* ctx, const double* v, double* y, int n_rhs, int precision,
+                                        void* stream);
+
 /* y = A^T w: the transpose of the velocity operator of eq. (velocity.sys),
  * A^T = T^T (x) rho Mbar + dt^2 (W T^-T W) (x) K (K is symmetric, Section 5),
  * used by the discrete adjoint.  Same arguments, layouts and errors as

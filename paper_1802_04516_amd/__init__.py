@@ -40,7 +40,7 @@ EXPORTED = ("sdg_last_error", "sdg_create", "sdg_destroy", "sdg_set_mesh", "sdg_
             "sdg_apply_velocity_operator", "sdg_apply_adjoint", "sdg_set_sources", "sdg_solve_step",
             "sdg_energy", "sdg_sample_velocity", "sdg_eval_stress", "sdg_adjoint_step",
             "sdg_sample_velocity_adjoint", "sdg_set_mesh_batch", "sdg_set_mesh_sources",
-            "sdg_projection_points", "sdg_project_state")
+            "sdg_projection_points", "sdg_project_state", "sdg_apply_velocity_operator_noalloc")
 
 
 class SdgError(RuntimeError):
@@ -105,6 +105,7 @@ def lib():
         "sdg_face_table": ([_P, _I64P, _I32P, _I64P, _I32P], i),
         "sdg_apply_velocity_operator": ([_P, _P, _P, i, i, _P], i),
         "sdg_apply_adjoint": ([_P, _P, _P, i, i, _P], i),
+        "sdg_apply_velocity_operator_noalloc": ([_P, _P, _P, i, i, _P], i),
         "sdg_set_sources": ([_P, ctypes.c_int64, _DP, _DP], i),
         "sdg_solve_step": ([_P, _P, _P, _DP, i, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P, _P, _P], i),
         "sdg_energy": ([_P, _P, _P, i, _DP, _P], i),
@@ -243,6 +244,11 @@ def sdg_face_table(h, n_face):
 def sdg_apply_velocity_operator(h, v, y, n_rhs=1, precision=SDG_PREC_F64, stream=None):
     _check(lib().sdg_apply_velocity_operator(h, _dev(v, name="v"), _dev(y, name="y"), n_rhs, precision,
                                              _stream(stream)))
+
+
+def sdg_apply_velocity_operator_noalloc(h, v, y, n_rhs=1, precision=SDG_PREC_F64, stream=None):
+    _check(lib().sdg_apply_velocity_operator_noalloc(h, _dev(v, name="v"), _dev(y, name="y"), n_rhs, precision,
+                                                     _stream(stream)))
 
 
 def sdg_apply_adjoint(h, w, y, n_rhs=1, precision=SDG_PREC_F64, stream=None):

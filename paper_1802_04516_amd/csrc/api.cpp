@@ -104,11 +104,11 @@ void check_prec(Ctx& c, int prec) {
 
 }  // namespace
 
-void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s, int ncols) {
+void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s, int ncols, void* z) {
   OpArgs a = base_args(c, prec);
   a.variant = prec == SDG_PREC_F32 ? c.variant32 : c.variant64;
   a.v = v;
-  a.z = c.d_z.p;
+  a.z = z ? static_cast<double*>(z) : c.d_z.p;
   a.y = y;
   a.use_g = 1;
   a.c = transpose ? c.adj : c.op;
@@ -385,6 +385,9 @@ int sdg_create(sdg_ctx** out, int device) {
     SDG_HIP(hipGetDeviceCount(&n));
     require(device >= 0 && device < n, SDG_EDEVICE, "no such HIP device");
     SDG_HIP(hipSetDevice(device));
+    // resolve this device's copy of the allocation-free apply's scratch
+    // array now, once per device, with the device current
+    (void)noalloc_scratch(device);
     Ctx* c = new Ctx();
     c->device = device;
     *out = reinterpret_cast<sdg_ctx*>(c);
@@ -785,6 +788,26 @@ int sdg_apply_velocity_operator(sdg_ctx* ctx, const double* v, double* y, int n_
 
 int sdg_apply_adjoint(sdg_ctx* ctx, const double* w, double* y, int n_rhs, int precision, void* stream) {
   return apply_common(ctx, w, y, n_rhs, precision, stream, true);
+}
+
+int sdg_apply_velocity_operator_noalloc(sdg_ctx* ctx, const double* v, double* y, int n_rhs, int precision,
+                                        void* stream) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.assembled, SDG_ESTATE, "assemble first");
+    require(v && y, SDG_EINVAL, "null vector");
+    require(v != y, SDG_EINVAL, "v and y must not alias");
+    require(n_rhs >= 1 && n_rhs <= c.max_rhs, SDG_EINVAL, "n_rhs must be in [1, max_rhs of sdg_assemble]");
+    check_prec(c, precision);
+    // the face slots of every column; FP32 applies write FP32 slots, but the
+    // limit is stated for FP64 slots so that it does not depend on precision
+    const size_t need = (size_t)c.z_col * (size_t)n_rhs * sizeof(double);
+    require(need <= noalloc_scratch_bytes(), SDG_EINVAL,
+            "face-slot workspace of " + std::to_string(need) + " bytes exceeds the " +
+                std::to_string(noalloc_scratch_bytes()) + "-byte scratch array of the allocation-free apply");
+    SDG_HIP(hipSetDevice(c.device));
+    apply_op(c, v, y, precision, false, (hipStream_t)stream, n_rhs, noalloc_scratch(c.device));
+  });
 }
 
 static int set_sources_impl(sdg_ctx* ctx, int64_t n_src, const double* pos, const double* dir, const int32_t* mesh) {

@@ -202,7 +202,15 @@ struct Ctx {
 
 // operator application on slab vectors (FP64 in / out)
 // ncols > 1: ncols independent columns stored one after another (stride n_slab)
-void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s, int ncols = 1);
+// z: face-slot workspace of z_col values per column (default: the context's)
+void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s, int ncols = 1,
+              void* z = nullptr);
+
+// Face-slot workspace of the allocation-free apply: a file-scope device
+// array of noalloc_scratch_bytes() per GPU; noalloc_scratch(device) returns
+// this device's copy (resolved once per device, with the device current).
+size_t noalloc_scratch_bytes();
+void* noalloc_scratch(int device);
 
 // vector kernels
 void vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
