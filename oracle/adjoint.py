@@ -36,6 +36,8 @@ class MisfitProblem:
     def __init__(self, slab: Slab, receivers, sources=None, amps=None, data=None):
         self.S = slab
         B = slab.B
+        if B.Et_j is not None:
+            raise ValueError("the material gradients are taken for the isotropic parameters")
         self.rec = np.asarray(receivers, float)
         self.rec_elem = [locate(B.topo, x) for x in self.rec]
         self.rec_phi = [phys_basis(B.lb, B.maps[e], x[None, :])[0][0]

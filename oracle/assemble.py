@@ -44,6 +44,35 @@ def stiffness(dim, lam, mu):
             + mu * (np.einsum("pc,ql->pqcl", I, I) + np.einsum("pl,qc->pqcl", I, I)))
 
 
+def voigt_weights(dim):
+    """W: 1 on normal, 2 on shear Voigt components, so that the tensor
+    contraction sigma : eps equals s^T W e for the Voigt vectors (Section 2
+    lists each shear component once)."""
+    return np.array([1.0] * dim + [2.0] * (n_sigma(dim) - dim))
+
+
+def stiffness_from_voigt(dim, Et):
+    """E[p,q,c,l] (sigma_pq = sum_cl E[p,q,c,l] d_l v_c) of a general
+    material given by the matrix E~ of Section 2, s~ = E~ e~, where the strain
+    rate's Voigt entry for (c, l) is (d_l v_c + d_c v_l) / 2.  Each Voigt
+    column (c, l), c < l, contributes half to d_l v_c and half to d_c v_l;
+    a normal column (c, c) contributes fully to d_c v_c."""
+    vo = voigt_index(dim)
+    Et = np.asarray(Et, float)
+    E = np.zeros((dim, dim, dim, dim))
+    for p in range(dim):
+        for q in range(dim):
+            for c in range(dim):
+                for l in range(c, dim):
+                    e = Et[vo[p, q], vo[c, l]]
+                    if c == l:
+                        E[p, q, c, c] += e
+                    else:
+                        E[p, q, c, l] += 0.5 * e
+                        E[p, q, l, c] += 0.5 * e
+    return E
+
+
 def compliance_voigt(dim, lam, mu):
     """C with sigma : E^{-1} sigma = s^T C s for the Voigt vector s.
 
@@ -64,6 +93,13 @@ def compliance_voigt(dim, lam, mu):
     return Wt @ np.linalg.inv(Et)
 
 
+def compliance_from_voigt(dim, Et):
+    """C with sigma : E^{-1} sigma = s^T C s for a general E~ (Section 2):
+    the strain is e~ = E~^{-1} s~ and the contraction sigma : eps is
+    s~^T W e~, so C = W E~^{-1}."""
+    return np.diag(voigt_weights(dim)) @ np.linalg.inv(np.asarray(Et, float))
+
+
 class Blocks:
     """All blocks of one mesh / degree pair.
 
@@ -72,10 +108,15 @@ class Blocks:
     D[j][s]      (N_phi, d, N_psi)    int_G phi_k psi_m n_{i,j} - int_{T_ij} d_l phi_k psi_m   (MD_3)
     Qt[j][s]     (N_psi, d, N_phi)    int_{T_ij} psi d_l phi - int_G psi phi s_ij n_j          (qtilde)
     L[j]         Cholesky factor of M[j]: canonical coefficients = L^T raw coefficients
-    lam_j, mu_j  dual-element material
+    lam_j, mu_j  dual-element material (isotropic)
+    Et_j         dual-element Voigt stiffness E~_j (anisotropic), else None
+
+    ``stiffness`` (n_elem, n_sigma, n_sigma), when given, is a general
+    material per element in the Voigt form of Section 2; lam and mu are then
+    ignored.  E~_j is the volume-weighted mean over R_j, like lambda_j.
     """
 
-    def __init__(self, topo: Topology, p: int, lam, mu, rho):
+    def __init__(self, topo: Topology, p: int, lam, mu, rho, stiffness=None):
         self.topo = topo
         d = self.dim = topo.dim
         self.p = p
@@ -84,6 +125,8 @@ class Blocks:
         self.npsi = n_psi(d, p)
         self.nsig = n_sigma(d)
         self.rho = np.asarray(rho, float)
+        if stiffness is not None:   # isotropic parameters unused: NaN makes any use loud
+            lam = mu = np.full(topo.n_elem, np.nan)
         lam = np.asarray(lam, float)
         mu = np.asarray(mu, float)
         psi_deg = 2 * p if d == 2 else p
@@ -143,6 +186,29 @@ class Blocks:
             else:
                 self.lam_j[j] = lam[F.left]
                 self.mu_j[j] = mu[F.left]
+        self.Et_j = None
+        if stiffness is not None:
+            Et = np.asarray(stiffness, float)
+            self.Et_j = np.zeros((topo.n_face, self.nsig, self.nsig))
+            for j, F in enumerate(topo.faces):
+                vl = self.vol_sub[j, 0]
+                if F.right >= 0:
+                    vr = self.vol_sub[j, 1]
+                    self.Et_j[j] = (vl * Et[F.left] + vr * Et[F.right]) / (vl + vr)
+                else:
+                    self.Et_j[j] = Et[F.left]
+
+    def face_stiffness(self, j):
+        """E[p,q,c,l] of dual element j."""
+        if self.Et_j is not None:
+            return stiffness_from_voigt(self.dim, self.Et_j[j])
+        return stiffness(self.dim, self.lam_j[j], self.mu_j[j])
+
+    def face_compliance(self, j):
+        """Voigt compliance form C of dual element j (sigma : E^-1 sigma = s^T C s)."""
+        if self.Et_j is not None:
+            return compliance_from_voigt(self.dim, self.Et_j[j])
+        return compliance_voigt(self.dim, self.lam_j[j], self.mu_j[j])
 
     def _dual_basis(self, F):
         if self.dim == 2:
@@ -156,7 +222,22 @@ class Blocks:
             pts.append(F.br[None, :])
         c = np.vstack(pts).mean(axis=0)
         h = np.max(np.linalg.norm(F.X - c[None, :], axis=1))
-        return DualRawBasis(3, self.p, c, scale=h)
+        mono = DualRawBasis(3, self.p, c, scale=h)
+        # Gram-Schmidt of the monomial sequence over the dual element, taken
+        # as a Householder QR of its weighted values at an exact rule
+        # (A = Q R, basis = monomials R^-1): the monomial Gram matrices of
+        # the tetrahedral dual elements reach cond 1e8 at p = 4, where a
+        # Cholesky factor would lose half the digits
+        xs, ws = [], []
+        for Ts in ([np.vstack([F.X, F.bl[None, :]])] +
+                   ([np.vstack([F.X, F.br[None, :]])] if F.br is not None else [])):
+            x, w = quad.simplex_rule(Ts, 2 * self.p)
+            xs.append(x)
+            ws.append(w)
+        A = np.sqrt(np.concatenate(ws))[:, None] * mono.eval(np.vstack(xs))
+        R = np.linalg.qr(A, mode="r")
+        R = R * np.sign(np.diag(R))[:, None]
+        return DualRawBasis(3, self.p, c, scale=h, mix=np.linalg.inv(R))
 
     # ------------------------------------------------------------ evaluation
 

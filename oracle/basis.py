@@ -189,10 +189,14 @@ class DualRawBasis:
         e1, e2); the affine shift keeps the nested spans of xi^a eta^b.
     3D: monomials ((x - c)/h)^alpha with c the dual element centroid and h
         a length scale (neither changes the canonical basis).
+    ``mix`` (optional, n x n upper triangular): the basis is the monomials
+        times mix, i.e. function i is a combination of monomials 0..i, which
+        keeps the nested spans.
     """
 
-    def __init__(self, dim: int, p: int, origin, axes=None, scale=1.0):
+    def __init__(self, dim: int, p: int, origin, axes=None, scale=1.0, mix=None):
         self.dim, self.p = dim, p
+        self.mix = mix
         self.exps = dual_exponents(dim, p)
         self.origin = np.asarray(origin, float)
         if dim == 2:
@@ -212,4 +216,5 @@ class DualRawBasis:
 
     def eval(self, x):
         y = self.coords(x)
-        return np.stack([np.prod(y ** np.array(e)[None, :], axis=1) for e in self.exps], axis=1)
+        mono = np.stack([np.prod(y ** np.array(e)[None, :], axis=1) for e in self.exps], axis=1)
+        return mono if self.mix is None else mono @ self.mix

@@ -111,7 +111,7 @@ class Slab:
                 P[c, l, vo[c, l]] = 1.0
         Ev = np.zeros((nf, nsig, d, d))
         for j in range(nf):
-            E = stiffness(d, B.lam_j[j], B.mu_j[j])
+            E = B.face_stiffness(j)
             for pp in range(d):
                 for qq in range(pp, d):
                     Ev[j, vo[pp, qq]] = E[pp, qq]
@@ -153,6 +153,43 @@ class Slab:
         S = Avv - Avs @ (Ainv @ Asv)
         self._schur_parts = (S.tocsr(), Avs.tocsr(), Asv, Ainv)
         return self._schur_parts[0]
+
+    def _element_neighbours(self):
+        nb = [set() for _ in range(self.ne)]
+        for F in self.B.topo.faces:
+            if F.right >= 0 and F.right != F.left:
+                nb[F.left].add(F.right)
+                nb[F.right].add(F.left)
+        return nb
+
+    def block_jacobi(self):
+        """Pre1 of Appendix A (eq. pre1): the inverses of the element diagonal
+        blocks of the velocity operator, as a block-diagonal sparse matrix."""
+        S = self._schur_parts[0] if getattr(self, "_schur_parts", None) is not None else self.schur()
+        nb = self.ng * self.d * self.nphi
+        blocks = [np.linalg.inv(S[i * nb:(i + 1) * nb, i * nb:(i + 1) * nb].toarray()) for i in range(self.ne)]
+        return sp.block_diag(blocks, format="csr")
+
+    def patch_preconditioner(self):
+        """Pre2 of Appendix A (eqs. APPRE1, APPRE2): for each element i the
+        velocity operator restricted to the stencil S_i of i and its face
+        neighbours (diagonal blocks D and neighbour blocks N), inverted; the
+        block row of element i of that inverse gives (P x)_i = sum_e
+        A_i^-1(0, e) x_g(e).  Returned as a sparse matrix P."""
+        S = self._schur_parts[0] if getattr(self, "_schur_parts", None) is not None else self.schur()
+        S = S.tocsr()
+        nb = self.ng * self.d * self.nphi
+        nbrs = self._element_neighbours()
+        rows, cols, vals = [], [], []
+        for i in range(self.ne):
+            st = [i] + sorted(nbrs[i])
+            idx = np.concatenate([np.arange(e * nb, (e + 1) * nb) for e in st])
+            Ainv = np.linalg.inv(S[idx][:, idx].toarray())
+            rows.append(np.repeat(np.arange(i * nb, (i + 1) * nb), len(idx)))
+            cols.append(np.tile(idx, nb))
+            vals.append(Ainv[:nb].ravel())
+        n = self.nv
+        return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
 
     def step_schur(self, v_old, s_old_raw, sources=None, rtol=1e-10, maxiter=100000):
         """The same step as step(), computed the way Section 4 describes:
@@ -279,7 +316,7 @@ class Slab:
         es = 0.0
         psi_deg = 2 * B.p if d == 2 else B.p
         for j, F in enumerate(B.topo.faces):
-            C = compliance_voigt(d, B.lam_j[j], B.mu_j[j])
+            C = B.face_compliance(j)
             for side in ([0] if F.right < 0 else [0, 1]):
                 x, w = quad.simplex_rule(B.topo.sub_simplex(j, side), 2 * psi_deg)
                 sv = B.stress_at(s_raw[j], j, x)  # (npts, nsig)

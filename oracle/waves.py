@@ -85,6 +85,43 @@ class ShearWave3D:
         return np.outer(self._phase(x, t), sv)
 
 
+class AnisotropicPlaneWave:
+    """Plane wave in a homogeneous general medium with stiffness tensor
+    E[p,q,c,l] (sigma_pq = sum E[p,q,c,l] d_l v_c, eq. 1.1) and density rho:
+    v = alpha a sin(k.x - omega t),
+    sigma_pq = -(alpha / omega) sum_cl E[p,q,c,l] a_c k_l sin(k.x - omega t),
+    which solves eq. (1.1) identically and eq. (1.2) when
+    rho omega^2 a = Gamma a, Gamma_pc = sum_ql E[p,q,c,l] k_q k_l (the
+    Christoffel matrix).  ``branch`` picks the eigenpair (0 = fastest)."""
+
+    def __init__(self, E, rho, kvec, alpha=0.1, branch=0):
+        self.E = np.asarray(E, float)
+        self.d = self.E.shape[0]
+        self.k = np.asarray(kvec, float)
+        self.rho = float(rho)
+        self.alpha = alpha
+        G = np.einsum("pqcl,q,l->pc", self.E, self.k, self.k)
+        w, V = np.linalg.eigh(0.5 * (G + G.T))
+        i = np.argsort(w)[::-1][branch]
+        self.a = V[:, i]
+        self.omega = np.sqrt(w[i] / self.rho)
+        self.S = -(alpha / self.omega) * np.einsum("pqcl,c,l->pq", self.E, self.a, self.k)
+
+    def _phase(self, x, t):
+        return np.sin(np.atleast_2d(x) @ self.k - self.omega * t)
+
+    def velocity(self, x, t):
+        return self.alpha * np.outer(self._phase(x, t), self.a)
+
+    def stress_voigt(self, x, t):
+        vo = voigt_index(self.d)
+        sv = np.zeros(self.d * (self.d + 1) // 2)
+        for p in range(self.d):
+            for q in range(p, self.d):
+                sv[vo[p, q]] = self.S[p, q]
+        return np.outer(self._phase(x, t), sv)
+
+
 def project(B: Blocks, wave, t=0.0, extra_degree=6):
     """L2 projections of the wave's velocity onto P_p per element and of its
     stress onto the dual space per dual element (raw basis).

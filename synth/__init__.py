@@ -30,10 +30,14 @@ __all__ = [
     "kuhn_cube",
     "layered_material",
     "lognormal_material",
+    "anisotropic_material",
     "homogeneous_material",
     "ricker",
     "random_points",
     "top_edge_receivers",
+    "with_slivers",
+    "inradius",
+    "ragged_meshes",
     "workload",
 ]
 
@@ -145,6 +149,60 @@ def split_square(n: int, m: int | None = None, *, jitter: float = 0.0,
                           periodic=periodic, diagonal=diagonal))
 
 
+def inradius(V: np.ndarray) -> np.ndarray:
+    """Incircle radii of triangles with vertex coordinates V (n, 3, 2)."""
+    V = np.asarray(V, float)
+    a = np.linalg.norm(V[:, 1] - V[:, 2], axis=1)
+    b = np.linalg.norm(V[:, 0] - V[:, 2], axis=1)
+    c = np.linalg.norm(V[:, 0] - V[:, 1], axis=1)
+    e1, e2 = V[:, 1] - V[:, 0], V[:, 2] - V[:, 0]
+    area = 0.5 * np.abs(e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0])
+    return 2.0 * area / (a + b + c)
+
+
+def with_slivers(mesh: Mesh, squares, ratio: float) -> Mesh:
+    """The same split-square mesh ('/' diagonals) with one sliver per listed
+    square (i, j): the corner (i+1, j) moves towards the midpoint of the
+    square's diagonal until the incircle radius of the square's triangle
+    (v00, v10, v11) is ``ratio`` times smaller than before (Section 6.6
+    reduces it 70.53 times).  The square's other triangle is unchanged; the
+    triangles of the neighbouring squares that share the moved corner are
+    stretched but stay valid.  The squares must not share corners.  Returns
+    a new mesh; the sliver triangles are meta["slivers"]."""
+    n, m = mesh.meta["n"], mesh.meta["m"]
+    if mesh.meta.get("diagonal", "/") != "/":
+        raise ValueError("expects '/' diagonals")
+    periodic = mesh.period is not None
+    nvx = n if periodic else n + 1
+
+    def vid(a, b):
+        return (b % m) * nvx + (a % n) if periodic else b * nvx + a
+
+    xyz = mesh.xyz.copy()
+    U = mesh.unwrapped_vertices()
+    slivers = []
+    for i, j in squares:
+        e0 = 2 * (j * n + i)                   # triangle (v00, v10, v11)
+        v00, v10, v11 = U[e0]
+        r0 = inradius(U[e0:e0 + 1])[0]
+        mid = 0.5 * (v00 + v11)
+        d = v11 - v00
+        nrm = np.array([d[1], -d[0]]) / np.linalg.norm(d)   # towards v10 on a counter-clockwise square
+        target = r0 / ratio
+        lo, hi = 0.0, 0.5 * np.linalg.norm(d)
+        for _ in range(200):
+            mid_d = 0.5 * (lo + hi)
+            if inradius(np.array([[v00, mid + mid_d * nrm, v11]]))[0] < target:
+                lo = mid_d
+            else:
+                hi = mid_d
+        new10 = mid + 0.5 * (lo + hi) * nrm
+        xyz[vid(i + 1, j)] = xyz[vid(i + 1, j)] + (new10 - v10)   # in the stored vertex's frame
+        slivers.append(e0)
+    meta = dict(mesh.meta, slivers=tuple(slivers), sliver_ratio=ratio, sliver_squares=tuple(map(tuple, squares)))
+    return Mesh(xyz=xyz, elem=mesh.elem.copy(), period=mesh.period, meta=meta)
+
+
 def kuhn_cube(n: int, *, periodic: bool = True, lo=(0.0, 0.0, 0.0),
               hi=(1.0, 1.0, 1.0)) -> Mesh:
     """n^3 cubes, each cut into the 6 tetrahedra along its main diagonal.
@@ -204,6 +262,44 @@ def lognormal_material(n_elem: int, *, base=(2.0, 1.0, 1.0), sigma: float = 0.2,
     return base[0] * f[:, 0], base[1] * f[:, 1], base[2] * f[:, 2]
 
 
+def anisotropic_material(n_elem: int, dim: int, *, lam: float = 2.0, mu: float = 1.0, rho: float = 1.0,
+                         sigma: float = 0.2, strength: float = 0.5, homogeneous: bool = False,
+                         seed: int = 0):
+    """General (anisotropic) media in the Voigt form of Section 2: per
+    element the matrix E~ with s~ = E~ e~ (tensor shear strains, so 2 mu on
+    the isotropic shear diagonal), Voigt order (xx, yy, xy) or (xx, yy, zz,
+    yz, xz, xy).  Returns (E~ (n_elem, n_sigma, n_sigma), rho (n_elem,)).
+
+    The tensor entries E_ijkl of each element, laid out as the symmetric
+    n_sigma x n_sigma matrix H[v(ij)][v(kl)], are exp(sigma Z) times those of
+    the isotropic (lam, mu) medium plus strength * G G^T / n_sigma with
+    G ~ N(0,1) n_sigma x n_sigma (positive definite, every normal-shear
+    coupling present); E~ = H W with W = 1 on normal, 2 on shear columns.
+    Draws are element-major: Z, then G row-major, then Z_rho with
+    rho exp(sigma Z_rho).  ``homogeneous`` repeats element 0's draw."""
+    ns = dim * (dim + 1) // 2
+    rng = np.random.default_rng(seed)
+    H0 = np.zeros((ns, ns))
+    H0[:dim, :dim] = lam
+    H0[np.arange(dim), np.arange(dim)] = lam + 2 * mu
+    H0[np.arange(dim, ns), np.arange(dim, ns)] = mu
+    W = np.array([1.0] * dim + [2.0] * (ns - dim))
+    m = 1 if homogeneous else n_elem
+    Et = np.empty((m, ns, ns))
+    r = np.empty(m)
+    for e in range(m):
+        z = rng.standard_normal()
+        G = rng.standard_normal((ns, ns))
+        zr = rng.standard_normal()
+        H = np.exp(sigma * z) * H0 + strength * (G @ G.T) / ns
+        Et[e] = H * W[None, :]
+        r[e] = rho * np.exp(sigma * zr)
+    if homogeneous:
+        Et = np.repeat(Et, n_elem, axis=0)
+        r = np.repeat(r, n_elem)
+    return Et, r
+
+
 def layered_material(centroids: np.ndarray, *, sigma: float = 0.1, seed: int = 0,
                      axis: int = 1):
     """Three layers by centroid coordinate along ``axis``.
@@ -245,6 +341,22 @@ def top_edge_receivers(n: int, y: float = 1.0) -> np.ndarray:
     """n receivers at ((r + 1/2)/n, y)."""
     x = (np.arange(n) + 0.5) / n
     return np.stack([x, np.full(n, y)], axis=1)
+
+
+def ragged_meshes(n_mesh: int = 16, seed: int = 4002, lo: int = 512, hi: int = 16384):
+    """Meshes of uneven size for a mesh batch: N_k = exp(U(ln lo, ln hi))
+    triangles (seed), n_x = round(sqrt(N_k / 2)), n_y = round(N_k / (2 n_x))
+    split squares of the unit square with 20% jitter (seed 4100 + k), and
+    three lognormal layers (seed 4200 + k).  Returns [(mesh, (lam, mu, rho))]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_mesh):
+        Nk = math.exp(rng.uniform(math.log(lo), math.log(hi)))
+        nx = max(1, round(math.sqrt(Nk / 2)))
+        ny = max(1, round(Nk / (2 * nx)))
+        m = split_square(nx, ny, jitter=0.2, seed=4100 + k)
+        out.append((m, layered_material(m.centroids(), sigma=0.1, seed=4200 + k)))
+    return out
 
 
 def workload(name: str, scale: int | None = None) -> dict:

@@ -436,3 +436,47 @@ def test_schur_krylov_step_equals_coupled_lu_step(case):
     assert its > 0
     assert np.linalg.norm(v2 - v1) <= 1e-10 * np.linalg.norm(v1)
     assert np.linalg.norm(s2 - s1) <= 1e-10 * np.linalg.norm(s1)
+
+
+@pytest.mark.parametrize("case", ["stdg_2d_free", "cn_3d_periodic"])
+def test_preconditioners_invert_single_element_columns(case):
+    """Pre1 and Pre2 (Appendix A): for u supported on one element i, S u is
+    supported on the stencil of i, whose restriction of S is exactly the
+    diagonal block (Pre1) or the patch matrix A_i of eq. APPRE1 (Pre2); so
+    (P S u)_i = u_i for both.  Pre2 is not block-diagonal, Pre1 is."""
+    if case == "stdg_2d_free":
+        mesh, p, pg, sch = synth.split_square(4, jitter=0.2, seed=5), 2, 1, "stdg"
+    else:
+        mesh, p, pg, sch = synth.kuhn_cube(3), 1, 0, "cn"
+    B = _blocks(mesh, p, synth.lognormal_material(mesh.n_elem, seed=9))
+    slab = Slab(B, pg, 0.02, sch)
+    S = slab.schur()
+    P1, P2 = slab.block_jacobi(), slab.patch_preconditioner()
+    nb = slab.ng * B.dim * B.nphi
+    rng = np.random.default_rng(3)
+    for i in rng.choice(B.topo.n_elem, 5, replace=False):
+        u = np.zeros(slab.nv)
+        u[i * nb:(i + 1) * nb] = rng.standard_normal(nb)
+        for P in (P1, P2):
+            got = (P @ (S @ u))[i * nb:(i + 1) * nb]
+            assert np.allclose(got, u[i * nb:(i + 1) * nb], rtol=0, atol=1e-10 * np.abs(u).max())
+    # Pre2 couples an element to its neighbours' values, Pre1 does not
+    i = 0
+    off = P2[i * nb:(i + 1) * nb].toarray().copy()
+    off[:, i * nb:(i + 1) * nb] = 0.0
+    assert np.abs(off).max() > 1e-6 * np.abs(P2[i * nb:(i + 1) * nb].toarray()).max()
+    off1 = P1[i * nb:(i + 1) * nb].toarray().copy()
+    off1[:, i * nb:(i + 1) * nb] = 0.0
+    assert not off1.any()
+
+
+def test_patch_preconditioner_is_the_inverse_when_stencils_cover_the_mesh():
+    """On two triangles (one square, free surface) each element's stencil is
+    the whole mesh, so the patch matrix of eq. APPRE1 is the whole velocity
+    operator and Pre2 is its exact inverse."""
+    mesh = synth.split_square(1)
+    B = _blocks(mesh, 2, synth.lognormal_material(mesh.n_elem, seed=4))
+    slab = Slab(B, 1, 0.05, "stdg")
+    S = slab.schur().toarray()
+    P2 = slab.patch_preconditioner().toarray()
+    assert np.abs(P2 @ S - np.eye(slab.nv)).max() <= 1e-10
