@@ -209,52 +209,90 @@ def bench_batched(args, t_single_fp64):
 def bench_mesh_batch(args):
     """16 meshes with log-uniform sizes in [512, 16384] triangles (seed
     4002), jitter seeds 4100+k, layered lognormal media seeds 4200+k, one
-    Ricker source each, one step of all meshes (HIP graphs and eager)."""
-    import math
-
+    Ricker source each: steps of all meshes in one batch (HIP graphs and
+    eager, FP64 and FP32 + FP64 refinement), against the same steps solved
+    one mesh after another (16 contexts, single-system GMRES)."""
     import numpy as np
     import torch
 
     import paper_1802_04516_amd as sdg
     import synth
-    rng = np.random.default_rng(4002)
-    meshes, mats = [], []
-    for k in range(16):
-        Nk = math.exp(rng.uniform(math.log(512), math.log(16384)))
-        nx = max(1, round(math.sqrt(Nk / 2)))
-        ny = max(1, round(Nk / (2 * nx)))
-        m = synth.split_square(nx, ny, jitter=0.2, seed=4100 + k)
-        meshes.append(m)
-        mats.append(synth.layered_material(m.centroids(), sigma=0.1, seed=4200 + k))
+    batch = synth.ragged_meshes(16, seed=4002)
+    meshes = [m for m, _ in batch]
+    mats = [mt for _, mt in batch]
     lam, mu, rho = (np.concatenate([mt[i] for mt in mats]) for i in range(3))
-    ctx = sdg.Context(0)
     dt = 2.5e-3
-    sizes = ctx.setup_batch([(m.xyz, m.elem) for m in meshes], 3, 3, sdg.SDG_SCHEME_STDG, dt, lam, mu, rho,
-                            sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND)
+    prc = sdg.SDG_PREC_F64 | sdg.SDG_PREC_F32 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND
+    ctx = sdg.Context(0)
+    sizes = ctx.setup_batch([(m.xyz, m.elem) for m in meshes], 3, 3, sdg.SDG_SCHEME_STDG, dt, lam, mu, rho, prc)
     ctx.set_mesh_sources(np.tile([[0.503, 0.497]], (16, 1)), np.tile([[0.0, 1.0]], (16, 1)),
                          np.arange(16, dtype=np.int32))
     tau = np.array(sizes["tau"])
     step0 = int(0.05 / dt)
+    steps = 3
 
-    def amps(k):
+    def amp1(k):
         t = (step0 + k) * dt + tau * dt
-        return np.tile(synth.ricker(t, 10.0, 0.1)[None, :], (16, 1)).ravel()
+        return synth.ricker(t, 10.0, 0.1)[None, :]
 
-    res = {"n_mesh": 16, "elements": [m.n_elem for m in meshes], "velocity_dofs": sizes["n_vel_slab"]}
-    for name, flags in (("fp64_hip_graph", sdg.SDG_SOLVE_GRAPH), ("fp64_eager", 0)):
+    def opts(prec, flags, solver=sdg.SDG_SOLVER_GMRES):
+        o = _solve_opts(sdg, prec, sdg.SDG_PRECOND_BLOCK, flags, solver)
+        if prec == sdg.SDG_PREC_F32:
+            o.inner_rtol = IR_INNER_RTOL
+        return o
+
+    res = {"n_mesh": 16, "elements": [m.n_elem for m in meshes], "velocity_dofs": sizes["n_vel_slab"],
+           "timed_steps": steps}
+    for name, flags, prec in (("fp64_hip_graph", sdg.SDG_SOLVE_GRAPH, sdg.SDG_PREC_F64),
+                              ("fp64_eager", 0, sdg.SDG_PREC_F64),
+                              ("fp32_ir_hip_graph", sdg.SDG_SOLVE_GRAPH, sdg.SDG_PREC_F32),
+                              ("fp32_ir_eager", 0, sdg.SDG_PREC_F32)):
         v = torch.zeros(sizes["n_vel_state"], dtype=torch.float64, device="cuda")
         s = torch.zeros(sizes["n_stress_state"], dtype=torch.float64, device="cuda")
-        o = _solve_opts(sdg, sdg.SDG_PREC_F64, sdg.SDG_PRECOND_BLOCK, flags, sdg.SDG_SOLVER_GMRES)
-        ctx.step(v, s, amps(0), opts=o)  # warm-up (records the graphs)
+        o = opts(prec, flags)
+        ctx.step(v, s, np.tile(amp1(0), (16, 1)).ravel(), opts=o)  # warm-up (records the graphs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        info = ctx.step(v, s, amps(1), opts=o)
+        it = mv = 0
+        for k in range(steps):
+            info = ctx.step(v, s, np.tile(amp1(1 + k), (16, 1)).ravel(), opts=o)
+            it += info["iterations"]
+            mv += info["matvecs"]
         torch.cuda.synchronize()
-        t = time.perf_counter() - t0
-        res[name] = {"s_per_step": t, "iterations": info["iterations"], "matvecs": info["matvecs"],
-                     "gdofs": sizes["n_vel_slab"] * info["matvecs"] / t / 1e9}
-        log(f"mesh batch 16 ({sizes['n_elem']} elems) {name}: {t * 1e3:.1f} ms/step, {info['iterations']} it")
+        t = (time.perf_counter() - t0) / steps
+        res[name] = {"s_per_step": t, "iterations_per_step": it / steps,
+                     "gdofs": sizes["n_vel_slab"] * (mv / steps) / t / 1e9}
+        log(f"mesh batch 16 ({sizes['n_elem']} elems) {name}: {t * 1e3:.1f} ms/step, {it / steps:.0f} it")
     ctx.close()
+    # the same 16 steps solved one mesh after another, each in its own context
+    ctxs, states = [], []
+    for q, (m, mt) in enumerate(zip(meshes, mats)):
+        cq = sdg.Context(0)
+        sq = cq.setup(m.xyz, m.elem, None, 3, 3, sdg.SDG_SCHEME_STDG, dt, *mt, prc)
+        cq.set_sources(np.array([[0.503, 0.497]]), np.array([[0.0, 1.0]]))
+        ctxs.append(cq)
+        states.append((sq["n_vel_state"], sq["n_stress_state"]))
+    for name, prec in (("sequential_fp64", sdg.SDG_PREC_F64), ("sequential_fp32_ir", sdg.SDG_PREC_F32)):
+        vs = [torch.zeros(nv, dtype=torch.float64, device="cuda") for nv, _ in states]
+        ss = [torch.zeros(ns, dtype=torch.float64, device="cuda") for _, ns in states]
+        o = opts(prec, 0)
+        for q, cq in enumerate(ctxs):
+            cq.step(vs[q], ss[q], amp1(0).ravel(), opts=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it = 0
+        for k in range(steps):
+            for q, cq in enumerate(ctxs):
+                it += cq.step(vs[q], ss[q], amp1(1 + k).ravel(), opts=o)["iterations"]
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        res[name] = {"s_per_step": t, "iterations_per_step_all_meshes": it / steps}
+        log(f"16 meshes one after another {name}: {t * 1e3:.1f} ms/step")
+    for cq in ctxs:
+        cq.close()
+    best_seq = min(res["sequential_fp64"]["s_per_step"], res["sequential_fp32_ir"]["s_per_step"])
+    for name in ("fp64_hip_graph", "fp64_eager", "fp32_ir_hip_graph", "fp32_ir_eager"):
+        res[name]["speedup_vs_best_sequential"] = best_seq / res[name]["s_per_step"]
     return res
 
 
@@ -662,6 +700,8 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--prec", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--only", choices=["mesh_batch", "batched"],
+                    help="only run one extra measurement (no headline line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB x 10 (scale for the rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -670,7 +710,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     oracle = None
-    if not (args.no_cpu_baseline or args.apply_probe or args.calibrate_copy):
+    if not (args.no_cpu_baseline or args.apply_probe or args.calibrate_copy or args.only):
         # before anything touches the GPU: the oracle child starts from a
         # process without GPU state
         oracle = start_oracle(CPU_SAMPLE_N)
@@ -690,6 +730,12 @@ def main():
         return
     if args.apply_probe:
         apply_probe(args)
+        return
+    if args.only == "mesh_batch":
+        print(json.dumps({"mesh_batch_16": bench_mesh_batch(args)}), flush=True)
+        return
+    if args.only == "batched":
+        print(json.dumps({"batched_64_sources": bench_batched(args, float("nan"))}), flush=True)
         return
 
     c3 = bench_c3(args)

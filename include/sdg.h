@@ -83,14 +83,20 @@ enum {
 
 enum { SDG_SCHEME_STDG = 0, SDG_SCHEME_CN = 1 };
 enum { SDG_PREC_F64 = 1, SDG_PREC_F32 = 2 };
-/* extra sdg_assemble flag: also build the block preconditioner (eq. pre1) */
-enum { SDG_ASSEMBLE_BLOCK_PRECOND = 4 };
+/* extra sdg_assemble flags: also build the block preconditioner (eq. pre1),
+ * the patch preconditioner (eqs. APPRE1-APPRE2) */
+enum { SDG_ASSEMBLE_BLOCK_PRECOND = 4, SDG_ASSEMBLE_PATCH_PRECOND = 8 };
 enum { SDG_SOLVER_AUTO = 0, SDG_SOLVER_CG = 1, SDG_SOLVER_GMRES = 2 };
-/* Preconditioners (Appendix A discusses block-Jacobi preconditioning):
+/* Preconditioners (Appendix A):
  * MASS  = element block-Jacobi on the mass term, (T (x) rho Mbar_i)^-1, no storage;
- * BLOCK = element block-Jacobi on the full diagonal block of the velocity
- *         operator (eq. pre1), inverses stored at assemble time. */
-enum { SDG_PRECOND_NONE = 0, SDG_PRECOND_MASS = 1, SDG_PRECOND_BLOCK = 2 };
+ * BLOCK = Pre1, element block-Jacobi on the full diagonal block of the
+ *         velocity operator (eq. pre1), inverses stored at assemble time;
+ * PATCH = Pre2, for each element the first block row of the inverse of the
+ *         velocity operator restricted to the element and its face
+ *         neighbours (eqs. APPRE1, APPRE2), stored at assemble time in FP32,
+ *         (N_gamma d N_phi)^2 (d + 2) floats per element; not symmetric, so
+ *         it is used with GMRES (CG rejects it) and not in the adjoint. */
+enum { SDG_PRECOND_NONE = 0, SDG_PRECOND_MASS = 1, SDG_PRECOND_BLOCK = 2, SDG_PRECOND_PATCH = 3 };
 /* Solve flags (sdg_solve_opts.flags):
  * GRAPH        replay the step from HIP graphs (see sdg_solve_step);
  * EXTRAPOLATE  initial guess continued from the previous slab (sdg_solve_step);
@@ -121,9 +127,11 @@ typedef struct {
   int32_t op_variant;     /* face-kernel variant in use for FP64 (see sdg_set_operator_variant) */
   int32_t op_variant_f32;
   int32_t op_bvariant;    /* batched FP64 apply (see sdg_set_batched_variant) */
-  double tune_us_f64[8];  /* autotuner timings of the variants (microseconds per apply) */
-  double tune_us_f32[8];
+  double tune_us_f64[9];  /* autotuner timings of the variants (microseconds per apply; 0 = not available) */
+  double tune_us_f32[9];
   double tune_us_batched[3]; /* batched applies of max_rhs columns per batched variant */
+  int64_t cmp_bytes_f64;  /* bytes read per apply by the compressed 3D operator (variant 8), 0 if not built */
+  int64_t cmp_bytes_f32;
 } sdg_sizes;
 
 typedef struct {
@@ -209,6 +217,26 @@ int sdg_set_discretization(sdg_ctx* ctx, int p, int p_gamma, int scheme, double 
  * a non-finite or out-of-range value. */
 int sdg_set_material(sdg_ctx* ctx, const double* lambda, const double* mu, const double* rho);
 
+/* General (anisotropic) linear elastic material, Section 2: per element the
+ * n_sigma x n_sigma matrix E~ of the Voigt form s~ = E~ e~ (host, n_elem
+ * matrices row-major, n_sigma = 3 in 2D, 6 in 3D), with the Voigt order
+ * (xx, yy, xy) in 2D and (xx, yy, zz, yz, xz, xy) in 3D and the strain with
+ * tensor shear components e_xy = (d_y u + d_x v) / 2, so that an isotropic
+ * material has 2 mu on the shear diagonal (eq. 5), and density rho (n_elem,
+ * > 0).  The stiffness tensor has the major symmetry E_ijkl = E_klij, which
+ * makes E~ W^-1 symmetric (W = 1 on normal, 2 on shear components); the
+ * library symmetrises it and rejects (SDG_EINVAL) a violation beyond 1e-12
+ * of the largest entry, or a non-finite entry.  As in sdg_set_material,
+ * E_j on the dual element R_j is the volume-weighted mean of its two
+ * elements' E~ and must be positive definite (checked at sdg_assemble,
+ * SDG_EINVAL).  The Hooke law of eq. (1.1) then enters every operator apply,
+ * right-hand side, back-substitution and energy.  The face kernels that
+ * apply it are variants 3, 4 and 8 (sdg_set_operator_variant refuses the
+ * others, autotuning picks among these) and batched applies use the column
+ * grid; sdg_adjoint_step refuses an anisotropic material
+ * (SDG_EUNSUPPORTED).  sdg_set_material returns to an isotropic material. */
+int sdg_set_material_anisotropic(sdg_ctx* ctx, const double* stiffness, const double* rho);
+
 /* Build topology, geometry, bases and the operator blocks on the host and
  * upload them: the element mass Mbar_i and time matrices of eqs. (MD_2) to
  * (MD_2_3), the coupling blocks D_{i,j} of eq. (MD_3) in the canonical dual
@@ -248,6 +276,13 @@ int sdg_query(const sdg_ctx* ctx, sdg_sizes* out);
  *   7 = one face per wavefront on the FP64 matrix cores (the face gradient
  *       and scatter as 16x16x4 MFMA sequences, the rows padded to 16; in
  *       FP32, or where N_gamma d > 16 or N_phi > 16, variant 5);
+ *   8 = compressed 3D operator (tetrahedra, p <= 2; built by sdg_assemble
+ *       beside the blocks): no block is read; each face side's block of eq.
+ *       (MD_3) is applied through its factors, the change of basis C from
+ *       the canonical dual basis to a reference basis of P_p on the side's
+ *       reference sub-simplex (N_psi^2 values per side), the face-term
+ *       coefficients of the side and |J| J^-1 of its element, and reference
+ *       tables of the four local faces (SDG_EUNSUPPORTED elsewhere);
  *  -1 reruns the autotuner (sdg_assemble runs it: every variant is timed on
  *       the assembled operator and the fastest kept, per precision).
  * All variants compute the same operator. */
@@ -292,6 +327,12 @@ int sdg_apply_velocity_operator(sdg_ctx* ctx, const double* v, double* y, int n_
 int sdg_apply_velocity_operator_noalloc(sdg_ctx* ctx, const double* v, double* y, int n_rhs, int precision,
                                         void* stream);
 
+/* y = P^-1 x for the preconditioner `kind` (SDG_PRECOND_*; NONE copies),
+ * the approximate inverse the Krylov solves apply on the right (Appendix A):
+ * x, y device slab vectors of n_rhs columns (must not alias).  SDG_ESTATE
+ * if BLOCK or PATCH was not assembled. */
+int sdg_apply_preconditioner(sdg_ctx* ctx, int kind, const double* x, double* y, int n_rhs, void* stream);
+
 /* y = A^T w: the transpose of the velocity operator of eq. (velocity.sys),
  * A^T = T^T (x) rho Mbar + dt^2 (W T^-T W) (x) K (K is symmetric, Section 5),
  * used by the discrete adjoint.  Same arguments, layouts and errors as
@@ -332,12 +373,19 @@ int sdg_set_mesh_sources(sdg_ctx* ctx, int64_t n_src, const double* pos, const d
  * the old state as usual.  Both guesses converge to the same tolerance.
  * On SDG_ENOCONV the states hold the step computed from the last iterate
  * and *info is filled.
- * With opts->flags & SDG_SOLVE_GRAPH (FP64, GMRES) the step's launches are
- * recorded once into HIP graphs (right-hand side + first restart cycle, one
- * restart cycle, residual check, back-substitution) and replayed; the host
- * only reads the device count of unconverged systems between replays, and
- * every cycle runs its full restart length (converged systems are masked
- * on the device).  The graphs are kept while the state, slab and amplitude
+ * With opts->flags & SDG_SOLVE_GRAPH (GMRES, FP64 or FP32 + refinement)
+ * the step's launches are recorded once into HIP graphs (right-hand side +
+ * first restart cycle, one restart cycle, residual check, back-substitution;
+ * with SDG_PREC_F32 also the refinement update x += e with the new outer
+ * residual) and replayed; the host only reads the device count of
+ * unconverged systems between replays.  With the default delayed
+ * orthogonalisation each restart cycle is recorded in parts of
+ * check_every steps, polled between parts as the eager solver polls, so
+ * both take the same iterations; with SDG_SOLVE_CGS2 every cycle runs its
+ * full restart length (converged systems are masked on the device).  With
+ * SDG_PREC_F32 each system's outer test runs on the device: a system that
+ * has reached rtol takes no further inner step, and the step ends when
+ * every system has, or after max_refine corrections.  The graphs are kept while the state, slab and amplitude
  * pointers, n_rhs and the solver options stay the same; they are rebuilt
  * otherwise and dropped by sdg_assemble, sdg_set_sources and
  * sdg_set_operator_variant.  The call synchronises `stream` before the

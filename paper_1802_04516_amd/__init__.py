@@ -25,8 +25,10 @@ SDG_ENOCONV, SDG_ENONFINITE, SDG_EUNSUPPORTED, SDG_ESTATE = -5, -6, -7, -8
 SDG_SCHEME_STDG, SDG_SCHEME_CN = 0, 1
 SDG_PREC_F64, SDG_PREC_F32 = 1, 2
 SDG_ASSEMBLE_BLOCK_PRECOND = 4
+SDG_ASSEMBLE_PATCH_PRECOND = 8
 SDG_SOLVER_AUTO, SDG_SOLVER_CG, SDG_SOLVER_GMRES = 0, 1, 2
-SDG_PRECOND_NONE, SDG_PRECOND_MASS, SDG_PRECOND_BLOCK = 0, 1, 2
+SDG_PRECOND_NONE, SDG_PRECOND_MASS, SDG_PRECOND_BLOCK, SDG_PRECOND_PATCH = 0, 1, 2, 3
+N_VARIANTS = 9
 SDG_SOLVE_GRAPH = 1
 SDG_SOLVE_EXTRAPOLATE = 2
 SDG_SOLVE_CGS2 = 4
@@ -36,11 +38,12 @@ _ERRNAMES = {SDG_EINVAL: "EINVAL", SDG_ENOMEM: "ENOMEM", SDG_EDEVICE: "EDEVICE",
              SDG_ESTATE: "ESTATE"}
 
 EXPORTED = ("sdg_last_error", "sdg_create", "sdg_destroy", "sdg_set_mesh", "sdg_set_discretization",
-            "sdg_set_material", "sdg_assemble", "sdg_query", "sdg_set_operator_variant", "sdg_set_batched_variant", "sdg_face_table",
+            "sdg_set_material", "sdg_set_material_anisotropic", "sdg_assemble", "sdg_query", "sdg_set_operator_variant", "sdg_set_batched_variant", "sdg_face_table",
             "sdg_apply_velocity_operator", "sdg_apply_adjoint", "sdg_set_sources", "sdg_solve_step",
             "sdg_energy", "sdg_sample_velocity", "sdg_eval_stress", "sdg_adjoint_step",
             "sdg_sample_velocity_adjoint", "sdg_set_mesh_batch", "sdg_set_mesh_sources",
-            "sdg_projection_points", "sdg_project_state", "sdg_apply_velocity_operator_noalloc")
+            "sdg_projection_points", "sdg_project_state", "sdg_apply_velocity_operator_noalloc",
+            "sdg_apply_preconditioner")
 
 
 class SdgError(RuntimeError):
@@ -59,8 +62,9 @@ class Sizes(ctypes.Structure):
                 ("dt", ctypes.c_double), ("tau", ctypes.c_double * 8), ("op_bytes_f64", ctypes.c_int64),
                 ("op_bytes_f32", ctypes.c_int64), ("max_rhs", ctypes.c_int32), ("op_variant", ctypes.c_int32),
                 ("op_variant_f32", ctypes.c_int32), ("op_bvariant", ctypes.c_int32),
-                ("tune_us_f64", ctypes.c_double * 8), ("tune_us_f32", ctypes.c_double * 8),
-                ("tune_us_batched", ctypes.c_double * 3)]
+                ("tune_us_f64", ctypes.c_double * 9), ("tune_us_f32", ctypes.c_double * 9),
+                ("tune_us_batched", ctypes.c_double * 3), ("cmp_bytes_f64", ctypes.c_int64),
+                ("cmp_bytes_f32", ctypes.c_int64)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -98,6 +102,7 @@ def lib():
         "sdg_set_mesh": ([_P, i, ctypes.c_int64, _DP, ctypes.c_int64, _I64P, _DP], i),
         "sdg_set_discretization": ([_P, i, i, i, ctypes.c_double], i),
         "sdg_set_material": ([_P, _DP, _DP, _DP], i),
+        "sdg_set_material_anisotropic": ([_P, _DP, _DP], i),
         "sdg_assemble": ([_P, ctypes.c_uint, i], i),
         "sdg_query": ([_P, ctypes.POINTER(Sizes)], i),
         "sdg_set_operator_variant": ([_P, i], i),
@@ -106,6 +111,7 @@ def lib():
         "sdg_apply_velocity_operator": ([_P, _P, _P, i, i, _P], i),
         "sdg_apply_adjoint": ([_P, _P, _P, i, i, _P], i),
         "sdg_apply_velocity_operator_noalloc": ([_P, _P, _P, i, i, _P], i),
+        "sdg_apply_preconditioner": ([_P, i, _P, _P, i, _P], i),
         "sdg_set_sources": ([_P, ctypes.c_int64, _DP, _DP], i),
         "sdg_solve_step": ([_P, _P, _P, _DP, i, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P, _P, _P], i),
         "sdg_energy": ([_P, _P, _P, i, _DP, _P], i),
@@ -211,6 +217,15 @@ def sdg_set_material(h, lam, mu, rho):
                                   _hp(rho, ctypes.c_double)))
 
 
+def sdg_set_material_anisotropic(h, stiffness, rho):
+    """stiffness: (n_elem, n_sigma, n_sigma) Voigt matrices E~ (tensor shear
+    strains, so 2 mu on the isotropic shear diagonal); rho: (n_elem,)."""
+    E, rho = _host(stiffness, np.float64), _host(rho, np.float64)
+    if E.ndim != 3 or E.shape[1] != E.shape[2] or E.shape[0] != rho.shape[0]:
+        raise ValueError("stiffness must be (n_elem, n_sigma, n_sigma) and rho (n_elem,)")
+    _check(lib().sdg_set_material_anisotropic(h, _hp(E, ctypes.c_double), _hp(rho, ctypes.c_double)))
+
+
 def sdg_assemble(h, precisions=SDG_PREC_F64 | SDG_PREC_F32, max_rhs=1):
     _check(lib().sdg_assemble(h, precisions, max_rhs))
 
@@ -221,8 +236,8 @@ def sdg_query(h) -> dict:
     out = {f: getattr(s, f) for f, _ in Sizes._fields_
            if f not in ("tau", "tune_us_f64", "tune_us_f32", "tune_us_batched")}
     out["tau"] = [s.tau[a] for a in range(s.n_gamma)]
-    out["tune_us_f64"] = [x for x in s.tune_us_f64][:8]
-    out["tune_us_f32"] = [x for x in s.tune_us_f32][:8]
+    out["tune_us_f64"] = list(s.tune_us_f64)
+    out["tune_us_f32"] = list(s.tune_us_f32)
     out["tune_us_batched"] = list(s.tune_us_batched)
     return out
 
@@ -249,6 +264,10 @@ def sdg_apply_velocity_operator(h, v, y, n_rhs=1, precision=SDG_PREC_F64, stream
 def sdg_apply_velocity_operator_noalloc(h, v, y, n_rhs=1, precision=SDG_PREC_F64, stream=None):
     _check(lib().sdg_apply_velocity_operator_noalloc(h, _dev(v, name="v"), _dev(y, name="y"), n_rhs, precision,
                                                      _stream(stream)))
+
+
+def sdg_apply_preconditioner(h, kind, x, y, n_rhs=1, stream=None):
+    _check(lib().sdg_apply_preconditioner(h, kind, _dev(x, name="x"), _dev(y, name="y"), n_rhs, _stream(stream)))
 
 
 def sdg_apply_adjoint(h, w, y, n_rhs=1, precision=SDG_PREC_F64, stream=None):
@@ -374,6 +393,17 @@ class Context:
         self.sizes = sdg_query(self.h)
         return self.sizes
 
+    def setup_anisotropic(self, mesh_xyz, elem, period, p, p_gamma, scheme, dt, stiffness, rho,
+                          precisions=SDG_PREC_F64 | SDG_PREC_F32, max_rhs=1):
+        """As setup(), with per-element Voigt stiffness matrices E~ (Section 2)."""
+        sdg_set_mesh(self.h, mesh_xyz, elem, period)
+        self.mesh_elem_off = None
+        sdg_set_discretization(self.h, p, p_gamma, scheme, dt)
+        sdg_set_material_anisotropic(self.h, stiffness, rho)
+        sdg_assemble(self.h, precisions, max_rhs)
+        self.sizes = sdg_query(self.h)
+        return self.sizes
+
     def setup_batch(self, meshes, p, p_gamma, scheme, dt, lam, mu, rho, precisions=SDG_PREC_F64 | SDG_PREC_F32):
         """Several independent meshes (list of (xyz, elem)) solved together;
         lam, mu, rho are concatenated mesh after mesh."""
@@ -405,7 +435,7 @@ class Context:
         sdg_apply_adjoint(self.h, w, y, n_rhs, precision, stream)
 
     def set_operator_variant(self, variant):
-        """0..7 pins a face-kernel variant, -1 reruns the autotuner."""
+        """0..8 pins a face-kernel variant, -1 reruns the autotuner."""
         sdg_set_operator_variant(self.h, variant)
         self.sizes = sdg_query(self.h)
         return self.sizes
@@ -418,6 +448,11 @@ class Context:
 
     def set_sources(self, pos, direction):
         sdg_set_sources(self.h, pos, direction)
+
+    def apply_preconditioner(self, kind, x, y, n_rhs=1, stream=None):
+        n = self._n("n_vel_slab") * n_rhs
+        _dev(x, n, "x"), _dev(y, n, "y")
+        sdg_apply_preconditioner(self.h, kind, x, y, n_rhs, stream)
 
     def step(self, v_state, sigma_state, amp=None, n_rhs=1, **kw):
         _dev(v_state, self._n("n_vel_state") * n_rhs, "v_state")

@@ -90,10 +90,16 @@ OpArgs base_args(Ctx& c, int prec) {
   a.faces = c.d_faces.p;
   a.Dt = prec == SDG_PREC_F32 ? (const void*)c.d_Dt32.p : (const void*)c.d_Dt64.p;
   a.face_lm = c.d_face_lm.p;
+  a.face_E = c.d_face_E.p;
   a.elem_w = c.d_elem_w.p;
   a.Mref = c.d_Mref.p;
   a.y_scale = 1.0;
   a.sig_in_ng = 1;
+  a.cmpC = prec == SDG_PREC_F32 ? (const void*)c.d_cmpC32.p : (const void*)c.d_cmpC64.p;
+  a.cmpA = c.d_cmpA.p;
+  a.cmpB = c.d_cmpB.p;
+  a.cmpF = c.d_cmpF.p;
+  a.cmpG = c.d_cmpG.p;
   return a;
 }
 
@@ -123,6 +129,15 @@ void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipS
   SDG_HIP(hipGetLastError());
 }
 
+// The compressed 3D operator (variant 8) exists for this precision.
+static bool compressed_available(const Ctx& c, int prec) {
+  return prec == SDG_PREC_F32 ? c.d_cmpC32.p != nullptr : c.d_cmpC64.p != nullptr;
+}
+
+// Face-kernel variants that apply an anisotropic Hooke law: the
+// column-parallel kernels (3, 4) and the compressed operator (8).
+static bool aniso_variant(int v) { return v == 3 || v == 4 || v == 8; }
+
 // Time every face-kernel variant on the assembled operator and keep the
 // fastest per precision (the project's tile-shape autotuner).
 static void autotune(Ctx& c) {
@@ -137,6 +152,10 @@ static void autotune(Ctx& c) {
     int best = 0;
     double best_t = 1e30;
     for (int var = 0; var < kNumVariants; ++var) {
+      if ((var == 8 && !compressed_available(c, prec)) || (c.aniso && !aniso_variant(var))) {
+        c.tune_us[pi][var] = 0.0;
+        continue;
+      }
       if (pi == 0) c.variant64 = var; else c.variant32 = var;
       for (int w = 0; w < 3; ++w) apply_op(c, c.d_x.p, c.d_r.p, prec, false, s);
       SDG_HIP(hipEventRecord(e0, s));
@@ -153,8 +172,9 @@ static void autotune(Ctx& c) {
     if (pi == 0) c.variant64 = best; else c.variant32 = best;
   }
   // batched FP64 applies: column grid against the matrix-core tile widths
+  // (the matrix-core kernel applies the isotropic law only)
   c.bvariant = 0;
-  if (c.max_rhs > 1 && (c.precisions & SDG_PREC_F64)) {
+  if (c.max_rhs > 1 && (c.precisions & SDG_PREC_F64) && !c.aniso) {
     const int R = c.max_rhs;
     vec_fill(c.n_slab * R, 1.0, c.d_x.p, s);
     int best = 0;
@@ -191,6 +211,10 @@ void apply_precond(Ctx& c, int kind, const double* x, double* y, bool transpose,
     a.cs_v = a.cs_y = c.n_slab;
     launch_elem(hs.dim, hs.p, hs.ng, a, s);
     SDG_HIP(hipGetLastError());
+  } else if (kind == SDG_PRECOND_PATCH) {
+    require(c.d_P2.p != nullptr, SDG_ESTATE, "patch preconditioner not assembled (pass SDG_ASSEMBLE_PATCH_PRECOND)");
+    require(!transpose, SDG_EUNSUPPORTED, "the transposed patch preconditioner is not built");
+    launch_patch_apply(hs.n_elem, c.p2_nb, c.p2_slots, c.d_P2.p, c.d_P2nbr.p, x, y, s, ncols, c.n_slab);
   } else if (kind == SDG_PRECOND_BLOCK) {
     require(c.d_Pblk.p != nullptr || c.d_Pq.p != nullptr, SDG_ESTATE,
             "block preconditioner not assembled (pass SDG_ASSEMBLE_BLOCK_PRECOND)");
@@ -501,6 +525,49 @@ int sdg_set_material(sdg_ctx* ctx, const double* lambda, const double* mu, const
       require(std::isfinite(lambda[i]) && std::isfinite(mu[i]) && std::isfinite(rho[i]) && lambda[i] >= 0 &&
                   mu[i] > 0 && rho[i] > 0,
               SDG_EINVAL, "material parameters must be finite with lambda >= 0, mu > 0, rho > 0");
+    c.aniso = false;
+    c.elemE.clear();
+    c.have_mat = true;
+    c.assembled = false;
+  });
+}
+
+int sdg_set_material_anisotropic(sdg_ctx* ctx, const double* stiffness, const double* rho) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.have_mesh, SDG_ESTATE, "set the mesh first");
+    require(stiffness && rho, SDG_EINVAL, "null material array");
+    const size_t n = c.elem.size() / (c.dim + 1);
+    const int ns = n_sig_of(c.dim);
+    c.elemE.assign(stiffness, stiffness + n * ns * ns);
+    c.rho.assign(rho, rho + n);
+    // E~ W^-1 (W = 1 on normal, 2 on shear components) holds the tensor
+    // entries E_ijkl and is symmetric by the major symmetry; it is made
+    // exactly symmetric here
+    auto wt = [&](int k) { return k < c.dim ? 1.0 : 2.0; };
+    for (size_t i = 0; i < n; ++i) {
+      require(std::isfinite(rho[i]) && rho[i] > 0, SDG_EINVAL, "density must be finite and positive");
+      double* E = &c.elemE[i * ns * ns];
+      double scale = 0.0;
+      for (int a = 0; a < ns * ns; ++a) {
+        require(std::isfinite(E[a]), SDG_EINVAL, "non-finite stiffness entry");
+        scale = std::max(scale, std::fabs(E[a]));
+      }
+      for (int a = 0; a < ns; ++a)
+        for (int b = a + 1; b < ns; ++b) {
+          const double x = E[a * ns + b] / wt(b), y = E[b * ns + a] / wt(a);
+          require(std::fabs(x - y) <= 1e-12 * scale, SDG_EINVAL,
+                  "stiffness violates the major symmetry (E~ W^-1 must be symmetric)");
+          const double m = 0.5 * (x + y);
+          E[a * ns + b] = m * wt(b);
+          E[b * ns + a] = m * wt(a);
+        }
+    }
+    // the isotropic parameters are not used with an anisotropic material; the
+    // set-up's own checks take positive placeholders
+    c.lam.assign(n, 1.0);
+    c.mu.assign(n, 1.0);
+    c.aniso = true;
     c.have_mat = true;
     c.assembled = false;
   });
@@ -510,8 +577,9 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
   return guard([&] {
     Ctx& c = ctx_of(ctx);
     require(c.have_mesh && c.have_disc && c.have_mat, SDG_ESTATE, "mesh, discretization and material must be set");
-    require((precisions & (SDG_PREC_F64 | SDG_PREC_F32)) != 0 && (precisions & ~7u) == 0, SDG_EINVAL,
-            "precisions must be a non-empty subset of SDG_PREC_F64 | SDG_PREC_F32 (| SDG_ASSEMBLE_BLOCK_PRECOND)");
+    require((precisions & (SDG_PREC_F64 | SDG_PREC_F32)) != 0 && (precisions & ~15u) == 0, SDG_EINVAL,
+            "precisions must be a non-empty subset of SDG_PREC_F64 | SDG_PREC_F32 (| SDG_ASSEMBLE_BLOCK_PRECOND "
+            "| SDG_ASSEMBLE_PATCH_PRECOND)");
     require(max_rhs >= 1 && max_rhs <= kMaxSystems, SDG_EINVAL, "max_rhs must be in [1, 1024]");
     require(max_rhs == 1 || c.n_mesh == 1, SDG_EUNSUPPORTED, "batched right-hand sides on a mesh batch");
     SDG_HIP(hipSetDevice(c.device));
@@ -524,6 +592,9 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     const int64_t n_vert = (int64_t)(c.xyz.size() / c.dim);
     build_host_setup(hs, c.dim, n_vert, c.xyz.data(), n_elem, c.elem.data(), c.period.empty() ? nullptr : c.period.data(),
                      c.p, c.pg, c.scheme, c.dt, c.lam.data(), c.mu.data(), c.rho.data());
+    hs.face_E.clear();
+    hs.face_Cw.clear();
+    if (c.aniso) set_anisotropic_faces(hs, c.elemE.data());
     const int d = hs.dim, ng = hs.ng, nphi = hs.nphi;
     c.mesh_face_off.assign(c.n_mesh + 1, hs.n_face);
     {
@@ -594,6 +665,47 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
       }
     }
 
+    c.d_P2.free();
+    c.d_P2nbr.free();
+    c.p2_nb = c.p2_slots = 0;
+    if (precisions & SDG_ASSEMBLE_PATCH_PRECOND) {
+      PatchPrecond pp = patch_inverses(hs, op);
+      c.d_P2.alloc(pp.P.size());
+      SDG_HIP(hipMemcpy(c.d_P2.p, pp.P.data(), pp.P.size() * sizeof(float), hipMemcpyHostToDevice));
+      c.d_P2nbr.alloc(pp.nbr.size());
+      SDG_HIP(hipMemcpy(c.d_P2nbr.p, pp.nbr.data(), pp.nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+      c.p2_nb = pp.nb;
+      c.p2_slots = pp.slots;
+    }
+
+    // compressed 3D operator (face-kernel variant 8), kept beside the blocks
+    for (DevBuf<double>* b : {&c.d_cmpC64, &c.d_cmpA, &c.d_cmpB, &c.d_cmpF, &c.d_cmpG}) b->free();
+    c.d_cmpC32.free();
+    c.cmp_bytes_f64 = c.cmp_bytes_f32 = 0;
+    if (hs.dim == 3 && hs.p <= 2) {
+      CompressedOp co;
+      build_compressed(hs, c.elem.data(), co);
+      auto up = [](DevBuf<double>& b, const std::vector<double>& v) {
+        b.alloc(v.size());
+        SDG_HIP(hipMemcpy(b.p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+      };
+      if (precisions & SDG_PREC_F64) up(c.d_cmpC64, co.C);
+      if (precisions & SDG_PREC_F32) {
+        std::vector<float> f(co.C.begin(), co.C.end());
+        c.d_cmpC32.alloc(f.size());
+        SDG_HIP(hipMemcpy(c.d_cmpC32.p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+      }
+      up(c.d_cmpA, co.fa);
+      up(c.d_cmpB, co.eB);
+      up(c.d_cmpF, co.F);
+      up(c.d_cmpG, co.G);
+      // bytes per apply: C of the sides that exist, the face-term coefficients
+      // and the element factors
+      const int64_t nside = 2 * hs.n_face - hs.n_bface;
+      c.cmp_bytes_f64 = nside * (int64_t)co.npsi * co.npsi * 8 + nside * 3 * 8 + hs.n_elem * 9 * 8;
+      c.cmp_bytes_f32 = nside * (int64_t)co.npsi * co.npsi * 4 + nside * 3 * 8 + hs.n_elem * 9 * 8;
+    }
+
     // operator blocks
     c.d_faces.alloc(hs.n_face);
     SDG_HIP(hipMemcpy(c.d_faces.p, hs.faces.data(), hs.n_face * sizeof(FaceRec), hipMemcpyHostToDevice));
@@ -612,6 +724,14 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     }
     c.d_face_lm.alloc(hs.face_lm.size());
     SDG_HIP(hipMemcpy(c.d_face_lm.p, hs.face_lm.data(), hs.face_lm.size() * sizeof(double), hipMemcpyHostToDevice));
+    c.d_face_E.free();
+    c.d_face_Cw.free();
+    if (c.aniso) {
+      c.d_face_E.alloc(hs.face_E.size());
+      SDG_HIP(hipMemcpy(c.d_face_E.p, hs.face_E.data(), hs.face_E.size() * sizeof(double), hipMemcpyHostToDevice));
+      c.d_face_Cw.alloc(hs.face_Cw.size());
+      SDG_HIP(hipMemcpy(c.d_face_Cw.p, hs.face_Cw.data(), hs.face_Cw.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     c.d_elem_w.alloc(hs.elem_w.size());
     SDG_HIP(hipMemcpy(c.d_elem_w.p, hs.elem_w.data(), hs.elem_w.size() * sizeof(double), hipMemcpyHostToDevice));
     c.d_Mref.alloc(hs.Mref.size());
@@ -659,7 +779,10 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     c.d_z.alloc((size_t)c.z_col * R);
     const size_t n = c.n_slab * R;
     const bool multi = max_rhs > 1 || c.n_mesh > 1;
-    c.d_V.alloc(c.scheme == SDG_SCHEME_CN && !multi ? n : (size_t)(kMaxRestart + 1) * n);
+    // Crank-Nicolson single systems run CG, unless the patch preconditioner
+    // (not symmetric) asks for GMRES
+    const bool cg_only = c.scheme == SDG_SCHEME_CN && !multi && !(precisions & SDG_ASSEMBLE_PATCH_PRECOND);
+    c.d_V.alloc(cg_only ? n : (size_t)(kMaxRestart + 1) * n);
     c.d_x.alloc(n);
     c.d_b.alloc(n);
     c.d_r.alloc(n);
@@ -697,7 +820,11 @@ int sdg_set_operator_variant(sdg_ctx* ctx, int variant) {
   return guard([&] {
     Ctx& c = ctx_of(ctx);
     require(c.assembled, SDG_ESTATE, "assemble first");
-    require(variant >= -1 && variant < kNumVariants, SDG_EINVAL, "variant must be -1 (autotune) or 0..7");
+    require(variant >= -1 && variant < kNumVariants, SDG_EINVAL, "variant must be -1 (autotune) or 0..8");
+    require(variant != 8 || compressed_available(c, SDG_PREC_F64) || compressed_available(c, SDG_PREC_F32),
+            SDG_EUNSUPPORTED, "variant 8 needs the compressed operator (3D, p <= 2)");
+    require(!c.aniso || variant < 0 || aniso_variant(variant), SDG_EUNSUPPORTED,
+            "with an anisotropic material only face-kernel variants 3, 4 and 8 apply");
     SDG_HIP(hipSetDevice(c.device));
     c.graphs.clear();
     if (variant < 0) autotune(c);
@@ -710,6 +837,8 @@ int sdg_set_batched_variant(sdg_ctx* ctx, int bvariant) {
     Ctx& c = ctx_of(ctx);
     require(c.assembled, SDG_ESTATE, "assemble first");
     require(bvariant >= 0 && bvariant <= 2, SDG_EINVAL, "batched variant must be 0, 1 or 2");
+    require(!c.aniso || bvariant == 0, SDG_EUNSUPPORTED,
+            "with an anisotropic material batched applies use the column grid (batched variant 0)");
     c.graphs.clear();
     c.bvariant = bvariant;
   });
@@ -744,6 +873,8 @@ int sdg_query(const sdg_ctx* ctx, sdg_sizes* out) {
     const int64_t nblk = 2 * hs.n_face - hs.n_bface;
     out->op_bytes_f64 = nblk * blk * 8;
     out->op_bytes_f32 = nblk * blk * 4;
+    out->cmp_bytes_f64 = c.cmp_bytes_f64;
+    out->cmp_bytes_f32 = c.cmp_bytes_f32;
     out->max_rhs = c.max_rhs;
     out->op_variant = c.variant64;
     out->op_variant_f32 = c.variant32;
@@ -788,6 +919,20 @@ int sdg_apply_velocity_operator(sdg_ctx* ctx, const double* v, double* y, int n_
 
 int sdg_apply_adjoint(sdg_ctx* ctx, const double* w, double* y, int n_rhs, int precision, void* stream) {
   return apply_common(ctx, w, y, n_rhs, precision, stream, true);
+}
+
+int sdg_apply_preconditioner(sdg_ctx* ctx, int kind, const double* x, double* y, int n_rhs, void* stream) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.assembled, SDG_ESTATE, "assemble first");
+    require(x && y, SDG_EINVAL, "null vector");
+    require(x != y, SDG_EINVAL, "x and y must not alias");
+    require(n_rhs >= 1 && n_rhs <= c.max_rhs, SDG_EINVAL, "n_rhs must be in [1, max_rhs of sdg_assemble]");
+    require(kind >= SDG_PRECOND_NONE && kind <= SDG_PRECOND_PATCH, SDG_EINVAL, "unknown preconditioner");
+    SDG_HIP(hipSetDevice(c.device));
+    apply_precond(c, kind, x, y, false, (hipStream_t)stream, n_rhs);
+    SDG_HIP(hipGetLastError());
+  });
 }
 
 int sdg_apply_velocity_operator_noalloc(sdg_ctx* ctx, const double* v, double* y, int n_rhs, int precision,
@@ -883,12 +1028,13 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     require(solver == SDG_SOLVER_CG || solver == SDG_SOLVER_GMRES, SDG_EINVAL, "unknown solver");
     require(!multi || solver == SDG_SOLVER_GMRES, SDG_EUNSUPPORTED,
             "batched, mesh-batch and graph solves use GMRES (SDG_SOLVER_GMRES or AUTO)");
-    require(!graph || prec == SDG_PREC_F64, SDG_EUNSUPPORTED, "graph mode runs the FP64 solve");
+    require(solver != SDG_SOLVER_CG || opts->precond != SDG_PRECOND_PATCH, SDG_EUNSUPPORTED,
+            "the patch preconditioner is not symmetric: use GMRES with it");
     require(solver != SDG_SOLVER_GMRES || c.d_V.n >= (size_t)(kMaxRestart + 1) * c.n_slab * R, SDG_EINVAL,
-            "GMRES workspace is only allocated for the space-time scheme or batched solves");
+            "GMRES workspace is only allocated for the space-time scheme, batched solves or the patch preconditioner");
     const int restart = opts->restart > 0 ? opts->restart : 30;
     require(restart <= kMaxRestart, SDG_EINVAL, "restart must be <= 32");
-    require(opts->precond >= SDG_PRECOND_NONE && opts->precond <= SDG_PRECOND_BLOCK, SDG_EINVAL,
+    require(opts->precond >= SDG_PRECOND_NONE && opts->precond <= SDG_PRECOND_PATCH, SDG_EINVAL,
             "unknown preconditioner");
     SDG_HIP(hipSetDevice(c.device));
     hipStream_t s = (hipStream_t)stream;
@@ -914,17 +1060,34 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
       StepGraphs& G = c.graphs;
       if (!G.stream) SDG_HIP(hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
       hipStream_t gs = G.stream;
-      std::function<void(const double*, double*)> op = [&c, R, gs](const double* in, double* out) {
-        apply_op(c, in, out, SDG_PREC_F64, false, gs, R);
+      // FP64: GMRES on A x = b.  FP32: the FP32 operator inside FP64
+      // iterative refinement, every decision on the device: inner GMRES on
+      // A32 e = d from e = 0, then x += e, d = b - A64 x and the per-system
+      // outer test, which also sets the next inner targets.
+      const bool ir = prec == SDG_PREC_F32;
+      const double inner_tol = opts->inner_rtol > 0 ? opts->inner_rtol : 1e-4;
+      const int max_ref = opts->max_refine > 0 ? opts->max_refine : 10;
+      std::function<void(const double*, double*)> op = [&c, R, gs, prec](const double* in, double* out) {
+        apply_op(c, in, out, prec, false, gs, R);
       };
       std::function<void(const double*, double*)> pre = [&c, R, gs, kc](const double* in, double* out) {
         apply_precond(c, kc.precond, in, out, false, gs, R);
       };
       const std::function<void(const double*, double*)>* pp = kc.precond != SDG_PRECOND_NONE ? &pre : nullptr;
+      double* const kb = ir ? c.d_d.p : c.d_b.p;  // the Krylov system's right-hand side and unknown
+      double* const kx = ir ? c.d_e.p : c.d_x.p;
+      auto outer_residual = [&]() {  // d = b - A64 x, the outer test and the inner targets
+        apply_op(c, c.d_x.p, c.d_t.p, SDG_PREC_F64, false, gs, R);
+        vec_copy(N, c.d_b.p, c.d_d.p, gs);
+        vec_axpby(N, -1.0, c.d_t.p, 1.0, c.d_d.p, gs);
+        multi_refine_check(m, c.d_d.p, kc.rtol, inner_tol, gs);
+        vec_fill(N, 0.0, c.d_e.p, gs);
+      };
       const bool src = amp && c.n_src > 0;
       const bool same = G.head && G.v == v_state && G.sig == sigma_state && G.vslab == v_slab &&
                         G.sslab == sigma_slab && G.R == R && G.precond == kc.precond && G.restart == restart &&
-                        G.rtol == kc.rtol && G.src == src && G.flags == opts->flags;
+                        G.rtol == kc.rtol && G.src == src && G.flags == opts->flags && G.prec == prec &&
+                        (!ir || G.inner_rtol == inner_tol) && G.check_every == kc.check_every;
       if (!same) {
         G.clear();
         auto record = [&](auto&& body) {
@@ -948,15 +1111,40 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
         bool done = false;
         G.head = record([&] {
           step_rhs(c, v_state, sigma_state, R, src, gs, extrap);
-          multi_setup(m, c.d_b.p, c.d_x.p, kc.rtol, gs);
-          multi_cycle(m, c.d_b.p, c.d_x.p, kc, gs, op, pp, c.d_V.p, c.d_r.p, c.d_w.p, c.d_t.p, false, restart, &mv,
-                      &done);
+          if (ir) {
+            multi_outer_setup(m, c.d_b.p, gs);
+            outer_residual();
+          } else {
+            multi_setup(m, c.d_b.p, c.d_x.p, kc.rtol, gs);
+          }
+          if (!kc.delayed)
+            multi_cycle(m, kb, kx, kc, gs, op, pp, c.d_V.p, c.d_r.p, c.d_w.p, c.d_t.p, false, restart, &mv, &done);
         });
-        G.cycle = record([&] {
-          multi_cycle(m, c.d_b.p, c.d_x.p, kc, gs, op, pp, c.d_V.p, c.d_r.p, c.d_w.p, c.d_t.p, false, restart, &mv,
-                      &done);
-        });
-        G.verify = record([&] { multi_residual(m, c.d_b.p, c.d_x.p, gs, op, c.d_r.p); });
+        if (kc.delayed) {
+          // the cycle in parts of check_every steps, polled between parts as
+          // the eager solver polls, and the early end after each part
+          const int ce = std::max(1, std::min(kc.check_every, restart));
+          for (int j0 = 0; j0 < restart; j0 += ce) {
+            const int j1 = std::min(j0 + ce, restart);
+            G.part.push_back(record([&] {
+              multi_cycle_part(m, kb, kx, kc, gs, op, pp, c.d_V.p, c.d_w.p, c.d_t.p, restart, j0, j1, &mv);
+            }));
+            G.part_end.push_back(j1);
+            if (j1 < restart)
+              G.stop.push_back(record([&] { multi_cycle_stop(m, kx, kc, gs, pp, c.d_V.p, c.d_w.p, c.d_t.p, j1); }));
+          }
+        } else {
+          G.cycle = record([&] {
+            multi_cycle(m, kb, kx, kc, gs, op, pp, c.d_V.p, c.d_r.p, c.d_w.p, c.d_t.p, false, restart, &mv, &done);
+          });
+        }
+        G.verify = record([&] { multi_residual(m, kb, kx, gs, op, c.d_r.p); });
+        if (ir) {
+          G.refine = record([&] {
+            vec_axpby(N, 1.0, c.d_e.p, 1.0, c.d_x.p, gs);
+            outer_residual();
+          });
+        }
         G.tail = record([&] { step_backsub(c, v_state, sigma_state, v_slab, sigma_slab, R, gs, extrap); });
         G.v = v_state;
         G.sig = sigma_state;
@@ -968,29 +1156,63 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
         G.rtol = kc.rtol;
         G.src = src;
         G.flags = opts->flags;
+        G.prec = prec;
+        G.inner_rtol = inner_tol;
+        G.check_every = kc.check_every;
       }
       SDG_HIP(hipStreamSynchronize(s));
       if (src)
         SDG_HIP(hipMemcpyAsync(c.d_src_amp.p, amp, c.n_src * c.hs.ng * sizeof(double), hipMemcpyHostToDevice, gs));
       SDG_HIP(hipGraphLaunch(G.head, gs));
-      res.iters = restart;
-      res.matvecs = restart + 1;
+      res.iters = kc.delayed ? 0 : restart;
+      res.matvecs = (kc.delayed ? 0 : restart + 1) + (ir ? 1 : 0);
+      // one restart cycle: whole, or in parts with a poll after each
+      auto run_cycle = [&]() {
+        if (!kc.delayed) {
+          SDG_HIP(hipGraphLaunch(G.cycle, gs));
+          res.iters += restart;
+          res.matvecs += restart + 1;
+          return;
+        }
+        int j0 = 0;
+        for (size_t p = 0; p < G.part.size(); ++p) {
+          SDG_HIP(hipGraphLaunch(G.part[p], gs));
+          res.iters += G.part_end[p] - j0;
+          res.matvecs += G.part_end[p] - j0 + (p == 0 ? 1 : 0);
+          j0 = G.part_end[p];
+          if (p + 1 < G.part.size() && multi_nactive(m, gs) == 0) {
+            SDG_HIP(hipGraphLaunch(G.stop[p], gs));
+            return;
+          }
+        }
+      };
+      if (kc.delayed) run_cycle();
       for (;;) {
         if (multi_nactive(m, gs) == 0) {
           SDG_HIP(hipGraphLaunch(G.verify, gs));
           ++res.matvecs;
           if (multi_nactive(m, gs) == 0) {
-            res.converged = true;
-            break;
+            if (!ir) {
+              res.converged = true;
+              break;
+            }
+            // inner solve done: apply the correction and test the outer system
+            SDG_HIP(hipGraphLaunch(G.refine, gs));
+            ++res.matvecs;
+            ++res.refinements;
+            if (multi_nouter(m, gs) == 0) {
+              res.converged = true;
+              break;
+            }
+            if (res.refinements >= max_ref) break;
           }
         }
         if (res.iters >= kc.max_iter) break;
-        SDG_HIP(hipGraphLaunch(G.cycle, gs));
-        res.iters += restart;
-        res.matvecs += restart + 1;
+        run_cycle();
       }
       SDG_HIP(hipGraphLaunch(G.tail, gs));
-      multi_result(m, gs, res);
+      if (ir) multi_outer_result(m, gs, res);
+      else multi_result(m, gs, res);
       SDG_HIP(hipStreamSynchronize(gs));
       if (!res.converged) throw Error(SDG_ENOCONV, "Krylov solver did not reach rtol within max_iter");
       return;
@@ -1085,6 +1307,7 @@ int sdg_adjoint_step(sdg_ctx* ctx, const double* v_old, const double* v_slab, do
     require(opts->rtol > 0 && opts->max_iter > 0, SDG_EINVAL, "rtol and max_iter must be positive");
     require(opts->precision == 0 || opts->precision == SDG_PREC_F64, SDG_EUNSUPPORTED,
             "the adjoint step runs in FP64");
+    require(!c.aniso, SDG_EUNSUPPORTED, "the adjoint step takes an isotropic material");
     check_prec(c, SDG_PREC_F64);
     int solver = opts->solver;
     if (solver == SDG_SOLVER_AUTO) solver = c.scheme == SDG_SCHEME_CN ? SDG_SOLVER_CG : SDG_SOLVER_GMRES;

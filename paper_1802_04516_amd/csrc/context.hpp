@@ -81,6 +81,10 @@ struct MultiSys {
   DevBuf<SysScalars> d_ss;
   DevBuf<double> d_partials;
   DevBuf<int> d_nactive;
+  // iterative refinement driven on the device: outer ||b_s|| (S values),
+  // then the last outer relative residual per system (S values)
+  DevBuf<double> d_outer;
+  DevBuf<int> d_nouter;  // systems whose outer residual is above rtol
   int* h_pinned = nullptr;
   void build(const std::vector<int64_t>& offsets);
   void read_scalars(std::vector<SysScalars>& out, hipStream_t s) const;
@@ -93,14 +97,26 @@ struct MultiSys {
 // Step recorded in HIP graphs, with the arguments it was recorded for.
 struct StepGraphs {
   hipGraphExec_t head = nullptr, cycle = nullptr, verify = nullptr, tail = nullptr;
+  hipGraphExec_t refine = nullptr;  // FP32 inner solves: x += e, new d, outer test
+  // delayed GMRES: the restart cycle in parts between polls, and the early
+  // ends of a cycle after each part but the last
+  std::vector<hipGraphExec_t> part, stop;
+  std::vector<int> part_end;
+  int prec = 0;
+  double inner_rtol = 0.0;
   hipStream_t stream = nullptr;
   const void *v = nullptr, *sig = nullptr, *vslab = nullptr, *sslab = nullptr;
   int R = 0, precond = 0, restart = 0, max_iter = 0, check_every = 0, flags = 0;
   double rtol = 0.0;
   bool src = false;
   void clear() {
-    for (hipGraphExec_t* g : {&head, &cycle, &verify, &tail})
+    for (hipGraphExec_t* g : {&head, &cycle, &verify, &tail, &refine})
       if (*g) { (void)hipGraphExecDestroy(*g); *g = nullptr; }
+    for (hipGraphExec_t g : part) (void)hipGraphExecDestroy(g);
+    for (hipGraphExec_t g : stop) (void)hipGraphExecDestroy(g);
+    part.clear();
+    stop.clear();
+    part_end.clear();
   }
   ~StepGraphs() {
     clear();
@@ -119,6 +135,9 @@ struct Ctx {
   int p = 0, pg = 0, scheme = 0;
   double dt = 0.0;
   std::vector<double> lam, mu, rho;
+  // anisotropic material: per-element Voigt stiffness (n_elem * n_sigma^2)
+  bool aniso = false;
+  std::vector<double> elemE;
   unsigned precisions = 0;
   int max_rhs = 1;
 
@@ -130,10 +149,11 @@ struct Ctx {
   DevBuf<double> d_Dt64;
   DevBuf<float> d_Dt32;
   DevBuf<double> d_face_lm, d_elem_w, d_Mref;
+  DevBuf<double> d_face_E, d_face_Cw;  // anisotropic dual material (empty when isotropic)
   DevBuf<double> d_z;  // element face slots
   Coefs op{}, adj{};   // operator and its transpose
   int variant64 = 0, variant32 = 0;   // face-kernel variant per precision (autotuned)
-  double tune_us[2][8] = {{0}};  // measured apply times [prec][variant]
+  double tune_us[2][kNumVariants] = {{0}};  // measured apply times [prec][variant]
   int bvariant = 0;              // batched FP64 apply: 0 column grid, 1/2 matrix-core kernel
   double tune_b_us[3] = {0};     // measured batched applies (max_rhs columns) per bvariant
   // preconditioners: mass block-Jacobi (reference mass inverse, 1/(rho|J|),
@@ -144,6 +164,16 @@ struct Ctx {
   DevBuf<float> d_Pblk;                 // explicit inverses (one time node), packed upper triangles
   DevBuf<float> d_Pq, d_Pb;             // factored inverses (several time nodes)
   bool pblk_factored = false;
+  // patch preconditioner (Appendix A, eqs. APPRE1-APPRE2): first block rows
+  // of the stencil inverses [elem][slot][q][r] and the stencils [elem][slot]
+  DevBuf<float> d_P2;
+  DevBuf<int32_t> d_P2nbr;
+  int p2_nb = 0, p2_slots = 0;
+  // compressed 3D operator (variant 8): per face side C, face-term
+  // coefficients, per element |J| J^-1, reference tables
+  DevBuf<double> d_cmpC64, d_cmpA, d_cmpB, d_cmpF, d_cmpG;
+  DevBuf<float> d_cmpC32;
+  int64_t cmp_bytes_f64 = 0, cmp_bytes_f32 = 0;
 
   // solver workspace
   DevBuf<double> d_V;                   // (restart+1) * n_slab   (GMRES) or 4 * n_slab (CG)
@@ -248,8 +278,29 @@ int multi_cycle(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hip
                 const std::function<void(const double*, double*)>& op,
                 const std::function<void(const double*, double*)>* pre, double* V, double* r, double* w, double* t,
                 bool poll, int max_steps, int* matvecs, bool* all_converged);
+//   multi_cycle_part / multi_cycle_stop  the delayed cycle split at its
+//                   polling points (graph mode records each part once)
+void multi_cycle_part(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
+                      const std::function<void(const double*, double*)>& op,
+                      const std::function<void(const double*, double*)>* pre, double* V, double* w, double* t,
+                      int steps, int j0, int j1, int* matvecs);
+void multi_cycle_stop(MultiSys& m, double* x, const KrylovCfg& k, hipStream_t s,
+                      const std::function<void(const double*, double*)>* pre, double* V, double* w, double* t,
+                      int j);
 int multi_nactive(MultiSys& m, hipStream_t s);
 void multi_result(MultiSys& m, hipStream_t s, SolveResult& res);
+// Iterative refinement with every decision on the device (graph-capturable):
+//   multi_outer_setup   per-system ||b|| of the outer system;
+//   multi_refine_check  from d = b - A x: per-system outer relative residual,
+//                       the count of systems above rtol, and the inner
+//                       targets (inner_rtol ||d_s||; none for converged
+//                       systems, which then take no inner step);
+//   multi_nouter        that count (host read, synchronises);
+//   multi_outer_result  worst outer relative residual and largest ||b_s||.
+void multi_outer_setup(MultiSys& m, const double* b, hipStream_t s);
+void multi_refine_check(MultiSys& m, const double* d, double rtol, double inner_rtol, hipStream_t s);
+int multi_nouter(MultiSys& m, hipStream_t s);
+void multi_outer_result(MultiSys& m, hipStream_t s, SolveResult& res);
 // Largest ||r_s|| / ||b_s|| over the systems of m (bnorm_max: largest ||b_s||).
 double multi_rel_residual(MultiSys& m, const double* b, const double* r, hipStream_t s, double* bnorm_max);
 MultiSys& systems(Ctx& c, int ncols);
@@ -266,6 +317,8 @@ void launch_block_apply(int64_t n_elem, int nv, const float* P, const double* x,
                         hipStream_t s, int ncols = 1, int64_t cstride = 0);
 void launch_block_apply_fact(int64_t n_elem, int ng, int ns, const float* Q, const float* B, const double* x,
                              double* y, bool transpose, hipStream_t s, int ncols = 1, int64_t cstride = 0);
+void launch_patch_apply(int64_t n_elem, int nb, int slots, const float* P, const int32_t* nbr, const double* x,
+                        double* y, hipStream_t s, int ncols, int64_t cstride);
 
 // step pieces
 void launch_broadcast_time(int64_t n_elem, int ng, int nvs, const double* state, double* slab,

@@ -90,7 +90,8 @@ __device__ inline double wsum(double v) {
 template <int D>
 __global__ void k_energy(int64_t n_elem, int64_t n_face, int nphi, int npsi, const double* __restrict__ Mref,
                          const double* __restrict__ ew, const double* __restrict__ flm,
-                         const double* __restrict__ v, const double* __restrict__ sig, double* partials) {
+                         const double* __restrict__ fcw, const double* __restrict__ v,
+                         const double* __restrict__ sig, double* partials) {
   constexpr int NS = D * (D + 1) / 2;
   __shared__ double sh[16];
   double acc = 0.0;
@@ -114,7 +115,15 @@ __global__ void k_energy(int64_t n_elem, int64_t n_face, int nphi, int npsi, con
       for (int m = 0; m < npsi; ++m) {
         double s[NS];
         for (int c = 0; c < NS; ++c) s[c] = sb[c * npsi + m];
-        if (D == 2) {
+        if (fcw != nullptr) {
+          // anisotropic: s^T (W E~^-1) s with the face's compliance form
+          const double* C = fcw + j * NS * NS;
+          for (int a = 0; a < NS; ++a) {
+            double t = 0.0;
+            for (int b = 0; b < NS; ++b) t += C[a * NS + b] * s[b];
+            q += s[a] * t;
+          }
+        } else if (D == 2) {
           const double den = 4.0 * mu * (lam + mu);
           const double a = (lam + 2.0 * mu) / den, b = -lam / den;
           q += a * (s[0] * s[0] + s[1] * s[1]) + 2.0 * b * s[0] * s[1] + s[2] * s[2] / mu;
@@ -296,10 +305,12 @@ void launch_energy(Ctx& c, const double* v, const double* sig, double* out_dev, 
   const double* vv = v + e0 * hs.dim * hs.nphi;
   const double* ss = sig + f0 * hs.nsig * hs.npsi;
   if (hs.dim == 2)
-    k_energy<2><<<g, kT, 0, s>>>(ne, nf, hs.nphi, hs.npsi, c.d_Mref.p, c.d_elem_w.p + e0, c.d_face_lm.p + 2 * f0, vv,
+    k_energy<2><<<g, kT, 0, s>>>(ne, nf, hs.nphi, hs.npsi, c.d_Mref.p, c.d_elem_w.p + e0, c.d_face_lm.p + 2 * f0,
+                                 c.d_face_Cw.p ? c.d_face_Cw.p + f0 * hs.nsig * hs.nsig : nullptr, vv,
                                  ss, c.d_partials.p);
   else
-    k_energy<3><<<g, kT, 0, s>>>(ne, nf, hs.nphi, hs.npsi, c.d_Mref.p, c.d_elem_w.p + e0, c.d_face_lm.p + 2 * f0, vv,
+    k_energy<3><<<g, kT, 0, s>>>(ne, nf, hs.nphi, hs.npsi, c.d_Mref.p, c.d_elem_w.p + e0, c.d_face_lm.p + 2 * f0,
+                                 c.d_face_Cw.p ? c.d_face_Cw.p + f0 * hs.nsig * hs.nsig : nullptr, vv,
                                  ss, c.d_partials.p);
   SDG_HIP(hipGetLastError());
   k_energy_fin<<<1, 64, 0, s>>>(c.d_partials.p, (int)g, out_dev);

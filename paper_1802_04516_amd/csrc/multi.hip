@@ -293,6 +293,37 @@ __global__ void km_cycle_start(int S, SysScalars* ss, int* nactive) {
   if (threadIdx.x == 0) *nactive = n;
 }
 
+// Outer ||b_s|| of iterative refinement from ss.dot = b.b.
+__global__ void km_outer_bnorm(int S, const SysScalars* ss, double* outer) {
+  const int s = threadIdx.x;
+  if (s < S) outer[s] = sqrt(ss[s].dot);
+}
+
+// Outer test of iterative refinement from ss.dot = d.d (d = b - A x): the
+// relative residual per system (outer[S + s]), the number of systems above
+// rtol, and the targets of the next inner solve A e = d: inner_rtol ||d_s||,
+// or +inf for a converged system, which km_cycle_start then leaves inactive
+// (its correction stays zero).
+__global__ void km_refine_check(int S, SysScalars* ss, double* outer, double rtol, double inner_rtol,
+                                int* nouter) {
+  __shared__ int sh[16];
+  const int s = threadIdx.x;
+  int act = 0;
+  if (s < S) {
+    SysScalars& q = ss[s];
+    const double dn = sqrt(q.dot), bn = outer[s];
+    const double rr = bn > 0.0 ? dn / bn : dn;
+    outer[S + s] = rr;
+    act = rr <= rtol ? 0 : 1;   // a NaN residual stays active (and is reported)
+    q.bnorm = dn;
+    q.tol_abs = act ? inner_rtol * dn : INFINITY;
+    q.active = 1;
+    q.k = 0;
+  }
+  const int n = block_count(act, sh);
+  if (threadIdx.x == 0) *nouter = n;
+}
+
 // bnorm and tolerance per system from ss.dot = b.b
 __global__ void km_set_tol(int S, SysScalars* ss, double rtol) {
   const int s = threadIdx.x;
@@ -665,6 +696,8 @@ void MultiSys::build(const std::vector<int64_t>& offsets) {
   SDG_HIP(hipMemset(d_ss.p, 0, S * sizeof(SysScalars)));
   d_partials.alloc((size_t)(2 * kMaxRestart + 2) * n_blocks);
   d_nactive.alloc(1);
+  d_outer.alloc(2 * (size_t)S);
+  d_nouter.alloc(1);
   if (!h_pinned) SDG_HIP(hipHostMalloc((void**)&h_pinned, 16 * sizeof(int), hipHostMallocDefault));
 }
 
@@ -773,6 +806,63 @@ static int multi_cycle_delayed(MultiSys& m, const double* b, double* x, const Kr
   return j;
 }
 
+// Part of one delayed-GMRES restart cycle of `steps` Arnoldi steps, for
+// recording in graphs: with j0 == 0 the cycle's start (r = b - A x into V[0]),
+// then steps [j0, j1); with j1 == steps the cycle's end (last Hessenberg
+// column, triangular solve, correction).  The steps are those of
+// multi_cycle_delayed, split where it polls.
+void multi_cycle_part(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
+                      const std::function<void(const double*, double*)>& op,
+                      const std::function<void(const double*, double*)>* pre, double* V, double* w, double* t,
+                      int steps, int j0, int j1, int* matvecs) {
+  require(k.delayed && 0 <= j0 && j0 < j1 && j1 <= steps && steps <= k.restart, SDG_EINVAL, "bad cycle part");
+  const int64_t n = m.n_total;
+  const BlockMap bm = map_of(m);
+  if (j0 == 0) {
+    multi_residual(m, b, x, s, op, V);
+    ++*matvecs;
+  }
+  for (int j = j0; j < j1; ++j) {
+    double* vj = V + (size_t)j * n;
+    if (pre) {
+      (*pre)(vj, t);
+      op(t, w);
+    } else {
+      op(vj, w);
+    }
+    ++*matvecs;
+    const bool last = j + 1 == steps;
+    launch_dm(Dm::Multidot, j, m, bm, s, V, w);
+    launch_dm(Dm::Fin, j, m, bm, s, V, w);
+    launch_dm(last ? Dm::UpdateDots : Dm::Update, j, m, bm, s, V, w);
+  }
+  if (j1 == steps) {
+    launch_dm(Dm::FinU, steps, m, bm, s, V, nullptr);
+    multi_cycle_stop(m, x, k, s, pre, V, w, t, steps);
+  }
+}
+
+// End of a cycle after its step j: triangular solve and correction (every
+// system's column j-1 is complete; after an early stop the converged systems
+// need no further column).
+void multi_cycle_stop(MultiSys& m, double* x, const KrylovCfg& k, hipStream_t s,
+                      const std::function<void(const double*, double*)>* pre, double* V, double* w, double* t,
+                      int j) {
+  (void)k;
+  const int64_t n = m.n_total;
+  const BlockMap bm = map_of(m);
+  km_trisolve<<<(unsigned)((m.S * 64 + 255) / 256), 256, 0, s>>>(m.S, m.d_ss.p);
+  SDG_HIP(hipGetLastError());
+  if (pre) {
+    vec_fill(n, 0.0, t, s);
+    launch_m(Op::Update, j, bm, s, n, V, t, m.d_ss.p, nullptr);
+    (*pre)(t, w);
+    vec_axpby(n, 1.0, w, 1.0, x, s);
+  } else {
+    launch_m(Op::Update, j, bm, s, n, V, x, m.d_ss.p, nullptr);
+  }
+}
+
 int multi_cycle(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
                 const std::function<void(const double*, double*)>& op,
                 const std::function<void(const double*, double*)>* pre, double* V, double* r, double* w, double* t,
@@ -833,6 +923,34 @@ int multi_cycle(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hip
 }
 
 int multi_nactive(MultiSys& m, hipStream_t s) { return read_int(m.d_nactive.p, m.h_pinned, s); }
+
+void multi_outer_setup(MultiSys& m, const double* b, hipStream_t s) {
+  seg_norm2(m, b, s);
+  km_outer_bnorm<<<1, sys_threads(m.S), 0, s>>>(m.S, m.d_ss.p, m.d_outer.p);
+  SDG_HIP(hipGetLastError());
+}
+
+void multi_refine_check(MultiSys& m, const double* d, double rtol, double inner_rtol, hipStream_t s) {
+  seg_norm2(m, d, s);
+  km_refine_check<<<1, sys_threads(m.S), 0, s>>>(m.S, m.d_ss.p, m.d_outer.p, rtol, inner_rtol, m.d_nouter.p);
+  SDG_HIP(hipGetLastError());
+}
+
+int multi_nouter(MultiSys& m, hipStream_t s) { return read_int(m.d_nouter.p, m.h_pinned + 1, s); }
+
+void multi_outer_result(MultiSys& m, hipStream_t s, SolveResult& res) {
+  std::vector<double> h(2 * (size_t)m.S);
+  SDG_HIP(hipMemcpyAsync(h.data(), m.d_outer.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  SDG_HIP(hipStreamSynchronize(s));
+  double worst = 0.0, bmax = 0.0;
+  for (int q = 0; q < m.S; ++q) {
+    bmax = std::max(bmax, h[q]);
+    worst = std::isfinite(h[m.S + q]) ? std::max(worst, h[m.S + q]) : h[m.S + q];
+    require(std::isfinite(worst), SDG_ENONFINITE, "non-finite residual");
+  }
+  res.rel_res = worst;
+  res.bnorm = bmax;
+}
 
 void multi_result(MultiSys& m, hipStream_t s, SolveResult& res) {
   std::vector<SysScalars> h;

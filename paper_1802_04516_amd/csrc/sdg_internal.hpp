@@ -34,7 +34,7 @@ inline void require(bool ok, int code, const std::string& msg) {
 
 // ---------------------------------------------------------------- sizes
 
-constexpr int kNumVariants = 8;
+constexpr int kNumVariants = 9;
 constexpr int kMaxGamma = 4;   // N_gamma <= 4 (p_gamma <= 3)
 constexpr int kMaxRhs = 64;
 
@@ -62,6 +62,10 @@ struct HostSetup {
   std::vector<int32_t> elem_face;       // n_elem*(dim+1): face id of local face f
   std::vector<double> Dt;               // n_face*2*nphi*dim*npsi, canonical dual basis
   std::vector<double> face_lm;          // n_face*2: lambda_j, mu_j
+  // anisotropic material (empty when isotropic): the Voigt stiffness of the
+  // dual element, n_face * n_sigma^2 (row-major), and its compliance form
+  // W E^-1 (W = 1 on normal, 2 on shear components) for the energy
+  std::vector<double> face_E, face_Cw;
   std::vector<double> face_wt;          // n_face*2: |T_{left,j}|/|R_j|, |T_{right,j}|/|R_j| (1, 0 on the boundary)
   std::vector<double> elem_w;           // n_elem: rho_i |det J_i|
   std::vector<double> elem_detJ;        // n_elem
@@ -87,6 +91,29 @@ int64_t locate_point(const HostSetup& hs, const double* x, int64_t e_begin = 0, 
 // Canonical dual basis functions of face j at n points x (n*dim) -> out (n*npsi).
 void eval_dual_canonical(const HostSetup& hs, const int64_t* elem, int64_t j, int64_t n,
                          const double* x, double* out);
+
+// Compressed 3D operator: each face side's block of eq. (MD_3) as
+//   Dt[k][l][m] = sum_m' C[m][m'] (a_l F_f[k][m'] - sum_a B[a][l] G_f[k][a][m'])
+// with reference tables F_f, G_f per local face f, the change of basis C of
+// the side (N_psi x N_psi), the face-term coefficients a (3 per side, zero on
+// free-surface faces) and B = |J| J^-1 per element.
+struct CompressedOp {
+  int npsi = 0;
+  std::vector<double> C;   // [face][side][m][m'] (zero for the missing side)
+  std::vector<double> fa;  // [face][side][l]
+  std::vector<double> eB;  // [elem][a][l]
+  std::vector<double> F;   // [f][k][m']
+  std::vector<double> G;   // [f][k][a][m']
+  std::vector<double> face_area_ref;  // areas of the reference faces
+};
+void build_compressed(const HostSetup& hs, const int64_t* elem, CompressedOp& out);
+
+// Anisotropic dual material: E_j = (|T_{l,j}| E_l + |T_{r,j}| E_r) / |R_j|
+// from per-element Voigt matrices E~ (n_elem * n_sigma^2, tensor shear
+// strains, E~ W^-1 symmetric) and the volume fractions of hs.face_wt; fills
+// hs.face_E (E~_j) and hs.face_Cw (the energy's compliance W E~_j^-1).
+// SDG_EINVAL if some E~_j W^-1 is not positive definite.
+void set_anisotropic_faces(HostSetup& hs, const double* E);
 
 // L2 projection of initial data (the state at t^{0,-}) onto the velocity
 // space (which = 0, per element) or the dual space (which = 1, per face, in
@@ -121,6 +148,7 @@ struct OpArgs {
   const FaceRec* faces;
   const void* Dt;          // double or float blocks
   const double* face_lm;
+  const double* face_E;    // anisotropic Voigt stiffness per face (n_sigma^2), or null (isotropic)
   const double* elem_w;
   const double* v;         // [elem][ng_in][d][nphi] (ng_in = NG, or 1 when v_spatial)
   const double* sig_in;    // [face][nsig][npsi] or null
@@ -143,7 +171,8 @@ struct OpArgs {
                            // 3 = column-parallel, persistent and pipelined, 4 = column-parallel,
                            // 5 = column-parallel reading blocks from HBM into registers,
                            // 6 = the same with the scatter summed across the face's lanes,
-                           // 7 = one face per wavefront on the FP64 matrix cores
+                           // 7 = one face per wavefront on the FP64 matrix cores,
+                           // 8 = compressed 3D operator (blocks rebuilt from factors)
   // Several independent columns (right-hand sides) of the same mesh: the
   // launch grid's y index is the column and every per-column array is offset
   // by column * its stride (0 = shared by all columns).
@@ -154,6 +183,15 @@ struct OpArgs {
                            // 1, 2 = matrix-core kernel with 8 or 16 columns per workgroup
   int64_t cs_v, cs_y, cs_z, cs_sig_in, cs_s_out, cs_s_end, cs_y_add;
   Coefs c;
+  // compressed 3D operator (variant 8): per face side C [face][side][m][m']
+  // (double or float as Dt), face-term coefficients [face][side][3], per
+  // element B = |J| J^-1 [elem][3][3], reference tables F [4][k][m'] and
+  // G [4][k][a][m']; cmpC == nullptr when not assembled
+  const void* cmpC = nullptr;
+  const double* cmpA = nullptr;
+  const double* cmpB = nullptr;
+  const double* cmpF = nullptr;
+  const double* cmpG = nullptr;
 };
 
 // Launch the face kernel and/or the element kernel for (dim, p, NG).
@@ -196,5 +234,17 @@ struct BlockPrecond {
   std::vector<float> P, Q, B;
 };
 BlockPrecond block_inverses(const HostSetup& hs, const Coefs& op);
+
+// Patch preconditioner (Appendix A, eqs. APPRE1-APPRE2): the first block row
+// of the inverse of the velocity operator restricted to each element and its
+// face neighbours, FP32, P[i][e][q][r] (nb = N_gamma d N_phi rows r and
+// columns q per stencil slot e < slots = d + 2), and the stencil's element
+// indices nbr[i][e] (slot 0 = i, -1 = no neighbour).
+struct PatchPrecond {
+  int nb = 0, slots = 0;
+  std::vector<float> P;
+  std::vector<int32_t> nbr;
+};
+PatchPrecond patch_inverses(const HostSetup& hs, const Coefs& op);
 
 }  // namespace sdg

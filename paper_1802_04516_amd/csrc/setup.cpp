@@ -801,6 +801,171 @@ void eval_dual_canonical(const HostSetup& hs, const int64_t* elem, int64_t j, in
   for (int64_t q = 0; q < n; ++q) db.canonical(x + q * hs.dim, out + q * hs.npsi);
 }
 
+// ---------------------------------------------------------------- compressed 3D operator
+
+// In 3D the dual functions are polynomials of degree p in physical
+// coordinates (Section 3), so on the sub-simplex T_{i,j} each one is a
+// polynomial of degree p in the reference coordinates xi of element i.  With
+// a basis mu^(f) of P_p orthonormal over the reference sub-simplex T_f^ref
+// (reference face f and the reference barycentre; f = local face of j in i):
+//   psi_m(x(xi)) = sum_m' C_{i,j}[m][m'] mu^(f)_m'(xi),
+// and the block of eq. (MD_3) factors into reference tables and a little
+// geometry:
+//   Dt[k][l][m] = sum_m' C[m][m'] (a_l F_f[k][m'] - sum_a B[a][l] G_f[k][a][m']),
+//   F_f[k][m']    = int_{face f} phi_k mu_m' dS_ref,
+//   G_f[k][a][m'] = int_{T_f^ref} d_{xi_a} phi_k mu_m' dxi,
+//   a_l = (+1 left, -1 right) |Gamma_j| / |face f| n_l (0 on a free-surface face),
+//   B[a][l] = |J_i| (J_i^-1)[a][l].
+namespace {
+
+// reference tetrahedron and its local face f (the face opposite vertex f)
+const double kRefTet[12] = {0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0, 1};
+
+void ref_sub_simplex(int f, double* T) {  // face f's three vertices, then the barycentre
+  int q = 0;
+  for (int a = 0; a < 4; ++a) {
+    if (a == f) continue;
+    for (int c = 0; c < 3; ++c) T[q * 3 + c] = kRefTet[a * 3 + c];
+    ++q;
+  }
+  for (int c = 0; c < 3; ++c) T[9 + c] = 0.25;
+}
+
+// Orthonormal basis mu^(f) of P_p over T_f^ref: Legendre products (ordered
+// as the 3D dual sequence) times Li.
+struct RefDual {
+  DualBasis raw{3, 1};
+  std::vector<double> Li;
+  explicit RefDual(int p, int f) : raw(3, p) {
+    // Legendre products in coordinates centred on T_f^ref and scaled by its
+    // size, for a well-conditioned orthonormalisation
+    double T[12];
+    ref_sub_simplex(f, T);
+    double h = 0.0;
+    for (int c = 0; c < 3; ++c) raw.origin[c] = 0.25 * (T[c] + T[3 + c] + T[6 + c] + T[9 + c]);
+    for (int a = 0; a < 4; ++a) {
+      double sq = 0.0;
+      for (int c = 0; c < 3; ++c) sq += (T[a * 3 + c] - raw.origin[c]) * (T[a * 3 + c] - raw.origin[c]);
+      h = std::max(h, std::sqrt(sq));
+    }
+    for (int k = 0; k < 9; ++k) raw.Ainv[k] = (k % 4 == 0) ? 1.0 / h : 0.0;
+    Rule r = simplex_rule(T, 3, 3, 2 * p);
+    std::vector<double> A, v(raw.n);
+    for (int q = 0; q < r.n(); ++q) {
+      raw.raw(&r.x[q * 3], v.data());
+      const double sw = std::sqrt(r.w[q]);
+      for (int a = 0; a < raw.n; ++a) A.push_back(sw * v[a]);
+    }
+    Li = orthonormaliser(std::move(A), r.n(), raw.n);
+  }
+  void eval(const double* xi, double* out) const {
+    double rv[64];
+    raw.raw(xi, rv);
+    for (int i = 0; i < raw.n; ++i) {
+      double s = 0.0;
+      for (int k = 0; k <= i; ++k) s += Li[i * raw.n + k] * rv[k];
+      out[i] = s;
+    }
+  }
+};
+
+}  // namespace
+
+void build_compressed(const HostSetup& hs, const int64_t* elem, CompressedOp& out) {
+  require(hs.dim == 3, SDG_EUNSUPPORTED, "the compressed operator is built for tetrahedra");
+  const int p = hs.p, nphi = hs.nphi, npsi = hs.npsi;
+  out.npsi = npsi;
+  VelBasis vb(3, p);
+  std::vector<RefDual> mu;
+  for (int f = 0; f < 4; ++f) mu.emplace_back(p, f);
+  // reference tables
+  out.F.assign((size_t)4 * nphi * npsi, 0.0);
+  out.G.assign((size_t)4 * nphi * 3 * npsi, 0.0);
+  out.face_area_ref.assign(4, 0.0);
+  std::vector<double> phi(nphi), gphi(nphi * 3), m(npsi);
+  for (int f = 0; f < 4; ++f) {
+    double T[12];
+    ref_sub_simplex(f, T);
+    Rule rv = simplex_rule(T, 3, 3, std::max(p - 1, 0) + p);
+    for (int q = 0; q < rv.n(); ++q) {
+      vb.eval(&rv.x[q * 3], phi.data(), gphi.data());
+      mu[f].eval(&rv.x[q * 3], m.data());
+      for (int k = 0; k < nphi; ++k)
+        for (int a = 0; a < 3; ++a)
+          for (int mm = 0; mm < npsi; ++mm)
+            out.G[(((size_t)f * nphi + k) * 3 + a) * npsi + mm] += rv.w[q] * gphi[k * 3 + a] * m[mm];
+    }
+    Rule rf = simplex_rule(T, 2, 3, 2 * p);
+    for (int q = 0; q < rf.n(); ++q) {
+      vb.eval(&rf.x[q * 3], phi.data(), nullptr);
+      mu[f].eval(&rf.x[q * 3], m.data());
+      out.face_area_ref[f] += rf.w[q];
+      for (int k = 0; k < nphi; ++k)
+        for (int mm = 0; mm < npsi; ++mm)
+          out.F[((size_t)f * nphi + k) * npsi + mm] += rf.w[q] * phi[k] * m[mm];
+    }
+  }
+  // per element: B = |J| J^-1
+  out.eB.assign((size_t)hs.n_elem * 9, 0.0);
+  parallel_for(hs.n_elem, [&](int64_t e) {
+    double Jinv[9];
+    const double det = det_and_inverse(&hs.elem_xyz[e * 12], 3, Jinv);
+    for (int k = 0; k < 9; ++k) out.eB[e * 9 + k] = std::fabs(det) * Jinv[k];
+  });
+  // per face and side: C and the face-term coefficients
+  out.C.assign((size_t)hs.n_face * 2 * npsi * npsi, 0.0);
+  out.fa.assign((size_t)hs.n_face * 2 * 3, 0.0);
+  int err_code = 0;
+  std::string err_msg;
+  std::mutex err_mu;
+  parallel_for(hs.n_face, [&](int64_t j) {
+    try {
+      FaceGeom fg;
+      face_geometry(hs, elem, j, fg);
+      DualBasis db(3, p);
+      double vol[2];
+      build_dual(hs, j, fg, db, vol);
+      const FaceRec& fr = hs.faces[j];
+      const bool interior = fr.right >= 0;
+      // |Gamma_j| from the face vertices
+      const double t1[3] = {fg.X[3] - fg.X[0], fg.X[4] - fg.X[1], fg.X[5] - fg.X[2]};
+      const double t2[3] = {fg.X[6] - fg.X[0], fg.X[7] - fg.X[1], fg.X[8] - fg.X[2]};
+      const double cx = t1[1] * t2[2] - t1[2] * t2[1], cy = t1[2] * t2[0] - t1[0] * t2[2],
+                   cz = t1[0] * t2[1] - t1[1] * t2[0];
+      const double area = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+      std::vector<double> psi(npsi), mv(npsi);
+      for (int s = 0; s < (interior ? 2 : 1); ++s) {
+        const double* Ve = s == 0 ? fg.Vl : fg.Vr;
+        const int f = s == 0 ? fr.lf : fr.rf;
+        double T[12];
+        ref_sub_simplex(f, T);
+        Rule r = simplex_rule(T, 3, 3, 2 * p);
+        double* Co = &out.C[((size_t)j * 2 + s) * npsi * npsi];
+        for (int q = 0; q < r.n(); ++q) {
+          const double* xi = &r.x[q * 3];
+          double x[3];
+          for (int c = 0; c < 3; ++c) {
+            x[c] = Ve[c];
+            for (int a = 0; a < 3; ++a) x[c] += (Ve[(a + 1) * 3 + c] - Ve[c]) * xi[a];
+          }
+          db.canonical(x, psi.data());
+          mu[f].eval(xi, mv.data());
+          for (int a = 0; a < npsi; ++a)
+            for (int b = 0; b < npsi; ++b) Co[a * npsi + b] += r.w[q] * psi[a] * mv[b];
+        }
+        if (interior) {
+          const double sgn = s == 0 ? 1.0 : -1.0;
+          for (int l = 0; l < 3; ++l) out.fa[((size_t)j * 2 + s) * 3 + l] = sgn * area / out.face_area_ref[f] * fg.nrm[l];
+        }
+      }
+    } catch (const Error& e) {
+      std::lock_guard<std::mutex> lk(err_mu);
+      if (!err_code) { err_code = e.code; err_msg = e.what(); }
+    }
+  });
+  if (err_code) throw Error(err_code, err_msg);
+}
+
 // ---------------------------------------------------------------- projection of data
 
 // Lowest rule degree of the L2 projection of initial data (the state at
@@ -905,6 +1070,30 @@ void project_values(const HostSetup& hs, const int64_t* elem, int which, int deg
 // inverted on the host; returned in FP32, column-major per element.
 namespace {
 
+// Voigt index of the tensor entry (c, l): 2D (xx, yy, xy); 3D (xx, yy, zz,
+// yz, xz, xy), Section 2.
+int voigt_of(int d, int c, int l) {
+  if (c == l) return c;
+  if (d == 2) return 2;
+  return 6 - c - l;
+}
+
+// E[c][l][c2][l2] of the dual material of face j: sigma_cl = sum E d_l2 v_c2.
+// Isotropic (eq. 1.1b): lambda delta_cl delta_c2l2 + mu (delta_cc2 delta_ll2 +
+// delta_cl2 delta_lc2).  Anisotropic: the Voigt stiffness acts on the strain
+// rate with the shear components halved (Section 2), so
+// E = E~[v(c,l)][v(c2,l2)] (1 if c2 == l2, else 1/2).
+double hooke_entry(const HostSetup& hs, int64_t j, int c, int l, int c2, int l2) {
+  const int d = hs.dim;
+  if (!hs.face_E.empty()) {
+    const int ns = hs.nsig;
+    const double e = hs.face_E[(size_t)j * ns * ns + voigt_of(d, c, l) * ns + voigt_of(d, c2, l2)];
+    return c2 == l2 ? e : 0.5 * e;
+  }
+  const double lam = hs.face_lm[2 * j], mu = hs.face_lm[2 * j + 1];
+  return mu * ((c == c2 && l == l2) + (c == l2 && l == c2)) + lam * (c == l && c2 == l2);
+}
+
 // Element stiffness of the Schur operator restricted to element e (the
 // diagonal block of K): K[(c,k),(c2,k2)] = sum over the faces of e of
 // sum_{l,l2,m} Dt[k][l][m] E_{cl,c2l2} Dt[k2][l2][m].
@@ -917,12 +1106,11 @@ void element_stiffness(const HostSetup& hs, int64_t e, std::vector<double>& K) {
     const FaceRec& fr = hs.faces[j];
     const int side = (fr.left == e && fr.lf == f) ? 0 : 1;
     const double* Db = &hs.Dt[((size_t)j * 2 + side) * blk];
-    const double lam = hs.face_lm[2 * j], mu = hs.face_lm[2 * j + 1];
     for (int c = 0; c < d; ++c)
       for (int l = 0; l < d; ++l)
         for (int c2 = 0; c2 < d; ++c2)
           for (int l2 = 0; l2 < d; ++l2) {
-            double E = mu * ((c == c2 && l == l2) + (c == l2 && l == c2)) + lam * (c == l && c2 == l2);
+            const double E = hooke_entry(hs, j, c, l, c2, l2);
             if (E == 0.0) continue;
             for (int k = 0; k < nphi; ++k)
               for (int k2 = 0; k2 < nphi; ++k2) {
@@ -934,6 +1122,63 @@ void element_stiffness(const HostSetup& hs, int64_t e, std::vector<double>& K) {
               }
           }
   }
+}
+
+// Stiffness coupling of element sides sl and sm of face j (the face's part
+// of the block of K between the two elements):
+// K[(c,k),(c2,k2)] += sum_{l,l2,m} Dt_sl[k][l][m] E_{cl,c2l2} Dt_sm[k2][l2][m].
+void face_coupling(const HostSetup& hs, int64_t j, int sl, int sm, std::vector<double>& K) {
+  const int d = hs.dim, nphi = hs.nphi, npsi = hs.npsi;
+  const int ns = d * nphi, blk = nphi * d * npsi;
+  const double* D1 = &hs.Dt[((size_t)j * 2 + sl) * blk];
+  const double* D2 = &hs.Dt[((size_t)j * 2 + sm) * blk];
+  for (int c = 0; c < d; ++c)
+    for (int l = 0; l < d; ++l)
+      for (int c2 = 0; c2 < d; ++c2)
+        for (int l2 = 0; l2 < d; ++l2) {
+          const double E = hooke_entry(hs, j, c, l, c2, l2);
+          if (E == 0.0) continue;
+          for (int k = 0; k < nphi; ++k)
+            for (int k2 = 0; k2 < nphi; ++k2) {
+              double sacc = 0.0;
+              const double* a1 = D1 + (k * d + l) * npsi;
+              const double* a2 = D2 + (k2 * d + l2) * npsi;
+              for (int m = 0; m < npsi; ++m) sacc += a1[m] * a2[m];
+              K[(c * nphi + k) * ns + c2 * nphi + k2] += E * sacc;
+            }
+        }
+}
+
+// Solve A X = B in place with partial pivoting (A n x n row-major, destroyed;
+// B n x m row-major); false if singular.
+bool lu_solve(std::vector<double>& A, std::vector<double>& B, int n, int m) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[(size_t)r * n + c]) > std::fabs(A[(size_t)piv * n + c])) piv = r;
+    if (A[(size_t)piv * n + c] == 0.0) return false;
+    if (piv != c) {
+      for (int k = 0; k < n; ++k) std::swap(A[(size_t)c * n + k], A[(size_t)piv * n + k]);
+      for (int k = 0; k < m; ++k) std::swap(B[(size_t)c * m + k], B[(size_t)piv * m + k]);
+    }
+    const double dinv = 1.0 / A[(size_t)c * n + c];
+    for (int r = c + 1; r < n; ++r) {
+      const double f = A[(size_t)r * n + c] * dinv;
+      if (f == 0.0) continue;
+      A[(size_t)r * n + c] = f;
+      for (int k = c + 1; k < n; ++k) A[(size_t)r * n + k] -= f * A[(size_t)c * n + k];
+      for (int k = 0; k < m; ++k) B[(size_t)r * m + k] -= f * B[(size_t)c * m + k];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    const double dinv = 1.0 / A[(size_t)c * n + c];
+    for (int k = 0; k < m; ++k) {
+      double v = B[(size_t)c * m + k];
+      for (int r = c + 1; r < n; ++r) v -= A[(size_t)c * n + r] * B[(size_t)r * m + k];
+      B[(size_t)c * m + k] = v * dinv;
+    }
+  }
+  return true;
 }
 
 // Gauss-Jordan inverse with partial pivoting (row-major, n x n); false if singular.
@@ -1110,6 +1355,139 @@ BlockPrecond block_inverses(const HostSetup& hs, const Coefs& op) {
   });
   require(!err, SDG_EMESH, "singular diagonal block");
   return out;
+}
+
+// Patch preconditioner Pre2 (Appendix A, eqs. APPRE1, APPRE2): for each
+// element i the velocity operator restricted to the stencil S_i of i and its
+// face neighbours (the diagonal blocks of eq. pre1 and the neighbour blocks
+// N_{l,m}), inverted, and the first block row of the inverse kept.  Stored
+// in FP32 per element as P[i][e][q][r] = A_i^-1[r][(e, q)] (r, q < nb =
+// N_gamma d N_phi, e < d + 2 stencil slots, zero for missing neighbours),
+// with the stencil's element indices (slot 0 = i, -1 = none).
+PatchPrecond patch_inverses(const HostSetup& hs, const Coefs& op) {
+  const int d = hs.dim, nphi = hs.nphi, ng = hs.ng, nfe = d + 1;
+  const int ns = d * nphi, nb = ng * ns, slots = d + 2;
+  PatchPrecond out;
+  out.nb = nb;
+  out.slots = slots;
+  out.P.assign((size_t)hs.n_elem * slots * nb * nb, 0.0f);
+  out.nbr.assign((size_t)hs.n_elem * slots, -1);
+  std::atomic<int> err{0};
+  parallel_for(hs.n_elem, [&](int64_t i) {
+    // stencil: i, then its face neighbours in local face order (each once)
+    int64_t st[8];
+    int n_s = 0;
+    st[n_s++] = i;
+    for (int f = 0; f < nfe; ++f) {
+      const FaceRec& fr = hs.faces[hs.elem_face[i * nfe + f]];
+      const int64_t o = (fr.left == i && fr.lf == f) ? fr.right : fr.left;
+      if (o < 0) continue;
+      bool seen = false;
+      for (int q = 0; q < n_s; ++q) seen |= st[q] == o;
+      if (!seen) st[n_s++] = o;
+    }
+    const int n = n_s * nb;
+    std::vector<double> A((size_t)n * n, 0.0), K;
+    auto add_block = [&](int p, int q, const std::vector<double>& Ks, bool mass) {
+      // rows (a, c, k) of slot p, columns (b, c2, k2) of slot q:
+      // Tm[a][b] delta_{c c2} w Mref[k][k2] (mass, p == q) + Cg[a][b] Ks[(c,k),(c2,k2)]
+      for (int a = 0; a < ng; ++a)
+        for (int b = 0; b < ng; ++b) {
+          const double cg = op.Cg[a * ng + b], tm = op.Tm[a * ng + b];
+          for (int r = 0; r < ns; ++r)
+            for (int cc = 0; cc < ns; ++cc) {
+              double v = cg * Ks[(size_t)r * ns + cc];
+              if (mass && r / nphi == cc / nphi)
+                v += tm * hs.elem_w[st[p]] * hs.Mref[(r % nphi) * nphi + cc % nphi];
+              A[(size_t)(p * nb + a * ns + r) * n + q * nb + b * ns + cc] += v;
+            }
+        }
+    };
+    for (int p = 0; p < n_s; ++p) {
+      element_stiffness(hs, st[p], K);
+      add_block(p, p, K, true);
+    }
+    // neighbour blocks N_{p,q}: every face shared by two stencil elements
+    for (int p = 0; p < n_s; ++p)
+      for (int f = 0; f < nfe; ++f) {
+        const int64_t j = hs.elem_face[st[p] * nfe + f];
+        const FaceRec& fr = hs.faces[j];
+        const int sp = (fr.left == st[p] && fr.lf == f) ? 0 : 1;
+        const int64_t o = sp == 0 ? fr.right : fr.left;
+        if (o < 0) continue;
+        for (int q = 0; q < n_s; ++q) {
+          if (q == p || st[q] != o) continue;
+          K.assign((size_t)ns * ns, 0.0);
+          face_coupling(hs, j, sp, 1 - sp, K);
+          add_block(p, q, K, false);
+        }
+      }
+    // first block row of A^-1: rows of A^-T E_0, solved as A^T Y = E_0
+    std::vector<double> At((size_t)n * n), Y((size_t)n * nb, 0.0);
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < n; ++c) At[(size_t)c * n + r] = A[(size_t)r * n + c];
+    for (int r = 0; r < nb; ++r) Y[(size_t)r * nb + r] = 1.0;
+    if (!lu_solve(At, Y, n, nb)) { err = 1; return; }
+    // A^-1[r][col] = Y[col][r]
+    float* Pi = &out.P[(size_t)i * slots * nb * nb];
+    for (int e = 0; e < n_s; ++e) {
+      out.nbr[(size_t)i * slots + e] = (int32_t)st[e];
+      for (int q = 0; q < nb; ++q)
+        for (int r = 0; r < nb; ++r) Pi[((size_t)e * nb + q) * nb + r] = (float)Y[(size_t)(e * nb + q) * nb + r];
+    }
+  });
+  require(!err, SDG_EMESH, "singular patch block");
+  return out;
+}
+
+void set_anisotropic_faces(HostSetup& hs, const double* E) {
+  const int ns = hs.nsig;
+  hs.face_E.assign((size_t)hs.n_face * ns * ns, 0.0);
+  hs.face_Cw.assign((size_t)hs.n_face * ns * ns, 0.0);
+  int bad = 0;
+  for (int64_t j = 0; j < hs.n_face; ++j) {
+    const FaceRec& fr = hs.faces[j];
+    double* Ej = &hs.face_E[(size_t)j * ns * ns];
+    for (int a = 0; a < ns * ns; ++a) {
+      double v = hs.face_wt[2 * j] * E[(size_t)fr.left * ns * ns + a];
+      if (fr.right >= 0) v += hs.face_wt[2 * j + 1] * E[(size_t)fr.right * ns * ns + a];
+      Ej[a] = v;
+    }
+    // The strain energy density is 1/2 s~^T W E~^-1 s~ and W E~^-1 is the
+    // inverse of the symmetric E^ = E~ W^-1 (the tensor entries E_ijkl);
+    // it is taken by Cholesky, which is also the positive-definiteness check
+    auto wt = [&](int k) { return k < hs.dim ? 1.0 : 2.0; };
+    std::vector<double> Lc((size_t)ns * ns, 0.0);
+    for (int i = 0; i < ns && !bad; ++i)
+      for (int k = 0; k <= i; ++k) {
+        double sum = Ej[i * ns + k] / wt(k);
+        for (int q = 0; q < k; ++q) sum -= Lc[i * ns + q] * Lc[k * ns + q];
+        if (i == k) {
+          if (!(sum > 0.0)) { bad = 1; break; }
+          Lc[i * ns + i] = std::sqrt(sum);
+        } else {
+          Lc[i * ns + k] = sum / Lc[k * ns + k];
+        }
+      }
+    if (bad) break;
+    std::vector<double> Inv((size_t)ns * ns);
+    for (int col = 0; col < ns; ++col) {
+      std::vector<double> y(ns, 0.0);
+      for (int i = 0; i < ns; ++i) {  // L y = e_col
+        double sum = i == col ? 1.0 : 0.0;
+        for (int q = 0; q < i; ++q) sum -= Lc[i * ns + q] * y[q];
+        y[i] = sum / Lc[i * ns + i];
+      }
+      for (int i = ns - 1; i >= 0; --i) {  // L^T x = y
+        double sum = y[i];
+        for (int q = i + 1; q < ns; ++q) sum -= Lc[q * ns + i] * y[q];
+        y[i] = sum / Lc[i * ns + i];
+      }
+      for (int i = 0; i < ns; ++i) Inv[i * ns + col] = y[i];
+    }
+    for (int i = 0; i < ns * ns; ++i) hs.face_Cw[(size_t)j * ns * ns + i] = Inv[i];
+  }
+  require(!bad, SDG_EINVAL, "dual-element stiffness is not symmetric positive definite");
 }
 
 }  // namespace sdg

@@ -880,7 +880,7 @@ void launch_block_apply(int64_t n_elem, int nv, const float* P, const double* x,
                         hipStream_t s, int ncols, int64_t cstride) {
   (void)transpose;  // symmetric blocks
   const unsigned gy = (unsigned)std::max(1, ncols);
-  // d N_phi for 2D p = 1..4 and 3D p = 1..3 (one time node)
+  // d N_phi for 2D p = 1..4 and 3D p = 1..4 (one time node)
 #define SDG_BLK_NV(NV_)                                                                                      \
   if (nv == NV_) {                                                                                           \
     constexpr int epb = 256 / NV_;                                                                           \
@@ -891,7 +891,7 @@ void launch_block_apply(int64_t n_elem, int nv, const float* P, const double* x,
     check_launch();                                                                                          \
     return;                                                                                                  \
   }
-  SDG_BLK_NV(6) SDG_BLK_NV(12) SDG_BLK_NV(20) SDG_BLK_NV(30) SDG_BLK_NV(60)
+  SDG_BLK_NV(6) SDG_BLK_NV(12) SDG_BLK_NV(20) SDG_BLK_NV(30) SDG_BLK_NV(60) SDG_BLK_NV(105)
 #undef SDG_BLK_NV
   throw Error(SDG_EUNSUPPORTED, "no block-preconditioner kernel for this element size");
 }

@@ -270,11 +270,14 @@ GRAPH_CASES = {
 }
 
 
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32_ir"])
 @pytest.mark.parametrize("name", sorted(GRAPH_CASES))
-def test_graph_replays_match_eager_steps_and_oracle(name):
+def test_graph_replays_match_eager_steps_and_oracle(name, fp32):
     """The step recorded in HIP graphs is replayed for several steps with
     other work and synchronisations in between; every replayed step is
-    checked against the same step run eagerly and against the oracle."""
+    checked against the same step run eagerly and against the oracle.  With
+    fp32_ir both run the FP32 operator inside FP64 refinement, the graph
+    with its per-system outer tests on the device."""
     import torch
     import paper_1802_04516_amd as sdg
     mks, p, pg, scheme, R = GRAPH_CASES[name]
@@ -283,7 +286,7 @@ def test_graph_replays_match_eager_steps_and_oracle(name):
     lam, mu, rho = (np.concatenate([mt[i] for mt in mats]) for i in range(3))
     dt = 0.01
     sch = sdg.SDG_SCHEME_CN if scheme == "cn" else sdg.SDG_SCHEME_STDG
-    prc = sdg.SDG_PREC_F64 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND
+    prc = sdg.SDG_PREC_F64 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND | (sdg.SDG_PREC_F32 if fp32 else 0)
     ctx = sdg.Context(0)
     if len(meshes) > 1:
         ctx.setup_batch([(m.xyz, m.elem) for m in meshes], p, pg, sch, dt, lam, mu, rho, prc)
@@ -301,9 +304,10 @@ def test_graph_replays_match_eager_steps_and_oracle(name):
     s0 = np.zeros(sz["n_stress_state"] * R)
     vg, sg = _gpu(v0), _gpu(s0)          # graph-mode state
     ve, se = _gpu(v0), _gpu(s0)          # eager state
-    opts_g = _opts(precond=sdg.SDG_PRECOND_BLOCK)
+    pr = sdg.SDG_PREC_F32 if fp32 else sdg.SDG_PREC_F64
+    opts_g = _opts(precision=pr, precond=sdg.SDG_PRECOND_BLOCK)
     opts_g.flags = sdg.SDG_SOLVE_GRAPH
-    opts_e = _opts(precond=sdg.SDG_PRECOND_BLOCK)
+    opts_e = _opts(precision=pr, precond=sdg.SDG_PRECOND_BLOCK)
     scratch_v = torch.randn(sz["n_vel_slab"], dtype=torch.float64, device="cuda")
     scratch_y = torch.empty_like(scratch_v)
     for n in range(4):
@@ -347,7 +351,9 @@ def test_graph_replays_match_eager_steps_and_oracle(name):
                 worst = max(worst, rel(vg.cpu().numpy().reshape(R, -1)[r], v1),
                             rel(sg.cpu().numpy().reshape(R, -1)[r],
                                 np.stack([S.B.to_canonical(j, s1[j]) for j in range(S.nf)])))
-        print(f"{name} step {n}: graph vs eager {d_ge:.2e}, vs oracle {worst:.2e}, iters graph "
-              f"{info_g['iterations']} eager {info_e['iterations']}")
+        print(f"{name} {'fp32_ir' if fp32 else 'fp64'} step {n}: graph vs eager {d_ge:.2e}, vs oracle "
+              f"{worst:.2e}, iters graph {info_g['iterations']} eager {info_e['iterations']}, refinements "
+              f"graph {info_g['refinements']} eager {info_e['refinements']}")
         assert d_ge <= 1e-11 and worst <= 1e-11
+        assert info_g["rel_residual"] <= 1e-13
     ctx.close()

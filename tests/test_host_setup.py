@@ -34,6 +34,7 @@ MESHES = {
     "2d_periodic_p2": (lambda: synth.split_square(4, periodic=True, jitter=0.1, seed=6), 2, True, 1),
     "3d_free_p2": (lambda: synth.kuhn_cube(2, periodic=False), 2, False, 2),
     "3d_periodic_p1": (lambda: synth.kuhn_cube(3, periodic=True), 1, True, 0),
+    "3d_free_p4": (lambda: synth.kuhn_cube(2, periodic=False), 4, False, 0),
 }
 
 
@@ -89,7 +90,10 @@ def test_library_dual_basis_equals_oracle_gram_schmidt(harness, tmp_path, name):
         err = np.abs(got[j] - ref).max() / np.abs(ref).max()
         worst = max(worst, err)
     print(f"{name}: {topo.n_face} faces, worst relative difference {worst:.2e}")
-    assert worst <= 1e-9
+    # degree 4 on tetrahedra: Gram matrices of cond 1e8, two QR-based
+    # orthonormalisations of different raw sequences agree to ~1e-11
+    p4 = d == 3 and p == 4
+    assert worst <= (1e-10 if p4 else 1e-9)
     # the coupling blocks D (eq. MD_3) in the canonical basis: D_can = D_raw L^-T
     Dt = np.fromfile(bfile, dtype=np.float64).reshape(topo.n_face, 2, B.nphi, d, B.npsi)
     worst_d = 0.0
@@ -101,7 +105,7 @@ def test_library_dual_basis_equals_oracle_gram_schmidt(harness, tmp_path, name):
             ref = np.linalg.solve(B.L[j], B.D[j][side].reshape(-1, B.npsi).T).T.reshape(B.nphi, d, B.npsi)
             worst_d = max(worst_d, np.abs(Dt[j, side] - ref).max() / np.abs(ref).max())
     print(f"{name}: worst relative difference of the coupling blocks {worst_d:.2e}")
-    assert worst_d <= 1e-11
+    assert worst_d <= (1e-10 if p4 else 1e-11)
     # dual material (volume-weighted Lame parameters), element mass rho |J| M_ref
     # against the oracle's rho M_bar, and the time basis (Section 4)
     nf, ne, nphi, ng = topo.n_face, topo.n_elem, B.nphi, pg + 1
@@ -198,4 +202,45 @@ def test_library_projection_of_initial_data_equals_oracle(proj_harness, tmp_path
         got = np.fromfile(ofile, dtype=np.float64).reshape(ref.shape)
         err = np.abs(got - ref).max() / np.abs(ref).max()
         print(f"{name} which={which}: {nq} points per cell, max rel difference {err:.2e}")
-        assert err <= 1e-11
+        assert err <= (1e-10 if (d == 3 and p == 4) else 1e-11)
+
+
+@pytest.mark.parametrize("name,p", [("periodic_p2", 2), ("free_p1", 1), ("free_jitter_p2", 2),
+                                    ("free_jitter_p3", 3)])
+def test_compressed_3d_operator_rebuilds_the_blocks(tmp_path, name, p):
+    """The compressed 3D operator (per face side: the change of basis C from
+    the canonical dual basis to a reference basis of P_p on the element's
+    reference sub-simplex, and the face-term and Jacobian coefficients; per
+    local face: reference tables) rebuilds every stored block of eq. (MD_3)."""
+    gxx = shutil.which("g++")
+    if gxx is None or not os.path.exists(os.path.join(HIP_INCLUDE, "hip", "hip_runtime.h")):
+        pytest.skip("needs g++ and the HIP headers")
+    exe = str(tmp_path / "compressed")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", f"-I{HIP_INCLUDE}", "-w",
+                    os.path.join(HERE, "host", "compressed.cpp"), "-o", exe, "-lpthread"], check=True)
+    if name == "periodic_p2":
+        mesh, periodic = synth.kuhn_cube(3, periodic=True), True
+    elif name == "free_p1":
+        mesh, periodic = synth.kuhn_cube(2, periodic=False), False
+    else:
+        mesh = synth.kuhn_cube(2, periodic=False)
+        rng = np.random.default_rng(7)
+        xyz = mesh.xyz + rng.uniform(-0.08, 0.08, mesh.xyz.shape) * (mesh.xyz > 0) * (mesh.xyz < 1)
+        mesh = synth.Mesh(xyz=xyz, elem=mesh.elem, period=None)
+        periodic = False
+    elem = np.asarray(mesh.elem, dtype=np.int64)
+    xyz = np.asarray(mesh.xyz, dtype=np.float64)
+    lam, mu, rho = synth.lognormal_material(elem.shape[0], sigma=0.3, seed=31)
+    mfile = tmp_path / "mesh.bin"
+    with open(mfile, "wb") as f:
+        np.array([3, xyz.shape[0], elem.shape[0], p, int(periodic), 0], dtype=np.int64).tofile(f)
+        xyz.tofile(f)
+        elem.tofile(f)
+        for a in (lam, mu, rho):
+            np.asarray(a, dtype=np.float64).tofile(f)
+    out = subprocess.run([exe, str(mfile)], check=True, capture_output=True, text=True).stdout
+    err = float(out.split()[0])
+    print(f"{name}: largest difference of the rebuilt blocks {err:.2e} of the largest entry")
+    # rounding of the factored sum grows with the degree (2.8e-13 at p = 2,
+    # 4.1e-12 at p = 3 on the jittered mesh)
+    assert err <= (1e-12 if p <= 2 else 1e-11)
