@@ -132,6 +132,9 @@ typedef struct {
   double tune_us_batched[3]; /* batched applies of max_rhs columns per batched variant */
   int64_t cmp_bytes_f64;  /* bytes read per apply by the compressed 3D operator (variant 8), 0 if not built */
   int64_t cmp_bytes_f32;
+  int32_t op_bvariant_f32;   /* batched FP32 apply */
+  int32_t reserved0;
+  double tune_us_batched_f32[3];
 } sdg_sizes;
 
 typedef struct {
@@ -288,13 +291,15 @@ int sdg_query(const sdg_ctx* ctx, sdg_sizes* out);
  * All variants compute the same operator. */
 int sdg_set_operator_variant(sdg_ctx* ctx, int variant);
 
-/* Kernel of the batched FP64 operator apply (n_rhs > 1): 0 = the face
- * kernel variant above launched once per column (column grid), 1 and 2 =
- * the matrix-core kernel (v_mfma_f64_16x16x4: the face gradient and the
- * scatter of each face become GEMMs over the columns) with 8 or 16 columns
- * per workgroup.  sdg_assemble picks the fastest for max_rhs columns when
- * max_rhs > 1; shapes the matrix-core kernel does not cover (N_gamma d not
- * dividing 16, or N_phi > 16) use the column grid whatever is set. */
+/* Kernel of the batched operator apply (n_rhs > 1), for both precisions:
+ * 0 = the face kernel variant above launched once per column (column grid),
+ * 1 and 2 = the matrix-core kernel (v_mfma_f64_16x16x4, or
+ * v_mfma_f32_16x16x4 with FP32 face slots in an FP32 apply: the face
+ * gradient and the scatter of each face become GEMMs over the columns)
+ * with 8 or 16 columns per workgroup.  sdg_assemble picks the fastest per
+ * precision for max_rhs columns when max_rhs > 1 (op_bvariant,
+ * op_bvariant_f32); shapes the matrix-core kernel does not cover (N_gamma d
+ * not dividing 16, or N_phi > 16) use the column grid whatever is set. */
 int sdg_set_batched_variant(sdg_ctx* ctx, int bvariant);
 
 /* Face table in the library's face order (Section 3: each face Gamma_j has a

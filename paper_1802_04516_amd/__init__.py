@@ -64,7 +64,8 @@ class Sizes(ctypes.Structure):
                 ("op_variant_f32", ctypes.c_int32), ("op_bvariant", ctypes.c_int32),
                 ("tune_us_f64", ctypes.c_double * 9), ("tune_us_f32", ctypes.c_double * 9),
                 ("tune_us_batched", ctypes.c_double * 3), ("cmp_bytes_f64", ctypes.c_int64),
-                ("cmp_bytes_f32", ctypes.c_int64)]
+                ("cmp_bytes_f32", ctypes.c_int64), ("op_bvariant_f32", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("tune_us_batched_f32", ctypes.c_double * 3)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -234,11 +235,12 @@ def sdg_query(h) -> dict:
     s = Sizes()
     _check(lib().sdg_query(h, ctypes.byref(s)))
     out = {f: getattr(s, f) for f, _ in Sizes._fields_
-           if f not in ("tau", "tune_us_f64", "tune_us_f32", "tune_us_batched")}
+           if f not in ("tau", "tune_us_f64", "tune_us_f32", "tune_us_batched", "tune_us_batched_f32", "reserved0")}
     out["tau"] = [s.tau[a] for a in range(s.n_gamma)]
     out["tune_us_f64"] = list(s.tune_us_f64)
     out["tune_us_f32"] = list(s.tune_us_f32)
     out["tune_us_batched"] = list(s.tune_us_batched)
+    out["tune_us_batched_f32"] = list(s.tune_us_batched_f32)
     return out
 
 

@@ -110,8 +110,15 @@ void check_prec(Ctx& c, int prec) {
 
 }  // namespace
 
-void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s, int ncols, void* z) {
+void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s, int ncols, void* z,
+              const int* mask_active) {
   OpArgs a = base_args(c, prec);
+  if (mask_active) {
+    a.mask_active = mask_active;
+    a.mask_stride = MultiSys::mask_stride();
+    a.face_sys = c.d_face_sys.p;
+    a.elem_sys = c.d_elem_sys.p;
+  }
   a.variant = prec == SDG_PREC_F32 ? c.variant32 : c.variant64;
   a.v = v;
   a.z = z ? static_cast<double*>(z) : c.d_z.p;
@@ -119,7 +126,7 @@ void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipS
   a.use_g = 1;
   a.c = transpose ? c.adj : c.op;
   a.n_cols = ncols;
-  a.bvariant = c.bvariant;
+  a.bvariant = prec == SDG_PREC_F32 ? c.bvariant32 : c.bvariant;
   a.cs_v = a.cs_y = c.n_slab;
   a.cs_z = c.z_col;
   a.z_f32 = prec == SDG_PREC_F32;
@@ -171,28 +178,34 @@ static void autotune(Ctx& c) {
     }
     if (pi == 0) c.variant64 = best; else c.variant32 = best;
   }
-  // batched FP64 applies: column grid against the matrix-core tile widths
-  // (the matrix-core kernel applies the isotropic law only)
-  c.bvariant = 0;
-  if (c.max_rhs > 1 && (c.precisions & SDG_PREC_F64) && !c.aniso) {
+  // batched applies: column grid against the matrix-core tile widths, per
+  // precision (the matrix-core kernel applies the isotropic law only)
+  c.bvariant = c.bvariant32 = 0;
+  if (c.max_rhs > 1 && !c.aniso) {
     const int R = c.max_rhs;
     vec_fill(c.n_slab * R, 1.0, c.d_x.p, s);
-    int best = 0;
-    double best_t = 1e30;
-    for (int bv = 0; bv < 3; ++bv) {
-      c.bvariant = bv;
-      apply_op(c, c.d_x.p, c.d_r.p, SDG_PREC_F64, false, s, R);
-      SDG_HIP(hipEventRecord(e0, s));
-      const int reps = 3;
-      for (int w = 0; w < reps; ++w) apply_op(c, c.d_x.p, c.d_r.p, SDG_PREC_F64, false, s, R);
-      SDG_HIP(hipEventRecord(e1, s));
-      SDG_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      SDG_HIP(hipEventElapsedTime(&ms, e0, e1));
-      c.tune_b_us[bv] = 1e3 * ms / reps;
-      if (c.tune_b_us[bv] < best_t) { best_t = c.tune_b_us[bv]; best = bv; }
+    for (int pi = 0; pi < 2; ++pi) {
+      const int prec = pi == 0 ? SDG_PREC_F64 : SDG_PREC_F32;
+      if (!(c.precisions & prec)) continue;
+      int& bvar = pi == 0 ? c.bvariant : c.bvariant32;
+      double* tb = pi == 0 ? c.tune_b_us : c.tune_b32_us;
+      int best = 0;
+      double best_t = 1e30;
+      for (int bv = 0; bv < 3; ++bv) {
+        bvar = bv;
+        apply_op(c, c.d_x.p, c.d_r.p, prec, false, s, R);
+        SDG_HIP(hipEventRecord(e0, s));
+        const int reps = 3;
+        for (int w = 0; w < reps; ++w) apply_op(c, c.d_x.p, c.d_r.p, prec, false, s, R);
+        SDG_HIP(hipEventRecord(e1, s));
+        SDG_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        SDG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        tb[bv] = 1e3 * ms / reps;
+        if (tb[bv] < best_t) { best_t = tb[bv]; best = bv; }
+      }
+      bvar = best;
     }
-    c.bvariant = best;
   }
   SDG_HIP(hipEventDestroy(e0));
   SDG_HIP(hipEventDestroy(e1));
@@ -605,6 +618,21 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
         c.mesh_face_off[q] = j;
       }
     }
+    c.d_face_sys.free();
+    c.d_elem_sys.free();
+    if (c.n_mesh > 1) {
+      // mesh of each face and element: the systems of a mesh-batch solve
+      std::vector<int> fs(hs.n_face), es(hs.n_elem);
+      for (int q = 0; q < c.n_mesh; ++q) {
+        for (int64_t e = c.mesh_elem_off[q]; e < c.mesh_elem_off[q + 1]; ++e) es[e] = q;
+        const int64_t f1 = q + 1 < c.n_mesh ? c.mesh_face_off[q + 1] : hs.n_face;
+        for (int64_t f = c.mesh_face_off[q]; f < f1; ++f) fs[f] = q;
+      }
+      c.d_face_sys.alloc(fs.size());
+      SDG_HIP(hipMemcpy(c.d_face_sys.p, fs.data(), fs.size() * sizeof(int), hipMemcpyHostToDevice));
+      c.d_elem_sys.alloc(es.size());
+      SDG_HIP(hipMemcpy(c.d_elem_sys.p, es.data(), es.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
     c.n_slab = hs.n_elem * ng * d * nphi;
     c.n_state = hs.n_elem * d * nphi;
     c.n_sig_state = hs.n_face * hs.nsig * hs.npsi;
@@ -840,7 +868,7 @@ int sdg_set_batched_variant(sdg_ctx* ctx, int bvariant) {
     require(!c.aniso || bvariant == 0, SDG_EUNSUPPORTED,
             "with an anisotropic material batched applies use the column grid (batched variant 0)");
     c.graphs.clear();
-    c.bvariant = bvariant;
+    c.bvariant = c.bvariant32 = bvariant;
   });
 }
 
@@ -880,6 +908,9 @@ int sdg_query(const sdg_ctx* ctx, sdg_sizes* out) {
     out->op_variant_f32 = c.variant32;
     out->op_bvariant = c.bvariant;
     for (int v = 0; v < 3; ++v) out->tune_us_batched[v] = c.tune_b_us[v];
+    out->op_bvariant_f32 = c.bvariant32;
+    out->reserved0 = 0;
+    for (int v = 0; v < 3; ++v) out->tune_us_batched_f32[v] = c.tune_b32_us[v];
     for (int v = 0; v < kNumVariants; ++v) { out->tune_us_f64[v] = c.tune_us[0][v]; out->tune_us_f32[v] = c.tune_us[1][v]; }
   });
 }
@@ -1067,8 +1098,9 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
       const bool ir = prec == SDG_PREC_F32;
       const double inner_tol = opts->inner_rtol > 0 ? opts->inner_rtol : 1e-4;
       const int max_ref = opts->max_refine > 0 ? opts->max_refine : 10;
-      std::function<void(const double*, double*)> op = [&c, R, gs, prec](const double* in, double* out) {
-        apply_op(c, in, out, prec, false, gs, R);
+      const int* act = m.active_flags();
+      MultiOp op = [&c, R, gs, prec, act](const double* in, double* out, bool masked) {
+        apply_op(c, in, out, prec, false, gs, R, nullptr, masked ? act : nullptr);
       };
       std::function<void(const double*, double*)> pre = [&c, R, gs, kc](const double* in, double* out) {
         apply_precond(c, kc.precond, in, out, false, gs, R);
@@ -1230,10 +1262,13 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
       k2.max_iter = maxit;
       k2.prec = pr;
       k2.x_zero = x_zero && !multi;
+      // FP32 inner solves of several systems take the targets the outer test set
+      k2.keep_targets = multi && pr == SDG_PREC_F32;
       if (!multi) return solver == SDG_SOLVER_CG ? solve_cg(c, b, x, k2, s) : solve_gmres(c, b, x, k2, s);
       MultiSys& m = systems(c, R);
-      std::function<void(const double*, double*)> op = [&](const double* in, double* out) {
-        apply_op(c, in, out, pr, false, s, R);
+      const int* act = m.active_flags();
+      MultiOp op = [&](const double* in, double* out, bool masked) {
+        apply_op(c, in, out, pr, false, s, R, nullptr, masked ? act : nullptr);
       };
       std::function<void(const double*, double*)> pre = [&](const double* in, double* out) {
         apply_precond(c, k2.precond, in, out, false, s, R);
@@ -1247,6 +1282,9 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
       // FP32 operator inside FP64 iterative refinement
       const double inner_tol = opts->inner_rtol > 0 ? opts->inner_rtol : 1e-4;
       const int max_ref = opts->max_refine > 0 ? opts->max_refine : 10;
+      // several systems: each system's outer test on the device; a system at
+      // rtol takes no further inner step (its inner target is +inf)
+      if (multi) multi_outer_setup(systems(c, R), c.d_b.p, s);
       auto rel_residual = [&](double* bnorm_out) {
         // d = b - A64 x and the worst relative residual over the systems
         apply_op(c, c.d_x.p, c.d_t.p, SDG_PREC_F64, false, s, R);
@@ -1259,7 +1297,12 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
           *bnorm_out = bn;
           return bn > 0 ? rn / bn : rn;
         }
-        return multi_rel_residual(systems(c, R), c.d_b.p, c.d_d.p, s, bnorm_out);
+        MultiSys& m = systems(c, R);
+        multi_refine_check(m, c.d_d.p, opts->rtol, inner_tol, s);
+        SolveResult o;
+        multi_outer_result(m, s, o);
+        *bnorm_out = o.bnorm;
+        return o.rel_res;
       };
       for (int k = 0; k <= max_ref; ++k) {
         double bnorm = 0.0;

@@ -71,6 +71,10 @@ struct DevBuf {
 
 // Independent systems as contiguous segments [off[s], off[s+1]) of one
 // vector, with the reduction-block partition used by the segmented kernels.
+// Operator of the multi-system solver: masked = true inside Arnoldi steps,
+// where the work of converged systems may be skipped.
+using MultiOp = std::function<void(const double*, double*, bool masked)>;
+
 struct MultiSys {
   int S = 0;
   int64_t n_total = 0;
@@ -85,6 +89,8 @@ struct MultiSys {
   // then the last outer relative residual per system (S values)
   DevBuf<double> d_outer;
   DevBuf<int> d_nouter;  // systems whose outer residual is above rtol
+  const int* active_flags() const;  // &d_ss[0].active (stride: mask_stride())
+  static int mask_stride();
   int* h_pinned = nullptr;
   void build(const std::vector<int64_t>& offsets);
   void read_scalars(std::vector<SysScalars>& out, hipStream_t s) const;
@@ -150,12 +156,15 @@ struct Ctx {
   DevBuf<float> d_Dt32;
   DevBuf<double> d_face_lm, d_elem_w, d_Mref;
   DevBuf<double> d_face_E, d_face_Cw;  // anisotropic dual material (empty when isotropic)
+  DevBuf<int> d_face_sys, d_elem_sys;   // mesh of each face / element (mesh batches only)
   DevBuf<double> d_z;  // element face slots
   Coefs op{}, adj{};   // operator and its transpose
   int variant64 = 0, variant32 = 0;   // face-kernel variant per precision (autotuned)
   double tune_us[2][kNumVariants] = {{0}};  // measured apply times [prec][variant]
   int bvariant = 0;              // batched FP64 apply: 0 column grid, 1/2 matrix-core kernel
-  double tune_b_us[3] = {0};     // measured batched applies (max_rhs columns) per bvariant
+  int bvariant32 = 0;            // the same for the FP32 apply
+  double tune_b_us[3] = {0};     // measured batched FP64 applies (max_rhs columns) per bvariant
+  double tune_b32_us[3] = {0};   // and FP32
   // preconditioners: mass block-Jacobi (reference mass inverse, 1/(rho|J|),
   // T^-1) and the element diagonal-block inverses of eq. (pre1) in FP32,
   // column-major per element
@@ -234,7 +243,7 @@ struct Ctx {
 // ncols > 1: ncols independent columns stored one after another (stride n_slab)
 // z: face-slot workspace of z_col values per column (default: the context's)
 void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s, int ncols = 1,
-              void* z = nullptr);
+              void* z = nullptr, const int* mask_active = nullptr);
 
 // Face-slot workspace of the allocation-free apply: a file-scope device
 // array of noalloc_scratch_bytes() per GPU; noalloc_scratch(device) returns
@@ -262,6 +271,7 @@ struct KrylovCfg {
   bool transpose = false;    // solve with A^T (adjoint)
   bool delayed = true;       // GMRES: delayed reorthogonalisation (one reduction per step)
   bool x_zero = false;       // x is zero on entry: the first residual is b itself (no operator apply)
+  bool keep_targets = false; // multi-system: per-system targets already set (multi_refine_check)
 };
 SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s);
 SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s);
@@ -273,15 +283,15 @@ SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, 
 //                   steps with device-side masks, then the correction.
 void multi_setup(MultiSys& m, const double* b, double* x, double rtol, hipStream_t s);
 void multi_residual(MultiSys& m, const double* b, const double* x, hipStream_t s,
-                    const std::function<void(const double*, double*)>& op, double* r);
+                    const MultiOp& op, double* r);
 int multi_cycle(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
-                const std::function<void(const double*, double*)>& op,
+                const MultiOp& op,
                 const std::function<void(const double*, double*)>* pre, double* V, double* r, double* w, double* t,
                 bool poll, int max_steps, int* matvecs, bool* all_converged);
 //   multi_cycle_part / multi_cycle_stop  the delayed cycle split at its
 //                   polling points (graph mode records each part once)
 void multi_cycle_part(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
-                      const std::function<void(const double*, double*)>& op,
+                      const MultiOp& op,
                       const std::function<void(const double*, double*)>* pre, double* V, double* w, double* t,
                       int steps, int j0, int j1, int* matvecs);
 void multi_cycle_stop(MultiSys& m, double* x, const KrylovCfg& k, hipStream_t s,
@@ -308,7 +318,7 @@ void locate_points(Ctx& c, int64_t n_pts, const double* pts);
 // Restarted GMRES on the independent systems of m (right preconditioning
 // with *pre when given); V holds (restart+1) basis vectors of m.n_total.
 SolveResult solve_gmres_multi(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
-                              const std::function<void(const double*, double*)>& op,
+                              const MultiOp& op,
                               const std::function<void(const double*, double*)>* pre, double* V, double* r,
                               double* w, double* t);
 // y = P^-1 x for the chosen preconditioner (transpose: P^-T)

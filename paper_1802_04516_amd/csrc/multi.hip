@@ -19,6 +19,7 @@
 // (as the single-system solver); with SDG_SOLVE_CGS2 both projections run
 // within the step.
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <functional>
@@ -662,6 +663,14 @@ int read_int(int* dev, int* pinned, hipStream_t s) {
 
 }  // namespace
 
+const int* MultiSys::active_flags() const {
+  return reinterpret_cast<const int*>(reinterpret_cast<const char*>(d_ss.p) + offsetof(SysScalars, active));
+}
+int MultiSys::mask_stride() {
+  static_assert(sizeof(SysScalars) % sizeof(int) == 0, "system records must tile ints");
+  return (int)(sizeof(SysScalars) / sizeof(int));
+}
+
 void MultiSys::build(const std::vector<int64_t>& offsets) {
   require(offsets.size() >= 2, SDG_EINVAL, "at least one system");
   S = (int)offsets.size() - 1;
@@ -737,8 +746,8 @@ void multi_setup(MultiSys& m, const double* b, double* x, double rtol, hipStream
 }
 
 void multi_residual(MultiSys& m, const double* b, const double* x, hipStream_t s,
-                    const std::function<void(const double*, double*)>& op, double* r) {
-  op(x, r);
+                    const MultiOp& op, double* r) {
+  op(x, r, false);
   vec_axpby(m.n_total, 1.0, b, -1.0, r, s);
   seg_norm2(m, r, s);
   km_cycle_start<<<1, sys_threads(m.S), 0, s>>>(m.S, m.d_ss.p, m.d_nactive.p);
@@ -751,7 +760,7 @@ void multi_residual(MultiSys& m, const double* b, const double* x, hipStream_t s
 // column j-1 and switches systems whose estimate has converged off; the last
 // step's update sweep forms the dots that complete the last column.
 static int multi_cycle_delayed(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
-                               const std::function<void(const double*, double*)>& op,
+                               const MultiOp& op,
                                const std::function<void(const double*, double*)>* pre, double* V, double* w,
                                double* t, bool poll, int max_steps, int* matvecs, bool* all_converged) {
   const int64_t n = m.n_total;
@@ -775,9 +784,9 @@ static int multi_cycle_delayed(MultiSys& m, const double* b, double* x, const Kr
     double* vj = V + (size_t)j * n;
     if (pre) {
       (*pre)(vj, t);
-      op(t, w);
+      op(t, w, true);
     } else {
-      op(vj, w);
+      op(vj, w, true);
     }
     ++*matvecs;
     const bool last = j + 1 == steps;
@@ -812,7 +821,7 @@ static int multi_cycle_delayed(MultiSys& m, const double* b, double* x, const Kr
 // column, triangular solve, correction).  The steps are those of
 // multi_cycle_delayed, split where it polls.
 void multi_cycle_part(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
-                      const std::function<void(const double*, double*)>& op,
+                      const MultiOp& op,
                       const std::function<void(const double*, double*)>* pre, double* V, double* w, double* t,
                       int steps, int j0, int j1, int* matvecs) {
   require(k.delayed && 0 <= j0 && j0 < j1 && j1 <= steps && steps <= k.restart, SDG_EINVAL, "bad cycle part");
@@ -826,9 +835,9 @@ void multi_cycle_part(MultiSys& m, const double* b, double* x, const KrylovCfg& 
     double* vj = V + (size_t)j * n;
     if (pre) {
       (*pre)(vj, t);
-      op(t, w);
+      op(t, w, true);
     } else {
-      op(vj, w);
+      op(vj, w, true);
     }
     ++*matvecs;
     const bool last = j + 1 == steps;
@@ -864,7 +873,7 @@ void multi_cycle_stop(MultiSys& m, double* x, const KrylovCfg& k, hipStream_t s,
 }
 
 int multi_cycle(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
-                const std::function<void(const double*, double*)>& op,
+                const MultiOp& op,
                 const std::function<void(const double*, double*)>* pre, double* V, double* r, double* w, double* t,
                 bool poll, int max_steps, int* matvecs, bool* all_converged) {
   if (k.delayed) return multi_cycle_delayed(m, b, x, k, s, op, pre, V, w, t, poll, max_steps, matvecs, all_converged);
@@ -890,9 +899,9 @@ int multi_cycle(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hip
     double* vj = V + (size_t)j * n;
     if (pre) {
       (*pre)(vj, t);
-      op(t, w);
+      op(t, w, true);
     } else {
-      op(vj, w);
+      op(vj, w, true);
     }
     ++*matvecs;
     launch_m(Op::Multidot, j + 1, bm, s, n, V, w, ss, m.d_partials.p);
@@ -966,11 +975,11 @@ void multi_result(MultiSys& m, hipStream_t s, SolveResult& res) {
 }
 
 SolveResult solve_gmres_multi(MultiSys& m, const double* b, double* x, const KrylovCfg& k, hipStream_t s,
-                              const std::function<void(const double*, double*)>& op,
+                              const MultiOp& op,
                               const std::function<void(const double*, double*)>* pre, double* V, double* r,
                               double* w, double* t) {
   SolveResult res;
-  multi_setup(m, b, x, k.rtol, s);
+  if (!k.keep_targets) multi_setup(m, b, x, k.rtol, s);
   for (;;) {
     bool done = false;
     const int it = multi_cycle(m, b, x, k, s, op, pre, V, r, w, t, true, k.max_iter - res.iters, &res.matvecs, &done);

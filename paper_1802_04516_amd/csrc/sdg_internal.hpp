@@ -192,6 +192,15 @@ struct OpArgs {
   const double* cmpB = nullptr;
   const double* cmpF = nullptr;
   const double* cmpG = nullptr;
+  // Inside multi-system Arnoldi steps the operator skips the work of
+  // converged systems, whose rows are no longer read: mask_active[s *
+  // mask_stride] is system s's activity flag (null: no mask).  Systems are
+  // the columns (grid y) of a batched solve, or the meshes of a mesh batch,
+  // given per face and per element by face_sys / elem_sys.
+  const int* mask_active = nullptr;
+  int mask_stride = 0;
+  const int* face_sys = nullptr;
+  const int* elem_sys = nullptr;
 };
 
 // Launch the face kernel and/or the element kernel for (dim, p, NG).

@@ -74,7 +74,9 @@ def test_batched_apply_matches_columns_and_oracle(bcase, bvariant):
     """Batched applies against the single-column apply and the oracle's
     Schur complement.  The column grid (bvariant 0) runs the single-column
     kernels on offset pointers and is equal bit for bit; the matrix-core
-    kernel (1, 2; FP64) sums in another order and is held to 1e-12."""
+    kernel (1, 2) sums in another order: FP64 within 1e-13 of the single
+    apply, FP32 (v_mfma_f32_16x16x4, FP32 face slots) within 1e-6 of it,
+    and both within the usual bars of the oracle."""
     import torch
     import paper_1802_04516_amd as sdg
     ctx, R, n = bcase["ctx"], bcase["R"], bcase["sizes"]["n_vel_slab"]
@@ -91,10 +93,10 @@ def test_batched_apply_matches_columns_and_oracle(bcase, bvariant):
             for r in range(R):
                 ctx.apply(_gpu(V[r]), ys, prec)
                 col = yb[r * n:(r + 1) * n]
-                if bvariant == 0 or prec == sdg.SDG_PREC_F32:
+                if bvariant == 0:
                     assert torch.equal(ys, col), f"column {r} differs from the single apply"
                 else:
-                    assert rel(col.cpu().numpy(), ys.cpu().numpy()) <= 1e-13
+                    assert rel(col.cpu().numpy(), ys.cpu().numpy()) <= (1e-6 if prec == sdg.SDG_PREC_F32 else 1e-13)
                 assert rel(col.cpu().numpy(), S @ V[r]) <= tol
         yt = torch.empty(R * n, dtype=torch.float64, device="cuda")
         ctx.apply_adjoint(_gpu(V), yt, n_rhs=R)
@@ -102,10 +104,11 @@ def test_batched_apply_matches_columns_and_oracle(bcase, bvariant):
             assert rel(yt[r * n:(r + 1) * n].cpu().numpy(), S.T @ V[r]) <= 1e-12
         # a partial last tile: fewer columns than the workgroup width
         if R > 1:
-            vb, yb = _gpu(V[:R - 1]), torch.empty((R - 1) * n, dtype=torch.float64, device="cuda")
-            ctx.apply(vb, yb, sdg.SDG_PREC_F64, n_rhs=R - 1)
-            for r in range(R - 1):
-                assert rel(yb[r * n:(r + 1) * n].cpu().numpy(), S @ V[r]) <= 1e-12
+            for prec, tol in ((sdg.SDG_PREC_F64, 1e-12), (sdg.SDG_PREC_F32, 2e-6)):
+                vb, yb = _gpu(V[:R - 1]), torch.empty((R - 1) * n, dtype=torch.float64, device="cuda")
+                ctx.apply(vb, yb, prec, n_rhs=R - 1)
+                for r in range(R - 1):
+                    assert rel(yb[r * n:(r + 1) * n].cpu().numpy(), S @ V[r]) <= tol
     finally:
         ctx.set_batched_variant(old)
 
