@@ -135,6 +135,8 @@ typedef struct {
   int32_t op_bvariant_f32;   /* batched FP32 apply */
   int32_t reserved0;
   double tune_us_batched_f32[3];
+  int32_t proj_min_degree[2]; /* lowest rule degree sdg_projection_points / sdg_project_state accept for
+                                 elements [0] and dual elements [1] */
 } sdg_sizes;
 
 typedef struct {
@@ -200,6 +202,31 @@ int sdg_set_mesh(sdg_ctx* ctx, int dim, int64_t n_vert, const double* xyz,
  * drops the point sources. */
 int sdg_set_mesh_batch(sdg_ctx* ctx, int dim, int n_mesh, const int64_t* vert_off, const double* xyz,
                        const int64_t* elem_off, const int64_t* elem);
+
+/* Curved elements (Section 3: sub- and iso-parametric maps of the
+ * reference triangle), 2D, on a single non-periodic mesh set by
+ * sdg_set_mesh.  Element elem_ids[c] (c < n_curved, each listed once) is
+ * the image of the reference triangle under the Lagrange map of degree q
+ * (1..4) through its (q+1)(q+2)/2 geometry nodes, given in
+ * nodes[c][node][2] (host) in the velocity node order of degree q:
+ * node (i, j)/q of the reference triangle, for j in 0..q, for i in
+ * 0..q-j, vertex 0 at (0,0), 1 at (1,0), 2 at (0,1).  The corner nodes must
+ * be the element's vertices, and a face shared with another element must
+ * be straight (its nodes at the affine positions): only boundary faces,
+ * which are free surface, may curve (SDG_EMESH at sdg_assemble otherwise).
+ * A curved element's velocity basis is the reference basis composed with
+ * the inverse map; its barycentre and sub-simplices T_{i,j}, hence the dual
+ * elements, are the images of the reference ones; its mass, coupling
+ * blocks (eq. MD_3) and dual Gram matrices are integrated in reference
+ * coordinates with |det J|.  Point sources, sampling and the projection of
+ * initial data locate points in it by Newton iteration on the map.
+ * n_curved = 0 removes all curved elements.  Cleared by sdg_set_mesh; drops
+ * the point sources; takes effect at the next sdg_assemble.  The adjoint
+ * step refuses a mesh with curved elements (SDG_EUNSUPPORTED); SDG_EINVAL
+ * for a bad degree, index or node, SDG_EUNSUPPORTED in 3D, on a periodic
+ * mesh or a mesh batch. */
+int sdg_set_curved_elements(sdg_ctx* ctx, int q, int64_t n_curved, const int64_t* elem_ids,
+                            const double* nodes);
 
 /* Space degree p (Section 3: N_phi = C(p+dim, dim) velocity functions,
  * N_psi = (p+1)^2 in 2D and N_phi in 3D stress functions), time degree

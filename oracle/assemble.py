@@ -18,8 +18,8 @@ from __future__ import annotations
 import numpy as np
 
 from . import quad
-from .basis import (DualRawBasis, ElementMap, LagrangeBasis, n_phi, n_psi,
-                    phys_basis)
+from .basis import (CurvedMap, DualRawBasis, ElementMap, LagrangeBasis,
+                    basis_at_ref, n_phi, n_psi, phys_basis)
 from .mesh import Topology
 
 
@@ -114,9 +114,18 @@ class Blocks:
     ``stiffness`` (n_elem, n_sigma, n_sigma), when given, is a general
     material per element in the Voigt form of Section 2; lam and mu are then
     ignored.  E~_j is the volume-weighted mean over R_j, like lambda_j.
+
+    ``curved`` = (element ids, geometry nodes (n_c, N_q, d)) gives curved
+    elements (Section 3: sub-/iso-parametric maps of degree q, 2D): their
+    velocity basis is the reference basis composed with the inverse map,
+    their barycentre and sub-simplices T_{i,j} are the images of the
+    reference ones, and every integral over them is taken in reference
+    coordinates with |det J|.  Their faces shared with other elements must
+    be straight (geometry nodes at the affine positions); boundary faces may
+    be curved.
     """
 
-    def __init__(self, topo: Topology, p: int, lam, mu, rho, stiffness=None):
+    def __init__(self, topo: Topology, p: int, lam, mu, rho, stiffness=None, curved=None):
         self.topo = topo
         d = self.dim = topo.dim
         self.p = p
@@ -132,10 +141,15 @@ class Blocks:
         psi_deg = 2 * p if d == 2 else p
 
         self.maps = [ElementMap(topo.V[e]) for e in range(topo.n_elem)]
+        self.curved = {}
+        if curved is not None:
+            self._set_curved(*curved)
+        self.bary = np.array([self.maps[e].x(np.full((1, d), 1.0 / (d + 1)))[0] if e in self.curved
+                              else topo.V[e].mean(axis=0) for e in range(topo.n_elem)])
         self.Mbar = []
         for e in range(topo.n_elem):
-            x, w = quad.simplex_rule(topo.V[e], 2 * p)
-            phi, _ = phys_basis(self.lb, self.maps[e], x)
+            x, w, xi = self.elem_rule(e, 2 * p)
+            phi, _ = basis_at_ref(self.lb, self.maps[e], xi)
             self.Mbar.append((phi * w[:, None]).T @ phi)
 
         self.duals, self.M, self.L, self.D, self.Qt = [], [], [], [], []
@@ -150,16 +164,19 @@ class Blocks:
             Dj, Qj = [], []
             for s in sides:
                 e = F.left if s == 0 else F.right
-                emap = self.maps[e] if s == 0 else ElementMap(F.Vr)
-                Tij = topo.sub_simplex(j, s)
-                x, w = quad.simplex_rule(Tij, 2 * psi_deg)
+                emap = self.maps[e] if (s == 0 or e in self.curved) else ElementMap(F.Vr)
+                x, w, _ = self.sub_rule(j, s, 2 * psi_deg)
                 pv = psi.eval(x)
                 G += (pv * w[:, None]).T @ pv
                 self.vol_sub[j, s] = w.sum()
-                # volume parts
-                x, w = quad.simplex_rule(Tij, max(p - 1, 0) + psi_deg)
+                # volume parts (a curved side integrates d_l phi through its
+                # map: the rule is exact for J^-1 |det J| = adj J)
+                x, w, xi = self.sub_rule(j, s, max(p - 1, 0) + psi_deg, extra=-1)
                 pv = psi.eval(x)
-                _, gphi = phys_basis(self.lb, emap, x)
+                if e in self.curved:
+                    _, gphi = basis_at_ref(self.lb, emap, xi)
+                else:
+                    _, gphi = phys_basis(self.lb, emap, x)
                 Dv = -np.einsum("q,qlk,qm->klm", w, gphi, pv)
                 Qv = np.einsum("q,qm,qlk->mlk", w, pv, gphi)
                 if F.right >= 0:
@@ -210,12 +227,99 @@ class Blocks:
             return compliance_from_voigt(self.dim, self.Et_j[j])
         return compliance_voigt(self.dim, self.lam_j[j], self.mu_j[j])
 
+    # ------------------------------------------------------------ geometry
+
+    def _set_curved(self, ids, nodes):
+        topo, d = self.topo, self.dim
+        if d != 2:
+            raise ValueError("curved elements are 2D here")
+        nodes = np.asarray(nodes, float)
+        nq = nodes.shape[1]
+        q = next(k for k in range(1, 12) if (k + 1) * (k + 2) // 2 == nq)
+        corner = [0, q, nq - 1]            # node indices of xi = (0,0), (1,0), (0,1)
+        for e, X in zip(np.asarray(ids), nodes):
+            e = int(e)
+            V = topo.V[e]
+            h = np.max(np.abs(V[1:] - V[0]))
+            if np.max(np.abs(X[corner] - V)) > 1e-12 * max(1.0, np.max(np.abs(V))):
+                raise ValueError(f"curved element {e}: corner nodes differ from its vertices")
+            cm = CurvedMap(X, q)
+            self.maps[e] = cm
+            self.curved[e] = cm
+            # faces shared with another element must be straight
+            aff = ElementMap(V)
+            ref = cm.gb.nodes
+            for f in range(d + 1):
+                j = topo.elem_faces[e, f]
+                if topo.faces[j].right < 0:
+                    continue
+                lam = np.column_stack([1.0 - ref.sum(axis=1), ref])
+                on = np.abs(lam[:, f]) < 1e-12
+                straight = V[0][None, :] + ref[on] @ aff.J.T
+                if np.max(np.abs(X[on] - straight)) > 1e-12 * max(1.0, h):
+                    raise ValueError(f"curved element {e}: interior face {j} is not straight")
+
+    def _ref_sub(self, e, f):
+        """Reference vertices of T_{e,j} for local face f of e: the face's
+        reference vertices, then the reference barycentre."""
+        d = self.dim
+        corners = np.vstack([np.zeros(d), np.eye(d)])
+        return np.vstack([corners[[a for a in range(d + 1) if a != f]], np.full((1, d), 1.0 / (d + 1))])
+
+    def elem_rule(self, e, degree):
+        """(x, w, xi) of a rule over element e exact for integrands of degree
+        ``degree`` in physical coordinates (their composition with a curved
+        map of degree q, times |det J|, in reference coordinates)."""
+        cm = self.curved.get(e)
+        d = self.dim
+        if cm is None:
+            x, w = quad.simplex_rule(self.topo.V[e], degree)
+            return x, w, self.maps[e].to_ref(x)
+        corners = np.vstack([np.zeros(d), np.eye(d)])
+        return quad.mapped_rule(cm, corners, degree * cm.q + d * (cm.q - 1))
+
+    def sub_rule(self, j, side, degree, extra=0):
+        """(x, w, xi) of a rule over T_{i,j} (i the element of ``side``), exact
+        like elem_rule; ``extra`` adjusts the degree added for |det J| (-1:
+        an integrand carrying J^-1, whose product with |det J| is adj J)."""
+        F = self.topo.faces[j]
+        e = F.left if side == 0 else F.right
+        cm = self.curved.get(e)
+        d = self.dim
+        if cm is None:
+            b = F.bl if side == 0 else F.br
+            x, w = quad.simplex_rule(np.vstack([F.X, b[None, :]]), degree)
+            emap = self.maps[e] if side == 0 else ElementMap(F.Vr)
+            return x, w, emap.to_ref(x)
+        f = F.lf if side == 0 else F.rf
+        jdeg = d * (cm.q - 1) if extra == 0 else (d - 1) * (cm.q - 1)
+        return quad.mapped_rule(cm, self._ref_sub(e, f), degree * cm.q + jdeg)
+
+    def face_bary(self, F):
+        """Barycentres of the face's elements in the left frame (images of the
+        reference barycentre for curved elements)."""
+        bl = self.bary[F.left] if F.left in self.curved else F.bl
+        if F.right < 0:
+            return bl, None
+        return bl, (self.bary[F.right] if F.right in self.curved else F.br)
+
+    def locate(self, x, tol=1e-12):
+        """Lowest element index whose closed element contains x."""
+        x = np.asarray(x, float)
+        for e in range(self.topo.n_elem):
+            xi = self.maps[e].to_ref(x[None, :])[0]
+            bary = np.concatenate([[1 - xi.sum()], xi])
+            if np.all(bary >= -tol):
+                return e
+        return -1
+
     def _dual_basis(self, F):
         if self.dim == 2:
             n1, n2 = F.X[0], F.X[1]
-            br = F.br if F.br is not None else (n1 + n2 - F.bl)
+            bl, br = self.face_bary(F)
+            br = br if br is not None else (n1 + n2 - bl)
             d1 = n2 - n1
-            d2 = br - F.bl
+            d2 = br - bl
             return DualRawBasis(2, self.p, n1, axes=[(d1 - d2) / 2, (d1 + d2) / 2])
         pts = [F.X, F.bl[None, :]]
         if F.br is not None:

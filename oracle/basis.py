@@ -121,14 +121,63 @@ class ElementMap:
         return (np.atleast_2d(x) - self.V[0][None, :]) @ self.Jinv.T
 
 
-def phys_basis(lb: LagrangeBasis, emap: ElementMap, x):
+class CurvedMap:
+    """Map of degree q of a curved element (Section 3, sub- or iso-parametric
+    maps): x(xi) = sum_a X_a N_a(xi) with N_a the Lagrange basis of degree q
+    on the reference simplex (nodes in the velocity node order) and X_a the
+    given geometry nodes.  q = 1 is the affine map."""
+
+    curved = True
+
+    def __init__(self, X, q):
+        self.X = np.asarray(X, float)
+        self.q = q
+        self.dim = self.X.shape[1]
+        self.gb = LagrangeBasis(self.dim, q)
+        if self.gb.n != self.X.shape[0]:
+            raise ValueError("geometry nodes do not match the degree")
+        corners = np.vstack([np.zeros(self.dim), np.eye(self.dim)])
+        self.V = self.x(corners)
+
+    def x(self, xi):
+        return self.gb.eval(np.atleast_2d(xi)) @ self.X
+
+    def jac(self, xi):
+        """(npts, d, d): J[p, c, a] = d x_c / d xi_a."""
+        return np.einsum("pak,kc->pca", self.gb.grad(np.atleast_2d(xi)), self.X)
+
+    def to_ref(self, x, tol=1e-14, maxit=50):
+        """Reference points of physical points x (Newton from the affine guess)."""
+        x = np.atleast_2d(np.asarray(x, float))
+        A = (self.V[1:] - self.V[0]).T
+        xi = np.linalg.solve(A, (x - self.V[0][None, :]).T).T
+        for _ in range(maxit):
+            r = self.x(xi) - x
+            step = np.linalg.solve(self.jac(xi), r[..., None])[..., 0]
+            xi = xi - step
+            if np.max(np.abs(step)) <= tol:
+                break
+        return xi
+
+
+def basis_at_ref(lb: LagrangeBasis, emap, xi):
     """Values (npts, N_phi) and physical gradients (npts, d, N_phi) of the
-    velocity basis of the element ``emap`` at physical points ``x``."""
-    xi = emap.to_ref(x)
+    velocity basis of element ``emap`` (affine or curved) at reference points."""
+    xi = np.atleast_2d(xi)
     val = lb.eval(xi)
     g_ref = lb.grad(xi)
-    g = np.einsum("ba,pbk->pak", emap.Jinv, g_ref)  # d/dx_a = sum_b Jinv[b,a] d/dxi_b
+    if getattr(emap, "curved", False):
+        Jinv = np.linalg.inv(emap.jac(xi))                     # (npts, a, c)
+        g = np.einsum("pba,pbk->pak", Jinv, g_ref)
+    else:
+        g = np.einsum("ba,pbk->pak", emap.Jinv, g_ref)      # d/dx_a = sum_b Jinv[b,a] d/dxi_b
     return val, g
+
+
+def phys_basis(lb: LagrangeBasis, emap, x):
+    """Values (npts, N_phi) and physical gradients (npts, d, N_phi) of the
+    velocity basis of the element ``emap`` at physical points ``x``."""
+    return basis_at_ref(lb, emap, emap.to_ref(x))
 
 
 # ---------------------------------------------------------------- time basis

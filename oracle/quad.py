@@ -82,3 +82,17 @@ def simplex_rule(verts: np.ndarray, degree: int):
     else:
         vol = np.sqrt(abs(np.linalg.det(J.T @ J)))
     return pts, w * vol
+
+
+def mapped_rule(cmap, ref_verts: np.ndarray, degree: int):
+    """Rule on the image under the element map ``cmap`` (x(xi), jac(xi)) of
+    the reference sub-simplex with vertex rows ``ref_verts`` (d+1, d), exact
+    for integrands of total degree <= ``degree`` in the reference
+    coordinates (the weights include |det J(xi)|).  Returns (x, w, xi)."""
+    ref_verts = np.asarray(ref_verts, float)
+    d = ref_verts.shape[1]
+    r, w = reference_rule(d, degree)
+    A = (ref_verts[1:] - ref_verts[0]).T
+    xi = ref_verts[0][None, :] + r @ A.T
+    detJ = np.abs(np.linalg.det(cmap.jac(xi)))
+    return cmap.x(xi), w * abs(np.linalg.det(A)) * detJ, xi

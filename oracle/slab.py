@@ -34,7 +34,7 @@ import scipy.sparse.linalg as spla
 from . import quad
 from .assemble import (Blocks, compliance_voigt, locate, stiffness,
                        voigt_index)
-from .basis import TimeBasis, phys_basis
+from .basis import TimeBasis, basis_at_ref, phys_basis
 
 
 class Slab:
@@ -243,7 +243,7 @@ class Slab:
         w = np.array([1.0]) if self.scheme == "cn" else self.tb.w
         for s in range(len(sources["pos"])):
             x = np.asarray(sources["pos"][s], float)
-            e = locate(B.topo, x)
+            e = B.locate(x)
             if e < 0:
                 raise ValueError("source outside the mesh")
             phi, _ = phys_basis(B.lb, B.maps[e], x[None, :])
@@ -310,15 +310,15 @@ class Slab:
         B, d = self.B, self.d
         ek = 0.0
         for i in range(self.ne):
-            x, w = quad.simplex_rule(B.topo.V[i], 2 * B.p)
-            val = B.velocity_at(v[i], i, x)
+            x, w, xi = B.elem_rule(i, 2 * B.p)
+            val = basis_at_ref(B.lb, B.maps[i], xi)[0] @ v[i].T
             ek += 0.5 * B.rho[i] * np.sum(w[:, None] * val * val)
         es = 0.0
         psi_deg = 2 * B.p if d == 2 else B.p
         for j, F in enumerate(B.topo.faces):
             C = B.face_compliance(j)
             for side in ([0] if F.right < 0 else [0, 1]):
-                x, w = quad.simplex_rule(B.topo.sub_simplex(j, side), 2 * psi_deg)
+                x, w, _ = B.sub_rule(j, side, 2 * psi_deg)
                 sv = B.stress_at(s_raw[j], j, x)  # (npts, nsig)
                 es += 0.5 * np.sum(w * np.einsum("ps,st,pt->p", sv, C, sv))
         return ek + es

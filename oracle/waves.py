@@ -16,7 +16,7 @@ import numpy as np
 
 from . import quad
 from .assemble import Blocks, voigt_index
-from .basis import phys_basis
+from .basis import basis_at_ref, phys_basis
 
 
 def eigvec_2d(kind, lam, mu, rho, n):
@@ -132,8 +132,8 @@ def project(B: Blocks, wave, t=0.0, extra_degree=6):
     ne, nf = B.topo.n_elem, B.topo.n_face
     v = np.zeros((ne, d, B.nphi))
     for e in range(ne):
-        x, w = quad.simplex_rule(B.topo.V[e], 2 * B.p + extra_degree)
-        phi, _ = phys_basis(B.lb, B.maps[e], x)
+        x, w, xi = B.elem_rule(e, 2 * B.p + extra_degree)
+        phi, _ = basis_at_ref(B.lb, B.maps[e], xi)
         rhs = (phi * w[:, None]).T @ wave.velocity(x, t)  # (nphi, d)
         v[e] = np.linalg.solve(B.Mbar[e], rhs).T
     s = np.zeros((nf, B.nsig, B.npsi))
@@ -141,7 +141,7 @@ def project(B: Blocks, wave, t=0.0, extra_degree=6):
     for j, F in enumerate(B.topo.faces):
         rhs = np.zeros((B.npsi, B.nsig))
         for side in ([0] if F.right < 0 else [0, 1]):
-            x, w = quad.simplex_rule(B.topo.sub_simplex(j, side), psi_deg + B.p + extra_degree)
+            x, w, _ = B.sub_rule(j, side, psi_deg + B.p + extra_degree)
             pv = B.duals[j].eval(x)
             rhs += (pv * w[:, None]).T @ wave.stress_voigt(x, t)
         s[j] = np.linalg.solve(B.M[j], rhs).T
@@ -153,14 +153,14 @@ def l2_errors(B: Blocks, v, s_raw, wave, t, extra_degree=6):
     d = B.dim
     ev = np.zeros(d)
     for e in range(B.topo.n_elem):
-        x, w = quad.simplex_rule(B.topo.V[e], 2 * B.p + extra_degree)
-        diff = B.velocity_at(v[e], e, x) - wave.velocity(x, t)
+        x, w, xi = B.elem_rule(e, 2 * B.p + extra_degree)
+        diff = basis_at_ref(B.lb, B.maps[e], xi)[0] @ v[e].T - wave.velocity(x, t)
         ev += (w[:, None] * diff ** 2).sum(axis=0)
     es = np.zeros(B.nsig)
     psi_deg = 2 * B.p if d == 2 else B.p
     for j, F in enumerate(B.topo.faces):
         for side in ([0] if F.right < 0 else [0, 1]):
-            x, w = quad.simplex_rule(B.topo.sub_simplex(j, side), 2 * psi_deg + extra_degree)
+            x, w, _ = B.sub_rule(j, side, 2 * psi_deg + extra_degree)
             diff = B.stress_at(s_raw[j], j, x) - wave.stress_voigt(x, t)
             es += (w[:, None] * diff ** 2).sum(axis=0)
     return np.sqrt(ev), np.sqrt(es)

@@ -38,7 +38,7 @@ _ERRNAMES = {SDG_EINVAL: "EINVAL", SDG_ENOMEM: "ENOMEM", SDG_EDEVICE: "EDEVICE",
              SDG_ESTATE: "ESTATE"}
 
 EXPORTED = ("sdg_last_error", "sdg_create", "sdg_destroy", "sdg_set_mesh", "sdg_set_discretization",
-            "sdg_set_material", "sdg_set_material_anisotropic", "sdg_assemble", "sdg_query", "sdg_set_operator_variant", "sdg_set_batched_variant", "sdg_face_table",
+            "sdg_set_material", "sdg_set_material_anisotropic", "sdg_set_curved_elements", "sdg_assemble", "sdg_query", "sdg_set_operator_variant", "sdg_set_batched_variant", "sdg_face_table",
             "sdg_apply_velocity_operator", "sdg_apply_adjoint", "sdg_set_sources", "sdg_solve_step",
             "sdg_energy", "sdg_sample_velocity", "sdg_eval_stress", "sdg_adjoint_step",
             "sdg_sample_velocity_adjoint", "sdg_set_mesh_batch", "sdg_set_mesh_sources",
@@ -65,7 +65,7 @@ class Sizes(ctypes.Structure):
                 ("tune_us_f64", ctypes.c_double * 9), ("tune_us_f32", ctypes.c_double * 9),
                 ("tune_us_batched", ctypes.c_double * 3), ("cmp_bytes_f64", ctypes.c_int64),
                 ("cmp_bytes_f32", ctypes.c_int64), ("op_bvariant_f32", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("tune_us_batched_f32", ctypes.c_double * 3)]
+                ("tune_us_batched_f32", ctypes.c_double * 3), ("proj_min_degree", ctypes.c_int32 * 2)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -104,6 +104,7 @@ def lib():
         "sdg_set_discretization": ([_P, i, i, i, ctypes.c_double], i),
         "sdg_set_material": ([_P, _DP, _DP, _DP], i),
         "sdg_set_material_anisotropic": ([_P, _DP, _DP], i),
+        "sdg_set_curved_elements": ([_P, i, ctypes.c_int64, _I64P, _DP], i),
         "sdg_assemble": ([_P, ctypes.c_uint, i], i),
         "sdg_query": ([_P, ctypes.POINTER(Sizes)], i),
         "sdg_set_operator_variant": ([_P, i], i),
@@ -227,6 +228,22 @@ def sdg_set_material_anisotropic(h, stiffness, rho):
     _check(lib().sdg_set_material_anisotropic(h, _hp(E, ctypes.c_double), _hp(rho, ctypes.c_double)))
 
 
+def sdg_set_curved_elements(h, ids, nodes):
+    """ids: (n_c,) element indices; nodes: (n_c, (q+1)(q+2)/2, 2) geometry
+    nodes of degree q in the velocity node order (None, None: no curved
+    elements)."""
+    if ids is None or len(ids) == 0:
+        _check(lib().sdg_set_curved_elements(h, 1, 0, None, None))
+        return
+    ids = _host(ids, np.int64)
+    nodes = _host(nodes, np.float64)
+    nq = nodes.shape[1]
+    q = next((k for k in range(1, 5) if (k + 1) * (k + 2) // 2 == nq), None)
+    if q is None or nodes.shape[0] != ids.shape[0] or nodes.shape[2] != 2:
+        raise ValueError("nodes must be (n_curved, (q+1)(q+2)/2, 2) with q in 1..4")
+    _check(lib().sdg_set_curved_elements(h, q, ids.shape[0], _hp(ids, ctypes.c_int64), _hp(nodes, ctypes.c_double)))
+
+
 def sdg_assemble(h, precisions=SDG_PREC_F64 | SDG_PREC_F32, max_rhs=1):
     _check(lib().sdg_assemble(h, precisions, max_rhs))
 
@@ -235,12 +252,14 @@ def sdg_query(h) -> dict:
     s = Sizes()
     _check(lib().sdg_query(h, ctypes.byref(s)))
     out = {f: getattr(s, f) for f, _ in Sizes._fields_
-           if f not in ("tau", "tune_us_f64", "tune_us_f32", "tune_us_batched", "tune_us_batched_f32", "reserved0")}
+           if f not in ("tau", "tune_us_f64", "tune_us_f32", "tune_us_batched", "tune_us_batched_f32", "reserved0",
+                        "proj_min_degree")}
     out["tau"] = [s.tau[a] for a in range(s.n_gamma)]
     out["tune_us_f64"] = list(s.tune_us_f64)
     out["tune_us_f32"] = list(s.tune_us_f32)
     out["tune_us_batched"] = list(s.tune_us_batched)
     out["tune_us_batched_f32"] = list(s.tune_us_batched_f32)
+    out["proj_min_degree"] = list(s.proj_min_degree)
     return out
 
 
@@ -341,7 +360,8 @@ def sdg_eval_stress(h, sigma_state, pts, face, out, n_rhs=1, stream=None):
 
 def projection_min_degree(dim, p, which):
     """Lowest projection rule degree accepted for elements (0) or dual
-    elements (1)."""
+    elements (1) on a mesh of straight elements (sdg_query reports it for
+    the assembled mesh, curved elements included)."""
     return 2 * p if which == 0 else (2 * p if dim == 2 else p) + p
 
 
@@ -389,6 +409,19 @@ class Context:
               precisions=SDG_PREC_F64 | SDG_PREC_F32, max_rhs=1):
         sdg_set_mesh(self.h, mesh_xyz, elem, period)
         self.mesh_elem_off = None
+        sdg_set_discretization(self.h, p, p_gamma, scheme, dt)
+        sdg_set_material(self.h, lam, mu, rho)
+        sdg_assemble(self.h, precisions, max_rhs)
+        self.sizes = sdg_query(self.h)
+        return self.sizes
+
+    def setup_curved(self, mesh_xyz, elem, curved, p, p_gamma, scheme, dt, lam, mu, rho,
+                     precisions=SDG_PREC_F64 | SDG_PREC_F32, max_rhs=1):
+        """As setup() on a non-periodic 2D mesh with curved elements
+        curved = (element ids, geometry nodes (n_c, N_q, 2))."""
+        sdg_set_mesh(self.h, mesh_xyz, elem, None)
+        self.mesh_elem_off = None
+        sdg_set_curved_elements(self.h, *curved)
         sdg_set_discretization(self.h, p, p_gamma, scheme, dt)
         sdg_set_material(self.h, lam, mu, rho)
         sdg_assemble(self.h, precisions, max_rhs)
@@ -487,7 +520,7 @@ class Context:
         elements (which = 0) or dual elements (which = 1), with a rule exact
         to the lowest accepted degree plus extra_degree."""
         n = self._n("n_elem") if which == 0 else self._n("n_face")
-        deg = projection_min_degree(self._n("dim"), self._n("p"), which) + extra_degree
+        deg = self.sizes["proj_min_degree"][which] + extra_degree
         return sdg_projection_points(self.h, which, deg, n, self._n("dim"))
 
     def project_state(self, velocity_fn, stress_fn, extra_degree=0, stream=None):
@@ -501,7 +534,7 @@ class Context:
             vals = np.asarray(fn(pts.reshape(-1, pts.shape[-1])), np.float64)
             del pts
             t = torch.empty(self._n(key), dtype=torch.float64, device=f"cuda:{self.device}")
-            deg = projection_min_degree(self._n("dim"), self._n("p"), which) + extra_degree
+            deg = self.sizes["proj_min_degree"][which] + extra_degree
             sdg_project_state(self.h, which, deg, vals, t, stream)
             out.append(t)
         return out[0], out[1]

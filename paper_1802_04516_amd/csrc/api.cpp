@@ -93,6 +93,8 @@ OpArgs base_args(Ctx& c, int prec) {
   a.face_E = c.d_face_E.p;
   a.elem_w = c.d_elem_w.p;
   a.Mref = c.d_Mref.p;
+  a.curved_idx = c.d_curved_idx.p;
+  a.curved_M = c.d_curved_M.p;
   a.y_scale = 1.0;
   a.sig_in_ng = 1;
   a.cmpC = prec == SDG_PREC_F32 ? (const void*)c.d_cmpC32.p : (const void*)c.d_cmpC64.p;
@@ -216,6 +218,7 @@ void apply_precond(Ctx& c, int kind, const double* x, double* y, bool transpose,
   if (kind == SDG_PRECOND_MASS) {
     OpArgs a = base_args(c, SDG_PREC_F64);
     a.Mref = c.d_Minv.p;
+    a.curved_M = c.d_curved_Minv.p;
     a.elem_w = c.d_winv.p;
     a.v = x;
     a.y = y;
@@ -460,7 +463,36 @@ int sdg_set_mesh(sdg_ctx* ctx, int dim, int64_t n_vert, const double* xyz, int64
     }
     for (double x : c.xyz) require(std::isfinite(x), SDG_EINVAL, "non-finite vertex coordinate");
     clear_sources(c);
+    c.curved_q = 0;
+    c.curved_ids.clear();
+    c.curved_nodes.clear();
     c.have_mesh = true;
+    c.assembled = false;
+  });
+}
+
+int sdg_set_curved_elements(sdg_ctx* ctx, int q, int64_t n_curved, const int64_t* elem_ids, const double* nodes) {
+  return guard([&] {
+    Ctx& c = ctx_of(ctx);
+    require(c.have_mesh, SDG_ESTATE, "set the mesh first");
+    require(n_curved >= 0, SDG_EINVAL, "negative count");
+    if (n_curved == 0) {
+      c.curved_q = 0;
+      c.curved_ids.clear();
+      c.curved_nodes.clear();
+      c.assembled = false;
+      return;
+    }
+    require(c.dim == 2, SDG_EUNSUPPORTED, "curved elements are supported in 2D");
+    require(c.period.empty() && c.n_mesh == 1, SDG_EUNSUPPORTED,
+            "curved elements need a single non-periodic mesh");
+    require(q >= 1 && q <= 4, SDG_EINVAL, "geometry degree must be 1..4");
+    require(elem_ids && nodes, SDG_EINVAL, "null curved-element array");
+    const int64_t nq = (int64_t)(q + 1) * (q + 2) / 2;
+    clear_sources(c);  // their basis values depend on the geometry
+    c.curved_q = q;
+    c.curved_ids.assign(elem_ids, elem_ids + n_curved);
+    c.curved_nodes.assign(nodes, nodes + n_curved * nq * c.dim);
     c.assembled = false;
   });
 }
@@ -498,6 +530,9 @@ int sdg_set_mesh_batch(sdg_ctx* ctx, int dim, int n_mesh, const int64_t* vert_of
     c.mesh_vert_off.assign(vert_off, vert_off + n_mesh + 1);
     c.mesh_elem_off.assign(elem_off, elem_off + n_mesh + 1);
     clear_sources(c);
+    c.curved_q = 0;
+    c.curved_ids.clear();
+    c.curved_nodes.clear();
     c.have_mesh = true;
     c.assembled = false;
   });
@@ -603,8 +638,13 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     HostSetup& hs = c.hs;
     const int64_t n_elem = (int64_t)(c.elem.size() / (c.dim + 1));
     const int64_t n_vert = (int64_t)(c.xyz.size() / c.dim);
+    CurvedInput cin;
+    cin.q = c.curved_q;
+    cin.n = (int64_t)c.curved_ids.size();
+    cin.ids = c.curved_ids.data();
+    cin.nodes = c.curved_nodes.data();
     build_host_setup(hs, c.dim, n_vert, c.xyz.data(), n_elem, c.elem.data(), c.period.empty() ? nullptr : c.period.data(),
-                     c.p, c.pg, c.scheme, c.dt, c.lam.data(), c.mu.data(), c.rho.data());
+                     c.p, c.pg, c.scheme, c.dt, c.lam.data(), c.mu.data(), c.rho.data(), &cin);
     hs.face_E.clear();
     hs.face_Cw.clear();
     if (c.aniso) set_anisotropic_faces(hs, c.elemE.data());
@@ -674,6 +714,26 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
       for (int64_t e = 0; e < hs.n_elem; ++e) wi[e] = 1.0 / hs.elem_w[e];
       c.d_winv.alloc(wi.size());
       SDG_HIP(hipMemcpy(c.d_winv.p, wi.data(), wi.size() * sizeof(double), hipMemcpyHostToDevice));
+      // curved elements: their own mass matrices and inverses
+      c.d_curved_idx.free();
+      c.d_curved_M.free();
+      c.d_curved_Minv.free();
+      if (!hs.curved_ids.empty()) {
+        c.d_curved_idx.alloc(hs.curved_idx.size());
+        SDG_HIP(hipMemcpy(c.d_curved_idx.p, hs.curved_idx.data(), hs.curved_idx.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+        c.d_curved_M.alloc(hs.curved_M.size());
+        SDG_HIP(hipMemcpy(c.d_curved_M.p, hs.curved_M.data(), hs.curved_M.size() * sizeof(double),
+                          hipMemcpyHostToDevice));
+        std::vector<double> Ci(hs.curved_M.size());
+        for (size_t k = 0; k < hs.curved_ids.size(); ++k) {
+          std::vector<double> Mk(hs.curved_M.begin() + k * nphi * nphi, hs.curved_M.begin() + (k + 1) * nphi * nphi);
+          std::vector<double> Mi2 = inverse(Mk, nphi);
+          std::copy(Mi2.begin(), Mi2.end(), Ci.begin() + k * nphi * nphi);
+        }
+        c.d_curved_Minv.alloc(Ci.size());
+        SDG_HIP(hipMemcpy(c.d_curved_Minv.p, Ci.data(), Ci.size() * sizeof(double), hipMemcpyHostToDevice));
+      }
     }
     c.d_Pblk.free();
     c.d_Pq.free();
@@ -911,6 +971,7 @@ int sdg_query(const sdg_ctx* ctx, sdg_sizes* out) {
     out->op_bvariant_f32 = c.bvariant32;
     out->reserved0 = 0;
     for (int v = 0; v < 3; ++v) out->tune_us_batched_f32[v] = c.tune_b32_us[v];
+    for (int w = 0; w < 2; ++w) out->proj_min_degree[w] = c.assembled ? projection_min_degree(c.hs, w) : 0;
     for (int v = 0; v < kNumVariants; ++v) { out->tune_us_f64[v] = c.tune_us[0][v]; out->tune_us_f32[v] = c.tune_us[1][v]; }
   });
 }
@@ -1351,6 +1412,7 @@ int sdg_adjoint_step(sdg_ctx* ctx, const double* v_old, const double* v_slab, do
     require(opts->precision == 0 || opts->precision == SDG_PREC_F64, SDG_EUNSUPPORTED,
             "the adjoint step runs in FP64");
     require(!c.aniso, SDG_EUNSUPPORTED, "the adjoint step takes an isotropic material");
+    require(c.hs.curved_ids.empty(), SDG_EUNSUPPORTED, "the adjoint step takes straight elements");
     check_prec(c, SDG_PREC_F64);
     int solver = opts->solver;
     if (solver == SDG_SOLVER_AUTO) solver = c.scheme == SDG_SCHEME_CN ? SDG_SOLVER_CG : SDG_SOLVER_GMRES;

@@ -141,6 +141,11 @@ struct Ctx {
   int p = 0, pg = 0, scheme = 0;
   double dt = 0.0;
   std::vector<double> lam, mu, rho;
+  // curved elements given by sdg_set_curved_elements (geometry degree, ids,
+  // nodes); cleared with the mesh
+  int curved_q = 0;
+  std::vector<int64_t> curved_ids;
+  std::vector<double> curved_nodes;
   // anisotropic material: per-element Voigt stiffness (n_elem * n_sigma^2)
   bool aniso = false;
   std::vector<double> elemE;
@@ -157,6 +162,11 @@ struct Ctx {
   DevBuf<double> d_face_lm, d_elem_w, d_Mref;
   DevBuf<double> d_face_E, d_face_Cw;  // anisotropic dual material (empty when isotropic)
   DevBuf<int> d_face_sys, d_elem_sys;   // mesh of each face / element (mesh batches only)
+  // curved elements: index per element (-1 straight), their mass matrices
+  // and the inverses of those (mass preconditioner); empty without curved
+  // elements
+  DevBuf<int32_t> d_curved_idx;
+  DevBuf<double> d_curved_M, d_curved_Minv;
   DevBuf<double> d_z;  // element face slots
   Coefs op{}, adj{};   // operator and its transpose
   int variant64 = 0, variant32 = 0;   // face-kernel variant per precision (autotuned)

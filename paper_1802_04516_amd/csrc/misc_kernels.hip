@@ -89,6 +89,7 @@ __device__ inline double wsum(double v) {
 // Partial energies per block -> partials[block]; k_energy_fin adds them.
 template <int D>
 __global__ void k_energy(int64_t n_elem, int64_t n_face, int nphi, int npsi, const double* __restrict__ Mref,
+                         const int32_t* __restrict__ cidx, const double* __restrict__ cM,
                          const double* __restrict__ ew, const double* __restrict__ flm,
                          const double* __restrict__ fcw, const double* __restrict__ v,
                          const double* __restrict__ sig, double* partials) {
@@ -100,10 +101,12 @@ __global__ void k_energy(int64_t n_elem, int64_t n_face, int nphi, int npsi, con
     if (i < nk) {
       const int64_t e = i / D;
       const double* vb = v + i * nphi;
+      // a curved element's own mass matrix (Section 3 maps), else Mref
+      const double* M = (cidx != nullptr && cidx[e] >= 0) ? cM + (int64_t)cidx[e] * nphi * nphi : Mref;
       double q = 0.0;
       for (int k = 0; k < nphi; ++k) {
         double mv = 0.0;
-        for (int kk = 0; kk < nphi; ++kk) mv += Mref[k * nphi + kk] * vb[kk];
+        for (int kk = 0; kk < nphi; ++kk) mv += M[k * nphi + kk] * vb[kk];
         q += vb[k] * mv;
       }
       acc += 0.5 * ew[e] * q;
@@ -305,11 +308,13 @@ void launch_energy(Ctx& c, const double* v, const double* sig, double* out_dev, 
   const double* vv = v + e0 * hs.dim * hs.nphi;
   const double* ss = sig + f0 * hs.nsig * hs.npsi;
   if (hs.dim == 2)
-    k_energy<2><<<g, kT, 0, s>>>(ne, nf, hs.nphi, hs.npsi, c.d_Mref.p, c.d_elem_w.p + e0, c.d_face_lm.p + 2 * f0,
+    k_energy<2><<<g, kT, 0, s>>>(ne, nf, hs.nphi, hs.npsi, c.d_Mref.p, c.d_curved_idx.p ? c.d_curved_idx.p + e0 : nullptr,
+                                 c.d_curved_M.p, c.d_elem_w.p + e0, c.d_face_lm.p + 2 * f0,
                                  c.d_face_Cw.p ? c.d_face_Cw.p + f0 * hs.nsig * hs.nsig : nullptr, vv,
                                  ss, c.d_partials.p);
   else
-    k_energy<3><<<g, kT, 0, s>>>(ne, nf, hs.nphi, hs.npsi, c.d_Mref.p, c.d_elem_w.p + e0, c.d_face_lm.p + 2 * f0,
+    k_energy<3><<<g, kT, 0, s>>>(ne, nf, hs.nphi, hs.npsi, c.d_Mref.p, nullptr, nullptr, c.d_elem_w.p + e0,
+                                 c.d_face_lm.p + 2 * f0,
                                  c.d_face_Cw.p ? c.d_face_Cw.p + f0 * hs.nsig * hs.nsig : nullptr, vv,
                                  ss, c.d_partials.p);
   SDG_HIP(hipGetLastError());

@@ -67,21 +67,43 @@ struct HostSetup {
   // W E^-1 (W = 1 on normal, 2 on shear components) for the energy
   std::vector<double> face_E, face_Cw;
   std::vector<double> face_wt;          // n_face*2: |T_{left,j}|/|R_j|, |T_{right,j}|/|R_j| (1, 0 on the boundary)
-  std::vector<double> elem_w;           // n_elem: rho_i |det J_i|
+  std::vector<double> elem_w;           // n_elem: rho_i |det J_i| (rho_i for a curved element)
   std::vector<double> elem_detJ;        // n_elem
   std::vector<double> elem_rho;         // n_elem
   std::vector<double> Mref;             // nphi*nphi reference mass matrix
   // unwrapped element vertices (n_elem*(dim+1)*dim) for point location
   std::vector<double> elem_xyz;
+  // curved elements (2D; Section 3, sub-/iso-parametric maps of degree
+  // curved_q): index of each element in the curved list (-1: straight),
+  // their geometry nodes [c][node][dim] in the velocity node order of degree
+  // curved_q, and their mass int phi_k phi_m (without rho; a curved element's
+  // mass is elem_w * curved_M, a straight one's elem_w * Mref)
+  int curved_q = 0;
+  std::vector<int32_t> curved_idx;
+  std::vector<int64_t> curved_ids;
+  std::vector<double> curved_nodes;
+  std::vector<double> curved_M;
   // time basis
   std::vector<double> tau, w, e0, e1, T;  // T is ng*ng row-major
   std::vector<double> Ext;                 // ng*ng: time basis of the slab evaluated on the next slab
 };
 
+// Curved elements given to build_host_setup: n elements (ids), each with
+// its (q+1)(q+2)/2 geometry nodes (nodes[c][node][2]).
+struct CurvedInput {
+  int q = 0;
+  int64_t n = 0;
+  const int64_t* ids = nullptr;
+  const double* nodes = nullptr;
+};
+
 // Build topology, geometry, bases and blocks.  Throws Error.
 void build_host_setup(HostSetup& hs, int dim, int64_t n_vert, const double* xyz, int64_t n_elem,
                       const int64_t* elem, const double* period, int p, int pg, int scheme,
-                      double dt, const double* lam, const double* mu, const double* rho);
+                      double dt, const double* lam, const double* mu, const double* rho,
+                      const CurvedInput* curved = nullptr);
+// Mass of element e (rho included): elem_w[e] * (curved_M or Mref)[k][m].
+double elem_mass(const HostSetup& hs, int64_t e, int k, int m);
 
 // Nodal basis values of element e at physical point x (nphi values); returns
 // false if x is not in the closed element (tolerance tol in barycentric units).
@@ -201,6 +223,11 @@ struct OpArgs {
   int mask_stride = 0;
   const int* face_sys = nullptr;
   const int* elem_sys = nullptr;
+  // curved elements (Section 3, sub-/iso-parametric maps): the element
+  // kernels take element e's mass matrix from curved_M + curved_idx[e] *
+  // N_phi^2 instead of Mref when curved_idx[e] >= 0 (null: no curved element)
+  const int32_t* curved_idx = nullptr;
+  const double* curved_M = nullptr;
 };
 
 // Launch the face kernel and/or the element kernel for (dim, p, NG).

@@ -397,6 +397,109 @@ void phys_eval(const VelBasis& vb, const double* V, const double* Jinv, const do
       }
 }
 
+// Map of degree q of a curved element (Section 3, sub-/iso-parametric
+// maps): x(xi) = sum_a X_a N_a(xi) with N_a the equispaced Lagrange basis of
+// degree q (velocity node order) and X_a the element's geometry nodes.
+struct CurvedGeom {
+  int d, q;
+  const double* X;  // nodes [a][c]
+  VelBasis gb;
+  CurvedGeom(int d_, int q_, const double* X_) : d(d_), q(q_), X(X_), gb(d_, q_) {}
+  // x(xi) and J[c][b] = d x_c / d xi_b; returns det J
+  double map(const double* xi, double* x, double* J) const {
+    double val[64], grad[64 * 3];
+    gb.eval(xi, val, grad);
+    for (int c = 0; c < d; ++c) {
+      double s = 0.0;
+      for (int a = 0; a < gb.n; ++a) s += val[a] * X[a * d + c];
+      x[c] = s;
+      for (int b = 0; b < d; ++b) {
+        double t = 0.0;
+        for (int a = 0; a < gb.n; ++a) t += grad[a * d + b] * X[a * d + c];
+        J[c * d + b] = t;
+      }
+    }
+    return d == 2 ? J[0] * J[3] - J[1] * J[2]
+                  : J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                        J[2] * (J[3] * J[7] - J[4] * J[6]);
+  }
+  // reference point of physical point x by Newton from the affine guess of
+  // the corner nodes; false if it does not converge
+  bool to_ref(const HostSetup& hs, int64_t e, const double* x, double* xi) const {
+    const double* V = &hs.elem_xyz[e * (d + 1) * d];
+    double Jinv[9];
+    det_and_inverse(V, d, Jinv);
+    for (int b = 0; b < d; ++b) {
+      double s = 0;
+      for (int c = 0; c < d; ++c) s += Jinv[b * d + c] * (x[c] - V[c]);
+      xi[b] = s;
+    }
+    for (int it = 0; it < 60; ++it) {
+      double xx[3], J[9], Ji[9];
+      map(xi, xx, J);
+      // invert J (2D here)
+      const double det = J[0] * J[3] - J[1] * J[2];
+      if (!(std::fabs(det) > 0.0)) return false;
+      Ji[0] = J[3] / det; Ji[1] = -J[1] / det; Ji[2] = -J[2] / det; Ji[3] = J[0] / det;
+      double step[2] = {Ji[0] * (xx[0] - x[0]) + Ji[1] * (xx[1] - x[1]),
+                        Ji[2] * (xx[0] - x[0]) + Ji[3] * (xx[1] - x[1])};
+      xi[0] -= step[0];
+      xi[1] -= step[1];
+      if (std::fabs(step[0]) + std::fabs(step[1]) <= 1e-15) return true;
+    }
+    return false;
+  }
+};
+
+CurvedGeom curved_geom(const HostSetup& hs, int64_t e) {
+  const int nq = (hs.curved_q + 1) * (hs.curved_q + 2) / 2;
+  return CurvedGeom(hs.dim, hs.curved_q, &hs.curved_nodes[(size_t)hs.curved_idx[e] * nq * hs.dim]);
+}
+
+bool is_curved(const HostSetup& hs, int64_t e) {
+  return e >= 0 && !hs.curved_idx.empty() && hs.curved_idx[e] >= 0;
+}
+
+// The element's barycentre: the image of the reference barycentre (the
+// vertex mean for a straight element, left unchanged).
+void curved_bary(const HostSetup& hs, int64_t e, double* b) {
+  if (!is_curved(hs, e)) return;
+  const double xi[3] = {1.0 / (hs.dim + 1), 1.0 / (hs.dim + 1), 1.0 / (hs.dim + 1)};
+  double J[9];
+  curved_geom(hs, e).map(xi, b, J);
+}
+
+// Rule over the sub-simplex T_{e,j} of a curved element e (local face f):
+// the reference rule of the reference sub-simplex (face f's reference
+// vertices and the reference barycentre), exact to total degree `deg` in
+// the reference coordinates, mapped: physical points x, reference points
+// xi, weights w |det J(xi)| (with the sub-simplex's volume factor).
+struct MappedRule {
+  std::vector<double> x, xi, w, J;  // J: d*d per point
+  int n() const { return (int)w.size(); }
+};
+MappedRule curved_sub_rule(const HostSetup& hs, int64_t e, int f, int deg) {
+  const int d = hs.dim;
+  std::vector<double> T;
+  for (int a = 0; a <= d; ++a) {
+    if (a == f) continue;
+    for (int b = 0; b < d; ++b) T.push_back(a > 0 && b == a - 1 ? 1.0 : 0.0);
+  }
+  for (int b = 0; b < d; ++b) T.push_back(1.0 / (d + 1));
+  Rule r = simplex_rule(T.data(), d, d, deg);
+  const CurvedGeom cg = curved_geom(hs, e);
+  MappedRule m;
+  m.x.resize((size_t)r.n() * d);
+  m.J.resize((size_t)r.n() * d * d);
+  m.xi = r.x;
+  m.w.resize(r.n());
+  for (int q = 0; q < r.n(); ++q) {
+    const double det = cg.map(&r.x[q * d], &m.x[q * d], &m.J[(size_t)q * d * d]);
+    m.w[q] = r.w[q] * std::fabs(det);
+  }
+  return m;
+}
+
 // Geometry of face j in the frame of its left element.
 struct FaceGeom {
   double X[9];            // face vertices, ordered by global vertex index
@@ -423,6 +526,7 @@ void face_geometry(const HostSetup& hs, const int64_t* elem, int64_t j, FaceGeom
   for (int c = 0; c < d; ++c) { g.bl[c] = 0; g.br[c] = 0; }
   for (int a = 0; a < nv; ++a)
     for (int c = 0; c < d; ++c) g.bl[c] += Vl[a * d + c] / nv;
+  curved_bary(hs, fr.left, g.bl);
   const bool interior = fr.right >= 0;
   if (interior) {
     const double* Vr0 = &hs.elem_xyz[(int64_t)fr.right * nv * d];
@@ -445,6 +549,7 @@ void face_geometry(const HostSetup& hs, const int64_t* elem, int64_t j, FaceGeom
     }
     for (int a = 0; a < nv; ++a)
       for (int c = 0; c < d; ++c) g.br[c] += g.Vr[a * d + c] / nv;
+    curved_bary(hs, fr.right, g.br);  // curved meshes are not periodic: no shift
   } else {
     for (int c = 0; c < d; ++c) {
       double mid = 0;
@@ -518,7 +623,17 @@ void build_dual(const HostSetup& hs, int64_t j, const FaceGeom& g, DualBasis& db
   vol[0] = vol[1] = 0.0;
   int nq = 0;
   for (int s = 0; s < (interior ? 2 : 1); ++s) {
-    Rule r = simplex_rule(g.Tsub[s], d, d, 2 * psi_deg);
+    const FaceRec& fr = hs.faces[j];
+    const int64_t e = s == 0 ? fr.left : fr.right;
+    Rule r;
+    if (is_curved(hs, e)) {
+      // psi_m psi_n |det J| in the reference coordinates
+      MappedRule m = curved_sub_rule(hs, e, s == 0 ? fr.lf : fr.rf, 2 * psi_deg * hs.curved_q + d * (hs.curved_q - 1));
+      r.x = m.x;
+      r.w = m.w;
+    } else {
+      r = simplex_rule(g.Tsub[s], d, d, 2 * psi_deg);
+    }
     for (int q = 0; q < r.n(); ++q, ++nq) {
       db.raw(&r.x[q * d], raw.data());
       vol[s] += r.w[q];
@@ -535,7 +650,8 @@ void build_dual(const HostSetup& hs, int64_t j, const FaceGeom& g, DualBasis& db
 
 void build_host_setup(HostSetup& hs, int dim, int64_t n_vert, const double* xyz, int64_t n_elem,
                       const int64_t* elem, const double* period, int p, int pg, int scheme,
-                      double dt, const double* lam, const double* mu, const double* rho) {
+                      double dt, const double* lam, const double* mu, const double* rho,
+                      const CurvedInput* curved) {
   require(dim == 2 || dim == 3, SDG_EINVAL, "dim must be 2 or 3");
   require(n_elem > 0 && n_vert > 0, SDG_EINVAL, "empty mesh");
   const int d = dim, nv = dim + 1;
@@ -577,6 +693,42 @@ void build_host_setup(HostSetup& hs, int dim, int64_t n_vert, const double* xyz,
     require(std::isfinite(det) && std::fabs(det) > 1e-12 * std::pow(scale, d), SDG_EMESH,
             "degenerate element " + std::to_string(e));
     hs.elem_detJ[e] = std::fabs(det);
+  }
+
+  // --- curved elements: geometry nodes of degree q whose corner nodes are
+  // the element's vertices
+  hs.curved_q = 0;
+  hs.curved_idx.clear();
+  hs.curved_ids.clear();
+  hs.curved_nodes.clear();
+  hs.curved_M.clear();
+  if (curved && curved->n > 0) {
+    require(d == 2, SDG_EUNSUPPORTED, "curved elements are supported in 2D");
+    require(!period, SDG_EUNSUPPORTED, "curved elements on a periodic mesh");
+    require(curved->q >= 1 && curved->q <= 4, SDG_EINVAL, "geometry degree must be 1..4");
+    require(curved->ids && curved->nodes, SDG_EINVAL, "null curved-element array");
+    const int q = curved->q, nq = (q + 1) * (q + 2) / 2;
+    hs.curved_q = q;
+    hs.curved_idx.assign(n_elem, -1);
+    const int corner[3] = {0, q, nq - 1};  // nodes at xi = (0,0), (1,0), (0,1)
+    for (int64_t c = 0; c < curved->n; ++c) {
+      const int64_t e = curved->ids[c];
+      require(e >= 0 && e < n_elem, SDG_EINVAL, "curved element index out of range");
+      require(hs.curved_idx[e] < 0, SDG_EINVAL, "curved element listed twice");
+      const double* X = curved->nodes + (size_t)c * nq * d;
+      const double* V = &hs.elem_xyz[e * nv * d];
+      double scale = 1.0;
+      for (int a = 0; a < nv * d; ++a) scale = std::max(scale, std::fabs(V[a]));
+      for (int a = 0; a < nv; ++a)
+        for (int k = 0; k < d; ++k) {
+          require(std::isfinite(X[corner[a] * d + k]), SDG_EINVAL, "non-finite geometry node");
+          require(std::fabs(X[corner[a] * d + k] - V[a * d + k]) <= 1e-12 * scale, SDG_EMESH,
+                  "curved element " + std::to_string(e) + ": corner nodes differ from its vertices");
+        }
+      hs.curved_idx[e] = (int32_t)hs.curved_ids.size();
+      hs.curved_ids.push_back(e);
+      hs.curved_nodes.insert(hs.curved_nodes.end(), X, X + (size_t)nq * d);
+    }
   }
 
   // --- faces: sort (sorted vertex key, elem, local face)
@@ -630,12 +782,38 @@ void build_host_setup(HostSetup& hs, int dim, int64_t n_vert, const double* xyz,
     else ++hs.n_bface;
   }
 
+  // a curved element's faces shared with another element must be straight:
+  // their geometry nodes at the affine positions (a boundary face may curve)
+  if (hs.curved_q > 0) {
+    const int q = hs.curved_q, nq = (q + 1) * (q + 2) / 2;
+    VelBasis gb(d, q);
+    for (int64_t e : hs.curved_ids) {
+      const double* X = &hs.curved_nodes[(size_t)hs.curved_idx[e] * nq * d];
+      const double* V = &hs.elem_xyz[e * nv * d];
+      double scale = 1.0;
+      for (int a = 0; a < nv * d; ++a) scale = std::max(scale, std::fabs(V[a]));
+      for (int f = 0; f < nv; ++f) {
+        if (hs.faces[hs.elem_face[e * nv + f]].right < 0) continue;
+        for (int k = 0; k < nq; ++k) {
+          if (gb.alpha[k][f] != 0) continue;  // node not on local face f
+          for (int c = 0; c < d; ++c) {
+            double xa = 0.0;
+            for (int a = 0; a < nv; ++a) xa += gb.alpha[k][a] / (double)q * V[a * d + c];
+            require(std::fabs(X[k * d + c] - xa) <= 1e-12 * scale, SDG_EMESH,
+                    "curved element " + std::to_string(e) + ": a face shared with another element is not straight");
+          }
+        }
+      }
+    }
+  }
+
   // --- material and reference mass
   hs.elem_rho.assign(rho, rho + n_elem);
   hs.elem_w.resize(n_elem);
   for (int64_t e = 0; e < n_elem; ++e) {
     require(rho[e] > 0 && lam[e] >= 0 && mu[e] > 0, SDG_EINVAL, "material must be positive");
-    hs.elem_w[e] = rho[e] * hs.elem_detJ[e];
+    // a curved element's mass is rho times its own matrix (curved_M)
+    hs.elem_w[e] = is_curved(hs, e) ? rho[e] : rho[e] * hs.elem_detJ[e];
   }
   VelBasis vb(d, p);
   {
@@ -648,6 +826,24 @@ void build_host_setup(HostSetup& hs, int dim, int64_t n_vert, const double* xyz,
       vb.eval(&r.x[q * d], val.data(), nullptr);
       for (int k = 0; k < hs.nphi; ++k)
         for (int m = 0; m < hs.nphi; ++m) hs.Mref[k * hs.nphi + m] += r.w[q] * val[k] * val[m];
+    }
+    // curved elements: int phi_k phi_m |det J| on the reference element
+    if (hs.curved_q > 0) {
+      const int q = hs.curved_q, nq = (q + 1) * (q + 2) / 2;
+      Rule rc = simplex_rule(Vref.data(), d, d, 2 * p + d * (q - 1));
+      hs.curved_M.assign(hs.curved_ids.size() * hs.nphi * hs.nphi, 0.0);
+      for (size_t c = 0; c < hs.curved_ids.size(); ++c) {
+        CurvedGeom cg(d, q, &hs.curved_nodes[c * nq * d]);
+        double* M = &hs.curved_M[c * hs.nphi * hs.nphi];
+        for (int qq = 0; qq < rc.n(); ++qq) {
+          double x[3], J[9];
+          const double det = cg.map(&rc.x[qq * d], x, J);
+          require(det > 0.0, SDG_EMESH, "curved element " + std::to_string(hs.curved_ids[c]) + " is folded");
+          vb.eval(&rc.x[qq * d], val.data(), nullptr);
+          for (int k = 0; k < hs.nphi; ++k)
+            for (int m = 0; m < hs.nphi; ++m) M[k * hs.nphi + m] += rc.w[qq] * det * val[k] * val[m];
+        }
+      }
     }
   }
 
@@ -715,7 +911,35 @@ void build_host_setup(HostSetup& hs, int dim, int64_t n_vert, const double* xyz,
           double Jinv[9];
           det_and_inverse(Ve, d, Jinv);
           double* out = &hs.Dt[((size_t)j * 2 + s) * blk];
-          Rule r = simplex_rule(fg.Tsub[s], d, d, std::max(p - 1, 0) + psi_deg);
+          const int64_t es = s == 0 ? fr.left : fr.right;
+          if (is_curved(hs, es)) {
+            // -int d_l phi_k psi_m over the curved T_{i,j}: the reference
+            // gradient through J(xi)^-T, times |det J| (together adj J)
+            const int q = hs.curved_q;
+            MappedRule m = curved_sub_rule(hs, es, s == 0 ? fr.lf : fr.rf,
+                                           std::max(p - 1, 0) + psi_deg * q + (d - 1) * (q - 1));
+            std::vector<double> gref(nphi * d);
+            for (int qq = 0; qq < m.n(); ++qq) {
+              const double* J = &m.J[(size_t)qq * d * d];
+              const double det = J[0] * J[3] - J[1] * J[2];
+              const double Ji[4] = {J[3] / det, -J[1] / det, -J[2] / det, J[0] / det};  // Ji[b][c]
+              vb.eval(&m.xi[qq * d], phi.data(), gref.data());
+              for (int k = 0; k < nphi; ++k)
+                for (int l = 0; l < d; ++l) {
+                  double sgl = 0.0;
+                  for (int b = 0; b < d; ++b) sgl += Ji[b * d + l] * gref[k * d + b];
+                  gphi[k * d + l] = sgl;
+                }
+              db.canonical(&m.x[qq * d], psi.data());
+              for (int k = 0; k < nphi; ++k)
+                for (int l = 0; l < d; ++l) {
+                  double f = -m.w[qq] * gphi[k * d + l];
+                  double* o = out + (k * d + l) * npsi;
+                  for (int mm = 0; mm < npsi; ++mm) o[mm] += f * psi[mm];
+                }
+            }
+          }
+          Rule r = is_curved(hs, es) ? Rule() : simplex_rule(fg.Tsub[s], d, d, std::max(p - 1, 0) + psi_deg);
           for (int qq = 0; qq < r.n(); ++qq) {
             const double* x = &r.x[qq * d];
             phys_eval(vb, Ve, Jinv, x, phi.data(), gphi.data());
@@ -763,8 +987,31 @@ void build_host_setup(HostSetup& hs, int dim, int64_t n_vert, const double* xyz,
   if (err_code) throw Error(err_code, err_msg);
 }
 
+double elem_mass(const HostSetup& hs, int64_t e, int k, int m) {
+  const int n = hs.nphi;
+  if (is_curved(hs, e)) return hs.elem_w[e] * hs.curved_M[((size_t)hs.curved_idx[e] * n + k) * n + m];
+  return hs.elem_w[e] * hs.Mref[k * n + m];
+}
+
 bool eval_velocity_basis(const HostSetup& hs, int64_t e, const double* x, double* phi, double tol) {
   const int d = hs.dim, nv = d + 1;
+  if (is_curved(hs, e)) {
+    // reference point by Newton on the element's map (the affine guess first
+    // rejects points far outside)
+    double xi[3];
+    if (!curved_geom(hs, e).to_ref(hs, e, x, xi)) return false;
+    double lam0 = 1.0;
+    for (int b = 0; b < d; ++b) {
+      if (xi[b] < -tol) return false;
+      lam0 -= xi[b];
+    }
+    if (lam0 < -tol) return false;
+    if (phi) {
+      VelBasis vb(d, hs.p);
+      vb.eval(xi, phi, nullptr);
+    }
+    return true;
+  }
   const double* V = &hs.elem_xyz[e * nv * d];
   double Jinv[9];
   det_and_inverse(V, d, Jinv);
@@ -974,6 +1221,12 @@ void build_compressed(const HostSetup& hs, const int64_t* elem, CompressedOp& ou
 // tensor products), and the projected data is at least of degree p.
 int projection_min_degree(const HostSetup& hs, int which) {
   const int psi_deg = hs.dim == 2 ? 2 * hs.p : hs.p;
+  if (hs.curved_q > 1) {
+    // curved elements integrate in reference coordinates: phi phi |det J|,
+    // and psi (degree psi_deg + p data) composed with the map, times |det J|
+    const int q = hs.curved_q, jd = hs.dim * (q - 1);
+    return which == 0 ? 2 * hs.p + jd : (psi_deg + hs.p) * q + jd;
+  }
   return which == 0 ? 2 * hs.p : psi_deg + hs.p;
 }
 
@@ -989,7 +1242,19 @@ void projection_points(const HostSetup& hs, const int64_t* elem, int which, int 
   const int d = hs.dim, nv = d + 1;
   const int nq = projection_rule_size(hs, which, degree);
   if (which == 0) {
+    std::vector<double> Vref(nv * d, 0.0);
+    for (int a = 0; a < d; ++a) Vref[(a + 1) * d + a] = 1.0;
+    const Rule rref = simplex_rule(Vref.data(), d, d, degree);
     parallel_for(hs.n_elem, [&](int64_t e) {
+      if (is_curved(hs, e)) {  // the reference rule mapped, weights times |det J|
+        const CurvedGeom cg = curved_geom(hs, e);
+        for (int q = 0; q < nq; ++q) {
+          double J[9];
+          const double det = cg.map(&rref.x[q * d], &pts[(e * nq + q) * d], J);
+          if (wts) wts[e * nq + q] = rref.w[q] * std::fabs(det);
+        }
+        return;
+      }
       Rule r = simplex_rule(&hs.elem_xyz[e * nv * d], d, d, degree);
       for (int q = 0; q < nq; ++q) {
         for (int c = 0; c < d; ++c) pts[(e * nq + q) * d + c] = r.x[q * d + c];
@@ -1006,7 +1271,17 @@ void projection_points(const HostSetup& hs, const int64_t* elem, int which, int 
     for (int s = 0; s < 2; ++s) {
       // a free-surface dual element is T_{l,j} alone: its second half of
       // points repeats the first with zero weights
-      Rule r = simplex_rule(fg.Tsub[interior ? s : 0], d, d, degree);
+      const int sd = interior ? s : 0;
+      const FaceRec& fr = hs.faces[j];
+      const int64_t e = sd == 0 ? fr.left : fr.right;
+      Rule r;
+      if (is_curved(hs, e)) {
+        MappedRule m = curved_sub_rule(hs, e, sd == 0 ? fr.lf : fr.rf, degree);
+        r.x = m.x;
+        r.w = m.w;
+      } else {
+        r = simplex_rule(fg.Tsub[sd], d, d, degree);
+      }
       for (int q = 0; q < half; ++q) {
         const int64_t o = j * nq + s * half + q;
         for (int c = 0; c < d; ++c) pts[o * d + c] = r.x[q * d + c];
@@ -1031,10 +1306,27 @@ void project_values(const HostSetup& hs, const int64_t* elem, int which, int deg
     for (int q = 0; q < nq; ++q) vb.eval(&r.x[q * d], &Phi[(size_t)q * nphi], nullptr);
     parallel_for(hs.n_elem, [&](int64_t e) {
       std::vector<double> B((size_t)nphi * d, 0.0);  // [k][c]
+      const bool cur = is_curved(hs, e);
+      std::vector<double> wq(r.w);
+      if (cur) {  // a curved element's integral carries |det J|, its mass is curved_M
+        const CurvedGeom cg = curved_geom(hs, e);
+        for (int q = 0; q < nq; ++q) {
+          double x[3], J[9];
+          wq[q] *= std::fabs(cg.map(&r.x[q * d], x, J));
+        }
+      }
       for (int q = 0; q < nq; ++q) {
         const double* f = values + (e * nq + q) * d;
         for (int k = 0; k < nphi; ++k)
-          for (int c = 0; c < d; ++c) B[k * d + c] += r.w[q] * Phi[(size_t)q * nphi + k] * f[c];
+          for (int c = 0; c < d; ++c) B[k * d + c] += wq[q] * Phi[(size_t)q * nphi + k] * f[c];
+      }
+      if (cur) {
+        std::vector<double> Mc(&hs.curved_M[(size_t)hs.curved_idx[e] * nphi * nphi],
+                               &hs.curved_M[(size_t)(hs.curved_idx[e] + 1) * nphi * nphi]);
+        solve_dense(Mc, B, nphi, d);
+        for (int c = 0; c < d; ++c)
+          for (int k = 0; k < nphi; ++k) out[(e * d + c) * nphi + k] = B[k * d + c];
+        return;
       }
       solve_dense(hs.Mref, B, nphi, d);
       for (int c = 0; c < d; ++c)
@@ -1271,7 +1563,7 @@ BlockPrecond block_inverses(const HostSetup& hs, const Coefs& op) {
         for (int i2 = 0; i2 < ns; ++i2) {
           const int c = i / nphi, k = i % nphi, c2 = i2 / nphi, k2 = i2 % nphi;
           double v = op.Cg[0] * K[i * ns + i2];
-          if (c == c2) v += op.Tm[0] * hs.elem_w[e] * hs.Mref[k * nphi + k2];
+          if (c == c2) v += op.Tm[0] * elem_mass(hs, e, k, k2);
           Dm[i * nv + i2] = v;
         }
       if (!gj_inverse(Dm, nv, Inv)) { err = 1; return; }
@@ -1284,35 +1576,39 @@ BlockPrecond block_inverses(const HostSetup& hs, const Coefs& op) {
     return out;
   }
   // Several time nodes: the diagonal block is Tm (x) M_e + Cg (x) K_e with
-  // M_e = rho_e|J_e| (I (x) Mref).  With the generalised eigenvectors
+  // M_e = rho_e|J_e| (I (x) Mref) (rho_e (I (x) curved_M) on a curved element).  With the generalised eigenvectors
   // K_e Q = M_e Q Lambda, Q^T M_e Q = I, it factors as
   //   (I (x) Q^-T) (Tm (x) I + Cg (x) Lambda) (I (x) Q^-1),
   // whose inverse is (I (x) Q) blockdiag_i (Tm + lambda_i Cg)^-1 (I (x) Q^T).
   // Stored per element: Q (ns x ns, row-major [ck][i]) and the ns inverses
   // (ng x ng, row-major [a][b]).
-  std::vector<double> Lref((size_t)nphi * nphi, 0.0);
-  {
-    const std::vector<double>& M = hs.Mref;
+  // inverse of the Cholesky factor of a mass matrix M (nphi x nphi)
+  auto chol_inverse = [nphi](const double* M, std::vector<double>& Linv) {
+    std::vector<double> L((size_t)nphi * nphi, 0.0);
     for (int i = 0; i < nphi; ++i)
       for (int j = 0; j <= i; ++j) {
         double s = M[i * nphi + j];
-        for (int k = 0; k < j; ++k) s -= Lref[i * nphi + k] * Lref[j * nphi + k];
+        for (int k = 0; k < j; ++k) s -= L[i * nphi + k] * L[j * nphi + k];
         if (i == j) {
-          require(s > 0.0, SDG_EMESH, "reference mass matrix is not positive definite");
-          Lref[i * nphi + i] = std::sqrt(s);
+          if (!(s > 0.0)) return false;
+          L[i * nphi + i] = std::sqrt(s);
         } else {
-          Lref[i * nphi + j] = s / Lref[j * nphi + j];
+          L[i * nphi + j] = s / L[j * nphi + j];
         }
       }
-  }
-  std::vector<double> Linv;  // inverse of the lower-triangular factor
-  require(gj_inverse(Lref, nphi, Linv), SDG_EMESH, "reference mass matrix is singular");
+    return gj_inverse(L, nphi, Linv);
+  };
+  std::vector<double> Linv_ref;
+  require(chol_inverse(hs.Mref.data(), Linv_ref), SDG_EMESH, "reference mass matrix is not positive definite");
   out.Q.resize((size_t)hs.n_elem * ns * ns);
   out.B.resize((size_t)hs.n_elem * ns * ng * ng);
   parallel_for(hs.n_elem, [&](int64_t e) {
-    std::vector<double> K, C((size_t)ns * ns), lam, U, Bi((size_t)ng * ng), BiInv;
+    std::vector<double> K, C((size_t)ns * ns), lam, U, Bi((size_t)ng * ng), BiInv, Lc;
     element_stiffness(hs, e, K);
     const double w = hs.elem_w[e], sw = std::sqrt(w);
+    const bool curved_e = is_curved(hs, e);
+    if (curved_e && !chol_inverse(&hs.curved_M[(size_t)hs.curved_idx[e] * nphi * nphi], Lc)) { err = 1; return; }
+    const std::vector<double>& Linv = curved_e ? Lc : Linv_ref;
     // C = L^-1 K L^-T with L = sqrt(w) (I (x) Lref)
     auto Li = [&](int r, int col) {  // (I (x) Linv)[r][col]
       const int c = r / nphi, k = r % nphi, c2 = col / nphi, k2 = col % nphi;
@@ -1398,7 +1694,7 @@ PatchPrecond patch_inverses(const HostSetup& hs, const Coefs& op) {
             for (int cc = 0; cc < ns; ++cc) {
               double v = cg * Ks[(size_t)r * ns + cc];
               if (mass && r / nphi == cc / nphi)
-                v += tm * hs.elem_w[st[p]] * hs.Mref[(r % nphi) * nphi + cc % nphi];
+                v += tm * elem_mass(hs, st[p], r % nphi, cc % nphi);
               A[(size_t)(p * nb + a * ns + r) * n + q * nb + b * ns + cc] += v;
             }
         }

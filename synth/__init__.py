@@ -37,6 +37,7 @@ __all__ = [
     "top_edge_receivers",
     "with_slivers",
     "inradius",
+    "disk_mesh",
     "ragged_meshes",
     "workload",
 ]
@@ -147,6 +148,87 @@ def split_square(n: int, m: int | None = None, *, jitter: float = 0.0,
     return Mesh(xyz=xyz, elem=elem, period=period,
                 meta=dict(kind="split_square", n=n, m=m, jitter=jitter, seed=seed,
                           periodic=periodic, diagonal=diagonal))
+
+
+def disk_mesh(n: int, *, radius: float = 1.0, q: int = 2, jitter: float = 0.0, seed: int | None = None) -> Mesh:
+    """Triangulation of the disk of the given radius: the triangular lattice
+    of a hexagon of n rings, ring k (k = 1..n) placed on the circle of radius
+    k/n * radius with its 6k vertices at equal angles (vertex 0 at angle 0 of
+    ring k is the lattice point on the first hexagon corner).  Counter-
+    clockwise triangles.  ``jitter`` moves interior vertices radially and in
+    angle by U(-jitter, jitter) times the ring spacing.
+
+    Curved boundary (Section 3, iso-/sub-parametric maps): every triangle
+    with an edge on the circle gets geometry nodes of degree q (the
+    equispaced nodes of the reference triangle, in the velocity node order)
+    placed by the affine map, except that the nodes inside its boundary edge
+    move onto the circle at equally spaced angles between the edge's end
+    vertices.  meta["curved"] = (elem ids (n_c,), nodes (n_c, N_q, 2)).
+    """
+    rng = np.random.default_rng(seed)
+    # axial hexagon lattice points with their ring and position along the ring
+    corners = [(1, 0), (0, 1), (-1, 1), (-1, 0), (0, -1), (1, -1)]
+    index = {(0, 0): 0}
+    pts = [(0.0, 0.0)]
+    for k in range(1, n + 1):
+        for side in range(6):
+            c0, c1 = corners[side], corners[(side + 1) % 6]
+            for t in range(k):
+                a_ = (k * c0[0] + t * (c1[0] - c0[0]), k * c0[1] + t * (c1[1] - c0[1]))
+                pos = side * k + t
+                ang = 2.0 * np.pi * pos / (6 * k)
+                r = k / n * radius
+                if 0 < k < n and jitter > 0.0:
+                    r += rng.uniform(-jitter, jitter) * radius / n
+                    ang += rng.uniform(-jitter, jitter) * 2.0 * np.pi / (6 * k)
+                index[a_] = len(pts)
+                pts.append((r * np.cos(ang), r * np.sin(ang)))
+    xyz = np.array(pts)
+
+    def hexdist(a_):
+        x, y = a_
+        return max(abs(x), abs(y), abs(x + y))
+
+    elem = []
+    # the two lattice triangles with first corner (x, y): neighbours differ
+    # by (1, 0), (0, 1) or (-1, 1)
+    for (x, y) in sorted(index, key=lambda a_: index[a_]):
+        for tri in (((x, y), (x + 1, y), (x, y + 1)), ((x, y), (x + 1, y - 1), (x + 1, y))):
+            if all(v in index for v in tri) and max(hexdist(v) for v in tri) <= n:
+                ids = [index[v] for v in tri]
+                P = xyz[ids]
+                area = (P[1, 0] - P[0, 0]) * (P[2, 1] - P[0, 1]) - (P[2, 0] - P[0, 0]) * (P[1, 1] - P[0, 1])
+                elem.append(ids if area > 0 else [ids[0], ids[2], ids[1]])
+    elem = np.array(elem, dtype=np.int64)
+    ring = np.zeros(len(pts), dtype=np.int64)
+    for a_, i0 in index.items():
+        ring[i0] = hexdist(a_)
+    # geometry nodes of the boundary triangles
+    ref = [(i / q, j / q) for j in range(q + 1) for i in range(q + 1 - j)]
+    ids, nodes = [], []
+    for e, (a0, a1, a2) in enumerate(elem):
+        verts = [a0, a1, a2]
+        on = [ring[v] == n for v in verts]
+        edges = [(0, 1), (1, 2), (2, 0)]
+        bnd = [(u, w) for (u, w) in edges if on[u] and on[w]]
+        if not bnd:
+            continue
+        V = xyz[verts]
+        X = np.array([V[0] + xi * (V[1] - V[0]) + eta * (V[2] - V[0]) for xi, eta in ref])
+        for (u, w) in bnd:
+            th0 = np.arctan2(V[u, 1], V[u, 0])
+            th1 = np.arctan2(V[w, 1], V[w, 0])
+            dth = (th1 - th0 + np.pi) % (2 * np.pi) - np.pi
+            for qi, (xi, eta) in enumerate(ref):
+                lam = np.array([1 - xi - eta, xi, eta])
+                if abs(lam[u] + lam[w] - 1.0) < 1e-12 and lam[u] > 1e-12 and lam[w] > 1e-12:
+                    th = th0 + lam[w] * dth
+                    X[qi] = radius * np.array([np.cos(th), np.sin(th)])
+        ids.append(e)
+        nodes.append(X)
+    meta = dict(kind="disk", n=n, radius=radius, q=q, jitter=jitter, seed=seed,
+                curved=(np.array(ids, dtype=np.int64), np.array(nodes)))
+    return Mesh(xyz=xyz, elem=elem, period=None, meta=meta)
 
 
 def inradius(V: np.ndarray) -> np.ndarray:

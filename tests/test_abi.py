@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     import ctypes
     # sdg_sizes: 8 int32, 7 int64, 1 double, 8 doubles, 2 int64, 4 int32, 21 doubles, 2 int64
-    assert ctypes.sizeof(sdg.Sizes) == 8 * 4 + 7 * 8 + 8 + 8 * 8 + 2 * 8 + 4 * 4 + 21 * 8 + 2 * 8 + 2 * 4 + 3 * 8
+    assert ctypes.sizeof(sdg.Sizes) == 8 * 4 + 7 * 8 + 8 + 8 * 8 + 2 * 8 + 4 * 4 + 21 * 8 + 2 * 8 + 2 * 4 + 3 * 8 + 2 * 4
     assert ctypes.sizeof(sdg.SolveOpts) == 4 + 4 + 8 + 4 * 4 + 8 + 4 + 4
     assert ctypes.sizeof(sdg.SolveInfo) == 4 * 4 + 2 * 8
 

@@ -244,3 +244,57 @@ def test_compressed_3d_operator_rebuilds_the_blocks(tmp_path, name, p):
     # rounding of the factored sum grows with the degree (2.8e-13 at p = 2,
     # 4.1e-12 at p = 3 on the jittered mesh)
     assert err <= (1e-12 if p <= 2 else 1e-11)
+
+
+@pytest.fixture(scope="module")
+def curved_harness(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None or not os.path.exists(os.path.join(HIP_INCLUDE, "hip", "hip_runtime.h")):
+        pytest.skip("needs g++ and the HIP headers")
+    exe = str(tmp_path_factory.mktemp("host") / "curved")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", f"-I{HIP_INCLUDE}", "-w",
+                    os.path.join(HERE, "host", "curved.cpp"), "-o", exe, "-lpthread"], check=True)
+    return exe
+
+
+@pytest.mark.parametrize("p,q", [(2, 2), (3, 2), (2, 3)])
+def test_library_curved_elements_equal_oracle(curved_harness, tmp_path, p, q):
+    """Curved boundary elements (Section 3 maps): the library's coupling
+    blocks in the canonical basis, element masses, volume fractions and
+    barycentres against the oracle's, on a jittered disk whose boundary
+    triangles carry geometry of degree q."""
+    m = synth.disk_mesh(3, q=q, jitter=0.15, seed=41)
+    ids, nodes = m.meta["curved"]
+    lam, mu, rho = synth.lognormal_material(m.n_elem, sigma=0.3, seed=42)
+    mfile, ofile = tmp_path / "mesh.bin", tmp_path / "out.bin"
+    with open(mfile, "wb") as f:
+        np.array([m.n_vert, m.n_elem, p, 1, q, len(ids)], dtype=np.int64).tofile(f)
+        np.asarray(m.xyz, np.float64).tofile(f)
+        np.asarray(m.elem, np.int64).tofile(f)
+        for a in (lam, mu, rho):
+            np.asarray(a, np.float64).tofile(f)
+        np.asarray(ids, np.int64).tofile(f)
+        np.asarray(nodes, np.float64).tofile(f)
+    subprocess.run([curved_harness, str(mfile), str(ofile)], check=True)
+    topo = Topology(m.xyz, m.elem, None)
+    B = Blocks(topo, p, lam, mu, rho, curved=(ids, nodes))
+    nf, ne, nphi, npsi = topo.n_face, topo.n_elem, B.nphi, B.npsi
+    data = np.fromfile(ofile, dtype=np.float64)
+    sizes = [nf * 2 * nphi * 2 * npsi, ne * nphi * nphi, nf * 2, ne * 2]
+    assert data.size == sum(sizes)
+    Dt, mass, wt, bary = np.split(data, np.cumsum(sizes)[:-1])
+    Dt = Dt.reshape(nf, 2, nphi, 2, npsi)
+    worst = 0.0
+    for j, F in enumerate(topo.faces):
+        for s in range(len(B.D[j])):
+            ref = np.linalg.solve(B.L[j], B.D[j][s].reshape(-1, npsi).T).T.reshape(nphi, 2, npsi)
+            worst = max(worst, np.abs(Dt[j, s] - ref).max() / np.abs(ref).max())
+    print(f"p={p} q={q}: worst relative difference of the coupling blocks {worst:.2e}")
+    assert worst <= 1e-11
+    mass = mass.reshape(ne, nphi, nphi)
+    for e in range(ne):
+        ref = B.rho[e] * B.Mbar[e]
+        assert np.abs(mass[e] - ref).max() <= 1e-12 * np.abs(ref).max(), e
+    vt = B.vol_sub.sum(axis=1, keepdims=True)
+    assert np.allclose(wt.reshape(nf, 2), B.vol_sub / vt, rtol=0, atol=1e-13)
+    assert np.allclose(bary.reshape(ne, 2), B.bary, rtol=0, atol=1e-14)
