@@ -97,21 +97,26 @@ def apply_probe(args):
     sch = sdg.SDG_SCHEME_CN if w["scheme"] == "cn" else sdg.SDG_SCHEME_STDG
     prec = sdg.SDG_PREC_F64 if args.prec == "f64" else sdg.SDG_PREC_F32
     ctx = sdg.Context(0)
-    sz = ctx.setup(m.xyz, m.elem, m.period, w["p"], w["p_gamma"], sch, w["dt"], w["lam"], w["mu"], w["rho"], prec)
-    n = sz["n_vel_slab"]
+    R = max(1, args.cols)
+    sz = ctx.setup(m.xyz, m.elem, m.period, w["p"], w["p_gamma"], sch, w["dt"], w["lam"], w["mu"], w["rho"], prec,
+                   max_rhs=R)
+    n = sz["n_vel_slab"] * R
     x = torch.randn(n, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
-    ctx.apply(x, y, prec)
+    ctx.apply(x, y, prec, n_rhs=R)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(args.reps):
-        ctx.apply(x, y, prec)
+        ctx.apply(x, y, prec, n_rhs=R)
     e1.record()
     e1.synchronize()
     t = e0.elapsed_time(e1) / 1e3 / args.reps
-    print(json.dumps({"workload": args.workload, "variant": sz["op_variant"] if prec == sdg.SDG_PREC_F64
-                      else sz["op_variant_f32"], "precision": args.prec, "apply_us": t * 1e6}), flush=True)
+    rec = {"workload": args.workload, "columns": R, "precision": args.prec, "apply_us": t * 1e6,
+           "variant": sz["op_variant"] if prec == sdg.SDG_PREC_F64 else sz["op_variant_f32"]}
+    if R > 1:
+        rec["batched_variant"] = sz["op_bvariant"] if prec == sdg.SDG_PREC_F64 else sz["op_bvariant_f32"]
+    print(json.dumps(rec), flush=True)
     ctx.close()
 
 
@@ -700,6 +705,7 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--prec", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--cols", type=int, default=1, help="right-hand sides of the --apply-probe applies")
     ap.add_argument("--only", choices=["mesh_batch", "batched"],
                     help="only run one extra measurement (no headline line)")
     ap.add_argument("--calibrate-copy", action="store_true",
