@@ -141,7 +141,10 @@ template <int NJ>
 __global__ __launch_bounds__(kT) void km_update(BlockMap bm, int64_t ld, const double* __restrict__ V,
                                                 double* __restrict__ x, const SysScalars* ss) {
   const int sys = bm.seg[blockIdx.x];
-  if (ss[sys].k == 0) return;
+  // a system that stopped after k < NJ steps never wrote V[k+1 ..): only its
+  // own k columns are read (a zero coefficient times a stale NaN is NaN)
+  const int k = ss[sys].k;
+  if (k == 0) return;
   double ys[NJ];
 #pragma unroll
   for (int i = 0; i < NJ; ++i) ys[i] = ss[sys].y[i];
@@ -149,10 +152,11 @@ __global__ __launch_bounds__(kT) void km_update(BlockMap bm, int64_t ld, const d
   for (int64_t t = bm.beg[blockIdx.x] + threadIdx.x; t < e; t += kT) {
     double vi[NJ];
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) vi[i] = V[(size_t)i * ld + t];
+    for (int i = 0; i < NJ; ++i) vi[i] = i < k ? V[(size_t)i * ld + t] : 0.0;
     double acc = x[t];
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) acc += ys[i] * vi[i];
+    for (int i = 0; i < NJ; ++i)
+      if (i < k) acc += ys[i] * vi[i];
     x[t] = acc;
   }
 }
@@ -966,6 +970,8 @@ void multi_result(MultiSys& m, hipStream_t s, SolveResult& res) {
   m.read_scalars(h, s);
   double worst = 0.0, bmax = 0.0;
   for (const SysScalars& q : h) {
+    // std::max drops a NaN operand: test every system's residual itself
+    require(std::isfinite(q.rnorm), SDG_ENONFINITE, "non-finite residual");
     if (q.bnorm > 0.0) worst = std::max(worst, q.rnorm / q.bnorm);
     bmax = std::max(bmax, q.bnorm);
   }

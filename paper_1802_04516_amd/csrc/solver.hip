@@ -1025,6 +1025,124 @@ void launch_block_apply_fact(int64_t n_elem, int ng, int ns, const float* Q, con
   throw Error(SDG_EUNSUPPORTED, "no factored block-preconditioner kernel for this element size");
 }
 
+// CG update fused with the explicit element block preconditioner and the
+// reductions of the two inner products that follow it.  Per group of EPB
+// elements (NV rows each): alpha = rz / pq, x += alpha p, r -= alpha q,
+// z_e = P_e r_e (packed symmetric block, as in k_block_apply_sym), and the
+// partial sums of r.r (slot 0) and r.z (slot 1).  A workgroup walks the
+// groups with stride gridDim.x and writes its two partials to
+// partials[slot * kCgBlocks + block].  Launched with 256 threads (whole
+// wavefronts for the block reduction; rows past EPB * NV idle).
+constexpr int kCgBlocks = 2048;
+static_assert(2 * kCgBlocks <= kRedBlocks * kRedSlots, "fused CG partials exceed the partials buffer");
+
+template <int NV>
+__global__ __launch_bounds__(256) void k_cg_update_blk(int64_t n_elem, const float* __restrict__ P,
+                                                       double* __restrict__ x, double* __restrict__ r,
+                                                       const double* __restrict__ p, const double* __restrict__ q,
+                                                       double* __restrict__ z, const DevScalars* sc,
+                                                       double* partials) {
+  constexpr int EPB = 256 / NV, NP = NV * (NV + 1) / 2;
+  constexpr int PPT = (EPB * NP + 255) / 256;
+  __shared__ double sx[EPB * NV];
+  __shared__ float sP[EPB * NP];
+  const double alpha = sc->rr / sc->pq;
+  const int le = threadIdx.x / NV, row = threadIdx.x % NV;
+  const int64_t ngroups = (n_elem + EPB - 1) / EPB;
+  double acc[2] = {0.0, 0.0};
+  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const int64_t e0 = g * EPB;
+    const int ne = (int)min((int64_t)EPB, n_elem - e0);
+    const bool act = le < ne;
+    const int64_t i = (e0 + le) * NV + row;
+    const float* Pg = P + (size_t)e0 * NP;
+    float pv[PPT];
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      const int j = threadIdx.x + u * 256;
+      pv[u] = j < ne * NP ? Pg[j] : 0.0f;
+    }
+    double xi = 0.0, pi = 0.0, ri = 0.0, qi = 0.0;
+    if (act) {
+      xi = x[i];
+      pi = p[i];
+      ri = r[i];
+      qi = q[i];
+    }
+    __syncthreads();  // the previous group's products have read sP and sx
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      const int j = threadIdx.x + u * 256;
+      if (j < ne * NP) sP[j] = pv[u];
+    }
+    if (act) {
+      x[i] = xi + alpha * pi;
+      ri = ri - alpha * qi;
+      r[i] = ri;
+      sx[le * NV + row] = ri;
+      acc[0] += ri * ri;
+    }
+    __syncthreads();
+    if (act) {
+      const float* Pe = sP + le * NP;
+      const int rr = row * (row + 1) / 2;
+      double zi = 0.0;
+#pragma unroll
+      for (int col = 0; col < NV; ++col)
+        zi += (double)Pe[row <= col ? col * (col + 1) / 2 + row : rr + col] * sx[le * NV + col];
+      z[i] = zi;
+      acc[1] += ri * zi;
+    }
+  }
+  block_partials_to<2>(acc, partials, kCgBlocks);
+}
+
+// alpha = rz / pq, rr_new = r.r, beta = (r.z)_new / rz, rz = (r.z)_new from
+// the fused update's partials (one workgroup, fixed summation order).
+__global__ __launch_bounds__(256) void k_cg_update_blk_fin(const double* partials, int nblocks, DevScalars* sc) {
+  __shared__ double sh[2][4];
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += 256) {
+    v[0] += partials[b];
+    v[1] += partials[kCgBlocks + b];
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    v[j] = warp_sum(v[j]);
+    if (lane == 0) sh[j][wid] = v[j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double rr = ((sh[0][0] + sh[0][1]) + sh[0][2]) + sh[0][3];
+    const double rz = ((sh[1][0] + sh[1][1]) + sh[1][2]) + sh[1][3];
+    sc->alpha = sc->rr / sc->pq;
+    sc->rr_new = rr;
+    sc->beta = rz / sc->rr;
+    sc->rr = rz;
+  }
+}
+
+// The fused update for the element block size nv; false when there is no
+// instantiation for it (the caller then runs the separate kernels).
+static bool launch_cg_update_blk(Ctx& c, int nv, double* x, double* r, const double* p, const double* q, double* z,
+                                 hipStream_t s) {
+  const int64_t n_elem = c.hs.n_elem;
+  auto go = [&](auto kernel, int epb) {
+    const int64_t groups = (n_elem + epb - 1) / epb;
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(groups, kCgBlocks));
+    kernel<<<nb, 256, 0, s>>>(n_elem, c.d_Pblk.p, x, r, p, q, z, c.d_sc.p, c.d_partials.p);
+    check_launch();
+    k_cg_update_blk_fin<<<1, 256, 0, s>>>(c.d_partials.p, nb, c.d_sc.p);
+    check_launch();
+  };
+#define SDG_CGB(NV_) \
+  if (nv == NV_) { go(k_cg_update_blk<NV_>, 256 / NV_); return true; }
+  SDG_CGB(6) SDG_CGB(12) SDG_CGB(20) SDG_CGB(30) SDG_CGB(60) SDG_CGB(105)
+#undef SDG_CGB
+  return false;
+}
+
 // ---------------------------------------------------------------- CG
 
 // Preconditioned conjugate gradients (P = I for SDG_PRECOND_NONE):
@@ -1040,6 +1158,11 @@ SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hip
   double* z = c.d_V.p;  // first basis vector (always allocated) holds z = P^-1 r
   DevScalars* sc = c.d_sc.p;
   const bool pre = k.precond != SDG_PRECOND_NONE;
+  // the explicit element block preconditioner (one time node, symmetric
+  // blocks) is applied inside the fused update kernel
+  const int nv = c.hs.ng * c.hs.dim * c.hs.nphi;
+  const bool fused = k.precond == SDG_PRECOND_BLOCK && !c.pblk_factored && c.d_Pblk.p != nullptr &&
+                     n == c.hs.n_elem * (int64_t)nv;
   const int check_every = std::max(1, k.check_every);
   res.bnorm = std::sqrt(vec_dot_host(c, n, b, b, s));
   require(std::isfinite(res.bnorm), SDG_ENONFINITE, "non-finite right-hand side");
@@ -1072,17 +1195,19 @@ SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hip
     apply_op(c, pv, q, k.prec, k.transpose, s);
     ++res.matvecs;
     dev_dot(c, n, pv, q, &sc->pq, s);
-    const unsigned g = red_grid(n);
-    k_cg_update<<<g, kThreads, 0, s>>>(n, x, r, pv, q, sc, c.d_partials.p);
-    check_launch();
-    k_cg_update_fin<<<1, kThreads, 0, s>>>(c.d_partials.p, (int)g, sc, pre ? 0 : 1);
-    check_launch();
-    if (pre) {
-      apply_precond(c, k.precond, r, z, k.transpose, s);
-      k_dot<<<g, kThreads, 0, s>>>(n, r, z, c.d_partials.p);
+    if (!(fused && launch_cg_update_blk(c, nv, x, r, pv, q, z, s))) {
+      const unsigned g = red_grid(n);
+      k_cg_update<<<g, kThreads, 0, s>>>(n, x, r, pv, q, sc, c.d_partials.p);
       check_launch();
-      k_dot_beta_fin<<<1, kThreads, 0, s>>>(c.d_partials.p, (int)g, sc);
+      k_cg_update_fin<<<1, kThreads, 0, s>>>(c.d_partials.p, (int)g, sc, pre ? 0 : 1);
       check_launch();
+      if (pre) {
+        apply_precond(c, k.precond, r, z, k.transpose, s);
+        k_dot<<<g, kThreads, 0, s>>>(n, r, z, c.d_partials.p);
+        check_launch();
+        k_dot_beta_fin<<<1, kThreads, 0, s>>>(c.d_partials.p, (int)g, sc);
+        check_launch();
+      }
     }
     k_cg_p<<<vgrid(n), kThreads, 0, s>>>(n, pv, z, sc);
     check_launch();

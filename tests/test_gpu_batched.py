@@ -28,6 +28,18 @@ def _gpu(x):
     return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
 
 
+def _poison_freed_device_memory(nbytes=1 << 30):
+    """Leave NaN bit patterns in device memory handed back to the driver, so
+    that the library's next workspace allocations are likely to start from
+    NaN: a solver that reads workspace values it never wrote (say a zero
+    coefficient times a stale basis vector) then returns NaN."""
+    import torch
+    t = torch.full((nbytes // 8,), float("nan"), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    del t
+    torch.cuda.empty_cache()
+
+
 def _canon(B, s_raw):
     return np.stack([B.to_canonical(j, s_raw[j]) for j in range(B.topo.n_face)])
 
@@ -280,7 +292,10 @@ def test_graph_replays_match_eager_steps_and_oracle(name, fp32):
     other work and synchronisations in between; every replayed step is
     checked against the same step run eagerly and against the oracle.  With
     fp32_ir both run the FP32 operator inside FP64 refinement, the graph
-    with its per-system outer tests on the device."""
+    with its per-system outer tests on the device.  The context is created
+    after NaN has been left in freed device memory, and every result must be
+    finite: a system that converges within a recorded part of a cycle must
+    not pick up basis vectors it never wrote."""
     import torch
     import paper_1802_04516_amd as sdg
     mks, p, pg, scheme, R = GRAPH_CASES[name]
@@ -290,6 +305,7 @@ def test_graph_replays_match_eager_steps_and_oracle(name, fp32):
     dt = 0.01
     sch = sdg.SDG_SCHEME_CN if scheme == "cn" else sdg.SDG_SCHEME_STDG
     prc = sdg.SDG_PREC_F64 | sdg.SDG_ASSEMBLE_BLOCK_PRECOND | (sdg.SDG_PREC_F32 if fp32 else 0)
+    _poison_freed_device_memory()
     ctx = sdg.Context(0)
     if len(meshes) > 1:
         ctx.setup_batch([(m.xyz, m.elem) for m in meshes], p, pg, sch, dt, lam, mu, rho, prc)
@@ -357,6 +373,7 @@ def test_graph_replays_match_eager_steps_and_oracle(name, fp32):
         print(f"{name} {'fp32_ir' if fp32 else 'fp64'} step {n}: graph vs eager {d_ge:.2e}, vs oracle "
               f"{worst:.2e}, iters graph {info_g['iterations']} eager {info_e['iterations']}, refinements "
               f"graph {info_g['refinements']} eager {info_e['refinements']}")
+        assert np.isfinite(vg.cpu().numpy()).all() and np.isfinite(sg.cpu().numpy()).all()
         assert d_ge <= 1e-11 and worst <= 1e-11
         assert info_g["rel_residual"] <= 1e-13
     ctx.close()
