@@ -113,8 +113,10 @@ void check_prec(Ctx& c, int prec) {
 }  // namespace
 
 void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s, int ncols, void* z,
-              const int* mask_active) {
+              const int* mask_active, double* dot_part) {
+  require(!dot_part || (ncols == 1 && !mask_active), SDG_EINVAL, "the fused inner product takes one unmasked column");
   OpArgs a = base_args(c, prec);
+  a.dot_part = dot_part;
   if (mask_active) {
     a.mask_active = mask_active;
     a.mask_stride = MultiSys::mask_stride();

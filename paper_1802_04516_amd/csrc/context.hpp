@@ -198,6 +198,7 @@ struct Ctx {
   DevBuf<double> d_V;                   // (restart+1) * n_slab   (GMRES) or 4 * n_slab (CG)
   DevBuf<double> d_x, d_b, d_r, d_w, d_t, d_d, d_e;
   DevBuf<double> d_partials;            // kRedSlots * kRedBlocks, slot-major
+  DevBuf<double> d_cg_partials;         // fused CG update: r.r and r.z per element group
   DevBuf<DevScalars> d_sc;
   double* h_pinned = nullptr;           // pinned host copy of a few scalars
   // convergence poll of the delayed GMRES: {latest stamp, estimate of step
@@ -253,7 +254,7 @@ struct Ctx {
 // ncols > 1: ncols independent columns stored one after another (stride n_slab)
 // z: face-slot workspace of z_col values per column (default: the context's)
 void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s, int ncols = 1,
-              void* z = nullptr, const int* mask_active = nullptr);
+              void* z = nullptr, const int* mask_active = nullptr, double* dot_part = nullptr);
 
 // Face-slot workspace of the allocation-free apply: a file-scope device
 // array of noalloc_scratch_bytes() per GPU; noalloc_scratch(device) returns

@@ -228,6 +228,10 @@ struct OpArgs {
   // N_phi^2 instead of Mref when curved_idx[e] >= 0 (null: no curved element)
   const int32_t* curved_idx = nullptr;
   const double* curved_M = nullptr;
+  // one right-hand side, no mask: the element kernel also writes each
+  // workgroup's sum of v . y (the CG inner product p . A p) to dot_part
+  // [blockIdx.x] (null: not formed)
+  double* dot_part = nullptr;
 };
 
 // Launch the face kernel and/or the element kernel for (dim, p, NG).

@@ -1026,85 +1026,91 @@ void launch_block_apply_fact(int64_t n_elem, int ng, int ns, const float* Q, con
 }
 
 // CG update fused with the explicit element block preconditioner and the
-// reductions of the two inner products that follow it.  Per group of EPB
-// elements (NV rows each): alpha = rz / pq, x += alpha p, r -= alpha q,
-// z_e = P_e r_e (packed symmetric block, as in k_block_apply_sym), and the
-// partial sums of r.r (slot 0) and r.z (slot 1).  A workgroup walks the
-// groups with stride gridDim.x and writes its two partials to
-// partials[slot * kCgBlocks + block].  Launched with 256 threads (whole
+// reductions of the two inner products that follow it.  One workgroup per
+// group of EPB elements (NV rows each): alpha = rz / pq, x += alpha p,
+// r -= alpha q, z_e = P_e r_e (packed symmetric block, as in
+// k_block_apply_sym), and the group's partial sums of r.r and r.z, written
+// to partials[block] and partials[ngroups + block].  (One group per
+// workgroup rather than a loop over groups: a loop would wait for each
+// group's stores before the next group's loads could be used, since one
+// counter retires both in issue order.)  Launched with 256 threads (whole
 // wavefronts for the block reduction; rows past EPB * NV idle).
-constexpr int kCgBlocks = 2048;
-static_assert(2 * kCgBlocks <= kRedBlocks * kRedSlots, "fused CG partials exceed the partials buffer");
-
 template <int NV>
 __global__ __launch_bounds__(256) void k_cg_update_blk(int64_t n_elem, const float* __restrict__ P,
                                                        double* __restrict__ x, double* __restrict__ r,
                                                        const double* __restrict__ p, const double* __restrict__ q,
                                                        double* __restrict__ z, const DevScalars* sc,
-                                                       double* partials) {
+                                                       double* partials, int ngroups) {
   constexpr int EPB = 256 / NV, NP = NV * (NV + 1) / 2;
   constexpr int PPT = (EPB * NP + 255) / 256;
   __shared__ double sx[EPB * NV];
   __shared__ float sP[EPB * NP];
-  const double alpha = sc->rr / sc->pq;
   const int le = threadIdx.x / NV, row = threadIdx.x % NV;
-  const int64_t ngroups = (n_elem + EPB - 1) / EPB;
-  double acc[2] = {0.0, 0.0};
-  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
-    const int64_t e0 = g * EPB;
-    const int ne = (int)min((int64_t)EPB, n_elem - e0);
-    const bool act = le < ne;
-    const int64_t i = (e0 + le) * NV + row;
-    const float* Pg = P + (size_t)e0 * NP;
-    float pv[PPT];
+  const int64_t e0 = (int64_t)blockIdx.x * EPB;
+  const int ne = (int)min((int64_t)EPB, n_elem - e0);
+  const bool act = le < ne;
+  const int64_t i = (e0 + le) * NV + row;
+  const float* Pg = P + (size_t)e0 * NP;
+  float pv[PPT];
 #pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-      const int j = threadIdx.x + u * 256;
-      pv[u] = j < ne * NP ? Pg[j] : 0.0f;
-    }
-    double xi = 0.0, pi = 0.0, ri = 0.0, qi = 0.0;
-    if (act) {
-      xi = x[i];
-      pi = p[i];
-      ri = r[i];
-      qi = q[i];
-    }
-    __syncthreads();  // the previous group's products have read sP and sx
-#pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-      const int j = threadIdx.x + u * 256;
-      if (j < ne * NP) sP[j] = pv[u];
-    }
-    if (act) {
-      x[i] = xi + alpha * pi;
-      ri = ri - alpha * qi;
-      r[i] = ri;
-      sx[le * NV + row] = ri;
-      acc[0] += ri * ri;
-    }
-    __syncthreads();
-    if (act) {
-      const float* Pe = sP + le * NP;
-      const int rr = row * (row + 1) / 2;
-      double zi = 0.0;
-#pragma unroll
-      for (int col = 0; col < NV; ++col)
-        zi += (double)Pe[row <= col ? col * (col + 1) / 2 + row : rr + col] * sx[le * NV + col];
-      z[i] = zi;
-      acc[1] += ri * zi;
-    }
+  for (int u = 0; u < PPT; ++u) {
+    const int j = threadIdx.x + u * 256;
+    pv[u] = j < ne * NP ? Pg[j] : 0.0f;
   }
-  block_partials_to<2>(acc, partials, kCgBlocks);
+  double xi = 0.0, pi = 0.0, ri = 0.0, qi = 0.0;
+  if (act) {
+    xi = x[i];
+    pi = p[i];
+    ri = r[i];
+    qi = q[i];
+  }
+  const double alpha = sc->rr / sc->pq;
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int j = threadIdx.x + u * 256;
+    if (j < ne * NP) sP[j] = pv[u];
+  }
+  double acc[2] = {0.0, 0.0};
+  if (act) {
+    x[i] = xi + alpha * pi;
+    ri = ri - alpha * qi;
+    r[i] = ri;
+    sx[le * NV + row] = ri;
+    acc[0] = ri * ri;
+  }
+  __syncthreads();
+  if (act) {
+    const float* Pe = sP + le * NP;
+    const int rr = row * (row + 1) / 2;
+    double zi = 0.0;
+#pragma unroll
+    for (int col = 0; col < NV; ++col)
+      zi += (double)Pe[row <= col ? col * (col + 1) / 2 + row : rr + col] * sx[le * NV + col];
+    z[i] = zi;
+    acc[1] = ri * zi;
+  }
+  block_partials_to<2>(acc, partials, ngroups);
 }
 
 // alpha = rz / pq, rr_new = r.r, beta = (r.z)_new / rz, rz = (r.z)_new from
 // the fused update's partials (one workgroup, fixed summation order).
-__global__ __launch_bounds__(256) void k_cg_update_blk_fin(const double* partials, int nblocks, DevScalars* sc) {
-  __shared__ double sh[2][4];
+__global__ __launch_bounds__(1024) void k_cg_update_blk_fin(const double* partials, int nblocks, DevScalars* sc) {
+  __shared__ double sh[2][16];
   double v[2] = {0.0, 0.0};
-  for (int b = threadIdx.x; b < nblocks; b += 256) {
-    v[0] += partials[b];
-    v[1] += partials[kCgBlocks + b];
+  // 8 blocks per thread and slot in flight at once, added in a fixed order
+  for (int b0 = threadIdx.x; b0 < nblocks; b0 += 8 * 1024) {
+    double t[2][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = b0 + u * 1024;
+      t[0][u] = b < nblocks ? partials[b] : 0.0;
+      t[1][u] = b < nblocks ? partials[nblocks + b] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      v[0] += t[0][u];
+      v[1] += t[1][u];
+    }
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -1114,12 +1120,40 @@ __global__ __launch_bounds__(256) void k_cg_update_blk_fin(const double* partial
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double rr = ((sh[0][0] + sh[0][1]) + sh[0][2]) + sh[0][3];
-    const double rz = ((sh[1][0] + sh[1][1]) + sh[1][2]) + sh[1][3];
+    double rr = 0.0, rz = 0.0;
+    for (int w = 0; w < 16; ++w) {
+      rr += sh[0][w];
+      rz += sh[1][w];
+    }
     sc->alpha = sc->rr / sc->pq;
     sc->rr_new = rr;
     sc->beta = rz / sc->rr;
     sc->rr = rz;
+  }
+}
+
+// *out = sum of partials[0 .. nblocks) (one workgroup, fixed order): the
+// inner product p . A p from the element kernel's per-workgroup sums.
+__global__ __launch_bounds__(1024) void k_sum_partials(const double* partials, int nblocks, double* out) {
+  __shared__ double sh[16];
+  double v = 0.0;
+  for (int b0 = threadIdx.x; b0 < nblocks; b0 += 8 * 1024) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = b0 + u * 1024;
+      t[u] = b < nblocks ? partials[b] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += t[u];
+  }
+  v = warp_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < 16; ++w) tot += sh[w];
+    *out = tot;
   }
 }
 
@@ -1130,10 +1164,12 @@ static bool launch_cg_update_blk(Ctx& c, int nv, double* x, double* r, const dou
   const int64_t n_elem = c.hs.n_elem;
   auto go = [&](auto kernel, int epb) {
     const int64_t groups = (n_elem + epb - 1) / epb;
-    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(groups, kCgBlocks));
-    kernel<<<nb, 256, 0, s>>>(n_elem, c.d_Pblk.p, x, r, p, q, z, c.d_sc.p, c.d_partials.p);
+    require(groups <= 0x7fffffff && c.d_cg_partials.n >= (size_t)(2 * groups), SDG_EINVAL,
+            "fused CG update: element grid exceeds its partials");
+    kernel<<<(unsigned)groups, 256, 0, s>>>(n_elem, c.d_Pblk.p, x, r, p, q, z, c.d_sc.p, c.d_cg_partials.p,
+                                           (int)groups);
     check_launch();
-    k_cg_update_blk_fin<<<1, 256, 0, s>>>(c.d_partials.p, nb, c.d_sc.p);
+    k_cg_update_blk_fin<<<1, 1024, 0, s>>>(c.d_cg_partials.p, (int)groups, c.d_sc.p);
     check_launch();
   };
 #define SDG_CGB(NV_) \
@@ -1161,8 +1197,15 @@ SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hip
   // the explicit element block preconditioner (one time node, symmetric
   // blocks) is applied inside the fused update kernel
   const int nv = c.hs.ng * c.hs.dim * c.hs.nphi;
-  const bool fused = k.precond == SDG_PRECOND_BLOCK && !c.pblk_factored && c.d_Pblk.p != nullptr &&
-                     n == c.hs.n_elem * (int64_t)nv;
+  // p . A p is summed by the operator's element kernel (one partial per
+  // workgroup of 256 / nv elements) when the velocity is one time node
+  const bool dotfused = n == c.hs.n_elem * (int64_t)nv && nv <= 256 && c.hs.ng == 1;
+  const bool fused = dotfused && k.precond == SDG_PRECOND_BLOCK && !c.pblk_factored && c.d_Pblk.p != nullptr;
+  const int64_t egroups = (c.hs.n_elem + 256 / nv - 1) / (256 / nv);
+  if (dotfused) {  // partial sums per element group (two for the fused update)
+    const size_t need = 2 * (size_t)egroups;
+    if (c.d_cg_partials.n < need) c.d_cg_partials.alloc(need);
+  }
   const int check_every = std::max(1, k.check_every);
   res.bnorm = std::sqrt(vec_dot_host(c, n, b, b, s));
   require(std::isfinite(res.bnorm), SDG_ENONFINITE, "non-finite right-hand side");
@@ -1192,9 +1235,15 @@ SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hip
     return res;
   }
   for (int it = 0; it < k.max_iter; ++it) {
-    apply_op(c, pv, q, k.prec, k.transpose, s);
+    if (dotfused) {
+      apply_op(c, pv, q, k.prec, k.transpose, s, 1, nullptr, nullptr, c.d_cg_partials.p);
+      k_sum_partials<<<1, 1024, 0, s>>>(c.d_cg_partials.p, (int)egroups, &sc->pq);
+      check_launch();
+    } else {
+      apply_op(c, pv, q, k.prec, k.transpose, s);
+      dev_dot(c, n, pv, q, &sc->pq, s);
+    }
     ++res.matvecs;
-    dev_dot(c, n, pv, q, &sc->pq, s);
     if (!(fused && launch_cg_update_blk(c, nv, x, r, pv, q, z, s))) {
       const unsigned g = red_grid(n);
       k_cg_update<<<g, kThreads, 0, s>>>(n, x, r, pv, q, sc, c.d_partials.p);
