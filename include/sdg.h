@@ -148,7 +148,9 @@ typedef struct {
   int32_t restart;     /* GMRES restart length (<= 32)                                  */
   int32_t check_every; /* host convergence poll period in iterations                    */
   int32_t max_refine;  /* outer refinement sweeps for SDG_PREC_F32                      */
-  double inner_rtol;   /* relative tolerance of each inner FP32 solve                   */
+  double inner_rtol;   /* relative tolerance of each inner FP32 solve; with one system
+                          an inner solve reduces its right-hand side d only to
+                          0.5 rtol ||b|| when that target is looser               */
   int32_t precond;     /* SDG_PRECOND_*: right preconditioner (GMRES) / PCG (CG)        */
   int32_t flags;       /* SDG_SOLVE_GRAPH | SDG_SOLVE_EXTRAPOLATE | SDG_SOLVE_CGS2      */
 } sdg_solve_opts;
@@ -402,7 +404,12 @@ int sdg_set_mesh_sources(sdg_ctx* ctx, int64_t n_src, const double* pos, const d
  * slab (kept by the context) continued to the new slab's time nodes, which
  * is meant for consecutive steps of one trajectory: the first such step,
  * or one after a step without the flag or with another n_rhs, starts from
- * the old state as usual.  Both guesses converge to the same tolerance.
+ * the old state as usual.  With one time node per slab (Crank-Nicolson,
+ * p_gamma = 0), where that continuation is the old state itself, the eager
+ * step extrapolates the trajectory instead: 2 x_n - x_{n-1} from the second
+ * such step and 3 x_n - 3 x_{n-1} + x_{n-2} from the third (x_k: the slab of
+ * step k; the context keeps the last three, graph mode keeps the
+ * continuation).  Every guess converges to the same tolerance.
  * On SDG_ENOCONV the states hold the step computed from the last iterate
  * and *info is filled.
  * With opts->flags & SDG_SOLVE_GRAPH (GMRES, FP64 or FP32 + refinement)

@@ -270,7 +270,7 @@ void locate_points(Ctx& c, int64_t n_pts, const double* pts) {
 // into d_b (point sources from d_src_amp when src), and the initial guess
 // (old state at every time node) into d_x.
 void step_rhs(Ctx& c, const double* v_state, const double* sigma_state, int R, bool src, hipStream_t s,
-              bool extrap) {
+              bool extrap, int hist = 0) {
   const HostSetup& hs = c.hs;
   const int d = hs.dim, ng = hs.ng, nvs = d * hs.nphi;
   const double dt = hs.dt;
@@ -321,16 +321,29 @@ void step_rhs(Ctx& c, const double* v_state, const double* sigma_state, int R, b
   }
   SDG_HIP(hipGetLastError());
   if (src) launch_add_sources(c, c.d_b.p, c.d_src_amp.p, s, R);
-  if (extrap)
+  if (extrap && hist >= 2) {
+    // one-node slabs: the trajectory of the last slabs extrapolated in time,
+    // linearly (2 x_n - x_{n-1}) or quadratically (3 x_n - 3 x_{n-1} + x_{n-2})
+    const int64_t N = c.n_slab * R;
+    if (hist >= 3) {
+      vec_copy(N, c.d_prev3.p, c.d_x.p, s);
+      vec_axpby(N, 3.0, c.d_prev.p, 1.0, c.d_x.p, s);
+      vec_axpby(N, -3.0, c.d_prev2.p, 1.0, c.d_x.p, s);
+    } else {
+      vec_copy(N, c.d_prev.p, c.d_x.p, s);
+      vec_axpby(N, -1.0, c.d_prev2.p, 2.0, c.d_x.p, s);
+    }
+  } else if (extrap) {
     launch_time_map(hs.n_elem * R, ng, nvs, hs.Ext.data(), c.d_prev.p, c.d_x.p, s);
-  else
+  } else {
     launch_broadcast_time(hs.n_elem * R, ng, nvs, v_state, c.d_x.p, s);
+  }
 }
 
 // Stress back-substitution (eq. NM26 or NM26.cn) from the velocity slab in
 // d_x, then the end-of-slab state, for R columns.
 void step_backsub(Ctx& c, double* v_state, double* sigma_state, double* v_slab, double* sigma_slab, int R,
-                  hipStream_t s, bool extrap) {
+                  hipStream_t s, bool extrap, bool hist = false) {
   const HostSetup& hs = c.hs;
   const int d = hs.dim, ng = hs.ng, nvs = d * hs.nphi;
   const double dt = hs.dt;
@@ -374,6 +387,11 @@ void step_backsub(Ctx& c, double* v_state, double* sigma_state, double* v_slab, 
     vec_copy(c.n_sig_state * R, c.d_tmp_sig.p, sigma_state, s);
     if (v_slab) vec_copy(N, c.d_x.p, v_slab, s);
     launch_end_of_slab(hs.n_elem * R, ng, nvs, c.d_e1.p, c.d_x.p, v_state, s);
+  }
+  if (extrap && hist) {
+    // the oldest slab's buffer takes the new one
+    std::swap(c.d_prev3.p, c.d_prev2.p);
+    std::swap(c.d_prev2.p, c.d_prev.p);
   }
   if (extrap) vec_copy(N, c.d_x.p, c.d_prev.p, s);
 }
@@ -893,6 +911,7 @@ int sdg_assemble(sdg_ctx* ctx, unsigned precisions, int max_rhs) {
     c.d_tmp_state.alloc(c.n_state * R);
     c.d_prev.alloc(n);
     c.prev_valid = false;
+    c.prev_count = 0;
     c.d_tmp_sig.alloc(c.n_sig_state * R);
     c.d_src_amp.alloc((size_t)std::max<int64_t>(c.n_src, 1) * ng);
     SDG_HIP(hipDeviceSynchronize());
@@ -1144,10 +1163,23 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     // a previous slab of this width, seed it with the old state at every node
     // (the continuation of a constant is the constant)
     const bool extrap = (opts->flags & SDG_SOLVE_EXTRAPOLATE) != 0;
-    if (extrap && (!c.prev_valid || c.prev_R != R))
+    if (extrap && (!c.prev_valid || c.prev_R != R)) {
       launch_broadcast_time(c.hs.n_elem * R, c.hs.ng, c.hs.dim * c.hs.nphi, v_state, c.d_prev.p, s);
+      c.prev_count = 1;
+    }
     c.prev_valid = extrap;
     c.prev_R = R;
+    // one-node slabs outside graph mode keep the trajectory's last slabs and
+    // extrapolate them (a recorded graph would keep the history length it
+    // was recorded with)
+    const bool hist = extrap && c.hs.ng == 1 && !graph;
+    if (!hist) c.prev_count = extrap ? 1 : 0;
+    if (hist && (c.d_prev2.n != c.d_prev.n || c.d_prev3.n != c.d_prev.n)) {
+      c.d_prev2.alloc(c.d_prev.n);
+      c.d_prev3.alloc(c.d_prev.n);
+      c.prev_count = 1;
+    }
+    const int hist_order = hist ? std::min(c.prev_count, 3) : 0;
 
     if (graph) {
       MultiSys& m = systems(c, R);
@@ -1316,7 +1348,7 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     // 1. right-hand side (one launch for all columns)
     const bool src = amp && c.n_src > 0;
     if (src) SDG_HIP(hipMemcpyAsync(c.d_src_amp.p, amp, c.n_src * c.hs.ng * sizeof(double), hipMemcpyHostToDevice, s));
-    step_rhs(c, v_state, sigma_state, R, src, s, extrap);
+    step_rhs(c, v_state, sigma_state, R, src, s, extrap, hist_order);
 
     // 2. Krylov solve from the old state copied to every time node
     auto inner = [&](const double* b, double* x, double tol, int maxit, int pr, bool x_zero) {
@@ -1377,9 +1409,13 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
           res.converged = rr <= opts->rtol;
           break;
         }
-        // correction: A32 e = d from a zero initial guess, then x += e
+        // correction: A32 e = d from a zero initial guess, then x += e.  One
+        // system: an inner solve needs to reduce d only by what is left to
+        // rtol (with a factor 2 to spare), never more tightly than inner_tol
+        // asks; the device sets several systems' targets
+        const double tol_k = multi ? inner_tol : std::max(inner_tol, 0.5 * opts->rtol / rr);
         vec_fill(N, 0.0, c.d_e.p, s);
-        SolveResult in = inner(c.d_d.p, c.d_e.p, inner_tol, opts->max_iter - res.iters, SDG_PREC_F32, true);
+        SolveResult in = inner(c.d_d.p, c.d_e.p, tol_k, opts->max_iter - res.iters, SDG_PREC_F32, true);
         res.iters += in.iters;
         res.matvecs += in.matvecs;
         ++res.refinements;
@@ -1388,7 +1424,8 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     }
 
     // 3. stress back-substitution and 4. end-of-slab state
-    step_backsub(c, v_state, sigma_state, v_slab, sigma_slab, R, s, extrap);
+    step_backsub(c, v_state, sigma_state, v_slab, sigma_slab, R, s, extrap, hist);
+    if (hist) c.prev_count = std::min(c.prev_count + 1, 3);
     SDG_HIP(hipStreamSynchronize(s));
     if (!res.converged) throw Error(SDG_ENOCONV, "Krylov solver did not reach rtol within max_iter");
   });

@@ -238,6 +238,11 @@ struct Ctx {
   DevBuf<double> d_prev;
   bool prev_valid = false;
   int prev_R = 0;
+  // one-node slabs (Crank-Nicolson, p_gamma = 0): the two slabs before d_prev
+  // and how many of d_prev, d_prev2, d_prev3 hold consecutive slabs of the
+  // current trajectory
+  DevBuf<double> d_prev2, d_prev3;
+  int prev_count = 0;
 
   // located sampling points of the last call
   std::vector<double> samp_pts;
