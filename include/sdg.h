@@ -148,9 +148,9 @@ typedef struct {
   int32_t restart;     /* GMRES restart length (<= 32)                                  */
   int32_t check_every; /* host convergence poll period in iterations                    */
   int32_t max_refine;  /* outer refinement sweeps for SDG_PREC_F32                      */
-  double inner_rtol;   /* relative tolerance of each inner FP32 solve; with one system
-                          an inner solve reduces its right-hand side d only to
-                          0.5 rtol ||b|| when that target is looser               */
+  double inner_rtol;   /* relative tolerance of each inner FP32 solve; a system's inner
+                          solve reduces its right-hand side d only to 0.5 rtol ||b||
+                          when that target is looser                              */
   int32_t precond;     /* SDG_PRECOND_*: right preconditioner (GMRES) / PCG (CG)        */
   int32_t flags;       /* SDG_SOLVE_GRAPH | SDG_SOLVE_EXTRAPOLATE | SDG_SOLVE_CGS2      */
 } sdg_solve_opts;

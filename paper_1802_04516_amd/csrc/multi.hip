@@ -306,9 +306,9 @@ __global__ void km_outer_bnorm(int S, const SysScalars* ss, double* outer) {
 
 // Outer test of iterative refinement from ss.dot = d.d (d = b - A x): the
 // relative residual per system (outer[S + s]), the number of systems above
-// rtol, and the targets of the next inner solve A e = d: inner_rtol ||d_s||,
-// or +inf for a converged system, which km_cycle_start then leaves inactive
-// (its correction stays zero).
+// rtol, and the targets of the next inner solve A e = d:
+// max(inner_rtol ||d_s||, rtol ||b_s|| / 2), or +inf for a converged system,
+// which km_cycle_start then leaves inactive (its correction stays zero).
 __global__ void km_refine_check(int S, SysScalars* ss, double* outer, double rtol, double inner_rtol,
                                 int* nouter) {
   __shared__ int sh[16];
@@ -321,7 +321,9 @@ __global__ void km_refine_check(int S, SysScalars* ss, double* outer, double rto
     outer[S + s] = rr;
     act = rr <= rtol ? 0 : 1;   // a NaN residual stays active (and is reported)
     q.bnorm = dn;
-    q.tol_abs = act ? inner_rtol * dn : INFINITY;
+    // the inner solve reduces d by inner_rtol, or only to half of what is
+    // left to rtol when that is looser (the last sweep does not over-solve)
+    q.tol_abs = act ? fmax(inner_rtol * dn, 0.5 * rtol * (bn > 0.0 ? bn : 1.0)) : INFINITY;
     q.active = 1;
     q.k = 0;
   }
