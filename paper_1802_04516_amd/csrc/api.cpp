@@ -1359,6 +1359,8 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
       k2.x_zero = x_zero && !multi;
       // FP32 inner solves of several systems take the targets the outer test set
       k2.keep_targets = multi && pr == SDG_PREC_F32;
+      // the refinement loop computes the FP64 residual after every inner solve
+      k2.recurrence_only = pr == SDG_PREC_F32;
       if (!multi) return solver == SDG_SOLVER_CG ? solve_cg(c, b, x, k2, s) : solve_gmres(c, b, x, k2, s);
       MultiSys& m = systems(c, R);
       const int* act = m.active_flags();

@@ -288,6 +288,10 @@ struct KrylovCfg {
   bool delayed = true;       // GMRES: delayed reorthogonalisation (one reduction per step)
   bool x_zero = false;       // x is zero on entry: the first residual is b itself (no operator apply)
   bool keep_targets = false; // multi-system: per-system targets already set (multi_refine_check)
+  // the caller tests the residual itself (inner solves of iterative
+  // refinement): CG reports its recurrence's residual instead of applying
+  // the operator once more at the end
+  bool recurrence_only = false;
 };
 SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s);
 SolveResult solve_gmres(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s);

@@ -1267,6 +1267,13 @@ SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hip
       if (std::sqrt(rr) <= k.rtol * res.bnorm) break;
     }
   }
+  if (k.recurrence_only) {
+    rr = read_scalar(c, &sc->rr_new, s);
+    require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
+    res.rel_res = std::sqrt(rr) / res.bnorm;
+    res.converged = res.rel_res <= k.rtol;
+    return res;
+  }
   // true residual
   apply_op(c, x, q, k.prec, k.transpose, s);
   ++res.matvecs;
