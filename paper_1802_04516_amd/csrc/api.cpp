@@ -140,6 +140,41 @@ void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipS
   SDG_HIP(hipGetLastError());
 }
 
+// y = A32 v with FP32 vectors (one column, forward operator, FP32 face
+// slots), for the FP32-vector CG inside iterative refinement; dot_part as
+// in apply_op.  Only the persistent face kernel (variant 3) and the
+// element-blocked kernel take FP32 vectors: the caller checks
+// fp32_vectors_ok first.
+void apply_op_f32v(Ctx& c, const float* v, float* y, hipStream_t s, double* dot_part) {
+  require(fp32_vectors_ok(c), SDG_EUNSUPPORTED, "no FP32-vector operator for this configuration");
+  OpArgs a = base_args(c, SDG_PREC_F32);
+  a.dot_part = dot_part;
+  a.variant = c.variant32;
+  a.v = reinterpret_cast<const double*>(v);  // FP32 values (vy_f32)
+  a.y = reinterpret_cast<double*>(y);
+  a.vy_f32 = 1;
+  a.z = c.d_z.p;
+  a.use_g = 1;
+  a.c = c.op;
+  a.n_cols = 1;
+  a.bvariant = c.bvariant32;
+  a.cs_v = a.cs_y = c.n_slab;
+  a.cs_z = c.z_col;
+  a.z_f32 = true;
+  launch_face(c.hs.dim, c.hs.p, c.hs.ng, SDG_PREC_F32, kScatter, a, s);
+  SDG_HIP(hipGetLastError());
+  launch_elem(c.hs.dim, c.hs.p, c.hs.ng, a, s);
+  SDG_HIP(hipGetLastError());
+}
+
+// The FP32-vector operator exists: the FP32 operator tuned to variant 3
+// (the persistent face kernel), isotropic material, one time node and at
+// most 256 values per element (the element-blocked kernel).
+bool fp32_vectors_ok(const Ctx& c) {
+  return (c.precisions & SDG_PREC_F32) && c.variant32 == 3 && !c.aniso && c.hs.ng == 1 &&
+         c.hs.dim * c.hs.nphi <= 256;
+}
+
 // The compressed 3D operator (variant 8) exists for this precision.
 static bool compressed_available(const Ctx& c, int prec) {
   return prec == SDG_PREC_F32 ? c.d_cmpC32.p != nullptr : c.d_cmpC64.p != nullptr;

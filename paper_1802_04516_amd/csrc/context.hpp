@@ -199,6 +199,7 @@ struct Ctx {
   DevBuf<double> d_x, d_b, d_r, d_w, d_t, d_d, d_e;
   DevBuf<double> d_partials;            // kRedSlots * kRedBlocks, slot-major
   DevBuf<double> d_cg_partials;         // fused CG update: r.r and r.z per element group
+  DevBuf<float> d_cg32;                 // FP32-vector CG: r, p, q, z, x (n_slab each)
   DevBuf<DevScalars> d_sc;
   double* h_pinned = nullptr;           // pinned host copy of a few scalars
   // convergence poll of the delayed GMRES: {latest stamp, estimate of step
@@ -260,6 +261,8 @@ struct Ctx {
 // z: face-slot workspace of z_col values per column (default: the context's)
 void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s, int ncols = 1,
               void* z = nullptr, const int* mask_active = nullptr, double* dot_part = nullptr);
+bool fp32_vectors_ok(const Ctx& c);
+void apply_op_f32v(Ctx& c, const float* v, float* y, hipStream_t s, double* dot_part);
 
 // Face-slot workspace of the allocation-free apply: a file-scope device
 // array of noalloc_scratch_bytes() per GPU; noalloc_scratch(device) returns

@@ -232,6 +232,10 @@ struct OpArgs {
   // workgroup's sum of v . y (the CG inner product p . A p) to dot_part
   // [blockIdx.x] (null: not formed)
   double* dot_part = nullptr;
+  // v and y hold FP32 values (the FP32-vector CG inside iterative
+  // refinement: the FP32 operator of variant 3 and the element-blocked
+  // kernel, one column)
+  int vy_f32 = 0;
 };
 
 // Launch the face kernel and/or the element kernel for (dim, p, NG).

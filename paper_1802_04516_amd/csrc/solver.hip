@@ -1035,11 +1035,11 @@ void launch_block_apply_fact(int64_t n_elem, int ng, int ns, const float* Q, con
 // group's stores before the next group's loads could be used, since one
 // counter retires both in issue order.)  Launched with 256 threads (whole
 // wavefronts for the block reduction; rows past EPB * NV idle).
-template <int NV>
+template <int NV, typename VT = double>
 __global__ __launch_bounds__(256) void k_cg_update_blk(int64_t n_elem, const float* __restrict__ P,
-                                                       double* __restrict__ x, double* __restrict__ r,
-                                                       const double* __restrict__ p, const double* __restrict__ q,
-                                                       double* __restrict__ z, const DevScalars* sc,
+                                                       VT* __restrict__ x, VT* __restrict__ r,
+                                                       const VT* __restrict__ p, const VT* __restrict__ q,
+                                                       VT* __restrict__ z, const DevScalars* sc,
                                                        double* partials, int ngroups) {
   constexpr int EPB = 256 / NV, NP = NV * (NV + 1) / 2;
   constexpr int PPT = (EPB * NP + 255) / 256;
@@ -1059,10 +1059,10 @@ __global__ __launch_bounds__(256) void k_cg_update_blk(int64_t n_elem, const flo
   }
   double xi = 0.0, pi = 0.0, ri = 0.0, qi = 0.0;
   if (act) {
-    xi = x[i];
-    pi = p[i];
-    ri = r[i];
-    qi = q[i];
+    xi = (double)x[i];
+    pi = (double)p[i];
+    ri = (double)r[i];
+    qi = (double)q[i];
   }
   const double alpha = sc->rr / sc->pq;
 #pragma unroll
@@ -1072,9 +1072,9 @@ __global__ __launch_bounds__(256) void k_cg_update_blk(int64_t n_elem, const flo
   }
   double acc[2] = {0.0, 0.0};
   if (act) {
-    x[i] = xi + alpha * pi;
-    ri = ri - alpha * qi;
-    r[i] = ri;
+    x[i] = (VT)(xi + alpha * pi);
+    ri = (double)(VT)(ri - alpha * qi);  // the stored residual
+    r[i] = (VT)ri;
     sx[le * NV + row] = ri;
     acc[0] = ri * ri;
   }
@@ -1086,10 +1086,115 @@ __global__ __launch_bounds__(256) void k_cg_update_blk(int64_t n_elem, const flo
 #pragma unroll
     for (int col = 0; col < NV; ++col)
       zi += (double)Pe[row <= col ? col * (col + 1) / 2 + row : rr + col] * sx[le * NV + col];
-    z[i] = zi;
+    zi = (double)(VT)zi;  // the stored preconditioned residual
+    z[i] = (VT)zi;
     acc[1] = ri * zi;
   }
   block_partials_to<2>(acc, partials, ngroups);
+}
+
+// Start of the FP32-vector CG (x = 0): r = (FP32) b, z = P_e r, p = z, and
+// per element group the partial sums of r.r (slot 0) and r.z (slot 1), as
+// in k_cg_update_blk.
+template <int NV>
+__global__ __launch_bounds__(256) void k_cg_init_blk(int64_t n_elem, const float* __restrict__ P,
+                                                     const double* __restrict__ b, float* __restrict__ r,
+                                                     float* __restrict__ z, float* __restrict__ p,
+                                                     double* partials, int ngroups) {
+  constexpr int EPB = 256 / NV, NP = NV * (NV + 1) / 2;
+  constexpr int PPT = (EPB * NP + 255) / 256;
+  __shared__ double sx[EPB * NV];
+  __shared__ float sP[EPB * NP];
+  const int le = threadIdx.x / NV, row = threadIdx.x % NV;
+  const int64_t e0 = (int64_t)blockIdx.x * EPB;
+  const int ne = (int)min((int64_t)EPB, n_elem - e0);
+  const bool act = le < ne;
+  const int64_t i = (e0 + le) * NV + row;
+  const float* Pg = P + (size_t)e0 * NP;
+  float pv[PPT];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int j = threadIdx.x + u * 256;
+    pv[u] = j < ne * NP ? Pg[j] : 0.0f;
+  }
+  const double ri = act ? (double)(float)b[i] : 0.0;
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int j = threadIdx.x + u * 256;
+    if (j < ne * NP) sP[j] = pv[u];
+  }
+  double acc[2] = {0.0, 0.0};
+  if (act) {
+    r[i] = (float)ri;
+    sx[le * NV + row] = ri;
+    acc[0] = ri * ri;
+  }
+  __syncthreads();
+  if (act) {
+    const float* Pe = sP + le * NP;
+    const int rr = row * (row + 1) / 2;
+    double zi = 0.0;
+#pragma unroll
+    for (int col = 0; col < NV; ++col)
+      zi += (double)Pe[row <= col ? col * (col + 1) / 2 + row : rr + col] * sx[le * NV + col];
+    const float zf = (float)zi;
+    z[i] = zf;
+    p[i] = zf;
+    acc[1] = ri * (double)zf;
+  }
+  block_partials_to<2>(acc, partials, ngroups);
+}
+
+// rz = (r.z) and rr_new = (r.r) from the init kernel's partials
+__global__ __launch_bounds__(1024) void k_cg_init_blk_fin(const double* partials, int nblocks, DevScalars* sc) {
+  __shared__ double sh[2][16];
+  double v[2] = {0.0, 0.0};
+  for (int b0 = threadIdx.x; b0 < nblocks; b0 += 8 * 1024) {
+    double t[2][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = b0 + u * 1024;
+      t[0][u] = b < nblocks ? partials[b] : 0.0;
+      t[1][u] = b < nblocks ? partials[nblocks + b] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      v[0] += t[0][u];
+      v[1] += t[1][u];
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    v[j] = warp_sum(v[j]);
+    if (lane == 0) sh[j][wid] = v[j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double rr = 0.0, rz = 0.0;
+    for (int w = 0; w < 16; ++w) {
+      rr += sh[0][w];
+      rz += sh[1][w];
+    }
+    sc->rr_new = rr;
+    sc->rr = rz;
+  }
+}
+
+__global__ void k_cg_p32(int64_t n, float* __restrict__ p, const float* __restrict__ z, const DevScalars* sc) {
+  const double beta = sc->beta;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (float)((double)z[i] + beta * (double)p[i]);
+}
+
+__global__ void k_fill_f32(int64_t n, float* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = 0.0f;
+}
+
+__global__ void k_f32_to_f64(int64_t n, const float* __restrict__ x, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (double)x[i];
 }
 
 // alpha = rz / pq, rr_new = r.r, beta = (r.z)_new / rz, rz = (r.z)_new from
@@ -1159,8 +1264,8 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double* partials, i
 
 // The fused update for the element block size nv; false when there is no
 // instantiation for it (the caller then runs the separate kernels).
-static bool launch_cg_update_blk(Ctx& c, int nv, double* x, double* r, const double* p, const double* q, double* z,
-                                 hipStream_t s) {
+template <typename VT>
+static bool launch_cg_update_blk(Ctx& c, int nv, VT* x, VT* r, const VT* p, const VT* q, VT* z, hipStream_t s) {
   const int64_t n_elem = c.hs.n_elem;
   auto go = [&](auto kernel, int epb) {
     const int64_t groups = (n_elem + epb - 1) / epb;
@@ -1173,10 +1278,84 @@ static bool launch_cg_update_blk(Ctx& c, int nv, double* x, double* r, const dou
     check_launch();
   };
 #define SDG_CGB(NV_) \
-  if (nv == NV_) { go(k_cg_update_blk<NV_>, 256 / NV_); return true; }
+  if (nv == NV_) { go(k_cg_update_blk<NV_, VT>, 256 / NV_); return true; }
   SDG_CGB(6) SDG_CGB(12) SDG_CGB(20) SDG_CGB(30) SDG_CGB(60) SDG_CGB(105)
 #undef SDG_CGB
   return false;
+}
+
+// Preconditioned CG on FP32 vectors for the inner solves of iterative
+// refinement (x = 0 on entry, FP32 operator, explicit element block
+// preconditioner; the caller tests the FP64 residual afterwards): the
+// iteration of solve_cg with r, p, q, z, x stored in FP32, which halves the
+// vector traffic of the operator's gather and of the update kernels.  Inner
+// products and scalars stay FP64.  x (FP64) receives the FP32 iterate.
+static SolveResult solve_cg_f32(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s) {
+  SolveResult res;
+  const int64_t n = c.n_slab;
+  const int nv = c.hs.dim * c.hs.nphi;
+  const int64_t egroups = (c.hs.n_elem + 256 / nv - 1) / (256 / nv);
+  if (c.d_cg32.n < (size_t)(5 * n)) c.d_cg32.alloc((size_t)(5 * n));
+  if (c.d_cg_partials.n < (size_t)(2 * egroups)) c.d_cg_partials.alloc((size_t)(2 * egroups));
+  float* r = c.d_cg32.p;
+  float* pv = r + n;
+  float* q = pv + n;
+  float* z = q + n;
+  float* x32 = z + n;
+  DevScalars* sc = c.d_sc.p;
+  const int check_every = std::max(1, k.check_every);
+  res.bnorm = std::sqrt(vec_dot_host(c, n, b, b, s));
+  require(std::isfinite(res.bnorm), SDG_ENONFINITE, "non-finite right-hand side");
+  if (res.bnorm == 0.0) {
+    vec_fill(n, 0.0, x, s);
+    res.converged = true;
+    return res;
+  }
+  k_fill_f32<<<vgrid(n), kThreads, 0, s>>>(n, x32);
+  check_launch();
+  bool started = false;
+  auto go_init = [&](auto kernel) {
+    kernel<<<(unsigned)egroups, 256, 0, s>>>(c.hs.n_elem, c.d_Pblk.p, b, r, z, pv, c.d_cg_partials.p,
+                                            (int)egroups);
+    check_launch();
+    k_cg_init_blk_fin<<<1, 1024, 0, s>>>(c.d_cg_partials.p, (int)egroups, sc);
+    check_launch();
+    started = true;
+  };
+#define SDG_CGI(NV_) \
+  if (nv == NV_) go_init(k_cg_init_blk<NV_>);
+  SDG_CGI(6) SDG_CGI(12) SDG_CGI(20) SDG_CGI(30) SDG_CGI(60) SDG_CGI(105)
+#undef SDG_CGI
+  require(started, SDG_EUNSUPPORTED, "no FP32-vector CG kernel for this element size");
+  double rr = read_scalar(c, &sc->rr_new, s);
+  require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
+  if (std::sqrt(rr) <= k.rtol * res.bnorm) {
+    vec_fill(n, 0.0, x, s);
+    res.converged = true;
+    res.rel_res = std::sqrt(rr) / res.bnorm;
+    return res;
+  }
+  for (int it = 0; it < k.max_iter; ++it) {
+    apply_op_f32v(c, pv, q, s, c.d_cg_partials.p);
+    k_sum_partials<<<1, 1024, 0, s>>>(c.d_cg_partials.p, (int)egroups, &sc->pq);
+    check_launch();
+    ++res.matvecs;
+    launch_cg_update_blk<float>(c, nv, x32, r, pv, q, z, s);
+    k_cg_p32<<<vgrid(n), kThreads, 0, s>>>(n, pv, z, sc);
+    check_launch();
+    ++res.iters;
+    if ((it + 1) % check_every == 0 || it + 1 == k.max_iter) {
+      rr = read_scalar(c, &sc->rr_new, s);
+      require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
+      if (std::sqrt(rr) <= k.rtol * res.bnorm) break;
+    }
+  }
+  k_f32_to_f64<<<vgrid(n), kThreads, 0, s>>>(n, x32, x);
+  check_launch();
+  rr = read_scalar(c, &sc->rr_new, s);
+  res.rel_res = std::sqrt(rr) / res.bnorm;
+  res.converged = res.rel_res <= k.rtol;
+  return res;
 }
 
 // ---------------------------------------------------------------- CG
@@ -1186,6 +1365,11 @@ static bool launch_cg_update_blk(Ctx& c, int nv, double* x, double* r, const dou
 //   q = A p; alpha = rz / p.q; x += alpha p; r -= alpha q; z = P^-1 r;
 //   beta = r.z_new / rz; p = z + beta p.
 SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hipStream_t s) {
+  // inner FP32 solves of iterative refinement on FP32 vectors
+  if (k.prec == SDG_PREC_F32 && k.x_zero && k.recurrence_only && !k.transpose && k.precond == SDG_PRECOND_BLOCK &&
+      !c.pblk_factored && c.d_Pblk.p != nullptr && c.n_slab == c.hs.n_elem * (int64_t)(c.hs.dim * c.hs.nphi) &&
+      fp32_vectors_ok(c))
+    return solve_cg_f32(c, b, x, k, s);
   SolveResult res;
   const int64_t n = c.n_slab;
   double* r = c.d_r.p;

@@ -275,6 +275,24 @@ def test_fp32_operator_with_fp64_refinement():
     case["ctx"].close()
 
 
+@pytest.mark.parametrize("variant", [3, 4])
+def test_fp32_refinement_cg_on_fp32_vectors(variant):
+    """Crank-Nicolson, the FP32 operator inside FP64 refinement with the
+    element block preconditioner: with face-kernel variant 3 the inner CG
+    keeps r, p, q, z and x in FP32 (the FP32-vector operator), with variant 4
+    in FP64.  Both reach the oracle's steps at the parity bar."""
+    import paper_1802_04516_amd as sdg
+    case = build("3d_cn_p2")
+    case["ctx"].set_operator_variant(variant)
+    assert case["ctx"].sizes["op_variant_f32"] == variant
+    v0, s0 = waves.project(case["B"], waves.ShearWave3D(), 0.0)
+    errs = _run_pair(case, v0, s0, 3, precision=sdg.SDG_PREC_F32, rtol=1e-12, precond=sdg.SDG_PRECOND_BLOCK)
+    for ev, es, it, rr in errs:
+        assert ev <= 1e-11 and es <= 1e-11, errs
+        assert rr <= 1e-12
+    case["ctx"].close()
+
+
 def test_energy_matches_oracle_and_cn_conserves():
     import torch
     case = build("c1")
