@@ -142,7 +142,10 @@ typedef struct {
 typedef struct {
   int32_t solver;      /* SDG_SOLVER_*; AUTO = CG for Crank-Nicolson, GMRES otherwise    */
   int32_t precision;   /* SDG_PREC_F64, or SDG_PREC_F32 = FP32 operator inside FP64
-                          iterative refinement (dots, residuals, updates stay FP64)     */
+                          iterative refinement (outer residuals and updates and every
+                          inner product stay FP64; the inner CG of one system with the
+                          block preconditioner and face-kernel variant 3 keeps its
+                          vectors in FP32)                                            */
   double rtol;         /* stop when ||b - A v||_2 <= rtol ||b||_2                       */
   int32_t max_iter;    /* total Krylov iterations (inner iterations for FP32)          */
   int32_t restart;     /* GMRES restart length (<= 32)                                  */
