@@ -1352,7 +1352,6 @@ static SolveResult solve_cg_f32(Ctx& c, const double* b, double* x, const Krylov
   }
   k_f32_to_f64<<<vgrid(n), kThreads, 0, s>>>(n, x32, x);
   check_launch();
-  rr = read_scalar(c, &sc->rr_new, s);
   res.rel_res = std::sqrt(rr) / res.bnorm;
   res.converged = res.rel_res <= k.rtol;
   return res;
@@ -1451,9 +1450,7 @@ SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hip
       if (std::sqrt(rr) <= k.rtol * res.bnorm) break;
     }
   }
-  if (k.recurrence_only) {
-    rr = read_scalar(c, &sc->rr_new, s);
-    require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
+  if (k.recurrence_only) {  // rr: the last residual read (the start's without iterations)
     res.rel_res = std::sqrt(rr) / res.bnorm;
     res.converged = res.rel_res <= k.rtol;
     return res;
