@@ -1055,7 +1055,7 @@ __global__ __launch_bounds__(256) void k_cg_update_blk(int64_t n_elem, const flo
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
     const int j = threadIdx.x + u * 256;
-    pv[u] = j < ne * NP ? Pg[j] : 0.0f;
+    pv[u] = j < ne * NP ? __builtin_nontemporal_load(&Pg[j]) : 0.0f;  // read once: non-temporal
   }
   double xi = 0.0, pi = 0.0, ri = 0.0, qi = 0.0;
   if (act) {
@@ -1115,7 +1115,7 @@ __global__ __launch_bounds__(256) void k_cg_init_blk(int64_t n_elem, const float
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
     const int j = threadIdx.x + u * 256;
-    pv[u] = j < ne * NP ? Pg[j] : 0.0f;
+    pv[u] = j < ne * NP ? __builtin_nontemporal_load(&Pg[j]) : 0.0f;  // read once: non-temporal
   }
   const double ri = act ? (double)(float)b[i] : 0.0;
 #pragma unroll
