@@ -208,12 +208,15 @@ def test_preconditioners_agree_and_rank(precond):
     v0 = rng.standard_normal((B.topo.n_elem, 2, B.nphi))
     s0 = 0.1 * rng.standard_normal((B.topo.n_face, 3, B.npsi))
     errs = _run_pair(case, v0, s0, 2, precond=precond)
-    # without a preconditioner the error is the residual times the system's
-    # condition number (~1e2 here), so only 1e-10 is asked of that option
-    bar = 1e-10 if precond == 0 else 1e-11
-    for ev, es, it, rr in errs:
-        assert ev <= bar and es <= bar, errs
+    # the iteration counts are compared at the same tolerance (1e-12)
     test_preconditioners_agree_and_rank.iters[precond] = errs[0][2]
+    if precond == 0:
+        # without a preconditioner the error is the residual times the
+        # system's condition number (about 1e2 here), so that option is held
+        # to the same 1e-11 bar on a solve to 3e-14
+        errs = _run_pair(case, v0, s0, 2, precond=precond, rtol=3e-14)
+    for ev, es, it, rr in errs:
+        assert ev <= 1e-11 and es <= 1e-11, errs
     if precond == 2:
         it = test_preconditioners_agree_and_rank.iters
         assert it[2] <= it[1] <= it[0], it
