@@ -534,12 +534,15 @@ def bench_c3(args):
     log(f"C3 initial state: L2 projection of the plane S-wave in {time.time() - t0:.1f}s")
     # initial guess of each step: the trajectory's last velocities
     # extrapolated in time (SDG_SOLVE_EXTRAPOLATE on one-node slabs); the
-    # old state as the guess is timed too
-    ex = sdg.SDG_SOLVE_EXTRAPOLATE
+    # old state as the guess is timed too; CG stops on the device
+    # (SDG_SOLVE_DEVICE_STOP), so no iteration runs past the one that meets
+    # the tolerance between two polls
+    dst = sdg.SDG_SOLVE_DEVICE_STOP
+    ex = sdg.SDG_SOLVE_EXTRAPOLATE | dst
     opts64 = _solve_opts(sdg, sdg.SDG_PREC_F64, sdg.SDG_PRECOND_BLOCK, ex)
     opts32 = _solve_opts(sdg, sdg.SDG_PREC_F32, sdg.SDG_PRECOND_BLOCK, ex)
     opts32.inner_rtol = IR_INNER_RTOL_3D
-    opts64_old = _solve_opts(sdg, sdg.SDG_PREC_F64, sdg.SDG_PRECOND_BLOCK)
+    opts64_old = _solve_opts(sdg, sdg.SDG_PREC_F64, sdg.SDG_PRECOND_BLOCK, dst)
     E0 = ctx.energy(v, s)
     drift = 0.0
     for _ in range(args.warmup):
@@ -614,8 +617,8 @@ def bench_c3_sample(n_cubes):
     rng = np.random.default_rng(9301)
     v0 = rng.standard_normal((sz["n_elem"], 3, sz["n_phi"]))
     s0 = 0.1 * rng.standard_normal((sz["n_face"], 6, sz["n_psi"]))
-    opts64 = _solve_opts(sdg, sdg.SDG_PREC_F64, sdg.SDG_PRECOND_BLOCK)
-    opts32 = _solve_opts(sdg, sdg.SDG_PREC_F32, sdg.SDG_PRECOND_BLOCK)
+    opts64 = _solve_opts(sdg, sdg.SDG_PREC_F64, sdg.SDG_PRECOND_BLOCK, sdg.SDG_SOLVE_DEVICE_STOP)
+    opts32 = _solve_opts(sdg, sdg.SDG_PREC_F32, sdg.SDG_PRECOND_BLOCK, sdg.SDG_SOLVE_DEVICE_STOP)
     opts32.inner_rtol = IR_INNER_RTOL_3D
     out = {}
     for name, o in (("fp64", opts64), ("fp32_operator_fp64_refinement", opts32)):

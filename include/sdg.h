@@ -106,8 +106,15 @@ enum { SDG_PRECOND_NONE = 0, SDG_PRECOND_MASS = 1, SDG_PRECOND_BLOCK = 2, SDG_PR
  *              sweeps over the basis).  The default delays the second projection
  *              of a vector to the next step (Swirydowicz et al. 2020, Bielich et
  *              al. 2022): one reduction and two sweeps per step; the residual
- *              estimate polled every check_every steps then lags by one step. */
-enum { SDG_SOLVE_GRAPH = 1, SDG_SOLVE_EXTRAPOLATE = 2, SDG_SOLVE_CGS2 = 4 };
+ *              estimate polled every check_every steps then lags by one step.
+ * DEVICE_STOP  CG with the explicit element block preconditioner (Crank-
+ *              Nicolson, Section 4) stops on the device: the iteration whose
+ *              residual meets rtol clears a flag, and the up to check_every - 1
+ *              iterations already queued behind it return at entry instead of
+ *              iterating on.  The solution is then the first iterate that meets
+ *              rtol (without the flag, the iterate of the next poll); the
+ *              reported iterations are those that ran.  Ignored elsewhere. */
+enum { SDG_SOLVE_GRAPH = 1, SDG_SOLVE_EXTRAPOLATE = 2, SDG_SOLVE_CGS2 = 4, SDG_SOLVE_DEVICE_STOP = 8 };
 
 typedef struct sdg_ctx sdg_ctx;
 
@@ -155,7 +162,7 @@ typedef struct {
                           solve reduces its right-hand side d only to 0.5 rtol ||b||
                           when that target is looser                              */
   int32_t precond;     /* SDG_PRECOND_*: right preconditioner (GMRES) / PCG (CG)        */
-  int32_t flags;       /* SDG_SOLVE_GRAPH | SDG_SOLVE_EXTRAPOLATE | SDG_SOLVE_CGS2      */
+  int32_t flags;       /* SDG_SOLVE_GRAPH | _EXTRAPOLATE | _CGS2 | _DEVICE_STOP         */
 } sdg_solve_opts;
 
 typedef struct {

@@ -32,6 +32,7 @@ N_VARIANTS = 9
 SDG_SOLVE_GRAPH = 1
 SDG_SOLVE_EXTRAPOLATE = 2
 SDG_SOLVE_CGS2 = 4
+SDG_SOLVE_DEVICE_STOP = 8
 
 _ERRNAMES = {SDG_EINVAL: "EINVAL", SDG_ENOMEM: "ENOMEM", SDG_EDEVICE: "EDEVICE", SDG_EMESH: "EMESH",
              SDG_ENOCONV: "ENOCONV", SDG_ENONFINITE: "ENONFINITE", SDG_EUNSUPPORTED: "EUNSUPPORTED",

@@ -113,10 +113,11 @@ void check_prec(Ctx& c, int prec) {
 }  // namespace
 
 void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s, int ncols, void* z,
-              const int* mask_active, double* dot_part) {
+              const int* mask_active, double* dot_part, const int* run_flag) {
   require(!dot_part || (ncols == 1 && !mask_active), SDG_EINVAL, "the fused inner product takes one unmasked column");
   OpArgs a = base_args(c, prec);
   a.dot_part = dot_part;
+  a.run_flag = run_flag;
   if (mask_active) {
     a.mask_active = mask_active;
     a.mask_stride = MultiSys::mask_stride();
@@ -141,14 +142,15 @@ void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipS
 }
 
 // y = A32 v with FP32 vectors (one column, forward operator, FP32 face
-// slots), for the FP32-vector CG inside iterative refinement; dot_part as
-// in apply_op.  Only the persistent face kernel (variant 3) and the
+// slots), for the FP32-vector CG inside iterative refinement; dot_part and
+// run_flag as in apply_op.  Only the persistent face kernel (variant 3) and the
 // element-blocked kernel take FP32 vectors: the caller checks
 // fp32_vectors_ok first.
-void apply_op_f32v(Ctx& c, const float* v, float* y, hipStream_t s, double* dot_part) {
+void apply_op_f32v(Ctx& c, const float* v, float* y, hipStream_t s, double* dot_part, const int* run_flag) {
   require(fp32_vectors_ok(c), SDG_EUNSUPPORTED, "no FP32-vector operator for this configuration");
   OpArgs a = base_args(c, SDG_PREC_F32);
   a.dot_part = dot_part;
+  a.run_flag = run_flag;
   a.variant = c.variant32;
   a.v = reinterpret_cast<const double*>(v);  // FP32 values (vy_f32)
   a.y = reinterpret_cast<double*>(y);
@@ -1163,7 +1165,8 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     require(v_state && sigma_state && opts, SDG_EINVAL, "null argument");
     require(n_rhs >= 1 && n_rhs <= c.max_rhs, SDG_EINVAL, "n_rhs must be in [1, max_rhs of sdg_assemble]");
     require(opts->rtol > 0 && opts->max_iter > 0, SDG_EINVAL, "rtol and max_iter must be positive");
-    require((opts->flags & ~(SDG_SOLVE_GRAPH | SDG_SOLVE_EXTRAPOLATE | SDG_SOLVE_CGS2)) == 0, SDG_EINVAL,
+    require((opts->flags & ~(SDG_SOLVE_GRAPH | SDG_SOLVE_EXTRAPOLATE | SDG_SOLVE_CGS2 | SDG_SOLVE_DEVICE_STOP)) == 0,
+            SDG_EINVAL,
             "unknown solve flags");
     const int prec = opts->precision == 0 ? SDG_PREC_F64 : opts->precision;
     check_prec(c, SDG_PREC_F64);
@@ -1194,6 +1197,7 @@ int sdg_solve_step(sdg_ctx* ctx, double* v_state, double* sigma_state, const dou
     kc.rtol = opts->rtol;
     kc.max_iter = opts->max_iter;
     kc.delayed = (opts->flags & SDG_SOLVE_CGS2) == 0;
+    kc.device_stop = (opts->flags & SDG_SOLVE_DEVICE_STOP) != 0;
     // extrapolated initial guess: the previous slab continued in time; without
     // a previous slab of this width, seed it with the old state at every node
     // (the continuation of a constant is the constant)
@@ -1559,6 +1563,7 @@ int sdg_adjoint_step(sdg_ctx* ctx, const double* v_old, const double* v_slab, do
     kc.prec = SDG_PREC_F64;
     kc.transpose = true;
     kc.delayed = (opts->flags & SDG_SOLVE_CGS2) == 0;
+    kc.device_stop = (opts->flags & SDG_SOLVE_DEVICE_STOP) != 0;
     kc.x_zero = true;
     res = solver == SDG_SOLVER_CG ? solve_cg(c, c.d_b.p, c.d_x.p, kc, s) : solve_gmres(c, c.d_b.p, c.d_x.p, kc, s);
 

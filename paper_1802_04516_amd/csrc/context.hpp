@@ -33,6 +33,13 @@ struct DevScalars {
   double Hu[(kMaxRestart + 1) * kMaxRestart];
   double f[kMaxRestart + 1];
   double e;
+  // CG's stop on the device: the fused update's finalize counts the
+  // iterations it ran, copies (r.r, count) to cg_stat for one read-back and
+  // clears cg_on once sqrt(r.r) <= cg_tol; the iterations queued after that
+  // return at entry.
+  double cg_tol;
+  double cg_stat[2];
+  int cg_on, cg_iters;
 };
 
 // Scalars of one system of a multi-system Krylov solve.
@@ -260,9 +267,10 @@ struct Ctx {
 // ncols > 1: ncols independent columns stored one after another (stride n_slab)
 // z: face-slot workspace of z_col values per column (default: the context's)
 void apply_op(Ctx& c, const double* v, double* y, int prec, bool transpose, hipStream_t s, int ncols = 1,
-              void* z = nullptr, const int* mask_active = nullptr, double* dot_part = nullptr);
+              void* z = nullptr, const int* mask_active = nullptr, double* dot_part = nullptr,
+              const int* run_flag = nullptr);
 bool fp32_vectors_ok(const Ctx& c);
-void apply_op_f32v(Ctx& c, const float* v, float* y, hipStream_t s, double* dot_part);
+void apply_op_f32v(Ctx& c, const float* v, float* y, hipStream_t s, double* dot_part, const int* run_flag = nullptr);
 
 // Face-slot workspace of the allocation-free apply: a file-scope device
 // array of noalloc_scratch_bytes() per GPU; noalloc_scratch(device) returns
@@ -289,6 +297,7 @@ struct KrylovCfg {
   int precond = SDG_PRECOND_NONE;
   bool transpose = false;    // solve with A^T (adjoint)
   bool delayed = true;       // GMRES: delayed reorthogonalisation (one reduction per step)
+  bool device_stop = false;  // CG with the fused update: stop on the device (SDG_SOLVE_DEVICE_STOP)
   bool x_zero = false;       // x is zero on entry: the first residual is b itself (no operator apply)
   bool keep_targets = false; // multi-system: per-system targets already set (multi_refine_check)
   // the caller tests the residual itself (inner solves of iterative

@@ -221,6 +221,10 @@ struct OpArgs {
   // given per face and per element by face_sys / elem_sys.
   const int* mask_active = nullptr;
   int mask_stride = 0;
+  // run_flag (null: always run): while *run_flag is 0 every operator
+  // kernel returns at entry, so the iterations a solver queued past its
+  // convergence cost only their launches.
+  const int* run_flag = nullptr;
   const int* face_sys = nullptr;
   const int* elem_sys = nullptr;
   // curved elements (Section 3, sub-/iso-parametric maps): the element

@@ -245,6 +245,7 @@ __global__ __launch_bounds__(256) void k_block_apply_fact(int64_t n_elem, const 
 }
 
 __global__ void k_cg_p(int64_t n, double* __restrict__ p, const double* __restrict__ r, const DevScalars* sc) {
+  if (sc->cg_on == 0) return;
   const double beta = sc->beta;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = r[i] + beta * p[i];
@@ -791,6 +792,15 @@ double read_scalar(Ctx& c, const double* dev, hipStream_t s) {
   return c.h_pinned[0];
 }
 
+// r.r of the last iteration the fused CG update ran, and their count (one
+// read-back of cg_stat)
+static double read_cg_stat(Ctx& c, const DevScalars* sc, hipStream_t s, int& iters) {
+  SDG_HIP(hipMemcpyAsync(c.h_pinned, sc->cg_stat, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  SDG_HIP(hipStreamSynchronize(s));
+  iters = (int)c.h_pinned[1];
+  return c.h_pinned[0];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- public helpers
@@ -1041,6 +1051,7 @@ __global__ __launch_bounds__(256) void k_cg_update_blk(int64_t n_elem, const flo
                                                        const VT* __restrict__ p, const VT* __restrict__ q,
                                                        VT* __restrict__ z, const DevScalars* sc,
                                                        double* partials, int ngroups) {
+  if (sc->cg_on == 0) return;  // converged: an iteration queued past the stop
   constexpr int EPB = 256 / NV, NP = NV * (NV + 1) / 2;
   constexpr int PPT = (EPB * NP + 255) / 256;
   __shared__ double sx[EPB * NV];
@@ -1182,6 +1193,7 @@ __global__ __launch_bounds__(1024) void k_cg_init_blk_fin(const double* partials
 }
 
 __global__ void k_cg_p32(int64_t n, float* __restrict__ p, const float* __restrict__ z, const DevScalars* sc) {
+  if (sc->cg_on == 0) return;
   const double beta = sc->beta;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = (float)((double)z[i] + beta * (double)p[i]);
@@ -1198,8 +1210,11 @@ __global__ void k_f32_to_f64(int64_t n, const float* __restrict__ x, double* __r
 }
 
 // alpha = rz / pq, rr_new = r.r, beta = (r.z)_new / rz, rz = (r.z)_new from
-// the fused update's partials (one workgroup, fixed summation order).
+// the fused update's partials (one workgroup, fixed summation order); then
+// the device-side stop: count the iteration, copy (r.r, count) to cg_stat
+// and clear cg_on once sqrt(r.r) <= cg_tol (the host's own test).
 __global__ __launch_bounds__(1024) void k_cg_update_blk_fin(const double* partials, int nblocks, DevScalars* sc) {
+  if (sc->cg_on == 0) return;
   __shared__ double sh[2][16];
   double v[2] = {0.0, 0.0};
   // 8 blocks per thread and slot in flight at once, added in a fixed order
@@ -1234,12 +1249,30 @@ __global__ __launch_bounds__(1024) void k_cg_update_blk_fin(const double* partia
     sc->rr_new = rr;
     sc->beta = rz / sc->rr;
     sc->rr = rz;
+    const int it = sc->cg_iters + 1;
+    sc->cg_iters = it;
+    sc->cg_stat[0] = rr;
+    sc->cg_stat[1] = (double)it;
+    if (sqrt(rr) <= sc->cg_tol) sc->cg_on = 0;
   }
+}
+
+// Arms the device-side stop of a CG solve: tol = rtol ||b|| (negative: never
+// stop on the device, for the loops without the fused update).
+__global__ void k_cg_arm(DevScalars* sc, double tol) {
+  sc->cg_tol = tol;
+  sc->cg_on = 1;
+  sc->cg_iters = 0;
+  sc->cg_stat[0] = 0.0;
+  sc->cg_stat[1] = 0.0;
 }
 
 // *out = sum of partials[0 .. nblocks) (one workgroup, fixed order): the
 // inner product p . A p from the element kernel's per-workgroup sums.
-__global__ __launch_bounds__(1024) void k_sum_partials(const double* partials, int nblocks, double* out) {
+// run (null: always): nothing is written while *run is 0.
+__global__ __launch_bounds__(1024) void k_sum_partials(const double* partials, int nblocks, double* out,
+                                                       const int* run) {
+  if (run != nullptr && *run == 0) return;
   __shared__ double sh[16];
   double v = 0.0;
   for (int b0 = threadIdx.x; b0 < nblocks; b0 += 8 * 1024) {
@@ -1335,19 +1368,26 @@ static SolveResult solve_cg_f32(Ctx& c, const double* b, double* x, const Krylov
     res.rel_res = std::sqrt(rr) / res.bnorm;
     return res;
   }
+  // device_stop: the iterations queued past convergence (up to
+  // check_every - 1) return at entry; res counts the ones that ran
+  const int* run = k.device_stop ? &sc->cg_on : nullptr;
+  k_cg_arm<<<1, 1, 0, s>>>(sc, k.device_stop ? k.rtol * res.bnorm : -1.0);
+  check_launch();
   for (int it = 0; it < k.max_iter; ++it) {
-    apply_op_f32v(c, pv, q, s, c.d_cg_partials.p);
-    k_sum_partials<<<1, 1024, 0, s>>>(c.d_cg_partials.p, (int)egroups, &sc->pq);
+    apply_op_f32v(c, pv, q, s, c.d_cg_partials.p, run);
+    k_sum_partials<<<1, 1024, 0, s>>>(c.d_cg_partials.p, (int)egroups, &sc->pq, run);
     check_launch();
-    ++res.matvecs;
     launch_cg_update_blk<float>(c, nv, x32, r, pv, q, z, s);
     k_cg_p32<<<vgrid(n), kThreads, 0, s>>>(n, pv, z, sc);
     check_launch();
-    ++res.iters;
     if ((it + 1) % check_every == 0 || it + 1 == k.max_iter) {
-      rr = read_scalar(c, &sc->rr_new, s);
+      int ran = 0;
+      rr = read_cg_stat(c, sc, s, ran);
+      res.iters = ran;
+      res.matvecs = ran;
       require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
-      if (std::sqrt(rr) <= k.rtol * res.bnorm) break;
+      // fewer iterations ran than were queued: the device has stopped
+      if (std::sqrt(rr) <= k.rtol * res.bnorm || ran < it + 1) break;
     }
   }
   k_f32_to_f64<<<vgrid(n), kThreads, 0, s>>>(n, x32, x);
@@ -1417,10 +1457,18 @@ SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hip
     res.rel_res = std::sqrt(rr) / res.bnorm;
     return res;
   }
+  // device_stop with the fused update: the device stops the iteration, the
+  // iterations queued past convergence (up to check_every - 1) return at
+  // entry, and res counts the ones that ran.  Otherwise the host stops it.
+  const bool dstop = fused && k.device_stop;
+  const int* run = dstop ? &sc->cg_on : nullptr;
+  const int matvecs0 = res.matvecs;
+  k_cg_arm<<<1, 1, 0, s>>>(sc, dstop ? k.rtol * res.bnorm : -1.0);
+  check_launch();
   for (int it = 0; it < k.max_iter; ++it) {
     if (dotfused) {
-      apply_op(c, pv, q, k.prec, k.transpose, s, 1, nullptr, nullptr, c.d_cg_partials.p);
-      k_sum_partials<<<1, 1024, 0, s>>>(c.d_cg_partials.p, (int)egroups, &sc->pq);
+      apply_op(c, pv, q, k.prec, k.transpose, s, 1, nullptr, nullptr, c.d_cg_partials.p, run);
+      k_sum_partials<<<1, 1024, 0, s>>>(c.d_cg_partials.p, (int)egroups, &sc->pq, run);
       check_launch();
     } else {
       apply_op(c, pv, q, k.prec, k.transpose, s);
@@ -1445,9 +1493,18 @@ SolveResult solve_cg(Ctx& c, const double* b, double* x, const KrylovCfg& k, hip
     check_launch();
     ++res.iters;
     if ((it + 1) % check_every == 0 || it + 1 == k.max_iter) {
-      rr = read_scalar(c, &sc->rr_new, s);
+      bool stopped = false;  // fewer iterations ran than were queued
+      if (fused) {
+        int ran = 0;
+        rr = read_cg_stat(c, sc, s, ran);
+        res.iters = ran;
+        res.matvecs = matvecs0 + ran;
+        stopped = ran < it + 1;
+      } else {
+        rr = read_scalar(c, &sc->rr_new, s);
+      }
       require(std::isfinite(rr), SDG_ENONFINITE, "non-finite residual");
-      if (std::sqrt(rr) <= k.rtol * res.bnorm) break;
+      if (std::sqrt(rr) <= k.rtol * res.bnorm || stopped) break;
     }
   }
   if (k.recurrence_only) {  // rr: the last residual read (the start's without iterations)

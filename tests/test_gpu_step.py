@@ -444,3 +444,26 @@ def test_projection_of_initial_data_matches_oracle(case):
     print(f"{case}: projection v {ev:.2e} sigma {es:.2e}")
     assert ev <= 1e-12 and es <= 1e-12
     ctx.close()
+
+
+def test_crank_nicolson_device_stop():
+    """SDG_SOLVE_DEVICE_STOP: the CG iteration that meets the tolerance stops
+    the iterations queued behind it on the device.  Polled every 5
+    iterations, each step then takes exactly the iterations of a host test at
+    every iteration, and matches the oracle at the parity bar (FP64, and FP32
+    operator with FP64 refinement, whose inner CG solves stop the same way)."""
+    import paper_1802_04516_amd as sdg
+    for prec in (None, sdg.SDG_PREC_F32):
+        case = build("3d_cn_p2")
+        v0, s0 = waves.project(case["B"], waves.ShearWave3D(), 0.0)
+        dev = _run_pair(case, v0, s0, 4, precision=prec, precond=sdg.SDG_PRECOND_BLOCK,
+                        flags=sdg.SDG_SOLVE_DEVICE_STOP, check_every=5)
+        case["ctx"].close()
+        case2 = build("3d_cn_p2")
+        host = _run_pair(case2, v0, s0, 4, precision=prec, precond=sdg.SDG_PRECOND_BLOCK, check_every=1)
+        case2["ctx"].close()
+        for ev, es, it, rr in dev:
+            assert ev <= 1e-11 and es <= 1e-11, dev
+        print("iterations with the device stop", [e[2] for e in dev], "host test every iteration",
+              [e[2] for e in host])
+        assert [e[2] for e in dev] == [e[2] for e in host], (dev, host)
